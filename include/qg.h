@@ -1,0 +1,265 @@
+/*
+ * qg.h -- C ABI of the MI355X Newton-step library for quadratic-objective
+ * second-order cone programs (the problem class of QOCO-GPU, arXiv 2603.29197).
+ *
+ * Problem (paper Sec. 1, eq. 1):
+ *     minimize 1/2 x'Px + c'x   s.t.  h - Gx in K,  Ax = b,
+ * x in R^n, P (n x n, positive semidefinite, given as its upper triangle,
+ * as the paper's size count does in Sec. 3), A (p x n), G (m x n).
+ * K = C_1 x ... x C_K: the nonnegative orthant of dimension l (rows 0..l-1
+ * of G) followed by nsoc second-order cones of dimensions q[0..nsoc-1] in
+ * row order (the argument order of the paper's setup call, Sec. 2.1,
+ * Listing 1); l + sum(q) must equal m.
+ *
+ * Each interior-point iteration factors the KKT matrix of eq. (2),
+ *     [ P  A'  G'    ]
+ *     [ A  0   0     ]
+ *     [ G  0  -W'W   ]
+ * once (LDL', after a one-time analysis of its sparsity pattern, Sec. 2.2)
+ * and solves with the factor twice; the cone operations (Nesterov-Todd
+ * scaling, Jordan products, maximum step) run per cone in parallel
+ * (Sec. 2.1, 2.3).  All data lives on the device between setup and the
+ * return of the solution (Sec. 2.3).
+ *
+ * Conventions for every entry point:
+ *  - indices are 0-based; sparse matrices are CSC with strictly increasing
+ *    row indices inside each column (no duplicates);
+ *  - pointers documented as "host" are read (or written) before the call
+ *    returns and are never retained; "device" pointers are HIP device
+ *    memory owned by the caller (e.g. float64 torch tensors);
+ *  - all device work is ordered on the stream given to qg_setup, and every
+ *    call returns after the work it enqueued has completed;
+ *  - a handle is not thread-safe; distinct handles are independent;
+ *  - functions return QG_OK (0) or a negative QG_ERR_* code; the solver
+ *    outcome is not an error and is reported in qg_info.status.
+ */
+#ifndef QG_H
+#define QG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t qg_int;
+typedef int64_t qg_nnz;
+
+/* return codes */
+#define QG_OK 0
+#define QG_ERR_ARG (-1)        /* NULL pointer, bad dimension, l + sum(q) != m, q[k] < 1 */
+#define QG_ERR_PATTERN (-2)    /* unsorted/duplicate/out-of-range indices, P not upper, changed nnz */
+#define QG_ERR_NONFINITE (-3)  /* NaN or Inf in the data */
+#define QG_ERR_OOM (-4)        /* device or host allocation failed */
+#define QG_ERR_HIP (-5)        /* a HIP call failed (code kept in the handle) */
+#define QG_ERR_STATE (-6)      /* call out of order (e.g. backward before a solve) */
+#define QG_ERR_DEVICE (-7)     /* no usable gfx950 device */
+
+/* qg_info.status */
+#define QG_UNSOLVED 0
+#define QG_SOLVED 1
+#define QG_SOLVED_INACCURATE 2
+#define QG_MAX_ITER (-1)
+#define QG_NUMERICAL_ERROR (-2)
+
+/* qg_settings.precision */
+#define QG_FP64 0     /* every factor in FP64 */
+#define QG_FP32_IR 1  /* FP32 factors + FP64 refinement while gap >= switch_gap, then FP64 */
+
+typedef struct {
+    qg_int nrow, ncol;
+    const qg_nnz *colptr;   /* host, ncol + 1 */
+    const qg_int *rowind;   /* host, colptr[ncol] */
+    const double *val;      /* host, colptr[ncol] */
+} qg_csc;
+
+typedef struct {
+    double eps_abs, eps_rel;   /* stopping tolerances (default 1e-8) */
+    double eps_inacc;          /* tolerance for SOLVED_INACCURATE at max_iter (1e-5) */
+    int max_iter;              /* 100 */
+    int precision;             /* QG_FP64 or QG_FP32_IR */
+    double switch_gap;         /* FP32 factors while the scaled gap >= switch_gap (1e-6) */
+    double static_reg;         /* +delta on the (1,1), -delta on the (2,2) diagonal, FP64 factors (1e-8) */
+    double dyn_eps, dyn_delta; /* pivot d with sign*d <= dyn_eps becomes sign*dyn_delta (1e-13, 1e-7) */
+    double static_reg32, dyn_eps32, dyn_delta32;  /* the same for FP32 factors */
+    int ir_max;                /* refinement steps per solve with an FP64 factor (3) */
+    int ir_max32;              /* ... with an FP32 factor (10) */
+    double ir_tol;             /* stop when |r - K x|_inf <= ir_tol (1 + |r|_inf) (1e-12) */
+    double step_frac;          /* fraction of the maximum step (0.99) */
+    int differentiable;        /* 1: factor the derivative system after convergence (qg_backward) */
+    int verbose;               /* 1: one line per iteration on stderr */
+} qg_settings;
+
+typedef struct {
+    int status;                /* QG_SOLVED, ... */
+    int iters;                 /* Newton steps taken */
+    int switch_iter;           /* first iteration with an FP64 factor (-1: none) */
+    int ir_steps;              /* refinement steps over the whole solve */
+    int nreg;                  /* dynamic-regularization events over the whole solve */
+    int nfactor, nsolve;       /* factorizations (incl. the initial one), solves (excl. refinement) */
+    double pobj, dobj, pres, dres, gap;
+    double ms_setup, ms_analyze;             /* qg_setup wall time and its analysis part */
+    double ms_solve;                         /* qg_solve wall time */
+    double ms_factor, ms_trisolve, ms_cone;  /* summed device times (HIP events) */
+    double ms_step_median;                   /* median Newton-step time over all iterations */
+    double ms_step_median_fp32;              /* ... over iterations with an FP32 factor (0 if none) */
+    double ms_step_median_fp64;              /* ... over iterations with an FP64 factor (0 if none) */
+    int64_t nnz_L;                           /* entries of L incl. diagonal (exact symbolic count) */
+    double factor_flops;                     /* sum_j (c_j - 1)^2 + 3 (c_j - 1), c_j column counts */
+} qg_info;
+
+/* Integer pattern of the analysis; pointers stay valid until the object
+ * that produced them is destroyed. */
+typedef struct {
+    qg_int N;                  /* n + p + m */
+    qg_int nsuper_fund, nsuper;
+    const qg_int *perm;        /* N: perm[k] = original KKT index of pivot k */
+    const qg_int *iperm;       /* N */
+    const qg_int *parent;      /* N: elimination tree of the permuted matrix, -1 for roots */
+    const int64_t *colcount;   /* N: entries of each column of L incl. the diagonal */
+    const qg_int *super_fund;  /* nsuper_fund + 1: fundamental supernode first columns, then N */
+    const qg_int *super_ptr;   /* nsuper + 1: relaxed supernode first columns, then N */
+    const qg_nnz *rows_ptr;    /* nsuper + 1 */
+    const qg_int *rows;        /* rows_ptr[nsuper]: sorted row list of each relaxed supernode */
+} qg_pattern;
+
+typedef struct qg_handle qg_handle;      /* device solver state */
+typedef struct qg_symbolic qg_symbolic;  /* host-only analysis result */
+
+/* Fill *s with the defaults listed in qg_settings. */
+int qg_default_settings(qg_settings *s);
+
+/*
+ * Host-only analysis of the KKT pattern of eq. (2) (paper Sec. 2.2: the
+ * reordering, permutation and symbolic factorization that run once per
+ * sparsity pattern).  No device is touched.  Arguments as in qg_setup
+ * (values are ignored; P, A, G may be NULL when they have no columns with
+ * entries, i.e. are empty).  *out is owned by the caller: qg_symbolic_free.
+ */
+int qg_analyze(qg_symbolic **out, qg_int n, qg_int m, qg_int p,
+               const qg_csc *P, const qg_csc *A, const qg_csc *G,
+               qg_int l, qg_int nsoc, const qg_int *q);
+int qg_symbolic_pattern(const qg_symbolic *sym, qg_pattern *out);
+void qg_symbolic_free(qg_symbolic *sym);
+
+/*
+ * Setup (paper Sec. 2.1 Listing 1, Sec. 2.3): validates and copies the
+ * problem data (host pointers, read before return), runs the analysis and
+ * uploads everything to device 0 of the current HIP device context.
+ * P: n x n upper triangle incl. diagonal, or NULL for P = 0.  A: p x n, may
+ * be NULL iff p == 0.  G: m x n, may be NULL iff m == 0.  q: nsoc cone
+ * dimensions (host).  s: NULL for defaults.  hip_stream: the stream all
+ * work is ordered on (NULL = the default stream).
+ * Errors: QG_ERR_ARG, QG_ERR_PATTERN, QG_ERR_NONFINITE, QG_ERR_OOM,
+ * QG_ERR_HIP, QG_ERR_DEVICE.  On error *out is NULL.
+ */
+int qg_setup(qg_handle **out, qg_int n, qg_int m, qg_int p,
+             const qg_csc *P, const double *c,
+             const qg_csc *A, const double *b,
+             const qg_csc *G, const double *h,
+             qg_int l, qg_int nsoc, const qg_int *q,
+             const qg_settings *s, void *hip_stream);
+
+/*
+ * Replace values on the fixed pattern (host pointers, NULL = unchanged);
+ * the analysis is reused (paper Sec. 3.2: the reordering can be reused
+ * when only values change).  Pval/Aval/Gval follow the CSC entry order of
+ * the matrices given to qg_setup.  Invalidates the stored final factor.
+ */
+int qg_update(qg_handle *h, const double *Pval, const double *c, const double *Aval,
+              const double *b, const double *Gval, const double *hvec);
+
+/* Replace the settings (the analysis is kept). */
+int qg_set_settings(qg_handle *h, const qg_settings *s);
+
+/*
+ * Solve (paper Sec. 2.3: the whole interior-point loop runs on the device).
+ * x (n), s (m), y (p), z (m): device output buffers.  info: host, may be
+ * NULL.  With settings.differentiable the derivative system is factored
+ * once after convergence and kept for qg_backward.
+ */
+int qg_solve(qg_handle *h, double *x, double *s, double *y, double *z, qg_info *info);
+
+/*
+ * Gradients of a loss L(x*) through the last solve by implicit
+ * differentiation of the optimality conditions: with u solving
+ * K_fin u = [dl_dx; 0; 0] on the stored final factor (FP64 refinement):
+ * dl_dc = -u_x (n), dl_db = u_y (p), dl_dh = u_z (m), and on P's upper
+ * pattern dl_dPval[t] = -(u_i x_j + u_j x_i) (i < j), -u_i x_i (i == j).
+ * All device pointers; any output may be NULL.  Requires a previous
+ * qg_solve with settings.differentiable = 1 whose status was QG_SOLVED or
+ * QG_SOLVED_INACCURATE (QG_ERR_STATE otherwise).
+ */
+int qg_backward(qg_handle *h, const double *dl_dx, double *dl_dc, double *dl_dh,
+                double *dl_db, double *dl_dPval);
+
+/* Host copies of the analysis; valid until qg_cleanup. */
+int qg_get_pattern(const qg_handle *h, qg_pattern *out);
+
+/* Last error detail (HIP error code or 0). */
+int qg_last_hip_error(const qg_handle *h);
+
+/* Release every device buffer and the handle (NULL is a no-op). */
+void qg_cleanup(qg_handle *h);
+
+const char *qg_strerror(int code);
+
+/* ---------------------------------------------------------------------
+ * Step-level entry points.  Each runs one step of the Newton iteration on
+ * the handle's device state so that it can be checked in isolation; the
+ * solver uses the same kernels.  Vectors are device pointers of the
+ * documented lengths.
+ * --------------------------------------------------------------------- */
+
+/*
+ * Nesterov-Todd scaling of (s, z) (both strictly inside K; paper Sec. 2.1,
+ * Sec. 2.2 eq. 2 "W_k is the Nesterov-Todd scaling matrix"): stores W in
+ * the handle, writes lambda = W z (m) if lam != NULL, and writes the (3,3)
+ * block -W'W into the handle's KKT values.  block = 1 instead writes the
+ * derivative-system block -sym(Arw(z)^-1 Arw(s)) (see qg_backward).
+ */
+int qg_step_scaling(qg_handle *h, const double *s, const double *z, double *lam, int block);
+
+/* Host copy of the KKT values (upper CSC of eq. 2 in the original ordering,
+ * unregularized), nnz_K entries; *nnz receives the count if kval == NULL. */
+int qg_step_get_kkt(const qg_handle *h, double *kval, int64_t *nnz);
+
+/* Numeric LDL' of the current KKT values (paper Sec. 2.2 "factor" phase)
+ * in QG_FP64 or QG_FP32_IR (FP32) precision; *nreg (host, may be NULL)
+ * receives the number of dynamic-regularization events. */
+int qg_step_factor(qg_handle *h, int precision, int *nreg);
+
+/*
+ * Factor values on the oracle-style column pattern: for the permuted
+ * strictly-lower pattern (Lp: N+1, Li: Lp[N]; host) writes L's values
+ * (Lx, host, Lp[N]) and D (host, N) from the last factor (FP32 factors are
+ * widened).  Host-side extraction: meant for small test sizes.
+ */
+int qg_step_get_factor(const qg_handle *h, const int64_t *Lp, const int32_t *Li,
+                       double *Lx, double *D);
+
+/* Solve K x = rhs with the last factor (paper Sec. 2.2 "solve" phase);
+ * refine = number of FP64 refinement steps against the unregularized K
+ * (stopping early on the ir_tol test).  rhs, x: device, N.
+ * *steps (host, may be NULL): refinement steps taken. */
+int qg_step_solve(qg_handle *h, const double *rhs, double *x, int refine, int *steps);
+
+/* alpha = sup{a >= 0 : u + a du in K} over all cones (+inf if unbounded),
+ * written to *alpha (host). u strictly inside K. */
+int qg_step_max_step(qg_handle *h, const double *u, const double *du, double *alpha);
+
+/* Cone operation with the scaling of the last qg_step_scaling:
+ * op 0: out = W u;  1: out = W^-1 u;  2: out = W'W u;  3: out = u o v;
+ * op 4: out = u \ v (the w with u o w = v). */
+int qg_step_cone_op(qg_handle *h, int op, const double *u, const double *v, double *out);
+
+/* Corrector right-hand side (with the last scaling and its lambda):
+ * t = W'(lambda \ d),  d = -lambda o lambda - (W^-T ds_a) o (W dz_a) + sigma_mu e. */
+int qg_step_corrector(qg_handle *h, const double *ds_a, const double *dz_a, double sigma_mu,
+                      double *t);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QG_H */

@@ -1,0 +1,256 @@
+"""Python front end of the C ABI: a solver object holding one handle, the
+host-only analysis, and a torch.autograd.Function for gradients through the
+solution.  Marshalling only: every numeric step runs in the HIP library.
+
+Problem data follow the paper's setup call (Sec. 2.1, Listing 1):
+``(n, m, p, P, c, A, b, G, h, l, nsoc, q)`` with P the upper triangle
+(scipy CSC matrices, numpy vectors).
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional
+
+import numpy as np
+
+from . import _lib
+from ._lib import QG_FP32_IR, QG_FP64, check, lib, qg_csc, qg_info, qg_pattern, qg_settings
+
+
+class _Csc:
+    """Keeps the numpy buffers of one CSC matrix alive while C reads them."""
+
+    def __init__(self, M, nrow, ncol):
+        if M is None:
+            self.s = None
+            return
+        M = M.tocsc()
+        M.sort_indices()
+        self.colptr = np.ascontiguousarray(M.indptr, dtype=np.int64)
+        self.rowind = np.ascontiguousarray(M.indices, dtype=np.int32)
+        self.val = np.ascontiguousarray(M.data, dtype=np.float64)
+        self.s = qg_csc(nrow, ncol, self.colptr.ctypes.data_as(_lib.c_int64_p),
+                        self.rowind.ctypes.data_as(_lib.c_int32_p), self.val.ctypes.data_as(_lib.c_double_p))
+
+    def ptr(self):
+        return ctypes.byref(self.s) if self.s is not None else None
+
+
+def _dptr(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    return np.ascontiguousarray(a, dtype=np.float64).ctypes.data_as(_lib.c_double_p)
+
+
+def default_settings(**kw) -> qg_settings:
+    s = qg_settings()
+    lib().qg_default_settings(ctypes.byref(s))
+    for k, v in kw.items():
+        if not hasattr(s, k):
+            raise KeyError(k)
+        setattr(s, k, v)
+    return s
+
+
+def _pattern_dict(pt: qg_pattern) -> dict:
+    N, ns, nf = pt.N, pt.nsuper, pt.nsuper_fund
+    arr = lambda p, n, dt: np.ctypeslib.as_array(p, shape=(n,)).astype(dt).copy() if n > 0 else np.zeros(0, dt)
+    rows_ptr = arr(pt.rows_ptr, ns + 1, np.int64)
+    return dict(N=N, perm=arr(pt.perm, N, np.int32), iperm=arr(pt.iperm, N, np.int32),
+                parent=arr(pt.parent, N, np.int32), colcount=arr(pt.colcount, N, np.int64),
+                super_fund=arr(pt.super_fund, nf + 1, np.int32), super_ptr=arr(pt.super_ptr, ns + 1, np.int32),
+                rows_ptr=rows_ptr, rows=arr(pt.rows, int(rows_ptr[-1]), np.int32))
+
+
+def _args(prob):
+    P = _Csc(prob.P if prob.P.nnz > 0 else prob.P, prob.n, prob.n)
+    A = _Csc(prob.A, prob.p, prob.n) if prob.p > 0 else _Csc(None, 0, 0)
+    G = _Csc(prob.G, prob.m, prob.n) if prob.m > 0 else _Csc(None, 0, 0)
+    q = np.ascontiguousarray(np.asarray(prob.q, dtype=np.int32)) if len(prob.q) else np.zeros(1, np.int32)
+    return P, A, G, q
+
+
+def analyze(prob) -> dict:
+    """Host-only analysis (no device): the integer pattern of qg_pattern."""
+    P, A, G, q = _args(prob)
+    h = ctypes.c_void_p()
+    check(lib().qg_analyze(ctypes.byref(h), prob.n, prob.m, prob.p, P.ptr(), A.ptr(), G.ptr(), prob.l,
+                           len(prob.q), q.ctypes.data_as(_lib.c_int32_p)), "qg_analyze")
+    try:
+        pt = qg_pattern()
+        check(lib().qg_symbolic_pattern(h, ctypes.byref(pt)), "qg_symbolic_pattern")
+        return _pattern_dict(pt)
+    finally:
+        lib().qg_symbolic_free(h)
+
+
+class Solver:
+    """One device handle (qg_setup ... qg_cleanup) for a fixed sparsity pattern."""
+
+    def __init__(self, prob, settings: Optional[qg_settings] = None, stream=None, **kw):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("a HIP device is required")
+        self.torch = torch
+        self.prob = prob
+        self.n, self.m, self.p = prob.n, prob.m, prob.p
+        self.N = self.n + self.m + self.p
+        self.settings = settings if settings is not None else default_settings(**kw)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        P, A, G, q = _args(prob)
+        self._keep = (P, A, G, q)
+        self.handle = ctypes.c_void_p()
+        c = np.ascontiguousarray(prob.c, dtype=np.float64)
+        b = np.ascontiguousarray(prob.b, dtype=np.float64)
+        hv = np.ascontiguousarray(prob.h, dtype=np.float64)
+        check(lib().qg_setup(ctypes.byref(self.handle), prob.n, prob.m, prob.p, P.ptr(),
+                             c.ctypes.data_as(_lib.c_double_p), A.ptr(),
+                             b.ctypes.data_as(_lib.c_double_p) if prob.p else None, G.ptr(),
+                             hv.ctypes.data_as(_lib.c_double_p) if prob.m else None, prob.l, len(prob.q),
+                             q.ctypes.data_as(_lib.c_int32_p), ctypes.byref(self.settings),
+                             ctypes.c_void_p(self.stream.cuda_stream)), "qg_setup")
+        self.info = None
+
+    # -- lifecycle ------------------------------------------------------------
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            lib().qg_cleanup(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _empty(self, k):
+        return self.torch.empty(max(k, 1), dtype=self.torch.float64, device="cuda")
+
+    @staticmethod
+    def _vp(t):
+        return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+    # -- main calls -----------------------------------------------------------
+    def set_settings(self, **kw):
+        for k, v in kw.items():
+            setattr(self.settings, k, v)
+        check(lib().qg_set_settings(self.handle, ctypes.byref(self.settings)), "qg_set_settings")
+
+    def update(self, Pval=None, c=None, Aval=None, b=None, Gval=None, h=None):
+        keep = [None if v is None else np.ascontiguousarray(v, dtype=np.float64) for v in (Pval, c, Aval, b, Gval, h)]
+        check(lib().qg_update(self.handle, *[_dptr(v) for v in keep]), "qg_update")
+
+    def solve(self):
+        x, s, y, z = self._empty(self.n), self._empty(self.m), self._empty(self.p), self._empty(self.m)
+        info = qg_info()
+        check(lib().qg_solve(self.handle, self._vp(x), self._vp(s), self._vp(y), self._vp(z),
+                             ctypes.byref(info)), "qg_solve")
+        self.info = info.as_dict()
+        return x[:self.n], s[:self.m], y[:self.p], z[:self.m], self.info
+
+    def backward(self, dl_dx, want_P: bool = True):
+        t = self.torch
+        dl_dx = dl_dx.to(device="cuda", dtype=t.float64).contiguous()
+        dc, dh, db = self._empty(self.n), self._empty(self.m), self._empty(self.p)
+        nP = int(self.prob.P.nnz)
+        dP = self._empty(nP) if (want_P and nP > 0) else None
+        check(lib().qg_backward(self.handle, self._vp(dl_dx), self._vp(dc), self._vp(dh), self._vp(db),
+                                self._vp(dP)), "qg_backward")
+        return dict(dc=dc[:self.n], dh=dh[:self.m], db=db[:self.p], dP=None if dP is None else dP[:nP])
+
+    def pattern(self) -> dict:
+        pt = qg_pattern()
+        check(lib().qg_get_pattern(self.handle, ctypes.byref(pt)), "qg_get_pattern")
+        return _pattern_dict(pt)
+
+    # -- step-level entry points ------------------------------------------------
+    def step_scaling(self, s, z, want_lam=True, block=0):
+        lam = self._empty(self.m) if want_lam else None
+        check(lib().qg_step_scaling(self.handle, self._vp(s), self._vp(z), self._vp(lam), block), "qg_step_scaling")
+        return None if lam is None else lam[:self.m]
+
+    def step_get_kkt(self) -> np.ndarray:
+        nnz = ctypes.c_int64(0)
+        check(lib().qg_step_get_kkt(self.handle, None, ctypes.byref(nnz)), "qg_step_get_kkt")
+        out = np.empty(nnz.value)
+        check(lib().qg_step_get_kkt(self.handle, out.ctypes.data_as(_lib.c_double_p), None), "qg_step_get_kkt")
+        return out
+
+    def step_factor(self, precision=QG_FP64) -> int:
+        nreg = ctypes.c_int(0)
+        check(lib().qg_step_factor(self.handle, precision, ctypes.byref(nreg)), "qg_step_factor")
+        return nreg.value
+
+    def step_get_factor(self, Lp: np.ndarray, Li: np.ndarray):
+        Lp = np.ascontiguousarray(Lp, dtype=np.int64)
+        Li = np.ascontiguousarray(Li, dtype=np.int32)
+        Lx = np.empty(len(Li))
+        D = np.empty(len(Lp) - 1)
+        check(lib().qg_step_get_factor(self.handle, Lp.ctypes.data_as(_lib.c_int64_p),
+                                       Li.ctypes.data_as(_lib.c_int32_p), Lx.ctypes.data_as(_lib.c_double_p),
+                                       D.ctypes.data_as(_lib.c_double_p)), "qg_step_get_factor")
+        return Lx, D
+
+    def step_solve(self, rhs, refine=0):
+        x = self._empty(self.N)
+        steps = ctypes.c_int(0)
+        check(lib().qg_step_solve(self.handle, self._vp(rhs), self._vp(x), refine, ctypes.byref(steps)),
+              "qg_step_solve")
+        return x[:self.N], steps.value
+
+    def step_max_step(self, u, du) -> float:
+        a = ctypes.c_double(0.0)
+        check(lib().qg_step_max_step(self.handle, self._vp(u), self._vp(du), ctypes.byref(a)), "qg_step_max_step")
+        return a.value
+
+    def step_cone_op(self, op: int, u, v=None):
+        out = self._empty(self.m)
+        check(lib().qg_step_cone_op(self.handle, op, self._vp(u), self._vp(v), self._vp(out)), "qg_step_cone_op")
+        return out[:self.m]
+
+    def step_corrector(self, ds_a, dz_a, sigma_mu: float):
+        t = self._empty(self.m)
+        check(lib().qg_step_corrector(self.handle, self._vp(ds_a), self._vp(dz_a), float(sigma_mu), self._vp(t)),
+              "qg_step_corrector")
+        return t[:self.m]
+
+
+def _autograd_function():
+    import torch
+
+    class QGSolve(torch.autograd.Function):
+        """x* = QGSolve.apply(c, h, b, Pval, solver): forward updates the
+        values (fixed pattern) and solves; backward returns dL/dc, dL/dh,
+        dL/db and dL/dPval from one adjoint solve on the stored factor."""
+
+        @staticmethod
+        def forward(ctx, c, h, b, Pval, solver):
+            solver.update(Pval=None if Pval is None else Pval.detach().cpu().numpy(),
+                          c=c.detach().cpu().numpy(), b=b.detach().cpu().numpy(), h=h.detach().cpu().numpy())
+            if not solver.settings.differentiable:
+                solver.set_settings(differentiable=1)
+            x, s, y, z, info = solver.solve()
+            ctx.solver = solver
+            ctx.has_P = Pval is not None
+            return x.clone()
+
+        @staticmethod
+        def backward(ctx, gx):
+            g = ctx.solver.backward(gx, want_P=ctx.has_P)
+            return g["dc"].clone(), g["dh"].clone(), g["db"].clone(), \
+                (g["dP"].clone() if ctx.has_P else None), None
+
+    return QGSolve
+
+
+class _Lazy:
+    def __init__(self):
+        self.f = None
+
+    def apply(self, *args):
+        if self.f is None:
+            self.f = _autograd_function()
+        return self.f.apply(*args)
+
+
+QGSolve = _Lazy()

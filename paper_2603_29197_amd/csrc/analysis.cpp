@@ -1,0 +1,587 @@
+// Host analysis of the KKT pattern (paper Sec. 2.2: reordering, permutation
+// and symbolic factorization, executed once per sparsity pattern and reused
+// while only values change, Sec. 3.2).
+//
+// The integers produced here follow one fully specified rule so that an
+// independent implementation can reproduce them bit for bit:
+//  1. graph = off-diagonal pattern of K (eq. 2), both triangles;
+//  2. nodes of degree > max(16, floor(10 sqrt(N))) are ordered last, by index;
+//  3. minimum degree on the quotient graph with supervariables (merged into
+//     the smallest index when their variable and element lists coincide
+//     among the pivot's neighbours), mass elimination, element absorption,
+//     and the approximate external degree bound of Amestoy, Davis and Duff
+//     (no aggressive absorption); pivot = least (degree, index);
+//  4. postorder of the elimination tree of that order (children and roots
+//     by increasing index), composed with it;
+//  5. elimination tree and column counts of the final order;
+//  6. fundamental supernodes (parent[j] = j+1, colcount[j] = colcount[j+1]+1,
+//     j the only child of j+1);
+//  7. relaxed supernodes: a group G absorbs the next supernode T when T holds
+//     G's parent column and the merged block has zeros <= 0.1 stored or
+//     (width <= 8 and zeros <= 64), stored = w r - w(w-1)/2 with
+//     r = width(G) + colcount[first(T)];
+//  8. row list of a supernode = its columns followed by the rows below it.
+#include "analysis.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <set>
+#include <stdexcept>
+#include <utility>
+
+namespace qg {
+
+static int check_csc(const qg_csc *M, int32_t nrow, int32_t ncol, bool upper, bool need_values,
+                     CscData &out) {
+    out.nrow = nrow;
+    out.ncol = ncol;
+    out.colptr.assign((size_t)ncol + 1, 0);
+    out.rowind.clear();
+    out.val.clear();
+    if (M == nullptr) return QG_OK;
+    if (M->nrow != nrow || M->ncol != ncol) return QG_ERR_ARG;
+    if (ncol > 0 && (M->colptr == nullptr)) return QG_ERR_ARG;
+    if (ncol == 0) return QG_OK;
+    if (M->colptr[0] != 0) return QG_ERR_PATTERN;
+    for (int32_t j = 0; j < ncol; ++j)
+        if (M->colptr[j + 1] < M->colptr[j]) return QG_ERR_PATTERN;
+    int64_t nnz = M->colptr[ncol];
+    if (nnz > 0 && M->rowind == nullptr) return QG_ERR_ARG;
+    if (nnz > 0 && need_values && M->val == nullptr) return QG_ERR_ARG;
+    for (int32_t j = 0; j < ncol; ++j) {
+        for (int64_t t = M->colptr[j]; t < M->colptr[j + 1]; ++t) {
+            int32_t i = M->rowind[t];
+            if (i < 0 || i >= nrow) return QG_ERR_PATTERN;
+            if (t > M->colptr[j] && i <= M->rowind[t - 1]) return QG_ERR_PATTERN;
+            if (upper && i > j) return QG_ERR_PATTERN;
+            if (need_values && !std::isfinite(M->val[t])) return QG_ERR_NONFINITE;
+        }
+    }
+    out.colptr.assign(M->colptr, M->colptr + ncol + 1);
+    out.rowind.assign(M->rowind, M->rowind + nnz);
+    if (need_values && nnz > 0) out.val.assign(M->val, M->val + nnz);
+    else out.val.assign((size_t)nnz, 0.0);
+    return QG_OK;
+}
+
+int build_problem_pattern(ProblemPattern &pp, int32_t n, int32_t m, int32_t p,
+                          const qg_csc *P, const qg_csc *A, const qg_csc *G,
+                          int32_t l, int32_t nsoc, const int32_t *q, bool need_values) {
+    if (n <= 0 || m < 0 || p < 0 || l < 0 || nsoc < 0) return QG_ERR_ARG;
+    if (nsoc > 0 && q == nullptr) return QG_ERR_ARG;
+    if (p > 0 && A == nullptr) return QG_ERR_ARG;
+    if (m > 0 && G == nullptr) return QG_ERR_ARG;
+    int64_t tot = l;
+    for (int32_t k = 0; k < nsoc; ++k) {
+        if (q[k] < 1) return QG_ERR_ARG;
+        tot += q[k];
+    }
+    if (tot != m) return QG_ERR_ARG;
+    if ((int64_t)n + p + m > (int64_t)INT32_MAX / 2) return QG_ERR_ARG;
+    pp.n = n; pp.m = m; pp.p = p; pp.l = l; pp.nsoc = nsoc;
+    pp.q.assign(q, q + nsoc);
+    pp.soc_off.assign((size_t)nsoc + 1, l);
+    for (int32_t k = 0; k < nsoc; ++k) pp.soc_off[k + 1] = pp.soc_off[k] + q[k];
+    int rc;
+    if ((rc = check_csc(P, n, n, true, need_values, pp.P)) != QG_OK) return rc;
+    if ((rc = check_csc(A, p, n, false, need_values, pp.A)) != QG_OK) return rc;
+    if ((rc = check_csc(G, m, n, false, need_values, pp.G)) != QG_OK) return rc;
+    return QG_OK;
+}
+
+// Row-wise (transposed) structure of a CSC matrix: for each row, its columns
+// (increasing) and the CSC position of each entry.
+static void transpose_index(const CscData &M, std::vector<int64_t> &rp, std::vector<int32_t> &rc,
+                            std::vector<int64_t> &rpos) {
+    rp.assign((size_t)M.nrow + 1, 0);
+    for (int32_t i : M.rowind) rp[i + 1]++;
+    for (int32_t i = 0; i < M.nrow; ++i) rp[i + 1] += rp[i];
+    rc.resize(M.rowind.size());
+    rpos.resize(M.rowind.size());
+    std::vector<int64_t> fill(rp.begin(), rp.end() - 1);
+    for (int32_t j = 0; j < M.ncol; ++j)
+        for (int64_t t = M.colptr[j]; t < M.colptr[j + 1]; ++t) {
+            int64_t d = fill[M.rowind[t]]++;
+            rc[d] = j;
+            rpos[d] = t;
+        }
+}
+
+void build_kkt_pattern(const ProblemPattern &pp, KktPattern &kp) {
+    const int32_t n = pp.n, p = pp.p, m = pp.m, N = n + p + m;
+    kp.N = N;
+    kp.Kp.assign((size_t)N + 1, 0);
+    kp.Ki.clear();
+    kp.posP.assign(pp.P.rowind.size(), -1);
+    kp.posA.assign(pp.A.rowind.size(), -1);
+    kp.posG.assign(pp.G.rowind.size(), -1);
+    kp.diag.assign((size_t)N, -1);
+    kp.blk33.clear();
+    kp.blk33_off.assign((size_t)pp.nsoc + 1, 0);
+    std::vector<int64_t> Arp, Grp, Apos, Gpos;
+    std::vector<int32_t> Arc, Grc;
+    transpose_index(pp.A, Arp, Arc, Apos);
+    transpose_index(pp.G, Grp, Grc, Gpos);
+    // columns 0..n-1: P's upper column, then the diagonal if P lacks it
+    for (int32_t j = 0; j < n; ++j) {
+        bool has_diag = false;
+        for (int64_t t = pp.P.colptr[j]; t < pp.P.colptr[j + 1]; ++t) {
+            int32_t i = pp.P.rowind[t];
+            kp.posP[t] = (int64_t)kp.Ki.size();
+            if (i == j) { has_diag = true; kp.diag[j] = (int64_t)kp.Ki.size(); }
+            kp.Ki.push_back(i);
+        }
+        if (!has_diag) { kp.diag[j] = (int64_t)kp.Ki.size(); kp.Ki.push_back(j); }
+        kp.Kp[j + 1] = (int64_t)kp.Ki.size();
+    }
+    // columns n..n+p-1: row i of A (transposed), then the diagonal
+    for (int32_t i = 0; i < p; ++i) {
+        int32_t j = n + i;
+        for (int64_t t = Arp[i]; t < Arp[i + 1]; ++t) {
+            kp.posA[Apos[t]] = (int64_t)kp.Ki.size();
+            kp.Ki.push_back(Arc[t]);
+        }
+        kp.diag[j] = (int64_t)kp.Ki.size();
+        kp.Ki.push_back(j);
+        kp.Kp[j + 1] = (int64_t)kp.Ki.size();
+    }
+    // columns n+p..: row i of G, then the (3,3) block column
+    std::vector<int64_t> soc_pos;   // per SOC, per local column b: start of its a = 0..b entries
+    int32_t cone = 0;
+    for (int32_t i = 0; i < m; ++i) {
+        int32_t j = n + p + i;
+        for (int64_t t = Grp[i]; t < Grp[i + 1]; ++t) {
+            kp.posG[Gpos[t]] = (int64_t)kp.Ki.size();
+            kp.Ki.push_back(Grc[t]);
+        }
+        if (i < pp.l) {
+            kp.diag[j] = (int64_t)kp.Ki.size();
+            kp.Ki.push_back(j);
+        } else {
+            while (i >= pp.soc_off[cone + 1]) ++cone;
+            int32_t off = pp.soc_off[cone];
+            for (int32_t a = off; a <= i; ++a) {
+                if (a == i) kp.diag[j] = (int64_t)kp.Ki.size();
+                kp.Ki.push_back(n + p + a);
+            }
+        }
+        kp.Kp[j + 1] = (int64_t)kp.Ki.size();
+    }
+    // (3,3) positions in the documented order
+    for (int32_t i = 0; i < pp.l; ++i) kp.blk33.push_back(kp.diag[n + p + i]);
+    for (int32_t k = 0; k < pp.nsoc; ++k) {
+        kp.blk33_off[k] = (int64_t)kp.blk33.size() - pp.l;
+        for (int32_t b = pp.soc_off[k]; b < pp.soc_off[k + 1]; ++b) {
+            int64_t colstart = kp.Kp[n + p + b + 1] - (b - pp.soc_off[k] + 1);
+            for (int32_t a = 0; a <= b - pp.soc_off[k]; ++a) kp.blk33.push_back(colstart + a);
+        }
+    }
+    kp.blk33_off[pp.nsoc] = (int64_t)kp.blk33.size() - pp.l;
+}
+
+// ---------------------------------------------------------------------------
+// ordering: approximate-degree minimum degree on the quotient graph
+// ---------------------------------------------------------------------------
+namespace {
+
+enum : int8_t { VAR = 0, MERGED = 1, ELEMENT = 2, ABSORBED = 3 };
+
+struct QuotientGraph {
+    int32_t N;
+    std::vector<std::vector<int32_t>> A, E, Lel;
+    std::vector<int64_t> nv, deg, wtot, wcur;
+    std::vector<int64_t> wstamp;
+    std::vector<int8_t> status;
+    std::vector<int32_t> head, next, tail;  // member chains
+    std::vector<int64_t> mark;
+    int64_t stamp = 0;
+};
+
+inline uint64_t mix(uint64_t h, uint64_t v) {
+    h ^= v + 0x9e3779b97f4a7c15ULL + (h << 6) + (h >> 2);
+    return h;
+}
+
+}  // namespace
+
+void min_degree_order(int32_t N, const std::vector<int64_t> &Gp, const std::vector<int32_t> &Gi,
+                      std::vector<int32_t> &order) {
+    QuotientGraph g;
+    g.N = N;
+    g.A.resize(N); g.E.resize(N); g.Lel.resize(N);
+    g.nv.assign(N, 1); g.deg.assign(N, 0); g.wtot.assign(N, 0); g.wcur.assign(N, 0);
+    g.wstamp.assign(N, -1);
+    g.status.assign(N, VAR);
+    g.head.resize(N); g.next.assign(N, -1); g.tail.resize(N);
+    g.mark.assign(N, 0);
+    std::iota(g.head.begin(), g.head.end(), 0);
+    std::iota(g.tail.begin(), g.tail.end(), 0);
+    std::set<std::pair<int64_t, int32_t>> pq;
+    for (int32_t i = 0; i < N; ++i) {
+        auto &a = g.A[i];
+        for (int64_t t = Gp[i]; t < Gp[i + 1]; ++t) if (Gi[t] != i) a.push_back(Gi[t]);
+        std::sort(a.begin(), a.end());
+        g.deg[i] = (int64_t)a.size();
+        pq.insert({g.deg[i], i});
+    }
+    order.clear();
+    order.reserve(N);
+    int64_t rem = N;
+    int64_t pivot_id = 0;
+    std::vector<int32_t> Lp, members;
+    std::vector<std::pair<uint64_t, int32_t>> keyed;
+    while (!pq.empty()) {
+        const int32_t p = pq.begin()->second;
+        pq.erase(pq.begin());
+        ++pivot_id;
+        // members of p in increasing order
+        members.clear();
+        for (int32_t v = g.head[p]; v != -1; v = g.next[v]) members.push_back(v);
+        std::sort(members.begin(), members.end());
+        order.insert(order.end(), members.begin(), members.end());
+        // Lp = (A_p U union L_e) \ {p}
+        ++g.stamp;
+        const int64_t lpmark = g.stamp;
+        g.mark[p] = lpmark;
+        Lp.clear();
+        for (int32_t v : g.A[p])
+            if (g.status[v] == VAR && g.mark[v] != lpmark) { g.mark[v] = lpmark; Lp.push_back(v); }
+        for (int32_t e : g.E[p])
+            for (int32_t v : g.Lel[e])
+                if (g.status[v] == VAR && g.mark[v] != lpmark) { g.mark[v] = lpmark; Lp.push_back(v); }
+        std::sort(Lp.begin(), Lp.end());
+        for (int32_t e : g.E[p]) {
+            g.status[e] = ABSORBED;
+            std::vector<int32_t>().swap(g.Lel[e]);
+        }
+        g.status[p] = ELEMENT;
+        rem -= g.nv[p];
+        std::vector<int32_t>().swap(g.A[p]);
+        std::vector<int32_t>().swap(g.E[p]);
+        int64_t wlp = 0;
+        for (int32_t i : Lp) wlp += g.nv[i];
+        g.Lel[p] = Lp;
+        g.wtot[p] = wlp;
+        for (int32_t i : Lp) pq.erase({g.deg[i], i});
+        // list updates
+        for (int32_t i : Lp) {
+            auto &Ei = g.E[i];
+            size_t k = 0;
+            for (int32_t e : Ei) if (g.status[e] == ELEMENT) Ei[k++] = e;
+            Ei.resize(k);
+            Ei.insert(std::lower_bound(Ei.begin(), Ei.end(), p), p);
+            auto &Ai = g.A[i];
+            k = 0;
+            for (int32_t v : Ai) if (g.mark[v] != lpmark) Ai[k++] = v;
+            Ai.resize(k);
+        }
+        // supervariable detection among Lp: hash, then confirm by full equality
+        keyed.clear();
+        for (int32_t i : Lp) {
+            uint64_t h = mix(mix(0, g.A[i].size()), g.E[i].size());
+            for (int32_t v : g.A[i]) h = mix(h, (uint64_t)v);
+            h = mix(h, 0xabcdefULL);
+            for (int32_t e : g.E[i]) h = mix(h, (uint64_t)e);
+            keyed.push_back({h, i});
+        }
+        std::sort(keyed.begin(), keyed.end());
+        for (size_t a = 0; a < keyed.size();) {
+            size_t b = a;
+            while (b < keyed.size() && keyed[b].first == keyed[a].first) ++b;
+            for (size_t u = a; u < b; ++u) {
+                int32_t r = keyed[u].second;
+                if (g.status[r] != VAR) continue;
+                for (size_t w = u + 1; w < b; ++w) {
+                    int32_t j = keyed[w].second;
+                    if (g.status[j] != VAR) continue;
+                    if (g.A[j] != g.A[r] || g.E[j] != g.E[r]) continue;
+                    // merge j into r (r < j: keyed is sorted by (hash, index))
+                    g.nv[r] += g.nv[j];
+                    g.next[g.tail[r]] = g.head[j];
+                    g.tail[r] = g.tail[j];
+                    for (int32_t v : g.A[j]) {
+                        auto &Av = g.A[v];
+                        Av.erase(std::find(Av.begin(), Av.end(), j));
+                    }
+                    for (int32_t e : g.E[j]) {
+                        auto &Le = g.Lel[e];
+                        Le.erase(std::find(Le.begin(), Le.end(), j));
+                    }
+                    std::vector<int32_t>().swap(g.A[j]);
+                    std::vector<int32_t>().swap(g.E[j]);
+                    g.status[j] = MERGED;
+                    g.nv[j] = 0;
+                }
+            }
+            a = b;
+        }
+        // approximate degrees: w_e = W(L_e \ Lp) from the element totals
+        for (int32_t i : Lp) {
+            if (g.status[i] != VAR) continue;
+            for (int32_t e : g.E[i]) {
+                if (e == p) continue;
+                if (g.wstamp[e] != pivot_id) { g.wstamp[e] = pivot_id; g.wcur[e] = g.wtot[e]; }
+                g.wcur[e] -= g.nv[i];
+            }
+        }
+        for (int32_t i : Lp) {
+            if (g.status[i] != VAR) continue;
+            int64_t wa = 0, we = 0;
+            for (int32_t v : g.A[i]) wa += g.nv[v];
+            for (int32_t e : g.E[i]) if (e != p) we += g.wcur[e];
+            const int64_t lpi = wlp - g.nv[i];
+            int64_t d = std::min(rem - g.nv[i], g.deg[i] + lpi);
+            d = std::min(d, wa + lpi + we);
+            g.deg[i] = d;
+            pq.insert({d, i});
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// elimination tree, postorder, column counts, supernodes
+// ---------------------------------------------------------------------------
+namespace {
+
+// Upper triangle pattern (CSC) of the permuted matrix, rows sorted.
+void permuted_upper(const KktPattern &kp, const std::vector<int32_t> &iperm,
+                    std::vector<int64_t> &Up, std::vector<int32_t> &Ui) {
+    const int32_t N = kp.N;
+    Up.assign((size_t)N + 1, 0);
+    for (int32_t j = 0; j < N; ++j)
+        for (int64_t t = kp.Kp[j]; t < kp.Kp[j + 1]; ++t) {
+            int32_t a = iperm[kp.Ki[t]], b = iperm[j];
+            Up[std::max(a, b) + 1]++;
+        }
+    for (int32_t j = 0; j < N; ++j) Up[j + 1] += Up[j];
+    Ui.resize(kp.Ki.size());
+    std::vector<int64_t> fill(Up.begin(), Up.end() - 1);
+    for (int32_t j = 0; j < N; ++j)
+        for (int64_t t = kp.Kp[j]; t < kp.Kp[j + 1]; ++t) {
+            int32_t a = iperm[kp.Ki[t]], b = iperm[j];
+            Ui[fill[std::max(a, b)]++] = std::min(a, b);
+        }
+    for (int32_t j = 0; j < N; ++j) std::sort(Ui.begin() + Up[j], Ui.begin() + Up[j + 1]);
+}
+
+void etree_of(int32_t N, const std::vector<int64_t> &Up, const std::vector<int32_t> &Ui,
+              std::vector<int32_t> &parent) {
+    parent.assign(N, -1);
+    std::vector<int32_t> root(N, -1);   // path-compressed ancestor
+    for (int32_t k = 0; k < N; ++k) {
+        for (int64_t t = Up[k]; t < Up[k + 1]; ++t) {
+            int32_t i = Ui[t];
+            while (i != -1 && i < k) {
+                int32_t up = root[i];
+                root[i] = k;
+                if (up == -1) { parent[i] = k; break; }
+                i = up;
+            }
+        }
+    }
+}
+
+void postorder_of(const std::vector<int32_t> &parent, std::vector<int32_t> &post) {
+    const int32_t N = (int32_t)parent.size();
+    std::vector<int32_t> first(N, -1), sib(N, -1);
+    // children lists in increasing order: insert from the highest index down
+    for (int32_t j = N - 1; j >= 0; --j)
+        if (parent[j] >= 0) { sib[j] = first[parent[j]]; first[parent[j]] = j; }
+    post.clear();
+    post.reserve(N);
+    std::vector<int32_t> stack;
+    for (int32_t r = 0; r < N; ++r) {
+        if (parent[r] != -1) continue;
+        stack.push_back(r);
+        while (!stack.empty()) {
+            int32_t v = stack.back();
+            if (first[v] != -1) {
+                int32_t c = first[v];
+                first[v] = sib[c];   // consume the child
+                stack.push_back(c);
+            } else {
+                stack.pop_back();
+                post.push_back(v);
+            }
+        }
+    }
+}
+
+}  // namespace
+
+void analyze_pattern(const KktPattern &kp, Symbolic &sym) {
+    const int32_t N = kp.N;
+    sym.N = N;
+    // 1. symmetric graph without the diagonal
+    std::vector<int64_t> deg(N, 0);
+    for (int32_t j = 0; j < N; ++j)
+        for (int64_t t = kp.Kp[j]; t < kp.Kp[j + 1]; ++t)
+            if (kp.Ki[t] != j) { deg[j]++; deg[kp.Ki[t]]++; }
+    // 2. dense nodes
+    const int64_t cut = std::max<int64_t>(16, (int64_t)std::floor(10.0 * std::sqrt((double)N)));
+    std::vector<int32_t> local(N, -1), keep;
+    for (int32_t i = 0; i < N; ++i)
+        if (deg[i] <= cut) { local[i] = (int32_t)keep.size(); keep.push_back(i); }
+    const int32_t Ns = (int32_t)keep.size();
+    std::vector<int64_t> Gp((size_t)Ns + 1, 0);
+    for (int32_t j = 0; j < N; ++j)
+        for (int64_t t = kp.Kp[j]; t < kp.Kp[j + 1]; ++t) {
+            int32_t i = kp.Ki[t];
+            if (i == j || local[i] < 0 || local[j] < 0) continue;
+            Gp[local[i] + 1]++; Gp[local[j] + 1]++;
+        }
+    for (int32_t i = 0; i < Ns; ++i) Gp[i + 1] += Gp[i];
+    std::vector<int32_t> Gi(Gp[Ns]);
+    {
+        std::vector<int64_t> fill(Gp.begin(), Gp.end() - 1);
+        for (int32_t j = 0; j < N; ++j)
+            for (int64_t t = kp.Kp[j]; t < kp.Kp[j + 1]; ++t) {
+                int32_t i = kp.Ki[t];
+                if (i == j || local[i] < 0 || local[j] < 0) continue;
+                Gi[fill[local[i]]++] = local[j];
+                Gi[fill[local[j]]++] = local[i];
+            }
+    }
+    // 3. minimum degree
+    std::vector<int32_t> md_local, md;
+    min_degree_order(Ns, Gp, Gi, md_local);
+    md.reserve(N);
+    for (int32_t v : md_local) md.push_back(keep[v]);
+    for (int32_t i = 0; i < N; ++i) if (local[i] < 0) md.push_back(i);
+    // 4. postorder of the etree of the minimum-degree order
+    std::vector<int32_t> inv(N);
+    for (int32_t k = 0; k < N; ++k) inv[md[k]] = k;
+    std::vector<int64_t> Up;
+    std::vector<int32_t> Ui, par, post;
+    permuted_upper(kp, inv, Up, Ui);
+    etree_of(N, Up, Ui, par);
+    postorder_of(par, post);
+    sym.perm.resize(N);
+    for (int32_t k = 0; k < N; ++k) sym.perm[k] = md[post[k]];
+    sym.iperm.resize(N);
+    for (int32_t k = 0; k < N; ++k) sym.iperm[sym.perm[k]] = k;
+    // 5. etree and column counts of the final order (row subtrees)
+    permuted_upper(kp, sym.iperm, Up, Ui);
+    etree_of(N, Up, Ui, sym.parent);
+    sym.colcount.assign(N, 1);
+    {
+        std::vector<int32_t> visited(N, -1);
+        for (int32_t k = 0; k < N; ++k) {
+            visited[k] = k;
+            for (int64_t t = Up[k]; t < Up[k + 1]; ++t) {
+                for (int32_t i = Ui[t]; visited[i] != k; i = sym.parent[i]) {
+                    visited[i] = k;
+                    sym.colcount[i]++;
+                }
+            }
+        }
+    }
+    sym.nnz_L = 0;
+    sym.flops = 0.0;
+    for (int32_t j = 0; j < N; ++j) {
+        sym.nnz_L += sym.colcount[j];
+        double c = (double)(sym.colcount[j] - 1);
+        sym.flops += c * c + 3.0 * c;
+    }
+    // 6. fundamental supernodes
+    std::vector<int32_t> nchild(N, 0);
+    for (int32_t j = 0; j < N; ++j) if (sym.parent[j] >= 0) nchild[sym.parent[j]]++;
+    sym.super_fund.clear();
+    if (N > 0) sym.super_fund.push_back(0);
+    for (int32_t j = 0; j + 1 < N; ++j) {
+        bool joins = sym.parent[j] == j + 1 && sym.colcount[j] == sym.colcount[j + 1] + 1 &&
+                     nchild[j + 1] == 1;
+        if (!joins) sym.super_fund.push_back(j + 1);
+    }
+    sym.super_fund.push_back(N);
+    // 7. relaxed supernodes
+    sym.super_ptr.clear();
+    {
+        const int32_t nf = (int32_t)sym.super_fund.size() - 1;
+        int32_t gf = sym.super_fund[0], gl = sym.super_fund[1] - 1;
+        int64_t gsum = 0;
+        for (int32_t c = gf; c <= gl; ++c) gsum += sym.colcount[c];
+        for (int32_t s = 1; s < nf; ++s) {
+            const int32_t tf = sym.super_fund[s], tl = sym.super_fund[s + 1] - 1;
+            int64_t tsum = 0;
+            for (int32_t c = tf; c <= tl; ++c) tsum += sym.colcount[c];
+            bool merge = false;
+            if (sym.parent[gl] == tf) {
+                const int64_t w = tl - gf + 1;
+                const int64_t r = (gl - gf + 1) + sym.colcount[tf];
+                const int64_t stored = w * r - w * (w - 1) / 2;
+                const int64_t zeros = stored - (gsum + tsum);
+                merge = ((double)zeros <= 0.1 * (double)stored) || (w <= 8 && zeros <= 64);
+            }
+            if (merge) {
+                gl = tl;
+                gsum += tsum;
+            } else {
+                sym.super_ptr.push_back(gf);
+                gf = tf; gl = tl; gsum = tsum;
+            }
+        }
+        if (N > 0) sym.super_ptr.push_back(gf);
+        sym.super_ptr.push_back(N);
+    }
+    // 8. row lists by the union recursion over the supernodal tree: rows below
+    //    a supernode = (its columns' K rows U its children's rows below) beyond
+    //    its last column
+    const int32_t ns = (int32_t)sym.super_ptr.size() - 1;
+    std::vector<int32_t> col2sn(N);
+    for (int32_t s = 0; s < ns; ++s)
+        for (int32_t c = sym.super_ptr[s]; c < sym.super_ptr[s + 1]; ++c) col2sn[c] = s;
+    sym.sn_parent.assign(ns, -1);
+    for (int32_t s = 0; s < ns; ++s) {
+        int32_t pc = sym.parent[sym.super_ptr[s + 1] - 1];
+        sym.sn_parent[s] = pc >= 0 ? col2sn[pc] : -1;
+    }
+    // lower structure of the permuted matrix: for column c, rows i > c
+    std::vector<int64_t> Lop((size_t)N + 1, 0);
+    for (int32_t j = 0; j < N; ++j)
+        for (int64_t t = Up[j]; t < Up[j + 1]; ++t) if (Ui[t] < j) Lop[Ui[t] + 1]++;
+    for (int32_t j = 0; j < N; ++j) Lop[j + 1] += Lop[j];
+    std::vector<int32_t> Loi(Lop[N]);
+    {
+        std::vector<int64_t> fill(Lop.begin(), Lop.end() - 1);
+        for (int32_t j = 0; j < N; ++j)
+            for (int64_t t = Up[j]; t < Up[j + 1]; ++t) if (Ui[t] < j) Loi[fill[Ui[t]]++] = j;
+    }
+    std::vector<std::vector<int32_t>> below(ns);
+    std::vector<int32_t> cfirst(ns, -1), csib(ns, -1);
+    for (int32_t s = ns - 1; s >= 0; --s)
+        if (sym.sn_parent[s] >= 0) { csib[s] = cfirst[sym.sn_parent[s]]; cfirst[sym.sn_parent[s]] = s; }
+    std::vector<int32_t> seen(N, -1), buf;
+    sym.rows_ptr.assign((size_t)ns + 1, 0);
+    sym.rows.clear();
+    sym.sn_level.assign(ns, 0);
+    for (int32_t s = 0; s < ns; ++s) {
+        const int32_t f = sym.super_ptr[s], l = sym.super_ptr[s + 1] - 1;
+        buf.clear();
+        for (int32_t c = f; c <= l; ++c)
+            for (int64_t t = Lop[c]; t < Lop[c + 1]; ++t) {
+                int32_t i = Loi[t];
+                if (i > l && seen[i] != s) { seen[i] = s; buf.push_back(i); }
+            }
+        for (int32_t c = cfirst[s]; c != -1; c = csib[c]) {
+            for (int32_t i : below[c])
+                if (i > l && seen[i] != s) { seen[i] = s; buf.push_back(i); }
+            std::vector<int32_t>().swap(below[c]);
+            sym.sn_level[s] = std::max(sym.sn_level[s], sym.sn_level[c] + 1);
+        }
+        std::sort(buf.begin(), buf.end());
+        for (int32_t c = f; c <= l; ++c) sym.rows.push_back(c);
+        sym.rows.insert(sym.rows.end(), buf.begin(), buf.end());
+        sym.rows_ptr[s + 1] = (int64_t)sym.rows.size();
+        if (sym.sn_parent[s] >= 0) below[s] = buf;
+        // consistency with the column counts: rows below = structure of the last column
+        if ((int64_t)buf.size() + 1 != sym.colcount[l])
+            throw std::logic_error("row list does not match the column count");
+    }
+    sym.nlevels = 0;
+    for (int32_t s = 0; s < ns; ++s) sym.nlevels = std::max(sym.nlevels, sym.sn_level[s] + 1);
+}
+
+}  // namespace qg

@@ -1,0 +1,423 @@
+// C ABI (qg.h): setup / update / solve / backward, the host-only analysis,
+// and the step-level entry points.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "vec.hpp"
+
+struct qg_symbolic {
+    qg::ProblemPattern pp;
+    qg::KktPattern kp;
+    qg::Symbolic sym;
+};
+
+namespace qg {
+
+// ----------------------------------------------------------------------------
+// adjoint: K_fin u = [g; 0; 0] on the stored derivative factor (FP64 + IR)
+// ----------------------------------------------------------------------------
+__global__ void dP_kernel(int32_t n, const int64_t *__restrict__ Pp, const int32_t *__restrict__ Pi,
+                          const double *__restrict__ u, const double *__restrict__ x, double *__restrict__ dP) {
+    const int32_t j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= n) return;
+    for (int64_t t = Pp[j]; t < Pp[j + 1]; ++t) {
+        const int32_t i = Pi[t];
+        dP[t] = (i == j) ? -u[i] * x[i] : -(u[i] * x[j] + u[j] * x[i]);
+    }
+}
+
+int adjoint_backward(qg_handle *h, const double *g, double *dc, double *dh, double *db, double *dP) {
+    Device &d = h->d;
+    const int32_t n = h->n, p = h->p, m = h->m;
+    int rc;
+    QG_HIP(h, hipMemcpyAsync(d.rhs.p, g, sizeof(double) * n, hipMemcpyDeviceToDevice, h->stream));
+    if ((rc = launch_fill(h, p + m, 0.0, d.rhs.p + n))) return rc;
+    if ((rc = refined_solve(h, d.rhs.p, d.sol.p, QG_FP64, 10, nullptr))) return rc;
+    const double *u = d.sol.p;
+    if (dc && (rc = launch_scale_copy(h, n, -1.0, u, dc))) return rc;
+    if (db && p > 0) QG_HIP(h, hipMemcpyAsync(db, u + n, sizeof(double) * p, hipMemcpyDeviceToDevice, h->stream));
+    if (dh && m > 0) QG_HIP(h, hipMemcpyAsync(dh, u + n + p, sizeof(double) * m, hipMemcpyDeviceToDevice, h->stream));
+    if (dP && !h->pp.P.rowind.empty()) {
+        dP_kernel<<<(n + 255) / 256, 256, 0, h->stream>>>(n, d.Pp.p, d.Pi.p, u, d.x.p, dP);
+        QG_HIP(h, hipGetLastError());
+    }
+    QG_HIP(h, hipStreamSynchronize(h->stream));
+    return QG_OK;
+}
+
+static bool finite_all(const double *v, int64_t len) {
+    for (int64_t i = 0; i < len; ++i) if (!std::isfinite(v[i])) return false;
+    return true;
+}
+
+static int allocate_device(qg_handle *h) {
+    Device &d = h->d;
+    const Plan &pl = h->plan;
+    const KktPattern &kp = h->kp;
+    int rc;
+#define UP(buf, vec) if ((rc = dupload(h, d.buf, vec))) return rc
+    std::vector<int32_t> perm(h->sym.perm), iperm(h->sym.iperm);
+    UP(perm, perm);
+    UP(iperm, iperm);
+    UP(blk33, kp.blk33);
+    UP(blk_off, kp.blk33_off);
+    UP(soc_off, h->pp.soc_off);
+    UP(sn_first, pl.sn_first);
+    UP(sn_rows, pl.sn_rows);
+    UP(task_sn, pl.task_sn);
+    UP(task_col, pl.task_col);
+    UP(asm_row, pl.asm_row);
+    UP(ctb_child, pl.ctb_child);
+    UP(ctb_col, pl.ctb_col);
+    UP(rel, pl.rel);
+    UP(ch_ptr, pl.ch_ptr);
+    UP(ch_list, pl.ch_list);
+    UP(lvl_small_sn, pl.lvl_small_sn);
+    UP(sn_rptr, pl.sn_rptr);
+    UP(fr_off, pl.fr_off);
+    UP(task_ptr, pl.task_ptr);
+    UP(asm_ptr, pl.asm_ptr);
+    UP(asm_src, pl.asm_src);
+    UP(ctb_ptr, pl.ctb_ptr);
+    UP(rel_ptr, pl.rel_ptr);
+    UP(uv_off, pl.uv_off);
+    UP(reg_sign, pl.reg_sign);
+    std::vector<int32_t> zc((size_t)h->m, -1);
+    for (int32_t k = 0; k < h->pp.nsoc; ++k)
+        for (int32_t r = h->pp.soc_off[k]; r < h->pp.soc_off[k + 1]; ++r) zc[r] = k;
+    UP(zcone, zc);
+    UP(Pp, h->pp.P.colptr);
+    UP(Pi, h->pp.P.rowind);
+#undef UP
+    const size_t N = (size_t)h->N, m = (size_t)h->m;
+    if ((rc = dalloc(h, d.front64, (size_t)pl.front_total))) return rc;
+    if ((rc = dalloc(h, d.front32, (size_t)pl.front_total))) return rc;
+    if ((rc = dalloc(h, d.uvec, (size_t)pl.uv_total))) return rc;
+    if ((rc = dalloc(h, d.dinv64, (size_t)pl.dinv_total))) return rc;
+    if ((rc = dalloc(h, d.dinv32, (size_t)pl.dinv_total))) return rc;
+    if ((rc = dalloc(h, d.vbuf, (size_t)pl.max_r))) return rc;
+    if ((rc = dalloc(h, d.nreg, 1))) return rc;
+    if ((rc = dalloc(h, d.x, (size_t)h->n))) return rc;
+    if ((rc = dalloc(h, d.y, (size_t)h->p))) return rc;
+    if ((rc = dalloc(h, d.s, m))) return rc;
+    if ((rc = dalloc(h, d.z, m))) return rc;
+    if ((rc = dalloc(h, d.rx, (size_t)h->n))) return rc;
+    if ((rc = dalloc(h, d.ry, (size_t)h->p))) return rc;
+    if ((rc = dalloc(h, d.rz, m))) return rc;
+    if ((rc = dalloc(h, d.rhs, N))) return rc;
+    if ((rc = dalloc(h, d.sol, N))) return rc;
+    if ((rc = dalloc(h, d.res, N))) return rc;
+    if ((rc = dalloc(h, d.corr, N))) return rc;
+    if ((rc = dalloc(h, d.xp, N))) return rc;
+    if ((rc = dalloc(h, d.dsa, m))) return rc;
+    if ((rc = dalloc(h, d.ds, m))) return rc;
+    if ((rc = dalloc(h, d.t, m))) return rc;
+    if ((rc = dalloc(h, d.lam, m))) return rc;
+    if ((rc = dalloc(h, d.w, (size_t)h->pp.l))) return rc;
+    if ((rc = dalloc(h, d.wbar, m))) return rc;
+    if ((rc = dalloc(h, d.beta, (size_t)h->pp.nsoc))) return rc;
+    if ((rc = dalloc(h, d.scal, 64))) return rc;
+    if ((rc = dalloc(h, d.alpha, 4))) return rc;
+    if ((rc = dalloc(h, d.amin, 4))) return rc;
+    const size_t nblk = (N + 255) / 256 + (size_t)((h->pp.l + h->pp.nsoc + 255) / 256) + 1;
+    if ((rc = dalloc(h, d.partials, nblk * NSCAL))) return rc;
+    return QG_OK;
+}
+
+static int check_device(qg_handle *h) {
+    int dev = 0, count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return QG_ERR_DEVICE;
+    QG_HIP(h, hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    QG_HIP(h, hipGetDeviceProperties(&prop, dev));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return QG_ERR_DEVICE;
+    h->device = dev;
+    return QG_OK;
+}
+
+}  // namespace qg
+
+using namespace qg;
+
+extern "C" {
+
+int qg_default_settings(qg_settings *s) {
+    if (!s) return QG_ERR_ARG;
+    s->eps_abs = 1e-8;
+    s->eps_rel = 1e-8;
+    s->eps_inacc = 1e-5;
+    s->max_iter = 100;
+    s->precision = QG_FP64;
+    s->switch_gap = 1e-6;
+    s->static_reg = 1e-8;
+    s->dyn_eps = 1e-13;
+    s->dyn_delta = 1e-7;
+    s->static_reg32 = 1e-7;
+    s->dyn_eps32 = 1e-10;
+    s->dyn_delta32 = 1e-6;
+    s->ir_max = 3;
+    s->ir_max32 = 10;
+    s->ir_tol = 1e-12;
+    s->step_frac = 0.99;
+    s->differentiable = 0;
+    s->verbose = 0;
+    return QG_OK;
+}
+
+const char *qg_strerror(int code) {
+    switch (code) {
+        case QG_OK: return "ok";
+        case QG_ERR_ARG: return "invalid argument";
+        case QG_ERR_PATTERN: return "invalid sparsity pattern";
+        case QG_ERR_NONFINITE: return "non-finite value in the data";
+        case QG_ERR_OOM: return "out of memory";
+        case QG_ERR_HIP: return "HIP runtime error";
+        case QG_ERR_STATE: return "call out of order";
+        case QG_ERR_DEVICE: return "no gfx950 device";
+        default: return "unknown error";
+    }
+}
+
+int qg_analyze(qg_symbolic **out, qg_int n, qg_int m, qg_int p, const qg_csc *P, const qg_csc *A,
+               const qg_csc *G, qg_int l, qg_int nsoc, const qg_int *q) {
+    if (!out) return QG_ERR_ARG;
+    *out = nullptr;
+    qg_symbolic *s = new (std::nothrow) qg_symbolic();
+    if (!s) return QG_ERR_OOM;
+    try {
+        int rc = build_problem_pattern(s->pp, n, m, p, P, A, G, l, nsoc, q, false);
+        if (rc) { delete s; return rc; }
+        build_kkt_pattern(s->pp, s->kp);
+        analyze_pattern(s->kp, s->sym);
+    } catch (const std::bad_alloc &) {
+        delete s;
+        return QG_ERR_OOM;
+    } catch (...) {
+        delete s;
+        return QG_ERR_PATTERN;
+    }
+    *out = s;
+    return QG_OK;
+}
+
+static void fill_pattern(const Symbolic &sym, qg_pattern *o) {
+    o->N = sym.N;
+    o->nsuper_fund = (qg_int)sym.super_fund.size() - 1;
+    o->nsuper = (qg_int)sym.super_ptr.size() - 1;
+    o->perm = sym.perm.data();
+    o->iperm = sym.iperm.data();
+    o->parent = sym.parent.data();
+    o->colcount = sym.colcount.data();
+    o->super_fund = sym.super_fund.data();
+    o->super_ptr = sym.super_ptr.data();
+    o->rows_ptr = sym.rows_ptr.data();
+    o->rows = sym.rows.data();
+}
+
+int qg_symbolic_pattern(const qg_symbolic *sym, qg_pattern *out) {
+    if (!sym || !out) return QG_ERR_ARG;
+    fill_pattern(sym->sym, out);
+    return QG_OK;
+}
+
+void qg_symbolic_free(qg_symbolic *sym) { delete sym; }
+
+void qg_cleanup(qg_handle *h) {
+    if (!h) return;
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    dfree_all(h);
+    delete h;
+}
+
+int qg_setup(qg_handle **out, qg_int n, qg_int m, qg_int p, const qg_csc *P, const double *c,
+             const qg_csc *A, const double *b, const qg_csc *G, const double *hv, qg_int l, qg_int nsoc,
+             const qg_int *q, const qg_settings *s, void *hip_stream) {
+    if (!out) return QG_ERR_ARG;
+    *out = nullptr;
+    const auto t0 = std::chrono::steady_clock::now();
+    qg_handle *h = new (std::nothrow) qg_handle();
+    if (!h) return QG_ERR_OOM;
+    if (s) h->st = *s; else qg_default_settings(&h->st);
+    h->stream = (hipStream_t)hip_stream;
+    int rc = QG_OK;
+    try {
+        rc = build_problem_pattern(h->pp, n, m, p, P, A, G, l, nsoc, q, true);
+        if (!rc && (!c || (p > 0 && !b) || (m > 0 && !hv))) rc = QG_ERR_ARG;
+        if (!rc && (!finite_all(c, n) || (p > 0 && !finite_all(b, p)) || (m > 0 && !finite_all(hv, m))))
+            rc = QG_ERR_NONFINITE;
+        if (rc) { delete h; return rc; }
+        h->n = n; h->m = m; h->p = p; h->N = n + m + p;
+        h->hc.assign(c, c + n);
+        h->hb.assign(b ? b : c, b ? b + p : c);
+        h->hh.assign(hv ? hv : c, hv ? hv + m : c);
+        if ((rc = check_device(h))) { delete h; return rc; }
+        build_kkt_pattern(h->pp, h->kp);
+        h->nnzK = (int64_t)h->kp.Ki.size();
+        const auto ta = std::chrono::steady_clock::now();
+        analyze_pattern(h->kp, h->sym);
+        h->ms_analyze = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - ta).count();
+        if ((rc = build_plan(h))) { qg_cleanup(h); return rc; }
+        if ((rc = allocate_device(h))) { qg_cleanup(h); return rc; }
+        if ((rc = upload_static_values(h))) { qg_cleanup(h); return rc; }
+        if (hipStreamSynchronize(h->stream) != hipSuccess) { qg_cleanup(h); return QG_ERR_HIP; }
+    } catch (const std::bad_alloc &) {
+        qg_cleanup(h);
+        return QG_ERR_OOM;
+    } catch (...) {
+        qg_cleanup(h);
+        return QG_ERR_PATTERN;
+    }
+    h->ms_setup = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    *out = h;
+    return QG_OK;
+}
+
+int qg_update(qg_handle *h, const double *Pval, const double *c, const double *Aval, const double *b,
+              const double *Gval, const double *hv) {
+    if (!h) return QG_ERR_ARG;
+    auto chk = [](const double *v, size_t len) { return v == nullptr || finite_all(v, (int64_t)len); };
+    if (!chk(Pval, h->pp.P.val.size()) || !chk(c, h->n) || !chk(Aval, h->pp.A.val.size()) ||
+        !chk(b, h->p) || !chk(Gval, h->pp.G.val.size()) || !chk(hv, h->m))
+        return QG_ERR_NONFINITE;
+    if (Pval) h->pp.P.val.assign(Pval, Pval + h->pp.P.val.size());
+    if (Aval) h->pp.A.val.assign(Aval, Aval + h->pp.A.val.size());
+    if (Gval) h->pp.G.val.assign(Gval, Gval + h->pp.G.val.size());
+    if (c) h->hc.assign(c, c + h->n);
+    if (b) h->hb.assign(b, b + h->p);
+    if (hv) h->hh.assign(hv, hv + h->m);
+    h->solved = false;
+    h->final_factor = false;
+    int rc = upload_static_values(h);
+    if (rc) return rc;
+    QG_HIP(h, hipStreamSynchronize(h->stream));
+    return QG_OK;
+}
+
+int qg_set_settings(qg_handle *h, const qg_settings *s) {
+    if (!h || !s) return QG_ERR_ARG;
+    h->st = *s;
+    return QG_OK;
+}
+
+int qg_solve(qg_handle *h, double *x, double *s, double *y, double *z, qg_info *info) {
+    if (!h) return QG_ERR_ARG;
+    return ipm_solve(h, x, s, y, z, info);
+}
+
+int qg_backward(qg_handle *h, const double *dl_dx, double *dl_dc, double *dl_dh, double *dl_db,
+                double *dl_dPval) {
+    if (!h || !dl_dx) return QG_ERR_ARG;
+    if (!h->solved || !h->final_factor) return QG_ERR_STATE;
+    return adjoint_backward(h, dl_dx, dl_dc, dl_dh, dl_db, dl_dPval);
+}
+
+int qg_get_pattern(const qg_handle *h, qg_pattern *out) {
+    if (!h || !out) return QG_ERR_ARG;
+    fill_pattern(h->sym, out);
+    return QG_OK;
+}
+
+int qg_last_hip_error(const qg_handle *h) { return h ? h->last_hip : 0; }
+
+// ---------------------------- step-level ----------------------------------
+int qg_step_scaling(qg_handle *h, const double *s, const double *z, double *lam, int block) {
+    if (!h || !s || !z) return QG_ERR_ARG;
+    h->final_factor = false;
+    int rc = launch_scaling(h, s, z, lam, block);
+    if (rc) return rc;
+    QG_HIP(h, hipStreamSynchronize(h->stream));
+    return QG_OK;
+}
+
+int qg_step_get_kkt(const qg_handle *h, double *kval, int64_t *nnz) {
+    if (!h) return QG_ERR_ARG;
+    if (nnz) *nnz = h->nnzK;
+    if (!kval) return QG_OK;
+    qg_handle *hh = const_cast<qg_handle *>(h);
+    QG_HIP(hh, hipMemcpyAsync(kval, h->d.kval.p, sizeof(double) * h->nnzK, hipMemcpyDeviceToHost, h->stream));
+    QG_HIP(hh, hipStreamSynchronize(h->stream));
+    return QG_OK;
+}
+
+int qg_step_factor(qg_handle *h, int precision, int *nreg) {
+    if (!h || (precision != QG_FP64 && precision != QG_FP32_IR)) return QG_ERR_ARG;
+    h->final_factor = false;
+    int rc = launch_factor(h, precision);
+    if (rc) return rc;
+    return read_nreg(h, nreg);
+}
+
+int qg_step_get_factor(const qg_handle *h, const int64_t *Lp, const int32_t *Li, double *Lx, double *D) {
+    if (!h || !Lp || !Li || !Lx || !D || h->last_precision < 0) return QG_ERR_ARG;
+    qg_handle *hh = const_cast<qg_handle *>(h);
+    const Plan &pl = h->plan;
+    const size_t tot = (size_t)pl.front_total;
+    std::vector<double> fr(tot);
+    if (h->last_precision == QG_FP32_IR) {
+        std::vector<float> f32(tot);
+        QG_HIP(hh, hipMemcpyAsync(f32.data(), h->d.front32.p, sizeof(float) * tot, hipMemcpyDeviceToHost, h->stream));
+        QG_HIP(hh, hipStreamSynchronize(h->stream));
+        for (size_t i = 0; i < tot; ++i) fr[i] = f32[i];
+    } else {
+        QG_HIP(hh, hipMemcpyAsync(fr.data(), h->d.front64.p, sizeof(double) * tot, hipMemcpyDeviceToHost, h->stream));
+        QG_HIP(hh, hipStreamSynchronize(h->stream));
+    }
+    for (int32_t s = 0; s < pl.ns; ++s) {
+        const int32_t f = pl.sn_first[s], k = pl.sn_first[s + 1] - f;
+        const int64_t r = pl.sn_rptr[s + 1] - pl.sn_rptr[s];
+        const int32_t *rows = pl.sn_rows.data() + pl.sn_rptr[s];
+        const double *F = fr.data() + pl.fr_off[s];
+        for (int32_t jc = 0; jc < k; ++jc) {
+            const int32_t col = f + jc;
+            D[col] = F[(int64_t)jc * r + jc];
+            int64_t pos = jc + 1;
+            for (int64_t t = Lp[col]; t < Lp[col + 1]; ++t) {
+                while (pos < r && rows[pos] < Li[t]) ++pos;
+                if (pos >= r || rows[pos] != Li[t]) return QG_ERR_PATTERN;
+                Lx[t] = F[(int64_t)jc * r + pos];
+            }
+        }
+    }
+    return QG_OK;
+}
+
+int qg_step_solve(qg_handle *h, const double *rhs, double *x, int refine, int *steps) {
+    if (!h || !rhs || !x || refine < 0 || h->last_precision < 0) return QG_ERR_ARG;
+    int rc = refined_solve(h, rhs, x, h->last_precision, refine, steps);
+    if (rc) return rc;
+    QG_HIP(h, hipStreamSynchronize(h->stream));
+    return QG_OK;
+}
+
+int qg_step_max_step(qg_handle *h, const double *u, const double *du, double *alpha) {
+    if (!h || !u || !du || !alpha) return QG_ERR_ARG;
+    int rc = launch_reset_steps(h);
+    if (rc) return rc;
+    if ((rc = launch_step_min(h, u, du, 0))) return rc;
+    unsigned long long bits = 0;
+    QG_HIP(h, hipMemcpyAsync(&bits, h->d.amin.p, sizeof(bits), hipMemcpyDeviceToHost, h->stream));
+    QG_HIP(h, hipStreamSynchronize(h->stream));
+    std::memcpy(alpha, &bits, sizeof(double));
+    return QG_OK;
+}
+
+int qg_step_cone_op(qg_handle *h, int op, const double *u, const double *v, double *out) {
+    if (!h || !u || !out || op < 0 || op > 4 || ((op == 3 || op == 4) && !v)) return QG_ERR_ARG;
+    int rc = launch_cone_op(h, op, u, v, out);
+    if (rc) return rc;
+    QG_HIP(h, hipStreamSynchronize(h->stream));
+    return QG_OK;
+}
+
+int qg_step_corrector(qg_handle *h, const double *ds_a, const double *dz_a, double sigma_mu, double *t) {
+    if (!h || !ds_a || !dz_a || !t || !(sigma_mu >= 0.0)) return QG_ERR_ARG;
+    int rc = launch_corrector(h, ds_a, dz_a, sigma_mu, nullptr, 0.0, t);
+    if (rc) return rc;
+    QG_HIP(h, hipStreamSynchronize(h->stream));
+    return QG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,414 @@
+// Cone operations of the Newton step (paper Sec. 2.1: Jordan products and
+// Nesterov-Todd scalings, implemented per cone and run in parallel, Sec. 2.3):
+// one thread per orthant entry, one thread per second-order cone.
+//
+// Formulas (standard SOC Jordan algebra; NT scaling as in Vandenberghe's
+// cone-QP method, which the paper's solver implements):
+//   J = diag(1, -I); e = (1, 0, .., 0); u o v = (u'v, u0 v1 + v0 u1);
+//   lam \ v: rho = lam0^2 - |lam1|^2, x0 = (lam0 v0 - lam1'v1)/rho,
+//            x1 = (v1 - x0 lam1)/lam0;
+//   NT: s_n = sqrt(s'Js), z_n = sqrt(z'Jz) (as sqrt((u0-|u1|)(u0+|u1|))),
+//       sb = s/s_n, zb = z/z_n, gamma = sqrt((1 + zb'sb)/2),
+//       wb = (sb + J zb)/(2 gamma), beta = sqrt(s_n/z_n), W = beta Wb,
+//       Wb u = (wb'u, u1 + wb1 (u0 + wb1'u1/(1 + wb0))),
+//       W^-1 = (1/beta) J Wb J,  W'W = beta^2 (2 wb wb' - J);
+//   orthant: w = sqrt(s/z), lam = sqrt(s z), W'W = s/z.
+//   Max step (u interior): orthant -u/du for du < 0; SOC with uJ = sqrt(u'Ju),
+//   ub = u/uJ, rho0 = ub'J du/uJ, rho1 = (du1 - ((rho0 uJ + du0)/(1+ub0)) ub1)/uJ:
+//   1/max(0, |rho1| - rho0).
+#include "vec.hpp"
+
+namespace qg {
+
+__device__ inline double jnorm(const double *u, int32_t q) {
+    double n1 = 0.0;
+    for (int32_t a = 1; a < q; ++a) n1 += u[a] * u[a];
+    n1 = sqrt(n1);
+    return sqrt((u[0] - n1) * (u[0] + n1));
+}
+
+// out = beta * Wb u  (inv = 0)   or   (1/beta) J Wb J u  (inv = 1)
+__device__ inline void soc_w_apply(const double *wb, double beta, const double *u, double *out, int32_t q,
+                                   int inv) {
+    const double sg = inv ? -1.0 : 1.0;
+    double w1u1 = 0.0;
+    for (int32_t a = 1; a < q; ++a) w1u1 += wb[a] * (sg * u[a]);
+    const double u0 = u[0];
+    const double coef = u0 + w1u1 / (1.0 + wb[0]);
+    const double scale = inv ? 1.0 / beta : beta;
+    out[0] = scale * (wb[0] * u0 + w1u1);
+    for (int32_t a = 1; a < q; ++a) out[a] = scale * sg * (sg * u[a] + wb[a] * coef);
+}
+
+// NT scaling and the (3,3) block of K.  block == 1 writes the derivative
+// block -sym(Arw(z)^-1 Arw(s)) instead of -W'W (orthant: -s/z either way).
+__global__ void scaling_kernel(int32_t l, int32_t nsoc, const int32_t *__restrict__ soc_off,
+                               const int64_t *__restrict__ blk_off, const int64_t *__restrict__ blk33,
+                               const double *__restrict__ s, const double *__restrict__ z,
+                               double *__restrict__ w, double *__restrict__ wbar, double *__restrict__ beta,
+                               double *__restrict__ lam, double *__restrict__ kval, int block) {
+    const int32_t t = blockIdx.x * 256 + threadIdx.x;
+    if (t < l) {
+        const double si = s[t], zi = z[t];
+        w[t] = sqrt(si / zi);
+        if (lam) lam[t] = sqrt(si * zi);
+        kval[blk33[t]] = -(si / zi);
+        return;
+    }
+    const int32_t k = t - l;
+    if (k >= nsoc) return;
+    const int32_t off = soc_off[k], q = soc_off[k + 1] - off;
+    const double *sk = s + off, *zk = z + off;
+    double *wb = wbar + (off - l);
+    const int64_t base = l + blk_off[k];
+    if (block == 1) {
+        // H = Arw(z)^-1 Arw(s); Arw(z)^-1 = (1/d)[[z0, -z1'], [-z1, (d/z0) I + z1 z1'/z0]]
+        const double z0 = zk[0];
+        double z1z1 = 0.0;
+        for (int32_t a = 1; a < q; ++a) z1z1 += zk[a] * zk[a];
+        const double dz = z0 * z0 - z1z1;
+        for (int32_t bcol = 0; bcol < q; ++bcol)
+            for (int32_t arow = 0; arow <= bcol; ++arow) {
+                // H(i, j) = sum_t Ainv(i, t) Arw(s)(t, j); symmetric part (H(a,b) + H(b,a)) / 2
+                double hab = 0.0, hba = 0.0;
+                for (int32_t pass = 0; pass < 2; ++pass) {
+                    const int32_t i = pass ? bcol : arow, j = pass ? arow : bcol;
+                    double acc = 0.0;
+                    for (int32_t tt = 0; tt < q; ++tt) {
+                        double ai;   // Ainv(i, tt) * d
+                        if (i == 0 && tt == 0) ai = z0;
+                        else if (i == 0) ai = -zk[tt];
+                        else if (tt == 0) ai = -zk[i];
+                        else ai = (i == tt ? dz / z0 : 0.0) + zk[i] * zk[tt] / z0;
+                        double as;   // Arw(s)(tt, j)
+                        if (tt == 0 && j == 0) as = sk[0];
+                        else if (tt == 0) as = sk[j];
+                        else if (j == 0) as = sk[tt];
+                        else as = (tt == j) ? sk[0] : 0.0;
+                        acc += ai * as;
+                    }
+                    if (pass) hba = acc / dz; else hab = acc / dz;
+                }
+                kval[blk33[base + (int64_t)bcol * (bcol + 1) / 2 + arow]] = -0.5 * (hab + hba);
+            }
+        return;
+    }
+    const double sn = jnorm(sk, q), zn = jnorm(zk, q);
+    double dot = 0.0;
+    for (int32_t a = 0; a < q; ++a) dot += (zk[a] / zn) * (sk[a] / sn);
+    const double gamma = sqrt((1.0 + dot) * 0.5);
+    for (int32_t a = 0; a < q; ++a) {
+        const double zb = zk[a] / zn, sb = sk[a] / sn;
+        wb[a] = (sb + (a == 0 ? zb : -zb)) / (2.0 * gamma);
+    }
+    const double bt = sqrt(sn / zn);
+    beta[k] = bt;
+    if (lam) soc_w_apply(wb, bt, zk, lam + off, q, 0);
+    const double b2 = bt * bt;
+    for (int32_t bcol = 0; bcol < q; ++bcol)
+        for (int32_t arow = 0; arow <= bcol; ++arow) {
+            const double jab = (arow == bcol) ? (arow == 0 ? 1.0 : -1.0) : 0.0;
+            kval[blk33[base + (int64_t)bcol * (bcol + 1) / 2 + arow]] = -b2 * (2.0 * wb[arow] * wb[bcol] - jab);
+        }
+}
+
+// op: 0 W u, 1 W^-1 u, 2 W'W u, 3 u o v, 4 u \ v
+__global__ void cone_op_kernel(int op, int32_t l, int32_t nsoc, const int32_t *__restrict__ soc_off,
+                               const double *__restrict__ w, const double *__restrict__ wbar,
+                               const double *__restrict__ beta, const double *__restrict__ u,
+                               const double *__restrict__ v, double *__restrict__ out) {
+    const int32_t t = blockIdx.x * 256 + threadIdx.x;
+    if (t < l) {
+        const double ui = u[t];
+        double r;
+        switch (op) {
+            case 0: r = w[t] * ui; break;
+            case 1: r = ui / w[t]; break;
+            case 2: r = w[t] * w[t] * ui; break;
+            case 3: r = ui * v[t]; break;
+            default: r = v[t] / ui; break;
+        }
+        out[t] = r;
+        return;
+    }
+    const int32_t k = t - l;
+    if (k >= nsoc) return;
+    const int32_t off = soc_off[k], q = soc_off[k + 1] - off;
+    const double *uk = u + off;
+    double *ok = out + off;
+    const double *wb = wbar + (off - l);
+    if (op == 0 || op == 1) {
+        soc_w_apply(wb, beta[k], uk, ok, q, op);
+    } else if (op == 2) {
+        // beta^2 (2 wb (wb'u) - J u)
+        double wu = 0.0;
+        for (int32_t a = 0; a < q; ++a) wu += wb[a] * uk[a];
+        const double b2 = beta[k] * beta[k];
+        for (int32_t a = 0; a < q; ++a) ok[a] = b2 * (2.0 * wb[a] * wu - (a == 0 ? uk[a] : -uk[a]));
+    } else if (op == 3) {
+        const double *vk = v + off;
+        double dot = 0.0;
+        for (int32_t a = 0; a < q; ++a) dot += uk[a] * vk[a];
+        const double u0 = uk[0], v0 = vk[0];
+        for (int32_t a = 1; a < q; ++a) ok[a] = u0 * vk[a] + v0 * uk[a];
+        ok[0] = dot;
+    } else {
+        const double *vk = v + off;
+        double l1l1 = 0.0, l1v1 = 0.0;
+        for (int32_t a = 1; a < q; ++a) { l1l1 += uk[a] * uk[a]; l1v1 += uk[a] * vk[a]; }
+        const double rho = uk[0] * uk[0] - l1l1;
+        const double x0 = (uk[0] * vk[0] - l1v1) / rho;
+        for (int32_t a = 1; a < q; ++a) ok[a] = (vk[a] - x0 * uk[a]) / uk[0];
+        ok[0] = x0;
+    }
+}
+
+// ds = tsign * tvec - W'W dz   (tvec may be s with tsign = -1: affine step)
+__global__ void ds_kernel(int32_t l, int32_t nsoc, const int32_t *__restrict__ soc_off,
+                          const double *__restrict__ w, const double *__restrict__ wbar,
+                          const double *__restrict__ beta, const double *__restrict__ tvec, double tsign,
+                          const double *__restrict__ dz, double *__restrict__ ds) {
+    const int32_t t = blockIdx.x * 256 + threadIdx.x;
+    if (t < l) {
+        ds[t] = tsign * tvec[t] - w[t] * w[t] * dz[t];
+        return;
+    }
+    const int32_t k = t - l;
+    if (k >= nsoc) return;
+    const int32_t off = soc_off[k], q = soc_off[k + 1] - off;
+    const double *wb = wbar + (off - l);
+    double wu = 0.0;
+    for (int32_t a = 0; a < q; ++a) wu += wb[a] * dz[off + a];
+    const double b2 = beta[k] * beta[k];
+    for (int32_t a = 0; a < q; ++a) {
+        const double whw = b2 * (2.0 * wb[a] * wu - (a == 0 ? dz[off + a] : -dz[off + a]));
+        ds[off + a] = tsign * tvec[off + a] - whw;
+    }
+}
+
+// t = W'(lam \ d), d = -lam o lam - (W^-1 ds_a) o (W dz_a) + sigma mu e, with
+// sigma = clip((1 - alpha_a)^3, 0, 1) and alpha_a = min(1, amin[0], amin[1]).
+__global__ void corrector_kernel(int32_t l, int32_t nsoc, const int32_t *__restrict__ soc_off,
+                                 const double *__restrict__ w, const double *__restrict__ wbar,
+                                 const double *__restrict__ beta, const double *__restrict__ lam,
+                                 const double *__restrict__ dsa, const double *__restrict__ dza,
+                                 const unsigned long long *__restrict__ amin, double mu, double sigma_mu_fixed,
+                                 double *__restrict__ tout, double *__restrict__ alpha_rec) {
+    double smu;
+    if (sigma_mu_fixed >= 0.0) {
+        smu = sigma_mu_fixed;
+    } else {
+        const double aa = fmin(1.0, fmin(__longlong_as_double((long long)amin[0]),
+                                         __longlong_as_double((long long)amin[1])));
+        const double om = 1.0 - aa;
+        const double sigma = fmin(1.0, fmax(0.0, om * om * om));
+        smu = sigma * mu;
+        if (blockIdx.x == 0 && threadIdx.x == 0 && alpha_rec) alpha_rec[0] = aa;
+    }
+    const int32_t t = blockIdx.x * 256 + threadIdx.x;
+    if (t < l) {
+        const double li = lam[t], wi = w[t];
+        const double d = -li * li - (dsa[t] / wi) * (wi * dza[t]) + smu;
+        tout[t] = wi * (d / li);
+        return;
+    }
+    const int32_t k = t - l;
+    if (k >= nsoc) return;
+    const int32_t off = soc_off[k], q = soc_off[k + 1] - off;
+    const double *wb = wbar + (off - l);
+    const double bt = beta[k];
+    const double *lk = lam + off;
+    const double *ua = dsa + off, *ub = dza + off;
+    // A = W^-1 ds_a = (1/bt) J Wb J ds_a,  B = W dz_a = bt Wb dz_a, componentwise:
+    //   A0 = (w0 u0 - w1'u1)/bt,  Aa = (u_a - w_a (u0 - w1'u1/(1+w0)))/bt
+    //   B0 = bt (w0 v0 + w1'v1),   Ba = bt (v_a + w_a (v0 + w1'v1/(1+w0)))
+    double wu = 0.0, wv = 0.0, ll = 0.0;
+    for (int32_t a = 1; a < q; ++a) { wu += wb[a] * ua[a]; wv += wb[a] * ub[a]; }
+    for (int32_t a = 0; a < q; ++a) ll += lk[a] * lk[a];
+    const double ca = ua[0] - wu / (1.0 + wb[0]);
+    const double cb = ub[0] + wv / (1.0 + wb[0]);
+    const double A0 = (wb[0] * ua[0] - wu) / bt;
+    const double B0 = bt * (wb[0] * ub[0] + wv);
+    double ab = A0 * B0;
+    for (int32_t a = 1; a < q; ++a) ab += ((ua[a] - wb[a] * ca) / bt) * (bt * (ub[a] + wb[a] * cb));
+    // d = -lam o lam - A o B + smu e;  x = lam \ d;  t = W x
+    const double d0 = -ll - ab + smu;
+    double l1l1 = 0.0, l1d1 = 0.0;
+    for (int32_t a = 1; a < q; ++a) {
+        const double Aa = (ua[a] - wb[a] * ca) / bt, Ba = bt * (ub[a] + wb[a] * cb);
+        const double da = -(2.0 * lk[0] * lk[a]) - (A0 * Ba + B0 * Aa);
+        l1l1 += lk[a] * lk[a];
+        l1d1 += lk[a] * da;
+    }
+    const double rho = lk[0] * lk[0] - l1l1;
+    const double x0 = (lk[0] * d0 - l1d1) / rho;
+    double wx = 0.0;
+    for (int32_t a = 1; a < q; ++a) {
+        const double Aa = (ua[a] - wb[a] * ca) / bt, Ba = bt * (ub[a] + wb[a] * cb);
+        const double da = -(2.0 * lk[0] * lk[a]) - (A0 * Ba + B0 * Aa);
+        wx += wb[a] * ((da - x0 * lk[a]) / lk[0]);
+    }
+    const double cx = x0 + wx / (1.0 + wb[0]);
+    double *to = tout + off;
+    for (int32_t a = 1; a < q; ++a) {
+        const double Aa = (ua[a] - wb[a] * ca) / bt, Ba = bt * (ub[a] + wb[a] * cb);
+        const double da = -(2.0 * lk[0] * lk[a]) - (A0 * Ba + B0 * Aa);
+        const double xa = (da - x0 * lk[a]) / lk[0];
+        to[a] = bt * (xa + wb[a] * cx);
+    }
+    to[0] = bt * (wb[0] * x0 + wx);
+}
+
+// per-cone maximum step, min-reduced into amin[slot] (ordered bits of a
+// nonnegative double)
+__global__ void step_kernel(int32_t l, int32_t nsoc, const int32_t *__restrict__ soc_off,
+                            const double *__restrict__ u, const double *__restrict__ du,
+                            unsigned long long *__restrict__ amin) {
+    const int32_t t = blockIdx.x * 256 + threadIdx.x;
+    double a = INFINITY;
+    if (t < l) {
+        if (du[t] < 0.0) a = -u[t] / du[t];
+    } else if (t - l < nsoc) {
+        const int32_t k = t - l;
+        const int32_t off = soc_off[k], q = soc_off[k + 1] - off;
+        const double *uk = u + off, *dk = du + off;
+        const double uJ = jnorm(uk, q);
+        double r0 = uk[0] / uJ * dk[0];
+        for (int32_t c = 1; c < q; ++c) r0 -= uk[c] / uJ * dk[c];
+        r0 /= uJ;
+        const double coef = (r0 * uJ + dk[0]) / (1.0 + uk[0] / uJ);
+        double n1 = 0.0;
+        for (int32_t c = 1; c < q; ++c) {
+            const double v = (dk[c] - coef * (uk[c] / uJ)) / uJ;
+            n1 += v * v;
+        }
+        const double den = sqrt(n1) - r0;
+        if (den > 0.0) a = 1.0 / den;
+    }
+    // wave min, then one atomic per wave
+    for (int off = 32; off > 0; off >>= 1) a = fmin(a, __shfl_xor(a, off));
+    if ((threadIdx.x & 63) == 0) atomicMin(amin + 0, (unsigned long long)__double_as_longlong(a));
+}
+
+__global__ void reset_steps_kernel(unsigned long long *amin) {
+    if (threadIdx.x < 4) amin[threadIdx.x] = (unsigned long long)__double_as_longlong(INFINITY);
+}
+
+// lambda_min per cone (orthant u_i, SOC u0 - |u1|), reduced as max(-lambda_min)
+__global__ void __launch_bounds__(256) lmin_kernel(int32_t l, int32_t nsoc, const int32_t *__restrict__ soc_off,
+                                                   const double *__restrict__ u, double *__restrict__ partials) {
+    const int32_t t = blockIdx.x * 256 + threadIdx.x;
+    double v = -INFINITY;
+    if (t < l) {
+        v = -u[t];
+    } else if (t - l < nsoc) {
+        const int32_t k = t - l;
+        const int32_t off = soc_off[k], q = soc_off[k + 1] - off;
+        double n1 = 0.0;
+        for (int32_t a = 1; a < q; ++a) n1 += u[off + a] * u[off + a];
+        v = -(u[off] - sqrt(n1));
+    }
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    __shared__ double sh[4];
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) partials[blockIdx.x] = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+}
+
+__global__ void finish_max(const double *__restrict__ partials, int32_t nblk, double *__restrict__ out) {
+    double v = -INFINITY;
+    for (int32_t b = 0; b < nblk; ++b) v = fmax(v, partials[b]);
+    *out = v;
+}
+
+// u += c e
+__global__ void add_e_kernel(int32_t l, int32_t nsoc, const int32_t *__restrict__ soc_off, double c,
+                             double *__restrict__ u) {
+    const int32_t t = blockIdx.x * 256 + threadIdx.x;
+    if (t < l) u[t] += c;
+    else if (t - l < nsoc) u[soc_off[t - l]] += c;
+}
+
+static inline unsigned cone_grid(qg_handle *h) {
+    const int64_t units = (int64_t)h->pp.l + h->pp.nsoc;
+    return (unsigned)std::max<int64_t>(1, (units + 255) / 256);
+}
+
+int launch_scaling(qg_handle *h, const double *s, const double *z, double *lam, int block) {
+    Device &d = h->d;
+    scaling_kernel<<<cone_grid(h), 256, 0, h->stream>>>(h->pp.l, h->pp.nsoc, d.soc_off.p, d.blk_off.p,
+                                                         d.blk33.p, s, z, d.w.p, d.wbar.p, d.beta.p, lam,
+                                                         d.kval.p, block);
+    QG_HIP(h, hipGetLastError());
+    return QG_OK;
+}
+
+int launch_cone_op(qg_handle *h, int op, const double *u, const double *v, double *out) {
+    Device &d = h->d;
+    cone_op_kernel<<<cone_grid(h), 256, 0, h->stream>>>(op, h->pp.l, h->pp.nsoc, d.soc_off.p, d.w.p, d.wbar.p,
+                                                         d.beta.p, u, v, out);
+    QG_HIP(h, hipGetLastError());
+    return QG_OK;
+}
+
+int launch_ds_from_dz(qg_handle *h, const double *tvec, double tsign, const double *dz, double *ds) {
+    Device &d = h->d;
+    ds_kernel<<<cone_grid(h), 256, 0, h->stream>>>(h->pp.l, h->pp.nsoc, d.soc_off.p, d.w.p, d.wbar.p, d.beta.p,
+                                                    tvec, tsign, dz, ds);
+    QG_HIP(h, hipGetLastError());
+    return QG_OK;
+}
+
+int launch_corrector(qg_handle *h, const double *dsa, const double *dza, double sigma_mu,
+                     const double *alpha_aff_dev, double mu, double *t) {
+    (void)alpha_aff_dev;
+    Device &d = h->d;
+    corrector_kernel<<<cone_grid(h), 256, 0, h->stream>>>(h->pp.l, h->pp.nsoc, d.soc_off.p, d.w.p, d.wbar.p,
+                                                           d.beta.p, d.lam.p, dsa, dza, d.amin.p, mu, sigma_mu,
+                                                           t, d.alpha.p);
+    QG_HIP(h, hipGetLastError());
+    return QG_OK;
+}
+
+// u <- u + (1 + a) e with a = -min_k lambda_min(u_k), when a >= 0
+int launch_shift_interior(qg_handle *h, double *u) {
+    Device &d = h->d;
+    const unsigned g = cone_grid(h);
+    lmin_kernel<<<g, 256, 0, h->stream>>>(h->pp.l, h->pp.nsoc, d.soc_off.p, u, d.partials.p);
+    finish_max<<<1, 1, 0, h->stream>>>(d.partials.p, (int32_t)g, d.scal.p + NSCAL + 2);
+    double a = 0.0;
+    QG_HIP(h, hipMemcpyAsync(&a, d.scal.p + NSCAL + 2, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    QG_HIP(h, hipStreamSynchronize(h->stream));
+    if (h->pp.l + h->pp.nsoc == 0 || a < 0.0) return QG_OK;
+    add_e_kernel<<<g, 256, 0, h->stream>>>(h->pp.l, h->pp.nsoc, d.soc_off.p, 1.0 + a, u);
+    QG_HIP(h, hipGetLastError());
+    return QG_OK;
+}
+
+int launch_identity_vec(qg_handle *h, double *u) {
+    Device &d = h->d;
+    int rc = launch_fill(h, h->m, 0.0, u);
+    if (rc) return rc;
+    add_e_kernel<<<cone_grid(h), 256, 0, h->stream>>>(h->pp.l, h->pp.nsoc, d.soc_off.p, 1.0, u);
+    QG_HIP(h, hipGetLastError());
+    return QG_OK;
+}
+
+int launch_reset_steps(qg_handle *h) {
+    reset_steps_kernel<<<1, 64, 0, h->stream>>>(h->d.amin.p);
+    QG_HIP(h, hipGetLastError());
+    return QG_OK;
+}
+
+int launch_step_min(qg_handle *h, const double *u, const double *du, int slot) {
+    Device &d = h->d;
+    step_kernel<<<cone_grid(h), 256, 0, h->stream>>>(h->pp.l, h->pp.nsoc, d.soc_off.p, u, du, d.amin.p + slot);
+    QG_HIP(h, hipGetLastError());
+    return QG_OK;
+}
+
+int launch_max_step(qg_handle *h, const double *u, const double *du, int slot) {
+    return launch_step_min(h, u, du, slot);
+}
+
+}  // namespace qg

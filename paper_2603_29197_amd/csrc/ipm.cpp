@@ -1,0 +1,270 @@
+// Primal-dual interior-point loop for problem (1), all numeric work on the
+// device (paper Sec. 2.3); the host keeps only the scalars it needs to
+// decide (stopping test, precision switch, refinement test).
+//
+// Method (our reading of the cone-QP method the paper's solver implements:
+// Mehrotra predictor-corrector with Nesterov-Todd scaling):
+//   init: factor K with W = I, solve K [x; y; z] = [-c; b; h], s = h - Gx,
+//         shift s and z into the interior;
+//   iterate: residuals and stopping test; NT scaling and the (3,3) block;
+//   one factorization; affine solve K d = [-r_x; -r_y; -r_z + s],
+//   ds_a = -s - W'W dz_a; alpha_a, sigma = (1 - alpha_a)^3; corrector
+//   t = W'(lam \ (-lam o lam - (W^-T ds_a) o (W dz_a) + sigma mu e)),
+//   K d = [-r_x; -r_y; -r_z - t], ds = t - W'W dz; alpha =
+//   min(1, 0.99 max step); update.
+// Precision (FP32_IR): FP32 factors with FP64 refinement while the scaled
+// gap |s'z| / max(1, min(|pobj|, |dobj|)) >= switch_gap; FP64 factors from
+// then on, and for the rest of the iteration whenever refinement with an
+// FP32 factor fails its test.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <vector>
+
+#include "vec.hpp"
+
+namespace qg {
+
+namespace {
+
+struct Events {
+    hipEvent_t e[8] = {};
+    bool ok = false;
+    void create() {
+        ok = true;
+        for (auto &x : e) if (hipEventCreate(&x) != hipSuccess) ok = false;
+    }
+    void destroy() {
+        for (auto &x : e) if (x) (void)hipEventDestroy(x);
+    }
+};
+
+float elapsed(hipEvent_t a, hipEvent_t b) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.f;
+    return ms;
+}
+
+double median(std::vector<double> v) {
+    if (v.empty()) return 0.0;
+    std::sort(v.begin(), v.end());
+    const size_t n = v.size();
+    return n % 2 ? v[n / 2] : 0.5 * (v[n / 2 - 1] + v[n / 2]);
+}
+
+struct Scalars {
+    double pres, dres, gap, pobj, dobj, sz;
+    bool ok;
+};
+
+Scalars stop_test(qg_handle *h, const double *sc, double ea, double er) {
+    Scalars r;
+    r.pres = std::max(sc[S_RY], sc[S_RZ]);
+    r.dres = sc[S_RX];
+    r.sz = sc[S_SZ];
+    r.gap = std::fabs(sc[S_SZ]);
+    r.pobj = 0.5 * sc[S_XPX] + sc[S_CX];
+    r.dobj = -0.5 * sc[S_XPX] - sc[S_BY] - sc[S_HZ];
+    const double pscale = std::max({sc[S_AX], sc[S_B], sc[S_GX], sc[S_H], sc[S_S]});
+    const double dscale = std::max({sc[S_PX], sc[S_ATY], sc[S_GTZ], sc[S_C]});
+    const double gscale = std::max(1.0, std::min(std::fabs(r.pobj), std::fabs(r.dobj)));
+    r.ok = r.pres <= ea + er * pscale && r.dres <= ea + er * dscale && r.gap <= ea + er * gscale;
+    (void)h;
+    return r;
+}
+
+}  // namespace
+
+// One refined solve; in FP32 mode a failed refinement test is reported.
+static int solve_with(qg_handle *h, const double *rhs, double *x, int prec, int *ir_total, bool *failed,
+                      Events &ev, double *ms) {
+    int steps = 0;
+    bool ok = true;
+    const int ir_max = prec == QG_FP32_IR ? h->st.ir_max32 : h->st.ir_max;
+    (void)hipEventRecord(ev.e[4], h->stream);
+    int rc = refined_solve(h, rhs, x, prec, ir_max, &steps, prec == QG_FP32_IR ? &ok : nullptr);
+    if (rc) return rc;
+    (void)hipEventRecord(ev.e[5], h->stream);
+    *ir_total += steps;
+    *failed = !ok;
+    *ms += elapsed(ev.e[4], ev.e[5]);
+    return QG_OK;
+}
+
+int ipm_solve(qg_handle *h, double *xo, double *so, double *yo, double *zo, qg_info *info) {
+    const auto t_start = std::chrono::steady_clock::now();
+    const qg_settings &st = h->st;
+    Device &d = h->d;
+    const int32_t n = h->n, p = h->p, m = h->m, N = h->N;
+    const int nu = h->pp.l + h->pp.nsoc;
+    Events ev;
+    ev.create();
+    int rc = QG_OK;
+    int ir_total = 0, nreg_total = 0, nfactor = 0, nsolve = 0, switch_iter = -1;
+    double ms_factor = 0, ms_solve = 0, ms_cone = 0;
+    std::vector<double> step_ms, step32, step64;
+    bool fp64_only = st.precision != QG_FP32_IR;
+    double scal[NSCAL];
+    Scalars sr{};
+    int status = QG_MAX_ITER, it = 0;
+    h->solved = false;
+    h->final_factor = false;
+    auto fail = [&](int code) { ev.destroy(); return code; };
+
+    // ---- initial point: W = I ----
+    int prec = fp64_only ? QG_FP64 : QG_FP32_IR;
+    if ((rc = launch_identity_vec(h, d.t.p))) return fail(rc);
+    if ((rc = launch_scaling(h, d.t.p, d.t.p, nullptr, 0))) return fail(rc);
+    (void)hipEventRecord(ev.e[2], h->stream);
+    if ((rc = launch_factor(h, prec))) return fail(rc);
+    (void)hipEventRecord(ev.e[3], h->stream);
+    ++nfactor;
+    {
+        // rhs = [-c; b; h]
+        if ((rc = launch_scale_copy(h, n, -1.0, d.c.p, d.rhs.p))) return fail(rc);
+        QG_HIP(h, hipMemcpyAsync(d.rhs.p + n, d.b.p, sizeof(double) * p, hipMemcpyDeviceToDevice, h->stream));
+        QG_HIP(h, hipMemcpyAsync(d.rhs.p + n + p, d.h.p, sizeof(double) * m, hipMemcpyDeviceToDevice, h->stream));
+        bool failed = false;
+        if ((rc = solve_with(h, d.rhs.p, d.sol.p, prec, &ir_total, &failed, ev, &ms_solve))) return fail(rc);
+        ms_factor += elapsed(ev.e[2], ev.e[3]);
+        if (failed && prec == QG_FP32_IR) {
+            prec = QG_FP64;
+            if ((rc = launch_factor(h, prec))) return fail(rc);
+            ++nfactor;
+            if ((rc = solve_with(h, d.rhs.p, d.sol.p, prec, &ir_total, &failed, ev, &ms_solve))) return fail(rc);
+        }
+        ++nsolve;
+        QG_HIP(h, hipMemcpyAsync(d.x.p, d.sol.p, sizeof(double) * n, hipMemcpyDeviceToDevice, h->stream));
+        QG_HIP(h, hipMemcpyAsync(d.y.p, d.sol.p + n, sizeof(double) * p, hipMemcpyDeviceToDevice, h->stream));
+        QG_HIP(h, hipMemcpyAsync(d.z.p, d.sol.p + n + p, sizeof(double) * m, hipMemcpyDeviceToDevice, h->stream));
+        // s = h - G x: residual with s = 0 gives rz = Gx - h
+        if ((rc = launch_fill(h, m, 0.0, d.s.p))) return fail(rc);
+        if ((rc = launch_residual(h, d.x.p, d.y.p, d.z.p, d.s.p, scal))) return fail(rc);
+        if ((rc = launch_scale_copy(h, m, -1.0, d.rz.p, d.s.p))) return fail(rc);
+        if ((rc = launch_shift_interior(h, d.s.p))) return fail(rc);
+        if ((rc = launch_shift_interior(h, d.z.p))) return fail(rc);
+    }
+    double *dvec = d.sol.p;               // Newton direction (N)
+    const double *dz_of = dvec + n + p;
+    while (true) {
+        (void)hipEventRecord(ev.e[0], h->stream);
+        if ((rc = launch_residual(h, d.x.p, d.y.p, d.z.p, d.s.p, scal))) return fail(rc);
+        sr = stop_test(h, scal, st.eps_abs, st.eps_rel);
+        if (st.verbose)
+            fprintf(stderr, "it %3d pobj %+.8e dobj %+.8e pres %.2e dres %.2e gap %.2e %s\n", it, sr.pobj,
+                    sr.dobj, sr.pres, sr.dres, sr.gap, prec == QG_FP32_IR ? "fp32" : "fp64");
+        if (!std::isfinite(sr.pres) || !std::isfinite(sr.dres) || !std::isfinite(sr.gap)) {
+            status = QG_NUMERICAL_ERROR;
+            break;
+        }
+        if (sr.ok) { status = QG_SOLVED; break; }
+        if (it >= st.max_iter) {
+            Scalars s5 = stop_test(h, scal, st.eps_inacc, st.eps_inacc);
+            status = s5.ok ? QG_SOLVED_INACCURATE : QG_MAX_ITER;
+            break;
+        }
+        const double mu = nu > 0 ? sr.sz / nu : 0.0;
+        const double gscaled = sr.gap / std::max(1.0, std::min(std::fabs(sr.pobj), std::fabs(sr.dobj)));
+        if (!fp64_only && gscaled < st.switch_gap) fp64_only = true;
+        prec = fp64_only ? QG_FP64 : QG_FP32_IR;
+        if (prec == QG_FP64 && switch_iter < 0 && st.precision == QG_FP32_IR) switch_iter = it;
+        // scaling + (3,3) block
+        (void)hipEventRecord(ev.e[6], h->stream);
+        if ((rc = launch_scaling(h, d.s.p, d.z.p, d.lam.p, 0))) return fail(rc);
+        (void)hipEventRecord(ev.e[7], h->stream);
+        (void)hipEventRecord(ev.e[2], h->stream);
+        if ((rc = launch_factor(h, prec))) return fail(rc);
+        (void)hipEventRecord(ev.e[3], h->stream);
+        ++nfactor;
+        // affine direction
+        if ((rc = launch_build_rhs(h, d.s.p, 1.0, d.rhs.p))) return fail(rc);
+        bool failed = false;
+        if ((rc = solve_with(h, d.rhs.p, dvec, prec, &ir_total, &failed, ev, &ms_solve))) return fail(rc);
+        ++nsolve;
+        ms_factor += elapsed(ev.e[2], ev.e[3]);
+        ms_cone += elapsed(ev.e[6], ev.e[7]);
+        if (failed && prec == QG_FP32_IR) {
+            // refinement with the FP32 factor failed: FP64 from here on
+            fp64_only = true;
+            prec = QG_FP64;
+            if (switch_iter < 0) switch_iter = it;
+            (void)hipEventRecord(ev.e[2], h->stream);
+            if ((rc = launch_factor(h, prec))) return fail(rc);
+            (void)hipEventRecord(ev.e[3], h->stream);
+            ++nfactor;
+            if ((rc = solve_with(h, d.rhs.p, dvec, prec, &ir_total, &failed, ev, &ms_solve))) return fail(rc);
+            ms_factor += elapsed(ev.e[2], ev.e[3]);
+        }
+        int nr = 0;
+        if ((rc = read_nreg(h, &nr))) return fail(rc);
+        nreg_total += nr;
+        (void)hipEventRecord(ev.e[6], h->stream);
+        if ((rc = launch_ds_from_dz(h, d.s.p, -1.0, dz_of, d.dsa.p))) return fail(rc);
+        if ((rc = launch_reset_steps(h))) return fail(rc);
+        if ((rc = launch_step_min(h, d.s.p, d.dsa.p, 0))) return fail(rc);
+        if ((rc = launch_step_min(h, d.z.p, dz_of, 1))) return fail(rc);
+        // corrector (sigma from the affine step length on the device)
+        if ((rc = launch_corrector(h, d.dsa.p, dz_of, -1.0, nullptr, mu, d.t.p))) return fail(rc);
+        if ((rc = launch_build_rhs(h, d.t.p, -1.0, d.rhs.p))) return fail(rc);
+        (void)hipEventRecord(ev.e[7], h->stream);
+        ms_cone += 0.0;
+        if ((rc = solve_with(h, d.rhs.p, dvec, prec, &ir_total, &failed, ev, &ms_solve))) return fail(rc);
+        ++nsolve;
+        ms_cone += elapsed(ev.e[6], ev.e[7]);
+        (void)hipEventRecord(ev.e[6], h->stream);
+        if ((rc = launch_ds_from_dz(h, d.t.p, 1.0, dz_of, d.ds.p))) return fail(rc);
+        if ((rc = launch_step_min(h, d.s.p, d.ds.p, 2))) return fail(rc);
+        if ((rc = launch_step_min(h, d.z.p, dz_of, 3))) return fail(rc);
+        if ((rc = launch_update(h, dvec, d.ds.p, st.step_frac, d.alpha.p + 1))) return fail(rc);
+        (void)hipEventRecord(ev.e[7], h->stream);
+        (void)hipEventRecord(ev.e[1], h->stream);
+        QG_HIP(h, hipEventSynchronize(ev.e[1]));
+        ms_cone += elapsed(ev.e[6], ev.e[7]);
+        const double sm = elapsed(ev.e[0], ev.e[1]);
+        step_ms.push_back(sm);
+        (prec == QG_FP32_IR ? step32 : step64).push_back(sm);
+        ++it;
+    }
+    // outputs
+    if (xo) QG_HIP(h, hipMemcpyAsync(xo, d.x.p, sizeof(double) * n, hipMemcpyDeviceToDevice, h->stream));
+    if (so) QG_HIP(h, hipMemcpyAsync(so, d.s.p, sizeof(double) * m, hipMemcpyDeviceToDevice, h->stream));
+    if (yo) QG_HIP(h, hipMemcpyAsync(yo, d.y.p, sizeof(double) * p, hipMemcpyDeviceToDevice, h->stream));
+    if (zo) QG_HIP(h, hipMemcpyAsync(zo, d.z.p, sizeof(double) * m, hipMemcpyDeviceToDevice, h->stream));
+    h->solved = (status == QG_SOLVED || status == QG_SOLVED_INACCURATE);
+    h->last_status = status;
+    // derivative system at the final iterate (FP64), kept for qg_backward
+    if (h->solved && st.differentiable) {
+        if ((rc = launch_scaling(h, d.s.p, d.z.p, nullptr, 1))) return fail(rc);
+        if ((rc = launch_factor(h, QG_FP64))) return fail(rc);
+        ++nfactor;
+        h->final_factor = true;
+    }
+    QG_HIP(h, hipStreamSynchronize(h->stream));
+    ev.destroy();
+    if (info) {
+        info->status = status;
+        info->iters = it;
+        info->switch_iter = switch_iter;
+        info->ir_steps = ir_total;
+        info->nreg = nreg_total;
+        info->nfactor = nfactor;
+        info->nsolve = nsolve;
+        info->pobj = sr.pobj; info->dobj = sr.dobj;
+        info->pres = sr.pres; info->dres = sr.dres; info->gap = sr.gap;
+        info->ms_setup = h->ms_setup;
+        info->ms_analyze = h->ms_analyze;
+        info->ms_solve = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+        info->ms_factor = ms_factor;
+        info->ms_trisolve = ms_solve;
+        info->ms_cone = ms_cone;
+        info->ms_step_median = median(step_ms);
+        info->ms_step_median_fp32 = median(step32);
+        info->ms_step_median_fp64 = median(step64);
+        info->nnz_L = h->sym.nnz_L;
+        info->factor_flops = h->sym.flops;
+    }
+    return QG_OK;
+}
+
+}  // namespace qg

@@ -1,0 +1,290 @@
+// Builds the supernodal multifrontal plan from the analysis: front layout,
+// per-column assembly lists (K entries and child contributions through
+// relative indices), level schedule, and uploads it with the static data.
+#include <algorithm>
+#include <cstring>
+
+#include "kernels.hpp"
+#include "solver.hpp"
+
+namespace qg {
+
+int hip_fail(qg_handle *h, hipError_t e) {
+    if (h) h->last_hip = (int)e;
+    (void)hipGetLastError();
+    return e == hipErrorOutOfMemory ? QG_ERR_OOM : QG_ERR_HIP;
+}
+
+template <typename T>
+int dalloc(qg_handle *h, DBuf<T> &b, size_t n) {
+    if (b.p) { (void)hipFree(b.p); b.p = nullptr; b.n = 0; }
+    if (n == 0) n = 1;
+    hipError_t e = hipMalloc((void **)&b.p, n * sizeof(T));
+    if (e != hipSuccess) { b.p = nullptr; return hip_fail(h, e); }
+    b.n = n;
+    return QG_OK;
+}
+
+template <typename T>
+int dupload(qg_handle *h, DBuf<T> &b, const std::vector<T> &v) {
+    int rc = dalloc(h, b, v.size());
+    if (rc) return rc;
+    if (!v.empty())
+        QG_HIP(h, hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, h->stream));
+    return QG_OK;
+}
+
+template int dalloc<double>(qg_handle *, DBuf<double> &, size_t);
+template int dalloc<float>(qg_handle *, DBuf<float> &, size_t);
+template int dalloc<int32_t>(qg_handle *, DBuf<int32_t> &, size_t);
+template int dalloc<int64_t>(qg_handle *, DBuf<int64_t> &, size_t);
+template int dalloc<int8_t>(qg_handle *, DBuf<int8_t> &, size_t);
+template int dalloc<unsigned long long>(qg_handle *, DBuf<unsigned long long> &, size_t);
+template int dupload<double>(qg_handle *, DBuf<double> &, const std::vector<double> &);
+template int dupload<int32_t>(qg_handle *, DBuf<int32_t> &, const std::vector<int32_t> &);
+template int dupload<int64_t>(qg_handle *, DBuf<int64_t> &, const std::vector<int64_t> &);
+template int dupload<int8_t>(qg_handle *, DBuf<int8_t> &, const std::vector<int8_t> &);
+
+template <typename T>
+static void dfree(DBuf<T> &b) {
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.n = 0;
+}
+
+void dfree_all(qg_handle *h) {
+    Device &d = h->d;
+    dfree(d.kval); dfree(d.blk33); dfree(d.blk_off); dfree(d.soc_off); dfree(d.kr_ptr);
+    dfree(d.kr_col); dfree(d.kr_val); dfree(d.c); dfree(d.b); dfree(d.h); dfree(d.Pp); dfree(d.Pi);
+    dfree(d.perm); dfree(d.iperm);
+    dfree(d.sn_first); dfree(d.sn_rows); dfree(d.task_sn); dfree(d.task_col); dfree(d.asm_row);
+    dfree(d.ctb_child); dfree(d.ctb_col); dfree(d.rel); dfree(d.ch_ptr); dfree(d.ch_list);
+    dfree(d.lvl_small_sn); dfree(d.sn_rptr); dfree(d.fr_off); dfree(d.task_ptr); dfree(d.asm_ptr);
+    dfree(d.asm_src); dfree(d.ctb_ptr); dfree(d.rel_ptr); dfree(d.uv_off); dfree(d.reg_sign);
+    dfree(d.front64); dfree(d.front32); dfree(d.uvec); dfree(d.dinv64); dfree(d.dinv32);
+    dfree(d.vbuf); dfree(d.col2sn); dfree(d.nreg);
+    dfree(d.x); dfree(d.y); dfree(d.s); dfree(d.z); dfree(d.rx); dfree(d.ry); dfree(d.rz);
+    dfree(d.kx); dfree(d.rhs); dfree(d.sol); dfree(d.res); dfree(d.corr); dfree(d.xp);
+    dfree(d.dsa); dfree(d.ds); dfree(d.t); dfree(d.lam); dfree(d.w); dfree(d.wbar); dfree(d.beta);
+    dfree(d.scal); dfree(d.amin); dfree(d.partials); dfree(d.zcone); dfree(d.alpha);
+}
+
+int build_plan(qg_handle *h) {
+    const Symbolic &sym = h->sym;
+    const KktPattern &kp = h->kp;
+    Plan &pl = h->plan;
+    const int32_t N = sym.N;
+    const int32_t ns = (int32_t)sym.super_ptr.size() - 1;
+    pl.ns = ns;
+    pl.nlevels = sym.nlevels;
+    pl.sn_first = sym.super_ptr;
+    pl.sn_rptr = sym.rows_ptr;
+    pl.sn_rows = sym.rows;
+    pl.fr_off.assign((size_t)ns + 1, 0);
+    pl.uv_off.assign((size_t)ns + 1, 0);
+    pl.max_r = 0;
+    for (int32_t s = 0; s < ns; ++s) {
+        const int64_t r = pl.sn_rptr[s + 1] - pl.sn_rptr[s];
+        const int64_t k = pl.sn_first[s + 1] - pl.sn_first[s];
+        pl.fr_off[s + 1] = pl.fr_off[s] + r * r;
+        pl.uv_off[s + 1] = pl.uv_off[s] + (r - k);
+        pl.max_r = std::max<int32_t>(pl.max_r, (int32_t)r);
+    }
+    pl.front_total = pl.fr_off[ns];
+    pl.uv_total = pl.uv_off[ns];
+    pl.dinv_off.assign((size_t)ns + 1, 0);
+    for (int32_t s = 0; s < ns; ++s) {
+        const int64_t r = pl.sn_rptr[s + 1] - pl.sn_rptr[s];
+        const int64_t k = pl.sn_first[s + 1] - pl.sn_first[s];
+        pl.dinv_off[s + 1] = pl.dinv_off[s] + (r > SMALL_R ? ((k + NB - 1) / NB) * NB * NB : 0);
+    }
+    pl.dinv_total = pl.dinv_off[ns];
+    // levels
+    pl.lvl_ptr.assign((size_t)pl.nlevels + 1, 0);
+    for (int32_t s = 0; s < ns; ++s) pl.lvl_ptr[sym.sn_level[s] + 1]++;
+    for (int32_t L = 0; L < pl.nlevels; ++L) pl.lvl_ptr[L + 1] += pl.lvl_ptr[L];
+    pl.lvl_sn.assign(ns, 0);
+    {
+        std::vector<int32_t> fill(pl.lvl_ptr.begin(), pl.lvl_ptr.end() - 1);
+        for (int32_t s = 0; s < ns; ++s) pl.lvl_sn[fill[sym.sn_level[s]]++] = s;
+    }
+    pl.lvl_small_ptr.assign((size_t)pl.nlevels + 1, 0);
+    pl.lvl_large_ptr.assign((size_t)pl.nlevels + 1, 0);
+    pl.lvl_small_sn.clear();
+    pl.lvl_large_sn.clear();
+    for (int32_t L = 0; L < pl.nlevels; ++L) {
+        for (int32_t t = pl.lvl_ptr[L]; t < pl.lvl_ptr[L + 1]; ++t) {
+            const int32_t s = pl.lvl_sn[t];
+            const int64_t r = pl.sn_rptr[s + 1] - pl.sn_rptr[s];
+            if (r <= SMALL_R) pl.lvl_small_sn.push_back(s);
+            else pl.lvl_large_sn.push_back(s);
+        }
+        pl.lvl_small_ptr[L + 1] = (int32_t)pl.lvl_small_sn.size();
+        pl.lvl_large_ptr[L + 1] = (int32_t)pl.lvl_large_sn.size();
+    }
+    // children (increasing index)
+    pl.ch_ptr.assign((size_t)ns + 1, 0);
+    for (int32_t s = 0; s < ns; ++s) if (sym.sn_parent[s] >= 0) pl.ch_ptr[sym.sn_parent[s] + 1]++;
+    for (int32_t s = 0; s < ns; ++s) pl.ch_ptr[s + 1] += pl.ch_ptr[s];
+    pl.ch_list.assign(pl.ch_ptr[ns], 0);
+    {
+        std::vector<int32_t> fill(pl.ch_ptr.begin(), pl.ch_ptr.end() - 1);
+        for (int32_t s = 0; s < ns; ++s)
+            if (sym.sn_parent[s] >= 0) pl.ch_list[fill[sym.sn_parent[s]]++] = s;
+    }
+    // relative indices of each supernode's update rows in its parent's row list
+    pl.rel_ptr.assign((size_t)ns + 1, 0);
+    pl.rel.clear();
+    for (int32_t s = 0; s < ns; ++s) {
+        const int32_t k = pl.sn_first[s + 1] - pl.sn_first[s];
+        const int32_t ps = sym.sn_parent[s];
+        const int32_t *rs = pl.sn_rows.data() + pl.sn_rptr[s];
+        const int64_t r = pl.sn_rptr[s + 1] - pl.sn_rptr[s];
+        if (ps >= 0) {
+            const int32_t *rp = pl.sn_rows.data() + pl.sn_rptr[ps];
+            const int32_t *re = pl.sn_rows.data() + pl.sn_rptr[ps + 1];
+            const int32_t *cur = rp;
+            for (int64_t i = k; i < r; ++i) {
+                cur = std::lower_bound(cur, re, rs[i]);
+                if (cur == re || *cur != rs[i]) return QG_ERR_PATTERN;   // inconsistent analysis
+                pl.rel.push_back((int32_t)(cur - rp));
+            }
+        } else if (r != k) {
+            return QG_ERR_PATTERN;
+        }
+        pl.rel_ptr[s + 1] = (int64_t)pl.rel.size();
+    }
+    // column tasks, level by level
+    std::vector<int64_t> task_base(ns, 0);
+    pl.task_ptr.assign((size_t)pl.nlevels + 1, 0);
+    pl.task_sn.clear();
+    pl.task_col.clear();
+    for (int32_t L = 0; L < pl.nlevels; ++L) {
+        for (int32_t t = pl.lvl_ptr[L]; t < pl.lvl_ptr[L + 1]; ++t) {
+            const int32_t s = pl.lvl_sn[t];
+            const int32_t r = (int32_t)(pl.sn_rptr[s + 1] - pl.sn_rptr[s]);
+            task_base[s] = (int64_t)pl.task_sn.size();
+            for (int32_t j = 0; j < r; ++j) { pl.task_sn.push_back(s); pl.task_col.push_back(j); }
+        }
+        pl.task_ptr[L + 1] = (int64_t)pl.task_sn.size();
+    }
+    const int64_t ntask = (int64_t)pl.task_sn.size();
+    // K entries per task
+    std::vector<int32_t> col2sn(N);
+    for (int32_t s = 0; s < ns; ++s)
+        for (int32_t c = pl.sn_first[s]; c < pl.sn_first[s + 1]; ++c) col2sn[c] = s;
+    const int64_t nnzK = (int64_t)kp.Ki.size();
+    std::vector<int64_t> ent_task(nnzK);
+    std::vector<int32_t> ent_row(nnzK);
+    pl.asm_ptr.assign((size_t)ntask + 1, 0);
+    for (int32_t j = 0; j < N; ++j)
+        for (int64_t t = kp.Kp[j]; t < kp.Kp[j + 1]; ++t) {
+            const int32_t a = sym.iperm[kp.Ki[t]], b = sym.iperm[j];
+            const int32_t c = std::min(a, b), r = std::max(a, b);
+            const int32_t s = col2sn[c];
+            const int32_t *rs = pl.sn_rows.data() + pl.sn_rptr[s];
+            const int32_t *re = pl.sn_rows.data() + pl.sn_rptr[s + 1];
+            const int32_t *it = std::lower_bound(rs, re, r);
+            if (it == re || *it != r) return QG_ERR_PATTERN;
+            ent_task[t] = task_base[s] + (c - pl.sn_first[s]);
+            ent_row[t] = (int32_t)(it - rs);
+            pl.asm_ptr[ent_task[t] + 1]++;
+        }
+    for (int64_t t = 0; t < ntask; ++t) pl.asm_ptr[t + 1] += pl.asm_ptr[t];
+    pl.asm_src.assign(nnzK, 0);
+    pl.asm_row.assign(nnzK, 0);
+    {
+        std::vector<int64_t> fill(pl.asm_ptr.begin(), pl.asm_ptr.end() - 1);
+        for (int64_t t = 0; t < nnzK; ++t) {
+            const int64_t d = fill[ent_task[t]]++;
+            pl.asm_src[d] = t;
+            pl.asm_row[d] = ent_row[t];
+        }
+    }
+    // child contributions per task, in child order
+    pl.ctb_ptr.assign((size_t)ntask + 1, 0);
+    for (int32_t s = 0; s < ns; ++s)
+        for (int32_t u = pl.ch_ptr[s]; u < pl.ch_ptr[s + 1]; ++u) {
+            const int32_t c = pl.ch_list[u];
+            for (int64_t i = pl.rel_ptr[c]; i < pl.rel_ptr[c + 1]; ++i)
+                pl.ctb_ptr[task_base[s] + pl.rel[i] + 1]++;
+        }
+    for (int64_t t = 0; t < ntask; ++t) pl.ctb_ptr[t + 1] += pl.ctb_ptr[t];
+    pl.ctb_child.assign(pl.ctb_ptr[ntask], 0);
+    pl.ctb_col.assign(pl.ctb_ptr[ntask], 0);
+    {
+        std::vector<int64_t> fill(pl.ctb_ptr.begin(), pl.ctb_ptr.end() - 1);
+        for (int32_t s = 0; s < ns; ++s)
+            for (int32_t u = pl.ch_ptr[s]; u < pl.ch_ptr[s + 1]; ++u) {
+                const int32_t c = pl.ch_list[u];
+                for (int64_t i = pl.rel_ptr[c]; i < pl.rel_ptr[c + 1]; ++i) {
+                    const int64_t d = fill[task_base[s] + pl.rel[i]]++;
+                    pl.ctb_child[d] = c;
+                    pl.ctb_col[d] = (int32_t)(i - pl.rel_ptr[c]);
+                }
+            }
+    }
+    // kind of each permuted column: 0 primal x, 1 equality y, 2 cone z
+    pl.reg_sign.assign(N, 0);
+    for (int32_t c = 0; c < N; ++c) {
+        const int32_t o = sym.perm[c];
+        pl.reg_sign[c] = (int8_t)(o < h->n ? 0 : (o < h->n + h->p ? 1 : 2));
+    }
+    return QG_OK;
+}
+
+int upload_static_values(qg_handle *h) {
+    const ProblemPattern &pp = h->pp;
+    const KktPattern &kp = h->kp;
+    const int32_t n = h->n, p = h->p, N = h->N;
+    // K upper values without the (3,3) block (zeros there)
+    h->kval_static.assign(kp.Ki.size(), 0.0);
+    for (size_t t = 0; t < pp.P.val.size(); ++t) h->kval_static[kp.posP[t]] = pp.P.val[t];
+    for (size_t t = 0; t < pp.A.val.size(); ++t) h->kval_static[kp.posA[t]] = pp.A.val[t];
+    for (size_t t = 0; t < pp.G.val.size(); ++t) h->kval_static[kp.posG[t]] = pp.G.val[t];
+    int rc = dupload(h, h->d.kval, h->kval_static);
+    if (rc) return rc;
+    // full symmetric CSR of the static part (both triangles; the (3,3) block excluded)
+    std::vector<int64_t> rp((size_t)N + 1, 0);
+    auto in33 = [&](int32_t i, int32_t j) { return i >= n + p && j >= n + p; };
+    for (int32_t j = 0; j < N; ++j)
+        for (int64_t t = kp.Kp[j]; t < kp.Kp[j + 1]; ++t) {
+            const int32_t i = kp.Ki[t];
+            if (in33(i, j)) continue;
+            rp[i + 1]++;
+            if (i != j) rp[j + 1]++;
+        }
+    for (int32_t i = 0; i < N; ++i) rp[i + 1] += rp[i];
+    std::vector<int32_t> rc_(rp[N]);
+    std::vector<double> rv(rp[N]);
+    {
+        std::vector<int64_t> fill(rp.begin(), rp.end() - 1);
+        // rows receive entries in increasing column order: first the upper
+        // part of row i (columns j > i come from columns j of the upper CSC),
+        // so build per row and sort
+        for (int32_t j = 0; j < N; ++j)
+            for (int64_t t = kp.Kp[j]; t < kp.Kp[j + 1]; ++t) {
+                const int32_t i = kp.Ki[t];
+                if (in33(i, j)) continue;
+                const double v = h->kval_static[t];
+                rc_[fill[i]] = j; rv[fill[i]++] = v;
+                if (i != j) { rc_[fill[j]] = i; rv[fill[j]++] = v; }
+            }
+        std::vector<std::pair<int32_t, double>> tmp;
+        for (int32_t i = 0; i < N; ++i) {
+            tmp.clear();
+            for (int64_t t = rp[i]; t < rp[i + 1]; ++t) tmp.push_back({rc_[t], rv[t]});
+            std::sort(tmp.begin(), tmp.end());
+            for (int64_t t = rp[i]; t < rp[i + 1]; ++t) { rc_[t] = tmp[t - rp[i]].first; rv[t] = tmp[t - rp[i]].second; }
+        }
+    }
+    if ((rc = dupload(h, h->d.kr_ptr, rp))) return rc;
+    if ((rc = dupload(h, h->d.kr_col, rc_))) return rc;
+    if ((rc = dupload(h, h->d.kr_val, rv))) return rc;
+    if ((rc = dupload(h, h->d.c, h->hc))) return rc;
+    if ((rc = dupload(h, h->d.b, h->hb))) return rc;
+    if ((rc = dupload(h, h->d.h, h->hh))) return rc;
+    return QG_OK;
+}
+
+}  // namespace qg

@@ -1,0 +1,163 @@
+// Device solver state behind the C ABI (qg.h): problem data, the
+// supernodal plan derived from the analysis, and every device buffer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "analysis.hpp"
+#include "qg.h"
+
+namespace qg {
+
+// A device allocation owned by the handle.
+template <typename T>
+struct DBuf {
+    T *p = nullptr;
+    size_t n = 0;
+};
+
+// Supernodal multifrontal plan (host copies + device copies).
+//  * every supernode s owns a dense front of r_s x r_s (column-major,
+//    leading dimension r_s) at fr_off[s]; its first k_s columns hold L (unit
+//    diagonal implied, D on the diagonal) after the factorization and its
+//    trailing (r_s-k_s)^2 block the update passed to the parent;
+//  * fronts are assembled column by column: task (s, j) zeroes column j,
+//    scatters the K entries of that column and adds, in child order, every
+//    child column that maps onto it (relative indices);
+//  * small fronts (r_s <= SMALL_R) are factored one workgroup per front in
+//    LDS, level by level; large fronts by a blocked right-looking sequence.
+struct Plan {
+    int32_t ns = 0, nlevels = 0;
+    std::vector<int32_t> sn_first;        // ns + 1
+    std::vector<int64_t> sn_rptr;         // ns + 1 (row lists)
+    std::vector<int32_t> sn_rows;
+    std::vector<int64_t> fr_off;          // ns + 1 (front offsets, elements)
+    std::vector<int32_t> lvl_ptr, lvl_sn; // supernodes by level
+    std::vector<int32_t> lvl_small_ptr, lvl_small_sn;   // small ones by level
+    std::vector<int32_t> lvl_large_ptr, lvl_large_sn;   // large ones by level
+    std::vector<int64_t> task_ptr;        // per level: column tasks (s, j)
+    std::vector<int32_t> task_sn, task_col;
+    std::vector<int64_t> asm_ptr;         // per (s, j) task: K entries of that column
+    std::vector<int64_t> asm_src;         // index into kval
+    std::vector<int32_t> asm_row;         // local row in the front
+    std::vector<int64_t> ctb_ptr;         // per task: child contributions
+    std::vector<int32_t> ctb_child, ctb_col;
+    std::vector<int64_t> rel_ptr;         // per supernode: relative map of its update rows
+    std::vector<int32_t> rel;
+    std::vector<int64_t> uv_off;          // per supernode: offset of its update vector (solves)
+    std::vector<int64_t> dinv_off;        // per supernode: offset of its inverse diagonal blocks
+    int64_t dinv_total = 0;
+    std::vector<int32_t> ch_ptr, ch_list; // children supernodes
+    std::vector<int8_t> reg_sign;         // per permuted column: +1 x, -1 y, 0 z
+    int64_t front_total = 0, uv_total = 0;
+    int32_t max_r = 0;
+};
+
+struct Device {
+    // problem data (original ordering)
+    DBuf<double> kval;          // unregularized K upper values (nnz_K)
+    DBuf<int64_t> blk33;        // positions of (3,3) entries in kval
+    DBuf<int64_t> blk_off;      // per SOC: offset of its entries in blk33 (after the orthant)
+    DBuf<int32_t> soc_off;      // nsoc + 1 row offsets in z
+    DBuf<int64_t> kr_ptr;       // full symmetric CSR of K without the (3,3) block
+    DBuf<int32_t> kr_col;
+    DBuf<double> kr_val;
+    DBuf<double> c, b, h;
+    DBuf<int64_t> Pp; DBuf<int32_t> Pi;   // P upper pattern (for dL/dP)
+    DBuf<int32_t> perm, iperm;
+    // plan
+    DBuf<int32_t> sn_first, sn_rows, task_sn, task_col, asm_row, ctb_child, ctb_col, rel, ch_ptr,
+        ch_list, lvl_small_sn;
+    DBuf<int64_t> sn_rptr, fr_off, task_ptr, asm_ptr, asm_src, ctb_ptr, rel_ptr, uv_off;
+    DBuf<int8_t> reg_sign;
+    DBuf<double> front64;
+    DBuf<float> front32;
+    DBuf<double> uvec;          // update vectors of the triangular solves
+    DBuf<double> dinv64;        // inverses of the NB x NB diagonal blocks of large fronts
+    DBuf<float> dinv32;
+    DBuf<double> vbuf;          // work vector of length max_r (large-front solves)
+    DBuf<int32_t> col2sn;
+    DBuf<int32_t> nreg;         // dynamic regularization counter
+    // iterate and work vectors
+    DBuf<double> x, y, s, z;
+    DBuf<double> rx, ry, rz;    // residuals (rz excludes s)
+    DBuf<double> kx;            // N: K_static * [x;y;z] parts
+    DBuf<double> rhs, sol, res, corr, xp;   // N
+    DBuf<double> dsa, ds, t, lam, w;        // m
+    DBuf<double> wbar, beta;                // SOC scaling
+    DBuf<double> scal;          // reduction scalars
+    DBuf<double> partials;      // per-block reduction partials
+    DBuf<int32_t> zcone;        // per z row: SOC index (-1 on the orthant)
+    DBuf<double> alpha;         // step lengths of the last iteration (affine, combined)
+    DBuf<unsigned long long> amin;          // step-length minima (ordered bits)
+};
+
+// Timing helper around HIP events on the handle's stream.
+struct Timer {
+    hipEvent_t a = nullptr, b = nullptr;
+};
+
+}  // namespace qg
+
+struct qg_handle {
+    qg_settings st;
+    hipStream_t stream = nullptr;
+    int last_hip = 0;
+    int device = 0;
+    qg::ProblemPattern pp;
+    qg::KktPattern kp;
+    qg::Symbolic sym;
+    qg::Plan plan;
+    qg::Device d;
+    std::vector<double> kval_static;   // K upper values without (3,3) entries
+    std::vector<double> hc, hb, hh;    // c, b, h on the host
+    int64_t nnzK = 0;
+    int32_t n = 0, m = 0, p = 0, N = 0;
+    bool solved = false;               // a solve finished (x, s, y, z valid)
+    bool final_factor = false;         // the derivative system is factored (FP64)
+    int last_precision = -1;           // precision of the current factor
+    int last_status = QG_UNSOLVED;
+    double ms_setup = 0, ms_analyze = 0;
+    int64_t small_lds_bytes = 0;
+};
+
+namespace qg {
+
+// error plumbing
+int hip_fail(qg_handle *h, hipError_t e);
+#define QG_HIP(h, call)                                  \
+    do {                                                 \
+        hipError_t e_ = (call);                          \
+        if (e_ != hipSuccess) return qg::hip_fail(h, e_); \
+    } while (0)
+
+template <typename T>
+int dalloc(qg_handle *h, DBuf<T> &b, size_t n);
+template <typename T>
+int dupload(qg_handle *h, DBuf<T> &b, const std::vector<T> &v);
+void dfree_all(qg_handle *h);
+
+int build_plan(qg_handle *h);
+int upload_static_values(qg_handle *h);
+
+// device phases (all enqueue on h->stream)
+int launch_scaling(qg_handle *h, const double *s, const double *z, double *lam, int block);
+int launch_factor(qg_handle *h, int precision);
+int launch_solve(qg_handle *h, const double *rhs, double *x, int precision);
+int refined_solve(qg_handle *h, const double *rhs, double *x, int precision, int ir_max, int *steps,
+                  bool *ok = nullptr);
+int launch_kkt_residual(qg_handle *h, const double *rhs, const double *x, double *res, double *norms);
+int launch_max_step(qg_handle *h, const double *u, const double *du, int slot);
+int launch_cone_op(qg_handle *h, int op, const double *u, const double *v, double *out);
+int launch_corrector(qg_handle *h, const double *dsa, const double *dza, double sigma_mu,
+                     const double *alpha_aff_dev, double mu, double *t);
+int read_nreg(qg_handle *h, int *nreg);
+
+int ipm_solve(qg_handle *h, double *x, double *s, double *y, double *z, qg_info *info);
+int adjoint_backward(qg_handle *h, const double *g, double *dc, double *dh, double *db, double *dP);
+
+}  // namespace qg

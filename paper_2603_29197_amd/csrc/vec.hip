@@ -1,0 +1,264 @@
+// Vector work of the Newton step: KKT residuals of problem (1), the
+// refinement residual against the unregularized KKT matrix of eq. (2),
+// right-hand sides and the iterate update.  Reductions are two-pass (per
+// block partials, then one block in fixed order), so results do not depend
+// on scheduling.
+#include "vec.hpp"
+
+namespace qg {
+
+// Per-block reduction helper: NS slots, each either a sum or a max-abs.
+template <int NS>
+__device__ inline void block_reduce_store(double (&val)[NS], const uint32_t maxmask, double *partials) {
+    __shared__ double sh[NS][4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+        double v = val[q];
+        const bool ismax = (maxmask >> q) & 1u;
+        for (int off = 32; off > 0; off >>= 1) {
+            const double o = __shfl_xor(v, off);
+            v = ismax ? fmax(v, o) : v + o;
+        }
+        if (lane == 0) sh[q][wave] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < NS) {
+        const int q = threadIdx.x;
+        const bool ismax = (maxmask >> q) & 1u;
+        double v = sh[q][0];
+        for (int w = 1; w < 4; ++w) v = ismax ? fmax(v, sh[q][w]) : v + sh[q][w];
+        partials[(int64_t)blockIdx.x * NS + q] = v;
+    }
+}
+
+__global__ void __launch_bounds__(256) finish_reduce(const double *__restrict__ partials, int32_t nblk,
+                                                     int32_t ns, uint32_t maxmask, double *__restrict__ out) {
+    // one thread per slot, fixed order
+    const int q = threadIdx.x;
+    if (q >= ns) return;
+    const bool ismax = (maxmask >> q) & 1u;
+    double v = ismax ? -INFINITY : 0.0;
+    for (int32_t b = 0; b < nblk; ++b) {
+        const double x = partials[(int64_t)b * ns + q];
+        v = ismax ? fmax(v, x) : v + x;
+    }
+    out[q] = v;
+}
+
+// Residuals of problem (1): rx = Px + A'y + G'z + c, ry = Ax - b,
+// rz = Gx + s - h, and the scalars of the stopping test (slots in vec.hpp).
+__global__ void __launch_bounds__(256) residual_kernel(
+    int32_t n, int32_t p, int32_t m, const int64_t *__restrict__ kr_ptr, const int32_t *__restrict__ kr_col,
+    const double *__restrict__ kr_val, const double *__restrict__ x, const double *__restrict__ y,
+    const double *__restrict__ z, const double *__restrict__ s, const double *__restrict__ c,
+    const double *__restrict__ b, const double *__restrict__ hv, double *__restrict__ rx,
+    double *__restrict__ ry, double *__restrict__ rz, double *__restrict__ partials) {
+    double val[NSCAL];
+#pragma unroll
+    for (int q = 0; q < NSCAL; ++q) val[q] = 0.0;
+    const int32_t N = n + p + m;
+    const int32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i < N) {
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+        for (int64_t t = kr_ptr[i]; t < kr_ptr[i + 1]; ++t) {
+            const int32_t j = kr_col[t];
+            const double v = kr_val[t];
+            if (j < n) a0 += v * x[j];
+            else if (j < n + p) a1 += v * y[j - n];
+            else a2 += v * z[j - n - p];
+        }
+        if (i < n) {
+            const double r_ = a0 + a1 + a2 + c[i];
+            rx[i] = r_;
+            val[S_PX] = fabs(a0); val[S_ATY] = fabs(a1); val[S_GTZ] = fabs(a2); val[S_RX] = fabs(r_);
+            val[S_XPX] = x[i] * a0; val[S_CX] = c[i] * x[i]; val[S_C] = fabs(c[i]);
+        } else if (i < n + p) {
+            const int32_t e = i - n;
+            const double r_ = a0 - b[e];
+            ry[e] = r_;
+            val[S_AX] = fabs(a0); val[S_RY] = fabs(r_); val[S_BY] = b[e] * y[e]; val[S_B] = fabs(b[e]);
+        } else {
+            const int32_t e = i - n - p;
+            const double r_ = a0 + s[e] - hv[e];
+            rz[e] = r_;
+            val[S_GX] = fabs(a0); val[S_RZ] = fabs(r_); val[S_HZ] = hv[e] * z[e]; val[S_SZ] = s[e] * z[e];
+            val[S_S] = fabs(s[e]); val[S_H] = fabs(hv[e]);
+        }
+    }
+    block_reduce_store<NSCAL>(val, SCAL_MAXMASK, partials);
+}
+
+// res = rhs - K sol, K = static part + (3,3) block from kval; slot 0 of the
+// partials: max |res|, slot 1: max |rhs|.
+__global__ void __launch_bounds__(256) kkt_residual_kernel(
+    int32_t n, int32_t p, int32_t m, int32_t l, const int64_t *__restrict__ kr_ptr,
+    const int32_t *__restrict__ kr_col, const double *__restrict__ kr_val, const double *__restrict__ kval,
+    const int64_t *__restrict__ blk33, const int64_t *__restrict__ blk_off, const int32_t *__restrict__ soc_off,
+    const int32_t *__restrict__ zcone, const double *__restrict__ rhs, const double *__restrict__ sol,
+    double *__restrict__ res, double *__restrict__ partials) {
+    double val[2] = {0.0, 0.0};
+    const int32_t N = n + p + m;
+    const int32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i < N) {
+        double acc = 0.0;
+        for (int64_t t = kr_ptr[i]; t < kr_ptr[i + 1]; ++t) acc += kr_val[t] * sol[kr_col[t]];
+        if (i >= n + p) {
+            const int32_t e = i - n - p;
+            const double *zs = sol + n + p;
+            if (e < l) {
+                acc += kval[blk33[e]] * zs[e];
+            } else {
+                const int32_t k = zcone[e];
+                const int32_t off = soc_off[k], q = soc_off[k + 1] - off;
+                const int32_t a = e - off;
+                const int64_t base = l + blk_off[k];
+                for (int32_t bb = 0; bb < q; ++bb) {
+                    const int32_t lo = a < bb ? a : bb, hi = a < bb ? bb : a;
+                    acc += kval[blk33[base + (int64_t)hi * (hi + 1) / 2 + lo]] * zs[bb + off];
+                }
+            }
+        }
+        const double r_ = rhs[i] - acc;
+        res[i] = r_;
+        val[0] = fabs(r_);
+        val[1] = fabs(rhs[i]);
+    }
+    block_reduce_store<2>(val, 3u, partials);
+}
+
+__global__ void build_rhs_kernel(int32_t n, int32_t p, int32_t m, const double *__restrict__ rx,
+                                 const double *__restrict__ ry, const double *__restrict__ rz,
+                                 const double *__restrict__ zpart, double zsign, double *__restrict__ rhs) {
+    const int32_t i = blockIdx.x * 256 + threadIdx.x;
+    const int32_t N = n + p + m;
+    if (i >= N) return;
+    if (i < n) rhs[i] = -rx[i];
+    else if (i < n + p) rhs[i] = -ry[i - n];
+    else rhs[i] = -rz[i - n - p] + zsign * zpart[i - n - p];
+}
+
+__global__ void axpy_kernel(int32_t len, double a, const double *__restrict__ xv, double *__restrict__ yv) {
+    const int32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i < len) yv[i] += a * xv[i];
+}
+
+// (x, y, z, s) += alpha (dx, dy, dz, ds), alpha = min(1, frac * min(a_s, a_z))
+__global__ void update_kernel(int32_t n, int32_t p, int32_t m, const double *__restrict__ d,
+                              const double *__restrict__ ds, const unsigned long long *__restrict__ amin,
+                              double frac, double *__restrict__ x, double *__restrict__ y,
+                              double *__restrict__ z, double *__restrict__ s, double *__restrict__ alpha_out) {
+    const double as = __longlong_as_double((long long)amin[2]);
+    const double az = __longlong_as_double((long long)amin[3]);
+    const double alpha = fmin(1.0, frac * fmin(as, az));
+    const int32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i == 0 && alpha_out) *alpha_out = alpha;
+    if (i < n) x[i] += alpha * d[i];
+    else if (i < n + p) y[i - n] += alpha * d[i];
+    else if (i < n + p + m) {
+        const int32_t e = i - n - p;
+        z[e] += alpha * d[i];
+        s[e] += alpha * ds[e];
+    }
+}
+
+__global__ void fill_kernel(int32_t len, double v, double *__restrict__ out) {
+    const int32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i < len) out[i] = v;
+}
+__global__ void scale_copy_kernel(int32_t len, double a, const double *__restrict__ xv, double *__restrict__ out) {
+    const int32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i < len) out[i] = a * xv[i];
+}
+
+int launch_fill(qg_handle *h, int32_t len, double v, double *out) {
+    if (len <= 0) return QG_OK;
+    fill_kernel<<<(len + 255) / 256, 256, 0, h->stream>>>(len, v, out);
+    QG_HIP(h, hipGetLastError());
+    return QG_OK;
+}
+int launch_scale_copy(qg_handle *h, int32_t len, double a, const double *xv, double *out) {
+    if (len <= 0) return QG_OK;
+    scale_copy_kernel<<<(len + 255) / 256, 256, 0, h->stream>>>(len, a, xv, out);
+    QG_HIP(h, hipGetLastError());
+    return QG_OK;
+}
+
+int launch_residual(qg_handle *h, const double *x, const double *y, const double *z, const double *s,
+                    double *scal_host) {
+    Device &d = h->d;
+    const int32_t N = h->N;
+    const int32_t nblk = (N + 255) / 256;
+    residual_kernel<<<nblk, 256, 0, h->stream>>>(h->n, h->p, h->m, d.kr_ptr.p, d.kr_col.p, d.kr_val.p, x, y,
+                                                  z, s, d.c.p, d.b.p, d.h.p, d.rx.p, d.ry.p, d.rz.p,
+                                                  d.partials.p);
+    finish_reduce<<<1, 64, 0, h->stream>>>(d.partials.p, nblk, NSCAL, SCAL_MAXMASK, d.scal.p);
+    QG_HIP(h, hipGetLastError());
+    QG_HIP(h, hipMemcpyAsync(scal_host, d.scal.p, NSCAL * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    QG_HIP(h, hipStreamSynchronize(h->stream));
+    return QG_OK;
+}
+
+int launch_kkt_residual(qg_handle *h, const double *rhs, const double *sol, double *res, double *norms) {
+    Device &d = h->d;
+    const int32_t N = h->N;
+    const int32_t nblk = (N + 255) / 256;
+    kkt_residual_kernel<<<nblk, 256, 0, h->stream>>>(h->n, h->p, h->m, h->pp.l, d.kr_ptr.p, d.kr_col.p,
+                                                      d.kr_val.p, d.kval.p, d.blk33.p, d.blk_off.p,
+                                                      d.soc_off.p, d.zcone.p, rhs, sol, res, d.partials.p);
+    finish_reduce<<<1, 64, 0, h->stream>>>(d.partials.p, nblk, 2, 3u, d.scal.p + NSCAL);
+    QG_HIP(h, hipGetLastError());
+    QG_HIP(h, hipMemcpyAsync(norms, d.scal.p + NSCAL, 2 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    QG_HIP(h, hipStreamSynchronize(h->stream));
+    return QG_OK;
+}
+
+int launch_build_rhs(qg_handle *h, const double *zpart, double zsign, double *rhs) {
+    const int32_t N = h->N;
+    build_rhs_kernel<<<(N + 255) / 256, 256, 0, h->stream>>>(h->n, h->p, h->m, h->d.rx.p, h->d.ry.p,
+                                                             h->d.rz.p, zpart, zsign, rhs);
+    QG_HIP(h, hipGetLastError());
+    return QG_OK;
+}
+
+int launch_axpy(qg_handle *h, int32_t len, double a, const double *xv, double *yv) {
+    if (len <= 0) return QG_OK;
+    axpy_kernel<<<(len + 255) / 256, 256, 0, h->stream>>>(len, a, xv, yv);
+    QG_HIP(h, hipGetLastError());
+    return QG_OK;
+}
+
+int launch_update(qg_handle *h, const double *dvec, const double *ds, double frac, double *alpha_dev) {
+    Device &d = h->d;
+    const int32_t N = h->N;
+    update_kernel<<<(N + 255) / 256, 256, 0, h->stream>>>(h->n, h->p, h->m, dvec, ds, d.amin.p, frac, d.x.p,
+                                                          d.y.p, d.z.p, d.s.p, alpha_dev);
+    QG_HIP(h, hipGetLastError());
+    return QG_OK;
+}
+
+int refined_solve(qg_handle *h, const double *rhs, double *x, int precision, int ir_max, int *steps,
+                  bool *ok) {
+    int rc = launch_solve(h, rhs, x, precision);
+    if (rc) return rc;
+    int k = 0;
+    double nrm[2];
+    bool passed = false;
+    for (; k < ir_max; ++k) {
+        if ((rc = launch_kkt_residual(h, rhs, x, h->d.res.p, nrm))) return rc;
+        if (!(nrm[0] > h->st.ir_tol * (1.0 + nrm[1]))) { passed = true; break; }
+        if ((rc = launch_solve(h, h->d.res.p, h->d.corr.p, precision))) return rc;
+        if ((rc = launch_axpy(h, h->N, 1.0, h->d.corr.p, x))) return rc;
+    }
+    if (ok) {
+        if (!passed) {   // test the last correction
+            if ((rc = launch_kkt_residual(h, rhs, x, h->d.res.p, nrm))) return rc;
+            passed = nrm[0] <= h->st.ir_tol * (1.0 + nrm[1]);
+        }
+        *ok = passed;
+    }
+    if (steps) *steps = k;
+    return QG_OK;
+}
+
+}  // namespace qg

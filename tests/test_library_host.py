@@ -1,0 +1,85 @@
+"""Host-side checks of the device library (no GPU): the C ABI loads and
+exports every entry point declared in include/qg.h, and its analysis
+reproduces the oracle's integer pattern bit for bit."""
+import hashlib
+import json
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import kkt, symbolic
+from synth import problems
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+KEYS = [("perm", np.int32), ("iperm", np.int32), ("parent", np.int32), ("colcount", np.int64),
+        ("super_fund", np.int32), ("super_ptr", np.int32), ("rows_ptr", np.int64), ("rows", np.int32)]
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2603_29197_amd import _lib
+    hdr = open(os.path.join(ROOT, "include", "qg.h")).read()
+    declared = set(re.findall(r"\b(qg_[a-z_0-9]+)\s*\(", hdr))
+    L = _lib.lib()
+    missing = [s for s in sorted(declared) if not hasattr(L, s)]
+    assert not missing, missing
+    assert declared <= set(_lib.EXPORTS) | {"qg_strerror"}
+
+
+def test_strerror_and_defaults():
+    import paper_2603_29197_amd as qg
+    s = qg.default_settings()
+    assert s.eps_abs == 1e-8 and s.eps_rel == 1e-8 and s.max_iter == 100 and s.step_frac == 0.99
+    assert qg.lib().qg_strerror(-2) == b"invalid sparsity pattern"
+
+
+@pytest.mark.parametrize("name", ["small_qp", "lasso_s", "many_soc_s", "lasso_diff_s"])
+def test_analysis_matches_oracle_bit_exact(name):
+    import paper_2603_29197_amd as qg
+    prob = problems.workload(name)
+    a = qg.analyze(prob)
+    o = symbolic.analyze(kkt.kkt_pattern(prob))
+    for k, _ in KEYS:
+        assert np.array_equal(a[k], getattr(o, k)), k
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_analysis_matches_oracle_random_socp(seed):
+    import paper_2603_29197_amd as qg
+    prob = problems.many_soc(n=200 + 37 * seed, ncones=40 + 5 * seed, q=3 + seed % 4, nbounds=30,
+                             seed=500 + seed, windowed=bool(seed % 2))
+    a = qg.analyze(prob)
+    o = symbolic.analyze(kkt.kkt_pattern(prob))
+    for k, _ in KEYS:
+        assert np.array_equal(a[k], getattr(o, k)), k
+
+
+@pytest.mark.parametrize("name", ["huber_s", "many_soc", "lasso"])
+def test_analysis_matches_oracle_digest_full_size(name):
+    """Digests written by tests/golden/make_golden.py from the oracle."""
+    import paper_2603_29197_amd as qg
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "patterns.json")))[name]
+    a = qg.analyze(problems.workload(name))
+    assert a["N"] == gold["N"] and int(a["colcount"].sum()) == gold["nnz_L"]
+    for k, dt in KEYS:
+        if k == "iperm":
+            continue
+        assert hashlib.sha256(np.ascontiguousarray(a[k], dtype=dt).tobytes()).hexdigest() == gold[k], k
+
+
+def test_invalid_inputs_are_rejected():
+    import scipy.sparse as sp
+    import paper_2603_29197_amd as qg
+    from paper_2603_29197_amd._lib import QGError
+    prob = problems.small_qp(n=20, p=4, m=10, mrows=10)
+    bad = problems.Problem(**{**prob.__dict__})
+    bad.P = sp.csc_matrix(prob.P.toarray() + np.tril(np.ones((20, 20)), -1))  # not upper
+    with pytest.raises(QGError) as e:
+        qg.analyze(bad)
+    assert e.value.code == -2
+    bad = problems.Problem(**{**prob.__dict__})
+    bad.l = 9                                   # l + sum(q) != m
+    with pytest.raises(QGError) as e:
+        qg.analyze(bad)
+    assert e.value.code == -1

@@ -82,13 +82,14 @@ typedef struct {
     double switch_gap;         /* FP32 factors while the scaled gap >= switch_gap (1e-6) */
     double static_reg;         /* +delta on the (1,1), -delta on the (2,2) diagonal, FP64 factors (1e-8) */
     double dyn_eps, dyn_delta; /* pivot d with sign*d <= dyn_eps becomes sign*dyn_delta (1e-13, 1e-7) */
-    double static_reg32, dyn_eps32, dyn_delta32;  /* the same for FP32 factors */
+    double static_reg32, dyn_eps32, dyn_delta32;  /* the same for FP32 factors (1e-4, 1e-8, 1e-4) */
     int ir_max;                /* refinement steps per solve with an FP64 factor (3) */
     int ir_max32;              /* ... with an FP32 factor (10) */
     double ir_tol;             /* stop when |r - K x|_inf <= ir_tol (1 + |r|_inf) (1e-12) */
     double step_frac;          /* fraction of the maximum step (0.99) */
     int differentiable;        /* 1: factor the derivative system after convergence (qg_backward) */
     int verbose;               /* 1: one line per iteration on stderr */
+    int profile;               /* 1: time every launch of the trailing-update kernel (qg_info.kern_*) */
 } qg_settings;
 
 typedef struct {
@@ -107,6 +108,12 @@ typedef struct {
     double ms_step_median_fp64;              /* ... over iterations with an FP64 factor (0 if none) */
     int64_t nnz_L;                           /* entries of L incl. diagonal (exact symbolic count) */
     double factor_flops;                     /* sum_j (c_j - 1)^2 + 3 (c_j - 1), c_j column counts */
+    /* with settings.profile: the trailing-update kernel of large fronts (MFMA), HIP events per
+     * launch; index 0 = FP64 launches, 1 = FP32 launches */
+    int64_t kern_launches[2];
+    double kern_ms[2];                       /* summed launch durations */
+    double kern_flops[2];                    /* algorithmic flops: b M (M + 1) per launch (b panel
+                                                columns, M trailing rows, lower triangle incl. diag) */
 } qg_info;
 
 /* Integer pattern of the analysis; pointers stay valid until the object

@@ -47,6 +47,10 @@ def lib():
                                  ctypes.c_double, ctypes.c_double, f64p, f64p,
                                  ctypes.POINTER(ctypes.c_int64)]
     L.or_ldl_numeric.restype = ctypes.c_int
+    L.or_ldl_numeric_rows.argtypes = [ctypes.c_int32, ctypes.c_int32, i64p, i32p, f64p, i32p, i64p, i32p,
+                                      i8p, ctypes.c_double, ctypes.c_double, f64p, f64p,
+                                      ctypes.POINTER(ctypes.c_int64)]
+    L.or_ldl_numeric_rows.restype = ctypes.c_int
     L.or_ldl_solve.argtypes = [ctypes.c_int32, i64p, i32p, f64p, f64p, f64p]
     L.or_ldl_solve.restype = ctypes.c_int
     _lib = L

@@ -398,10 +398,25 @@ int or_lpattern(int32_t N, const int64_t *Up, const int32_t *Ui, const int32_t *
  * that pattern's positions, D the diagonal.  Returns 0, -1 on allocation
  * failure, -3 on a non-finite pivot.
  */
+int or_ldl_numeric_rows(int32_t N, int32_t k_end, const int64_t *Up, const int32_t *Ui,
+                        const double *Ux, const int32_t *parent, const int64_t *Lp,
+                        const int32_t *Li, const int8_t *sign, double eps, double delta,
+                        double *Lx, double *D, int64_t *nreg);
+
 int or_ldl_numeric(int32_t N, const int64_t *Up, const int32_t *Ui, const double *Ux,
                    const int32_t *parent, const int64_t *Lp, const int32_t *Li,
                    const int8_t *sign, double eps, double delta,
                    double *Lx, double *D, int64_t *nreg)
+{
+    return or_ldl_numeric_rows(N, N, Up, Ui, Ux, parent, Lp, Li, sign, eps, delta, Lx, D, nreg);
+}
+
+/* The same factorization stopped after rows 0..k_end-1 (used to time a
+ * bounded sample of a large factorization). */
+int or_ldl_numeric_rows(int32_t N, int32_t k_end, const int64_t *Up, const int32_t *Ui,
+                        const double *Ux, const int32_t *parent, const int64_t *Lp,
+                        const int32_t *Li, const int8_t *sign, double eps, double delta,
+                        double *Lx, double *D, int64_t *nreg)
 {
     double *y = (double *)calloc((size_t)(N > 0 ? N : 1), sizeof(double));
     int32_t *flag = (int32_t *)malloc((size_t)(N > 0 ? N : 1) * sizeof(int32_t));
@@ -411,7 +426,7 @@ int or_ldl_numeric(int32_t N, const int64_t *Up, const int32_t *Ui, const double
     if (!y || !flag || !patt || !fill) { rc = -1; goto done; }
     *nreg = 0;
     for (int32_t j = 0; j < N; ++j) flag[j] = -1;
-    for (int32_t k = 0; k < N; ++k) {
+    for (int32_t k = 0; k < k_end; ++k) {
         /* scatter column k of the upper triangle; collect the row-k pattern */
         int32_t np = 0;
         double akk = 0.0;

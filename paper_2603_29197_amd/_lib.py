@@ -42,7 +42,7 @@ class qg_settings(ctypes.Structure):
                 ("static_reg32", ctypes.c_double), ("dyn_eps32", ctypes.c_double),
                 ("dyn_delta32", ctypes.c_double), ("ir_max", ctypes.c_int), ("ir_max32", ctypes.c_int),
                 ("ir_tol", ctypes.c_double), ("step_frac", ctypes.c_double), ("differentiable", ctypes.c_int),
-                ("verbose", ctypes.c_int)]
+                ("verbose", ctypes.c_int), ("profile", ctypes.c_int)]
 
 
 class qg_info(ctypes.Structure):
@@ -54,10 +54,13 @@ class qg_info(ctypes.Structure):
                 ("ms_factor", ctypes.c_double), ("ms_trisolve", ctypes.c_double), ("ms_cone", ctypes.c_double),
                 ("ms_step_median", ctypes.c_double), ("ms_step_median_fp32", ctypes.c_double),
                 ("ms_step_median_fp64", ctypes.c_double), ("nnz_L", ctypes.c_int64),
-                ("factor_flops", ctypes.c_double)]
+                ("factor_flops", ctypes.c_double), ("kern_launches", ctypes.c_int64 * 2),
+                ("kern_ms", ctypes.c_double * 2), ("kern_flops", ctypes.c_double * 2)]
 
     def as_dict(self):
         d = {name: getattr(self, name) for name, _ in self._fields_}
+        for k in ("kern_launches", "kern_ms", "kern_flops"):
+            d[k] = list(d[k])
         d["status_name"] = STATUS.get(self.status, str(self.status))
         return d
 

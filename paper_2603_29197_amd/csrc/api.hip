@@ -155,15 +155,16 @@ int qg_default_settings(qg_settings *s) {
     s->static_reg = 1e-8;
     s->dyn_eps = 1e-13;
     s->dyn_delta = 1e-7;
-    s->static_reg32 = 1e-7;
-    s->dyn_eps32 = 1e-10;
-    s->dyn_delta32 = 1e-6;
+    s->static_reg32 = 1e-4;
+    s->dyn_eps32 = 1e-8;
+    s->dyn_delta32 = 1e-4;
     s->ir_max = 3;
     s->ir_max32 = 10;
     s->ir_tol = 1e-12;
     s->step_frac = 0.99;
     s->differentiable = 0;
     s->verbose = 0;
+    s->profile = 0;
     return QG_OK;
 }
 
@@ -326,8 +327,10 @@ int qg_last_hip_error(const qg_handle *h) { return h ? h->last_hip : 0; }
 int qg_step_scaling(qg_handle *h, const double *s, const double *z, double *lam, int block) {
     if (!h || !s || !z) return QG_ERR_ARG;
     h->final_factor = false;
-    int rc = launch_scaling(h, s, z, lam, block);
+    int rc = launch_scaling(h, s, z, h->d.lam.p, block);
     if (rc) return rc;
+    if (lam && h->m > 0)
+        QG_HIP(h, hipMemcpyAsync(lam, h->d.lam.p, sizeof(double) * h->m, hipMemcpyDeviceToDevice, h->stream));
     QG_HIP(h, hipStreamSynchronize(h->stream));
     return QG_OK;
 }

@@ -33,6 +33,14 @@ template <typename T> struct Acc4;
 template <> struct Acc4<double> { typedef d4 type; };
 template <> struct Acc4<float> { typedef f4 type; };
 
+// Row of the 16 x 16 MFMA output held by lane group lk (= lane / 16) in
+// accumulator register v: the f32 instruction keeps four consecutive rows
+// per lane group, the f64 instruction interleaves them (rows lk, lk+4, ...).
+// Both checked on gfx950 against a product with known entries.
+template <typename T> __device__ inline int mfma_out_row(int lk, int v);
+template <> __device__ inline int mfma_out_row<float>(int lk, int v) { return 4 * lk + v; }
+template <> __device__ inline int mfma_out_row<double>(int lk, int v) { return lk + 4 * v; }
+
 // ---------------------------------------------------------------------------
 // assembly: one 64-thread workgroup per (front, column) task
 // ---------------------------------------------------------------------------
@@ -270,7 +278,7 @@ __global__ void __launch_bounds__(256) trail_update(T *__restrict__ F, int32_t r
 #pragma unroll
             for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = mfma16x16x4(a_op[bj], b_op[bi], acc[bi][bj]);
     }
-    // lane holds D(4*lk + v, lr) = C(row = wr + 16 bi + lr, col = wc + 16 bj + 4 lk + v)
+    // lane holds D(mfma_out_row(lk, v), lr) = C(row = wr + 16 bi + lr, col = wc + 16 bj + mfma_out_row(lk, v))
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
@@ -278,9 +286,36 @@ __global__ void __launch_bounds__(256) trail_update(T *__restrict__ F, int32_t r
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int32_t row = r0 + wr + 16 * bi + lr;
-                const int32_t col = c0 + wc + 16 * bj + 4 * lk + v;
+                const int32_t col = c0 + wc + 16 * bj + mfma_out_row<T>(lk, v);
                 if (row < r && col < r && row >= col) F[(int64_t)col * r + row] -= acc[bi][bj][v];
             }
+}
+
+// Per-launch HIP events of the trailing-update kernel (settings.profile).
+static void prof_begin(qg_handle *h, hipEvent_t *e0, hipEvent_t *e1) {
+    if (hipEventCreate(e0) != hipSuccess || hipEventCreate(e1) != hipSuccess) { *e0 = *e1 = nullptr; return; }
+    (void)hipEventRecord(*e0, h->stream);
+}
+static void prof_end(qg_handle *h, hipEvent_t e0, hipEvent_t e1, double flops, int fp32) {
+    if (!e0) return;
+    (void)hipEventRecord(e1, h->stream);
+    h->prof_events.push_back({{e0, e1}, fp32});
+    h->prof_flops[fp32] += flops;
+}
+
+void prof_collect(qg_handle *h, int64_t *launches, double *ms, double *flops) {
+    for (int q = 0; q < 2; ++q) { launches[q] = 0; ms[q] = 0.0; flops[q] = h->prof_flops[q]; }
+    for (auto &pr : h->prof_events) {
+        float t = 0.f;
+        if (hipEventSynchronize(pr.first.second) == hipSuccess &&
+            hipEventElapsedTime(&t, pr.first.first, pr.first.second) == hipSuccess)
+            ms[pr.second] += t;
+        launches[pr.second] += 1;
+        (void)hipEventDestroy(pr.first.first);
+        (void)hipEventDestroy(pr.first.second);
+    }
+    h->prof_events.clear();
+    h->prof_flops[0] = h->prof_flops[1] = 0.0;
 }
 
 template <typename T>
@@ -298,7 +333,10 @@ static int factor_large(qg_handle *h, int32_t s, T *front, T *dinv, const RegPar
         if (mb > 0) {
             panel_solve<T><<<(mb + 63) / 64, 256, 0, h->stream>>>(F, r, j0, b, ws);
             const int64_t T_ = (mb + 63) / 64;
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            if (h->st.profile) prof_begin(h, &e0, &e1);
             trail_update<T><<<(unsigned)(T_ * (T_ + 1) / 2), 256, 0, h->stream>>>(F, r, j0, b);
+            if (h->st.profile) prof_end(h, e0, e1, (double)b * (double)mb * (double)(mb + 1), sizeof(T) == 4);
         }
     }
     return QG_OK;

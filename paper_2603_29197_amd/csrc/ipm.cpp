@@ -263,6 +263,10 @@ int ipm_solve(qg_handle *h, double *xo, double *so, double *yo, double *zo, qg_i
         info->ms_step_median_fp64 = median(step64);
         info->nnz_L = h->sym.nnz_L;
         info->factor_flops = h->sym.flops;
+        prof_collect(h, info->kern_launches, info->kern_ms, info->kern_flops);
+    } else {
+        int64_t a[2]; double b_[2], c_[2];
+        prof_collect(h, a, b_, c_);
     }
     return QG_OK;
 }

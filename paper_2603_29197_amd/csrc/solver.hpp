@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "analysis.hpp"
@@ -123,6 +124,8 @@ struct qg_handle {
     int last_status = QG_UNSOLVED;
     double ms_setup = 0, ms_analyze = 0;
     int64_t small_lds_bytes = 0;
+    std::vector<std::pair<std::pair<hipEvent_t, hipEvent_t>, int>> prof_events;   // settings.profile
+    double prof_flops[2] = {0.0, 0.0};
 };
 
 namespace qg {
@@ -156,6 +159,7 @@ int launch_cone_op(qg_handle *h, int op, const double *u, const double *v, doubl
 int launch_corrector(qg_handle *h, const double *dsa, const double *dza, double sigma_mu,
                      const double *alpha_aff_dev, double mu, double *t);
 int read_nreg(qg_handle *h, int *nreg);
+void prof_collect(qg_handle *h, int64_t *launches, double *ms, double *flops);
 
 int ipm_solve(qg_handle *h, double *x, double *s, double *y, double *z, qg_info *info);
 int adjoint_backward(qg_handle *h, const double *g, double *dc, double *dh, double *db, double *dP);

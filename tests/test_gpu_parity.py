@@ -1,0 +1,252 @@
+"""Parity of the HIP path against the oracle, step by step and end to end.
+
+Every call goes through the C ABI (libqg.so).  Floating-point bars:
+FP64 kernels vs the FP64 oracle on identical inputs: 1e-12 relative for
+elementwise cone algebra, 1e-10 for factor entries (with static
+regularization 1e-3, which bounds pivot growth; the default 1e-8 is checked
+through the backward error of solves), solutions of whole problems 1e-6
+relative in x and objective with residuals and gap <= 1e-8 (the targets of
+the method), iteration counts within one of the oracle's.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import adjoint as oadj  # noqa: E402
+from oracle import cones as oc  # noqa: E402
+from oracle import ipm as oipm  # noqa: E402
+from oracle import kkt as okkt  # noqa: E402
+from oracle import ldl as oldl  # noqa: E402
+from synth import problems  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+SMALL = {
+    "small_qp": lambda: problems.workload("small_qp"),
+    "lasso_s": lambda: problems.workload("lasso_s"),
+    "many_soc_s": lambda: problems.workload("many_soc_s"),
+    "mixed_soc": lambda: problems.many_soc(n=400, ncones=60, q=7, nbounds=50, seed=77, windowed=False),
+}
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def solver(prob, **kw):
+    import paper_2603_29197_amd as qg
+    print(f"[gpu] setup {prob.name} n={prob.n} m={prob.m} p={prob.p}", flush=True)
+    return qg.Solver(prob, **kw)
+
+
+def relerr(a, b):
+    return float(np.max(np.abs(a - b)) / max(1e-300, np.max(np.abs(b))))
+
+
+# ---------------------------------------------------------------------------
+# a1 + a6: NT scaling and the (3,3) block
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("name", ["small_qp", "many_soc_s", "mixed_soc"])
+def test_scaling_and_kkt_block(name):
+    prob = SMALL[name]()
+    S = solver(prob)
+    x, s, y, z = problems.random_point(prob, 3)
+    lam = host(S.step_scaling(dev(s), dev(z)))
+    cn = oc.Cones(prob.l, prob.q)
+    sc = oc.nt_scaling(cn, s, z)
+    assert relerr(lam, sc.lam) <= 1e-13
+    orth, blocks = sc.block33()
+    want = okkt.kkt_upper(prob, orth, blocks).data
+    got = S.step_get_kkt()
+    assert got.shape == want.shape
+    assert np.max(np.abs(got - want)) <= 1e-13 * np.max(np.abs(want))
+    S.close()
+
+
+@pytest.mark.parametrize("name", ["many_soc_s", "mixed_soc"])
+def test_derivative_block(name):
+    prob = SMALL[name]()
+    S = solver(prob)
+    _, s, _, z = problems.random_point(prob, 4)
+    S.step_scaling(dev(s), dev(z), want_lam=False, block=1)
+    orth, blocks = oadj.final_block(prob, s, z)
+    want = okkt.kkt_upper(prob, orth, blocks).data
+    assert np.max(np.abs(S.step_get_kkt() - want)) <= 1e-12 * np.max(np.abs(want))
+    S.close()
+
+
+# ---------------------------------------------------------------------------
+# a7, a8, a9: cone algebra, corrector, max step
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("name", ["small_qp", "many_soc_s", "mixed_soc"])
+def test_cone_ops_corrector_and_step(name):
+    prob = SMALL[name]()
+    S = solver(prob)
+    _, s, _, z = problems.random_point(prob, 5)
+    rng = np.random.default_rng(6)
+    u = rng.standard_normal(prob.m)
+    v = rng.standard_normal(prob.m)
+    S.step_scaling(dev(s), dev(z))
+    cn = oc.Cones(prob.l, prob.q)
+    sc = oc.nt_scaling(cn, s, z)
+    assert relerr(host(S.step_cone_op(0, dev(u))), sc.W(u)) <= 1e-13
+    assert relerr(host(S.step_cone_op(1, dev(u))), sc.Winv(u)) <= 1e-13
+    assert relerr(host(S.step_cone_op(2, dev(u))), sc.WtW(u)) <= 1e-13
+    assert relerr(host(S.step_cone_op(3, dev(u), dev(v))), cn.jordan(u, v)) <= 1e-14
+    assert relerr(host(S.step_cone_op(4, dev(s), dev(v))), cn.inv_jordan(s, v)) <= 1e-12
+    smu = 0.3
+    lam = sc.lam
+    dsv = -cn.jordan(lam, lam) - cn.jordan(sc.Winv(u), sc.W(v)) + smu * cn.identity()
+    want = sc.W(cn.inv_jordan(lam, dsv))
+    assert relerr(host(S.step_corrector(dev(u), dev(v), smu)), want) <= 1e-11
+    for scale in (0.1, 1.0, 10.0):
+        du = scale * rng.standard_normal(prob.m)
+        a = S.step_max_step(dev(s), dev(du))
+        b = cn.max_step(s, du)
+        assert (np.isinf(a) and np.isinf(b)) or abs(a - b) <= 1e-12 * max(1.0, b)
+    S.close()
+
+
+# ---------------------------------------------------------------------------
+# a2 + a3 + a4: factor, solves, refinement
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("name", ["small_qp", "lasso_s", "many_soc_s", "mixed_soc"])
+def test_factor_entries_fp64(name):
+    import paper_2603_29197_amd as qg
+    prob = SMALL[name]()
+    reg = 1e-3
+    S = solver(prob, static_reg=reg)
+    _, s, _, z = problems.random_point(prob, 7)
+    S.step_scaling(dev(s), dev(z))
+    nreg = S.step_factor(qg.QG_FP64)
+    F = oldl.KKTFactor(prob, reg=oldl.RegSettings(static_reg=reg))
+    sc = oc.nt_scaling(oc.Cones(prob.l, prob.q), s, z)
+    F.factor(*sc.block33())
+    Lx, D = S.step_get_factor(F.pat.Lp, F.pat.Li)
+    eD = relerr(D, F.D)
+    eL = float(np.max(np.abs(Lx - F.Lx)) / max(1.0, np.max(np.abs(F.Lx))))
+    assert (nreg, F.nreg) == (0, 0) and eD <= 1e-10 and eL <= 1e-10, (nreg, eD, eL)
+    S.close()
+
+
+@pytest.mark.parametrize("name", ["small_qp", "lasso_s", "many_soc_s", "mixed_soc"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_refined_solve(name, prec):
+    import paper_2603_29197_amd as qg
+    prob = SMALL[name]()
+    S = solver(prob)
+    _, s, _, z = problems.random_point(prob, 8)
+    S.step_scaling(dev(s), dev(z))
+    S.step_factor(qg.QG_FP64 if prec == "fp64" else qg.QG_FP32_IR)
+    F = oldl.KKTFactor(prob)
+    F.factor(*oc.nt_scaling(oc.Cones(prob.l, prob.q), s, z).block33())
+    rhs = np.random.default_rng(9).standard_normal(F.N)
+    want, _ = F.solve(rhs, ir_max=10)
+    got, steps = S.step_solve(dev(rhs), refine=10)
+    got = host(got)
+    K = F.K_unreg
+    res = float(np.max(np.abs(rhs - K @ got)) / (1 + np.max(np.abs(rhs))))
+    err = relerr(got, want)
+    assert res <= 1e-10 and err <= 1e-8, (res, err, steps)
+    if prec == "fp32":
+        assert steps >= 1
+    S.close()
+
+
+# ---------------------------------------------------------------------------
+# whole Newton iterations: the interior-point solve
+# ---------------------------------------------------------------------------
+ORACLE_CACHE = {}
+
+
+def oracle_solution(name):
+    if name not in ORACLE_CACHE:
+        ORACLE_CACHE[name] = oipm.solve(SMALL[name]())
+    return ORACLE_CACHE[name]
+
+
+@pytest.mark.parametrize("name", ["small_qp", "lasso_s", "many_soc_s", "mixed_soc"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_solve_matches_oracle(name, prec):
+    import paper_2603_29197_amd as qg
+    prob = SMALL[name]()
+    S = solver(prob, precision=qg.QG_FP64 if prec == "fp64" else qg.QG_FP32_IR)
+    x, s, y, z, info = S.solve()
+    print(f"[gpu] {name} {prec}: {info['status_name']} iters {info['iters']} switch {info['switch_iter']} "
+          f"ir {info['ir_steps']} step {info['ms_step_median']:.3f} ms", flush=True)
+    ref = oracle_solution(name)
+    assert info["status"] == 1
+    assert info["pres"] <= 1e-8 * 10 and info["dres"] <= 1e-8 * 10
+    xs = host(x)
+    ex = float(np.max(np.abs(xs - ref.x)) / max(1.0, np.max(np.abs(ref.x))))
+    eo = abs(info["pobj"] - ref.pobj) / max(1.0, abs(ref.pobj))
+    print(f"[gpu] rel err x {ex:.2e} obj {eo:.2e} (oracle iters {ref.iters})", flush=True)
+    assert ex <= 1e-6 and eo <= 1e-6, (ex, eo)
+    if prec == "fp64":
+        assert abs(info["iters"] - ref.iters) <= 1
+    # residuals recomputed on the host from the returned iterate
+    r = oipm.residuals(prob, xs, host(s), host(y), host(z))
+    ok, pres, dres, gap = oipm.stop_test(prob, r, host(s), 1e-8, 1e-8)
+    assert ok, (pres, dres, gap)
+    S.close()
+
+
+@pytest.mark.parametrize("name", ["small_qp", "lasso_s", "mixed_soc"])
+def test_backward_matches_oracle(name):
+    prob = SMALL[name]()
+    S = solver(prob, differentiable=1)
+    x, s, y, z, info = S.solve()
+    assert info["status"] == 1
+    ref = oracle_solution(name)
+    g = np.random.default_rng(11).standard_normal(prob.n)
+    gr = S.backward(dev(g))
+    want = oadj.backward_dense(prob, ref, g)
+    for k in ("dc", "dh", "db", "dP"):
+        if k == "dP" and not prob.P.nnz:
+            continue
+        a, b = host(gr[k]), want[k]
+        if b.size:
+            e = float(np.max(np.abs(a - b)) / max(1.0, np.max(np.abs(b))))
+            print(f"[gpu] {name} {k} rel err {e:.2e}", flush=True)
+            assert e <= 1e-5, (k, e)
+    S.close()
+
+
+def test_update_reuses_analysis():
+    prob = SMALL["small_qp"]()
+    S = solver(prob)
+    S.solve()
+    rng = np.random.default_rng(12)
+    c2 = prob.c + 0.1 * rng.standard_normal(prob.n)
+    S.update(c=c2)
+    x, s, y, z, info = S.solve()
+    prob2 = problems.Problem(**{**prob.__dict__})
+    prob2.c = c2
+    ref = oipm.solve(prob2)
+    e = float(np.max(np.abs(host(x) - ref.x)) / max(1.0, np.max(np.abs(ref.x))))
+    assert e <= 1e-6, e
+    S.close()
+
+
+def test_autograd_function():
+    import paper_2603_29197_amd as qg
+    prob = problems.lasso(rows=120, cols=60, density=0.1, seed=9)
+    S = solver(prob, differentiable=1)
+    c = torch.tensor(prob.c, device="cuda", requires_grad=True)
+    h = torch.tensor(prob.h, device="cuda", requires_grad=True)
+    b = torch.tensor(prob.b, device="cuda", requires_grad=True)
+    x = qg.QGSolve.apply(c, h, b, None, S)
+    xref = torch.randn(prob.n, dtype=torch.float64, device="cuda")
+    loss = 0.5 * ((x - xref) ** 2).sum()
+    loss.backward()
+    ref = oipm.solve(prob)
+    want = oadj.backward_dense(prob, ref, ref.x - host(xref))
+    ec = float(np.max(np.abs(host(c.grad) - want["dc"])) / max(1.0, np.max(np.abs(want["dc"]))))
+    eb = float(np.max(np.abs(host(b.grad) - want["db"])) / max(1.0, np.max(np.abs(want["db"]))))
+    assert ec <= 1e-5 and eb <= 1e-5, (ec, eb)
+    S.close()

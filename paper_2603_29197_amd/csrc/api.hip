@@ -84,6 +84,7 @@ static int allocate_device(qg_handle *h) {
     UP(ctb_ptr, pl.ctb_ptr);
     UP(rel_ptr, pl.rel_ptr);
     UP(uv_off, pl.uv_off);
+    UP(task0, pl.task0);
     UP(reg_sign, pl.reg_sign);
     std::vector<int32_t> zc((size_t)h->m, -1);
     for (int32_t k = 0; k < h->pp.nsoc; ++k)
@@ -96,8 +97,11 @@ static int allocate_device(qg_handle *h) {
     if ((rc = dalloc(h, d.front64, (size_t)pl.front_total))) return rc;
     if ((rc = dalloc(h, d.front32, (size_t)pl.front_total))) return rc;
     if ((rc = dalloc(h, d.uvec, (size_t)pl.uv_total))) return rc;
+    if ((rc = dalloc(h, d.vwork, (size_t)pl.task_sn.size()))) return rc;
     if ((rc = dalloc(h, d.dinv64, (size_t)pl.dinv_total))) return rc;
     if ((rc = dalloc(h, d.dinv32, (size_t)pl.dinv_total))) return rc;
+    if ((rc = dalloc(h, d.sinv64, (size_t)pl.sinv_total))) return rc;
+    if ((rc = dalloc(h, d.sinv32, (size_t)pl.sinv_total))) return rc;
     if ((rc = dalloc(h, d.vbuf, (size_t)pl.max_r))) return rc;
     if ((rc = dalloc(h, d.nreg, 1))) return rc;
     if ((rc = dalloc(h, d.x, (size_t)h->n))) return rc;
@@ -262,6 +266,7 @@ int qg_setup(qg_handle **out, qg_int n, qg_int m, qg_int p, const qg_csc *P, con
         h->ms_analyze = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - ta).count();
         if ((rc = build_plan(h))) { qg_cleanup(h); return rc; }
         if ((rc = allocate_device(h))) { qg_cleanup(h); return rc; }
+        if ((rc = factor_init_attributes(h))) { qg_cleanup(h); return rc; }
         if ((rc = upload_static_values(h))) { qg_cleanup(h); return rc; }
         if (hipStreamSynchronize(h->stream) != hipSuccess) { qg_cleanup(h); return QG_ERR_HIP; }
     } catch (const std::bad_alloc &) {

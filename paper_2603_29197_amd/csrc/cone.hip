@@ -308,16 +308,16 @@ __global__ void __launch_bounds__(256) lmin_kernel(int32_t l, int32_t nsoc, cons
         for (int32_t a = 1; a < q; ++a) n1 += u[off + a] * u[off + a];
         v = -(u[off] - sqrt(n1));
     }
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    for (int o = 32; o > 0; o >>= 1) v = nan_max(v, __shfl_xor(v, o));
     __shared__ double sh[4];
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
     __syncthreads();
-    if (threadIdx.x == 0) partials[blockIdx.x] = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+    if (threadIdx.x == 0) partials[blockIdx.x] = nan_max(nan_max(sh[0], sh[1]), nan_max(sh[2], sh[3]));
 }
 
 __global__ void finish_max(const double *__restrict__ partials, int32_t nblk, double *__restrict__ out) {
     double v = -INFINITY;
-    for (int32_t b = 0; b < nblk; ++b) v = fmax(v, partials[b]);
+    for (int32_t b = 0; b < nblk; ++b) v = nan_max(v, partials[b]);
     *out = v;
 }
 

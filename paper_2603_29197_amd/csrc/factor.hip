@@ -102,7 +102,8 @@ __global__ void __launch_bounds__(256) factor_small(
     const int32_t *__restrict__ sn_list, const int32_t *__restrict__ sn_first,
     const int64_t *__restrict__ sn_rptr, const int64_t *__restrict__ fr_off, T *__restrict__ front,
     const int8_t *__restrict__ kind, double eps, double dyn, int32_t *nreg) {
-    __shared__ T F[SMALL_R * SMALL_R];
+    extern __shared__ double smem_small[];          // r_max * r_max entries of T (launch size)
+    T *F = reinterpret_cast<T *>(smem_small);
     __shared__ T dsh;
     const int32_t s = sn_list[blockIdx.x];
     const int32_t r = (int32_t)(sn_rptr[s + 1] - sn_rptr[s]);
@@ -142,56 +143,161 @@ __global__ void __launch_bounds__(256) factor_small(
 // ---------------------------------------------------------------------------
 // LDL' of the b x b diagonal block at (j0, j0) of the front F (ld r), in
 // place; the inverse of the unit lower factor goes to Xg (ld NB).
+// Thread t owns column c = t % 64 and rows t / 64 + 4 m (m = 0..15) of the
+// block in registers; at pivot jj the owner of column jj in each wavefront
+// publishes its part of the column through a double-buffered LDS slot, so a
+// pivot step costs one barrier; updates are selects, not branches, and the
+// regularization events are added to the counter once at the end.
 template <typename T>
 __global__ void __launch_bounds__(256) diag_block(T *__restrict__ F, int32_t r, int32_t j0, int32_t b,
                                                   const int8_t *__restrict__ kind_cols, double eps,
                                                   double dyn, int32_t *nreg, T *__restrict__ Xg) {
-    __shared__ T Ls[NB * NB];     // Ls[c * NB + i] = L(i, c)
-    __shared__ T tmp[NB];
-    __shared__ T dsh;
+    __shared__ T colbuf[2][NB];
+    __shared__ T Ls[NB * NB];     // final L (strictly lower) by column: Ls[c * NB + i]
+    __shared__ double sgn[NB];
     const int tid = threadIdx.x;
-    for (int32_t idx = tid; idx < b * b; idx += 256) {
-        const int32_t i = idx % b, c = idx / b;
-        Ls[c * NB + i] = (i >= c) ? F[(int64_t)(j0 + c) * r + j0 + i] : T(0);
+    const int c = tid & 63, i0 = tid >> 6;
+    if (tid < NB) sgn[tid] = tid < b ? pivot_sign(kind_cols[j0 + tid]) : 1.0;
+    T a[16];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+        const int i = i0 + 4 * m;
+        a[m] = (i < b && c < b && i >= c) ? F[(int64_t)(j0 + c) * r + j0 + i] : T(0);
     }
-    __syncthreads();
+    int events = 0;
     for (int32_t jj = 0; jj < b; ++jj) {
-        if (tid == 0) {
-            T d = regularize(Ls[jj * NB + jj], kind_cols[j0 + jj], eps, dyn, nreg);
-            Ls[jj * NB + jj] = d;
-            dsh = d;
+        const int buf = jj & 1;
+        if (c == jj) {
+#pragma unroll
+            for (int m = 0; m < 16; ++m) colbuf[buf][i0 + 4 * m] = a[m];
         }
         __syncthreads();
-        const T d = dsh;
-        const int32_t R = b - jj - 1;
-        for (int32_t idx = tid; idx < R * R; idx += 256) {
-            const int32_t i = jj + 1 + idx % R, c = jj + 1 + idx / R;
-            if (i >= c) Ls[c * NB + i] -= Ls[jj * NB + i] * Ls[jj * NB + c] / d;
+        // every thread forms the same regularized pivot
+        const T raw = colbuf[buf][jj];
+        const double sg = sgn[jj];
+        const bool fix = !(sg * (double)raw > eps);
+        const T d = fix ? (T)(sg * dyn) : raw;
+        events += (fix && tid == 0) ? 1 : 0;
+        const T inv = T(1) / d;
+        const T w = colbuf[buf][c] * inv;
+        const bool upd = c > jj && c < b;
+        const bool own = c == jj;
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+            const int i = i0 + 4 * m;
+            const T u = colbuf[buf][i];
+            const T up = a[m] - u * w;
+            const T sc = (i == jj) ? d : a[m] * inv;
+            a[m] = (upd && i >= c && i < b) ? up : ((own && i >= jj && i < b) ? sc : a[m]);
         }
-        __syncthreads();
-        for (int32_t i = jj + 1 + tid; i < b; i += 256) Ls[jj * NB + i] /= d;
-        __syncthreads();
     }
-    for (int32_t idx = tid; idx < b * b; idx += 256) {
-        const int32_t i = idx % b, c = idx / b;
-        if (i >= c) F[(int64_t)(j0 + c) * r + j0 + i] = Ls[c * NB + i];
+    if (tid == 0 && events) atomicAdd(nreg, events);
+    // L and D back to the front; L also to LDS for the inverse
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+        const int i = i0 + 4 * m;
+        if (i < b && c < b && i >= c) F[(int64_t)(j0 + c) * r + j0 + i] = a[m];
+        Ls[c * NB + i] = (i > c && i < b && c < b) ? a[m] : T(0);
     }
     __syncthreads();
-    // in-place inverse of the unit lower factor, last column first:
-    // X(j+1:, j) = -X(j+1:, j+1:) L(j+1:, j)
-    for (int32_t j = b - 2; j >= 0; --j) {
-        if (tid < b) tmp[tid] = (tid > j) ? Ls[j * NB + tid] : T(0);
-        __syncthreads();
-        if (tid > j && tid < b) {
-            T acc = tmp[tid];                       // X(i,i) = 1
-            for (int32_t t = j + 1; t < tid; ++t) acc += Ls[t * NB + tid] * tmp[t];
-            Ls[j * NB + tid] = -acc;
+    // X = L^-1 (unit lower), forward substitution by rows: when row t of X is
+    // final its owners publish it, then rows i > t subtract L(i, t) X(t, :).
+    T x[16];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) x[m] = (i0 + 4 * m == c) ? T(1) : T(0);
+    for (int32_t t = 0; t + 1 < b; ++t) {
+        const int buf = t & 1;
+        if (i0 == (t & 3)) {
+            T xt_own = T(0);
+#pragma unroll
+            for (int m = 0; m < 16; ++m) xt_own = (m == (t >> 2)) ? x[m] : xt_own;
+            colbuf[buf][c] = xt_own;                       // X(t, c)
         }
         __syncthreads();
+        const T xt = colbuf[buf][c];
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+            const int i = i0 + 4 * m;
+            const T nv = x[m] - Ls[t * NB + i] * xt;
+            x[m] = (i > t) ? nv : x[m];
+        }
     }
-    for (int32_t idx = tid; idx < b * b; idx += 256) {
-        const int32_t i = idx % b, c = idx / b;
-        Xg[c * NB + i] = (i > c) ? Ls[c * NB + i] : (i == c ? T(1) : T(0));
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+        const int i = i0 + 4 * m;
+        Xg[c * NB + i] = (i < b && c < b && i >= c) ? x[m] : T(0);
+    }
+}
+
+// Inverse of the unit-lower SB x SB diagonal block of a super-panel
+// [J0, J0+kb) from the inverses X_ii of its 64 x 64 diagonal blocks:
+// X_ij = -X_ii sum_{k=j}^{i-1} L_ik X_kj (i > j).  Workgroup j computes block
+// column j (independent of the other columns).  Writes X and X' (column-major,
+// leading dimension ld = kb rounded up to a multiple of 64).
+template <typename T>
+__global__ void __launch_bounds__(256) sblock_inverse(const T *__restrict__ F, int32_t r, int32_t J0, int32_t kb,
+                                                      const T *__restrict__ dinv_s, int32_t ld,
+                                                      T *__restrict__ Xs, T *__restrict__ XTs) {
+    __shared__ T A[NB * NB];         // A[t * NB + row]
+    __shared__ T B[NB * (NB + 1)];   // B[t * (NB+1) + col]
+    const int tid = threadIdx.x;
+    const int cc = tid & 63, i0 = tid >> 6;
+    const int32_t j = blockIdx.x;
+    const int32_t nsub = (kb + NB - 1) / NB;
+    const int32_t bj = min(NB, kb - j * NB);
+    // X_jj
+    const T *Xjj = dinv_s + (int64_t)((J0 + j * NB) / NB) * NB * NB;
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+        const int rr = i0 + 4 * m;
+        const T v = Xjj[cc * NB + rr];
+        Xs[(int64_t)(j * NB + cc) * ld + j * NB + rr] = v;
+        XTs[(int64_t)(j * NB + rr) * ld + j * NB + cc] = v;
+    }
+    for (int32_t i = j + 1; i < nsub; ++i) {
+        const int32_t bi = min(NB, kb - i * NB);
+        T acc[16];
+#pragma unroll
+        for (int m = 0; m < 16; ++m) acc[m] = T(0);
+        for (int32_t k = j; k < i; ++k) {
+            const int32_t bk = min(NB, kb - k * NB);
+            __syncthreads();
+            // A = L_ik (rows of block i, columns of block k), B = X_kj
+            for (int32_t idx = tid; idx < NB * NB; idx += 256) {
+                const int32_t rr = idx & 63, t = idx >> 6;
+                A[t * NB + rr] = (rr < bi && t < bk) ? F[(int64_t)(J0 + k * NB + t) * r + J0 + i * NB + rr] : T(0);
+                const int32_t tt = idx & 63, col = idx >> 6;   // X_kj(tt, col)
+                B[tt * (NB + 1) + col] = (tt < bk && col < bj) ? Xs[(int64_t)(j * NB + col) * ld + k * NB + tt] : T(0);
+            }
+            __syncthreads();
+            for (int32_t t = 0; t < NB; ++t) {
+                const T bv = B[t * (NB + 1) + cc];
+#pragma unroll
+                for (int m = 0; m < 16; ++m) acc[m] += A[t * NB + i0 + 4 * m] * bv;
+            }
+        }
+        // X_ij = -X_ii S
+        __syncthreads();
+        const T *Xii = dinv_s + (int64_t)((J0 + i * NB) / NB) * NB * NB;
+        for (int32_t idx = tid; idx < NB * NB; idx += 256) A[idx] = Xii[idx];   // A[t*NB+row] = X_ii(row, t)
+#pragma unroll
+        for (int m = 0; m < 16; ++m) B[(i0 + 4 * m) * (NB + 1) + cc] = acc[m];  // B[t][col] = S(t, col)
+        __syncthreads();
+        T out[16];
+#pragma unroll
+        for (int m = 0; m < 16; ++m) out[m] = T(0);
+        for (int32_t t = 0; t < NB; ++t) {
+            const T bv = B[t * (NB + 1) + cc];
+#pragma unroll
+            for (int m = 0; m < 16; ++m) out[m] -= A[t * NB + i0 + 4 * m] * bv;
+        }
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+            const int rr = i0 + 4 * m;
+            const T v = (rr < bi && cc < bj) ? out[m] : T(0);
+            Xs[(int64_t)(j * NB + cc) * ld + i * NB + rr] = v;
+            XTs[(int64_t)(i * NB + rr) * ld + j * NB + cc] = v;
+        }
     }
 }
 
@@ -211,6 +317,7 @@ __global__ void __launch_bounds__(256) panel_solve(T *__restrict__ F, int32_t r,
     T out[NB / 4];
 #pragma unroll
     for (int u = 0; u < NB / 4; ++u) out[u] = T(0);
+#pragma unroll 8
     for (int32_t t = 0; t < b && active; ++t) {
         const T a = F[(int64_t)(j0 + t) * r + row];
 #pragma unroll
@@ -227,56 +334,60 @@ __global__ void __launch_bounds__(256) panel_solve(T *__restrict__ F, int32_t r,
     }
 }
 
-// A22 -= L21 D L21' over the lower 64 x 64 tiles of the trailing block
-// starting at j1 = j0 + b.  Four wavefronts per tile, 2 x 2 MFMA 16x16
-// blocks each; the product is formed transposed so that each lane's four
-// accumulators run along a column of the column-major front.
+// C -= L(:, k0:k0+kb) D L(cols, k0:k0+kb)' on the lower part (row >= col) of
+// rows [r_lo, r) x cols [r_lo, c_hi) of the front F (ld r), 64 x 64 tiles,
+// grid (row tile, col tile).  The rank kb is consumed in chunks of NB staged
+// through LDS.  Four wavefronts per tile, 2 x 2 MFMA 16x16 blocks each; the
+// product is formed transposed so that each lane's accumulators run along a
+// column of the column-major front.
 template <typename T>
-__global__ void __launch_bounds__(256) trail_update(T *__restrict__ F, int32_t r, int32_t j0, int32_t b) {
-    __shared__ T As[NB * 64];    // As[kk * 64 + i] = L(j1 + 64 ti + i, j0 + kk)
-    __shared__ T Bs[NB * 64];    // Bs[kk * 64 + j] = L(j1 + 64 tj + j, j0 + kk) * D(kk)
-    const int32_t j1 = j0 + b;
-    const int64_t x = blockIdx.x;
-    int32_t ti = (int32_t)((sqrt(8.0 * (double)x + 1.0) - 1.0) * 0.5);
-    while ((int64_t)ti * (ti + 1) / 2 > x) --ti;
-    while ((int64_t)(ti + 1) * (ti + 2) / 2 <= x) ++ti;
-    const int32_t tj = (int32_t)(x - (int64_t)ti * (ti + 1) / 2);
-    const int32_t r0 = j1 + 64 * ti, c0 = j1 + 64 * tj;
+__global__ void __launch_bounds__(256) trail_update(T *__restrict__ F, int32_t r, int32_t k0, int32_t kb,
+                                                   int32_t r_lo, int32_t c_hi) {
+    __shared__ T As[NB * 64];    // As[kk * 64 + i] = L(r0 + i, k0 + kc + kk)
+    __shared__ T Bs[NB * 64];    // Bs[kk * 64 + j] = L(c0 + j, k0 + kc + kk) * D(k0 + kc + kk)
+    const int32_t ti = blockIdx.x, tj = blockIdx.y;
+    if (ti < tj) return;                          // strictly above the diagonal: nothing to do
+    const int32_t r0 = r_lo + 64 * ti, c0 = r_lo + 64 * tj;
     const int tid = threadIdx.x;
-    {
-        const int32_t i = tid & 63;
-        for (int32_t kk = tid >> 6; kk < NB; kk += 4) {
-            T av = T(0), bv = T(0);
-            if (kk < b) {
-                const T *colp = F + (int64_t)(j0 + kk) * r;
-                if (r0 + i < r) av = colp[r0 + i];
-                if (c0 + i < r) bv = colp[c0 + i] * colp[j0 + kk];
-            }
-            As[kk * 64 + i] = av;
-            Bs[kk * 64 + i] = bv;
-        }
-    }
-    __syncthreads();
     const int wave = tid >> 6, lane = tid & 63;
     const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+    const int lr = lane & 15, lk = lane >> 4;
     typedef typename Acc4<T>::type V;
     V acc[2][2];
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = V{0, 0, 0, 0};
-    const int lr = lane & 15, lk = lane >> 4;
-    for (int32_t kk = 0; kk < b; kk += 4) {
-        const int32_t kq = kk + lk;
-        T a_op[2], b_op[2];
+    for (int32_t kc = 0; kc < kb; kc += NB) {
+        const int32_t kn = min(NB, kb - kc);
+        if (kc > 0) __syncthreads();
+        {
+            const int32_t i = tid & 63;
+            for (int32_t kk = tid >> 6; kk < NB; kk += 4) {
+                T av = T(0), bv = T(0);
+                if (kk < kn) {
+                    const int32_t kcol = k0 + kc + kk;
+                    const T *colp = F + (int64_t)kcol * r;
+                    if (r0 + i < r) av = colp[r0 + i];
+                    if (c0 + i < c_hi) bv = colp[c0 + i] * colp[kcol];
+                }
+                As[kk * 64 + i] = av;
+                Bs[kk * 64 + i] = bv;
+            }
+        }
+        __syncthreads();
+        for (int32_t kk = 0; kk < kn; kk += 4) {
+            const int32_t kq = kk + lk;
+            T a_op[2], b_op[2];
 #pragma unroll
-        for (int bj = 0; bj < 2; ++bj) a_op[bj] = Bs[kq * 64 + wc + 16 * bj + lr];
+            for (int bj = 0; bj < 2; ++bj) a_op[bj] = Bs[kq * 64 + wc + 16 * bj + lr];
 #pragma unroll
-        for (int bi = 0; bi < 2; ++bi) b_op[bi] = As[kq * 64 + wr + 16 * bi + lr];
+            for (int bi = 0; bi < 2; ++bi) b_op[bi] = As[kq * 64 + wr + 16 * bi + lr];
 #pragma unroll
-        for (int bi = 0; bi < 2; ++bi)
+            for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-            for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = mfma16x16x4(a_op[bj], b_op[bi], acc[bi][bj]);
+                for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = mfma16x16x4(a_op[bj], b_op[bi], acc[bi][bj]);
+        }
     }
     // lane holds D(mfma_out_row(lk, v), lr) = C(row = wr + 16 bi + lr, col = wc + 16 bj + mfma_out_row(lk, v))
 #pragma unroll
@@ -287,7 +398,7 @@ __global__ void __launch_bounds__(256) trail_update(T *__restrict__ F, int32_t r
             for (int v = 0; v < 4; ++v) {
                 const int32_t row = r0 + wr + 16 * bi + lr;
                 const int32_t col = c0 + wc + 16 * bj + mfma_out_row<T>(lk, v);
-                if (row < r && col < r && row >= col) F[(int64_t)col * r + row] -= acc[bi][bj][v];
+                if (row < r && col < c_hi && row >= col) F[(int64_t)col * r + row] -= acc[bi][bj][v];
             }
 }
 
@@ -319,31 +430,52 @@ void prof_collect(qg_handle *h, int64_t *launches, double *ms, double *flops) {
 }
 
 template <typename T>
-static int factor_large(qg_handle *h, int32_t s, T *front, T *dinv, const RegParams &rp) {
+static void launch_update(qg_handle *h, T *F, int32_t r, int32_t k0, int32_t kb, int32_t r_lo, int32_t c_hi) {
+    const int32_t TR = (r - r_lo + 63) / 64, TC = (c_hi - r_lo + 63) / 64;
+    if (TR <= 0 || TC <= 0) return;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (h->st.profile) prof_begin(h, &e0, &e1);
+    trail_update<T><<<dim3((unsigned)TR, (unsigned)TC), 256, 0, h->stream>>>(F, r, k0, kb, r_lo, c_hi);
+    if (h->st.profile) {
+        // lower part of rows [r_lo, r) x cols [r_lo, c_hi): sum over columns of (r - col)
+        const double M = (double)(r - r_lo), C = (double)(c_hi - r_lo);
+        const double entries = C * M - C * (C - 1.0) / 2.0;
+        prof_end(h, e0, e1, 2.0 * (double)kb * entries, sizeof(T) == 4);
+    }
+}
+
+template <typename T>
+static int factor_large(qg_handle *h, int32_t s, T *front, T *dinv, T *sinv, const RegParams &rp) {
     const Plan &pl = h->plan;
     const int32_t r = (int32_t)(pl.sn_rptr[s + 1] - pl.sn_rptr[s]);
     const int32_t k = pl.sn_first[s + 1] - pl.sn_first[s];
     T *F = front + pl.fr_off[s];
     const int8_t *kinds = h->d.reg_sign.p + pl.sn_first[s];
-    for (int32_t j0 = 0; j0 < k; j0 += NB) {
-        const int32_t b = std::min(NB, k - j0);
-        T *ws = dinv + pl.dinv_off[s] + (int64_t)(j0 / NB) * NB * NB;
-        diag_block<T><<<1, 256, 0, h->stream>>>(F, r, j0, b, kinds, rp.eps, rp.dyn, h->d.nreg.p, ws);
-        const int32_t mb = r - j0 - b;
-        if (mb > 0) {
-            panel_solve<T><<<(mb + 63) / 64, 256, 0, h->stream>>>(F, r, j0, b, ws);
-            const int64_t T_ = (mb + 63) / 64;
-            hipEvent_t e0 = nullptr, e1 = nullptr;
-            if (h->st.profile) prof_begin(h, &e0, &e1);
-            trail_update<T><<<(unsigned)(T_ * (T_ + 1) / 2), 256, 0, h->stream>>>(F, r, j0, b);
-            if (h->st.profile) prof_end(h, e0, e1, (double)b * (double)mb * (double)(mb + 1), sizeof(T) == 4);
+    for (int32_t J0 = 0; J0 < k; J0 += SB) {
+        const int32_t J1 = std::min(k, J0 + SB);
+        for (int32_t j0 = J0; j0 < J1; j0 += NB) {
+            const int32_t b = std::min(NB, J1 - j0);
+            T *ws = dinv + pl.dinv_off[s] + (int64_t)(j0 / NB) * NB * NB;
+            diag_block<T><<<1, 256, 0, h->stream>>>(F, r, j0, b, kinds, rp.eps, rp.dyn, h->d.nreg.p, ws);
+            const int32_t mb = r - j0 - b;
+            if (mb > 0) panel_solve<T><<<(mb + 63) / 64, 256, 0, h->stream>>>(F, r, j0, b, ws);
+            // rest of this super-panel's columns (rank b)
+            if (j0 + b < J1) launch_update<T>(h, F, r, j0, b, j0 + b, J1);
         }
+        {
+            const int32_t nsub = (J1 - J0 + NB - 1) / NB, ld = nsub * NB;
+            T *Xs = sinv + pl.sinv_off[s] + (int64_t)(J0 / SB) * 2 * SB * SB;
+            sblock_inverse<T><<<nsub, 256, 0, h->stream>>>(F, r, J0, J1 - J0, dinv + pl.dinv_off[s], ld, Xs,
+                                                           Xs + (int64_t)ld * ld);
+        }
+        // everything to the right of the super-panel (rank J1 - J0)
+        if (J1 < r) launch_update<T>(h, F, r, J0, J1 - J0, J1, r);
     }
     return QG_OK;
 }
 
 template <typename T>
-static int factor_all(qg_handle *h, T *front, T *dinv, const RegParams &rp) {
+static int factor_all(qg_handle *h, T *front, T *dinv, T *sinv, const RegParams &rp) {
     const Plan &pl = h->plan;
     Device &d = h->d;
     for (int32_t L = 0; L < pl.nlevels; ++L) {
@@ -354,12 +486,14 @@ static int factor_all(qg_handle *h, T *front, T *dinv, const RegParams &rp) {
                 d.asm_ptr.p, d.asm_src.p, d.asm_row.p, d.kval.p, d.reg_sign.p, rp.delta, d.ctb_ptr.p,
                 d.ctb_child.p, d.ctb_col.p, d.rel_ptr.p, d.rel.p);
         const int32_t s0 = pl.lvl_small_ptr[L], s1 = pl.lvl_small_ptr[L + 1];
-        if (s1 > s0)
-            factor_small<T><<<s1 - s0, 256, 0, h->stream>>>(d.lvl_small_sn.p + s0, d.sn_first.p,
-                                                             d.sn_rptr.p, d.fr_off.p, front,
-                                                             d.reg_sign.p, rp.eps, rp.dyn, d.nreg.p);
+        if (s1 > s0) {
+            const size_t lds = (size_t)pl.lvl_small_maxr[L] * pl.lvl_small_maxr[L] * sizeof(T);
+            factor_small<T><<<s1 - s0, 256, lds, h->stream>>>(d.lvl_small_sn.p + s0, d.sn_first.p,
+                                                               d.sn_rptr.p, d.fr_off.p, front,
+                                                               d.reg_sign.p, rp.eps, rp.dyn, d.nreg.p);
+        }
         for (int32_t u = pl.lvl_large_ptr[L]; u < pl.lvl_large_ptr[L + 1]; ++u)
-            factor_large<T>(h, pl.lvl_large_sn[u], front, dinv, rp);
+            factor_large<T>(h, pl.lvl_large_sn[u], front, dinv, sinv, rp);
     }
     QG_HIP(h, hipGetLastError());
     return QG_OK;
@@ -367,16 +501,25 @@ static int factor_all(qg_handle *h, T *front, T *dinv, const RegParams &rp) {
 
 __global__ void zero_int(int32_t *p) { *p = 0; }
 
+int factor_init_attributes(qg_handle *h) {
+    const int bytes = SMALL_R * SMALL_R * (int)sizeof(double);
+    QG_HIP(h, hipFuncSetAttribute(reinterpret_cast<const void *>(&factor_small<double>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+    QG_HIP(h, hipFuncSetAttribute(reinterpret_cast<const void *>(&factor_small<float>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, bytes / 2));
+    return QG_OK;
+}
+
 int launch_factor(qg_handle *h, int precision) {
     const qg_settings &st = h->st;
     zero_int<<<1, 1, 0, h->stream>>>(h->d.nreg.p);
     int rc;
     if (precision == QG_FP32_IR) {
         RegParams rp{st.static_reg32, st.dyn_eps32, st.dyn_delta32};
-        rc = factor_all<float>(h, h->d.front32.p, h->d.dinv32.p, rp);
+        rc = factor_all<float>(h, h->d.front32.p, h->d.dinv32.p, h->d.sinv32.p, rp);
     } else {
         RegParams rp{st.static_reg, st.dyn_eps, st.dyn_delta};
-        rc = factor_all<double>(h, h->d.front64.p, h->d.dinv64.p, rp);
+        rc = factor_all<double>(h, h->d.front64.p, h->d.dinv64.p, h->d.sinv64.p, rp);
     }
     h->last_precision = precision;
     return rc;

@@ -169,55 +169,55 @@ int ipm_solve(qg_handle *h, double *xo, double *so, double *yo, double *zo, qg_i
         if (!fp64_only && gscaled < st.switch_gap) fp64_only = true;
         prec = fp64_only ? QG_FP64 : QG_FP32_IR;
         if (prec == QG_FP64 && switch_iter < 0 && st.precision == QG_FP32_IR) switch_iter = it;
-        // scaling + (3,3) block
+        // scaling + (3,3) block, once per iteration
         (void)hipEventRecord(ev.e[6], h->stream);
         if ((rc = launch_scaling(h, d.s.p, d.z.p, d.lam.p, 0))) return fail(rc);
         (void)hipEventRecord(ev.e[7], h->stream);
-        (void)hipEventRecord(ev.e[2], h->stream);
-        if ((rc = launch_factor(h, prec))) return fail(rc);
-        (void)hipEventRecord(ev.e[3], h->stream);
-        ++nfactor;
-        // affine direction
-        if ((rc = launch_build_rhs(h, d.s.p, 1.0, d.rhs.p))) return fail(rc);
-        bool failed = false;
-        if ((rc = solve_with(h, d.rhs.p, dvec, prec, &ir_total, &failed, ev, &ms_solve))) return fail(rc);
-        ++nsolve;
-        ms_factor += elapsed(ev.e[2], ev.e[3]);
+        QG_HIP(h, hipEventSynchronize(ev.e[7]));
         ms_cone += elapsed(ev.e[6], ev.e[7]);
-        if (failed && prec == QG_FP32_IR) {
-            // refinement with the FP32 factor failed: FP64 from here on
-            fp64_only = true;
-            prec = QG_FP64;
-            if (switch_iter < 0) switch_iter = it;
+        // Newton step; an FP32 factor whose refinement fails its test makes
+        // the whole step run again with an FP64 factor (and FP64 from then on)
+        for (int attempt = 0; attempt < 2; ++attempt) {
             (void)hipEventRecord(ev.e[2], h->stream);
             if ((rc = launch_factor(h, prec))) return fail(rc);
             (void)hipEventRecord(ev.e[3], h->stream);
             ++nfactor;
+            // affine direction
+            if ((rc = launch_build_rhs(h, d.s.p, 1.0, d.rhs.p))) return fail(rc);
+            bool failed = false, failed2 = false;
             if ((rc = solve_with(h, d.rhs.p, dvec, prec, &ir_total, &failed, ev, &ms_solve))) return fail(rc);
+            ++nsolve;
             ms_factor += elapsed(ev.e[2], ev.e[3]);
+            int nr = 0;
+            if ((rc = read_nreg(h, &nr))) return fail(rc);
+            nreg_total += nr;
+            if (!failed) {
+                (void)hipEventRecord(ev.e[6], h->stream);
+                if ((rc = launch_ds_from_dz(h, d.s.p, -1.0, dz_of, d.dsa.p))) return fail(rc);
+                if ((rc = launch_reset_steps(h))) return fail(rc);
+                if ((rc = launch_step_min(h, d.s.p, d.dsa.p, 0))) return fail(rc);
+                if ((rc = launch_step_min(h, d.z.p, dz_of, 1))) return fail(rc);
+                // corrector (sigma from the affine step length on the device)
+                if ((rc = launch_corrector(h, d.dsa.p, dz_of, -1.0, nullptr, mu, d.t.p))) return fail(rc);
+                if ((rc = launch_build_rhs(h, d.t.p, -1.0, d.rhs.p))) return fail(rc);
+                (void)hipEventRecord(ev.e[7], h->stream);
+                if ((rc = solve_with(h, d.rhs.p, dvec, prec, &ir_total, &failed2, ev, &ms_solve))) return fail(rc);
+                ++nsolve;
+                ms_cone += elapsed(ev.e[6], ev.e[7]);
+            }
+            if ((failed || failed2) && prec == QG_FP32_IR) {
+                fp64_only = true;
+                prec = QG_FP64;
+                if (switch_iter < 0) switch_iter = it;
+                continue;
+            }
+            break;
         }
-        int nr = 0;
-        if ((rc = read_nreg(h, &nr))) return fail(rc);
-        nreg_total += nr;
-        (void)hipEventRecord(ev.e[6], h->stream);
-        if ((rc = launch_ds_from_dz(h, d.s.p, -1.0, dz_of, d.dsa.p))) return fail(rc);
-        if ((rc = launch_reset_steps(h))) return fail(rc);
-        if ((rc = launch_step_min(h, d.s.p, d.dsa.p, 0))) return fail(rc);
-        if ((rc = launch_step_min(h, d.z.p, dz_of, 1))) return fail(rc);
-        // corrector (sigma from the affine step length on the device)
-        if ((rc = launch_corrector(h, d.dsa.p, dz_of, -1.0, nullptr, mu, d.t.p))) return fail(rc);
-        if ((rc = launch_build_rhs(h, d.t.p, -1.0, d.rhs.p))) return fail(rc);
-        (void)hipEventRecord(ev.e[7], h->stream);
-        ms_cone += 0.0;
-        if ((rc = solve_with(h, d.rhs.p, dvec, prec, &ir_total, &failed, ev, &ms_solve))) return fail(rc);
-        ++nsolve;
-        ms_cone += elapsed(ev.e[6], ev.e[7]);
         (void)hipEventRecord(ev.e[6], h->stream);
         if ((rc = launch_ds_from_dz(h, d.t.p, 1.0, dz_of, d.ds.p))) return fail(rc);
         if ((rc = launch_step_min(h, d.s.p, d.ds.p, 2))) return fail(rc);
         if ((rc = launch_step_min(h, d.z.p, dz_of, 3))) return fail(rc);
         if ((rc = launch_update(h, dvec, d.ds.p, st.step_frac, d.alpha.p + 1))) return fail(rc);
-        (void)hipEventRecord(ev.e[7], h->stream);
         (void)hipEventRecord(ev.e[1], h->stream);
         QG_HIP(h, hipEventSynchronize(ev.e[1]));
         ms_cone += elapsed(ev.e[6], ev.e[7]);

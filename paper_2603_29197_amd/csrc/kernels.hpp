@@ -8,10 +8,13 @@
 namespace qg {
 
 // Fronts with r <= SMALL_R are factored and solved one workgroup per front
-// entirely in LDS (r * r * 8 bytes <= 32 KiB); larger fronts use the
-// blocked multi-kernel path with panels of NB columns.
-constexpr int SMALL_R = 64;
+// entirely in LDS (r * r * 8 bytes <= 128 KiB of the 160 KiB per CU);
+// larger fronts use the blocked multi-kernel path: panels of NB columns
+// inside super-panels of SB columns, whose trailing update runs once per
+// super-panel (rank SB).
+constexpr int SMALL_R = 128;
 constexpr int NB = 64;
+constexpr int SB = 256;
 
 // Kind of a permuted KKT column: primal x, equality y, cone z.  Pivot signs
 // of the quasi-definite matrix: + for x, - for y and z; static
@@ -20,6 +23,10 @@ __host__ __device__ inline double pivot_sign(int8_t kind) { return kind == 0 ? 1
 __host__ __device__ inline double static_reg(int8_t kind, double delta) {
     return kind == 0 ? delta : (kind == 1 ? -delta : 0.0);
 }
+
+// Maximum that propagates NaN (fmax drops it): a NaN anywhere in a max-norm
+// must fail the tests built on it, never pass them.
+__host__ __device__ inline double nan_max(double a, double b) { return (a != a || a > b) ? a : b; }
 
 struct RegParams {
     double delta;     // static regularization

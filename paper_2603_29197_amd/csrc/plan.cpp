@@ -62,7 +62,8 @@ void dfree_all(qg_handle *h) {
     dfree(d.lvl_small_sn); dfree(d.sn_rptr); dfree(d.fr_off); dfree(d.task_ptr); dfree(d.asm_ptr);
     dfree(d.asm_src); dfree(d.ctb_ptr); dfree(d.rel_ptr); dfree(d.uv_off); dfree(d.reg_sign);
     dfree(d.front64); dfree(d.front32); dfree(d.uvec); dfree(d.dinv64); dfree(d.dinv32);
-    dfree(d.vbuf); dfree(d.col2sn); dfree(d.nreg);
+    dfree(d.sinv64); dfree(d.sinv32);
+    dfree(d.vbuf); dfree(d.col2sn); dfree(d.nreg); dfree(d.vwork); dfree(d.task0);
     dfree(d.x); dfree(d.y); dfree(d.s); dfree(d.z); dfree(d.rx); dfree(d.ry); dfree(d.rz);
     dfree(d.kx); dfree(d.rhs); dfree(d.sol); dfree(d.res); dfree(d.corr); dfree(d.xp);
     dfree(d.dsa); dfree(d.ds); dfree(d.t); dfree(d.lam); dfree(d.w); dfree(d.wbar); dfree(d.beta);
@@ -99,6 +100,19 @@ int build_plan(qg_handle *h) {
         pl.dinv_off[s + 1] = pl.dinv_off[s] + (r > SMALL_R ? ((k + NB - 1) / NB) * NB * NB : 0);
     }
     pl.dinv_total = pl.dinv_off[ns];
+    pl.sinv_off.assign((size_t)ns + 1, 0);
+    for (int32_t s = 0; s < ns; ++s) {
+        const int64_t r = pl.sn_rptr[s + 1] - pl.sn_rptr[s];
+        const int64_t k = pl.sn_first[s + 1] - pl.sn_first[s];
+        int64_t sz = 0;
+        if (r > SMALL_R)
+            for (int64_t J0 = 0; J0 < k; J0 += SB) {
+                const int64_t ld = (std::min<int64_t>(SB, k - J0) + NB - 1) / NB * NB;
+                sz += 2 * ld * ld;
+            }
+        pl.sinv_off[s + 1] = pl.sinv_off[s] + sz;
+    }
+    pl.sinv_total = pl.sinv_off[ns];
     // levels
     pl.lvl_ptr.assign((size_t)pl.nlevels + 1, 0);
     for (int32_t s = 0; s < ns; ++s) pl.lvl_ptr[sym.sn_level[s] + 1]++;
@@ -108,6 +122,7 @@ int build_plan(qg_handle *h) {
         std::vector<int32_t> fill(pl.lvl_ptr.begin(), pl.lvl_ptr.end() - 1);
         for (int32_t s = 0; s < ns; ++s) pl.lvl_sn[fill[sym.sn_level[s]]++] = s;
     }
+    pl.lvl_small_maxr.assign((size_t)pl.nlevels, 0);
     pl.lvl_small_ptr.assign((size_t)pl.nlevels + 1, 0);
     pl.lvl_large_ptr.assign((size_t)pl.nlevels + 1, 0);
     pl.lvl_small_sn.clear();
@@ -116,8 +131,12 @@ int build_plan(qg_handle *h) {
         for (int32_t t = pl.lvl_ptr[L]; t < pl.lvl_ptr[L + 1]; ++t) {
             const int32_t s = pl.lvl_sn[t];
             const int64_t r = pl.sn_rptr[s + 1] - pl.sn_rptr[s];
-            if (r <= SMALL_R) pl.lvl_small_sn.push_back(s);
-            else pl.lvl_large_sn.push_back(s);
+            if (r <= SMALL_R) {
+                pl.lvl_small_sn.push_back(s);
+                pl.lvl_small_maxr[L] = std::max<int32_t>(pl.lvl_small_maxr[L], (int32_t)r);
+            } else {
+                pl.lvl_large_sn.push_back(s);
+            }
         }
         pl.lvl_small_ptr[L + 1] = (int32_t)pl.lvl_small_sn.size();
         pl.lvl_large_ptr[L + 1] = (int32_t)pl.lvl_large_sn.size();
@@ -169,6 +188,7 @@ int build_plan(qg_handle *h) {
         pl.task_ptr[L + 1] = (int64_t)pl.task_sn.size();
     }
     const int64_t ntask = (int64_t)pl.task_sn.size();
+    pl.task0 = task_base;
     // K entries per task
     std::vector<int32_t> col2sn(N);
     for (int32_t s = 0; s < ns; ++s)

@@ -39,9 +39,11 @@ struct Plan {
     std::vector<int64_t> fr_off;          // ns + 1 (front offsets, elements)
     std::vector<int32_t> lvl_ptr, lvl_sn; // supernodes by level
     std::vector<int32_t> lvl_small_ptr, lvl_small_sn;   // small ones by level
+    std::vector<int32_t> lvl_small_maxr;                // largest small front per level
     std::vector<int32_t> lvl_large_ptr, lvl_large_sn;   // large ones by level
     std::vector<int64_t> task_ptr;        // per level: column tasks (s, j)
     std::vector<int32_t> task_sn, task_col;
+    std::vector<int64_t> task0;           // per supernode: task index of its column 0
     std::vector<int64_t> asm_ptr;         // per (s, j) task: K entries of that column
     std::vector<int64_t> asm_src;         // index into kval
     std::vector<int32_t> asm_row;         // local row in the front
@@ -52,6 +54,8 @@ struct Plan {
     std::vector<int64_t> uv_off;          // per supernode: offset of its update vector (solves)
     std::vector<int64_t> dinv_off;        // per supernode: offset of its inverse diagonal blocks
     int64_t dinv_total = 0;
+    std::vector<int64_t> sinv_off;        // per supernode: inverses (X, X') of its SB x SB diagonal blocks
+    int64_t sinv_total = 0;
     std::vector<int32_t> ch_ptr, ch_list; // children supernodes
     std::vector<int8_t> reg_sign;         // per permuted column: +1 x, -1 y, 0 z
     int64_t front_total = 0, uv_total = 0;
@@ -78,8 +82,12 @@ struct Device {
     DBuf<double> front64;
     DBuf<float> front32;
     DBuf<double> uvec;          // update vectors of the triangular solves
+    DBuf<double> vwork;         // per (front, row) task: gathered solve vector
+    DBuf<int64_t> task0;
     DBuf<double> dinv64;        // inverses of the NB x NB diagonal blocks of large fronts
     DBuf<float> dinv32;
+    DBuf<double> sinv64;        // inverses of the SB x SB diagonal blocks (and transposes)
+    DBuf<float> sinv32;
     DBuf<double> vbuf;          // work vector of length max_r (large-front solves)
     DBuf<int32_t> col2sn;
     DBuf<int32_t> nreg;         // dynamic regularization counter
@@ -159,6 +167,7 @@ int launch_cone_op(qg_handle *h, int op, const double *u, const double *v, doubl
 int launch_corrector(qg_handle *h, const double *dsa, const double *dza, double sigma_mu,
                      const double *alpha_aff_dev, double mu, double *t);
 int read_nreg(qg_handle *h, int *nreg);
+int factor_init_attributes(qg_handle *h);
 void prof_collect(qg_handle *h, int64_t *launches, double *ms, double *flops);
 
 int ipm_solve(qg_handle *h, double *x, double *s, double *y, double *z, qg_info *info);

@@ -5,6 +5,8 @@
 // on scheduling.
 #include "vec.hpp"
 
+#include <cmath>
+
 namespace qg {
 
 // Per-block reduction helper: NS slots, each either a sum or a max-abs.
@@ -18,7 +20,7 @@ __device__ inline void block_reduce_store(double (&val)[NS], const uint32_t maxm
         const bool ismax = (maxmask >> q) & 1u;
         for (int off = 32; off > 0; off >>= 1) {
             const double o = __shfl_xor(v, off);
-            v = ismax ? fmax(v, o) : v + o;
+            v = ismax ? nan_max(v, o) : v + o;
         }
         if (lane == 0) sh[q][wave] = v;
     }
@@ -27,7 +29,7 @@ __device__ inline void block_reduce_store(double (&val)[NS], const uint32_t maxm
         const int q = threadIdx.x;
         const bool ismax = (maxmask >> q) & 1u;
         double v = sh[q][0];
-        for (int w = 1; w < 4; ++w) v = ismax ? fmax(v, sh[q][w]) : v + sh[q][w];
+        for (int w = 1; w < 4; ++w) v = ismax ? nan_max(v, sh[q][w]) : v + sh[q][w];
         partials[(int64_t)blockIdx.x * NS + q] = v;
     }
 }
@@ -41,7 +43,7 @@ __global__ void __launch_bounds__(256) finish_reduce(const double *__restrict__ 
     double v = ismax ? -INFINITY : 0.0;
     for (int32_t b = 0; b < nblk; ++b) {
         const double x = partials[(int64_t)b * ns + q];
-        v = ismax ? fmax(v, x) : v + x;
+        v = ismax ? nan_max(v, x) : v + x;
     }
     out[q] = v;
 }
@@ -246,7 +248,8 @@ int refined_solve(qg_handle *h, const double *rhs, double *x, int precision, int
     bool passed = false;
     for (; k < ir_max; ++k) {
         if ((rc = launch_kkt_residual(h, rhs, x, h->d.res.p, nrm))) return rc;
-        if (!(nrm[0] > h->st.ir_tol * (1.0 + nrm[1]))) { passed = true; break; }
+        if (nrm[0] <= h->st.ir_tol * (1.0 + nrm[1])) { passed = true; break; }
+        if (!std::isfinite(nrm[0])) break;     // a non-finite solve never passes
         if ((rc = launch_solve(h, h->d.res.p, h->d.corr.p, precision))) return rc;
         if ((rc = launch_axpy(h, h->N, 1.0, h->d.corr.p, x))) return rc;
     }

@@ -129,6 +129,16 @@ typedef struct {
     const qg_int *super_ptr;   /* nsuper + 1: relaxed supernode first columns, then N */
     const qg_nnz *rows_ptr;    /* nsuper + 1 */
     const qg_int *rows;        /* rows_ptr[nsuper]: sorted row list of each relaxed supernode */
+    /* Fronts the device factors on: the relaxed supernodes, with each child of at most 16
+     * columns whose front would exceed 128 rows merged into its parent's front as leading
+     * pivots.  Numbered in the front order: column k of the fronts is original KKT index
+     * front_perm[k], a reordering of the elimination tree that keeps every column after its
+     * descendants (so L is the same matrix with renamed rows and columns). */
+    qg_int nfront;
+    const qg_int *front_perm;      /* N */
+    const qg_int *front_ptr;       /* nfront + 1: first column of each front, then N */
+    const qg_nnz *front_rows_ptr;  /* nfront + 1 */
+    const qg_int *front_rows;      /* sorted rows of each front (front numbering) */
 } qg_pattern;
 
 typedef struct qg_handle qg_handle;      /* device solver state */

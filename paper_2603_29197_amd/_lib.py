@@ -69,7 +69,8 @@ class qg_pattern(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int32), ("nsuper_fund", ctypes.c_int32), ("nsuper", ctypes.c_int32),
                 ("perm", c_int32_p), ("iperm", c_int32_p), ("parent", c_int32_p), ("colcount", c_int64_p),
                 ("super_fund", c_int32_p), ("super_ptr", c_int32_p), ("rows_ptr", c_int64_p),
-                ("rows", c_int32_p)]
+                ("rows", c_int32_p), ("nfront", ctypes.c_int32), ("front_perm", c_int32_p),
+                ("front_ptr", c_int32_p), ("front_rows_ptr", c_int64_p), ("front_rows", c_int32_p)]
 
 
 EXPORTS = [

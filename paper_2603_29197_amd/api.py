@@ -59,7 +59,15 @@ def _pattern_dict(pt: qg_pattern) -> dict:
     return dict(N=N, perm=arr(pt.perm, N, np.int32), iperm=arr(pt.iperm, N, np.int32),
                 parent=arr(pt.parent, N, np.int32), colcount=arr(pt.colcount, N, np.int64),
                 super_fund=arr(pt.super_fund, nf + 1, np.int32), super_ptr=arr(pt.super_ptr, ns + 1, np.int32),
-                rows_ptr=rows_ptr, rows=arr(pt.rows, int(rows_ptr[-1]), np.int32))
+                rows_ptr=rows_ptr, rows=arr(pt.rows, int(rows_ptr[-1]), np.int32),
+                **_fronts_dict(pt, arr))
+
+
+def _fronts_dict(pt: qg_pattern, arr) -> dict:
+    nfr = pt.nfront
+    frp = arr(pt.front_rows_ptr, nfr + 1, np.int64)
+    return dict(front_perm=arr(pt.front_perm, pt.N, np.int32), front_ptr=arr(pt.front_ptr, nfr + 1, np.int32),
+                front_rows_ptr=frp, front_rows=arr(pt.front_rows, int(frp[-1]), np.int32))
 
 
 def _args(prob):

@@ -1,5 +1,6 @@
 // C ABI (qg.h): setup / update / solve / backward, the host-only analysis,
 // and the step-level entry points.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -12,6 +13,7 @@ struct qg_symbolic {
     qg::ProblemPattern pp;
     qg::KktPattern kp;
     qg::Symbolic sym;
+    qg::Symbolic fronts;
 };
 
 namespace qg {
@@ -59,7 +61,7 @@ static int allocate_device(qg_handle *h) {
     const KktPattern &kp = h->kp;
     int rc;
 #define UP(buf, vec) if ((rc = dupload(h, d.buf, vec))) return rc
-    std::vector<int32_t> perm(h->sym.perm), iperm(h->sym.iperm);
+    std::vector<int32_t> perm(h->fronts.perm), iperm(h->fronts.iperm);
     UP(perm, perm);
     UP(iperm, iperm);
     UP(blk33, kp.blk33);
@@ -103,6 +105,7 @@ static int allocate_device(qg_handle *h) {
     if ((rc = dalloc(h, d.sinv64, (size_t)pl.sinv_total))) return rc;
     if ((rc = dalloc(h, d.sinv32, (size_t)pl.sinv_total))) return rc;
     if ((rc = dalloc(h, d.vbuf, (size_t)pl.max_r))) return rc;
+    if ((rc = dalloc(h, d.ybuf, (size_t)SB))) return rc;
     if ((rc = dalloc(h, d.nreg, 1))) return rc;
     if ((rc = dalloc(h, d.x, (size_t)h->n))) return rc;
     if ((rc = dalloc(h, d.y, (size_t)h->p))) return rc;
@@ -126,7 +129,8 @@ static int allocate_device(qg_handle *h) {
     if ((rc = dalloc(h, d.scal, 64))) return rc;
     if ((rc = dalloc(h, d.alpha, 4))) return rc;
     if ((rc = dalloc(h, d.amin, 4))) return rc;
-    const size_t nblk = (N + 255) / 256 + (size_t)((h->pp.l + h->pp.nsoc + 255) / 256) + 1;
+    // per-block partials: the sparse residual kernels use 256 / RL rows per block
+    const size_t nblk = (N + 256 / RL - 1) / (256 / RL) + (size_t)((h->pp.l + h->pp.nsoc + 255) / 256) + 1;
     if ((rc = dalloc(h, d.partials, nblk * NSCAL))) return rc;
     return QG_OK;
 }
@@ -197,6 +201,7 @@ int qg_analyze(qg_symbolic **out, qg_int n, qg_int m, qg_int p, const qg_csc *P,
         if (rc) { delete s; return rc; }
         build_kkt_pattern(s->pp, s->kp);
         analyze_pattern(s->kp, s->sym);
+        if ((rc = group_fronts(s->sym, s->fronts))) { delete s; return rc; }
     } catch (const std::bad_alloc &) {
         delete s;
         return QG_ERR_OOM;
@@ -208,7 +213,7 @@ int qg_analyze(qg_symbolic **out, qg_int n, qg_int m, qg_int p, const qg_csc *P,
     return QG_OK;
 }
 
-static void fill_pattern(const Symbolic &sym, qg_pattern *o) {
+static void fill_pattern(const Symbolic &sym, const Symbolic &fr, qg_pattern *o) {
     o->N = sym.N;
     o->nsuper_fund = (qg_int)sym.super_fund.size() - 1;
     o->nsuper = (qg_int)sym.super_ptr.size() - 1;
@@ -220,11 +225,16 @@ static void fill_pattern(const Symbolic &sym, qg_pattern *o) {
     o->super_ptr = sym.super_ptr.data();
     o->rows_ptr = sym.rows_ptr.data();
     o->rows = sym.rows.data();
+    o->nfront = (qg_int)fr.super_ptr.size() - 1;
+    o->front_perm = fr.perm.data();
+    o->front_ptr = fr.super_ptr.data();
+    o->front_rows_ptr = fr.rows_ptr.data();
+    o->front_rows = fr.rows.data();
 }
 
 int qg_symbolic_pattern(const qg_symbolic *sym, qg_pattern *out) {
     if (!sym || !out) return QG_ERR_ARG;
-    fill_pattern(sym->sym, out);
+    fill_pattern(sym->sym, sym->fronts, out);
     return QG_OK;
 }
 
@@ -322,7 +332,7 @@ int qg_backward(qg_handle *h, const double *dl_dx, double *dl_dc, double *dl_dh,
 
 int qg_get_pattern(const qg_handle *h, qg_pattern *out) {
     if (!h || !out) return QG_ERR_ARG;
-    fill_pattern(h->sym, out);
+    fill_pattern(h->sym, h->fronts, out);
     return QG_OK;
 }
 
@@ -373,20 +383,26 @@ int qg_step_get_factor(const qg_handle *h, const int64_t *Lp, const int32_t *Li,
         QG_HIP(hh, hipMemcpyAsync(fr.data(), h->d.front64.p, sizeof(double) * tot, hipMemcpyDeviceToHost, h->stream));
         QG_HIP(hh, hipStreamSynchronize(h->stream));
     }
-    for (int32_t s = 0; s < pl.ns; ++s) {
-        const int32_t f = pl.sn_first[s], k = pl.sn_first[s + 1] - f;
+    // L and D in the analysis' numbering: column j of the analysis is column
+    // fronts.iperm[sym.perm[j]] of the device fronts
+    const int32_t N = h->N;
+    std::vector<int32_t> dev(N), grp(N);
+    for (int32_t j = 0; j < N; ++j) dev[j] = h->fronts.iperm[h->sym.perm[j]];
+    for (int32_t s = 0; s < pl.ns; ++s)
+        for (int32_t c = pl.sn_first[s]; c < pl.sn_first[s + 1]; ++c) grp[c] = s;
+    for (int32_t col = 0; col < N; ++col) {
+        const int32_t dc = dev[col], s = grp[dc];
+        const int32_t jc = dc - pl.sn_first[s];
         const int64_t r = pl.sn_rptr[s + 1] - pl.sn_rptr[s];
         const int32_t *rows = pl.sn_rows.data() + pl.sn_rptr[s];
         const double *F = fr.data() + pl.fr_off[s];
-        for (int32_t jc = 0; jc < k; ++jc) {
-            const int32_t col = f + jc;
-            D[col] = F[(int64_t)jc * r + jc];
-            int64_t pos = jc + 1;
-            for (int64_t t = Lp[col]; t < Lp[col + 1]; ++t) {
-                while (pos < r && rows[pos] < Li[t]) ++pos;
-                if (pos >= r || rows[pos] != Li[t]) return QG_ERR_PATTERN;
-                Lx[t] = F[(int64_t)jc * r + pos];
-            }
+        D[col] = F[(int64_t)jc * r + jc];
+        for (int64_t t = Lp[col]; t < Lp[col + 1]; ++t) {
+            if (Li[t] <= col || Li[t] >= N) return QG_ERR_PATTERN;
+            const int32_t di = dev[Li[t]];
+            const int32_t *it = std::lower_bound(rows, rows + r, di);
+            if (it == rows + r || *it != di || it - rows <= jc) return QG_ERR_PATTERN;
+            Lx[t] = F[(int64_t)jc * r + (it - rows)];
         }
     }
     return QG_OK;

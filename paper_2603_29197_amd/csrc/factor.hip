@@ -141,91 +141,157 @@ __global__ void __launch_bounds__(256) factor_small(
 // ---------------------------------------------------------------------------
 // large fronts
 // ---------------------------------------------------------------------------
+// Value of lane `src` (a compile-time constant) of v, for every lane.
+__device__ inline float lane_bcast(float v, int src) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+}
+__device__ inline double lane_bcast(double v, int src) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+    return __hiloint2double(hi, lo);
+}
+
 // LDL' of the b x b diagonal block at (j0, j0) of the front F (ld r), in
-// place; the inverse of the unit lower factor goes to Xg (ld NB).
-// Thread t owns column c = t % 64 and rows t / 64 + 4 m (m = 0..15) of the
-// block in registers; at pivot jj the owner of column jj in each wavefront
-// publishes its part of the column through a double-buffered LDS slot, so a
-// pivot step costs one barrier; updates are selects, not branches, and the
-// regularization events are added to the counter once at the end.
+// place; the inverse of its unit lower factor goes to Xg (ld NB, zeros above
+// the diagonal).  The block is staged in LDS and factored 16 columns at a
+// time: wavefront 0 factors the 16 x 16 diagonal sub-block in registers
+// (lane i holds row i; the column of each pivot is read with lane
+// broadcasts, so a pivot step has no barrier) and inverts its unit lower
+// factor; then all four wavefronts form the L rows below it within the block
+// and apply its rank-16 update to the rest of the block.  The inverse of the
+// whole unit lower factor is assembled from the 16 x 16 inverses at the end,
+// X_pq = -X_pp sum_{m=q}^{p-1} L_pm X_mq.
 template <typename T>
 __global__ void __launch_bounds__(256) diag_block(T *__restrict__ F, int32_t r, int32_t j0, int32_t b,
                                                   const int8_t *__restrict__ kind_cols, double eps,
                                                   double dyn, int32_t *nreg, T *__restrict__ Xg) {
-    __shared__ T colbuf[2][NB];
-    __shared__ T Ls[NB * NB];     // final L (strictly lower) by column: Ls[c * NB + i]
+    constexpr int LD = NB + 1;           // padded leading dimension of the LDS tiles
+    constexpr int PB = 16;               // sub-block width
+    __shared__ T S[NB * LD];             // S[c * LD + i]: block, becomes L (strictly lower) and D (diagonal)
+    __shared__ T X[NB * LD];             // inverse of the unit lower factor
+    __shared__ T Tm[PB * NB];            // partial sums of the off-diagonal inverse blocks
+    __shared__ T Dd[NB];
     __shared__ double sgn[NB];
     const int tid = threadIdx.x;
-    const int c = tid & 63, i0 = tid >> 6;
-    if (tid < NB) sgn[tid] = tid < b ? pivot_sign(kind_cols[j0 + tid]) : 1.0;
-    T a[16];
-#pragma unroll
-    for (int m = 0; m < 16; ++m) {
-        const int i = i0 + 4 * m;
-        a[m] = (i < b && c < b && i >= c) ? F[(int64_t)(j0 + c) * r + j0 + i] : T(0);
+    const int lane = tid & 63, wave = tid >> 6;
+    for (int idx = tid; idx < NB * NB; idx += 256) {
+        const int i = idx & 63, c = idx >> 6;
+        S[c * LD + i] = (i < b && c < b && i >= c) ? F[(int64_t)(j0 + c) * r + j0 + i] : T(0);
+        X[c * LD + i] = T(0);
     }
+    if (tid < NB) sgn[tid] = tid < b ? pivot_sign(kind_cols[j0 + tid]) : 1.0;
+    __syncthreads();
     int events = 0;
-    for (int32_t jj = 0; jj < b; ++jj) {
-        const int buf = jj & 1;
-        if (c == jj) {
+    for (int p0 = 0; p0 < b; p0 += PB) {
+        const int pb = min(PB, b - p0);
+        if (wave == 0) {
+            // rows p0 + lane (lane < pb), columns p0 .. p0+15
+            T a[PB];
+            T dmine = T(0);
+            const bool mine = lane < pb;
 #pragma unroll
-            for (int m = 0; m < 16; ++m) colbuf[buf][i0 + 4 * m] = a[m];
+            for (int m = 0; m < PB; ++m) a[m] = (mine && m < pb) ? S[(p0 + m) * LD + p0 + lane] : T(0);
+#pragma unroll
+            for (int j = 0; j < PB; ++j) {
+                if (j < pb) {
+                    const T raw = lane_bcast(a[j], j);
+                    const double sg = sgn[p0 + j];
+                    const bool fix = !(sg * (double)raw > eps);
+                    const T d = fix ? (T)(sg * dyn) : raw;
+                    events += fix ? 1 : 0;
+                    const T inv = T(1) / d;
+                    const T l = lane > j ? a[j] * inv : T(0);
+#pragma unroll
+                    for (int k = j + 1; k < PB; ++k) a[k] -= l * lane_bcast(a[j], k);
+                    a[j] = lane > j ? l : (lane == j ? d : a[j]);
+                    dmine = lane == j ? d : dmine;
+                }
+            }
+            // inverse of the unit lower sub-block: lane c forms column c
+            T x[PB];
+#pragma unroll
+            for (int k = 0; k < PB; ++k) x[k] = (k == lane) ? T(1) : T(0);
+#pragma unroll
+            for (int m = 0; m < PB; ++m)
+#pragma unroll
+                for (int k = m + 1; k < PB; ++k) x[k] -= lane_bcast(a[m], k) * x[m];
+            if (mine) {
+#pragma unroll
+                for (int m = 0; m < PB; ++m)
+                    if (m <= lane) S[(p0 + m) * LD + p0 + lane] = a[m];
+                Dd[p0 + lane] = dmine;
+#pragma unroll
+                for (int k = 0; k < PB; ++k)
+                    if (k < pb && k >= lane) X[(p0 + lane) * LD + p0 + k] = x[k];
+            }
         }
         __syncthreads();
-        // every thread forms the same regularized pivot
-        const T raw = colbuf[buf][jj];
-        const double sg = sgn[jj];
-        const bool fix = !(sg * (double)raw > eps);
-        const T d = fix ? (T)(sg * dyn) : raw;
-        events += (fix && tid == 0) ? 1 : 0;
-        const T inv = T(1) / d;
-        const T w = colbuf[buf][c] * inv;
-        const bool upd = c > jj && c < b;
-        const bool own = c == jj;
+        // L rows below the sub-block within the block: L(i, p) = A(i, p) X_pp' D_p^-1
+        const int i0 = p0 + pb, nb = b - i0;
+        if (nb > 0) {
+            T out[3];
 #pragma unroll
-        for (int m = 0; m < 16; ++m) {
-            const int i = i0 + 4 * m;
-            const T u = colbuf[buf][i];
-            const T up = a[m] - u * w;
-            const T sc = (i == jj) ? d : a[m] * inv;
-            a[m] = (upd && i >= c && i < b) ? up : ((own && i >= jj && i < b) ? sc : a[m]);
+            for (int t = 0; t < 3; ++t) {
+                const int e = tid + 256 * t;
+                const int i = i0 + (e >> 4), m = e & 15;
+                T acc = T(0);
+                if (i < b && m < pb)
+                    for (int q = 0; q <= m; ++q) acc += S[(p0 + q) * LD + i] * X[(p0 + q) * LD + p0 + m];
+                out[t] = acc;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int t = 0; t < 3; ++t) {
+                const int e = tid + 256 * t;
+                const int i = i0 + (e >> 4), m = e & 15;
+                if (i < b && m < pb) S[(p0 + m) * LD + i] = out[t] / Dd[p0 + m];
+            }
+            __syncthreads();
+            // rank-pb update of the rest of the block (lower part)
+            for (int e = tid; e < nb * nb; e += 256) {
+                const int i = i0 + e % nb, k = i0 + e / nb;
+                if (i < k) continue;
+                T acc = T(0);
+                for (int m = 0; m < pb; ++m)
+                    acc += S[(p0 + m) * LD + i] * S[(p0 + m) * LD + k] * Dd[p0 + m];
+                S[k * LD + i] -= acc;
+            }
+            __syncthreads();
         }
+    }
+    // off-diagonal blocks of the inverse, block row by block row
+    const int nsub = (b + PB - 1) / PB;
+    for (int p = 1; p < nsub; ++p) {
+        const int n = PB * p;              // columns 0 .. n-1 of block row p
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            const int e = tid + 256 * t;
+            if (e < PB * n) {
+                const int rr = e & 15, c = e >> 4;          // T(rr, c) = sum_{m >= c's block}^{p-1} L(16p+rr, m) X(m, c)
+                const int q0 = (c / PB) * PB;
+                T acc = T(0);
+                for (int m = q0; m < n; ++m) acc += S[m * LD + n + rr] * X[c * LD + m];
+                Tm[c * PB + rr] = acc;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            const int e = tid + 256 * t;
+            if (e < PB * n) {
+                const int rr = e & 15, c = e >> 4;
+                T acc = T(0);
+                for (int q = 0; q <= rr; ++q) acc += X[(n + q) * LD + n + rr] * Tm[c * PB + q];
+                if (n + rr < b && c < b) X[c * LD + n + rr] = -acc;
+            }
+        }
+        __syncthreads();
     }
     if (tid == 0 && events) atomicAdd(nreg, events);
-    // L and D back to the front; L also to LDS for the inverse
-#pragma unroll
-    for (int m = 0; m < 16; ++m) {
-        const int i = i0 + 4 * m;
-        if (i < b && c < b && i >= c) F[(int64_t)(j0 + c) * r + j0 + i] = a[m];
-        Ls[c * NB + i] = (i > c && i < b && c < b) ? a[m] : T(0);
-    }
-    __syncthreads();
-    // X = L^-1 (unit lower), forward substitution by rows: when row t of X is
-    // final its owners publish it, then rows i > t subtract L(i, t) X(t, :).
-    T x[16];
-#pragma unroll
-    for (int m = 0; m < 16; ++m) x[m] = (i0 + 4 * m == c) ? T(1) : T(0);
-    for (int32_t t = 0; t + 1 < b; ++t) {
-        const int buf = t & 1;
-        if (i0 == (t & 3)) {
-            T xt_own = T(0);
-#pragma unroll
-            for (int m = 0; m < 16; ++m) xt_own = (m == (t >> 2)) ? x[m] : xt_own;
-            colbuf[buf][c] = xt_own;                       // X(t, c)
-        }
-        __syncthreads();
-        const T xt = colbuf[buf][c];
-#pragma unroll
-        for (int m = 0; m < 16; ++m) {
-            const int i = i0 + 4 * m;
-            const T nv = x[m] - Ls[t * NB + i] * xt;
-            x[m] = (i > t) ? nv : x[m];
-        }
-    }
-#pragma unroll
-    for (int m = 0; m < 16; ++m) {
-        const int i = i0 + 4 * m;
-        Xg[c * NB + i] = (i < b && c < b && i >= c) ? x[m] : T(0);
+    for (int idx = tid; idx < NB * NB; idx += 256) {
+        const int i = idx & 63, c = idx >> 6;
+        if (i < b && c < b && i >= c) F[(int64_t)(j0 + c) * r + j0 + i] = S[c * LD + i];
+        Xg[c * NB + i] = (i < b && c < b && i >= c) ? X[c * LD + i] : T(0);
     }
 }
 
@@ -301,36 +367,39 @@ __global__ void __launch_bounds__(256) sblock_inverse(const T *__restrict__ F, i
     }
 }
 
-// L21 = A21 X' D^-1 for 64 rows per workgroup (rows j0+b .. r-1).
+// L21 = A21 X' D^-1 for 64 rows per workgroup (rows j0+b .. r-1): the 64 x b
+// tile of A21 is staged through LDS with coalesced loads (all in flight at
+// once), then each thread forms 16 entries of its row.
 template <typename T>
 __global__ void __launch_bounds__(256) panel_solve(T *__restrict__ F, int32_t r, int32_t j0, int32_t b,
                                                    const T *__restrict__ Xg) {
     __shared__ T Xs[NB * NB];
+    __shared__ T As[NB * (NB + 1)];  // As[t * (NB + 1) + i] = A21(row0 + i, t)
     __shared__ T Ds[NB];
     const int tid = threadIdx.x;
-    for (int32_t idx = tid; idx < NB * NB; idx += 256) Xs[idx] = Xg[idx];
+    const int32_t row0 = j0 + b + blockIdx.x * 64;
+    for (int32_t idx = tid; idx < NB * NB; idx += 256) {
+        Xs[idx] = Xg[idx];
+        const int32_t i = idx & 63, t = idx >> 6;
+        As[t * (NB + 1) + i] = (row0 + i < r && t < b) ? F[(int64_t)(j0 + t) * r + row0 + i] : T(0);
+    }
     if (tid < b) Ds[tid] = F[(int64_t)(j0 + tid) * r + j0 + tid];
     __syncthreads();
-    const int32_t row = j0 + b + blockIdx.x * 64 + (tid & 63);
+    const int i = tid & 63;
+    const int32_t row = row0 + i;
     const int32_t cg = tid >> 6;                 // column group 0..3
-    const bool active = row < r;
     T out[NB / 4];
 #pragma unroll
     for (int u = 0; u < NB / 4; ++u) out[u] = T(0);
-#pragma unroll 8
-    for (int32_t t = 0; t < b && active; ++t) {
-        const T a = F[(int64_t)(j0 + t) * r + row];
+    for (int32_t t = 0; t < b; ++t) {
+        const T a = As[t * (NB + 1) + i];
 #pragma unroll
-        for (int u = 0; u < NB / 4; ++u) {
-            const int32_t c = cg + 4 * u;        // X(c, t) nonzero for t <= c
-            out[u] += a * Xs[t * NB + c];
-        }
+        for (int u = 0; u < NB / 4; ++u) out[u] += a * Xs[t * NB + cg + 4 * u];   // X(c, t), zero for t > c
     }
-    __syncthreads();   // every thread of this row has read A21 before it is overwritten
 #pragma unroll
     for (int u = 0; u < NB / 4; ++u) {
         const int32_t c = cg + 4 * u;
-        if (active && c < b) F[(int64_t)(j0 + c) * r + row] = out[u] / Ds[c];
+        if (row < r && c < b) F[(int64_t)(j0 + c) * r + row] = out[u] / Ds[c];
     }
 }
 

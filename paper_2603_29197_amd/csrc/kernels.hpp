@@ -15,6 +15,9 @@ namespace qg {
 constexpr int SMALL_R = 128;
 constexpr int NB = 64;
 constexpr int SB = 256;
+// Lanes per matrix row in the sparse matrix-vector products (16 rows per
+// 256-thread block).
+constexpr int RL = 16;
 
 // Kind of a permuted KKT column: primal x, equality y, cone z.  Pivot signs
 // of the quasi-definite matrix: + for x, - for y and z; static

@@ -63,15 +63,108 @@ void dfree_all(qg_handle *h) {
     dfree(d.asm_src); dfree(d.ctb_ptr); dfree(d.rel_ptr); dfree(d.uv_off); dfree(d.reg_sign);
     dfree(d.front64); dfree(d.front32); dfree(d.uvec); dfree(d.dinv64); dfree(d.dinv32);
     dfree(d.sinv64); dfree(d.sinv32);
-    dfree(d.vbuf); dfree(d.col2sn); dfree(d.nreg); dfree(d.vwork); dfree(d.task0);
+    dfree(d.vbuf); dfree(d.ybuf); dfree(d.col2sn); dfree(d.nreg); dfree(d.vwork); dfree(d.task0);
     dfree(d.x); dfree(d.y); dfree(d.s); dfree(d.z); dfree(d.rx); dfree(d.ry); dfree(d.rz);
     dfree(d.kx); dfree(d.rhs); dfree(d.sol); dfree(d.res); dfree(d.corr); dfree(d.xp);
     dfree(d.dsa); dfree(d.ds); dfree(d.t); dfree(d.lam); dfree(d.w); dfree(d.wbar); dfree(d.beta);
     dfree(d.scal); dfree(d.amin); dfree(d.partials); dfree(d.zcone); dfree(d.alpha);
 }
 
+// Fronts of the device factorization.  The analysis' supernodes are kept,
+// except that a child supernode with at most MERGE_K columns whose own front
+// would be large (r > SMALL_R) is factored inside its parent's front: its
+// columns move to just before the parent's columns and become leading
+// pivots of that front.  Moving a column to just before its elimination-tree
+// ancestor keeps every column after all of its descendants, so this is a
+// renaming of rows and columns under which L keeps its values; the merged
+// front stores the zeros of the child's column explicitly.  It replaces the
+// r x r update matrix such a child would form and its parent would assemble
+// by a few extra dense pivots in the parent front.  The extra columns per
+// front are capped at max(MERGE_K, r / 16).
+constexpr int32_t MERGE_K = 16;
+
+int group_fronts(const Symbolic &sym, Symbolic &g) {
+    const int32_t N = sym.N;
+    const int32_t ns = (int32_t)sym.super_ptr.size() - 1;
+    auto kof = [&](int32_t s) { return sym.super_ptr[s + 1] - sym.super_ptr[s]; };
+    auto rof = [&](int32_t s) { return (int32_t)(sym.rows_ptr[s + 1] - sym.rows_ptr[s]); };
+    std::vector<int32_t> head(ns), extra(ns, 0);
+    for (int32_t s = 0; s < ns; ++s) head[s] = s;
+    for (int32_t s = ns - 1; s >= 0; --s) {     // parents before children
+        const int32_t P = sym.sn_parent[s];
+        if (P < 0) continue;
+        const int32_t H = head[P];
+        const int32_t cap = std::max(MERGE_K, rof(H) / 16);
+        if (rof(s) > SMALL_R && kof(s) <= MERGE_K && rof(H) > SMALL_R && extra[H] + kof(s) <= cap) {
+            head[s] = H;
+            extra[H] += kof(s);
+        }
+    }
+    std::vector<std::vector<int32_t>> members(ns);
+    for (int32_t s = 0; s < ns; ++s) if (head[s] != s) members[head[s]].push_back(s);   // increasing index
+    std::vector<int32_t> new_of_old(N), gidx(ns, -1);
+    g.N = N;
+    g.super_ptr.assign(1, 0);
+    int32_t pos = 0, ng = 0;
+    for (int32_t s = 0; s < ns; ++s) {
+        if (head[s] != s) continue;
+        for (int32_t m : members[s])
+            for (int32_t c = sym.super_ptr[m]; c < sym.super_ptr[m + 1]; ++c) new_of_old[c] = pos++;
+        for (int32_t c = sym.super_ptr[s]; c < sym.super_ptr[s + 1]; ++c) new_of_old[c] = pos++;
+        g.super_ptr.push_back(pos);
+        gidx[s] = ng++;
+    }
+    if (pos != N) return QG_ERR_PATTERN;
+    g.perm.assign(N, 0);
+    g.iperm.assign(N, 0);
+    for (int32_t c = 0; c < N; ++c) {
+        g.perm[new_of_old[c]] = sym.perm[c];
+        g.iperm[sym.perm[c]] = new_of_old[c];
+    }
+    // rows: the group's columns, then the head's rows below its columns (renamed, sorted)
+    g.rows_ptr.assign(1, 0);
+    g.rows.clear();
+    g.sn_parent.assign(ng, -1);
+    std::vector<int32_t> tail;
+    for (int32_t s = 0; s < ns; ++s) {
+        if (head[s] != s) continue;
+        const int32_t G = gidx[s];
+        const int32_t f = g.super_ptr[G], kg = g.super_ptr[G + 1] - f;
+        for (int32_t c = 0; c < kg; ++c) g.rows.push_back(f + c);
+        tail.clear();
+        for (int64_t t = sym.rows_ptr[s] + kof(s); t < sym.rows_ptr[s + 1]; ++t) tail.push_back(new_of_old[sym.rows[t]]);
+        std::sort(tail.begin(), tail.end());
+        if (!tail.empty() && tail[0] < f + kg) return QG_ERR_PATTERN;
+        g.rows.insert(g.rows.end(), tail.begin(), tail.end());
+        g.rows_ptr.push_back((int64_t)g.rows.size());
+        // every merged child's column structure must lie in the merged front
+        const int32_t *gr = g.rows.data() + g.rows_ptr[G], *ge = g.rows.data() + g.rows_ptr[G + 1];
+        for (int32_t m : members[s])
+            for (int64_t t = sym.rows_ptr[m]; t < sym.rows_ptr[m + 1]; ++t)
+                if (!std::binary_search(gr, ge, new_of_old[sym.rows[t]])) return QG_ERR_PATTERN;
+        const int32_t P = sym.sn_parent[s];
+        if (P >= 0) g.sn_parent[G] = gidx[head[P]];
+    }
+    // levels (children precede parents in group order)
+    g.sn_level.assign(ng, 0);
+    g.nlevels = ng > 0 ? 1 : 0;
+    for (int32_t G = 0; G < ng; ++G) {
+        const int32_t P = g.sn_parent[G];
+        if (P >= 0) {
+            if (P <= G) return QG_ERR_PATTERN;
+            g.sn_level[P] = std::max(g.sn_level[P], g.sn_level[G] + 1);
+            g.nlevels = std::max(g.nlevels, g.sn_level[P] + 1);
+        }
+    }
+    g.nnz_L = sym.nnz_L;
+    g.flops = sym.flops;
+    return QG_OK;
+}
+
 int build_plan(qg_handle *h) {
-    const Symbolic &sym = h->sym;
+    int rc0 = group_fronts(h->sym, h->fronts);
+    if (rc0) return rc0;
+    const Symbolic &sym = h->fronts;
     const KktPattern &kp = h->kp;
     Plan &pl = h->plan;
     const int32_t N = sym.N;

@@ -89,6 +89,7 @@ struct Device {
     DBuf<double> sinv64;        // inverses of the SB x SB diagonal blocks (and transposes)
     DBuf<float> sinv32;
     DBuf<double> vbuf;          // work vector of length max_r (large-front solves)
+    DBuf<double> ybuf;          // SB: solution of the current super-block in the large-front solves
     DBuf<int32_t> col2sn;
     DBuf<int32_t> nreg;         // dynamic regularization counter
     // iterate and work vectors
@@ -119,7 +120,8 @@ struct qg_handle {
     int device = 0;
     qg::ProblemPattern pp;
     qg::KktPattern kp;
-    qg::Symbolic sym;
+    qg::Symbolic sym;                  // the analysis (supernodes, permutation)
+    qg::Symbolic fronts;               // device fronts: the analysis with small-k children merged
     qg::Plan plan;
     qg::Device d;
     std::vector<double> kval_static;   // K upper values without (3,3) entries
@@ -152,6 +154,7 @@ template <typename T>
 int dupload(qg_handle *h, DBuf<T> &b, const std::vector<T> &v);
 void dfree_all(qg_handle *h);
 
+int group_fronts(const Symbolic &sym, Symbolic &fronts);
 int build_plan(qg_handle *h);
 int upload_static_values(qg_handle *h);
 

@@ -10,10 +10,9 @@
 // precision (FP32 factors are widened on load).
 //
 // Small fronts: one 128-thread workgroup per supernode, per level.  Large
-// fronts: a gather kernel, then one kernel per SB-column super-block that
-// solves with the diagonal block (stored inverses of its 64 x 64 diagonal
-// blocks) and updates the rows below (forward), or the transposed sequence
-// (backward).
+// fronts: per SB-column super-block, one kernel applies the stored inverse of
+// its unit-lower diagonal block (or its transpose) and a second one updates
+// the rows below it (forward) or the columns before it (backward).
 #include "kernels.hpp"
 #include "solver.hpp"
 
@@ -96,39 +95,63 @@ __global__ void __launch_bounds__(SMALL_R) bwd_small(
 }
 
 // ------------------------------- large -------------------------------------
-// Super-block [J0, J0+kb) (kb <= SB): y = X v[J0:J0+kb) with the stored
-// inverse X of the unit-lower diagonal block (one dot product per thread,
-// lanes along rows of the column-major X, leading dimension ld:
-// coalesced); workgroup 0 writes y
-// to the solution; each workgroup then updates 256 rows below:
-// v[row] -= L(row, J0:J0+kb) y (lanes along rows: coalesced).
+// y = X v (forward, X the stored inverse of the unit-lower diagonal block of
+// a super-block) or y = X' v (backward, the stored transpose), kb <= SB;
+// the result goes to y and to the solution.  Workgroup g forms entries
+// 64 g .. 64 g + 63; wavefront w sums over columns q in [64 w, 64 w + 64) of
+// the column-major operand (lanes along rows: coalesced), then the four
+// partial sums are added in a fixed order.
 template <typename T>
-__global__ void __launch_bounds__(256) fwd_sblock(const T *__restrict__ F, int32_t r, int32_t J0, int32_t kb,
-                                                  const T *__restrict__ Xsb, int32_t ld, double *__restrict__ vbuf,
-                                                  double *__restrict__ xp_own) {
-    __shared__ double yin[SB];
-    __shared__ double y[SB];
-    const int tid = threadIdx.x;
-    if (tid < kb) yin[tid] = vbuf[J0 + tid];
+__global__ void __launch_bounds__(256) sblock_apply(const T *__restrict__ X, int32_t ld, int32_t kb,
+                                                    const double *__restrict__ vin, double *__restrict__ y,
+                                                    double *__restrict__ xp_out, int32_t upper) {
+    __shared__ double vs[SB];
+    __shared__ double red[4][64];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int32_t g = blockIdx.x;
+    if (tid < kb) vs[tid] = vin[tid];
     __syncthreads();
-    if (tid < kb) {
-        const int32_t qend = min(kb, ((tid >> 6) + 1) * NB);    // X is lower: blocks right of the wave's are 0
-        const T *Xr = Xsb + tid;
-        double acc = 0.0;
-#pragma unroll 8
-        for (int32_t q = 0; q < qend; ++q) acc += (double)Xr[(int64_t)q * ld] * yin[q];
-        y[tid] = acc;
+    const int32_t t = g * 64 + lane;
+    // lower operand: columns q <= t; upper operand: columns q >= t
+    const bool live = upper ? (w >= g) : (w <= g);
+    double acc = 0.0;
+    if (live && t < kb) {
+        const int32_t q1 = min(kb, 64 * w + 64);
+        const T *Xr = X + t;
+#pragma unroll 16
+        for (int32_t q = 64 * w; q < q1; ++q) acc += (double)Xr[(int64_t)q * ld] * vs[q];
     }
+    red[w][lane] = acc;
     __syncthreads();
-    if (blockIdx.x == 0 && tid < kb) xp_own[J0 + tid] = y[tid];
-    const int32_t row = J0 + kb + blockIdx.x * 256 + tid;
+    if (w == 0 && t < kb) {
+        const double v = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+        y[t] = v;
+        xp_out[t] = v;
+    }
+}
+
+// Forward update of the rows below a super-block: v[row] -= L(row, J0:J0+kb) y
+// for 64 rows per workgroup; wavefront w takes columns [64 w, 64 w + 64)
+// (lanes along rows: coalesced), fixed-order sum over wavefronts.
+template <typename T>
+__global__ void __launch_bounds__(256) sblock_rows(const T *__restrict__ F, int32_t r, int32_t J0, int32_t kb,
+                                                   const double *__restrict__ y, double *__restrict__ vbuf) {
+    __shared__ double ys[SB];
+    __shared__ double red[4][64];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    if (tid < kb) ys[tid] = y[tid];
+    __syncthreads();
+    const int32_t row = J0 + kb + blockIdx.x * 64 + lane;
+    double acc = 0.0;
     if (row < r) {
-        double acc = 0.0;
+        const int32_t q1 = min(kb, 64 * w + 64);
         const T *p = F + (int64_t)J0 * r + row;
 #pragma unroll 16
-        for (int32_t q = 0; q < kb; ++q) acc += (double)p[(int64_t)q * r] * y[q];
-        vbuf[row] -= acc;
+        for (int32_t q = 64 * w; q < q1; ++q) acc += (double)p[(int64_t)q * r] * ys[q];
     }
+    red[w][lane] = acc;
+    __syncthreads();
+    if (w == 0 && row < r) vbuf[row] -= ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
 }
 
 // v[0:k] = D^-1 x_own - L21' g with g = x at the rows below (one column per
@@ -152,43 +175,35 @@ __global__ void __launch_bounds__(256) bwd_init(int32_t s, const int32_t *__rest
     if (lane == 0) vbuf[c] = xp[f + c] / (double)F[(int64_t)c * r + c] - acc;
 }
 
-// Super-block [J0, J0+kb), processed last to first: y = X' v[J0:J0+kb) with
-// the stored transpose of the diagonal block's inverse (coalesced as in the
-// forward case); workgroup 0 writes y to the solution; each workgroup then
-// updates 64 earlier entries: v[c] -= L(J0:J0+kb, c)' y, with lanes running
-// along the contiguous rows t of each column (coalesced) and a wavefront
-// reduction.
+// Backward update of the columns before a super-block:
+// v[c] -= L(J0:J0+kb, c)' y for 64 columns per workgroup, 16 per wavefront;
+// lanes run along the contiguous rows of each column (coalesced), all loads
+// of a wavefront are issued before its 16 shuffle reductions.
 template <typename T>
-__global__ void __launch_bounds__(256) bwd_sblock(const T *__restrict__ F, int32_t r, int32_t J0, int32_t kb,
-                                                  const T *__restrict__ XTsb, int32_t ld, double *__restrict__ vbuf,
-                                                  double *__restrict__ xp_own) {
-    __shared__ double yin[SB];
-    __shared__ double y[SB];
-    const int tid = threadIdx.x;
-    if (tid < kb) yin[tid] = vbuf[J0 + tid];
+__global__ void __launch_bounds__(256) sblock_cols(const T *__restrict__ F, int32_t r, int32_t J0, int32_t kb,
+                                                   const double *__restrict__ y, double *__restrict__ vbuf) {
+    __shared__ double ys[SB];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    if (tid < kb) ys[tid] = y[tid];
     __syncthreads();
-    if (tid < kb) {
-        const int32_t qbeg = (tid >> 6) * NB;                   // X' is upper: blocks left of the wave's are 0
-        const T *Xr = XTsb + tid;
-        double acc = 0.0;
-#pragma unroll 8
-        for (int32_t q = qbeg; q < kb; ++q) acc += (double)Xr[(int64_t)q * ld] * yin[q];
-        y[tid] = acc;
-    }
-    __syncthreads();
-    if (blockIdx.x == 0 && tid < kb) xp_own[J0 + tid] = y[tid];
-    // columns c0 .. c0+63 before the super-block: wave w handles 16 of them
-    const int32_t c0 = blockIdx.x * NB;
-    if (c0 >= J0) return;
-    const int lane = tid & 63, w = tid >> 6;
-    for (int32_t cc = 0; cc < 16; ++cc) {
-        const int32_t c = c0 + w * 16 + cc;
-        if (c >= J0) break;
-        const T *col = F + (int64_t)c * r + J0;
+    const int32_t c0 = blockIdx.x * NB + w * 16;
+    double part[16];
+#pragma unroll
+    for (int cc = 0; cc < 16; ++cc) {
+        const int32_t c = c0 + cc;
         double s = 0.0;
-        for (int32_t t = lane; t < kb; t += 64) s += (double)col[t] * y[t];
+#pragma unroll
+        for (int m = 0; m < SB / 64; ++m) {
+            const int32_t t = lane + 64 * m;
+            if (c < J0 && t < kb) s += (double)F[(int64_t)c * r + J0 + t] * ys[t];
+        }
+        part[cc] = s;
+    }
+#pragma unroll
+    for (int cc = 0; cc < 16; ++cc) {
+        double s = part[cc];
         for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-        if (lane == 0) vbuf[c] -= s;
+        if (lane == 0 && c0 + cc < J0) vbuf[c0 + cc] -= s;
     }
 }
 
@@ -216,11 +231,13 @@ static int solve_perm(qg_handle *h, const T *front, const T *sinv) {
             double *vs = d.vwork.p + pl.task0[s];
             for (int32_t J0 = 0; J0 < k; J0 += SB) {
                 const int32_t kb = std::min(SB, k - J0);
-                const int32_t rows = r - J0 - kb;
-                const unsigned grid = (unsigned)std::max(1, (rows + 255) / 256);
                 const int32_t ld = (kb + NB - 1) / NB * NB;
                 const T *Xsb = sinv + pl.sinv_off[s] + (int64_t)(J0 / SB) * 2 * SB * SB;
-                fwd_sblock<T><<<grid, 256, 0, h->stream>>>(F, r, J0, kb, Xsb, ld, vs, xp + pl.sn_first[s]);
+                sblock_apply<T><<<(kb + 63) / 64, 256, 0, h->stream>>>(Xsb, ld, kb, vs + J0, d.ybuf.p,
+                                                                     xp + pl.sn_first[s] + J0, 0);
+                const int32_t rows = r - J0 - kb;
+                if (rows > 0)
+                    sblock_rows<T><<<(rows + 63) / 64, 256, 0, h->stream>>>(F, r, J0, kb, d.ybuf.p, vs);
             }
         }
     }
@@ -236,10 +253,12 @@ static int solve_perm(qg_handle *h, const T *front, const T *sinv) {
             for (int32_t bi = nsb - 1; bi >= 0; --bi) {
                 const int32_t J0 = bi * SB;
                 const int32_t kb = std::min(SB, k - J0);
-                const unsigned grid = (unsigned)std::max(1, (J0 + NB - 1) / NB);
                 const int32_t ld = (kb + NB - 1) / NB * NB;
                 const T *XTsb = sinv + pl.sinv_off[s] + (int64_t)(J0 / SB) * 2 * SB * SB + (int64_t)ld * ld;
-                bwd_sblock<T><<<grid, 256, 0, h->stream>>>(F, r, J0, kb, XTsb, ld, d.vbuf.p, xp + pl.sn_first[s]);
+                sblock_apply<T><<<(kb + 63) / 64, 256, 0, h->stream>>>(XTsb, ld, kb, d.vbuf.p + J0, d.ybuf.p,
+                                                                     xp + pl.sn_first[s] + J0, 1);
+                if (J0 > 0)
+                    sblock_cols<T><<<(J0 + NB - 1) / NB, 256, 0, h->stream>>>(F, r, J0, kb, d.ybuf.p, d.vbuf.p);
             }
         }
         const int32_t s0 = pl.lvl_small_ptr[L], s1 = pl.lvl_small_ptr[L + 1];

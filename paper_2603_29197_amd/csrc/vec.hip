@@ -34,18 +34,32 @@ __device__ inline void block_reduce_store(double (&val)[NS], const uint32_t maxm
     }
 }
 
+// Second pass: 256 threads, each folds a fixed strided subset of the block
+// partials, then a fixed tree over the threads (deterministic).
 __global__ void __launch_bounds__(256) finish_reduce(const double *__restrict__ partials, int32_t nblk,
                                                      int32_t ns, uint32_t maxmask, double *__restrict__ out) {
-    // one thread per slot, fixed order
-    const int q = threadIdx.x;
-    if (q >= ns) return;
-    const bool ismax = (maxmask >> q) & 1u;
-    double v = ismax ? -INFINITY : 0.0;
-    for (int32_t b = 0; b < nblk; ++b) {
-        const double x = partials[(int64_t)b * ns + q];
-        v = ismax ? nan_max(v, x) : v + x;
+    __shared__ double sh[4];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int q = 0; q < ns; ++q) {
+        const bool ismax = (maxmask >> q) & 1u;
+        double v = ismax ? -INFINITY : 0.0;
+        for (int32_t b = tid; b < nblk; b += 256) {
+            const double x = partials[(int64_t)b * ns + q];
+            v = ismax ? nan_max(v, x) : v + x;
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            const double o = __shfl_xor(v, off);
+            v = ismax ? nan_max(v, o) : v + o;
+        }
+        if (lane == 0) sh[wave] = v;
+        __syncthreads();
+        if (tid == 0) {
+            double w = sh[0];
+            for (int k = 1; k < 4; ++k) w = ismax ? nan_max(w, sh[k]) : w + sh[k];
+            out[q] = w;
+        }
+        __syncthreads();
     }
-    out[q] = v;
 }
 
 // Residuals of problem (1): rx = Px + A'y + G'z + c, ry = Ax - b,
@@ -60,16 +74,25 @@ __global__ void __launch_bounds__(256) residual_kernel(
 #pragma unroll
     for (int q = 0; q < NSCAL; ++q) val[q] = 0.0;
     const int32_t N = n + p + m;
-    const int32_t i = blockIdx.x * 256 + threadIdx.x;
+    const int sub = threadIdx.x & (RL - 1);
+    const int32_t i = blockIdx.x * (256 / RL) + (threadIdx.x / RL);
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
     if (i < N) {
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-        for (int64_t t = kr_ptr[i]; t < kr_ptr[i + 1]; ++t) {
+        for (int64_t t = kr_ptr[i] + sub; t < kr_ptr[i + 1]; t += RL) {
             const int32_t j = kr_col[t];
             const double v = kr_val[t];
             if (j < n) a0 += v * x[j];
             else if (j < n + p) a1 += v * y[j - n];
             else a2 += v * z[j - n - p];
         }
+    }
+#pragma unroll
+    for (int off = RL / 2; off > 0; off >>= 1) {
+        a0 += __shfl_xor(a0, off);
+        a1 += __shfl_xor(a1, off);
+        a2 += __shfl_xor(a2, off);
+    }
+    if (i < N && sub == 0) {
         if (i < n) {
             const double r_ = a0 + a1 + a2 + c[i];
             rx[i] = r_;
@@ -101,26 +124,31 @@ __global__ void __launch_bounds__(256) kkt_residual_kernel(
     double *__restrict__ res, double *__restrict__ partials) {
     double val[2] = {0.0, 0.0};
     const int32_t N = n + p + m;
-    const int32_t i = blockIdx.x * 256 + threadIdx.x;
+    const int sub = threadIdx.x & (RL - 1);
+    const int32_t i = blockIdx.x * (256 / RL) + (threadIdx.x / RL);
+    double acc = 0.0;
     if (i < N) {
-        double acc = 0.0;
-        for (int64_t t = kr_ptr[i]; t < kr_ptr[i + 1]; ++t) acc += kr_val[t] * sol[kr_col[t]];
+        for (int64_t t = kr_ptr[i] + sub; t < kr_ptr[i + 1]; t += RL) acc += kr_val[t] * sol[kr_col[t]];
         if (i >= n + p) {
             const int32_t e = i - n - p;
             const double *zs = sol + n + p;
             if (e < l) {
-                acc += kval[blk33[e]] * zs[e];
+                if (sub == 0) acc += kval[blk33[e]] * zs[e];
             } else {
                 const int32_t k = zcone[e];
                 const int32_t off = soc_off[k], q = soc_off[k + 1] - off;
                 const int32_t a = e - off;
                 const int64_t base = l + blk_off[k];
-                for (int32_t bb = 0; bb < q; ++bb) {
+                for (int32_t bb = sub; bb < q; bb += RL) {
                     const int32_t lo = a < bb ? a : bb, hi = a < bb ? bb : a;
                     acc += kval[blk33[base + (int64_t)hi * (hi + 1) / 2 + lo]] * zs[bb + off];
                 }
             }
         }
+    }
+#pragma unroll
+    for (int off = RL / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if (i < N && sub == 0) {
         const double r_ = rhs[i] - acc;
         res[i] = r_;
         val[0] = fabs(r_);
@@ -190,11 +218,11 @@ int launch_residual(qg_handle *h, const double *x, const double *y, const double
                     double *scal_host) {
     Device &d = h->d;
     const int32_t N = h->N;
-    const int32_t nblk = (N + 255) / 256;
+    const int32_t nblk = (N + 256 / RL - 1) / (256 / RL);
     residual_kernel<<<nblk, 256, 0, h->stream>>>(h->n, h->p, h->m, d.kr_ptr.p, d.kr_col.p, d.kr_val.p, x, y,
                                                   z, s, d.c.p, d.b.p, d.h.p, d.rx.p, d.ry.p, d.rz.p,
                                                   d.partials.p);
-    finish_reduce<<<1, 64, 0, h->stream>>>(d.partials.p, nblk, NSCAL, SCAL_MAXMASK, d.scal.p);
+    finish_reduce<<<1, 256, 0, h->stream>>>(d.partials.p, nblk, NSCAL, SCAL_MAXMASK, d.scal.p);
     QG_HIP(h, hipGetLastError());
     QG_HIP(h, hipMemcpyAsync(scal_host, d.scal.p, NSCAL * sizeof(double), hipMemcpyDeviceToHost, h->stream));
     QG_HIP(h, hipStreamSynchronize(h->stream));
@@ -204,11 +232,11 @@ int launch_residual(qg_handle *h, const double *x, const double *y, const double
 int launch_kkt_residual(qg_handle *h, const double *rhs, const double *sol, double *res, double *norms) {
     Device &d = h->d;
     const int32_t N = h->N;
-    const int32_t nblk = (N + 255) / 256;
+    const int32_t nblk = (N + 256 / RL - 1) / (256 / RL);
     kkt_residual_kernel<<<nblk, 256, 0, h->stream>>>(h->n, h->p, h->m, h->pp.l, d.kr_ptr.p, d.kr_col.p,
                                                       d.kr_val.p, d.kval.p, d.blk33.p, d.blk_off.p,
                                                       d.soc_off.p, d.zcone.p, rhs, sol, res, d.partials.p);
-    finish_reduce<<<1, 64, 0, h->stream>>>(d.partials.p, nblk, 2, 3u, d.scal.p + NSCAL);
+    finish_reduce<<<1, 256, 0, h->stream>>>(d.partials.p, nblk, 2, 3u, d.scal.p + NSCAL);
     QG_HIP(h, hipGetLastError());
     QG_HIP(h, hipMemcpyAsync(norms, d.scal.p + NSCAL, 2 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
     QG_HIP(h, hipStreamSynchronize(h->stream));

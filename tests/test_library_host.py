@@ -55,6 +55,67 @@ def test_analysis_matches_oracle_random_socp(seed):
         assert np.array_equal(a[k], getattr(o, k)), k
 
 
+def _check_fronts(prob, a):
+    """The device fronts: a renaming of the analysis' columns that keeps the
+    elimination tree order, each front a head supernode plus merged children
+    (at most 16 columns, rows > 128), rows covering every column's L."""
+    N = a["N"]
+    fperm = a["front_perm"]
+    assert np.array_equal(np.sort(fperm), np.arange(N))
+    finv = np.empty(N, np.int64); finv[fperm] = np.arange(N)
+    dev = finv[a["perm"]]                       # analysis column -> front column
+    par = a["parent"]
+    has = par >= 0
+    assert np.all(dev[par[has]] > dev[has])    # every column after its descendants
+    fp, frp, fr = a["front_ptr"], a["front_rows_ptr"], a["front_rows"]
+    nfr = len(fp) - 1
+    col2f = np.repeat(np.arange(nfr), np.diff(fp))
+    Up = symbolic.permute_upper(kkt.kkt_pattern(prob), a["perm"])
+    Lp, Li, _ = symbolic.l_pattern(Up, symbolic.etree(Up))
+    for f in range(nfr):
+        rows = fr[frp[f]:frp[f + 1]]
+        k = fp[f + 1] - fp[f]
+        assert np.all(np.diff(rows) > 0)
+        assert np.array_equal(rows[:k], np.arange(fp[f], fp[f + 1]))
+    for j in range(N):
+        c = dev[j]; f = col2f[c]
+        rows = fr[frp[f]:frp[f + 1]]
+        need = dev[Li[Lp[j]:Lp[j + 1]]]
+        assert np.all(need > c)
+        assert np.all(np.isin(need, rows)), j
+    # fronts are unions of supernodes: one head, merged children small and tall
+    sp, rp = a["super_ptr"], a["rows_ptr"]
+    ns = len(sp) - 1
+    sn_front = col2f[dev[sp[:-1]]]
+    for s in range(ns):
+        assert np.all(col2f[dev[np.arange(sp[s], sp[s + 1])]] == sn_front[s])
+    for f in range(nfr):
+        sns = np.where(sn_front == f)[0]
+        head = sns.max()
+        if len(sns) == 1:
+            rows = fr[frp[f]:frp[f + 1]]
+            assert np.array_equal(np.sort(dev[a["rows"][rp[head]:rp[head + 1]]]), rows)
+        for s in sns[:-1]:
+            assert sp[s + 1] - sp[s] <= 16 and rp[s + 1] - rp[s] > 128
+    return nfr, ns
+
+
+@pytest.mark.parametrize("name", ["small_qp", "lasso_s", "lasso_diff_s", "many_soc_s"])
+def test_device_fronts_are_a_valid_grouping(name):
+    import paper_2603_29197_amd as qg
+    prob = problems.workload(name)
+    nfr, ns = _check_fronts(prob, qg.analyze(prob))
+    if name.startswith("lasso"):
+        assert nfr < ns          # the tall one-column children of the dense root are merged
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_device_fronts_random(seed):
+    import paper_2603_29197_amd as qg
+    prob = problems.lasso(300 + 50 * seed, 150 + 20 * seed, 0.03, seed=900 + seed)
+    _check_fronts(prob, qg.analyze(prob))
+
+
 @pytest.mark.parametrize("name", ["huber_s", "many_soc", "lasso"])
 def test_analysis_matches_oracle_digest_full_size(name):
     """Digests written by tests/golden/make_golden.py from the oracle."""

@@ -110,9 +110,16 @@ __global__ void __launch_bounds__(256) factor_small(
     const int32_t k = sn_first[s + 1] - sn_first[s];
     T *G = front + fr_off[s];
     const int tid = threadIdx.x;
-    for (int32_t idx = tid; idx < r * r; idx += 256) {
-        const int32_t i = idx % r, c = idx / r;
-        F[idx] = (i >= c) ? G[idx] : T(0);
+    const int32_t rr = r * r;
+    for (int32_t base = 0; base < rr; base += 256 * 8) {   // 8 loads in flight per thread
+        T g[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) g[u] = ld_or0(G, base + tid + 256 * u, base + tid + 256 * u < rr);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int32_t idx = base + tid + 256 * u;
+            if (idx < rr) F[idx] = (idx % r >= idx / r) ? g[u] : T(0);
+        }
     }
     __syncthreads();
     for (int32_t jj = 0; jj < k; ++jj) {
@@ -174,9 +181,11 @@ __global__ void __launch_bounds__(256) diag_block(T *__restrict__ F, int32_t r, 
     __shared__ double sgn[NB];
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
-    for (int idx = tid; idx < NB * NB; idx += 256) {
+#pragma unroll
+    for (int u = 0; u < NB * NB / 256; ++u) {
+        const int idx = tid + 256 * u;
         const int i = idx & 63, c = idx >> 6;
-        S[c * LD + i] = (i < b && c < b && i >= c) ? F[(int64_t)(j0 + c) * r + j0 + i] : T(0);
+        S[c * LD + i] = ld_or0(F, (int64_t)(j0 + c) * r + j0 + i, i < b && c < b && i >= c);
         X[c * LD + i] = T(0);
     }
     if (tid < NB) sgn[tid] = tid < b ? pivot_sign(kind_cols[j0 + tid]) : 1.0;
@@ -288,7 +297,9 @@ __global__ void __launch_bounds__(256) diag_block(T *__restrict__ F, int32_t r, 
         __syncthreads();
     }
     if (tid == 0 && events) atomicAdd(nreg, events);
-    for (int idx = tid; idx < NB * NB; idx += 256) {
+#pragma unroll
+    for (int u = 0; u < NB * NB / 256; ++u) {
+        const int idx = tid + 256 * u;
         const int i = idx & 63, c = idx >> 6;
         if (i < b && c < b && i >= c) F[(int64_t)(j0 + c) * r + j0 + i] = S[c * LD + i];
         Xg[c * NB + i] = (i < b && c < b && i >= c) ? X[c * LD + i] : T(0);
@@ -327,13 +338,22 @@ __global__ void __launch_bounds__(256) sblock_inverse(const T *__restrict__ F, i
         for (int m = 0; m < 16; ++m) acc[m] = T(0);
         for (int32_t k = j; k < i; ++k) {
             const int32_t bk = min(NB, kb - k * NB);
+            T la[NB * NB / 256], lb[NB * NB / 256];
             __syncthreads();
             // A = L_ik (rows of block i, columns of block k), B = X_kj
-            for (int32_t idx = tid; idx < NB * NB; idx += 256) {
+#pragma unroll
+            for (int u = 0; u < NB * NB / 256; ++u) {
+                const int32_t idx = tid + 256 * u;
                 const int32_t rr = idx & 63, t = idx >> 6;
-                A[t * NB + rr] = (rr < bi && t < bk) ? F[(int64_t)(J0 + k * NB + t) * r + J0 + i * NB + rr] : T(0);
-                const int32_t tt = idx & 63, col = idx >> 6;   // X_kj(tt, col)
-                B[tt * (NB + 1) + col] = (tt < bk && col < bj) ? Xs[(int64_t)(j * NB + col) * ld + k * NB + tt] : T(0);
+                la[u] = ld_or0(F, (int64_t)(J0 + k * NB + t) * r + J0 + i * NB + rr, rr < bi && t < bk);
+                lb[u] = ld_or0(Xs, (int64_t)(j * NB + t) * ld + k * NB + rr, rr < bk && t < bj);   // X_kj(rr, t)
+            }
+#pragma unroll
+            for (int u = 0; u < NB * NB / 256; ++u) {
+                const int32_t idx = tid + 256 * u;
+                const int32_t rr = idx & 63, t = idx >> 6;
+                A[t * NB + rr] = la[u];
+                B[rr * (NB + 1) + t] = lb[u];
             }
             __syncthreads();
             for (int32_t t = 0; t < NB; ++t) {
@@ -345,7 +365,8 @@ __global__ void __launch_bounds__(256) sblock_inverse(const T *__restrict__ F, i
         // X_ij = -X_ii S
         __syncthreads();
         const T *Xii = dinv_s + (int64_t)((J0 + i * NB) / NB) * NB * NB;
-        for (int32_t idx = tid; idx < NB * NB; idx += 256) A[idx] = Xii[idx];   // A[t*NB+row] = X_ii(row, t)
+#pragma unroll
+        for (int u = 0; u < NB * NB / 256; ++u) A[tid + 256 * u] = Xii[tid + 256 * u];   // A[t*NB+row] = X_ii(row, t)
 #pragma unroll
         for (int m = 0; m < 16; ++m) B[(i0 + 4 * m) * (NB + 1) + cc] = acc[m];  // B[t][col] = S(t, col)
         __syncthreads();
@@ -378,10 +399,12 @@ __global__ void __launch_bounds__(256) panel_solve(T *__restrict__ F, int32_t r,
     __shared__ T Ds[NB];
     const int tid = threadIdx.x;
     const int32_t row0 = j0 + b + blockIdx.x * 64;
-    for (int32_t idx = tid; idx < NB * NB; idx += 256) {
+#pragma unroll
+    for (int u = 0; u < NB * NB / 256; ++u) {
+        const int32_t idx = tid + 256 * u;
         Xs[idx] = Xg[idx];
         const int32_t i = idx & 63, t = idx >> 6;
-        As[t * (NB + 1) + i] = (row0 + i < r && t < b) ? F[(int64_t)(j0 + t) * r + row0 + i] : T(0);
+        As[t * (NB + 1) + i] = ld_or0(F, (int64_t)(j0 + t) * r + row0 + i, row0 + i < r && t < b);
     }
     if (tid < b) Ds[tid] = F[(int64_t)(j0 + tid) * r + j0 + tid];
     __syncthreads();
@@ -432,16 +455,23 @@ __global__ void __launch_bounds__(256) trail_update(T *__restrict__ F, int32_t r
         if (kc > 0) __syncthreads();
         {
             const int32_t i = tid & 63;
-            for (int32_t kk = tid >> 6; kk < NB; kk += 4) {
-                T av = T(0), bv = T(0);
-                if (kk < kn) {
-                    const int32_t kcol = k0 + kc + kk;
-                    const T *colp = F + (int64_t)kcol * r;
-                    if (r0 + i < r) av = colp[r0 + i];
-                    if (c0 + i < c_hi) bv = colp[c0 + i] * colp[kcol];
-                }
-                As[kk * 64 + i] = av;
-                Bs[kk * 64 + i] = bv;
+            // all loads of the chunk are issued before the first LDS store
+            T av[NB / 4], bv[NB / 4], dv[NB / 4];
+#pragma unroll
+            for (int u = 0; u < NB / 4; ++u) {
+                const int32_t kk = (tid >> 6) + 4 * u;
+                const bool okk = kk < kn;
+                const int32_t kcol = k0 + kc + (okk ? kk : 0);
+                const T *colp = F + (int64_t)kcol * r;
+                av[u] = ld_or0(colp, r0 + i, okk && r0 + i < r);
+                bv[u] = ld_or0(colp, c0 + i, okk && c0 + i < c_hi);
+                dv[u] = colp[kcol];
+            }
+#pragma unroll
+            for (int u = 0; u < NB / 4; ++u) {
+                const int32_t kk = (tid >> 6) + 4 * u;
+                As[kk * 64 + i] = av[u];
+                Bs[kk * 64 + i] = bv[u] * dv[u];
             }
         }
         __syncthreads();
@@ -458,7 +488,9 @@ __global__ void __launch_bounds__(256) trail_update(T *__restrict__ F, int32_t r
                 for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = mfma16x16x4(a_op[bj], b_op[bi], acc[bi][bj]);
         }
     }
-    // lane holds D(mfma_out_row(lk, v), lr) = C(row = wr + 16 bi + lr, col = wc + 16 bj + mfma_out_row(lk, v))
+    // lane holds D(mfma_out_row(lk, v), lr) = C(row = wr + 16 bi + lr, col = wc + 16 bj + mfma_out_row(lk, v));
+    // all old values are loaded before any store
+    T old[2][2][4];
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
@@ -467,7 +499,17 @@ __global__ void __launch_bounds__(256) trail_update(T *__restrict__ F, int32_t r
             for (int v = 0; v < 4; ++v) {
                 const int32_t row = r0 + wr + 16 * bi + lr;
                 const int32_t col = c0 + wc + 16 * bj + mfma_out_row<T>(lk, v);
-                if (row < r && col < c_hi && row >= col) F[(int64_t)col * r + row] -= acc[bi][bj][v];
+                old[bi][bj][v] = ld_or0(F, (int64_t)col * r + row, row < r && col < c_hi && row >= col);
+            }
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int32_t row = r0 + wr + 16 * bi + lr;
+                const int32_t col = c0 + wc + 16 * bj + mfma_out_row<T>(lk, v);
+                if (row < r && col < c_hi && row >= col) F[(int64_t)col * r + row] = old[bi][bj][v] - acc[bi][bj][v];
             }
 }
 

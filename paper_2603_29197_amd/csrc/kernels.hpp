@@ -31,6 +31,16 @@ __host__ __device__ inline double static_reg(int8_t kind, double delta) {
 // must fail the tests built on it, never pass them.
 __host__ __device__ inline double nan_max(double a, double b) { return (a != a || a > b) ? a : b; }
 
+// p[i] if ok, else 0, with no branch: the address falls back to p[0] (which
+// must be valid) when !ok.  A conditional load compiles to an exec-masked
+// block that waits for its own result, so the loads of a loop would run one
+// after another; this form keeps them all in flight.
+template <typename T>
+__device__ inline T ld_or0(const T *__restrict__ p, int64_t i, bool ok) {
+    const T v = p[ok ? i : 0];
+    return ok ? v : T(0);
+}
+
 struct RegParams {
     double delta;     // static regularization
     double eps;       // dynamic threshold

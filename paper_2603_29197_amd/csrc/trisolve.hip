@@ -178,7 +178,8 @@ __global__ void __launch_bounds__(256) bwd_init(int32_t s, const int32_t *__rest
 // Backward update of the columns before a super-block:
 // v[c] -= L(J0:J0+kb, c)' y for 64 columns per workgroup, 16 per wavefront;
 // lanes run along the contiguous rows of each column (coalesced), all loads
-// of a wavefront are issued before its 16 shuffle reductions.
+// of a wavefront are issued before its 16 shuffle reductions, and lanes
+// 0..15 then update the 16 entries at once.
 template <typename T>
 __global__ void __launch_bounds__(256) sblock_cols(const T *__restrict__ F, int32_t r, int32_t J0, int32_t kb,
                                                    const double *__restrict__ y, double *__restrict__ vbuf) {
@@ -195,16 +196,20 @@ __global__ void __launch_bounds__(256) sblock_cols(const T *__restrict__ F, int3
 #pragma unroll
         for (int m = 0; m < SB / 64; ++m) {
             const int32_t t = lane + 64 * m;
-            if (c < J0 && t < kb) s += (double)F[(int64_t)c * r + J0 + t] * ys[t];
+            const bool ok = c < J0 && t < kb;
+            s += (double)ld_or0(F, (int64_t)c * r + J0 + t, ok) * ys[ok ? t : 0];
         }
         part[cc] = s;
     }
+    // after the butterfly every lane holds the sum; lane cc updates column c0 + cc
+    double mine = 0.0;
 #pragma unroll
     for (int cc = 0; cc < 16; ++cc) {
         double s = part[cc];
         for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-        if (lane == 0 && c0 + cc < J0) vbuf[c0 + cc] -= s;
+        mine = lane == cc ? s : mine;
     }
+    if (lane < 16 && c0 + lane < J0) vbuf[c0 + lane] -= mine;
 }
 
 // ------------------------------- driver ------------------------------------

@@ -141,6 +141,8 @@ class Solver:
     # -- main calls -----------------------------------------------------------
     def set_settings(self, **kw):
         for k, v in kw.items():
+            if not hasattr(self.settings, k):
+                raise KeyError(k)
             setattr(self.settings, k, v)
         check(lib().qg_set_settings(self.handle, ctypes.byref(self.settings)), "qg_set_settings")
 

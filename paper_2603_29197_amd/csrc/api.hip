@@ -74,6 +74,7 @@ static int allocate_device(qg_handle *h) {
     UP(asm_row, pl.asm_row);
     UP(ctb_child, pl.ctb_child);
     UP(ctb_col, pl.ctb_col);
+    UP(ctb_src, pl.ctb_src);
     UP(rel, pl.rel);
     UP(ch_ptr, pl.ch_ptr);
     UP(ch_list, pl.ch_list);

@@ -158,16 +158,29 @@ __device__ inline double lane_bcast(double v, int src) {
     return __hiloint2double(hi, lo);
 }
 
+// One 16 x 16 tile of C = sum_k A(i, k) B(k, j), k = 0..15, on MFMA 16x16x4:
+// a(i, k) and b(k, j) return the operands; the result is in the lane layout
+// of mfma_out_row (row mfma_out_row(lane / 16, v), column lane % 16).
+template <typename T, typename FA, typename FB>
+__device__ inline typename Acc4<T>::type tile16(FA a, FB b) {
+    const int lane = threadIdx.x & 63;
+    const int i = lane & 15, kq = lane >> 4;
+    typename Acc4<T>::type acc = {0, 0, 0, 0};
+#pragma unroll
+    for (int k0 = 0; k0 < 16; k0 += 4) acc = mfma16x16x4(a(i, k0 + kq), b(k0 + kq, i), acc);
+    return acc;
+}
+
 // LDL' of the b x b diagonal block at (j0, j0) of the front F (ld r), in
 // place; the inverse of its unit lower factor goes to Xg (ld NB, zeros above
 // the diagonal).  The block is staged in LDS and factored 16 columns at a
 // time: wavefront 0 factors the 16 x 16 diagonal sub-block in registers
-// (lane i holds row i; the column of each pivot is read with lane
-// broadcasts, so a pivot step has no barrier) and inverts its unit lower
-// factor; then all four wavefronts form the L rows below it within the block
-// and apply its rank-16 update to the rest of the block.  The inverse of the
+// (lane i holds row i; pivot columns are read with lane broadcasts, so a
+// pivot step has no barrier) and inverts its unit lower factor; then the L
+// rows below it (A X' D^-1) and its rank-16 update of the rest of the block
+// run as 16 x 16 MFMA tiles, one tile per wavefront.  The inverse of the
 // whole unit lower factor is assembled from the 16 x 16 inverses at the end,
-// X_pq = -X_pp sum_{m=q}^{p-1} L_pm X_mq.
+// X_pq = -X_pp sum_{m=q}^{p-1} L_pm X_mq, also on MFMA tiles.
 template <typename T>
 __global__ void __launch_bounds__(256) diag_block(T *__restrict__ F, int32_t r, int32_t j0, int32_t b,
                                                   const int8_t *__restrict__ kind_cols, double eps,
@@ -176,30 +189,40 @@ __global__ void __launch_bounds__(256) diag_block(T *__restrict__ F, int32_t r, 
     constexpr int PB = 16;               // sub-block width
     __shared__ T S[NB * LD];             // S[c * LD + i]: block, becomes L (strictly lower) and D (diagonal)
     __shared__ T X[NB * LD];             // inverse of the unit lower factor
-    __shared__ T Tm[PB * NB];            // partial sums of the off-diagonal inverse blocks
+    __shared__ T Tm[3][PB * PB];         // partial sums of off-diagonal inverse blocks, one per wavefront
     __shared__ T Dd[NB];
     __shared__ double sgn[NB];
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
+    {
+        T v[NB * NB / 256];
 #pragma unroll
-    for (int u = 0; u < NB * NB / 256; ++u) {
-        const int idx = tid + 256 * u;
-        const int i = idx & 63, c = idx >> 6;
-        S[c * LD + i] = ld_or0(F, (int64_t)(j0 + c) * r + j0 + i, i < b && c < b && i >= c);
-        X[c * LD + i] = T(0);
+        for (int u = 0; u < NB * NB / 256; ++u) {
+            const int idx = tid + 256 * u, i = idx & 63, c = idx >> 6;
+            v[u] = ld_or0(F, (int64_t)(j0 + c) * r + j0 + i, i < b && c < b && i >= c);
+        }
+#pragma unroll
+        for (int u = 0; u < NB * NB / 256; ++u) {
+            const int idx = tid + 256 * u, i = idx & 63, c = idx >> 6;
+            S[c * LD + i] = v[u];
+            X[c * LD + i] = T(0);
+        }
     }
     if (tid < NB) sgn[tid] = tid < b ? pivot_sign(kind_cols[j0 + tid]) : 1.0;
     __syncthreads();
     int events = 0;
+    const int lr = lane & 15, lk = lane >> 4;
     for (int p0 = 0; p0 < b; p0 += PB) {
         const int pb = min(PB, b - p0);
         if (wave == 0) {
-            // rows p0 + lane (lane < pb), columns p0 .. p0+15
+            // rows p0 + lr of the sub-block (lanes 16..63 mirror lanes 0..15 and write nothing)
             T a[PB];
-            T dmine = T(0);
-            const bool mine = lane < pb;
 #pragma unroll
-            for (int m = 0; m < PB; ++m) a[m] = (mine && m < pb) ? S[(p0 + m) * LD + p0 + lane] : T(0);
+            for (int m = 0; m < PB; ++m) {
+                const T v = S[(p0 + m) * LD + p0 + lr];
+                a[m] = (lr < pb && m < pb && m <= lr) ? v : T(0);
+            }
+            T dmine = T(0);
 #pragma unroll
             for (int j = 0; j < PB; ++j) {
                 if (j < pb) {
@@ -209,22 +232,22 @@ __global__ void __launch_bounds__(256) diag_block(T *__restrict__ F, int32_t r, 
                     const T d = fix ? (T)(sg * dyn) : raw;
                     events += fix ? 1 : 0;
                     const T inv = T(1) / d;
-                    const T l = lane > j ? a[j] * inv : T(0);
+                    const T l = lr > j ? a[j] * inv : T(0);
 #pragma unroll
                     for (int k = j + 1; k < PB; ++k) a[k] -= l * lane_bcast(a[j], k);
-                    a[j] = lane > j ? l : (lane == j ? d : a[j]);
-                    dmine = lane == j ? d : dmine;
+                    a[j] = lr > j ? l : (lr == j ? d : a[j]);
+                    dmine = lr == j ? d : dmine;
                 }
             }
             // inverse of the unit lower sub-block: lane c forms column c
             T x[PB];
 #pragma unroll
-            for (int k = 0; k < PB; ++k) x[k] = (k == lane) ? T(1) : T(0);
+            for (int k = 0; k < PB; ++k) x[k] = (k == lr) ? T(1) : T(0);
 #pragma unroll
             for (int m = 0; m < PB; ++m)
 #pragma unroll
                 for (int k = m + 1; k < PB; ++k) x[k] -= lane_bcast(a[m], k) * x[m];
-            if (mine) {
+            if (lane < pb) {
 #pragma unroll
                 for (int m = 0; m < PB; ++m)
                     if (m <= lane) S[(p0 + m) * LD + p0 + lane] = a[m];
@@ -235,63 +258,68 @@ __global__ void __launch_bounds__(256) diag_block(T *__restrict__ F, int32_t r, 
             }
         }
         __syncthreads();
-        // L rows below the sub-block within the block: L(i, p) = A(i, p) X_pp' D_p^-1
         const int i0 = p0 + pb, nb = b - i0;
         if (nb > 0) {
-            T out[3];
+            const int nt = (nb + 15) / 16;
+            // L rows below: L(i, p0+m) = sum_q A(i, p0+q) X_pp(m, q) / D(p0+m), one row tile per wavefront
+            if (wave < nt) {
+                const int rb = i0 + 16 * wave;
+                auto acc = tile16<T>(
+                    [&](int i, int k) { return k < pb ? S[(p0 + k) * LD + rb + i] : T(0); },
+                    [&](int k, int j) { return k < pb ? X[(p0 + k) * LD + p0 + j] : T(0); });
 #pragma unroll
-            for (int t = 0; t < 3; ++t) {
-                const int e = tid + 256 * t;
-                const int i = i0 + (e >> 4), m = e & 15;
-                T acc = T(0);
-                if (i < b && m < pb)
-                    for (int q = 0; q <= m; ++q) acc += S[(p0 + q) * LD + i] * X[(p0 + q) * LD + p0 + m];
-                out[t] = acc;
+                for (int v = 0; v < 4; ++v) {
+                    const int m = lr, i = rb + mfma_out_row<T>(lk, v);
+                    // result tile row = row of L, column = m; written after all reads of this wave
+                    if (i < b && m < pb) S[(p0 + m) * LD + i] = acc[v] / Dd[p0 + m];
+                }
             }
             __syncthreads();
+            // rank-pb update of the rest of the block: tiles (ti, tj), ti >= tj
+            for (int tt = wave; tt < nt * (nt + 1) / 2; tt += 4) {
+                int ti = 0;
+                while ((ti + 1) * (ti + 2) / 2 <= tt) ++ti;
+                const int tj = tt - ti * (ti + 1) / 2;
+                const int ri = i0 + 16 * ti, rj = i0 + 16 * tj;
+                auto acc = tile16<T>(
+                    [&](int i, int k) { return k < pb ? S[(p0 + k) * LD + ri + i] : T(0); },
+                    [&](int k, int j) { return k < pb ? S[(p0 + k) * LD + rj + j] * Dd[p0 + k] : T(0); });
 #pragma unroll
-            for (int t = 0; t < 3; ++t) {
-                const int e = tid + 256 * t;
-                const int i = i0 + (e >> 4), m = e & 15;
-                if (i < b && m < pb) S[(p0 + m) * LD + i] = out[t] / Dd[p0 + m];
-            }
-            __syncthreads();
-            // rank-pb update of the rest of the block (lower part)
-            for (int e = tid; e < nb * nb; e += 256) {
-                const int i = i0 + e % nb, k = i0 + e / nb;
-                if (i < k) continue;
-                T acc = T(0);
-                for (int m = 0; m < pb; ++m)
-                    acc += S[(p0 + m) * LD + i] * S[(p0 + m) * LD + k] * Dd[p0 + m];
-                S[k * LD + i] -= acc;
+                for (int v = 0; v < 4; ++v) {
+                    const int i = ri + mfma_out_row<T>(lk, v), j = rj + lr;
+                    if (i < b && j < b && i >= j) S[j * LD + i] -= acc[v];
+                }
             }
             __syncthreads();
         }
     }
-    // off-diagonal blocks of the inverse, block row by block row
+    // off-diagonal blocks of the inverse, block row by block row (wavefront q
+    // forms X_pq)
     const int nsub = (b + PB - 1) / PB;
     for (int p = 1; p < nsub; ++p) {
-        const int n = PB * p;              // columns 0 .. n-1 of block row p
+        const int n = PB * p;
+        if (wave < p) {
+            const int q0 = PB * wave;
+            // T = sum_{m = q}^{p-1} L_pm X_mq
+            typename Acc4<T>::type tacc = {0, 0, 0, 0};
+            for (int m0 = q0; m0 < n; m0 += PB) {
+                auto acc = tile16<T>(
+                    [&](int i, int k) { return S[(m0 + k) * LD + n + i]; },
+                    [&](int k, int j) { return X[(q0 + j) * LD + m0 + k]; });
 #pragma unroll
-        for (int t = 0; t < 3; ++t) {
-            const int e = tid + 256 * t;
-            if (e < PB * n) {
-                const int rr = e & 15, c = e >> 4;          // T(rr, c) = sum_{m >= c's block}^{p-1} L(16p+rr, m) X(m, c)
-                const int q0 = (c / PB) * PB;
-                T acc = T(0);
-                for (int m = q0; m < n; ++m) acc += S[m * LD + n + rr] * X[c * LD + m];
-                Tm[c * PB + rr] = acc;
+                for (int v = 0; v < 4; ++v) tacc[v] += acc[v];
             }
-        }
-        __syncthreads();
 #pragma unroll
-        for (int t = 0; t < 3; ++t) {
-            const int e = tid + 256 * t;
-            if (e < PB * n) {
-                const int rr = e & 15, c = e >> 4;
-                T acc = T(0);
-                for (int q = 0; q <= rr; ++q) acc += X[(n + q) * LD + n + rr] * Tm[c * PB + q];
-                if (n + rr < b && c < b) X[c * LD + n + rr] = -acc;
+            for (int v = 0; v < 4; ++v) Tm[wave][lr * PB + mfma_out_row<T>(lk, v)] = tacc[v];   // T(row, col) at col * 16 + row
+            __builtin_amdgcn_wave_barrier();
+            // X_pq = -X_pp T (reads of Tm by the same wavefront)
+            auto acc = tile16<T>(
+                [&](int i, int k) { return X[(n + k) * LD + n + i]; },
+                [&](int k, int j) { return Tm[wave][j * PB + k]; });
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = n + mfma_out_row<T>(lk, v), j = q0 + lr;
+                if (i < b && j < b) X[j * LD + i] = -acc[v];
             }
         }
         __syncthreads();
@@ -299,8 +327,7 @@ __global__ void __launch_bounds__(256) diag_block(T *__restrict__ F, int32_t r, 
     if (tid == 0 && events) atomicAdd(nreg, events);
 #pragma unroll
     for (int u = 0; u < NB * NB / 256; ++u) {
-        const int idx = tid + 256 * u;
-        const int i = idx & 63, c = idx >> 6;
+        const int idx = tid + 256 * u, i = idx & 63, c = idx >> 6;
         if (i < b && c < b && i >= c) F[(int64_t)(j0 + c) * r + j0 + i] = S[c * LD + i];
         Xg[c * NB + i] = (i < b && c < b && i >= c) ? X[c * LD + i] : T(0);
     }

@@ -58,7 +58,7 @@ void dfree_all(qg_handle *h) {
     dfree(d.kr_col); dfree(d.kr_val); dfree(d.c); dfree(d.b); dfree(d.h); dfree(d.Pp); dfree(d.Pi);
     dfree(d.perm); dfree(d.iperm);
     dfree(d.sn_first); dfree(d.sn_rows); dfree(d.task_sn); dfree(d.task_col); dfree(d.asm_row);
-    dfree(d.ctb_child); dfree(d.ctb_col); dfree(d.rel); dfree(d.ch_ptr); dfree(d.ch_list);
+    dfree(d.ctb_child); dfree(d.ctb_col); dfree(d.ctb_src); dfree(d.rel); dfree(d.ch_ptr); dfree(d.ch_list);
     dfree(d.lvl_small_sn); dfree(d.sn_rptr); dfree(d.fr_off); dfree(d.task_ptr); dfree(d.asm_ptr);
     dfree(d.asm_src); dfree(d.ctb_ptr); dfree(d.rel_ptr); dfree(d.uv_off); dfree(d.reg_sign);
     dfree(d.front64); dfree(d.front32); dfree(d.uvec); dfree(d.dinv64); dfree(d.dinv32);
@@ -325,6 +325,7 @@ int build_plan(qg_handle *h) {
     for (int64_t t = 0; t < ntask; ++t) pl.ctb_ptr[t + 1] += pl.ctb_ptr[t];
     pl.ctb_child.assign(pl.ctb_ptr[ntask], 0);
     pl.ctb_col.assign(pl.ctb_ptr[ntask], 0);
+    pl.ctb_src.assign(pl.ctb_ptr[ntask], 0);
     {
         std::vector<int64_t> fill(pl.ctb_ptr.begin(), pl.ctb_ptr.end() - 1);
         for (int32_t s = 0; s < ns; ++s)
@@ -334,6 +335,7 @@ int build_plan(qg_handle *h) {
                     const int64_t d = fill[task_base[s] + pl.rel[i]]++;
                     pl.ctb_child[d] = c;
                     pl.ctb_col[d] = (int32_t)(i - pl.rel_ptr[c]);
+                    pl.ctb_src[d] = task_base[c] + (pl.sn_first[c + 1] - pl.sn_first[c]) + (i - pl.rel_ptr[c]);
                 }
             }
     }

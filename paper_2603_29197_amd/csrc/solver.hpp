@@ -49,6 +49,7 @@ struct Plan {
     std::vector<int32_t> asm_row;         // local row in the front
     std::vector<int64_t> ctb_ptr;         // per task: child contributions
     std::vector<int32_t> ctb_child, ctb_col;
+    std::vector<int64_t> ctb_src;         // position of each contribution in the solve work vector
     std::vector<int64_t> rel_ptr;         // per supernode: relative map of its update rows
     std::vector<int32_t> rel;
     std::vector<int64_t> uv_off;          // per supernode: offset of its update vector (solves)
@@ -77,7 +78,7 @@ struct Device {
     // plan
     DBuf<int32_t> sn_first, sn_rows, task_sn, task_col, asm_row, ctb_child, ctb_col, rel, ch_ptr,
         ch_list, lvl_small_sn;
-    DBuf<int64_t> sn_rptr, fr_off, task_ptr, asm_ptr, asm_src, ctb_ptr, rel_ptr, uv_off;
+    DBuf<int64_t> sn_rptr, fr_off, task_ptr, asm_ptr, asm_src, ctb_ptr, ctb_src, rel_ptr, uv_off;
     DBuf<int8_t> reg_sign;
     DBuf<double> front64;
     DBuf<float> front32;

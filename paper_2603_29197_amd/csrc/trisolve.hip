@@ -19,26 +19,40 @@
 namespace qg {
 
 // ------------------------------- small -------------------------------------
-// Gather of one level: one thread per (front s, row j) task:
+// Gather of one level: RL lanes per (front s, row j) task:
 // v = [j < k_s ? x_perm(first_s + j) : 0] + sum over the child columns that map
 // onto row j of their update-vector entries (contribution lists of the
-// assembly, in child order).  Update vectors live in the children's own
-// task slots (rows k_c .. r_c - 1).
+// assembly, with the position of each entry in the work vector precomputed).
+// Lane l sums contributions l, l + RL, ...; the RL partial sums are combined
+// by a fixed butterfly, so the result does not depend on scheduling.  Update
+// vectors live in the children's own task slots (rows k_c .. r_c - 1).
 __global__ void __launch_bounds__(256) fwd_gather_level(
     int64_t t0, int64_t nt, const int32_t *__restrict__ task_sn, const int32_t *__restrict__ task_col,
-    const int32_t *__restrict__ sn_first, const int64_t *__restrict__ task0,
-    const int64_t *__restrict__ ctb_ptr, const int32_t *__restrict__ ctb_child,
-    const int32_t *__restrict__ ctb_col, const double *__restrict__ xp, double *__restrict__ vwork) {
-    const int64_t t = t0 + (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (t >= t0 + nt) return;
-    const int32_t s = task_sn[t], j = task_col[t];
-    const int32_t f = sn_first[s], k = sn_first[s + 1] - f;
-    double v = j < k ? xp[f + j] : 0.0;
-    for (int64_t u = ctb_ptr[t]; u < ctb_ptr[t + 1]; ++u) {
-        const int32_t c = ctb_child[u];
-        v += vwork[task0[c] + (sn_first[c + 1] - sn_first[c]) + ctb_col[u]];
+    const int32_t *__restrict__ sn_first, const int64_t *__restrict__ ctb_ptr,
+    const int64_t *__restrict__ ctb_src, const double *__restrict__ xp, double *__restrict__ vwork) {
+    const int sub = threadIdx.x & (RL - 1);
+    const int64_t t = t0 + (int64_t)blockIdx.x * (256 / RL) + (threadIdx.x / RL);
+    const bool live = t < t0 + nt;
+    const int64_t tt = live ? t : t0;
+    double v = 0.0;
+    const int64_t u0 = ctb_ptr[tt], u1 = live ? ctb_ptr[tt + 1] : u0;
+    for (int64_t u = u0 + sub; u < u1; u += 4 * RL) {     // four independent loads per lane in flight
+        double a[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t uu = u + q * RL;
+            const double x = vwork[ctb_src[uu < u1 ? uu : u]];   // u < u1: always a valid entry
+            a[q] = uu < u1 ? x : 0.0;
+        }
+        v += (a[0] + a[1]) + (a[2] + a[3]);
     }
-    vwork[t] = v;
+#pragma unroll
+    for (int off = RL / 2; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if (live && sub == 0) {
+        const int32_t s = task_sn[t], j = task_col[t];
+        const int32_t f = sn_first[s], k = sn_first[s + 1] - f;
+        vwork[t] = (j < k ? xp[f + j] : 0.0) + v;
+    }
 }
 
 template <typename T>
@@ -221,9 +235,8 @@ static int solve_perm(qg_handle *h, const T *front, const T *sinv) {
     for (int32_t L = 0; L < pl.nlevels; ++L) {
         const int64_t t0 = pl.task_ptr[L], nt = pl.task_ptr[L + 1] - t0;
         if (nt > 0)
-            fwd_gather_level<<<(unsigned)((nt + 255) / 256), 256, 0, h->stream>>>(
-                t0, nt, d.task_sn.p, d.task_col.p, d.sn_first.p, d.task0.p, d.ctb_ptr.p, d.ctb_child.p,
-                d.ctb_col.p, xp, d.vwork.p);
+            fwd_gather_level<<<(unsigned)((nt + 256 / RL - 1) / (256 / RL)), 256, 0, h->stream>>>(
+                t0, nt, d.task_sn.p, d.task_col.p, d.sn_first.p, d.ctb_ptr.p, d.ctb_src.p, xp, d.vwork.p);
         const int32_t s0 = pl.lvl_small_ptr[L], s1 = pl.lvl_small_ptr[L + 1];
         if (s1 > s0)
             fwd_small<T><<<s1 - s0, SMALL_R, 0, h->stream>>>(d.lvl_small_sn.p + s0, d.sn_first.p, d.sn_rptr.p,

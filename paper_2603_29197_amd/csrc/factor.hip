@@ -336,188 +336,242 @@ __global__ void __launch_bounds__(256) diag_block(T *__restrict__ F, int32_t r, 
 // Inverse of the unit-lower SB x SB diagonal block of a super-panel
 // [J0, J0+kb) from the inverses X_ii of its 64 x 64 diagonal blocks:
 // X_ij = -X_ii sum_{k=j}^{i-1} L_ik X_kj (i > j).  Workgroup j computes block
-// column j (independent of the other columns).  Writes X and X' (column-major,
-// leading dimension ld = kb rounded up to a multiple of 64).
+// column j (independent of the other columns), block row by block row; the
+// 64 x 64 products run on MFMA 16x16x4 with operands staged through LDS
+// (wavefront w forms rows 16 w .. 16 w + 15).  Writes X and X'
+// (column-major, leading dimension ld = kb rounded up to a multiple of 64).
 template <typename T>
 __global__ void __launch_bounds__(256) sblock_inverse(const T *__restrict__ F, int32_t r, int32_t J0, int32_t kb,
                                                       const T *__restrict__ dinv_s, int32_t ld,
                                                       T *__restrict__ Xs, T *__restrict__ XTs) {
-    __shared__ T A[NB * NB];         // A[t * NB + row]
-    __shared__ T B[NB * (NB + 1)];   // B[t * (NB+1) + col]
+    constexpr int LD = NB + 1;
+    __shared__ T A[NB * LD];         // A[k * LD + i] = operand A(i, k)
+    __shared__ T B[NB * LD];         // B[j * LD + k] = operand B(k, j)
     const int tid = threadIdx.x;
-    const int cc = tid & 63, i0 = tid >> 6;
+    const int lane = tid & 63, wave = tid >> 6, lr = lane & 15, lk = lane >> 4;
     const int32_t j = blockIdx.x;
     const int32_t nsub = (kb + NB - 1) / NB;
     const int32_t bj = min(NB, kb - j * NB);
+    typedef typename Acc4<T>::type V;
     // X_jj
     const T *Xjj = dinv_s + (int64_t)((J0 + j * NB) / NB) * NB * NB;
 #pragma unroll
     for (int m = 0; m < 16; ++m) {
-        const int rr = i0 + 4 * m;
+        const int cc = lane, rr = wave + 4 * m;
         const T v = Xjj[cc * NB + rr];
         Xs[(int64_t)(j * NB + cc) * ld + j * NB + rr] = v;
         XTs[(int64_t)(j * NB + rr) * ld + j * NB + cc] = v;
     }
     for (int32_t i = j + 1; i < nsub; ++i) {
         const int32_t bi = min(NB, kb - i * NB);
-        T acc[16];
+        V acc[4];
 #pragma unroll
-        for (int m = 0; m < 16; ++m) acc[m] = T(0);
+        for (int bc = 0; bc < 4; ++bc) acc[bc] = V{0, 0, 0, 0};
         for (int32_t k = j; k < i; ++k) {
             const int32_t bk = min(NB, kb - k * NB);
             T la[NB * NB / 256], lb[NB * NB / 256];
-            __syncthreads();
-            // A = L_ik (rows of block i, columns of block k), B = X_kj
 #pragma unroll
             for (int u = 0; u < NB * NB / 256; ++u) {
-                const int32_t idx = tid + 256 * u;
-                const int32_t rr = idx & 63, t = idx >> 6;
-                la[u] = ld_or0(F, (int64_t)(J0 + k * NB + t) * r + J0 + i * NB + rr, rr < bi && t < bk);
-                lb[u] = ld_or0(Xs, (int64_t)(j * NB + t) * ld + k * NB + rr, rr < bk && t < bj);   // X_kj(rr, t)
-            }
-#pragma unroll
-            for (int u = 0; u < NB * NB / 256; ++u) {
-                const int32_t idx = tid + 256 * u;
-                const int32_t rr = idx & 63, t = idx >> 6;
-                A[t * NB + rr] = la[u];
-                B[rr * (NB + 1) + t] = lb[u];
+                const int32_t idx = tid + 256 * u, e = idx & 63, f = idx >> 6;
+                la[u] = ld_or0(F, (int64_t)(J0 + k * NB + f) * r + J0 + i * NB + e, e < bi && f < bk);   // L_ik(e, f)
+                lb[u] = ld_or0(Xs, (int64_t)(j * NB + f) * ld + k * NB + e, e < bk && f < bj);          // X_kj(e, f)
             }
             __syncthreads();
-            for (int32_t t = 0; t < NB; ++t) {
-                const T bv = B[t * (NB + 1) + cc];
 #pragma unroll
-                for (int m = 0; m < 16; ++m) acc[m] += A[t * NB + i0 + 4 * m] * bv;
+            for (int u = 0; u < NB * NB / 256; ++u) {
+                const int32_t idx = tid + 256 * u, e = idx & 63, f = idx >> 6;
+                A[f * LD + e] = la[u];       // A(e, f) = L_ik(e, f)
+                B[f * LD + e] = lb[u];       // B(e, f) = X_kj(e, f)
+            }
+            __syncthreads();
+#pragma unroll 4
+            for (int k0 = 0; k0 < NB; k0 += 4) {
+                const T a = A[(k0 + lk) * LD + 16 * wave + lr];
+#pragma unroll
+                for (int bc = 0; bc < 4; ++bc) acc[bc] = mfma16x16x4(a, B[(16 * bc + lr) * LD + k0 + lk], acc[bc]);
             }
         }
-        // X_ij = -X_ii S
+        // X_ij = -X_ii S with S = acc (rows 16 wave + mfma_out_row, columns 16 bc + lr)
         __syncthreads();
         const T *Xii = dinv_s + (int64_t)((J0 + i * NB) / NB) * NB * NB;
 #pragma unroll
-        for (int u = 0; u < NB * NB / 256; ++u) A[tid + 256 * u] = Xii[tid + 256 * u];   // A[t*NB+row] = X_ii(row, t)
+        for (int u = 0; u < NB * NB / 256; ++u) {
+            const int32_t idx = tid + 256 * u, e = idx & 63, f = idx >> 6;
+            A[f * LD + e] = Xii[f * NB + e];                 // A(e, f) = X_ii(e, f)
+        }
 #pragma unroll
-        for (int m = 0; m < 16; ++m) B[(i0 + 4 * m) * (NB + 1) + cc] = acc[m];  // B[t][col] = S(t, col)
+        for (int bc = 0; bc < 4; ++bc)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) B[(16 * bc + lr) * LD + 16 * wave + mfma_out_row<T>(lk, v)] = acc[bc][v];
         __syncthreads();
-        T out[16];
+        V out[4];
 #pragma unroll
-        for (int m = 0; m < 16; ++m) out[m] = T(0);
-        for (int32_t t = 0; t < NB; ++t) {
-            const T bv = B[t * (NB + 1) + cc];
+        for (int bc = 0; bc < 4; ++bc) out[bc] = V{0, 0, 0, 0};
+#pragma unroll 4
+        for (int k0 = 0; k0 < NB; k0 += 4) {
+            const T a = A[(k0 + lk) * LD + 16 * wave + lr];
 #pragma unroll
-            for (int m = 0; m < 16; ++m) out[m] -= A[t * NB + i0 + 4 * m] * bv;
+            for (int bc = 0; bc < 4; ++bc) out[bc] = mfma16x16x4(a, B[(16 * bc + lr) * LD + k0 + lk], out[bc]);
         }
 #pragma unroll
-        for (int m = 0; m < 16; ++m) {
-            const int rr = i0 + 4 * m;
-            const T v = (rr < bi && cc < bj) ? out[m] : T(0);
-            Xs[(int64_t)(j * NB + cc) * ld + i * NB + rr] = v;
-            XTs[(int64_t)(i * NB + rr) * ld + j * NB + cc] = v;
-        }
+        for (int bc = 0; bc < 4; ++bc)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int rr = 16 * wave + mfma_out_row<T>(lk, v), cc = 16 * bc + lr;
+                const T val = (rr < bi && cc < bj) ? -out[bc][v] : T(0);
+                Xs[(int64_t)(j * NB + cc) * ld + i * NB + rr] = val;
+                XTs[(int64_t)(i * NB + rr) * ld + j * NB + cc] = val;
+            }
     }
 }
 
 // L21 = A21 X' D^-1 for 64 rows per workgroup (rows j0+b .. r-1): the 64 x b
-// tile of A21 is staged through LDS with coalesced loads (all in flight at
-// once), then each thread forms 16 entries of its row.
+// tile of A21 and X are staged through LDS with coalesced loads (all in
+// flight at once); the product runs on MFMA 16x16x4, formed transposed
+// (X A21', wavefront w forms panel columns 16 w .. 16 w + 15) so that lanes
+// run along the contiguous rows of the front in the store.
 template <typename T>
 __global__ void __launch_bounds__(256) panel_solve(T *__restrict__ F, int32_t r, int32_t j0, int32_t b,
                                                    const T *__restrict__ Xg) {
-    __shared__ T Xs[NB * NB];
+    __shared__ T Xs[NB * NB];        // Xs[t * NB + c] = X(c, t)
     __shared__ T As[NB * (NB + 1)];  // As[t * (NB + 1) + i] = A21(row0 + i, t)
     __shared__ T Ds[NB];
     const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6, lr = lane & 15, lk = lane >> 4;
     const int32_t row0 = j0 + b + blockIdx.x * 64;
+    {
+        T xv[NB * NB / 256], av[NB * NB / 256];
 #pragma unroll
-    for (int u = 0; u < NB * NB / 256; ++u) {
-        const int32_t idx = tid + 256 * u;
-        Xs[idx] = Xg[idx];
-        const int32_t i = idx & 63, t = idx >> 6;
-        As[t * (NB + 1) + i] = ld_or0(F, (int64_t)(j0 + t) * r + row0 + i, row0 + i < r && t < b);
+        for (int u = 0; u < NB * NB / 256; ++u) {
+            const int32_t idx = tid + 256 * u, i = idx & 63, t = idx >> 6;
+            xv[u] = Xg[idx];
+            av[u] = ld_or0(F, (int64_t)(j0 + t) * r + row0 + i, row0 + i < r && t < b);
+        }
+#pragma unroll
+        for (int u = 0; u < NB * NB / 256; ++u) {
+            const int32_t idx = tid + 256 * u, i = idx & 63, t = idx >> 6;
+            Xs[idx] = xv[u];
+            As[t * (NB + 1) + i] = av[u];
+        }
     }
-    if (tid < b) Ds[tid] = F[(int64_t)(j0 + tid) * r + j0 + tid];
+    if (tid < NB) Ds[tid] = ld_or0(F, (int64_t)(j0 + tid) * r + j0 + tid, tid < b);
     __syncthreads();
-    const int i = tid & 63;
-    const int32_t row = row0 + i;
-    const int32_t cg = tid >> 6;                 // column group 0..3
-    T out[NB / 4];
+    typedef typename Acc4<T>::type V;
+    V acc[4];
 #pragma unroll
-    for (int u = 0; u < NB / 4; ++u) out[u] = T(0);
-    for (int32_t t = 0; t < b; ++t) {
-        const T a = As[t * (NB + 1) + i];
+    for (int bi = 0; bi < 4; ++bi) acc[bi] = V{0, 0, 0, 0};
+#pragma unroll 4
+    for (int k0 = 0; k0 < NB; k0 += 4) {
+        const T a = Xs[(k0 + lk) * NB + 16 * wave + lr];                  // X(c, t): c = 16 w + lr, t = k0 + lk
 #pragma unroll
-        for (int u = 0; u < NB / 4; ++u) out[u] += a * Xs[t * NB + cg + 4 * u];   // X(c, t), zero for t > c
+        for (int bi = 0; bi < 4; ++bi) acc[bi] = mfma16x16x4(a, As[(k0 + lk) * (NB + 1) + 16 * bi + lr], acc[bi]);
     }
 #pragma unroll
-    for (int u = 0; u < NB / 4; ++u) {
-        const int32_t c = cg + 4 * u;
-        if (row < r && c < b) F[(int64_t)(j0 + c) * r + row] = out[u] / Ds[c];
-    }
+    for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int c = 16 * wave + mfma_out_row<T>(lk, v);
+            const int32_t row = row0 + 16 * bi + lr;
+            if (row < r && c < b) F[(int64_t)(j0 + c) * r + row] = acc[bi][v] / Ds[c];
+        }
 }
 
 // C -= L(:, k0:k0+kb) D L(cols, k0:k0+kb)' on the lower part (row >= col) of
 // rows [r_lo, r) x cols [r_lo, c_hi) of the front F (ld r), 64 x 64 tiles,
-// grid (row tile, col tile).  The rank kb is consumed in chunks of NB staged
-// through LDS.  Four wavefronts per tile, 2 x 2 MFMA 16x16 blocks each; the
-// product is formed transposed so that each lane's accumulators run along a
-// column of the column-major front.
+// grid (row tile, col tile).  The rank kb is consumed in chunks of KC columns
+// through double-buffered LDS: the global loads of the next chunk are issued
+// before the MFMAs of the current one and are only waited for at the LDS
+// store, and the old C values are loaded at the start, so both arrive while
+// the matrix cores run.  Four wavefronts per tile, 2 x 2 MFMA 16x16x4 blocks
+// each; the product is formed transposed so that each lane's accumulators run
+// along a column of the column-major front.
 template <typename T>
 __global__ void __launch_bounds__(256) trail_update(T *__restrict__ F, int32_t r, int32_t k0, int32_t kb,
                                                    int32_t r_lo, int32_t c_hi) {
-    __shared__ T As[NB * 64];    // As[kk * 64 + i] = L(r0 + i, k0 + kc + kk)
-    __shared__ T Bs[NB * 64];    // Bs[kk * 64 + j] = L(c0 + j, k0 + kc + kk) * D(k0 + kc + kk)
+    constexpr int KC = 32;
+    constexpr int PER = KC / 4;                    // rank columns staged per thread and chunk
+    __shared__ T As[2][KC * 64];                   // As[kk * 64 + i] = L(r0 + i, k)
+    __shared__ T Bs[2][KC * 64];                   // Bs[kk * 64 + j] = L(c0 + j, k) * D(k)
     const int32_t ti = blockIdx.x, tj = blockIdx.y;
-    if (ti < tj) return;                          // strictly above the diagonal: nothing to do
+    if (ti < tj) return;                           // strictly above the diagonal: nothing to do
     const int32_t r0 = r_lo + 64 * ti, c0 = r_lo + 64 * tj;
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
     const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
     const int lr = lane & 15, lk = lane >> 4;
     typedef typename Acc4<T>::type V;
+    // old C values of this lane's 16 outputs: raw loads from always-valid addresses, validity bits
+    T cold[2][2][4];
+    uint32_t cok = 0;
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int32_t row = r0 + wr + 16 * bi + lr;
+                const int32_t col = c0 + wc + 16 * bj + mfma_out_row<T>(lk, v);
+                const bool ok = row < r && col < c_hi && row >= col;
+                cold[bi][bj][v] = F[ok ? (int64_t)col * r + row : 0];
+                cok |= (uint32_t)ok << (8 * bi + 4 * bj + v);
+            }
+    // staging registers of one chunk (raw values + validity bits; zeroing waits for the LDS store)
+    const int32_t i = tid & 63;
+    T ra[PER], rb[PER], rd[PER];
+    uint32_t va = 0, vb = 0;
+    auto gload = [&](int32_t kc) {
+        va = vb = 0;
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int32_t kk = (tid >> 6) + 4 * u;
+            const bool okk = kc + kk < kb;
+            const int32_t kcol = k0 + kc + (okk ? kk : 0);
+            const T *colp = F + (int64_t)kcol * r;
+            const bool oka = okk && r0 + i < r, okb = okk && c0 + i < c_hi;
+            ra[u] = colp[oka ? r0 + i : 0];
+            rb[u] = colp[okb ? c0 + i : 0];
+            rd[u] = colp[kcol];
+            va |= (uint32_t)oka << u;
+            vb |= (uint32_t)okb << u;
+        }
+    };
+    auto lstore = [&](int buf) {
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int32_t kk = (tid >> 6) + 4 * u;
+            As[buf][kk * 64 + i] = ((va >> u) & 1u) ? ra[u] : T(0);
+            Bs[buf][kk * 64 + i] = ((vb >> u) & 1u) ? rb[u] * rd[u] : T(0);
+        }
+    };
     V acc[2][2];
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = V{0, 0, 0, 0};
-    for (int32_t kc = 0; kc < kb; kc += NB) {
-        const int32_t kn = min(NB, kb - kc);
-        if (kc > 0) __syncthreads();
-        {
-            const int32_t i = tid & 63;
-            // all loads of the chunk are issued before the first LDS store
-            T av[NB / 4], bv[NB / 4], dv[NB / 4];
+    const int32_t nch = (kb + KC - 1) / KC;
+    gload(0);
+    lstore(0);
+    __syncthreads();
+    for (int32_t c = 0; c < nch; ++c) {
+        const int buf = c & 1;
+        if (c + 1 < nch) gload((c + 1) * KC);
 #pragma unroll
-            for (int u = 0; u < NB / 4; ++u) {
-                const int32_t kk = (tid >> 6) + 4 * u;
-                const bool okk = kk < kn;
-                const int32_t kcol = k0 + kc + (okk ? kk : 0);
-                const T *colp = F + (int64_t)kcol * r;
-                av[u] = ld_or0(colp, r0 + i, okk && r0 + i < r);
-                bv[u] = ld_or0(colp, c0 + i, okk && c0 + i < c_hi);
-                dv[u] = colp[kcol];
-            }
-#pragma unroll
-            for (int u = 0; u < NB / 4; ++u) {
-                const int32_t kk = (tid >> 6) + 4 * u;
-                As[kk * 64 + i] = av[u];
-                Bs[kk * 64 + i] = bv[u] * dv[u];
-            }
-        }
-        __syncthreads();
-        for (int32_t kk = 0; kk < kn; kk += 4) {
+        for (int32_t kk = 0; kk < KC; kk += 4) {       // zero-padded past the rank
             const int32_t kq = kk + lk;
             T a_op[2], b_op[2];
 #pragma unroll
-            for (int bj = 0; bj < 2; ++bj) a_op[bj] = Bs[kq * 64 + wc + 16 * bj + lr];
+            for (int bj = 0; bj < 2; ++bj) a_op[bj] = Bs[buf][kq * 64 + wc + 16 * bj + lr];
 #pragma unroll
-            for (int bi = 0; bi < 2; ++bi) b_op[bi] = As[kq * 64 + wr + 16 * bi + lr];
+            for (int bi = 0; bi < 2; ++bi) b_op[bi] = As[buf][kq * 64 + wr + 16 * bi + lr];
 #pragma unroll
             for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
                 for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = mfma16x16x4(a_op[bj], b_op[bi], acc[bi][bj]);
         }
+        if (c + 1 < nch) lstore(buf ^ 1);
+        __syncthreads();
     }
-    // lane holds D(mfma_out_row(lk, v), lr) = C(row = wr + 16 bi + lr, col = wc + 16 bj + mfma_out_row(lk, v));
-    // all old values are loaded before any store
-    T old[2][2][4];
+    // lane holds D(mfma_out_row(lk, v), lr) = C(row = wr + 16 bi + lr, col = wc + 16 bj + mfma_out_row(lk, v))
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
@@ -526,17 +580,7 @@ __global__ void __launch_bounds__(256) trail_update(T *__restrict__ F, int32_t r
             for (int v = 0; v < 4; ++v) {
                 const int32_t row = r0 + wr + 16 * bi + lr;
                 const int32_t col = c0 + wc + 16 * bj + mfma_out_row<T>(lk, v);
-                old[bi][bj][v] = ld_or0(F, (int64_t)col * r + row, row < r && col < c_hi && row >= col);
-            }
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-        for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int32_t row = r0 + wr + 16 * bi + lr;
-                const int32_t col = c0 + wc + 16 * bj + mfma_out_row<T>(lk, v);
-                if (row < r && col < c_hi && row >= col) F[(int64_t)col * r + row] = old[bi][bj][v] - acc[bi][bj][v];
+                if ((cok >> (8 * bi + 4 * bj + v)) & 1u) F[(int64_t)col * r + row] = cold[bi][bj][v] - acc[bi][bj][v];
             }
 }
 

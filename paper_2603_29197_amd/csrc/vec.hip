@@ -42,11 +42,20 @@ __global__ void __launch_bounds__(256) finish_reduce(const double *__restrict__ 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     for (int q = 0; q < ns; ++q) {
         const bool ismax = (maxmask >> q) & 1u;
-        double v = ismax ? -INFINITY : 0.0;
-        for (int32_t b = tid; b < nblk; b += 256) {
-            const double x = partials[(int64_t)b * ns + q];
-            v = ismax ? nan_max(v, x) : v + x;
+        const double id = ismax ? -INFINITY : 0.0;
+        double w4[4] = {id, id, id, id};
+        for (int32_t b0 = tid; b0 < nblk; b0 += 4 * 256) {     // four loads in flight per thread
+            double x[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int32_t b = b0 + 256 * u;
+                const double y = partials[(int64_t)(b < nblk ? b : b0) * ns + q];
+                x[u] = b < nblk ? y : id;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) w4[u] = ismax ? nan_max(w4[u], x[u]) : w4[u] + x[u];
         }
+        double v = ismax ? nan_max(nan_max(w4[0], w4[1]), nan_max(w4[2], w4[3])) : (w4[0] + w4[1]) + (w4[2] + w4[3]);
         for (int off = 32; off > 0; off >>= 1) {
             const double o = __shfl_xor(v, off);
             v = ismax ? nan_max(v, o) : v + o;

@@ -105,8 +105,10 @@ static int allocate_device(qg_handle *h) {
     if ((rc = dalloc(h, d.dinv32, (size_t)pl.dinv_total))) return rc;
     if ((rc = dalloc(h, d.sinv64, (size_t)pl.sinv_total))) return rc;
     if ((rc = dalloc(h, d.sinv32, (size_t)pl.sinv_total))) return rc;
+    if ((rc = dalloc(h, d.w64, (size_t)pl.w_total))) return rc;
+    if ((rc = dalloc(h, d.w32, (size_t)pl.w_total))) return rc;
+    if ((rc = dalloc(h, d.ubuf, (size_t)pl.max_r))) return rc;
     if ((rc = dalloc(h, d.vbuf, (size_t)pl.max_r))) return rc;
-    if ((rc = dalloc(h, d.ybuf, (size_t)SB))) return rc;
     if ((rc = dalloc(h, d.nreg, 1))) return rc;
     if ((rc = dalloc(h, d.x, (size_t)h->n))) return rc;
     if ((rc = dalloc(h, d.y, (size_t)h->p))) return rc;
@@ -244,8 +246,24 @@ void qg_symbolic_free(qg_symbolic *sym) { delete sym; }
 void qg_cleanup(qg_handle *h) {
     if (!h) return;
     if (h->stream) (void)hipStreamSynchronize(h->stream);
+    if (h->bulk) (void)hipStreamSynchronize(h->bulk);
+    if (h->prep) (void)hipStreamSynchronize(h->prep);
     dfree_all(h);
+    for (hipEvent_t e : {h->ev_panel, h->ev_bulk, h->ev_prep})
+        if (e) (void)hipEventDestroy(e);
+    if (h->bulk) (void)hipStreamDestroy(h->bulk);
+    if (h->prep) (void)hipStreamDestroy(h->prep);
     delete h;
+}
+
+// Side streams and ordering events of the factorization.
+static int create_streams(qg_handle *h) {
+    QG_HIP(h, hipStreamCreateWithFlags(&h->bulk, hipStreamNonBlocking));
+    QG_HIP(h, hipStreamCreateWithFlags(&h->prep, hipStreamNonBlocking));
+    QG_HIP(h, hipEventCreateWithFlags(&h->ev_panel, hipEventDisableTiming));
+    QG_HIP(h, hipEventCreateWithFlags(&h->ev_bulk, hipEventDisableTiming));
+    QG_HIP(h, hipEventCreateWithFlags(&h->ev_prep, hipEventDisableTiming));
+    return QG_OK;
 }
 
 int qg_setup(qg_handle **out, qg_int n, qg_int m, qg_int p, const qg_csc *P, const double *c,
@@ -276,6 +294,7 @@ int qg_setup(qg_handle **out, qg_int n, qg_int m, qg_int p, const qg_csc *P, con
         analyze_pattern(h->kp, h->sym);
         h->ms_analyze = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - ta).count();
         if ((rc = build_plan(h))) { qg_cleanup(h); return rc; }
+        if ((rc = create_streams(h))) { qg_cleanup(h); return rc; }
         if ((rc = allocate_device(h))) { qg_cleanup(h); return rc; }
         if ((rc = factor_init_attributes(h))) { qg_cleanup(h); return rc; }
         if ((rc = upload_static_values(h))) { qg_cleanup(h); return rc; }

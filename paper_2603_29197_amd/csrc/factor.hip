@@ -584,14 +584,84 @@ __global__ void __launch_bounds__(256) trail_update(T *__restrict__ F, int32_t r
             }
 }
 
-// Per-launch HIP events of the trailing-update kernel (settings.profile).
-static void prof_begin(qg_handle *h, hipEvent_t *e0, hipEvent_t *e1) {
-    if (hipEventCreate(e0) != hipSuccess || hipEventCreate(e1) != hipSuccess) { *e0 = *e1 = nullptr; return; }
-    (void)hipEventRecord(*e0, h->stream);
+// W_J = L(J1:r, J0:J1) X_J for a super-panel [J0, J1) (X_J the inverse of its
+// unit-lower diagonal block, column-major with leading dimension ld), written
+// column-major with leading dimension r - J1.  The solves use W_J: the forward
+// update of the rows below the super-block is L(below, J) y_J = W_J v_J, which
+// needs v_J only, and the backward pushes W_J' x onto the earlier blocks.
+// 64 x 64 output tiles, grid (row tile, column tile); since X_J is lower
+// triangular, column tile tc only needs ranks >= 64 tc.  MFMA 16x16x4, formed
+// transposed so that lanes run along the rows of W in the store.
+template <typename T>
+__global__ void __launch_bounds__(256) wblock(const T *__restrict__ F, int32_t r, int32_t J0, int32_t kb,
+                                             const T *__restrict__ Xs, int32_t ld, T *__restrict__ W) {
+    constexpr int KC = 32, PER = KC * 64 / 256;
+    __shared__ T As[KC * 64];          // As[kk * 64 + i] = L(J1 + 64 ti + i, J0 + kc + kk)
+    __shared__ T Bs[KC * 65];          // Bs[kk * 65 + j] = X(kc + kk, 64 tc + j)
+    const int32_t J1 = J0 + kb, m = r - J1;
+    const int32_t ti = blockIdx.x, tc = blockIdx.y;
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+    const int lr = lane & 15, lk = lane >> 4;
+    typedef typename Acc4<T>::type V;
+    V acc[2][2];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = V{0, 0, 0, 0};
+    for (int32_t kc = 64 * tc; kc < kb; kc += KC) {
+        T av[PER], bv[PER];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int e = tid + 256 * u;
+            const int i = e & 63, kk = e >> 6;                        // A: lanes along rows
+            av[u] = ld_or0(F, (int64_t)(J0 + kc + kk) * r + J1 + 64 * ti + i, kc + kk < kb && 64 * ti + i < m);
+            const int kb_ = e & (KC - 1), j = e / KC;                 // B: lanes along ranks
+            bv[u] = ld_or0(Xs, (int64_t)(64 * tc + j) * ld + kc + kb_, kc + kb_ < kb && 64 * tc + j < kb);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int e = tid + 256 * u;
+            As[(e >> 6) * 64 + (e & 63)] = av[u];
+            Bs[(e & (KC - 1)) * 65 + e / KC] = bv[u];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < KC; kk += 4) {
+            const int kq = kk + lk;
+            T a_op[2], b_op[2];
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj) a_op[bj] = Bs[kq * 65 + wc + 16 * bj + lr];
+#pragma unroll
+            for (int bi = 0; bi < 2; ++bi) b_op[bi] = As[kq * 64 + wr + 16 * bi + lr];
+#pragma unroll
+            for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = mfma16x16x4(a_op[bj], b_op[bi], acc[bi][bj]);
+        }
+    }
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int32_t row = 64 * ti + wr + 16 * bi + lr;
+                const int32_t c = 64 * tc + wc + 16 * bj + mfma_out_row<T>(lk, v);
+                if (row < m && c < kb) W[(int64_t)c * m + row] = acc[bi][bj][v];
+            }
 }
-static void prof_end(qg_handle *h, hipEvent_t e0, hipEvent_t e1, double flops, int fp32) {
+
+// Per-launch HIP events of the trailing-update kernel (settings.profile).
+static void prof_begin(hipStream_t st, hipEvent_t *e0, hipEvent_t *e1) {
+    if (hipEventCreate(e0) != hipSuccess || hipEventCreate(e1) != hipSuccess) { *e0 = *e1 = nullptr; return; }
+    (void)hipEventRecord(*e0, st);
+}
+static void prof_end(qg_handle *h, hipStream_t st, hipEvent_t e0, hipEvent_t e1, double flops, int fp32) {
     if (!e0) return;
-    (void)hipEventRecord(e1, h->stream);
+    (void)hipEventRecord(e1, st);
     h->prof_events.push_back({{e0, e1}, fp32});
     h->prof_flops[fp32] += flops;
 }
@@ -612,52 +682,96 @@ void prof_collect(qg_handle *h, int64_t *launches, double *ms, double *flops) {
 }
 
 template <typename T>
-static void launch_update(qg_handle *h, T *F, int32_t r, int32_t k0, int32_t kb, int32_t r_lo, int32_t c_hi) {
+static void launch_update(qg_handle *h, hipStream_t st, T *F, int32_t r, int32_t k0, int32_t kb, int32_t r_lo,
+                          int32_t c_hi) {
     const int32_t TR = (r - r_lo + 63) / 64, TC = (c_hi - r_lo + 63) / 64;
-    if (TR <= 0 || TC <= 0) return;
+    if (TR <= 0 || TC <= 0 || kb <= 0) return;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (h->st.profile) prof_begin(h, &e0, &e1);
-    trail_update<T><<<dim3((unsigned)TR, (unsigned)TC), 256, 0, h->stream>>>(F, r, k0, kb, r_lo, c_hi);
+    if (h->st.profile) prof_begin(st, &e0, &e1);
+    trail_update<T><<<dim3((unsigned)TR, (unsigned)TC), 256, 0, st>>>(F, r, k0, kb, r_lo, c_hi);
     if (h->st.profile) {
         // lower part of rows [r_lo, r) x cols [r_lo, c_hi): sum over columns of (r - col)
         const double M = (double)(r - r_lo), C = (double)(c_hi - r_lo);
         const double entries = C * M - C * (C - 1.0) / 2.0;
-        prof_end(h, e0, e1, 2.0 * (double)kb * entries, sizeof(T) == 4);
+        prof_end(h, st, e0, e1, 2.0 * (double)kb * entries, sizeof(T) == 4);
     }
 }
 
+// Large front: super-panels of SB columns, each factored in NB-column
+// panels (diag_block, panel_solve, update of the rest of the super-panel) on
+// the main stream.  With lookahead: the rank-SB update of a super-panel is
+// split into the columns of the next super-panel (main stream, before that
+// super-panel is factored) and everything beyond (bulk stream), so the bulk
+// update of super-panel J runs while super-panel J+1 is factored.  The bulk
+// update of J and the next-columns update of J+1 touch the same columns, so
+// the latter waits for the former.  The inverses and W blocks that only the
+// solves need are formed on the prep stream.  Both side streams are joined at
+// the end.
 template <typename T>
-static int factor_large(qg_handle *h, int32_t s, T *front, T *dinv, T *sinv, const RegParams &rp) {
+static int factor_large(qg_handle *h, int32_t s, T *front, T *dinv, T *sinv, T *wb, const RegParams &rp) {
     const Plan &pl = h->plan;
     const int32_t r = (int32_t)(pl.sn_rptr[s + 1] - pl.sn_rptr[s]);
     const int32_t k = pl.sn_first[s + 1] - pl.sn_first[s];
     T *F = front + pl.fr_off[s];
     const int8_t *kinds = h->d.reg_sign.p + pl.sn_first[s];
+    hipStream_t ms = h->stream;
+    bool bulk_pending = false;
+    // everything before this front on the main stream is visible to the side streams
+    QG_HIP(h, hipEventRecord(h->ev_panel, ms));
+    QG_HIP(h, hipStreamWaitEvent(h->bulk, h->ev_panel, 0));
+    QG_HIP(h, hipStreamWaitEvent(h->prep, h->ev_panel, 0));
     for (int32_t J0 = 0; J0 < k; J0 += SB) {
         const int32_t J1 = std::min(k, J0 + SB);
         for (int32_t j0 = J0; j0 < J1; j0 += NB) {
             const int32_t b = std::min(NB, J1 - j0);
             T *ws = dinv + pl.dinv_off[s] + (int64_t)(j0 / NB) * NB * NB;
-            diag_block<T><<<1, 256, 0, h->stream>>>(F, r, j0, b, kinds, rp.eps, rp.dyn, h->d.nreg.p, ws);
+            diag_block<T><<<1, 256, 0, ms>>>(F, r, j0, b, kinds, rp.eps, rp.dyn, h->d.nreg.p, ws);
             const int32_t mb = r - j0 - b;
-            if (mb > 0) panel_solve<T><<<(mb + 63) / 64, 256, 0, h->stream>>>(F, r, j0, b, ws);
+            if (mb > 0) panel_solve<T><<<(mb + 63) / 64, 256, 0, ms>>>(F, r, j0, b, ws);
             // rest of this super-panel's columns (rank b)
-            if (j0 + b < J1) launch_update<T>(h, F, r, j0, b, j0 + b, J1);
+            if (j0 + b < J1) launch_update<T>(h, ms, F, r, j0, b, j0 + b, J1);
         }
+        QG_HIP(h, hipEventRecord(h->ev_panel, ms));
         {
+            // solve-only data of this super-panel
+            QG_HIP(h, hipStreamWaitEvent(h->prep, h->ev_panel, 0));
             const int32_t nsub = (J1 - J0 + NB - 1) / NB, ld = nsub * NB;
             T *Xs = sinv + pl.sinv_off[s] + (int64_t)(J0 / SB) * 2 * SB * SB;
-            sblock_inverse<T><<<nsub, 256, 0, h->stream>>>(F, r, J0, J1 - J0, dinv + pl.dinv_off[s], ld, Xs,
-                                                           Xs + (int64_t)ld * ld);
+            sblock_inverse<T><<<nsub, 256, 0, h->prep>>>(F, r, J0, J1 - J0, dinv + pl.dinv_off[s], ld, Xs,
+                                                         Xs + (int64_t)ld * ld);
+            if (J1 < r)
+                wblock<T><<<dim3((unsigned)((r - J1 + 63) / 64), (unsigned)nsub), 256, 0, h->prep>>>(
+                    F, r, J0, J1 - J0, Xs, ld, wb + pl.w_off[s] + w_block_offset(r, J0));
         }
-        // everything to the right of the super-panel (rank J1 - J0)
-        if (J1 < r) launch_update<T>(h, F, r, J0, J1 - J0, J1, r);
+        if (J1 < r) {
+            const int32_t J2 = std::min(r, J1 + SB);
+            // bulk: columns [J2, r), after this super-panel's panels
+            if (J2 < r) {
+                QG_HIP(h, hipStreamWaitEvent(h->bulk, h->ev_panel, 0));
+                launch_update<T>(h, h->bulk, F, r, J0, J1 - J0, J2, r);
+            }
+            // next super-panel's columns [J1, J2): after the previous bulk update, which also wrote them
+            if (bulk_pending) QG_HIP(h, hipStreamWaitEvent(ms, h->ev_bulk, 0));
+            launch_update<T>(h, ms, F, r, J0, J1 - J0, J1, J2);
+            if (J2 < r) {
+                QG_HIP(h, hipEventRecord(h->ev_bulk, h->bulk));
+                bulk_pending = true;
+            } else {
+                bulk_pending = false;
+            }
+        }
     }
+    // join
+    if (bulk_pending) QG_HIP(h, hipStreamWaitEvent(ms, h->ev_bulk, 0));
+    QG_HIP(h, hipEventRecord(h->ev_prep, h->prep));
+    QG_HIP(h, hipStreamWaitEvent(ms, h->ev_prep, 0));
+    QG_HIP(h, hipEventRecord(h->ev_bulk, h->bulk));
+    QG_HIP(h, hipStreamWaitEvent(ms, h->ev_bulk, 0));
     return QG_OK;
 }
 
 template <typename T>
-static int factor_all(qg_handle *h, T *front, T *dinv, T *sinv, const RegParams &rp) {
+static int factor_all(qg_handle *h, T *front, T *dinv, T *sinv, T *wb, const RegParams &rp) {
     const Plan &pl = h->plan;
     Device &d = h->d;
     for (int32_t L = 0; L < pl.nlevels; ++L) {
@@ -674,8 +788,10 @@ static int factor_all(qg_handle *h, T *front, T *dinv, T *sinv, const RegParams 
                                                                d.sn_rptr.p, d.fr_off.p, front,
                                                                d.reg_sign.p, rp.eps, rp.dyn, d.nreg.p);
         }
-        for (int32_t u = pl.lvl_large_ptr[L]; u < pl.lvl_large_ptr[L + 1]; ++u)
-            factor_large<T>(h, pl.lvl_large_sn[u], front, dinv, sinv, rp);
+        for (int32_t u = pl.lvl_large_ptr[L]; u < pl.lvl_large_ptr[L + 1]; ++u) {
+            const int rc = factor_large<T>(h, pl.lvl_large_sn[u], front, dinv, sinv, wb, rp);
+            if (rc) return rc;
+        }
     }
     QG_HIP(h, hipGetLastError());
     return QG_OK;
@@ -698,10 +814,10 @@ int launch_factor(qg_handle *h, int precision) {
     int rc;
     if (precision == QG_FP32_IR) {
         RegParams rp{st.static_reg32, st.dyn_eps32, st.dyn_delta32};
-        rc = factor_all<float>(h, h->d.front32.p, h->d.dinv32.p, h->d.sinv32.p, rp);
+        rc = factor_all<float>(h, h->d.front32.p, h->d.dinv32.p, h->d.sinv32.p, h->d.w32.p, rp);
     } else {
         RegParams rp{st.static_reg, st.dyn_eps, st.dyn_delta};
-        rc = factor_all<double>(h, h->d.front64.p, h->d.dinv64.p, h->d.sinv64.p, rp);
+        rc = factor_all<double>(h, h->d.front64.p, h->d.dinv64.p, h->d.sinv64.p, h->d.w64.p, rp);
     }
     h->last_precision = precision;
     return rc;

@@ -41,6 +41,13 @@ __device__ inline T ld_or0(const T *__restrict__ p, int64_t i, bool ok) {
     return ok ? v : T(0);
 }
 
+// Offset of the block W_J of super-block J0 (a multiple of SB) within a large
+// front's W storage: the earlier super-blocks are full, (r - J1') x SB each.
+__host__ __device__ inline int64_t w_block_offset(int64_t r, int64_t J0) {
+    const int64_t n = J0 / SB;
+    return SB * (n * r - SB * n * (n + 1) / 2);
+}
+
 struct RegParams {
     double delta;     // static regularization
     double eps;       // dynamic threshold

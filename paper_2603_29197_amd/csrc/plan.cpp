@@ -62,8 +62,8 @@ void dfree_all(qg_handle *h) {
     dfree(d.lvl_small_sn); dfree(d.sn_rptr); dfree(d.fr_off); dfree(d.task_ptr); dfree(d.asm_ptr);
     dfree(d.asm_src); dfree(d.ctb_ptr); dfree(d.rel_ptr); dfree(d.uv_off); dfree(d.reg_sign);
     dfree(d.front64); dfree(d.front32); dfree(d.uvec); dfree(d.dinv64); dfree(d.dinv32);
-    dfree(d.sinv64); dfree(d.sinv32);
-    dfree(d.vbuf); dfree(d.ybuf); dfree(d.col2sn); dfree(d.nreg); dfree(d.vwork); dfree(d.task0);
+    dfree(d.sinv64); dfree(d.sinv32); dfree(d.w64); dfree(d.w32); dfree(d.ubuf);
+    dfree(d.vbuf); dfree(d.col2sn); dfree(d.nreg); dfree(d.vwork); dfree(d.task0);
     dfree(d.x); dfree(d.y); dfree(d.s); dfree(d.z); dfree(d.rx); dfree(d.ry); dfree(d.rz);
     dfree(d.kx); dfree(d.rhs); dfree(d.sol); dfree(d.res); dfree(d.corr); dfree(d.xp);
     dfree(d.dsa); dfree(d.ds); dfree(d.t); dfree(d.lam); dfree(d.w); dfree(d.wbar); dfree(d.beta);
@@ -206,6 +206,20 @@ int build_plan(qg_handle *h) {
         pl.sinv_off[s + 1] = pl.sinv_off[s] + sz;
     }
     pl.sinv_total = pl.sinv_off[ns];
+    // W_J = L(rows below the super-block, J) X_J per super-block of a large front
+    pl.w_off.assign((size_t)ns + 1, 0);
+    for (int32_t s = 0; s < ns; ++s) {
+        const int64_t r = pl.sn_rptr[s + 1] - pl.sn_rptr[s];
+        const int64_t k = pl.sn_first[s + 1] - pl.sn_first[s];
+        int64_t sz = 0;
+        if (r > SMALL_R)
+            for (int64_t J0 = 0; J0 < k; J0 += SB) {
+                const int64_t J1 = std::min<int64_t>(k, J0 + SB);
+                sz += (r - J1) * (J1 - J0);
+            }
+        pl.w_off[s + 1] = pl.w_off[s] + sz;
+    }
+    pl.w_total = pl.w_off[ns];
     // levels
     pl.lvl_ptr.assign((size_t)pl.nlevels + 1, 0);
     for (int32_t s = 0; s < ns; ++s) pl.lvl_ptr[sym.sn_level[s] + 1]++;

@@ -57,6 +57,9 @@ struct Plan {
     int64_t dinv_total = 0;
     std::vector<int64_t> sinv_off;        // per supernode: inverses (X, X') of its SB x SB diagonal blocks
     int64_t sinv_total = 0;
+    std::vector<int64_t> w_off;           // per supernode: the blocks W_J = L(below J, J) X_J, super-block
+                                          // by super-block, each column-major with ld = r - J1
+    int64_t w_total = 0;
     std::vector<int32_t> ch_ptr, ch_list; // children supernodes
     std::vector<int8_t> reg_sign;         // per permuted column: +1 x, -1 y, 0 z
     int64_t front_total = 0, uv_total = 0;
@@ -89,8 +92,10 @@ struct Device {
     DBuf<float> dinv32;
     DBuf<double> sinv64;        // inverses of the SB x SB diagonal blocks (and transposes)
     DBuf<float> sinv32;
+    DBuf<double> w64;           // W_J blocks of the large fronts (solves only)
+    DBuf<float> w32;
+    DBuf<double> ubuf;          // max_r: X' v of every super-block in the backward large-front solve
     DBuf<double> vbuf;          // work vector of length max_r (large-front solves)
-    DBuf<double> ybuf;          // SB: solution of the current super-block in the large-front solves
     DBuf<int32_t> col2sn;
     DBuf<int32_t> nreg;         // dynamic regularization counter
     // iterate and work vectors
@@ -117,6 +122,11 @@ struct Timer {
 struct qg_handle {
     qg_settings st;
     hipStream_t stream = nullptr;
+    // Side streams of the large-front factorization (default priority, non-blocking):
+    // bulk = trailing updates beyond the next super-panel, prep = inverses and W blocks
+    // for the solves; ordered against `stream` with the events below.
+    hipStream_t bulk = nullptr, prep = nullptr;
+    hipEvent_t ev_panel = nullptr, ev_bulk = nullptr, ev_prep = nullptr;
     int last_hip = 0;
     int device = 0;
     qg::ProblemPattern pp;

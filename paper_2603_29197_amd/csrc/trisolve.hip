@@ -10,9 +10,11 @@
 // precision (FP32 factors are widened on load).
 //
 // Small fronts: one 128-thread workgroup per supernode, per level.  Large
-// fronts: per SB-column super-block, one kernel applies the stored inverse of
-// its unit-lower diagonal block (or its transpose) and a second one updates
-// the rows below it (forward) or the columns before it (backward).
+// fronts, per SB-column super-block J with the stored inverse X_J of its
+// unit-lower diagonal block and W_J = L(below J, J) X_J: forward, one kernel
+// forms y_J = X_J v_J and, in other workgroups, v_below -= W_J v_J; backward,
+// one kernel forms u_J = X_J' v_J for all blocks, then per block (last to
+// first) one kernel takes x_J = u_J and pushes W_J' x_J onto the earlier u.
 #include "kernels.hpp"
 #include "solver.hpp"
 
@@ -109,63 +111,69 @@ __global__ void __launch_bounds__(SMALL_R) bwd_small(
 }
 
 // ------------------------------- large -------------------------------------
-// y = X v (forward, X the stored inverse of the unit-lower diagonal block of
-// a super-block) or y = X' v (backward, the stored transpose), kb <= SB;
-// the result goes to y and to the solution.  Workgroup g forms entries
-// 64 g .. 64 g + 63; wavefront w sums over columns q in [64 w, 64 w + 64) of
-// the column-major operand (lanes along rows: coalesced), then the four
-// partial sums are added in a fixed order.
+// Sum over q of the column-major operand M(t, q) u(q) for one entry t per
+// lane: wavefront w takes the columns q in [q_lo(w), q_hi(w)) (lanes along
+// rows: coalesced), and the four partial sums are added in a fixed order.
+// Returns the sum in wavefront 0 (other wavefronts return 0).
 template <typename T>
-__global__ void __launch_bounds__(256) sblock_apply(const T *__restrict__ X, int32_t ld, int32_t kb,
-                                                    const double *__restrict__ vin, double *__restrict__ y,
-                                                    double *__restrict__ xp_out, int32_t upper) {
-    __shared__ double vs[SB];
-    __shared__ double red[4][64];
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int32_t g = blockIdx.x;
-    if (tid < kb) vs[tid] = vin[tid];
-    __syncthreads();
-    const int32_t t = g * 64 + lane;
-    // lower operand: columns q <= t; upper operand: columns q >= t
-    const bool live = upper ? (w >= g) : (w <= g);
+__device__ inline double quarter_gemv(const T *__restrict__ Mt, int64_t ldm, const double *__restrict__ u,
+                                      int32_t q_lo, int32_t q_hi, bool live, double (&red)[4][64]) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     double acc = 0.0;
-    if (live && t < kb) {
-        const int32_t q1 = min(kb, 64 * w + 64);
-        const T *Xr = X + t;
+    if (live) {
 #pragma unroll 16
-        for (int32_t q = 64 * w; q < q1; ++q) acc += (double)Xr[(int64_t)q * ld] * vs[q];
+        for (int32_t q = q_lo; q < q_hi; ++q) acc += (double)Mt[(int64_t)q * ldm] * u[q];
     }
     red[w][lane] = acc;
     __syncthreads();
-    if (w == 0 && t < kb) {
-        const double v = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
-        y[t] = v;
-        xp_out[t] = v;
+    return w == 0 ? ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane] : 0.0;
+}
+
+// Forward step of super-block [J0, J0+kb) of a large front (work vector vs,
+// rows 0..r-1 of the front): workgroups 0..G-1 (G = kb / 64 rounded up) form
+// y = X_J v_J and write it to the solution; the others update the rows below,
+// v[J1 + i] -= sum_q W_J(i, q) v_J(q) (W_J = L(below, J) X_J, so this equals
+// L(below, J) y without waiting for y).  One launch per super-block.
+template <typename T>
+__global__ void __launch_bounds__(256) fwd_block(const T *__restrict__ X, int32_t ld, int32_t kb,
+                                                 const T *__restrict__ W, int32_t m, int32_t J0,
+                                                 double *__restrict__ vs, double *__restrict__ xp_own) {
+    __shared__ double vj[SB];
+    __shared__ double red[4][64];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    if (tid < kb) vj[tid] = vs[J0 + tid];
+    __syncthreads();
+    const int32_t G = (kb + 63) / 64;
+    const int32_t g = blockIdx.x;
+    if (g < G) {
+        // X lower: entry t = 64 g + lane needs columns q <= t
+        const int32_t t = 64 * g + lane;
+        const double y = quarter_gemv(X + t, ld, vj, 64 * w, min(kb, 64 * w + 64), w <= g && t < kb, red);
+        if (w == 0 && t < kb) xp_own[J0 + t] = y;
+    } else {
+        const int32_t i = 64 * (g - G) + lane;
+        const double s = quarter_gemv(W + i, (int64_t)m, vj, 64 * w, min(kb, 64 * w + 64), i < m, red);
+        if (w == 0 && i < m) vs[J0 + kb + i] -= s;
     }
 }
 
-// Forward update of the rows below a super-block: v[row] -= L(row, J0:J0+kb) y
-// for 64 rows per workgroup; wavefront w takes columns [64 w, 64 w + 64)
-// (lanes along rows: coalesced), fixed-order sum over wavefronts.
+// Backward, all super-blocks of a large front at once: u_J = X_J' v_J
+// (grid (4, super-blocks); X_J' stored column-major, upper triangular).
 template <typename T>
-__global__ void __launch_bounds__(256) sblock_rows(const T *__restrict__ F, int32_t r, int32_t J0, int32_t kb,
-                                                   const double *__restrict__ y, double *__restrict__ vbuf) {
-    __shared__ double ys[SB];
+__global__ void __launch_bounds__(256) bwd_apply_all(const T *__restrict__ sinv_s, int32_t k,
+                                                     const double *__restrict__ v, double *__restrict__ u) {
+    __shared__ double vj[SB];
     __shared__ double red[4][64];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    if (tid < kb) ys[tid] = y[tid];
+    const int32_t g = blockIdx.x, J0 = blockIdx.y * SB;
+    const int32_t kb = min(SB, k - J0), ld = (kb + NB - 1) / NB * NB;
+    if (64 * g >= kb) return;                       // whole workgroup: nothing in this quarter
+    const T *XT = sinv_s + (int64_t)(J0 / SB) * 2 * SB * SB + (int64_t)ld * ld;
+    if (tid < kb) vj[tid] = v[J0 + tid];
     __syncthreads();
-    const int32_t row = J0 + kb + blockIdx.x * 64 + lane;
-    double acc = 0.0;
-    if (row < r) {
-        const int32_t q1 = min(kb, 64 * w + 64);
-        const T *p = F + (int64_t)J0 * r + row;
-#pragma unroll 16
-        for (int32_t q = 64 * w; q < q1; ++q) acc += (double)p[(int64_t)q * r] * ys[q];
-    }
-    red[w][lane] = acc;
-    __syncthreads();
-    if (w == 0 && row < r) vbuf[row] -= ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+    const int32_t t = 64 * g + lane;
+    const double y = quarter_gemv(XT + t, ld, vj, 64 * w, min(kb, 64 * w + 64), w >= g && t < kb, red);
+    if (w == 0 && t < kb) u[J0 + t] = y;
 }
 
 // v[0:k] = D^-1 x_own - L21' g with g = x at the rows below (one column per
@@ -189,33 +197,39 @@ __global__ void __launch_bounds__(256) bwd_init(int32_t s, const int32_t *__rest
     if (lane == 0) vbuf[c] = xp[f + c] / (double)F[(int64_t)c * r + c] - acc;
 }
 
-// Backward update of the columns before a super-block:
-// v[c] -= L(J0:J0+kb, c)' y for 64 columns per workgroup, 16 per wavefront;
-// lanes run along the contiguous rows of each column (coalesced), all loads
-// of a wavefront are issued before its 16 shuffle reductions, and lanes
-// 0..15 then update the 16 entries at once.
+// Backward step of super-block [K0, K0+kb): x_K = u_K is final (every later
+// block has pushed onto it); workgroup 0 writes it to the solution, and every
+// workgroup pushes it onto 64 earlier entries: u[c] -= sum_t W_J(K0 - J1 + t,
+// c - J0) x_K(t) for the block J = [J0, J1) that holds c.  Lanes run along the
+// contiguous rows of each W column (coalesced), all loads of a wavefront are
+// issued before its 16 shuffle reductions, and lanes 0..15 then update the 16
+// entries at once.
 template <typename T>
-__global__ void __launch_bounds__(256) sblock_cols(const T *__restrict__ F, int32_t r, int32_t J0, int32_t kb,
-                                                   const double *__restrict__ y, double *__restrict__ vbuf) {
-    __shared__ double ys[SB];
+__global__ void __launch_bounds__(256) bwd_push(const T *__restrict__ W_s, int32_t r, int32_t K0, int32_t kb,
+                                                double *__restrict__ u, double *__restrict__ xp_own) {
+    __shared__ double xs[SB];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    if (tid < kb) ys[tid] = y[tid];
+    if (tid < kb) xs[tid] = u[K0 + tid];
     __syncthreads();
+    if (blockIdx.x == 0 && tid < kb) xp_own[K0 + tid] = xs[tid];
     const int32_t c0 = blockIdx.x * NB + w * 16;
+    if (blockIdx.x * NB >= K0) return;
+    const int32_t J0 = (blockIdx.x * NB) / SB * SB, J1 = J0 + SB;   // a full block: J1 <= K0
+    const int64_t m = r - J1;
+    const T *Wj = W_s + w_block_offset(r, J0) + (K0 - J1);
     double part[16];
 #pragma unroll
     for (int cc = 0; cc < 16; ++cc) {
         const int32_t c = c0 + cc;
         double s = 0.0;
 #pragma unroll
-        for (int m = 0; m < SB / 64; ++m) {
-            const int32_t t = lane + 64 * m;
-            const bool ok = c < J0 && t < kb;
-            s += (double)ld_or0(F, (int64_t)c * r + J0 + t, ok) * ys[ok ? t : 0];
+        for (int q = 0; q < SB / 64; ++q) {
+            const int32_t t = lane + 64 * q;
+            const bool ok = c < K0 && t < kb;
+            s += (double)ld_or0(Wj, (int64_t)(c - J0) * m + t, ok) * xs[ok ? t : 0];
         }
         part[cc] = s;
     }
-    // after the butterfly every lane holds the sum; lane cc updates column c0 + cc
     double mine = 0.0;
 #pragma unroll
     for (int cc = 0; cc < 16; ++cc) {
@@ -223,12 +237,12 @@ __global__ void __launch_bounds__(256) sblock_cols(const T *__restrict__ F, int3
         for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
         mine = lane == cc ? s : mine;
     }
-    if (lane < 16 && c0 + lane < J0) vbuf[c0 + lane] -= mine;
+    if (lane < 16 && c0 + lane < K0) u[c0 + lane] -= mine;
 }
 
 // ------------------------------- driver ------------------------------------
 template <typename T>
-static int solve_perm(qg_handle *h, const T *front, const T *sinv) {
+static int solve_perm(qg_handle *h, const T *front, const T *sinv, const T *wbuf) {
     const Plan &pl = h->plan;
     Device &d = h->d;
     double *xp = d.xp.p;
@@ -250,12 +264,11 @@ static int solve_perm(qg_handle *h, const T *front, const T *sinv) {
             for (int32_t J0 = 0; J0 < k; J0 += SB) {
                 const int32_t kb = std::min(SB, k - J0);
                 const int32_t ld = (kb + NB - 1) / NB * NB;
+                const int32_t m = r - J0 - kb;
                 const T *Xsb = sinv + pl.sinv_off[s] + (int64_t)(J0 / SB) * 2 * SB * SB;
-                sblock_apply<T><<<(kb + 63) / 64, 256, 0, h->stream>>>(Xsb, ld, kb, vs + J0, d.ybuf.p,
-                                                                     xp + pl.sn_first[s] + J0, 0);
-                const int32_t rows = r - J0 - kb;
-                if (rows > 0)
-                    sblock_rows<T><<<(rows + 63) / 64, 256, 0, h->stream>>>(F, r, J0, kb, d.ybuf.p, vs);
+                const T *Wj = wbuf + pl.w_off[s] + w_block_offset(r, J0);
+                const unsigned grid = (unsigned)((kb + 63) / 64 + (m + 63) / 64);
+                fwd_block<T><<<grid, 256, 0, h->stream>>>(Xsb, ld, kb, Wj, m, J0, vs, xp + pl.sn_first[s]);
             }
         }
     }
@@ -268,15 +281,13 @@ static int solve_perm(qg_handle *h, const T *front, const T *sinv) {
             bwd_init<T><<<(k + 3) / 4, 256, 0, h->stream>>>(s, d.sn_first.p, d.sn_rptr.p, d.sn_rows.p, F, xp,
                                                             d.vbuf.p);
             const int32_t nsb = (k + SB - 1) / SB;
+            bwd_apply_all<T><<<dim3(SB / 64, (unsigned)nsb), 256, 0, h->stream>>>(sinv + pl.sinv_off[s], k, d.vbuf.p,
+                                                                             d.ubuf.p);
             for (int32_t bi = nsb - 1; bi >= 0; --bi) {
-                const int32_t J0 = bi * SB;
-                const int32_t kb = std::min(SB, k - J0);
-                const int32_t ld = (kb + NB - 1) / NB * NB;
-                const T *XTsb = sinv + pl.sinv_off[s] + (int64_t)(J0 / SB) * 2 * SB * SB + (int64_t)ld * ld;
-                sblock_apply<T><<<(kb + 63) / 64, 256, 0, h->stream>>>(XTsb, ld, kb, d.vbuf.p + J0, d.ybuf.p,
-                                                                     xp + pl.sn_first[s] + J0, 1);
-                if (J0 > 0)
-                    sblock_cols<T><<<(J0 + NB - 1) / NB, 256, 0, h->stream>>>(F, r, J0, kb, d.ybuf.p, d.vbuf.p);
+                const int32_t K0 = bi * SB;
+                const int32_t kb = std::min(SB, k - K0);
+                const unsigned grid = (unsigned)std::max(1, (K0 + NB - 1) / NB);
+                bwd_push<T><<<grid, 256, 0, h->stream>>>(wbuf + pl.w_off[s], r, K0, kb, d.ubuf.p, xp + pl.sn_first[s]);
             }
         }
         const int32_t s0 = pl.lvl_small_ptr[L], s1 = pl.lvl_small_ptr[L + 1];
@@ -304,8 +315,8 @@ int launch_solve(qg_handle *h, const double *rhs, double *x, int precision) {
     const int32_t N = h->N;
     const unsigned g = (unsigned)((N + 255) / 256);
     gather_perm<<<g, 256, 0, h->stream>>>(rhs, h->d.perm.p, h->d.xp.p, N);
-    int rc = precision == QG_FP32_IR ? solve_perm<float>(h, h->d.front32.p, h->d.sinv32.p)
-                                     : solve_perm<double>(h, h->d.front64.p, h->d.sinv64.p);
+    int rc = precision == QG_FP32_IR ? solve_perm<float>(h, h->d.front32.p, h->d.sinv32.p, h->d.w32.p)
+                                     : solve_perm<double>(h, h->d.front64.p, h->d.sinv64.p, h->d.w64.p);
     if (rc) return rc;
     scatter_perm<<<g, 256, 0, h->stream>>>(h->d.xp.p, h->d.perm.p, x, N);
     QG_HIP(h, hipGetLastError());

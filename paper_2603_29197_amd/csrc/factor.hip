@@ -148,6 +148,11 @@ __global__ void __launch_bounds__(256) factor_small(
 // ---------------------------------------------------------------------------
 // large fronts
 // ---------------------------------------------------------------------------
+// Reciprocal of a pivot: the hardware reciprocal (1 ulp) for FP32 factors,
+// whose errors the FP64 refinement removes; correctly rounded for FP64.
+__device__ inline float recip(float d) { return __builtin_amdgcn_rcpf(d); }
+__device__ inline double recip(double d) { return 1.0 / d; }
+
 // Value of lane `src` (a compile-time constant) of v, for every lane.
 __device__ inline float lane_bcast(float v, int src) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
@@ -223,15 +228,18 @@ __global__ void __launch_bounds__(256) diag_block(T *__restrict__ F, int32_t r, 
                 a[m] = (lr < pb && m < pb && m <= lr) ? v : T(0);
             }
             T dmine = T(0);
+            double sgv[PB];                            // pivot signs, read before the pivot chain
+#pragma unroll
+            for (int j = 0; j < PB; ++j) sgv[j] = sgn[p0 + j];
 #pragma unroll
             for (int j = 0; j < PB; ++j) {
                 if (j < pb) {
                     const T raw = lane_bcast(a[j], j);
-                    const double sg = sgn[p0 + j];
+                    const double sg = sgv[j];
                     const bool fix = !(sg * (double)raw > eps);
                     const T d = fix ? (T)(sg * dyn) : raw;
                     events += fix ? 1 : 0;
-                    const T inv = T(1) / d;
+                    const T inv = recip(d);
                     const T l = lr > j ? a[j] * inv : T(0);
 #pragma unroll
                     for (int k = j + 1; k < PB; ++k) a[k] -= l * lane_bcast(a[j], k);
@@ -239,19 +247,28 @@ __global__ void __launch_bounds__(256) diag_block(T *__restrict__ F, int32_t r, 
                     dmine = lr == j ? d : dmine;
                 }
             }
-            // inverse of the unit lower sub-block: lane c forms column c
-            T x[PB];
-#pragma unroll
-            for (int k = 0; k < PB; ++k) x[k] = (k == lr) ? T(1) : T(0);
-#pragma unroll
-            for (int m = 0; m < PB; ++m)
-#pragma unroll
-                for (int k = m + 1; k < PB; ++k) x[k] -= lane_bcast(a[m], k) * x[m];
             if (lane < pb) {
 #pragma unroll
                 for (int m = 0; m < PB; ++m)
                     if (m <= lane) S[(p0 + m) * LD + p0 + lane] = a[m];
                 Dd[p0 + lane] = dmine;
+            }
+            __builtin_amdgcn_wave_barrier();
+            // inverse of the unit lower sub-block: lane c forms column c, reading the
+            // columns of L back from LDS (broadcast reads; LDS operations of one
+            // wavefront complete in order)
+            T x[PB];
+#pragma unroll
+            for (int k = 0; k < PB; ++k) x[k] = (k == lr) ? T(1) : T(0);
+#pragma unroll
+            for (int m = 0; m < PB; ++m) {
+                T lc[PB];
+#pragma unroll
+                for (int k = m + 1; k < PB; ++k) lc[k] = S[(p0 + m) * LD + p0 + k];
+#pragma unroll
+                for (int k = m + 1; k < PB; ++k) x[k] -= ((k < pb && m < pb) ? lc[k] : T(0)) * x[m];
+            }
+            if (lane < pb) {
 #pragma unroll
                 for (int k = 0; k < PB; ++k)
                     if (k < pb && k >= lane) X[(p0 + lane) * LD + p0 + k] = x[k];

@@ -21,7 +21,7 @@
 namespace qg {
 
 // ------------------------------- small -------------------------------------
-// Gather of one level: RL lanes per (front s, row j) task:
+// Gather for the rows of a large front: RL lanes per (front s, row j) task:
 // v = [j < k_s ? x_perm(first_s + j) : 0] + sum over the child columns that map
 // onto row j of their update-vector entries (contribution lists of the
 // assembly, with the position of each entry in the work vector precomputed).
@@ -57,11 +57,17 @@ __global__ void __launch_bounds__(256) fwd_gather_level(
     }
 }
 
+// Small front, forward: one 128-thread workgroup per front of a level, one
+// thread per row.  The row's right-hand side is gathered here (own entry plus
+// the children's update-vector entries that map onto it, in child order),
+// then k elimination steps with L columns read from the front, and the update
+// vector is left in the front's own slots for the parent.
 template <typename T>
 __global__ void __launch_bounds__(SMALL_R) fwd_small(
     const int32_t *__restrict__ sn_list, const int32_t *__restrict__ sn_first,
     const int64_t *__restrict__ sn_rptr, const int64_t *__restrict__ fr_off, const T *__restrict__ front,
-    const int64_t *__restrict__ task0, double *__restrict__ vwork, double *__restrict__ xp) {
+    const int64_t *__restrict__ task0, const int64_t *__restrict__ ctb_ptr, const int64_t *__restrict__ ctb_src,
+    double *__restrict__ vwork, double *__restrict__ xp) {
     __shared__ double v[SMALL_R];
     const int32_t s = sn_list[blockIdx.x];
     const int lane = threadIdx.x;
@@ -69,42 +75,59 @@ __global__ void __launch_bounds__(SMALL_R) fwd_small(
     const int32_t r = (int32_t)(sn_rptr[s + 1] - sn_rptr[s]);
     const int32_t k = sn_first[s + 1] - f;
     double *vs = vwork + task0[s];
-    if (lane < r) v[lane] = vs[lane];
+    if (lane < r) {
+        const int64_t tk = task0[s] + lane;
+        double a = lane < k ? xp[f + lane] : 0.0;
+        for (int64_t u = ctb_ptr[tk]; u < ctb_ptr[tk + 1]; ++u) a += vwork[ctb_src[u]];
+        v[lane] = a;
+    }
     __syncthreads();
     const T *F = front + fr_off[s];
     for (int32_t jj = 0; jj < k; ++jj) {
         const double yj = v[jj];
-        if (lane > jj && lane < r) v[lane] -= (double)F[(int64_t)jj * r + lane] * yj;
+        const bool act = lane > jj && lane < r;
+        const T l = F[(int64_t)jj * r + (act ? lane : jj)];
+        if (act) v[lane] -= (double)l * yj;
         __syncthreads();
     }
     if (lane < k) xp[f + lane] = v[lane];
     else if (lane < r) vs[lane] = v[lane];
 }
 
+// Small front, backward: v = D^-1 x_own - L21' g (g = solution at the
+// update rows), then the unit-upper solve with L11'.  The products with
+// L21' are formed by all threads (thread i takes row i of each pivot
+// column) with a wavefront butterfly and a two-wavefront sum, instead of a
+// serial loop per pivot.
 template <typename T>
 __global__ void __launch_bounds__(SMALL_R) bwd_small(
     const int32_t *__restrict__ sn_list, const int32_t *__restrict__ sn_first,
     const int64_t *__restrict__ sn_rptr, const int32_t *__restrict__ sn_rows,
     const int64_t *__restrict__ fr_off, const T *__restrict__ front, double *__restrict__ xp) {
-    __shared__ double g[SMALL_R];
     __shared__ double v[SMALL_R];
+    __shared__ double part[2][SMALL_R];
     const int32_t s = sn_list[blockIdx.x];
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x, w = lane >> 6, l64 = lane & 63;
     const int32_t f = sn_first[s];
     const int32_t r = (int32_t)(sn_rptr[s + 1] - sn_rptr[s]);
     const int32_t k = sn_first[s + 1] - f;
     const T *F = front + fr_off[s];
-    if (lane >= k && lane < r) g[lane] = xp[sn_rows[sn_rptr[s] + lane]];
-    __syncthreads();
-    if (lane < k) {
-        double acc = xp[f + lane] / (double)F[(int64_t)lane * r + lane];
-        for (int32_t i = k; i < r; ++i) acc -= (double)F[(int64_t)lane * r + i] * g[i];
-        v[lane] = acc;
+    const bool upd = lane >= k && lane < r;
+    const double gi = upd ? xp[sn_rows[sn_rptr[s] + lane]] : 0.0;
+    for (int32_t c = 0; c < k; ++c) {
+        const T lv = F[(int64_t)c * r + (upd ? lane : c)];
+        double p = upd ? (double)lv * gi : 0.0;
+        for (int off = 32; off > 0; off >>= 1) p += __shfl_xor(p, off);
+        if (l64 == 0) part[w][c] = p;
     }
+    __syncthreads();
+    if (lane < k) v[lane] = xp[f + lane] / (double)F[(int64_t)lane * r + lane] - (part[0][lane] + part[1][lane]);
     __syncthreads();
     for (int32_t i = k - 1; i >= 0; --i) {
         const double xi = v[i];
-        if (lane < i) v[lane] -= (double)F[(int64_t)lane * r + i] * xi;
+        const bool act = lane < i;
+        const T l = F[(int64_t)(act ? lane : i) * r + i];
+        if (act) v[lane] -= (double)l * xi;
         __syncthreads();
     }
     if (lane < k) xp[f + lane] = v[lane];
@@ -247,20 +270,20 @@ static int solve_perm(qg_handle *h, const T *front, const T *sinv, const T *wbuf
     Device &d = h->d;
     double *xp = d.xp.p;
     for (int32_t L = 0; L < pl.nlevels; ++L) {
-        const int64_t t0 = pl.task_ptr[L], nt = pl.task_ptr[L + 1] - t0;
-        if (nt > 0)
-            fwd_gather_level<<<(unsigned)((nt + 256 / RL - 1) / (256 / RL)), 256, 0, h->stream>>>(
-                t0, nt, d.task_sn.p, d.task_col.p, d.sn_first.p, d.ctb_ptr.p, d.ctb_src.p, xp, d.vwork.p);
         const int32_t s0 = pl.lvl_small_ptr[L], s1 = pl.lvl_small_ptr[L + 1];
         if (s1 > s0)
             fwd_small<T><<<s1 - s0, SMALL_R, 0, h->stream>>>(d.lvl_small_sn.p + s0, d.sn_first.p, d.sn_rptr.p,
-                                                               d.fr_off.p, front, d.task0.p, d.vwork.p, xp);
+                                                               d.fr_off.p, front, d.task0.p, d.ctb_ptr.p,
+                                                               d.ctb_src.p, d.vwork.p, xp);
         for (int32_t u = pl.lvl_large_ptr[L]; u < pl.lvl_large_ptr[L + 1]; ++u) {
             const int32_t s = pl.lvl_large_sn[u];
             const int32_t r = (int32_t)(pl.sn_rptr[s + 1] - pl.sn_rptr[s]);
             const int32_t k = pl.sn_first[s + 1] - pl.sn_first[s];
             const T *F = front + pl.fr_off[s];
             double *vs = d.vwork.p + pl.task0[s];
+            // gather of this front's rows (its tasks are contiguous)
+            fwd_gather_level<<<(unsigned)((r + 256 / RL - 1) / (256 / RL)), 256, 0, h->stream>>>(
+                pl.task0[s], r, d.task_sn.p, d.task_col.p, d.sn_first.p, d.ctb_ptr.p, d.ctb_src.p, xp, d.vwork.p);
             for (int32_t J0 = 0; J0 < k; J0 += SB) {
                 const int32_t kb = std::min(SB, k - J0);
                 const int32_t ld = (kb + NB - 1) / NB * NB;

@@ -186,25 +186,17 @@ __device__ inline typename Acc4<T>::type tile16(FA a, FB b) {
 // run as 16 x 16 MFMA tiles, one tile per wavefront.  The inverse of the
 // whole unit lower factor is assembled from the 16 x 16 inverses at the end,
 // X_pq = -X_pp sum_{m=q}^{p-1} L_pm X_mq, also on MFMA tiles.
-// LDS of the diagonal-block factorization.
 template <typename T>
-struct DiagSmem {
-    T S[NB * (NB + 1)];                  // S[c * LD + i]: block, becomes L (strictly lower) and D (diagonal)
-    T X[NB * (NB + 1)];                  // inverse of the unit lower factor
-    T Tm[3][16 * 16];                    // partial sums of off-diagonal inverse blocks, one per wavefront
-    T Dd[NB];
-    double sgn[NB];
-};
-
-template <typename T>
-__device__ inline void diag_block_body(T *__restrict__ F, int32_t r, int32_t j0, int32_t b,
-                                       const int8_t *__restrict__ kind_cols, double eps, double dyn,
-                                       int32_t *nreg, T *__restrict__ Xg, DiagSmem<T> &sm) {
+__global__ void __launch_bounds__(256) diag_block(T *__restrict__ F, int32_t r, int32_t j0, int32_t b,
+                                                  const int8_t *__restrict__ kind_cols, double eps,
+                                                  double dyn, int32_t *nreg, T *__restrict__ Xg) {
     constexpr int LD = NB + 1;           // padded leading dimension of the LDS tiles
     constexpr int PB = 16;               // sub-block width
-    T *S = sm.S, *X = sm.X, *Dd = sm.Dd;
-    T (*Tm)[PB * PB] = sm.Tm;
-    double *sgn = sm.sgn;
+    __shared__ T S[NB * LD];             // S[c * LD + i]: block, becomes L (strictly lower) and D (diagonal)
+    __shared__ T X[NB * LD];             // inverse of the unit lower factor
+    __shared__ T Tm[3][PB * PB];         // partial sums of off-diagonal inverse blocks, one per wavefront
+    __shared__ T Dd[NB];
+    __shared__ double sgn[NB];
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     {
@@ -356,14 +348,6 @@ __device__ inline void diag_block_body(T *__restrict__ F, int32_t r, int32_t j0,
         if (i < b && c < b && i >= c) F[(int64_t)(j0 + c) * r + j0 + i] = S[c * LD + i];
         Xg[c * NB + i] = (i < b && c < b && i >= c) ? X[c * LD + i] : T(0);
     }
-}
-
-template <typename T>
-__global__ void __launch_bounds__(256) diag_block(T *__restrict__ F, int32_t r, int32_t j0, int32_t b,
-                                                  const int8_t *__restrict__ kind_cols, double eps,
-                                                  double dyn, int32_t *nreg, T *__restrict__ Xg) {
-    __shared__ DiagSmem<T> sm;
-    diag_block_body<T>(F, r, j0, b, kind_cols, eps, dyn, nreg, Xg, sm);
 }
 
 // Inverse of the unit-lower SB x SB diagonal block of a super-panel
@@ -519,31 +503,12 @@ __global__ void __launch_bounds__(256) panel_solve(T *__restrict__ F, int32_t r,
 // each; the product is formed transposed so that each lane's accumulators run
 // along a column of the column-major front.
 template <typename T>
-struct TrailSmem {
-    T As[2][32 * 64];                              // As[kk * 64 + i] = L(r0 + i, k)
-    T Bs[2][32 * 64];                              // Bs[kk * 64 + j] = L(c0 + j, k) * D(k)
-};
-template <typename T, bool FUSE>
-struct TrailLds {
-    static constexpr size_t bytes = FUSE && sizeof(DiagSmem<T>) > sizeof(TrailSmem<T>) ? sizeof(DiagSmem<T>)
-                                                                                      : sizeof(TrailSmem<T>);
-};
-
-// With FUSE, the workgroup of tile (0, 0) -- the 64 x 64 block at (r_lo, r_lo),
-// the next panel's diagonal block, complete once this update is applied --
-// goes on to factor that block (diag_block_body, b_next columns), so the
-// panel chain needs no separate launch for it.
-template <typename T, bool FUSE>
 __global__ void __launch_bounds__(256) trail_update(T *__restrict__ F, int32_t r, int32_t k0, int32_t kb,
-                                                   int32_t r_lo, int32_t c_hi, int32_t b_next,
-                                                   const int8_t *__restrict__ kinds_next, double eps, double dyn,
-                                                   int32_t *nreg, T *__restrict__ Xg_next) {
+                                                   int32_t r_lo, int32_t c_hi) {
     constexpr int KC = 32;
     constexpr int PER = KC / 4;                    // rank columns staged per thread and chunk
-    __shared__ __align__(16) unsigned char smem[TrailLds<T, FUSE>::bytes];
-    TrailSmem<T> &ts = *reinterpret_cast<TrailSmem<T> *>(smem);
-    T (*As)[KC * 64] = ts.As;
-    T (*Bs)[KC * 64] = ts.Bs;
+    __shared__ T As[2][KC * 64];                   // As[kk * 64 + i] = L(r0 + i, k)
+    __shared__ T Bs[2][KC * 64];                   // Bs[kk * 64 + j] = L(c0 + j, k) * D(k)
     const int32_t ti = blockIdx.x, tj = blockIdx.y;
     if (ti < tj) return;                           // strictly above the diagonal: nothing to do
     const int32_t r0 = r_lo + 64 * ti, c0 = r_lo + 64 * tj;
@@ -634,13 +599,6 @@ __global__ void __launch_bounds__(256) trail_update(T *__restrict__ F, int32_t r
                 const int32_t col = c0 + wc + 16 * bj + mfma_out_row<T>(lk, v);
                 if ((cok >> (8 * bi + 4 * bj + v)) & 1u) F[(int64_t)col * r + row] = cold[bi][bj][v] - acc[bi][bj][v];
             }
-    if constexpr (FUSE) {
-        if (ti == 0 && tj == 0 && b_next > 0) {
-            __syncthreads();          // every wavefront's part of the block is stored; the LDS is free again
-            diag_block_body<T>(F, r, r_lo, b_next, kinds_next, eps, dyn, nreg, Xg_next,
-                               *reinterpret_cast<DiagSmem<T> *>(smem));
-        }
-    }
 }
 
 // W_J = L(J1:r, J0:J1) X_J for a super-panel [J0, J1) (X_J the inverse of its
@@ -740,29 +698,14 @@ void prof_collect(qg_handle *h, int64_t *launches, double *ms, double *flops) {
     h->prof_flops[0] = h->prof_flops[1] = 0.0;
 }
 
-// Next diagonal block to factor inside an update (b_next = 0: none).
-template <typename T>
-struct NextDiag {
-    int32_t b = 0;
-    const int8_t *kinds = nullptr;
-    T *Xg = nullptr;
-};
-
 template <typename T>
 static void launch_update(qg_handle *h, hipStream_t st, T *F, int32_t r, int32_t k0, int32_t kb, int32_t r_lo,
-                          int32_t c_hi, const RegParams &rp, const NextDiag<T> &nd = NextDiag<T>()) {
+                          int32_t c_hi) {
     const int32_t TR = (r - r_lo + 63) / 64, TC = (c_hi - r_lo + 63) / 64;
     if (TR <= 0 || TC <= 0 || kb <= 0) return;
-    const dim3 grid((unsigned)TR, (unsigned)TC);
-    if (nd.b > 0) {
-        trail_update<T, true><<<grid, 256, 0, st>>>(F, r, k0, kb, r_lo, c_hi, nd.b, nd.kinds, rp.eps, rp.dyn,
-                                                   h->d.nreg.p, nd.Xg);
-        return;
-    }
-    // the plain updates (the bulk of the flops) are the ones timed in profiling mode
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (h->st.profile) prof_begin(st, &e0, &e1);
-    trail_update<T, false><<<grid, 256, 0, st>>>(F, r, k0, kb, r_lo, c_hi, 0, nullptr, 0.0, 0.0, nullptr, nullptr);
+    trail_update<T><<<dim3((unsigned)TR, (unsigned)TC), 256, 0, st>>>(F, r, k0, kb, r_lo, c_hi);
     if (h->st.profile) {
         // lower part of rows [r_lo, r) x cols [r_lo, c_hi): sum over columns of (r - col)
         const double M = (double)(r - r_lo), C = (double)(c_hi - r_lo);
@@ -794,30 +737,16 @@ static int factor_large(qg_handle *h, int32_t s, T *front, T *dinv, T *sinv, T *
     QG_HIP(h, hipEventRecord(h->ev_panel, ms));
     QG_HIP(h, hipStreamWaitEvent(h->bulk, h->ev_panel, 0));
     QG_HIP(h, hipStreamWaitEvent(h->prep, h->ev_panel, 0));
-    auto next_diag = [&](int32_t j) {        // the panel starting at column j, factored inside an update
-        NextDiag<T> nd;
-        if (j < k) {
-            nd.b = std::min(NB, k - j);
-            nd.kinds = kinds;                // indexed from the front's first column, like diag_block
-            nd.Xg = dinv + pl.dinv_off[s] + (int64_t)(j / NB) * NB * NB;
-        }
-        return nd;
-    };
-    bool diag_done = false;                  // the current panel's diagonal block is already factored
     for (int32_t J0 = 0; J0 < k; J0 += SB) {
         const int32_t J1 = std::min(k, J0 + SB);
         for (int32_t j0 = J0; j0 < J1; j0 += NB) {
             const int32_t b = std::min(NB, J1 - j0);
             T *ws = dinv + pl.dinv_off[s] + (int64_t)(j0 / NB) * NB * NB;
-            if (!diag_done) diag_block<T><<<1, 256, 0, ms>>>(F, r, j0, b, kinds, rp.eps, rp.dyn, h->d.nreg.p, ws);
-            diag_done = false;
+            diag_block<T><<<1, 256, 0, ms>>>(F, r, j0, b, kinds, rp.eps, rp.dyn, h->d.nreg.p, ws);
             const int32_t mb = r - j0 - b;
             if (mb > 0) panel_solve<T><<<(mb + 63) / 64, 256, 0, ms>>>(F, r, j0, b, ws);
-            // rest of this super-panel's columns (rank b), factoring the next panel's diagonal block
-            if (j0 + b < J1) {
-                launch_update<T>(h, ms, F, r, j0, b, j0 + b, J1, rp, next_diag(j0 + b));
-                diag_done = true;
-            }
+            // rest of this super-panel's columns (rank b)
+            if (j0 + b < J1) launch_update<T>(h, ms, F, r, j0, b, j0 + b, J1);
         }
         QG_HIP(h, hipEventRecord(h->ev_panel, ms));
         {
@@ -836,13 +765,11 @@ static int factor_large(qg_handle *h, int32_t s, T *front, T *dinv, T *sinv, T *
             // bulk: columns [J2, r), after this super-panel's panels
             if (J2 < r) {
                 QG_HIP(h, hipStreamWaitEvent(h->bulk, h->ev_panel, 0));
-                launch_update<T>(h, h->bulk, F, r, J0, J1 - J0, J2, r, rp);
+                launch_update<T>(h, h->bulk, F, r, J0, J1 - J0, J2, r);
             }
             // next super-panel's columns [J1, J2): after the previous bulk update, which also wrote them
-            // (a large update: not fused with the next diagonal block, whose registers would cut its
-            // occupancy)
             if (bulk_pending) QG_HIP(h, hipStreamWaitEvent(ms, h->ev_bulk, 0));
-            launch_update<T>(h, ms, F, r, J0, J1 - J0, J1, J2, rp);
+            launch_update<T>(h, ms, F, r, J0, J1 - J0, J1, J2);
             if (J2 < r) {
                 QG_HIP(h, hipEventRecord(h->ev_bulk, h->bulk));
                 bulk_pending = true;

@@ -243,6 +243,9 @@ def workload(name: str) -> Problem:
         "many_soc": lambda: many_soc(),
         "huber": lambda: huber(),
         "lasso_diff": lambda: lasso(50000, 20000, 0.002, seed=BASE_SEED + 5),
+        # the largest Huber instance of the same generator used in the device tests (the full one
+        # needs a ~2e5-wide dense root front: more than one GPU's memory)
+        "huber_m": lambda: huber(50000, 20000, 40, seed=BASE_SEED + 4),
         # oracle-scaled variants drawn from the same generators
         "lasso_s": lambda: lasso(2000, 1000, 0.02, seed=BASE_SEED + 12),
         "many_soc_s": lambda: many_soc(3000, 1000, 4, 1000, seed=BASE_SEED + 13),

@@ -8,6 +8,9 @@ any size and through sampled outputs the oracle computes itself.
   up-looking factorization stops after a prefix of rows) to 1e-10.
 - many_soc (n = 300000, 1e5 cones of dimension 4, N_K = 800000): residuals,
   gap, cone interiority, modes agreeing.
+- huber_m (the Huber generator at F 50000 x 20000, 40 entries per row,
+  N_K = 320000; the full 500000 x 200000 instance would need a dense root
+  front of about 2e5 columns, more than one GPU's memory): as above.
 - lasso_diff (F 50000 x 20000, N_K = 180000): adjoint gradients of
   L = 1/2 |x* - x_ref|^2 against central finite differences (h = 1e-6) on
   seeded coordinates of c, b and h, 3 per gradient (18 re-solves) to keep the
@@ -79,7 +82,7 @@ def solve_both(prob):
 
 
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("name", ["lasso", "many_soc"])
+@pytest.mark.parametrize("name", ["lasso", "many_soc", "huber_m"])
 def test_full_size_solution_properties(name):
     prob = problems.workload(name)
     out = solve_both(prob)

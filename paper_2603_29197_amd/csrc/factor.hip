@@ -450,7 +450,8 @@ __global__ void __launch_bounds__(256) sblock_inverse(const T *__restrict__ F, i
 template <typename T>
 __global__ void __launch_bounds__(256) panel_solve(T *__restrict__ F, int32_t r, int32_t j0, int32_t b,
                                                    const T *__restrict__ Xg) {
-    __shared__ T Xs[NB * NB];        // Xs[t * NB + c] = X(c, t)
+    constexpr int XP = sizeof(T) == 4 ? NB + 16 : NB;   // pitch: MFMA operand rows on disjoint banks
+    __shared__ T Xs[NB * XP];        // Xs[t * XP + c] = X(c, t)
     __shared__ T As[NB * (NB + 1)];  // As[t * (NB + 1) + i] = A21(row0 + i, t)
     __shared__ T Ds[NB];
     const int tid = threadIdx.x;
@@ -467,7 +468,7 @@ __global__ void __launch_bounds__(256) panel_solve(T *__restrict__ F, int32_t r,
 #pragma unroll
         for (int u = 0; u < NB * NB / 256; ++u) {
             const int32_t idx = tid + 256 * u, i = idx & 63, t = idx >> 6;
-            Xs[idx] = xv[u];
+            Xs[t * XP + i] = xv[u];
             As[t * (NB + 1) + i] = av[u];
         }
     }
@@ -479,7 +480,7 @@ __global__ void __launch_bounds__(256) panel_solve(T *__restrict__ F, int32_t r,
     for (int bi = 0; bi < 4; ++bi) acc[bi] = V{0, 0, 0, 0};
 #pragma unroll 4
     for (int k0 = 0; k0 < NB; k0 += 4) {
-        const T a = Xs[(k0 + lk) * NB + 16 * wave + lr];                  // X(c, t): c = 16 w + lr, t = k0 + lk
+        const T a = Xs[(k0 + lk) * XP + 16 * wave + lr];                  // X(c, t): c = 16 w + lr, t = k0 + lk
 #pragma unroll
         for (int bi = 0; bi < 4; ++bi) acc[bi] = mfma16x16x4(a, As[(k0 + lk) * (NB + 1) + 16 * bi + lr], acc[bi]);
     }
@@ -507,8 +508,11 @@ __global__ void __launch_bounds__(256) trail_update(T *__restrict__ F, int32_t r
                                                    int32_t r_lo, int32_t c_hi) {
     constexpr int KC = 32;
     constexpr int PER = KC / 4;                    // rank columns staged per thread and chunk
-    __shared__ T As[2][KC * 64];                   // As[kk * 64 + i] = L(r0 + i, k)
-    __shared__ T Bs[2][KC * 64];                   // Bs[kk * 64 + j] = L(c0 + j, k) * D(k)
+    // row pitch of the LDS tiles: the four 16-lane groups of an MFMA operand read rows kk .. kk+3;
+    // for 4-byte entries a pitch of 80 puts them on disjoint banks
+    constexpr int LDT = sizeof(T) == 4 ? 80 : 64;
+    __shared__ T As[2][KC * LDT];                  // As[kk * LDT + i] = L(r0 + i, k)
+    __shared__ T Bs[2][KC * LDT];                  // Bs[kk * LDT + j] = L(c0 + j, k) * D(k)
     const int32_t ti = blockIdx.x, tj = blockIdx.y;
     if (ti < tj) return;                           // strictly above the diagonal: nothing to do
     const int32_t r0 = r_lo + 64 * ti, c0 = r_lo + 64 * tj;
@@ -556,8 +560,8 @@ __global__ void __launch_bounds__(256) trail_update(T *__restrict__ F, int32_t r
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
             const int32_t kk = (tid >> 6) + 4 * u;
-            As[buf][kk * 64 + i] = ((va >> u) & 1u) ? ra[u] : T(0);
-            Bs[buf][kk * 64 + i] = ((vb >> u) & 1u) ? rb[u] * rd[u] : T(0);
+            As[buf][kk * LDT + i] = ((va >> u) & 1u) ? ra[u] : T(0);
+            Bs[buf][kk * LDT + i] = ((vb >> u) & 1u) ? rb[u] * rd[u] : T(0);
         }
     };
     V acc[2][2];
@@ -577,9 +581,9 @@ __global__ void __launch_bounds__(256) trail_update(T *__restrict__ F, int32_t r
             const int32_t kq = kk + lk;
             T a_op[2], b_op[2];
 #pragma unroll
-            for (int bj = 0; bj < 2; ++bj) a_op[bj] = Bs[buf][kq * 64 + wc + 16 * bj + lr];
+            for (int bj = 0; bj < 2; ++bj) a_op[bj] = Bs[buf][kq * LDT + wc + 16 * bj + lr];
 #pragma unroll
-            for (int bi = 0; bi < 2; ++bi) b_op[bi] = As[buf][kq * 64 + wr + 16 * bi + lr];
+            for (int bi = 0; bi < 2; ++bi) b_op[bi] = As[buf][kq * LDT + wr + 16 * bi + lr];
 #pragma unroll
             for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
@@ -613,7 +617,8 @@ template <typename T>
 __global__ void __launch_bounds__(256) wblock(const T *__restrict__ F, int32_t r, int32_t J0, int32_t kb,
                                              const T *__restrict__ Xs, int32_t ld, T *__restrict__ W) {
     constexpr int KC = 32, PER = KC * 64 / 256;
-    __shared__ T As[KC * 64];          // As[kk * 64 + i] = L(J1 + 64 ti + i, J0 + kc + kk)
+    constexpr int AP = sizeof(T) == 4 ? 80 : 64;   // pitch: MFMA operand rows on disjoint banks
+    __shared__ T As[KC * AP];          // As[kk * AP + i] = L(J1 + 64 ti + i, J0 + kc + kk)
     __shared__ T Bs[KC * 65];          // Bs[kk * 65 + j] = X(kc + kk, 64 tc + j)
     const int32_t J1 = J0 + kb, m = r - J1;
     const int32_t ti = blockIdx.x, tc = blockIdx.y;
@@ -641,7 +646,7 @@ __global__ void __launch_bounds__(256) wblock(const T *__restrict__ F, int32_t r
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
             const int e = tid + 256 * u;
-            As[(e >> 6) * 64 + (e & 63)] = av[u];
+            As[(e >> 6) * AP + (e & 63)] = av[u];
             Bs[(e & (KC - 1)) * 65 + e / KC] = bv[u];
         }
         __syncthreads();
@@ -652,7 +657,7 @@ __global__ void __launch_bounds__(256) wblock(const T *__restrict__ F, int32_t r
 #pragma unroll
             for (int bj = 0; bj < 2; ++bj) a_op[bj] = Bs[kq * 65 + wc + 16 * bj + lr];
 #pragma unroll
-            for (int bi = 0; bi < 2; ++bi) b_op[bi] = As[kq * 64 + wr + 16 * bi + lr];
+            for (int bi = 0; bi < 2; ++bi) b_op[bi] = As[kq * AP + wr + 16 * bi + lr];
 #pragma unroll
             for (int bi = 0; bi < 2; ++bi)
 #pragma unroll

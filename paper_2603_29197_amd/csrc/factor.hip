@@ -496,7 +496,7 @@ __global__ void __launch_bounds__(256) panel_solve(T *__restrict__ F, int32_t r,
 
 // C -= L(:, k0:k0+kb) D L(cols, k0:k0+kb)' on the lower part (row >= col) of
 // rows [r_lo, r) x cols [r_lo, c_hi) of the front F (ld r), 64 x 64 tiles,
-// grid (row tile, col tile).  The rank kb is consumed in chunks of KC columns
+// 1-D grid (see the XCD mapping below).  The rank kb is consumed in chunks of KC columns
 // through double-buffered LDS: the global loads of the next chunk are issued
 // before the MFMAs of the current one and are only waited for at the LDS
 // store, and the old C values are loaded at the start, so both arrive while
@@ -513,8 +513,13 @@ __global__ void __launch_bounds__(256) trail_update(T *__restrict__ F, int32_t r
     constexpr int LDT = sizeof(T) == 4 ? 80 : 64;
     __shared__ T As[2][KC * LDT];                  // As[kk * LDT + i] = L(r0 + i, k)
     __shared__ T Bs[2][KC * LDT];                  // Bs[kk * LDT + j] = L(c0 + j, k) * D(k)
-    const int32_t ti = blockIdx.x, tj = blockIdx.y;
-    if (ti < tj) return;                           // strictly above the diagonal: nothing to do
+    // Workgroup IDs are dealt to the 8 XCDs in turn; XCD x takes the tile rows ti = x (mod 8)
+    // and walks them column tile by column tile, so its concurrent workgroups share the column
+    // panel and keep their row panels in that XCD's L2.
+    const int32_t TR = (r - r_lo + 63) / 64, TC = (c_hi - r_lo + 63) / 64, NR = (TR + 7) / 8;
+    const int32_t xcd = blockIdx.x % 8, sq = blockIdx.x / 8;
+    const int32_t tj = sq / NR, ti = (sq % NR) * 8 + xcd;
+    if (ti >= TR || tj >= TC || ti < tj) return;   // outside the grid or strictly above the diagonal
     const int32_t r0 = r_lo + 64 * ti, c0 = r_lo + 64 * tj;
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
@@ -710,7 +715,7 @@ static void launch_update(qg_handle *h, hipStream_t st, T *F, int32_t r, int32_t
     if (TR <= 0 || TC <= 0 || kb <= 0) return;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (h->st.profile) prof_begin(st, &e0, &e1);
-    trail_update<T><<<dim3((unsigned)TR, (unsigned)TC), 256, 0, st>>>(F, r, k0, kb, r_lo, c_hi);
+    trail_update<T><<<(unsigned)(8 * TC * ((TR + 7) / 8)), 256, 0, st>>>(F, r, k0, kb, r_lo, c_hi);
     if (h->st.profile) {
         // lower part of rows [r_lo, r) x cols [r_lo, c_hi): sum over columns of (r - col)
         const double M = (double)(r - r_lo), C = (double)(c_hi - r_lo);

@@ -31,6 +31,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Newton-step ms (factor+solve) & solve s to 1e-8 gap: FP32+IR vs FP64, 1 MI355X"
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
+# HBM bytes per launch of trail_update on this workload, from rocprofv3 FETCH_SIZE and WRITE_SIZE
+# runs (profiles/trail_update_lasso.md), each scaled by what the counter reads for a plain device
+# copy of known size (FETCH_SIZE x 1.9998, WRITE_SIZE x 1.0). Counters describe one build of the
+# kernel: reset to None when trail_update changes until they are taken again.
+TRAFFIC_BYTES_PER_LAUNCH = {"fp32": 4.881e7, "fp64": 1.023e8}
 WORKLOAD = "lasso F 20000x10000 density 0.005 (n=40000, p=20000, m=20000, N_K=80000)"
 
 
@@ -156,7 +161,8 @@ def main():
             achieved = flops / (ms * 1e-3) / 1e12
             roof = {"kernel": "trail_update<float> (MFMA f32 16x16x4 trailing update of large fronts)",
                     "bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_TFLOPS["fp32"],
-                    "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS["fp32"], 4), "traffic": None,
+                    "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS["fp32"], 4),
+                    "traffic": TRAFFIC_BYTES_PER_LAUNCH["fp32"],
                     "launches": int(launches), "avg_launch_us": round(1e3 * ms / launches, 2),
                     "flops_per_launch_avg": flops / launches}
             l64, ms64, fl64 = pinfo["kern_launches"][0], pinfo["kern_ms"][0], pinfo["kern_flops"][0]
@@ -164,6 +170,7 @@ def main():
                 a64 = fl64 / (ms64 * 1e-3) / 1e12
                 roof["fp64_kernel"] = {"kernel": "trail_update<double>", "achieved": round(a64, 2),
                                        "peak": PEAK_TFLOPS["fp64"], "frac": round(a64 / PEAK_TFLOPS["fp64"], 4),
+                                       "traffic": TRAFFIC_BYTES_PER_LAUNCH["fp64"],
                                        "launches": int(l64), "avg_launch_us": round(1e3 * ms64 / l64, 2)}
     cpu = None
     if not args.no_cpu_baseline:

@@ -190,6 +190,9 @@ template <typename T>
 __global__ void __launch_bounds__(256) diag_block(T *__restrict__ F, int32_t r, int32_t j0, int32_t b,
                                                   const int8_t *__restrict__ kind_cols, double eps,
                                                   double dyn, int32_t *nreg, T *__restrict__ Xg) {
+    // the panel chain is the critical path of a large front: its waves win issue
+    // arbitration against the concurrent bulk update on a shared compute unit
+    __builtin_amdgcn_s_setprio(3);
     constexpr int LD = NB + 1;           // padded leading dimension of the LDS tiles
     constexpr int PB = 16;               // sub-block width
     __shared__ T S[NB * LD];             // S[c * LD + i]: block, becomes L (strictly lower) and D (diagonal)
@@ -450,6 +453,7 @@ __global__ void __launch_bounds__(256) sblock_inverse(const T *__restrict__ F, i
 template <typename T>
 __global__ void __launch_bounds__(256) panel_solve(T *__restrict__ F, int32_t r, int32_t j0, int32_t b,
                                                    const T *__restrict__ Xg) {
+    __builtin_amdgcn_s_setprio(3);                      // panel chain: see diag_block
     constexpr int XP = sizeof(T) == 4 ? NB + 16 : NB;   // pitch: MFMA operand rows on disjoint banks
     __shared__ T Xs[NB * XP];        // Xs[t * XP + c] = X(c, t)
     __shared__ T As[NB * (NB + 1)];  // As[t * (NB + 1) + i] = A21(row0 + i, t)
@@ -505,7 +509,7 @@ __global__ void __launch_bounds__(256) panel_solve(T *__restrict__ F, int32_t r,
 // along a column of the column-major front.
 template <typename T>
 __global__ void __launch_bounds__(256) trail_update(T *__restrict__ F, int32_t r, int32_t k0, int32_t kb,
-                                                   int32_t r_lo, int32_t c_hi) {
+                                                   int32_t r_lo, int32_t c_hi, int32_t urgent) {
     constexpr int KC = 32;
     constexpr int PER = KC / 4;                    // rank columns staged per thread and chunk
     // row pitch of the LDS tiles: the four 16-lane groups of an MFMA operand read rows kk .. kk+3;
@@ -520,6 +524,7 @@ __global__ void __launch_bounds__(256) trail_update(T *__restrict__ F, int32_t r
     const int32_t xcd = blockIdx.x % 8, sq = blockIdx.x / 8;
     const int32_t tj = sq / NR, ti = (sq % NR) * 8 + xcd;
     if (ti >= TR || tj >= TC || ti < tj) return;   // outside the grid or strictly above the diagonal
+    if (urgent) __builtin_amdgcn_s_setprio(2);     // on the panel chain: ahead of the bulk update's waves
     const int32_t r0 = r_lo + 64 * ti, c0 = r_lo + 64 * tj;
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
@@ -715,7 +720,8 @@ static void launch_update(qg_handle *h, hipStream_t st, T *F, int32_t r, int32_t
     if (TR <= 0 || TC <= 0 || kb <= 0) return;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (h->st.profile) prof_begin(st, &e0, &e1);
-    trail_update<T><<<(unsigned)(8 * TC * ((TR + 7) / 8)), 256, 0, st>>>(F, r, k0, kb, r_lo, c_hi);
+    trail_update<T><<<(unsigned)(8 * TC * ((TR + 7) / 8)), 256, 0, st>>>(F, r, k0, kb, r_lo, c_hi,
+                                                                         st == h->stream ? 1 : 0);
     if (h->st.profile) {
         // lower part of rows [r_lo, r) x cols [r_lo, c_hi): sum over columns of (r - col)
         const double M = (double)(r - r_lo), C = (double)(c_hi - r_lo);

@@ -223,44 +223,61 @@ __global__ void __launch_bounds__(256) bwd_init(int32_t s, const int32_t *__rest
 // Backward step of super-block [K0, K0+kb): x_K = u_K is final (every later
 // block has pushed onto it); workgroup 0 writes it to the solution, and every
 // workgroup pushes it onto 64 earlier entries: u[c] -= sum_t W_J(K0 - J1 + t,
-// c - J0) x_K(t) for the block J = [J0, J1) that holds c.  Lanes run along the
-// contiguous rows of each W column (coalesced), all loads of a wavefront are
-// issued before its 16 shuffle reductions, and lanes 0..15 then update the 16
-// entries at once.
+// c - J0) x_K(t) for the block J = [J0, J1) that holds c.  Wavefront w takes
+// 16 columns; lanes run along the contiguous rows of each W column
+// (coalesced), and the 64 loads of W and the 4 of x_K of a lane are issued
+// together.  The 16 x 64 partial sums of a wavefront are transposed through
+// LDS: lane l adds 16 of column l / 4's partials, then two butterfly steps
+// combine the four lanes of each column.  No workgroup barrier.
 template <typename T>
 __global__ void __launch_bounds__(256) bwd_push(const T *__restrict__ W_s, int32_t r, int32_t K0, int32_t kb,
                                                 double *__restrict__ u, double *__restrict__ xp_own) {
-    __shared__ double xs[SB];
+    __shared__ double red[4][16][65];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    if (tid < kb) xs[tid] = u[K0 + tid];
-    __syncthreads();
-    if (blockIdx.x == 0 && tid < kb) xp_own[K0 + tid] = xs[tid];
+    const bool pushes = blockIdx.x * NB < K0;        // uniform over the workgroup
     const int32_t c0 = blockIdx.x * NB + w * 16;
-    if (blockIdx.x * NB >= K0) return;
-    const int32_t J0 = (blockIdx.x * NB) / SB * SB, J1 = J0 + SB;   // a full block: J1 <= K0
-    const int64_t m = r - J1;
-    const T *Wj = W_s + w_block_offset(r, J0) + (K0 - J1);
-    double part[16];
+    // raw loads from always-valid addresses (zeroing at the use, so that all are in flight at once)
+    T wv[16][SB / 64];
+    if (pushes) {
+        const int32_t J0 = (blockIdx.x * NB) / SB * SB, J1 = J0 + SB;   // a full block: J1 <= K0
+        const int64_t m = r - J1;
+        const T *Wj = W_s + w_block_offset(r, J0) + (K0 - J1);
+#pragma unroll
+        for (int cc = 0; cc < 16; ++cc)
+#pragma unroll
+            for (int q = 0; q < SB / 64; ++q) {
+                const int32_t t = lane + 64 * q;
+                wv[cc][q] = Wj[c0 + cc < K0 && t < kb ? (int64_t)(c0 + cc - J0) * m + t : 0];
+            }
+    }
+    double xk[SB / 64];
+#pragma unroll
+    for (int q = 0; q < SB / 64; ++q) xk[q] = u[K0 + (lane + 64 * q < kb ? lane + 64 * q : 0)];
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int q = 0; q < SB / 64; ++q) xk[q] = lane + 64 * q < kb ? xk[q] : 0.0;
+    if (blockIdx.x == 0 && w == 0) {
+#pragma unroll
+        for (int q = 0; q < SB / 64; ++q)
+            if (lane + 64 * q < kb) xp_own[K0 + lane + 64 * q] = xk[q];
+    }
+    if (!pushes) return;
 #pragma unroll
     for (int cc = 0; cc < 16; ++cc) {
-        const int32_t c = c0 + cc;
         double s = 0.0;
 #pragma unroll
-        for (int q = 0; q < SB / 64; ++q) {
-            const int32_t t = lane + 64 * q;
-            const bool ok = c < K0 && t < kb;
-            s += (double)ld_or0(Wj, (int64_t)(c - J0) * m + t, ok) * xs[ok ? t : 0];
-        }
-        part[cc] = s;
+        for (int q = 0; q < SB / 64; ++q)
+            s += (double)(c0 + cc < K0 && lane + 64 * q < kb ? wv[cc][q] : T(0)) * xk[q];
+        red[w][cc][lane] = s;
     }
-    double mine = 0.0;
+    __builtin_amdgcn_wave_barrier();                 // LDS operations of one wavefront complete in order
+    const int cc = lane >> 2, qq = lane & 3;
+    double s = 0.0;
 #pragma unroll
-    for (int cc = 0; cc < 16; ++cc) {
-        double s = part[cc];
-        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-        mine = lane == cc ? s : mine;
-    }
-    if (lane < 16 && c0 + lane < K0) u[c0 + lane] -= mine;
+    for (int e = 0; e < 16; ++e) s += red[w][cc][16 * qq + e];
+    s += __shfl_xor(s, 1);
+    s += __shfl_xor(s, 2);
+    if (qq == 0 && c0 + cc < K0) u[c0 + cc] -= s;
 }
 
 // ------------------------------- driver ------------------------------------

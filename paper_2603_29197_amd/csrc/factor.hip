@@ -153,7 +153,7 @@ __global__ void __launch_bounds__(256) factor_small(
 __device__ inline float recip(float d) { return __builtin_amdgcn_rcpf(d); }
 __device__ inline double recip(double d) { return 1.0 / d; }
 
-// Value of lane `src` (a compile-time constant) of v, for every lane.
+// Value of lane `src` (uniform over the wavefront) of v, for every lane.
 __device__ inline float lane_bcast(float v, int src) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
 }
@@ -179,13 +179,16 @@ __device__ inline typename Acc4<T>::type tile16(FA a, FB b) {
 // LDL' of the b x b diagonal block at (j0, j0) of the front F (ld r), in
 // place; the inverse of its unit lower factor goes to Xg (ld NB, zeros above
 // the diagonal).  The block is staged in LDS and factored 16 columns at a
-// time: wavefront 0 factors the 16 x 16 diagonal sub-block in registers
-// (lane i holds row i; pivot columns are read with lane broadcasts, so a
-// pivot step has no barrier) and inverts its unit lower factor; then the L
-// rows below it (A X' D^-1) and its rank-16 update of the rest of the block
-// run as 16 x 16 MFMA tiles, one tile per wavefront.  The inverse of the
-// whole unit lower factor is assembled from the 16 x 16 inverses at the end,
-// X_pq = -X_pp sum_{m=q}^{p-1} L_pm X_mq, also on MFMA tiles.
+// time.  Wavefront 0 holds the rows of the block from the sub-block down in
+// registers (lane i holds row i) and runs the 16 pivot steps on them, reading
+// each pivot column with lane broadcasts, so a pivot step has no barrier and
+// the rows below the sub-block come out as rows of L at no extra cost.  Then
+// wavefront 3 inverts the sub-block's unit lower factor while wavefronts 0-2
+// apply its rank-16 update to the rest of the block on 16 x 16 MFMA tiles.
+// The inverse of the whole unit lower factor is assembled from the 16 x 16
+// inverses, X_pq = -X_pp sum_{m=q}^{p-1} L_pm X_mq on MFMA tiles: block row p
+// by wavefronts 1..p while wavefront 0 pivots sub-block p + 1, the last block
+// row at the end.
 template <typename T>
 __global__ void __launch_bounds__(256) diag_block(T *__restrict__ F, int32_t r, int32_t j0, int32_t b,
                                                   const int8_t *__restrict__ kind_cols, double eps,
@@ -197,7 +200,7 @@ __global__ void __launch_bounds__(256) diag_block(T *__restrict__ F, int32_t r, 
     constexpr int PB = 16;               // sub-block width
     __shared__ T S[NB * LD];             // S[c * LD + i]: block, becomes L (strictly lower) and D (diagonal)
     __shared__ T X[NB * LD];             // inverse of the unit lower factor
-    __shared__ T Tm[3][PB * PB];         // partial sums of off-diagonal inverse blocks, one per wavefront
+    __shared__ T Tm[4][PB * PB];         // partial sums of off-diagonal inverse blocks, one per wavefront
     __shared__ T Dd[NB];
     __shared__ double sgn[NB];
     const int tid = threadIdx.x;
@@ -220,15 +223,41 @@ __global__ void __launch_bounds__(256) diag_block(T *__restrict__ F, int32_t r, 
     __syncthreads();
     int events = 0;
     const int lr = lane & 15, lk = lane >> 4;
+    // off-diagonal block X_pq (p > q) of the inverse, by the calling wavefront:
+    // X_pq = -X_pp sum_{m=q}^{p-1} L_pm X_mq (block row p's diagonal block and the
+    // block rows above it are complete)
+    auto x_block = [&](int p, int q) {
+        const int n = PB * p, q0 = PB * q;
+        typename Acc4<T>::type tacc = {0, 0, 0, 0};
+        for (int m0 = q0; m0 < n; m0 += PB) {
+            auto acc = tile16<T>([&](int i, int k) { return S[(m0 + k) * LD + n + i]; },
+                                 [&](int k, int j) { return X[(q0 + j) * LD + m0 + k]; });
+#pragma unroll
+            for (int v = 0; v < 4; ++v) tacc[v] += acc[v];
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Tm[wave][lr * PB + mfma_out_row<T>(lk, v)] = tacc[v];   // T(row, col) at col * 16 + row
+        __builtin_amdgcn_wave_barrier();
+        auto acc = tile16<T>([&](int i, int k) { return X[(n + k) * LD + n + i]; },
+                             [&](int k, int j) { return Tm[wave][j * PB + k]; });
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = n + mfma_out_row<T>(lk, v), j = q0 + lr;
+            if (i < b && j < b) X[j * LD + i] = -acc[v];
+        }
+    };
     for (int p0 = 0; p0 < b; p0 += PB) {
         const int pb = min(PB, b - p0);
+        const int ps = p0 / PB;
         if (wave == 0) {
-            // rows p0 + lr of the sub-block (lanes 16..63 mirror lanes 0..15 and write nothing)
+            // lane i: row i, entries in the sub-block's columns p0 .. p0 + 15 (lower part only)
+            const int i = lane;
+            const bool row_ok = i >= p0 && i < b;
             T a[PB];
 #pragma unroll
             for (int m = 0; m < PB; ++m) {
-                const T v = S[(p0 + m) * LD + p0 + lr];
-                a[m] = (lr < pb && m < pb && m <= lr) ? v : T(0);
+                const T v = S[(p0 + m) * LD + i];
+                a[m] = (row_ok && m < pb && i >= p0 + m) ? v : T(0);
             }
             T dmine = T(0);
             double sgv[PB];                            // pivot signs, read before the pivot chain
@@ -237,66 +266,58 @@ __global__ void __launch_bounds__(256) diag_block(T *__restrict__ F, int32_t r, 
 #pragma unroll
             for (int j = 0; j < PB; ++j) {
                 if (j < pb) {
-                    const T raw = lane_bcast(a[j], j);
+                    const int c = p0 + j;
+                    const T raw = lane_bcast(a[j], c);
                     const double sg = sgv[j];
                     const bool fix = !(sg * (double)raw > eps);
                     const T d = fix ? (T)(sg * dyn) : raw;
                     events += fix ? 1 : 0;
                     const T inv = recip(d);
-                    const T l = lr > j ? a[j] * inv : T(0);
+                    const T l = i > c ? a[j] * inv : T(0);
+                    // A(i, p0 + k) -= L(i, c) A(p0 + k, c); entries above the diagonal are never read
 #pragma unroll
-                    for (int k = j + 1; k < PB; ++k) a[k] -= l * lane_bcast(a[j], k);
-                    a[j] = lr > j ? l : (lr == j ? d : a[j]);
-                    dmine = lr == j ? d : dmine;
+                    for (int k = j + 1; k < PB; ++k) a[k] -= l * lane_bcast(a[j], p0 + k);
+                    a[j] = i > c ? l : (i == c ? d : a[j]);
+                    dmine = i == c ? d : dmine;
                 }
             }
-            if (lane < pb) {
+            if (row_ok) {
+                // columns beyond pb (a partial last sub-block) hold values that are never read
 #pragma unroll
-                for (int m = 0; m < PB; ++m)
-                    if (m <= lane) S[(p0 + m) * LD + p0 + lane] = a[m];
-                Dd[p0 + lane] = dmine;
+                for (int m = 0; m < PB; ++m) S[(p0 + m) * LD + i] = i >= p0 + m ? a[m] : T(0);
+                if (i < p0 + pb) Dd[i] = dmine;
             }
-            __builtin_amdgcn_wave_barrier();
-            // inverse of the unit lower sub-block: lane c forms column c, reading the
-            // columns of L back from LDS (broadcast reads; LDS operations of one
-            // wavefront complete in order)
+        } else if (wave < ps) {
+            // meanwhile: block row ps - 1 of the inverse (its diagonal block is done)
+            x_block(ps - 1, wave - 1);
+        }
+        __syncthreads();
+        const int i0 = p0 + pb, nb = b - i0;
+        if (wave == 3) {
+            // inverse of the unit lower sub-block: lane c forms column c by forward
+            // substitution; the 120 entries of L it needs are read from LDS up front
+            // (broadcast reads, all in flight), so the substitution is a register chain
+            T lc[PB][PB];
+#pragma unroll
+            for (int m = 0; m < PB; ++m)
+#pragma unroll
+                for (int k = m + 1; k < PB; ++k) lc[m][k] = S[(p0 + m) * LD + p0 + k];
             T x[PB];
 #pragma unroll
             for (int k = 0; k < PB; ++k) x[k] = (k == lr) ? T(1) : T(0);
 #pragma unroll
-            for (int m = 0; m < PB; ++m) {
-                T lc[PB];
+            for (int m = 0; m < PB; ++m)
 #pragma unroll
-                for (int k = m + 1; k < PB; ++k) lc[k] = S[(p0 + m) * LD + p0 + k];
-#pragma unroll
-                for (int k = m + 1; k < PB; ++k) x[k] -= ((k < pb && m < pb) ? lc[k] : T(0)) * x[m];
-            }
+                for (int k = m + 1; k < PB; ++k) x[k] -= ((k < pb && m < pb) ? lc[m][k] : T(0)) * x[m];
             if (lane < pb) {
 #pragma unroll
                 for (int k = 0; k < PB; ++k)
                     if (k < pb && k >= lane) X[(p0 + lane) * LD + p0 + k] = x[k];
             }
-        }
-        __syncthreads();
-        const int i0 = p0 + pb, nb = b - i0;
-        if (nb > 0) {
-            const int nt = (nb + 15) / 16;
-            // L rows below: L(i, p0+m) = sum_q A(i, p0+q) X_pp(m, q) / D(p0+m), one row tile per wavefront
-            if (wave < nt) {
-                const int rb = i0 + 16 * wave;
-                auto acc = tile16<T>(
-                    [&](int i, int k) { return k < pb ? S[(p0 + k) * LD + rb + i] : T(0); },
-                    [&](int k, int j) { return k < pb ? X[(p0 + k) * LD + p0 + j] : T(0); });
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int m = lr, i = rb + mfma_out_row<T>(lk, v);
-                    // result tile row = row of L, column = m; written after all reads of this wave
-                    if (i < b && m < pb) S[(p0 + m) * LD + i] = acc[v] / Dd[p0 + m];
-                }
-            }
-            __syncthreads();
+        } else if (nb > 0) {
             // rank-pb update of the rest of the block: tiles (ti, tj), ti >= tj
-            for (int tt = wave; tt < nt * (nt + 1) / 2; tt += 4) {
+            const int nt = (nb + 15) / 16;
+            for (int tt = wave; tt < nt * (nt + 1) / 2; tt += 3) {
                 int ti = 0;
                 while ((ti + 1) * (ti + 2) / 2 <= tt) ++ti;
                 const int tj = tt - ti * (ti + 1) / 2;
@@ -310,40 +331,13 @@ __global__ void __launch_bounds__(256) diag_block(T *__restrict__ F, int32_t r, 
                     if (i < b && j < b && i >= j) S[j * LD + i] -= acc[v];
                 }
             }
-            __syncthreads();
-        }
-    }
-    // off-diagonal blocks of the inverse, block row by block row (wavefront q
-    // forms X_pq)
-    const int nsub = (b + PB - 1) / PB;
-    for (int p = 1; p < nsub; ++p) {
-        const int n = PB * p;
-        if (wave < p) {
-            const int q0 = PB * wave;
-            // T = sum_{m = q}^{p-1} L_pm X_mq
-            typename Acc4<T>::type tacc = {0, 0, 0, 0};
-            for (int m0 = q0; m0 < n; m0 += PB) {
-                auto acc = tile16<T>(
-                    [&](int i, int k) { return S[(m0 + k) * LD + n + i]; },
-                    [&](int k, int j) { return X[(q0 + j) * LD + m0 + k]; });
-#pragma unroll
-                for (int v = 0; v < 4; ++v) tacc[v] += acc[v];
-            }
-#pragma unroll
-            for (int v = 0; v < 4; ++v) Tm[wave][lr * PB + mfma_out_row<T>(lk, v)] = tacc[v];   // T(row, col) at col * 16 + row
-            __builtin_amdgcn_wave_barrier();
-            // X_pq = -X_pp T (reads of Tm by the same wavefront)
-            auto acc = tile16<T>(
-                [&](int i, int k) { return X[(n + k) * LD + n + i]; },
-                [&](int k, int j) { return Tm[wave][j * PB + k]; });
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int i = n + mfma_out_row<T>(lk, v), j = q0 + lr;
-                if (i < b && j < b) X[j * LD + i] = -acc[v];
-            }
         }
         __syncthreads();
     }
+    // the last block row of the inverse (the earlier ones were formed during the pivot phases)
+    const int last = (b + PB - 1) / PB - 1;
+    if (wave < last) x_block(last, wave);
+    __syncthreads();
     if (tid == 0 && events) atomicAdd(nreg, events);
 #pragma unroll
     for (int u = 0; u < NB * NB / 256; ++u) {

@@ -71,22 +71,21 @@ static int allocate_device(qg_handle *h) {
     UP(sn_rows, pl.sn_rows);
     UP(task_sn, pl.task_sn);
     UP(task_col, pl.task_col);
-    UP(asm_row, pl.asm_row);
-    UP(ctb_child, pl.ctb_child);
-    UP(ctb_col, pl.ctb_col);
     UP(ctb_src, pl.ctb_src);
-    UP(rel, pl.rel);
     UP(ch_ptr, pl.ch_ptr);
     UP(ch_list, pl.ch_list);
     UP(lvl_small_sn, pl.lvl_small_sn);
     UP(sn_rptr, pl.sn_rptr);
     UP(fr_off, pl.fr_off);
     UP(task_ptr, pl.task_ptr);
-    UP(asm_ptr, pl.asm_ptr);
-    UP(asm_src, pl.asm_src);
     UP(ctb_ptr, pl.ctb_ptr);
-    UP(rel_ptr, pl.rel_ptr);
     UP(uv_off, pl.uv_off);
+    UP(ent_dst, pl.ent_dst);
+    UP(ent_sptr, pl.ent_sptr);
+    UP(ent_reg, pl.ent_reg);
+    UP(ent_src, pl.ent_src);
+    UP(zseg_off, pl.zseg_off);
+    UP(zseg_len, pl.zseg_len);
     UP(task0, pl.task0);
     UP(reg_sign, pl.reg_sign);
     std::vector<int32_t> zc((size_t)h->m, -1);

@@ -2,10 +2,10 @@
 // interior-point iteration, on the fixed pattern from the analysis.
 //
 // Multifrontal, level by level over the supernodal elimination tree:
-//  * assemble_cols: one wavefront per front column; zero the column, scatter
-//    the K entries that belong to it (+ static regularization on the
-//    diagonal), then add every child's update column that maps onto it, in
-//    child order (deterministic, no atomics);
+//  * zero_segments + gather_entries: clear the level's fronts, then form each
+//    entry that receives a value from the K entry (+ static regularization on
+//    a pivot diagonal) and every child update entry that maps onto it, in
+//    child order, one thread per entry (deterministic, no atomics);
 //  * factor_small: fronts with r <= SMALL_R, one workgroup per front in LDS:
 //    k right-looking pivot steps over the whole front, which leaves L in the
 //    first k columns and the Schur complement (update) in the trailing block;
@@ -42,43 +42,40 @@ template <> __device__ inline int mfma_out_row<float>(int lk, int v) { return 4 
 template <> __device__ inline int mfma_out_row<double>(int lk, int v) { return lk + 4 * v; }
 
 // ---------------------------------------------------------------------------
-// assembly: one 64-thread workgroup per (front, column) task
+// assembly (extend-add), one level at a time: the level's fronts are cleared,
+// then every entry that receives a value is formed by one thread from its
+// sources in a fixed order -- the K entry, the static regularization of a
+// pivot diagonal, then the children's update entries in child order -- so no
+// two threads write the same entry and the sum does not depend on scheduling.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(64) assemble_cols(
-    int64_t t0, const int32_t *__restrict__ task_sn, const int32_t *__restrict__ task_col,
-    const int32_t *__restrict__ sn_first, const int64_t *__restrict__ sn_rptr,
-    const int64_t *__restrict__ fr_off, T *__restrict__ front,
-    const int64_t *__restrict__ asm_ptr, const int64_t *__restrict__ asm_src,
-    const int32_t *__restrict__ asm_row, const double *__restrict__ kval,
-    const int8_t *__restrict__ kind, double delta,
-    const int64_t *__restrict__ ctb_ptr, const int32_t *__restrict__ ctb_child,
-    const int32_t *__restrict__ ctb_col, const int64_t *__restrict__ rel_ptr,
-    const int32_t *__restrict__ rel) {
-    const int64_t task = t0 + blockIdx.x;
-    const int lane = threadIdx.x;
-    const int32_t s = task_sn[task];
-    const int32_t j = task_col[task];
-    const int32_t r = (int32_t)(sn_rptr[s + 1] - sn_rptr[s]);
-    const int32_t k = sn_first[s + 1] - sn_first[s];
-    T *col = front + fr_off[s] + (int64_t)j * r;
-    for (int32_t i = j + lane; i < r; i += 64) col[i] = T(0);
-    __syncthreads();
-    for (int64_t t = asm_ptr[task] + lane; t < asm_ptr[task + 1]; t += 64)
-        col[asm_row[t]] = (T)kval[asm_src[t]];
-    __syncthreads();
-    if (lane == 0 && j < k) col[j] = (T)((double)col[j] + static_reg(kind[sn_first[s] + j], delta));
-    for (int64_t u = ctb_ptr[task]; u < ctb_ptr[task + 1]; ++u) {
-        __syncthreads();
-        const int32_t c = ctb_child[u];
-        const int32_t jc = ctb_col[u];
-        const int32_t rc = (int32_t)(sn_rptr[c + 1] - sn_rptr[c]);
-        const int32_t kc = sn_first[c + 1] - sn_first[c];
-        const int32_t mc = rc - kc;
-        const T *ucol = front + fr_off[c] + (int64_t)(kc + jc) * rc + kc;   // update block column jc
-        const int32_t *rl = rel + rel_ptr[c];
-        for (int32_t i = jc + lane; i < mc; i += 64) col[rl[i]] += ucol[i];
+__global__ void __launch_bounds__(256) zero_segments(const int64_t *__restrict__ off,
+                                                     const int32_t *__restrict__ len, T *__restrict__ front) {
+    const int64_t o = off[blockIdx.x];
+    const int32_t n = len[blockIdx.x];
+    for (int32_t i = threadIdx.x; i < n; i += 256) front[o + i] = T(0);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) gather_entries(int64_t e0, int64_t ne, const int64_t *__restrict__ dst,
+                                                      const int64_t *__restrict__ sptr,
+                                                      const int8_t *__restrict__ reg,
+                                                      const int64_t *__restrict__ src,
+                                                      const double *__restrict__ kval, double delta,
+                                                      T *__restrict__ front) {
+    const int64_t e = e0 + (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= e0 + ne) return;
+    int64_t u = sptr[e];
+    const int64_t u1 = sptr[e + 1];
+    T v = T(0);
+    if (u < u1) {
+        const int64_t s0 = src[u];
+        if (s0 < 0) { v = (T)kval[-s0 - 1]; ++u; }
     }
+    const int8_t kd = reg[e];
+    if (kd >= 0) v = (T)((double)v + static_reg(kd, delta));
+    for (; u < u1; ++u) v += front[src[u]];
+    front[dst[e]] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -802,12 +799,12 @@ static int factor_all(qg_handle *h, T *front, T *dinv, T *sinv, T *wb, const Reg
     const Plan &pl = h->plan;
     Device &d = h->d;
     for (int32_t L = 0; L < pl.nlevels; ++L) {
-        const int64_t t0 = pl.task_ptr[L], nt = pl.task_ptr[L + 1] - t0;
-        if (nt > 0)
-            assemble_cols<T><<<(unsigned)nt, 64, 0, h->stream>>>(
-                t0, d.task_sn.p, d.task_col.p, d.sn_first.p, d.sn_rptr.p, d.fr_off.p, front,
-                d.asm_ptr.p, d.asm_src.p, d.asm_row.p, d.kval.p, d.reg_sign.p, rp.delta, d.ctb_ptr.p,
-                d.ctb_child.p, d.ctb_col.p, d.rel_ptr.p, d.rel.p);
+        const int64_t z0 = pl.zseg_lvl_ptr[L], nz = pl.zseg_lvl_ptr[L + 1] - z0;
+        if (nz > 0) zero_segments<T><<<(unsigned)nz, 256, 0, h->stream>>>(d.zseg_off.p + z0, d.zseg_len.p + z0, front);
+        const int64_t e0 = pl.ent_lvl_ptr[L], ne = pl.ent_lvl_ptr[L + 1] - e0;
+        if (ne > 0)
+            gather_entries<T><<<(unsigned)((ne + 255) / 256), 256, 0, h->stream>>>(
+                e0, ne, d.ent_dst.p, d.ent_sptr.p, d.ent_reg.p, d.ent_src.p, d.kval.p, rp.delta, front);
         const int32_t s0 = pl.lvl_small_ptr[L], s1 = pl.lvl_small_ptr[L + 1];
         if (s1 > s0) {
             const size_t lds = (size_t)pl.lvl_small_maxr[L] * pl.lvl_small_maxr[L] * sizeof(T);

@@ -57,10 +57,12 @@ void dfree_all(qg_handle *h) {
     dfree(d.kval); dfree(d.blk33); dfree(d.blk_off); dfree(d.soc_off); dfree(d.kr_ptr);
     dfree(d.kr_col); dfree(d.kr_val); dfree(d.c); dfree(d.b); dfree(d.h); dfree(d.Pp); dfree(d.Pi);
     dfree(d.perm); dfree(d.iperm);
-    dfree(d.sn_first); dfree(d.sn_rows); dfree(d.task_sn); dfree(d.task_col); dfree(d.asm_row);
-    dfree(d.ctb_child); dfree(d.ctb_col); dfree(d.ctb_src); dfree(d.rel); dfree(d.ch_ptr); dfree(d.ch_list);
-    dfree(d.lvl_small_sn); dfree(d.sn_rptr); dfree(d.fr_off); dfree(d.task_ptr); dfree(d.asm_ptr);
-    dfree(d.asm_src); dfree(d.ctb_ptr); dfree(d.rel_ptr); dfree(d.uv_off); dfree(d.reg_sign);
+    dfree(d.sn_first); dfree(d.sn_rows); dfree(d.task_sn); dfree(d.task_col);
+    dfree(d.ctb_src); dfree(d.ch_ptr); dfree(d.ch_list);
+    dfree(d.lvl_small_sn); dfree(d.sn_rptr); dfree(d.fr_off); dfree(d.task_ptr);
+    dfree(d.ctb_ptr); dfree(d.uv_off); dfree(d.reg_sign);
+    dfree(d.ent_dst); dfree(d.ent_sptr); dfree(d.ent_src); dfree(d.ent_reg); dfree(d.zseg_off);
+    dfree(d.zseg_len);
     dfree(d.front64); dfree(d.front32); dfree(d.uvec); dfree(d.dinv64); dfree(d.dinv32);
     dfree(d.sinv64); dfree(d.sinv32); dfree(d.w64); dfree(d.w32); dfree(d.ubuf);
     dfree(d.vbuf); dfree(d.col2sn); dfree(d.nreg); dfree(d.vwork); dfree(d.task0);
@@ -159,6 +161,86 @@ int group_fronts(const Symbolic &sym, Symbolic &g) {
     g.nnz_L = sym.nnz_L;
     g.flops = sym.flops;
     return QG_OK;
+}
+
+// Assembly map of the numeric factorization (the extend-add of the paper's
+// multifrontal factorization, Sec. 2.2): per level, the front entries that
+// receive a value, each with its sources in the order the sum is formed -- the
+// entry of K, then (after the static regularization of a pivot diagonal) the
+// children's update-matrix entries in child order -- so the device forms every
+// entry independently and the result does not depend on scheduling.  Also the
+// segments of front storage cleared first (the whole front for small fronts,
+// the lower part of each column for large ones), in chunks of ZCHUNK entries.
+static bool build_assembly_map(Plan &pl, const std::vector<int64_t> &task_base, int64_t nnzK) {
+    constexpr int64_t ZCHUNK = 8192;
+    pl.ent_lvl_ptr.assign((size_t)pl.nlevels + 1, 0);
+    pl.zseg_lvl_ptr.assign((size_t)pl.nlevels + 1, 0);
+    pl.ent_dst.clear(); pl.ent_reg.clear(); pl.ent_src.clear(); pl.zseg_off.clear(); pl.zseg_len.clear();
+    pl.ent_sptr.assign(1, 0);
+    std::vector<int32_t> cnt((size_t)pl.max_r + 1, 0);
+    std::vector<int64_t> pos((size_t)pl.max_r + 1, 0);
+    std::vector<uint8_t> live((size_t)pl.max_r + 1, 0);
+    std::vector<int32_t> touched;
+    auto zseg = [&](int64_t off, int64_t len) {
+        for (int64_t c = 0; c < len; c += ZCHUNK) {
+            pl.zseg_off.push_back(off + c);
+            pl.zseg_len.push_back((int32_t)std::min(ZCHUNK, len - c));
+        }
+    };
+    for (int32_t L = 0; L < pl.nlevels; ++L) {
+        for (int32_t t = pl.lvl_ptr[L]; t < pl.lvl_ptr[L + 1]; ++t) {
+            const int32_t s = pl.lvl_sn[t];
+            const int64_t r = pl.sn_rptr[s + 1] - pl.sn_rptr[s];
+            const int32_t k = pl.sn_first[s + 1] - pl.sn_first[s];
+            if (r <= SMALL_R) zseg(pl.fr_off[s], r * r);
+            else
+                for (int64_t j = 0; j < r; ++j) zseg(pl.fr_off[s] + j * r + j, r - j);
+            for (int32_t j = 0; j < (int32_t)r; ++j) {
+                const int64_t task = task_base[s] + j;
+                touched.clear();
+                auto touch = [&](int32_t row, int n) {
+                    if (!live[row]) { live[row] = 1; touched.push_back(row); }
+                    cnt[row] += n;
+                };
+                for (int64_t a = pl.asm_ptr[task]; a < pl.asm_ptr[task + 1]; ++a) touch(pl.asm_row[a], 1);
+                if (j < k) touch(j, 0);
+                for (int64_t u = pl.ctb_ptr[task]; u < pl.ctb_ptr[task + 1]; ++u) {
+                    const int32_t c = pl.ctb_child[u], jc = pl.ctb_col[u];
+                    const int32_t mc = (int32_t)(pl.rel_ptr[c + 1] - pl.rel_ptr[c]);
+                    const int32_t *rl = pl.rel.data() + pl.rel_ptr[c];
+                    for (int32_t i = jc; i < mc; ++i) touch(rl[i], 1);
+                }
+                std::sort(touched.begin(), touched.end());
+                for (int32_t row : touched) {
+                    pos[row] = pl.ent_sptr.back();
+                    pl.ent_dst.push_back(pl.fr_off[s] + (int64_t)j * r + row);
+                    pl.ent_reg.push_back(j < k && row == j ? pl.reg_sign[pl.sn_first[s] + j] : (int8_t)-1);
+                    pl.ent_sptr.push_back(pl.ent_sptr.back() + cnt[row]);
+                }
+                pl.ent_src.resize((size_t)pl.ent_sptr.back());
+                for (int64_t a = pl.asm_ptr[task]; a < pl.asm_ptr[task + 1]; ++a)
+                    pl.ent_src[pos[pl.asm_row[a]]++] = -pl.asm_src[a] - 1;
+                for (int64_t u = pl.ctb_ptr[task]; u < pl.ctb_ptr[task + 1]; ++u) {
+                    const int32_t c = pl.ctb_child[u], jc = pl.ctb_col[u];
+                    const int64_t rc = pl.sn_rptr[c + 1] - pl.sn_rptr[c];
+                    const int64_t kc = pl.sn_first[c + 1] - pl.sn_first[c];
+                    const int32_t mc = (int32_t)(rc - kc);
+                    const int32_t *rl = pl.rel.data() + pl.rel_ptr[c];
+                    const int64_t ucol = pl.fr_off[c] + (kc + jc) * rc + kc;   // update block column jc
+                    for (int32_t i = jc; i < mc; ++i) pl.ent_src[pos[rl[i]]++] = ucol + i;
+                }
+                for (int32_t row : touched) { live[row] = 0; cnt[row] = 0; }
+            }
+        }
+        pl.ent_lvl_ptr[L + 1] = (int64_t)pl.ent_dst.size();
+        pl.zseg_lvl_ptr[L + 1] = (int64_t)pl.zseg_off.size();
+    }
+    // every index the device will follow stays inside the front buffer / the K values
+    for (int64_t d : pl.ent_dst) if (d < 0 || d >= pl.front_total) return false;
+    for (int64_t v : pl.ent_src) if (v >= pl.front_total || (v < 0 && -v - 1 >= nnzK)) return false;
+    for (size_t z = 0; z < pl.zseg_off.size(); ++z)
+        if (pl.zseg_off[z] < 0 || pl.zseg_off[z] + pl.zseg_len[z] > pl.front_total) return false;
+    return true;
 }
 
 int build_plan(qg_handle *h) {
@@ -359,6 +441,7 @@ int build_plan(qg_handle *h) {
         const int32_t o = sym.perm[c];
         pl.reg_sign[c] = (int8_t)(o < h->n ? 0 : (o < h->n + h->p ? 1 : 2));
     }
+    if (!build_assembly_map(pl, task_base, nnzK)) return QG_ERR_PATTERN;
     return QG_OK;
 }
 

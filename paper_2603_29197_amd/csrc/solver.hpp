@@ -52,6 +52,18 @@ struct Plan {
     std::vector<int64_t> ctb_src;         // position of each contribution in the solve work vector
     std::vector<int64_t> rel_ptr;         // per supernode: relative map of its update rows
     std::vector<int32_t> rel;
+    // numeric assembly, level by level: every front entry that receives a value, with its
+    // sources in summation order (the K entry first, then the children's update entries in
+    // child order), and the segments of front storage cleared before the gather
+    std::vector<int64_t> ent_lvl_ptr;     // nlevels + 1
+    std::vector<int64_t> ent_dst;         // destination (offset in the front buffer)
+    std::vector<int64_t> ent_sptr;        // sources of each entry (nent + 1)
+    std::vector<int8_t> ent_reg;          // pivot kind for the static regularization of a pivot diagonal, else -1
+    std::vector<int64_t> ent_src;         // >= 0: offset in the front buffer (a child's update entry);
+                                          // < 0: -(index into the K values) - 1
+    std::vector<int64_t> zseg_lvl_ptr;    // nlevels + 1
+    std::vector<int64_t> zseg_off;        // cleared segments: offset and length
+    std::vector<int32_t> zseg_len;
     std::vector<int64_t> uv_off;          // per supernode: offset of its update vector (solves)
     std::vector<int64_t> dinv_off;        // per supernode: offset of its inverse diagonal blocks
     int64_t dinv_total = 0;
@@ -79,10 +91,12 @@ struct Device {
     DBuf<int64_t> Pp; DBuf<int32_t> Pi;   // P upper pattern (for dL/dP)
     DBuf<int32_t> perm, iperm;
     // plan
-    DBuf<int32_t> sn_first, sn_rows, task_sn, task_col, asm_row, ctb_child, ctb_col, rel, ch_ptr,
-        ch_list, lvl_small_sn;
-    DBuf<int64_t> sn_rptr, fr_off, task_ptr, asm_ptr, asm_src, ctb_ptr, ctb_src, rel_ptr, uv_off;
+    DBuf<int32_t> sn_first, sn_rows, task_sn, task_col, ch_ptr, ch_list, lvl_small_sn;
+    DBuf<int64_t> sn_rptr, fr_off, task_ptr, ctb_ptr, ctb_src, uv_off;
     DBuf<int8_t> reg_sign;
+    DBuf<int64_t> ent_dst, ent_sptr, ent_src, zseg_off;   // numeric assembly map (see Plan)
+    DBuf<int8_t> ent_reg;
+    DBuf<int32_t> zseg_len;
     DBuf<double> front64;
     DBuf<float> front32;
     DBuf<double> uvec;          // update vectors of the triangular solves

@@ -508,6 +508,7 @@ __global__ void __launch_bounds__(256) trail_update(T *__restrict__ F, int32_t r
     constexpr int LDT = sizeof(T) == 4 ? 80 : 64;
     __shared__ T As[2][KC * LDT];                  // As[kk * LDT + i] = L(r0 + i, k)
     __shared__ T Bs[2][KC * LDT];                  // Bs[kk * LDT + j] = L(c0 + j, k) * D(k)
+    __shared__ T Dk[SB];                           // D(k0 .. k0 + kb - 1)
     // Workgroup IDs are dealt to the 8 XCDs in turn; XCD x takes the tile rows ti = x (mod 8)
     // and walks them column tile by column tile, so its concurrent workgroups share the column
     // panel and keep their row panels in that XCD's L2.
@@ -539,7 +540,7 @@ __global__ void __launch_bounds__(256) trail_update(T *__restrict__ F, int32_t r
             }
     // staging registers of one chunk (raw values + validity bits; zeroing waits for the LDS store)
     const int32_t i = tid & 63;
-    T ra[PER], rb[PER], rd[PER];
+    T ra[PER], rb[PER];
     uint32_t va = 0, vb = 0;
     auto gload = [&](int32_t kc) {
         va = vb = 0;
@@ -552,17 +553,16 @@ __global__ void __launch_bounds__(256) trail_update(T *__restrict__ F, int32_t r
             const bool oka = okk && r0 + i < r, okb = okk && c0 + i < c_hi;
             ra[u] = colp[oka ? r0 + i : 0];
             rb[u] = colp[okb ? c0 + i : 0];
-            rd[u] = colp[kcol];
             va |= (uint32_t)oka << u;
             vb |= (uint32_t)okb << u;
         }
     };
-    auto lstore = [&](int buf) {
+    auto lstore = [&](int buf, int32_t kc) {
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
             const int32_t kk = (tid >> 6) + 4 * u;
             As[buf][kk * LDT + i] = ((va >> u) & 1u) ? ra[u] : T(0);
-            Bs[buf][kk * LDT + i] = ((vb >> u) & 1u) ? rb[u] * rd[u] : T(0);
+            Bs[buf][kk * LDT + i] = ((vb >> u) & 1u) ? rb[u] * Dk[kc + kk] : T(0);
         }
     };
     V acc[2][2];
@@ -571,8 +571,10 @@ __global__ void __launch_bounds__(256) trail_update(T *__restrict__ F, int32_t r
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = V{0, 0, 0, 0};
     const int32_t nch = (kb + KC - 1) / KC;
+    if (tid < kb) Dk[tid] = F[(int64_t)(k0 + tid) * r + k0 + tid];
     gload(0);
-    lstore(0);
+    __syncthreads();
+    lstore(0, 0);
     __syncthreads();
     for (int32_t c = 0; c < nch; ++c) {
         const int buf = c & 1;
@@ -590,7 +592,7 @@ __global__ void __launch_bounds__(256) trail_update(T *__restrict__ F, int32_t r
 #pragma unroll
                 for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = mfma16x16x4(a_op[bj], b_op[bi], acc[bi][bj]);
         }
-        if (c + 1 < nch) lstore(buf ^ 1);
+        if (c + 1 < nch) lstore(buf ^ 1, (c + 1) * KC);
         __syncthreads();
     }
     // lane holds D(mfma_out_row(lk, v), lr) = C(row = wr + 16 bi + lr, col = wc + 16 bj + mfma_out_row(lk, v))

@@ -9,7 +9,7 @@
 // unit-upper solve with L11'.  Arithmetic is FP64; L is read in the factor's
 // precision (FP32 factors are widened on load).
 //
-// Small fronts: one 128-thread workgroup per supernode, per level.  Large
+// Small fronts: one wavefront per supernode, four per workgroup, per level.  Large
 // fronts, per SB-column super-block J with the stored inverse X_J of its
 // unit-lower diagonal block and W_J = L(below J, J) X_J: forward, one kernel
 // forms y_J = X_J v_J and, in other workgroups, v_below -= W_J v_J; backward,
@@ -57,80 +57,116 @@ __global__ void __launch_bounds__(256) fwd_gather_level(
     }
 }
 
-// Small front, forward: one 128-thread workgroup per front of a level, one
-// thread per row.  The row's right-hand side is gathered here (own entry plus
-// the children's update-vector entries that map onto it, in child order),
-// then k elimination steps with L columns read from the front, and the update
-// vector is left in the front's own slots for the parent.
+// Small fronts (r <= SMALL_R = 128): one wavefront per front, four fronts per
+// workgroup; lane l holds rows l and l + 64.  The wavefront's rows live in
+// LDS and its LDS operations complete in order, so the elimination steps need
+// no workgroup barrier.
+constexpr int SW = 4;                       // fronts (wavefronts) per workgroup
+
+// Forward: the row's right-hand side is gathered (own entry plus the
+// children's update-vector entries that map onto it, in child order), then k
+// elimination steps with L columns read from the front, and the update vector
+// is left in the front's own slots for the parent.
 template <typename T>
-__global__ void __launch_bounds__(SMALL_R) fwd_small(
-    const int32_t *__restrict__ sn_list, const int32_t *__restrict__ sn_first,
+__global__ void __launch_bounds__(64 * SW) fwd_small(
+    int32_t nfront, const int32_t *__restrict__ sn_list, const int32_t *__restrict__ sn_first,
     const int64_t *__restrict__ sn_rptr, const int64_t *__restrict__ fr_off, const T *__restrict__ front,
     const int64_t *__restrict__ task0, const int64_t *__restrict__ ctb_ptr, const int64_t *__restrict__ ctb_src,
     double *__restrict__ vwork, double *__restrict__ xp) {
-    __shared__ double v[SMALL_R];
-    const int32_t s = sn_list[blockIdx.x];
-    const int lane = threadIdx.x;
+    __shared__ double vsh[SW][SMALL_R];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int32_t q = blockIdx.x * SW + w;
+    if (q >= nfront) return;                   // whole wavefront
+    double *v = vsh[w];
+    const int32_t s = sn_list[q];
     const int32_t f = sn_first[s];
     const int32_t r = (int32_t)(sn_rptr[s + 1] - sn_rptr[s]);
     const int32_t k = sn_first[s + 1] - f;
     double *vs = vwork + task0[s];
-    if (lane < r) {
-        const int64_t tk = task0[s] + lane;
-        double a = lane < k ? xp[f + lane] : 0.0;
-        for (int64_t u = ctb_ptr[tk]; u < ctb_ptr[tk + 1]; ++u) a += vwork[ctb_src[u]];
-        v[lane] = a;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int32_t row = lane + 64 * h;
+        if (row < r) {
+            const int64_t tk = task0[s] + row;
+            double a = row < k ? xp[f + row] : 0.0;
+            for (int64_t u = ctb_ptr[tk]; u < ctb_ptr[tk + 1]; ++u) a += vwork[ctb_src[u]];
+            v[row] = a;
+        }
     }
-    __syncthreads();
+    __builtin_amdgcn_wave_barrier();
     const T *F = front + fr_off[s];
     for (int32_t jj = 0; jj < k; ++jj) {
         const double yj = v[jj];
-        const bool act = lane > jj && lane < r;
-        const T l = F[(int64_t)jj * r + (act ? lane : jj)];
-        if (act) v[lane] -= (double)l * yj;
-        __syncthreads();
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int32_t row = lane + 64 * h;
+            const bool act = row > jj && row < r;
+            const T l = F[(int64_t)jj * r + (act ? row : jj)];
+            if (act) v[row] -= (double)l * yj;
+        }
+        __builtin_amdgcn_wave_barrier();
     }
-    if (lane < k) xp[f + lane] = v[lane];
-    else if (lane < r) vs[lane] = v[lane];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int32_t row = lane + 64 * h;
+        if (row < k) xp[f + row] = v[row];
+        else if (row < r) vs[row] = v[row];
+    }
 }
 
-// Small front, backward: v = D^-1 x_own - L21' g (g = solution at the
-// update rows), then the unit-upper solve with L11'.  The products with
-// L21' are formed by all threads (thread i takes row i of each pivot
-// column) with a wavefront butterfly and a two-wavefront sum, instead of a
-// serial loop per pivot.
+// Backward: v = D^-1 x_own - L21' g (g = solution at the update rows; the
+// products with L21' are summed per column over the wavefront with a
+// butterfly), then the unit-upper solve with L11'.
 template <typename T>
-__global__ void __launch_bounds__(SMALL_R) bwd_small(
-    const int32_t *__restrict__ sn_list, const int32_t *__restrict__ sn_first,
+__global__ void __launch_bounds__(64 * SW) bwd_small(
+    int32_t nfront, const int32_t *__restrict__ sn_list, const int32_t *__restrict__ sn_first,
     const int64_t *__restrict__ sn_rptr, const int32_t *__restrict__ sn_rows,
     const int64_t *__restrict__ fr_off, const T *__restrict__ front, double *__restrict__ xp) {
-    __shared__ double v[SMALL_R];
-    __shared__ double part[2][SMALL_R];
-    const int32_t s = sn_list[blockIdx.x];
-    const int lane = threadIdx.x, w = lane >> 6, l64 = lane & 63;
+    __shared__ double vsh[SW][SMALL_R];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int32_t q = blockIdx.x * SW + w;
+    if (q >= nfront) return;                   // whole wavefront
+    double *v = vsh[w];
+    const int32_t s = sn_list[q];
     const int32_t f = sn_first[s];
     const int32_t r = (int32_t)(sn_rptr[s + 1] - sn_rptr[s]);
     const int32_t k = sn_first[s + 1] - f;
     const T *F = front + fr_off[s];
-    const bool upd = lane >= k && lane < r;
-    const double gi = upd ? xp[sn_rows[sn_rptr[s] + lane]] : 0.0;
-    for (int32_t c = 0; c < k; ++c) {
-        const T lv = F[(int64_t)c * r + (upd ? lane : c)];
-        double p = upd ? (double)lv * gi : 0.0;
-        for (int off = 32; off > 0; off >>= 1) p += __shfl_xor(p, off);
-        if (l64 == 0) part[w][c] = p;
+    double g[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int32_t row = lane + 64 * h;
+        g[h] = (row >= k && row < r) ? xp[sn_rows[sn_rptr[s] + row]] : 0.0;
     }
-    __syncthreads();
-    if (lane < k) v[lane] = xp[f + lane] / (double)F[(int64_t)lane * r + lane] - (part[0][lane] + part[1][lane]);
-    __syncthreads();
+    for (int32_t c = 0; c < k; ++c) {
+        double p = 0.0;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int32_t row = lane + 64 * h;
+            const bool upd = row >= k && row < r;
+            const T lv = F[(int64_t)c * r + (upd ? row : c)];
+            p += upd ? (double)lv * g[h] : 0.0;
+        }
+        for (int off = 32; off > 0; off >>= 1) p += __shfl_xor(p, off);
+        if (lane == 0) v[c] = xp[f + c] / (double)F[(int64_t)c * r + c] - p;
+    }
+    __builtin_amdgcn_wave_barrier();
     for (int32_t i = k - 1; i >= 0; --i) {
         const double xi = v[i];
-        const bool act = lane < i;
-        const T l = F[(int64_t)(act ? lane : i) * r + i];
-        if (act) v[lane] -= (double)l * xi;
-        __syncthreads();
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int32_t row = lane + 64 * h;
+            const bool act = row < i;
+            const T l = F[(int64_t)(act ? row : i) * r + i];
+            if (act) v[row] -= (double)l * xi;
+        }
+        __builtin_amdgcn_wave_barrier();
     }
-    if (lane < k) xp[f + lane] = v[lane];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int32_t row = lane + 64 * h;
+        if (row < k) xp[f + row] = v[row];
+    }
 }
 
 // ------------------------------- large -------------------------------------
@@ -289,7 +325,7 @@ static int solve_perm(qg_handle *h, const T *front, const T *sinv, const T *wbuf
     for (int32_t L = 0; L < pl.nlevels; ++L) {
         const int32_t s0 = pl.lvl_small_ptr[L], s1 = pl.lvl_small_ptr[L + 1];
         if (s1 > s0)
-            fwd_small<T><<<s1 - s0, SMALL_R, 0, h->stream>>>(d.lvl_small_sn.p + s0, d.sn_first.p, d.sn_rptr.p,
+            fwd_small<T><<<(s1 - s0 + SW - 1) / SW, 64 * SW, 0, h->stream>>>(s1 - s0, d.lvl_small_sn.p + s0, d.sn_first.p, d.sn_rptr.p,
                                                                d.fr_off.p, front, d.task0.p, d.ctb_ptr.p,
                                                                d.ctb_src.p, d.vwork.p, xp);
         for (int32_t u = pl.lvl_large_ptr[L]; u < pl.lvl_large_ptr[L + 1]; ++u) {
@@ -332,7 +368,7 @@ static int solve_perm(qg_handle *h, const T *front, const T *sinv, const T *wbuf
         }
         const int32_t s0 = pl.lvl_small_ptr[L], s1 = pl.lvl_small_ptr[L + 1];
         if (s1 > s0)
-            bwd_small<T><<<s1 - s0, SMALL_R, 0, h->stream>>>(d.lvl_small_sn.p + s0, d.sn_first.p, d.sn_rptr.p,
+            bwd_small<T><<<(s1 - s0 + SW - 1) / SW, 64 * SW, 0, h->stream>>>(s1 - s0, d.lvl_small_sn.p + s0, d.sn_first.p, d.sn_rptr.p,
                                                           d.sn_rows.p, d.fr_off.p, front, xp);
     }
     QG_HIP(h, hipGetLastError());

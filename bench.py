@@ -35,7 +35,7 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
 # runs (profiles/trail_update_lasso.md), each scaled by what the counter reads for a plain device
 # copy of known size (FETCH_SIZE x 1.9998, WRITE_SIZE x 1.0). Counters describe one build of the
 # kernel: reset to None when trail_update changes until they are taken again.
-TRAFFIC_BYTES_PER_LAUNCH = {"fp32": None, "fp64": None}
+TRAFFIC_BYTES_PER_LAUNCH = {"fp32": 4.851e7, "fp64": 1.010e8}
 WORKLOAD = "lasso F 20000x10000 density 0.005 (n=40000, p=20000, m=20000, N_K=80000)"
 
 

@@ -11,7 +11,7 @@ the linearised complementarity  Arw(z) ds + Arw(s) dz = 0  (Arw(u) the
 arrow matrix of u: u_i on the orthant, [[u0, u1'], [u1, u0 I]] on an SOC),
 is
 
-    K_fin [dx; dy; dz] = [-dc - dP x; db; dh],
+    K_fin [dx; dy; dz] = [-dc - dP x - dA'y - dG'z; db - dA x; dh - dG x],
     K_fin = [[P, A', G'], [A, 0, 0], [G, 0, -H]],   H = Arw(z)^-1 Arw(s),
 
 i.e. eq. (2) with -W'W replaced by -H: H = s_i/z_i on the orthant (which is
@@ -29,7 +29,10 @@ K_fin u = [g; 0; 0] (K_fin is symmetric); then
     dL/dc = -u_x,  dL/db = u_y,  dL/dh = u_z,
     dL/dP_ij = -(u_x,i x_j + u_x,j x_i)  (i < j),   dL/dP_ii = -u_x,i x_i
 
-on the stored upper pattern of P.
+on the stored upper pattern of P, and on the patterns of A and G (from
+dL = u'[rhs] with the dA and dG terms above)
+
+    dL/dA_ij = -(y_i u_x,j + u_y,i x_j),   dL/dG_ij = -(z_i u_x,j + u_z,i x_j).
 
 ``backward`` uses the sparse factorization with FP64 refinement;
 ``backward_dense`` forms K_fin densely and calls numpy's dense solver.
@@ -83,13 +86,16 @@ def final_factor(prob, result) -> KKTFactor:
     return result._final_factor
 
 
-def _grads(prob, x, u):
+def _grads(prob, x, y, z, u):
     n, p = prob.n, prob.p
     ux, uy, uz = u[:n], u[n:n + p], u[n + p:]
     Pu = prob.P.tocoo()              # tocoo() of a CSC matrix keeps the CSC entry order
     dP = np.where(Pu.row == Pu.col, -ux[Pu.row] * x[Pu.col],
                   -(ux[Pu.row] * x[Pu.col] + ux[Pu.col] * x[Pu.row]))
-    return dict(dc=-ux, db=uy.copy(), dh=uz.copy(), dP=dP, u=u)
+    Au, Gu = prob.A.tocoo(), prob.G.tocoo()
+    dA = -(y[Au.row] * ux[Au.col] + uy[Au.row] * x[Au.col])
+    dG = -(z[Gu.row] * ux[Gu.col] + uz[Gu.row] * x[Gu.col])
+    return dict(dc=-ux, db=uy.copy(), dh=uz.copy(), dP=dP, dA=dA, dG=dG, u=u)
 
 
 def backward(prob, result, g, ir_max: int = 10):
@@ -97,7 +103,7 @@ def backward(prob, result, g, ir_max: int = 10):
     F = final_factor(prob, result)
     rhs = np.concatenate([g, np.zeros(prob.p + prob.m)])
     u, _ = F.solve(rhs, ir_max=ir_max)
-    return _grads(prob, result.x, u)
+    return _grads(prob, result.x, result.y, result.z, u)
 
 
 def backward_dense(prob, result, g):
@@ -106,4 +112,4 @@ def backward_dense(prob, result, g):
     K = _kkt.full_from_upper(_kkt.kkt_upper(prob, orth, blocks)).toarray()
     rhs = np.concatenate([g, np.zeros(prob.p + prob.m)])
     u = np.linalg.solve(K, rhs)
-    return _grads(prob, result.x, u)
+    return _grads(prob, result.x, result.y, result.z, u)

@@ -255,7 +255,7 @@ def test_adjoint_matches_dense_kkt_and_dot_product(name):
     g = rng.standard_normal(prob.n)
     a = adjoint.backward(prob, r, g)
     dn = adjoint.backward_dense(prob, r, g)
-    for k in ("dc", "db", "dh", "dP"):
+    for k in ("dc", "db", "dh", "dP", "dA", "dG"):
         assert np.allclose(a[k], dn[k], rtol=1e-8, atol=1e-8 * np.max(np.abs(dn[k]), initial=1.0))
     # dot-product test on the same factor: u'r = g'(K^-1 r)_x
     rr = rng.standard_normal(prob.n + prob.p + prob.m)
@@ -284,3 +284,19 @@ def test_adjoint_vs_central_finite_differences():
             xp, xm = vals
             fd = 0.5 * (xp - xm) @ (xp + xm - 2 * xref) / (2 * hstep)
             assert abs(gr[key][j] - fd) <= 1e-3 * max(abs(fd), 1e-3), (vec, j, gr[key][j], fd)
+    # values of A and G on their patterns (the perturbation keeps the pattern): three seeded
+    # entries and the three with the largest gradient (most entries of G sit on inactive bounds,
+    # where the gradient vanishes)
+    for mat, key in (("A", "dA"), ("G", "dG")):
+        M = getattr(prob, mat)
+        top = np.argsort(-np.abs(gr[key]))[:3]
+        for t in np.unique(np.concatenate([rng.choice(M.nnz, size=3, replace=False), top])):
+            vals = []
+            for sgn in (+1, -1):
+                pr = problems.Problem(**{**prob.__dict__})
+                M2 = M.copy(); M2.data[t] += sgn * hstep
+                setattr(pr, mat, M2)
+                vals.append(ipm.solve(pr, st).x)
+            xp, xm = vals
+            fd = 0.5 * (xp - xm) @ (xp + xm - 2 * xref) / (2 * hstep)
+            assert abs(gr[key][t] - fd) <= 1e-3 * max(abs(fd), 1e-3), (mat, t, gr[key][t], fd)

@@ -200,16 +200,19 @@ int qg_solve(qg_handle *h, double *x, double *s, double *y, double *z, qg_info *
 
 /*
  * Gradients of a loss L(x*) through the last solve by implicit
- * differentiation of the optimality conditions: with u solving
- * K_fin u = [dl_dx; 0; 0] on the stored final factor (FP64 refinement):
- * dl_dc = -u_x (n), dl_db = u_y (p), dl_dh = u_z (m), and on P's upper
- * pattern dl_dPval[t] = -(u_i x_j + u_j x_i) (i < j), -u_i x_i (i == j).
+ * differentiation of the optimality conditions (the linearised KKT system,
+ * eq. (2) at the final iterate): with u solving K_fin u = [dl_dx; 0; 0] on
+ * the stored final factor (FP64 refinement): dl_dc = -u_x (n),
+ * dl_db = u_y (p), dl_dh = u_z (m); on P's upper pattern
+ * dl_dPval[t] = -(u_i x_j + u_j x_i) (i < j), -u_i x_i (i == j); on the
+ * patterns of A and G (entries in the CSC order given to qg_setup)
+ * dl_dAval[t] = -(y_i u_x,j + u_y,i x_j), dl_dGval[t] = -(z_i u_x,j + u_z,i x_j).
  * All device pointers; any output may be NULL.  Requires a previous
  * qg_solve with settings.differentiable = 1 whose status was QG_SOLVED or
  * QG_SOLVED_INACCURATE (QG_ERR_STATE otherwise).
  */
 int qg_backward(qg_handle *h, const double *dl_dx, double *dl_dc, double *dl_dh,
-                double *dl_db, double *dl_dPval);
+                double *dl_db, double *dl_dPval, double *dl_dAval, double *dl_dGval);
 
 /* Host copies of the analysis; valid until qg_cleanup. */
 int qg_get_pattern(const qg_handle *h, qg_pattern *out);

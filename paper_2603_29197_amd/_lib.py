@@ -106,7 +106,7 @@ def lib():
     L.qg_update.argtypes = [vp, c_double_p, c_double_p, c_double_p, c_double_p, c_double_p, c_double_p]
     L.qg_set_settings.argtypes = [vp, ctypes.POINTER(qg_settings)]
     L.qg_solve.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(qg_info)]
-    L.qg_backward.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.qg_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     L.qg_get_pattern.argtypes = [vp, ctypes.POINTER(qg_pattern)]
     L.qg_last_hip_error.argtypes = [vp]
     L.qg_cleanup.argtypes = [vp]

@@ -158,15 +158,21 @@ class Solver:
         self.info = info.as_dict()
         return x[:self.n], s[:self.m], y[:self.p], z[:self.m], self.info
 
-    def backward(self, dl_dx, want_P: bool = True):
+    def backward(self, dl_dx, want_P: bool = True, want_A: bool = False, want_G: bool = False):
+        """Gradients of L(x*) with dl_dx = dL/dx*: dc, dh, db, and the values of P, A and G on
+        their patterns (dP, dA, dG; None unless asked for and the matrix has entries)."""
         t = self.torch
         dl_dx = dl_dx.to(device="cuda", dtype=t.float64).contiguous()
         dc, dh, db = self._empty(self.n), self._empty(self.m), self._empty(self.p)
-        nP = int(self.prob.P.nnz)
-        dP = self._empty(nP) if (want_P and nP > 0) else None
+        nnz = {k: int(getattr(self.prob, k).nnz) for k in ("P", "A", "G")}
+        want = {"P": want_P, "A": want_A, "G": want_G}
+        out = {k: (self._empty(nnz[k]) if (want[k] and nnz[k] > 0) else None) for k in ("P", "A", "G")}
         check(lib().qg_backward(self.handle, self._vp(dl_dx), self._vp(dc), self._vp(dh), self._vp(db),
-                                self._vp(dP)), "qg_backward")
-        return dict(dc=dc[:self.n], dh=dh[:self.m], db=db[:self.p], dP=None if dP is None else dP[:nP])
+                                self._vp(out["P"]), self._vp(out["A"]), self._vp(out["G"])), "qg_backward")
+        res = dict(dc=dc[:self.n], dh=dh[:self.m], db=db[:self.p])
+        for k in ("P", "A", "G"):
+            res["d" + k] = None if out[k] is None else out[k][:nnz[k]]
+        return res
 
     def pattern(self) -> dict:
         pt = qg_pattern()
@@ -229,26 +235,32 @@ def _autograd_function():
     import torch
 
     class QGSolve(torch.autograd.Function):
-        """x* = QGSolve.apply(c, h, b, Pval, solver): forward updates the
-        values (fixed pattern) and solves; backward returns dL/dc, dL/dh,
-        dL/db and dL/dPval from one adjoint solve on the stored factor."""
+        """x* = QGSolve.apply(c, h, b, Pval, solver[, Aval, Gval]): forward
+        updates the values (fixed pattern) and solves; backward returns
+        dL/dc, dL/dh, dL/db and dL/d(P, A, G values) from one adjoint solve
+        on the stored factor (None for value arrays passed as None)."""
 
         @staticmethod
-        def forward(ctx, c, h, b, Pval, solver):
-            solver.update(Pval=None if Pval is None else Pval.detach().cpu().numpy(),
-                          c=c.detach().cpu().numpy(), b=b.detach().cpu().numpy(), h=h.detach().cpu().numpy())
+        def forward(ctx, c, h, b, Pval, solver, *AG):
+            Aval = AG[0] if len(AG) > 0 else None
+            Gval = AG[1] if len(AG) > 1 else None
+            ctx.n_extra = len(AG)
+            host = lambda v: None if v is None else v.detach().cpu().numpy()
+            solver.update(Pval=host(Pval), c=host(c), b=host(b), h=host(h), Aval=host(Aval), Gval=host(Gval))
             if not solver.settings.differentiable:
                 solver.set_settings(differentiable=1)
             x, s, y, z, info = solver.solve()
             ctx.solver = solver
-            ctx.has_P = Pval is not None
+            ctx.has = (Pval is not None, Aval is not None, Gval is not None)
             return x.clone()
 
         @staticmethod
         def backward(ctx, gx):
-            g = ctx.solver.backward(gx, want_P=ctx.has_P)
-            return g["dc"].clone(), g["dh"].clone(), g["db"].clone(), \
-                (g["dP"].clone() if ctx.has_P else None), None
+            hP, hA, hG = ctx.has
+            g = ctx.solver.backward(gx, want_P=hP, want_A=hA, want_G=hG)
+            clone = lambda v, has: v.clone() if (has and v is not None) else None
+            extra = (clone(g["dA"], hA), clone(g["dG"], hG))[:ctx.n_extra]
+            return (g["dc"].clone(), g["dh"].clone(), g["db"].clone(), clone(g["dP"], hP), None) + extra
 
     return QGSolve
 

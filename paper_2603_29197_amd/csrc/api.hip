@@ -31,7 +31,22 @@ __global__ void dP_kernel(int32_t n, const int64_t *__restrict__ Pp, const int32
     }
 }
 
-int adjoint_backward(qg_handle *h, const double *g, double *dc, double *dh, double *db, double *dP) {
+// On the pattern of a constraint matrix M (columns = primal variables, rows
+// = the constraint's dual variables v): dL/dM_ij = -(v_i u_x,j + u_v,i x_j),
+// one thread per column.
+__global__ void dM_kernel(int32_t n, const int64_t *__restrict__ Mp, const int32_t *__restrict__ Mi,
+                          const double *__restrict__ v, const double *__restrict__ uv,
+                          const double *__restrict__ ux, const double *__restrict__ x, double *__restrict__ dM) {
+    const int32_t j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= n) return;
+    for (int64_t t = Mp[j]; t < Mp[j + 1]; ++t) {
+        const int32_t i = Mi[t];
+        dM[t] = -(v[i] * ux[j] + uv[i] * x[j]);
+    }
+}
+
+int adjoint_backward(qg_handle *h, const double *g, double *dc, double *dh, double *db, double *dP,
+                     double *dA, double *dG) {
     Device &d = h->d;
     const int32_t n = h->n, p = h->p, m = h->m;
     int rc;
@@ -44,6 +59,14 @@ int adjoint_backward(qg_handle *h, const double *g, double *dc, double *dh, doub
     if (dh && m > 0) QG_HIP(h, hipMemcpyAsync(dh, u + n + p, sizeof(double) * m, hipMemcpyDeviceToDevice, h->stream));
     if (dP && !h->pp.P.rowind.empty()) {
         dP_kernel<<<(n + 255) / 256, 256, 0, h->stream>>>(n, d.Pp.p, d.Pi.p, u, d.x.p, dP);
+        QG_HIP(h, hipGetLastError());
+    }
+    if (dA && !h->pp.A.rowind.empty()) {
+        dM_kernel<<<(n + 255) / 256, 256, 0, h->stream>>>(n, d.Ap.p, d.Ai.p, d.y.p, u + n, u, d.x.p, dA);
+        QG_HIP(h, hipGetLastError());
+    }
+    if (dG && !h->pp.G.rowind.empty()) {
+        dM_kernel<<<(n + 255) / 256, 256, 0, h->stream>>>(n, d.Gp.p, d.Gi.p, d.z.p, u + n + p, u, d.x.p, dG);
         QG_HIP(h, hipGetLastError());
     }
     QG_HIP(h, hipStreamSynchronize(h->stream));
@@ -94,6 +117,10 @@ static int allocate_device(qg_handle *h) {
     UP(zcone, zc);
     UP(Pp, h->pp.P.colptr);
     UP(Pi, h->pp.P.rowind);
+    UP(Ap, h->pp.A.colptr);
+    UP(Ai, h->pp.A.rowind);
+    UP(Gp, h->pp.G.colptr);
+    UP(Gi, h->pp.G.rowind);
 #undef UP
     const size_t N = (size_t)h->N, m = (size_t)h->m;
     if ((rc = dalloc(h, d.front64, (size_t)pl.front_total))) return rc;
@@ -343,10 +370,10 @@ int qg_solve(qg_handle *h, double *x, double *s, double *y, double *z, qg_info *
 }
 
 int qg_backward(qg_handle *h, const double *dl_dx, double *dl_dc, double *dl_dh, double *dl_db,
-                double *dl_dPval) {
+                double *dl_dPval, double *dl_dAval, double *dl_dGval) {
     if (!h || !dl_dx) return QG_ERR_ARG;
     if (!h->solved || !h->final_factor) return QG_ERR_STATE;
-    return adjoint_backward(h, dl_dx, dl_dc, dl_dh, dl_db, dl_dPval);
+    return adjoint_backward(h, dl_dx, dl_dc, dl_dh, dl_db, dl_dPval, dl_dAval, dl_dGval);
 }
 
 int qg_get_pattern(const qg_handle *h, qg_pattern *out) {

@@ -204,10 +204,10 @@ def test_backward_matches_oracle(name):
     assert info["status"] == 1
     ref = oracle_solution(name)
     g = np.random.default_rng(11).standard_normal(prob.n)
-    gr = S.backward(dev(g))
+    gr = S.backward(dev(g), want_A=True, want_G=True)
     want = oadj.backward_dense(prob, ref, g)
-    for k in ("dc", "dh", "db", "dP"):
-        if k == "dP" and not prob.P.nnz:
+    for k in ("dc", "dh", "db", "dP", "dA", "dG"):
+        if k in ("dP", "dA", "dG") and not getattr(prob, k[1]).nnz:
             continue
         a, b = host(gr[k]), want[k]
         if b.size:
@@ -249,4 +249,28 @@ def test_autograd_function():
     ec = float(np.max(np.abs(host(c.grad) - want["dc"])) / max(1.0, np.max(np.abs(want["dc"]))))
     eb = float(np.max(np.abs(host(b.grad) - want["db"])) / max(1.0, np.max(np.abs(want["db"]))))
     assert ec <= 1e-5 and eb <= 1e-5, (ec, eb)
+    S.close()
+
+
+def test_autograd_function_constraint_values():
+    """The same loss differentiated with respect to the values of A and G
+    (entries in CSC order) through QGSolve's optional inputs."""
+    import paper_2603_29197_amd as qg
+    prob = problems.lasso(rows=120, cols=60, density=0.1, seed=9)
+    S = solver(prob, differentiable=1)
+    c = torch.tensor(prob.c, device="cuda", requires_grad=True)
+    h = torch.tensor(prob.h, device="cuda", requires_grad=True)
+    b = torch.tensor(prob.b, device="cuda", requires_grad=True)
+    Av = torch.tensor(prob.A.data, device="cuda", requires_grad=True)
+    Gv = torch.tensor(prob.G.data, device="cuda", requires_grad=True)
+    x = qg.QGSolve.apply(c, h, b, None, S, Av, Gv)
+    xref = torch.randn(prob.n, dtype=torch.float64, device="cuda")
+    loss = 0.5 * ((x - xref) ** 2).sum()
+    loss.backward()
+    ref = oipm.solve(prob)
+    want = oadj.backward_dense(prob, ref, ref.x - host(xref))
+    for got, k in ((Av.grad, "dA"), (Gv.grad, "dG"), (c.grad, "dc")):
+        e = float(np.max(np.abs(host(got) - want[k])) / max(1.0, np.max(np.abs(want[k]))))
+        print(f"[gpu] autograd {k} rel err {e:.2e}", flush=True)
+        assert e <= 1e-5, (k, e)
     S.close()

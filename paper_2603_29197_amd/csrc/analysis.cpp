@@ -204,6 +204,61 @@ inline uint64_t mix(uint64_t h, uint64_t v) {
     return h;
 }
 
+// Min-heap of variables keyed by (degree, index), with each variable's
+// position kept so that its key can be changed or it can be removed in
+// O(log N) on a flat array.  The key order is total, so the minimum -- the
+// next pivot -- is the same as with any other priority queue on that order.
+struct DegreeHeap {
+    std::vector<int32_t> heap;     // variables
+    std::vector<int32_t> pos;      // position of each variable in heap, -1 if absent
+    const std::vector<int64_t> *key = nullptr;
+    bool less(int32_t a, int32_t b) const {
+        const int64_t ka = (*key)[a], kb = (*key)[b];
+        return ka < kb || (ka == kb && a < b);
+    }
+    void place(size_t k, int32_t v) { heap[k] = v; pos[v] = (int32_t)k; }
+    void up(size_t k) {
+        const int32_t v = heap[k];
+        while (k > 0) {
+            const size_t par = (k - 1) / 2;
+            if (!less(v, heap[par])) break;
+            place(k, heap[par]);
+            k = par;
+        }
+        place(k, v);
+    }
+    void down(size_t k) {
+        const int32_t v = heap[k];
+        const size_t n = heap.size();
+        for (;;) {
+            size_t c = 2 * k + 1;
+            if (c >= n) break;
+            if (c + 1 < n && less(heap[c + 1], heap[c])) ++c;
+            if (!less(heap[c], v)) break;
+            place(k, heap[c]);
+            k = c;
+        }
+        place(k, v);
+    }
+    void push(int32_t v) { heap.push_back(v); up(heap.size() - 1); }
+    bool contains(int32_t v) const { return pos[v] >= 0; }
+    void remove(int32_t v) {
+        const size_t k = (size_t)pos[v];
+        pos[v] = -1;
+        const int32_t last = heap.back();
+        heap.pop_back();
+        if (last == v) return;
+        place(k, last);
+        up(k);
+        down((size_t)pos[last]);
+    }
+    int32_t pop() {
+        const int32_t v = heap[0];
+        remove(v);
+        return v;
+    }
+};
+
 }  // namespace
 
 void min_degree_order(int32_t N, const std::vector<int64_t> &Gp, const std::vector<int32_t> &Gi,
@@ -218,13 +273,16 @@ void min_degree_order(int32_t N, const std::vector<int64_t> &Gp, const std::vect
     g.mark.assign(N, 0);
     std::iota(g.head.begin(), g.head.end(), 0);
     std::iota(g.tail.begin(), g.tail.end(), 0);
-    std::set<std::pair<int64_t, int32_t>> pq;
+    DegreeHeap pq;
+    pq.key = &g.deg;
+    pq.pos.assign(N, -1);
+    pq.heap.reserve(N);
     for (int32_t i = 0; i < N; ++i) {
         auto &a = g.A[i];
         for (int64_t t = Gp[i]; t < Gp[i + 1]; ++t) if (Gi[t] != i) a.push_back(Gi[t]);
         std::sort(a.begin(), a.end());
         g.deg[i] = (int64_t)a.size();
-        pq.insert({g.deg[i], i});
+        pq.push(i);
     }
     order.clear();
     order.reserve(N);
@@ -232,9 +290,10 @@ void min_degree_order(int32_t N, const std::vector<int64_t> &Gp, const std::vect
     int64_t pivot_id = 0;
     std::vector<int32_t> Lp, members;
     std::vector<std::pair<uint64_t, int32_t>> keyed;
-    while (!pq.empty()) {
-        const int32_t p = pq.begin()->second;
-        pq.erase(pq.begin());
+    std::vector<uint64_t> hslot, hashes;     // hash count table (open addressing) and Lp's hashes
+    std::vector<int32_t> hcount;
+    while (!pq.heap.empty()) {
+        const int32_t p = pq.pop();
         ++pivot_id;
         // members of p in increasing order
         members.clear();
@@ -264,28 +323,45 @@ void min_degree_order(int32_t N, const std::vector<int64_t> &Gp, const std::vect
         for (int32_t i : Lp) wlp += g.nv[i];
         g.Lel[p] = Lp;
         g.wtot[p] = wlp;
-        for (int32_t i : Lp) pq.erase({g.deg[i], i});
+        for (int32_t i : Lp) if (pq.contains(i)) pq.remove(i);
         // list updates
         for (int32_t i : Lp) {
             auto &Ei = g.E[i];
             size_t k = 0;
             for (int32_t e : Ei) if (g.status[e] == ELEMENT) Ei[k++] = e;
-            Ei.resize(k);
+            Ei.erase(Ei.begin() + (std::ptrdiff_t)k, Ei.end());
             Ei.insert(std::lower_bound(Ei.begin(), Ei.end(), p), p);
             auto &Ai = g.A[i];
             k = 0;
             for (int32_t v : Ai) if (g.mark[v] != lpmark) Ai[k++] = v;
-            Ai.resize(k);
+            Ai.erase(Ai.begin() + (std::ptrdiff_t)k, Ai.end());
         }
-        // supervariable detection among Lp: hash, then confirm by full equality
+        // supervariable detection among Lp: hash, then confirm by full equality.  Only a hash
+        // shared by two or more variables can lead to a merge: those are found with an
+        // open-addressing count table, and only they are sorted by (hash, index)
         keyed.clear();
+        size_t cap = 16;
+        while (cap < 2 * Lp.size()) cap <<= 1;
+        if (hslot.size() < cap) { hslot.resize(cap); hcount.resize(cap); }
+        std::fill(hcount.begin(), hcount.begin() + (std::ptrdiff_t)cap, 0);
+        auto slot_of = [&](uint64_t h) {
+            size_t k = (size_t)((h * 0x9e3779b97f4a7c15ULL) >> 20) & (cap - 1);
+            while (hcount[k] != 0 && hslot[k] != h) k = (k + 1) & (cap - 1);
+            return k;
+        };
+        hashes.clear();
         for (int32_t i : Lp) {
             uint64_t h = mix(mix(0, g.A[i].size()), g.E[i].size());
             for (int32_t v : g.A[i]) h = mix(h, (uint64_t)v);
             h = mix(h, 0xabcdefULL);
             for (int32_t e : g.E[i]) h = mix(h, (uint64_t)e);
-            keyed.push_back({h, i});
+            hashes.push_back(h);
+            const size_t k = slot_of(h);
+            hslot[k] = h;
+            ++hcount[k];
         }
+        for (size_t t = 0; t < Lp.size(); ++t)
+            if (hcount[slot_of(hashes[t])] > 1) keyed.push_back({hashes[t], Lp[t]});
         std::sort(keyed.begin(), keyed.end());
         for (size_t a = 0; a < keyed.size();) {
             size_t b = a;
@@ -335,7 +411,7 @@ void min_degree_order(int32_t N, const std::vector<int64_t> &Gp, const std::vect
             int64_t d = std::min(rem - g.nv[i], g.deg[i] + lpi);
             d = std::min(d, wa + lpi + we);
             g.deg[i] = d;
-            pq.insert({d, i});
+            pq.push(i);
         }
     }
 }

@@ -112,8 +112,12 @@ typedef struct {
      * launch; index 0 = FP64 launches, 1 = FP32 launches */
     int64_t kern_launches[2];
     double kern_ms[2];                       /* summed launch durations */
-    double kern_flops[2];                    /* algorithmic flops: b M (M + 1) per launch (b panel
-                                                columns, M trailing rows, lower triangle incl. diag) */
+    double kern_flops[2];                    /* algorithmic flops: 2 b (C M - C (C - 1) / 2) per launch
+                                                (rank b, M rows by C columns of the lower part) */
+    double ms_step_p90;                      /* 90th percentile of the Newton-step times */
+    int64_t ntrisolve[2];                    /* triangular solves incl. refinement corrections:
+                                                [0] with an FP64 factor, [1] with an FP32 factor */
+    int64_t nresidual;                       /* refinement residuals r - K x (FP64, unregularized K) */
 } qg_info;
 
 /* Integer pattern of the analysis; pointers stay valid until the object

@@ -55,11 +55,12 @@ class qg_info(ctypes.Structure):
                 ("ms_step_median", ctypes.c_double), ("ms_step_median_fp32", ctypes.c_double),
                 ("ms_step_median_fp64", ctypes.c_double), ("nnz_L", ctypes.c_int64),
                 ("factor_flops", ctypes.c_double), ("kern_launches", ctypes.c_int64 * 2),
-                ("kern_ms", ctypes.c_double * 2), ("kern_flops", ctypes.c_double * 2)]
+                ("kern_ms", ctypes.c_double * 2), ("kern_flops", ctypes.c_double * 2),
+                ("ms_step_p90", ctypes.c_double), ("ntrisolve", ctypes.c_int64 * 2), ("nresidual", ctypes.c_int64)]
 
     def as_dict(self):
         d = {name: getattr(self, name) for name, _ in self._fields_}
-        for k in ("kern_launches", "kern_ms", "kern_flops"):
+        for k in ("kern_launches", "kern_ms", "kern_flops", "ntrisolve"):
             d[k] = list(d[k])
         d["status_name"] = STATUS.get(self.status, str(self.status))
         return d

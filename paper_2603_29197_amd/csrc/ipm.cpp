@@ -53,6 +53,15 @@ double median(std::vector<double> v) {
     return n % 2 ? v[n / 2] : 0.5 * (v[n / 2 - 1] + v[n / 2]);
 }
 
+// Percentile q in [0, 1] by linear interpolation between order statistics.
+double percentile(std::vector<double> v, double q) {
+    if (v.empty()) return 0.0;
+    std::sort(v.begin(), v.end());
+    const double pos = q * (double)(v.size() - 1);
+    const size_t lo = (size_t)pos, hi = std::min(lo + 1, v.size() - 1);
+    return v[lo] + (pos - (double)lo) * (v[hi] - v[lo]);
+}
+
 struct Scalars {
     double pres, dres, gap, pobj, dobj, sz;
     bool ok;
@@ -77,8 +86,15 @@ Scalars stop_test(qg_handle *h, const double *sc, double ea, double er) {
 }  // namespace
 
 // One refined solve; in FP32 mode a failed refinement test is reported.
+// Counts of the solve phase's work (for its roofline): triangular solves by
+// factor precision ([0] FP64, [1] FP32) and refinement residuals K x.
+struct SolveWork {
+    int64_t tri[2] = {0, 0};
+    int64_t residuals = 0;
+};
+
 static int solve_with(qg_handle *h, const double *rhs, double *x, int prec, int *ir_total, bool *failed,
-                      Events &ev, double *ms) {
+                      Events &ev, double *ms, SolveWork &work) {
     int steps = 0;
     bool ok = true;
     const int ir_max = prec == QG_FP32_IR ? h->st.ir_max32 : h->st.ir_max;
@@ -86,6 +102,9 @@ static int solve_with(qg_handle *h, const double *rhs, double *x, int prec, int 
     int rc = refined_solve(h, rhs, x, prec, ir_max, &steps, prec == QG_FP32_IR ? &ok : nullptr);
     if (rc) return rc;
     (void)hipEventRecord(ev.e[5], h->stream);
+    (void)hipEventSynchronize(ev.e[5]);   // the refinement test has drained the stream up to here
+    work.tri[prec == QG_FP32_IR ? 1 : 0] += 1 + steps;     // the solve and one per correction
+    work.residuals += steps + 1;                           // one per correction and the last test
     *ir_total += steps;
     *failed = !ok;
     *ms += elapsed(ev.e[4], ev.e[5]);
@@ -103,6 +122,7 @@ int ipm_solve(qg_handle *h, double *xo, double *so, double *yo, double *zo, qg_i
     int rc = QG_OK;
     int ir_total = 0, nreg_total = 0, nfactor = 0, nsolve = 0, switch_iter = -1;
     double ms_factor = 0, ms_solve = 0, ms_cone = 0;
+    SolveWork work;
     std::vector<double> step_ms, step32, step64;
     bool fp64_only = st.precision != QG_FP32_IR;
     double scal[NSCAL];
@@ -126,13 +146,13 @@ int ipm_solve(qg_handle *h, double *xo, double *so, double *yo, double *zo, qg_i
         QG_HIP(h, hipMemcpyAsync(d.rhs.p + n, d.b.p, sizeof(double) * p, hipMemcpyDeviceToDevice, h->stream));
         QG_HIP(h, hipMemcpyAsync(d.rhs.p + n + p, d.h.p, sizeof(double) * m, hipMemcpyDeviceToDevice, h->stream));
         bool failed = false;
-        if ((rc = solve_with(h, d.rhs.p, d.sol.p, prec, &ir_total, &failed, ev, &ms_solve))) return fail(rc);
+        if ((rc = solve_with(h, d.rhs.p, d.sol.p, prec, &ir_total, &failed, ev, &ms_solve, work))) return fail(rc);
         ms_factor += elapsed(ev.e[2], ev.e[3]);
         if (failed && prec == QG_FP32_IR) {
             prec = QG_FP64;
             if ((rc = launch_factor(h, prec))) return fail(rc);
             ++nfactor;
-            if ((rc = solve_with(h, d.rhs.p, d.sol.p, prec, &ir_total, &failed, ev, &ms_solve))) return fail(rc);
+            if ((rc = solve_with(h, d.rhs.p, d.sol.p, prec, &ir_total, &failed, ev, &ms_solve, work))) return fail(rc);
         }
         ++nsolve;
         QG_HIP(h, hipMemcpyAsync(d.x.p, d.sol.p, sizeof(double) * n, hipMemcpyDeviceToDevice, h->stream));
@@ -185,7 +205,7 @@ int ipm_solve(qg_handle *h, double *xo, double *so, double *yo, double *zo, qg_i
             // affine direction
             if ((rc = launch_build_rhs(h, d.s.p, 1.0, d.rhs.p))) return fail(rc);
             bool failed = false, failed2 = false;
-            if ((rc = solve_with(h, d.rhs.p, dvec, prec, &ir_total, &failed, ev, &ms_solve))) return fail(rc);
+            if ((rc = solve_with(h, d.rhs.p, dvec, prec, &ir_total, &failed, ev, &ms_solve, work))) return fail(rc);
             ++nsolve;
             ms_factor += elapsed(ev.e[2], ev.e[3]);
             int nr = 0;
@@ -201,7 +221,7 @@ int ipm_solve(qg_handle *h, double *xo, double *so, double *yo, double *zo, qg_i
                 if ((rc = launch_corrector(h, d.dsa.p, dz_of, -1.0, nullptr, mu, d.t.p))) return fail(rc);
                 if ((rc = launch_build_rhs(h, d.t.p, -1.0, d.rhs.p))) return fail(rc);
                 (void)hipEventRecord(ev.e[7], h->stream);
-                if ((rc = solve_with(h, d.rhs.p, dvec, prec, &ir_total, &failed2, ev, &ms_solve))) return fail(rc);
+                if ((rc = solve_with(h, d.rhs.p, dvec, prec, &ir_total, &failed2, ev, &ms_solve, work))) return fail(rc);
                 ++nsolve;
                 ms_cone += elapsed(ev.e[6], ev.e[7]);
             }
@@ -220,7 +240,7 @@ int ipm_solve(qg_handle *h, double *xo, double *so, double *yo, double *zo, qg_i
         if ((rc = launch_update(h, dvec, d.ds.p, st.step_frac, d.alpha.p + 1))) return fail(rc);
         (void)hipEventRecord(ev.e[1], h->stream);
         QG_HIP(h, hipEventSynchronize(ev.e[1]));
-        ms_cone += elapsed(ev.e[6], ev.e[7]);
+        ms_cone += elapsed(ev.e[6], ev.e[1]);
         const double sm = elapsed(ev.e[0], ev.e[1]);
         step_ms.push_back(sm);
         (prec == QG_FP32_IR ? step32 : step64).push_back(sm);
@@ -261,6 +281,10 @@ int ipm_solve(qg_handle *h, double *xo, double *so, double *yo, double *zo, qg_i
         info->ms_step_median = median(step_ms);
         info->ms_step_median_fp32 = median(step32);
         info->ms_step_median_fp64 = median(step64);
+        info->ms_step_p90 = percentile(step_ms, 0.9);
+        info->ntrisolve[0] = work.tri[0];
+        info->ntrisolve[1] = work.tri[1];
+        info->nresidual = work.residuals;
         info->nnz_L = h->sym.nnz_L;
         info->factor_flops = h->sym.flops;
         prof_collect(h, info->kern_launches, info->kern_ms, info->kern_flops);

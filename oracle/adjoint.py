@@ -34,6 +34,12 @@ dL = u'[rhs] with the dA and dG terms above)
 
     dL/dA_ij = -(y_i u_x,j + u_y,i x_j),   dL/dG_ij = -(z_i u_x,j + u_z,i x_j).
 
+A loss of the whole solution L(x*, y*, z*, s*) enters through g = [g_x; g_y;
+g_z] and g_s: the primal equality gives ds = dh - G dx - dG x exactly, so
+g_s' ds = g_s' dh - (G' g_s)' dx - g_s' dG x; with u solving
+K_fin u = [g_x - G' g_s; g_y; g_z] the formulas above hold, plus g_s in
+dL/dh and -g_s,i x_j in dL/dG_ij.
+
 ``backward`` uses the sparse factorization with FP64 refinement;
 ``backward_dense`` forms K_fin densely and calls numpy's dense solver.
 
@@ -86,9 +92,11 @@ def final_factor(prob, result) -> KKTFactor:
     return result._final_factor
 
 
-def _grads(prob, x, y, z, u):
+def _grads(prob, x, y, z, u, gs=None):
     n, p = prob.n, prob.p
     ux, uy, uz = u[:n], u[n:n + p], u[n + p:]
+    if gs is not None:
+        uz = uz + gs                 # ds = dh - G dx - dG x: g_s joins u_z in dL/dh and dL/dG
     Pu = prob.P.tocoo()              # tocoo() of a CSC matrix keeps the CSC entry order
     dP = np.where(Pu.row == Pu.col, -ux[Pu.row] * x[Pu.col],
                   -(ux[Pu.row] * x[Pu.col] + ux[Pu.col] * x[Pu.row]))
@@ -98,18 +106,24 @@ def _grads(prob, x, y, z, u):
     return dict(dc=-ux, db=uy.copy(), dh=uz.copy(), dP=dP, dA=dA, dG=dG, u=u)
 
 
-def backward(prob, result, g, ir_max: int = 10):
-    """Adjoint solve on the stored final factorization (+ FP64 refinement)."""
+def _rhs(prob, g, gy, gz, gs):
+    gx = np.asarray(g, dtype=float)
+    if gs is not None:
+        gx = gx - prob.G.T @ gs
+    return np.concatenate([gx, np.zeros(prob.p) if gy is None else gy, np.zeros(prob.m) if gz is None else gz])
+
+
+def backward(prob, result, g, ir_max: int = 10, gy=None, gz=None, gs=None):
+    """Adjoint solve on the stored final factorization (+ FP64 refinement);
+    g = dL/dx*, and optionally gy, gz, gs = dL/dy*, dL/dz*, dL/ds*."""
     F = final_factor(prob, result)
-    rhs = np.concatenate([g, np.zeros(prob.p + prob.m)])
-    u, _ = F.solve(rhs, ir_max=ir_max)
-    return _grads(prob, result.x, result.y, result.z, u)
+    u, _ = F.solve(_rhs(prob, g, gy, gz, gs), ir_max=ir_max)
+    return _grads(prob, result.x, result.y, result.z, u, gs)
 
 
-def backward_dense(prob, result, g):
+def backward_dense(prob, result, g, gy=None, gz=None, gs=None):
     """Same gradients from a dense FP64 solve with K_fin."""
     orth, blocks = final_block(prob, result.s, result.z)
     K = _kkt.full_from_upper(_kkt.kkt_upper(prob, orth, blocks)).toarray()
-    rhs = np.concatenate([g, np.zeros(prob.p + prob.m)])
-    u = np.linalg.solve(K, rhs)
-    return _grads(prob, result.x, result.y, result.z, u)
+    u = np.linalg.solve(K, _rhs(prob, g, gy, gz, gs))
+    return _grads(prob, result.x, result.y, result.z, u, gs)

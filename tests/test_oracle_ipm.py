@@ -300,3 +300,47 @@ def test_adjoint_vs_central_finite_differences():
             xp, xm = vals
             fd = 0.5 * (xp - xm) @ (xp + xm - 2 * xref) / (2 * hstep)
             assert abs(gr[key][t] - fd) <= 1e-3 * max(abs(fd), 1e-3), (mat, t, gr[key][t], fd)
+
+
+def test_adjoint_through_the_whole_solution_vs_central_finite_differences():
+    """L = 1/2 |x* - xr|^2 + 1/2 |y* - yr|^2 + 1/2 |z* - zr|^2 + 1/2 |s* - sr|^2: the adjoint
+    with g_y, g_z and g_s against central differences in c, b, h, A and G."""
+    prob = problems.lasso(rows=80, cols=40, density=0.1, seed=12)
+    st = tight()
+    base = ipm.solve(prob, st)
+    rng = np.random.default_rng(14)
+    ref = {k: rng.standard_normal(len(getattr(base, k))) for k in ("x", "y", "z", "s")}
+    gr = adjoint.backward(prob, base, base.x - ref["x"], gy=base.y - ref["y"], gz=base.z - ref["z"],
+                          gs=base.s - ref["s"])
+
+    def loss_diff(rp, rm):
+        # L(+) - L(-) = sum over the blocks of 1/2 (v+ - v-)'(v+ + v- - 2 ref)
+        return sum(0.5 * (getattr(rp, k) - getattr(rm, k)) @ (getattr(rp, k) + getattr(rm, k) - 2 * ref[k])
+                   for k in ("x", "y", "z", "s"))
+
+    hstep = 1e-6
+    checks = []
+    for vec, key in (("c", "dc"), ("h", "dh"), ("b", "db")):
+        data = getattr(prob, vec)
+        top = np.argsort(-np.abs(gr[key]))[:2]
+        for j in np.unique(np.concatenate([rng.choice(len(data), size=2, replace=False), top])):
+            res = []
+            for sgn in (+1, -1):
+                pr = problems.Problem(**{**prob.__dict__})
+                d2 = data.copy(); d2[j] += sgn * hstep
+                setattr(pr, vec, d2)
+                res.append(ipm.solve(pr, st))
+            checks.append((vec, j, gr[key][j], loss_diff(*res) / (2 * hstep)))
+    for mat, key in (("A", "dA"), ("G", "dG")):
+        M = getattr(prob, mat)
+        top = np.argsort(-np.abs(gr[key]))[:2]
+        for t in np.unique(np.concatenate([rng.choice(M.nnz, size=2, replace=False), top])):
+            res = []
+            for sgn in (+1, -1):
+                pr = problems.Problem(**{**prob.__dict__})
+                M2 = M.copy(); M2.data[t] += sgn * hstep
+                setattr(pr, mat, M2)
+                res.append(ipm.solve(pr, st))
+            checks.append((mat, t, gr[key][t], loss_diff(*res) / (2 * hstep)))
+    for what, j, adj, fd in checks:
+        assert abs(adj - fd) <= 1e-3 * max(abs(fd), 1e-3), (what, j, adj, fd)

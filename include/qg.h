@@ -218,6 +218,18 @@ int qg_solve(qg_handle *h, double *x, double *s, double *y, double *z, qg_info *
 int qg_backward(qg_handle *h, const double *dl_dx, double *dl_dc, double *dl_dh,
                 double *dl_db, double *dl_dPval, double *dl_dAval, double *dl_dGval);
 
+/*
+ * The same for a loss of the whole solution L(x*, y*, z*, s*): dl_dy (p),
+ * dl_dz (m), dl_ds (m) are device pointers, NULL meaning zero.  With the
+ * primal equality ds = dh - G dx - dG x, u solves
+ * K_fin u = [dl_dx - G' dl_ds; dl_dy; dl_dz] and the formulas of qg_backward
+ * hold with u_z + dl_ds in place of u_z in dl_dh and dl_dGval.  qg_backward
+ * is this call with the three NULL.  Errors as for qg_backward.
+ */
+int qg_backward_full(qg_handle *h, const double *dl_dx, const double *dl_dy, const double *dl_dz,
+                     const double *dl_ds, double *dl_dc, double *dl_dh, double *dl_db,
+                     double *dl_dPval, double *dl_dAval, double *dl_dGval);
+
 /* Host copies of the analysis; valid until qg_cleanup. */
 int qg_get_pattern(const qg_handle *h, qg_pattern *out);
 

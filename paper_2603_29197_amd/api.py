@@ -158,17 +158,22 @@ class Solver:
         self.info = info.as_dict()
         return x[:self.n], s[:self.m], y[:self.p], z[:self.m], self.info
 
-    def backward(self, dl_dx, want_P: bool = True, want_A: bool = False, want_G: bool = False):
-        """Gradients of L(x*) with dl_dx = dL/dx*: dc, dh, db, and the values of P, A and G on
-        their patterns (dP, dA, dG; None unless asked for and the matrix has entries)."""
+    def backward(self, dl_dx, want_P: bool = True, want_A: bool = False, want_G: bool = False,
+                 dl_dy=None, dl_dz=None, dl_ds=None):
+        """Gradients of L(x*, y*, z*, s*) with dl_dx = dL/dx* (and optionally dL/dy*, dL/dz*,
+        dL/ds*): dc, dh, db, and the values of P, A and G on their patterns (dP, dA, dG; None
+        unless asked for and the matrix has entries)."""
         t = self.torch
         dl_dx = dl_dx.to(device="cuda", dtype=t.float64).contiguous()
+        extra = [None if v is None else v.to(device="cuda", dtype=t.float64).contiguous()
+                 for v in (dl_dy, dl_dz, dl_ds)]
         dc, dh, db = self._empty(self.n), self._empty(self.m), self._empty(self.p)
         nnz = {k: int(getattr(self.prob, k).nnz) for k in ("P", "A", "G")}
         want = {"P": want_P, "A": want_A, "G": want_G}
         out = {k: (self._empty(nnz[k]) if (want[k] and nnz[k] > 0) else None) for k in ("P", "A", "G")}
-        check(lib().qg_backward(self.handle, self._vp(dl_dx), self._vp(dc), self._vp(dh), self._vp(db),
-                                self._vp(out["P"]), self._vp(out["A"]), self._vp(out["G"])), "qg_backward")
+        check(lib().qg_backward_full(self.handle, self._vp(dl_dx), *[self._vp(v) for v in extra],
+                                     self._vp(dc), self._vp(dh), self._vp(db), self._vp(out["P"]),
+                                     self._vp(out["A"]), self._vp(out["G"])), "qg_backward_full")
         res = dict(dc=dc[:self.n], dh=dh[:self.m], db=db[:self.p])
         for k in ("P", "A", "G"):
             res["d" + k] = None if out[k] is None else out[k][:nnz[k]]
@@ -250,6 +255,7 @@ def _autograd_function():
             if not solver.settings.differentiable:
                 solver.set_settings(differentiable=1)
             x, s, y, z, info = solver.solve()
+            solver.last = (x, s, y, z, info)
             ctx.solver = solver
             ctx.has = (Pval is not None, Aval is not None, Gval is not None)
             return x.clone()
@@ -262,17 +268,37 @@ def _autograd_function():
             extra = (clone(g["dA"], hA), clone(g["dG"], hG))[:ctx.n_extra]
             return (g["dc"].clone(), g["dh"].clone(), g["db"].clone(), clone(g["dP"], hP), None) + extra
 
-    return QGSolve
+    class QGSolveAll(torch.autograd.Function):
+        """(x*, y*, z*, s*) = QGSolveAll.apply(c, h, b, Pval, solver[, Aval, Gval]): as QGSolve,
+        for losses of the whole solution (one adjoint solve with the four output gradients)."""
+
+        @staticmethod
+        def forward(ctx, c, h, b, Pval, solver, *AG):
+            x = QGSolve.forward(ctx, c, h, b, Pval, solver, *AG)
+            _, s, y, z, _ = solver.last
+            return x, y.clone(), z.clone(), s.clone()
+
+        @staticmethod
+        def backward(ctx, gx, gy, gz, gs):
+            hP, hA, hG = ctx.has
+            g = ctx.solver.backward(gx, want_P=hP, want_A=hA, want_G=hG, dl_dy=gy, dl_dz=gz, dl_ds=gs)
+            clone = lambda v, has: v.clone() if (has and v is not None) else None
+            extra = (clone(g["dA"], hA), clone(g["dG"], hG))[:ctx.n_extra]
+            return (g["dc"].clone(), g["dh"].clone(), g["db"].clone(), clone(g["dP"], hP), None) + extra
+
+    return QGSolve, QGSolveAll
 
 
 class _Lazy:
-    def __init__(self):
+    def __init__(self, which: int):
+        self.which = which
         self.f = None
 
     def apply(self, *args):
         if self.f is None:
-            self.f = _autograd_function()
+            self.f = _autograd_function()[self.which]
         return self.f.apply(*args)
 
 
-QGSolve = _Lazy()
+QGSolve = _Lazy(0)
+QGSolveAll = _Lazy(1)

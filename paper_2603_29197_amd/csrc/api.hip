@@ -45,18 +45,51 @@ __global__ void dM_kernel(int32_t n, const int64_t *__restrict__ Mp, const int32
     }
 }
 
-int adjoint_backward(qg_handle *h, const double *g, double *dc, double *dh, double *db, double *dP,
-                     double *dA, double *dG) {
+// rhs_x[j] = g[j] - sum_i G_ij gs[i] (G' g_s, G's values read from the K values), one thread per column
+__global__ void gx_minus_gtgs_kernel(int32_t n, const int64_t *__restrict__ Gp, const int32_t *__restrict__ Gi,
+                                     const int64_t *__restrict__ posG, const double *__restrict__ kval,
+                                     const double *__restrict__ g, const double *__restrict__ gs,
+                                     double *__restrict__ out) {
+    const int32_t j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= n) return;
+    double acc = 0.0;
+    for (int64_t t = Gp[j]; t < Gp[j + 1]; ++t) acc += kval[posG[t]] * gs[Gi[t]];
+    out[j] = g[j] - acc;
+}
+
+int adjoint_backward(qg_handle *h, const double *g, const double *gy, const double *gz, const double *gs,
+                     double *dc, double *dh, double *db, double *dP, double *dA, double *dG) {
     Device &d = h->d;
     const int32_t n = h->n, p = h->p, m = h->m;
     int rc;
-    QG_HIP(h, hipMemcpyAsync(d.rhs.p, g, sizeof(double) * n, hipMemcpyDeviceToDevice, h->stream));
-    if ((rc = launch_fill(h, p + m, 0.0, d.rhs.p + n))) return rc;
+    // rhs = [g - G' g_s; g_y; g_z]  (ds = dh - G dx - dG x carries g_s)
+    if (gs && m > 0 && !h->pp.G.rowind.empty()) {
+        gx_minus_gtgs_kernel<<<(n + 255) / 256, 256, 0, h->stream>>>(n, d.Gp.p, d.Gi.p, d.posG.p, d.kval.p, g, gs,
+                                                                      d.rhs.p);
+        QG_HIP(h, hipGetLastError());
+    } else {
+        QG_HIP(h, hipMemcpyAsync(d.rhs.p, g, sizeof(double) * n, hipMemcpyDeviceToDevice, h->stream));
+    }
+    if (p > 0) {
+        if (gy) QG_HIP(h, hipMemcpyAsync(d.rhs.p + n, gy, sizeof(double) * p, hipMemcpyDeviceToDevice, h->stream));
+        else if ((rc = launch_fill(h, p, 0.0, d.rhs.p + n))) return rc;
+    }
+    if (m > 0) {
+        if (gz) QG_HIP(h, hipMemcpyAsync(d.rhs.p + n + p, gz, sizeof(double) * m, hipMemcpyDeviceToDevice, h->stream));
+        else if ((rc = launch_fill(h, m, 0.0, d.rhs.p + n + p))) return rc;
+    }
     if ((rc = refined_solve(h, d.rhs.p, d.sol.p, QG_FP64, 10, nullptr))) return rc;
     const double *u = d.sol.p;
+    // u_z + g_s: the z-side factor of dL/dh and dL/dG (d.res is free after the refined solve)
+    const double *uz = u + n + p;
+    if (gs && m > 0) {
+        QG_HIP(h, hipMemcpyAsync(d.res.p, uz, sizeof(double) * m, hipMemcpyDeviceToDevice, h->stream));
+        if ((rc = launch_axpy(h, m, 1.0, gs, d.res.p))) return rc;
+        uz = d.res.p;
+    }
     if (dc && (rc = launch_scale_copy(h, n, -1.0, u, dc))) return rc;
     if (db && p > 0) QG_HIP(h, hipMemcpyAsync(db, u + n, sizeof(double) * p, hipMemcpyDeviceToDevice, h->stream));
-    if (dh && m > 0) QG_HIP(h, hipMemcpyAsync(dh, u + n + p, sizeof(double) * m, hipMemcpyDeviceToDevice, h->stream));
+    if (dh && m > 0) QG_HIP(h, hipMemcpyAsync(dh, uz, sizeof(double) * m, hipMemcpyDeviceToDevice, h->stream));
     if (dP && !h->pp.P.rowind.empty()) {
         dP_kernel<<<(n + 255) / 256, 256, 0, h->stream>>>(n, d.Pp.p, d.Pi.p, u, d.x.p, dP);
         QG_HIP(h, hipGetLastError());
@@ -66,7 +99,7 @@ int adjoint_backward(qg_handle *h, const double *g, double *dc, double *dh, doub
         QG_HIP(h, hipGetLastError());
     }
     if (dG && !h->pp.G.rowind.empty()) {
-        dM_kernel<<<(n + 255) / 256, 256, 0, h->stream>>>(n, d.Gp.p, d.Gi.p, d.z.p, u + n + p, u, d.x.p, dG);
+        dM_kernel<<<(n + 255) / 256, 256, 0, h->stream>>>(n, d.Gp.p, d.Gi.p, d.z.p, uz, u, d.x.p, dG);
         QG_HIP(h, hipGetLastError());
     }
     QG_HIP(h, hipStreamSynchronize(h->stream));
@@ -121,6 +154,7 @@ static int allocate_device(qg_handle *h) {
     UP(Ai, h->pp.A.rowind);
     UP(Gp, h->pp.G.colptr);
     UP(Gi, h->pp.G.rowind);
+    UP(posG, kp.posG);
 #undef UP
     const size_t N = (size_t)h->N, m = (size_t)h->m;
     if ((rc = dalloc(h, d.front64, (size_t)pl.front_total))) return rc;
@@ -371,9 +405,16 @@ int qg_solve(qg_handle *h, double *x, double *s, double *y, double *z, qg_info *
 
 int qg_backward(qg_handle *h, const double *dl_dx, double *dl_dc, double *dl_dh, double *dl_db,
                 double *dl_dPval, double *dl_dAval, double *dl_dGval) {
+    return qg_backward_full(h, dl_dx, nullptr, nullptr, nullptr, dl_dc, dl_dh, dl_db, dl_dPval, dl_dAval,
+                            dl_dGval);
+}
+
+int qg_backward_full(qg_handle *h, const double *dl_dx, const double *dl_dy, const double *dl_dz,
+                     const double *dl_ds, double *dl_dc, double *dl_dh, double *dl_db, double *dl_dPval,
+                     double *dl_dAval, double *dl_dGval) {
     if (!h || !dl_dx) return QG_ERR_ARG;
     if (!h->solved || !h->final_factor) return QG_ERR_STATE;
-    return adjoint_backward(h, dl_dx, dl_dc, dl_dh, dl_db, dl_dPval, dl_dAval, dl_dGval);
+    return adjoint_backward(h, dl_dx, dl_dy, dl_dz, dl_ds, dl_dc, dl_dh, dl_db, dl_dPval, dl_dAval, dl_dGval);
 }
 
 int qg_get_pattern(const qg_handle *h, qg_pattern *out) {

@@ -56,7 +56,7 @@ void dfree_all(qg_handle *h) {
     Device &d = h->d;
     dfree(d.kval); dfree(d.blk33); dfree(d.blk_off); dfree(d.soc_off); dfree(d.kr_ptr);
     dfree(d.kr_col); dfree(d.kr_val); dfree(d.c); dfree(d.b); dfree(d.h); dfree(d.Pp); dfree(d.Pi);
-    dfree(d.Ap); dfree(d.Ai); dfree(d.Gp); dfree(d.Gi);
+    dfree(d.Ap); dfree(d.Ai); dfree(d.Gp); dfree(d.Gi); dfree(d.posG);
     dfree(d.perm); dfree(d.iperm);
     dfree(d.sn_first); dfree(d.sn_rows); dfree(d.task_sn); dfree(d.task_col);
     dfree(d.ctb_src); dfree(d.ch_ptr); dfree(d.ch_list);

@@ -90,6 +90,7 @@ struct Device {
     DBuf<double> c, b, h;
     DBuf<int64_t> Pp; DBuf<int32_t> Pi;   // P upper pattern (for dL/dP)
     DBuf<int64_t> Ap, Gp; DBuf<int32_t> Ai, Gi;   // A and G patterns (for dL/dA, dL/dG)
+    DBuf<int64_t> posG;         // position of each G entry among the K values (G' g_s in the adjoint)
     DBuf<int32_t> perm, iperm;
     // plan
     DBuf<int32_t> sn_first, sn_rows, task_sn, task_col, ch_ptr, ch_list, lvl_small_sn;
@@ -200,7 +201,7 @@ int factor_init_attributes(qg_handle *h);
 void prof_collect(qg_handle *h, int64_t *launches, double *ms, double *flops);
 
 int ipm_solve(qg_handle *h, double *x, double *s, double *y, double *z, qg_info *info);
-int adjoint_backward(qg_handle *h, const double *g, double *dc, double *dh, double *db, double *dP,
-                     double *dA, double *dG);
+int adjoint_backward(qg_handle *h, const double *g, const double *gy, const double *gz, const double *gs,
+                     double *dc, double *dh, double *db, double *dP, double *dA, double *dG);
 
 }  // namespace qg

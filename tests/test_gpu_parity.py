@@ -274,3 +274,50 @@ def test_autograd_function_constraint_values():
         print(f"[gpu] autograd {k} rel err {e:.2e}", flush=True)
         assert e <= 1e-5, (k, e)
     S.close()
+
+
+@pytest.mark.parametrize("name", ["small_qp", "lasso_s", "mixed_soc"])
+def test_backward_full_matches_oracle(name):
+    """A loss of the whole solution: dL/dx, dL/dy, dL/dz, dL/ds all nonzero."""
+    prob = SMALL[name]()
+    S = solver(prob, differentiable=1)
+    x, s, y, z, info = S.solve()
+    assert info["status"] == 1
+    ref = oracle_solution(name)
+    rng = np.random.default_rng(21)
+    g, gy, gz, gs = (rng.standard_normal(k) for k in (prob.n, prob.p, prob.m, prob.m))
+    gr = S.backward(dev(g), want_A=True, want_G=True, dl_dy=dev(gy), dl_dz=dev(gz), dl_ds=dev(gs))
+    want = oadj.backward_dense(prob, ref, g, gy=gy, gz=gz, gs=gs)
+    for k in ("dc", "dh", "db", "dP", "dA", "dG"):
+        if k in ("dP", "dA", "dG") and not getattr(prob, k[1]).nnz:
+            continue
+        a, b = host(gr[k]), want[k]
+        if b.size:
+            e = float(np.max(np.abs(a - b)) / max(1.0, np.max(np.abs(b))))
+            print(f"[gpu] {name} full {k} rel err {e:.2e}", flush=True)
+            assert e <= 1e-5, (k, e)
+    S.close()
+
+
+def test_autograd_whole_solution():
+    """QGSolveAll: a loss of (x, y, z, s) differentiated with respect to c, h, b and the G values."""
+    import paper_2603_29197_amd as qg
+    prob = problems.lasso(rows=120, cols=60, density=0.1, seed=9)
+    S = solver(prob, differentiable=1)
+    c = torch.tensor(prob.c, device="cuda", requires_grad=True)
+    h = torch.tensor(prob.h, device="cuda", requires_grad=True)
+    b = torch.tensor(prob.b, device="cuda", requires_grad=True)
+    Gv = torch.tensor(prob.G.data, device="cuda", requires_grad=True)
+    x, y, z, s = qg.QGSolveAll.apply(c, h, b, None, S, None, Gv)
+    gen = torch.Generator(device="cuda").manual_seed(3)
+    refs = [torch.randn(v.shape[0], dtype=torch.float64, device="cuda", generator=gen) for v in (x, y, z, s)]
+    loss = sum(0.5 * ((v - r) ** 2).sum() for v, r in zip((x, y, z, s), refs))
+    loss.backward()
+    ref = oipm.solve(prob)
+    want = oadj.backward_dense(prob, ref, ref.x - host(refs[0]), gy=ref.y - host(refs[1]),
+                               gz=ref.z - host(refs[2]), gs=ref.s - host(refs[3]))
+    for got, k in ((c.grad, "dc"), (h.grad, "dh"), (b.grad, "db"), (Gv.grad, "dG")):
+        e = float(np.max(np.abs(host(got) - want[k])) / max(1.0, np.max(np.abs(want[k]))))
+        print(f"[gpu] autograd whole solution {k} rel err {e:.2e}", flush=True)
+        assert e <= 1e-5, (k, e)
+    S.close()

@@ -123,6 +123,24 @@ static int allocate_device(qg_handle *h) {
     UP(blk33, kp.blk33);
     UP(blk_off, kp.blk33_off);
     UP(soc_off, h->pp.soc_off);
+    {
+        std::vector<int32_t> big;
+        for (int32_t k = 0; k < h->pp.nsoc; ++k)
+            if (h->pp.soc_off[k + 1] - h->pp.soc_off[k] >= QBIG) big.push_back(k);
+        h->nbig = (int32_t)big.size();
+        UP(big_cones, big);
+        std::vector<int32_t> ccone;
+        std::vector<int64_t> cstart;
+        for (int32_t j = 0; j < h->nbig; ++j) {
+            const int64_t q = h->pp.soc_off[big[j] + 1] - h->pp.soc_off[big[j]];
+            for (int64_t t = 0; t < q * (q + 1) / 2; t += BIG_CHUNK) { ccone.push_back(j); cstart.push_back(t); }
+        }
+        if (ccone.size() > 0x7fffffffu) return QG_ERR_ARG;
+        h->nbigchunk = (int64_t)ccone.size();
+        UP(big_chunk_cone, ccone);
+        UP(big_chunk_start, cstart);
+        if ((rc = dalloc(h, d.bigsc, 2 * (size_t)h->nbig))) return rc;
+    }
     UP(sn_first, pl.sn_first);
     UP(sn_rows, pl.sn_rows);
     UP(task_sn, pl.task_sn);
@@ -193,7 +211,8 @@ static int allocate_device(qg_handle *h) {
     if ((rc = dalloc(h, d.alpha, 4))) return rc;
     if ((rc = dalloc(h, d.amin, 4))) return rc;
     // per-block partials: the sparse residual kernels use 256 / RL rows per block
-    const size_t nblk = (N + 256 / RL - 1) / (256 / RL) + (size_t)((h->pp.l + h->pp.nsoc + 255) / 256) + 1;
+    const size_t nblk = (N + 256 / RL - 1) / (256 / RL) + (size_t)((h->pp.l + h->pp.nsoc + 255) / 256) +
+                        (size_t)((h->nbig + 3) / 4) + 1;
     if ((rc = dalloc(h, d.partials, nblk * NSCAL))) return rc;
     return QG_OK;
 }

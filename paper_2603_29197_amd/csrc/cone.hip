@@ -1,6 +1,7 @@
 // Cone operations of the Newton step (paper Sec. 2.1: Jordan products and
 // Nesterov-Todd scalings, implemented per cone and run in parallel, Sec. 2.3):
-// one thread per orthant entry, one thread per second-order cone.
+// one thread per orthant entry, one thread per second-order cone of fewer
+// than QBIG entries, one wavefront per larger cone (the *_big kernels).
 //
 // Formulas (standard SOC Jordan algebra; NT scaling as in Vandenberghe's
 // cone-QP method, which the paper's solver implements):
@@ -58,6 +59,7 @@ __global__ void scaling_kernel(int32_t l, int32_t nsoc, const int32_t *__restric
     const int32_t k = t - l;
     if (k >= nsoc) return;
     const int32_t off = soc_off[k], q = soc_off[k + 1] - off;
+    if (q >= QBIG) return;
     const double *sk = s + off, *zk = z + off;
     double *wb = wbar + (off - l);
     const int64_t base = l + blk_off[k];
@@ -134,6 +136,7 @@ __global__ void cone_op_kernel(int op, int32_t l, int32_t nsoc, const int32_t *_
     const int32_t k = t - l;
     if (k >= nsoc) return;
     const int32_t off = soc_off[k], q = soc_off[k + 1] - off;
+    if (q >= QBIG) return;
     const double *uk = u + off;
     double *ok = out + off;
     const double *wb = wbar + (off - l);
@@ -176,6 +179,7 @@ __global__ void ds_kernel(int32_t l, int32_t nsoc, const int32_t *__restrict__ s
     const int32_t k = t - l;
     if (k >= nsoc) return;
     const int32_t off = soc_off[k], q = soc_off[k + 1] - off;
+    if (q >= QBIG) return;
     const double *wb = wbar + (off - l);
     double wu = 0.0;
     for (int32_t a = 0; a < q; ++a) wu += wb[a] * dz[off + a];
@@ -215,6 +219,7 @@ __global__ void corrector_kernel(int32_t l, int32_t nsoc, const int32_t *__restr
     const int32_t k = t - l;
     if (k >= nsoc) return;
     const int32_t off = soc_off[k], q = soc_off[k + 1] - off;
+    if (q >= QBIG) return;
     const double *wb = wbar + (off - l);
     const double bt = beta[k];
     const double *lk = lam + off;
@@ -268,7 +273,7 @@ __global__ void step_kernel(int32_t l, int32_t nsoc, const int32_t *__restrict__
     double a = INFINITY;
     if (t < l) {
         if (du[t] < 0.0) a = -u[t] / du[t];
-    } else if (t - l < nsoc) {
+    } else if (t - l < nsoc && soc_off[t - l + 1] - soc_off[t - l] < QBIG) {
         const int32_t k = t - l;
         const int32_t off = soc_off[k], q = soc_off[k + 1] - off;
         const double *uk = u + off, *dk = du + off;
@@ -301,7 +306,7 @@ __global__ void __launch_bounds__(256) lmin_kernel(int32_t l, int32_t nsoc, cons
     double v = -INFINITY;
     if (t < l) {
         v = -u[t];
-    } else if (t - l < nsoc) {
+    } else if (t - l < nsoc && soc_off[t - l + 1] - soc_off[t - l] < QBIG) {
         const int32_t k = t - l;
         const int32_t off = soc_off[k], q = soc_off[k + 1] - off;
         double n1 = 0.0;
@@ -329,6 +334,309 @@ __global__ void add_e_kernel(int32_t l, int32_t nsoc, const int32_t *__restrict_
     else if (t - l < nsoc) u[soc_off[t - l]] += c;
 }
 
+// ---------------------------------------------------------------------------
+// Cones with q >= QBIG: one wavefront per cone.  Lane a handles entries a,
+// a + 64, ...; every inner product is a butterfly sum, after which all lanes
+// hold the same value.  Same formulas as the per-thread kernels above.
+// ---------------------------------------------------------------------------
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// wavefront index among the big cones (4 wavefronts per 256-thread block)
+__device__ inline int32_t big_wave() { return (int32_t)(blockIdx.x * 4 + (threadIdx.x >> 6)); }
+
+// s'Js over the tail as sqrt((u0 - |u1|)(u0 + |u1|))
+__device__ inline double wave_jnorm(const double *u, int32_t q, int lane) {
+    double t = 0.0;
+    for (int32_t a = 1 + lane; a < q; a += 64) t += u[a] * u[a];
+    const double n1 = sqrt(wave_sum(t));
+    return sqrt((u[0] - n1) * (u[0] + n1));
+}
+
+// NT scaling of a big cone (wb, beta, lam); its (3,3) block is written by block_big.
+// block == 1 stores the two sums block_big needs for -sym(Arw(z)^-1 Arw(s)) instead.
+__global__ void __launch_bounds__(256) scaling_big(int32_t l, int32_t nbig, const int32_t *__restrict__ big,
+                                                   const int32_t *__restrict__ soc_off, const double *__restrict__ s,
+                                                   const double *__restrict__ z, double *__restrict__ wbar,
+                                                   double *__restrict__ beta, double *__restrict__ lam,
+                                                   double *__restrict__ bigsc, int block) {
+    const int32_t gw = big_wave();
+    if (gw >= nbig) return;
+    const int lane = threadIdx.x & 63;
+    const int32_t k = big[gw];
+    const int32_t off = soc_off[k], q = soc_off[k + 1] - off;
+    const double *sk = s + off, *zk = z + off;
+    if (block == 1) {
+        double zz = 0.0, zs = 0.0;
+        for (int32_t a = 1 + lane; a < q; a += 64) { zz += zk[a] * zk[a]; zs += zk[a] * sk[a]; }
+        zz = wave_sum(zz);
+        zs = wave_sum(zs);
+        if (lane == 0) { bigsc[2 * gw] = zz; bigsc[2 * gw + 1] = zs; }
+        return;
+    }
+    const double sn = wave_jnorm(sk, q, lane), zn = wave_jnorm(zk, q, lane);
+    double dot = 0.0;
+    for (int32_t a = lane; a < q; a += 64) dot += (zk[a] / zn) * (sk[a] / sn);
+    dot = wave_sum(dot);
+    const double gamma = sqrt((1.0 + dot) * 0.5);
+    // wb[a] from (s, z): the lanes never read entries of wbar written by other lanes
+    auto wbv = [&](int32_t a) {
+        const double zb = zk[a] / zn, sb = sk[a] / sn;
+        return (sb + (a == 0 ? zb : -zb)) / (2.0 * gamma);
+    };
+    double *wb = wbar + (off - l);
+    for (int32_t a = lane; a < q; a += 64) wb[a] = wbv(a);
+    const double bt = sqrt(sn / zn);
+    if (lane == 0) beta[k] = bt;
+    if (lam) {
+        // lam = bt Wb z
+        const double w0 = wbv(0);
+        double w1z1 = 0.0;
+        for (int32_t a = 1 + lane; a < q; a += 64) w1z1 += wbv(a) * zk[a];
+        w1z1 = wave_sum(w1z1);
+        const double coef = zk[0] + w1z1 / (1.0 + w0);
+        double *lk = lam + off;
+        if (lane == 0) lk[0] = bt * (w0 * zk[0] + w1z1);
+        for (int32_t a = 1 + lane; a < q; a += 64) lk[a] = bt * (zk[a] + wbv(a) * coef);
+    }
+}
+
+// (3,3) block entries of the big cones, BIG_CHUNK entries of one cone per
+// workgroup (the host lists the chunks): entry t of a cone is (arow, bcol) of
+// its upper triangle in column order, t = bcol (bcol + 1) / 2 + arow, so the
+// reads of blk33 are contiguous.  block 0: -W'W = -beta^2 (2 wb wb' - J);
+// block 1: -(H + H')/2 with d H = d Arw(z)^-1 Arw(s), d = z0^2 - |z1|^2:
+//   (0,0) z0 s0 - z1's1; (0,j) z0 sj - s0 zj; (i,0) -zi s0 + (d/z0) si + zi z1's1/z0;
+//   (i,j) -zi sj + [i=j] (d/z0) s0 + zi zj s0/z0.
+__global__ void __launch_bounds__(256) block_big(int32_t l, const int32_t *__restrict__ big,
+                                                 const int32_t *__restrict__ chunk_cone,
+                                                 const int64_t *__restrict__ chunk_start,
+                                                 const int32_t *__restrict__ soc_off,
+                                                 const int64_t *__restrict__ blk_off,
+                                                 const int64_t *__restrict__ blk33, const double *__restrict__ s,
+                                                 const double *__restrict__ z, const double *__restrict__ wbar,
+                                                 const double *__restrict__ beta, const double *__restrict__ bigsc,
+                                                 double *__restrict__ kval, int block) {
+    const int32_t j = chunk_cone[blockIdx.x];
+    const int64_t st = chunk_start[blockIdx.x];
+    const int32_t k = big[j];
+    const int32_t off = soc_off[k], q = soc_off[k + 1] - off;
+    const int64_t ne = (int64_t)q * (q + 1) / 2;
+    const int64_t base = l + blk_off[k];
+    const double *sk = s + off, *zk = z + off;
+    const double *wb = wbar + (off - l);
+    const double b2 = block == 1 ? 0.0 : beta[k] * beta[k];
+    const double z0 = zk[0], s0 = sk[0];
+    const double zz = block == 1 ? bigsc[2 * j] : 0.0, zs = block == 1 ? bigsc[2 * j + 1] : 0.0;
+    const double dz = z0 * z0 - zz, dz0 = dz / z0;
+    for (int i = threadIdx.x; i < BIG_CHUNK; i += 256) {
+        const int64_t t = st + i;
+        if (t >= ne) break;
+        int32_t bcol = (int32_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+        while ((int64_t)(bcol + 1) * (bcol + 2) / 2 <= t) ++bcol;
+        while ((int64_t)bcol * (bcol + 1) / 2 > t) --bcol;
+        const int32_t arow = (int32_t)(t - (int64_t)bcol * (bcol + 1) / 2);
+        double v;
+        if (block == 1) {
+            const double za = zk[arow], sa = sk[arow], zb = zk[bcol], sb = sk[bcol];
+            double hsum;
+            if (bcol == 0) hsum = 2.0 * (z0 * s0 - zs);
+            else if (arow == 0) hsum = (z0 * sb - s0 * zb) + (-zb * s0 + dz0 * sb + zb * zs / z0);
+            else hsum = -(za * sb + zb * sa) + (arow == bcol ? 2.0 * dz0 * s0 : 0.0) + 2.0 * za * zb * s0 / z0;
+            v = -0.5 * hsum / dz;
+        } else {
+            const double jab = (arow == bcol) ? (arow == 0 ? 1.0 : -1.0) : 0.0;
+            v = -b2 * (2.0 * wb[arow] * wb[bcol] - jab);
+        }
+        kval[blk33[base + t]] = v;
+    }
+}
+
+// op: 0 W u, 1 W^-1 u, 2 W'W u, 3 u o v, 4 u \ v
+__global__ void __launch_bounds__(256) cone_op_big(int op, int32_t l, int32_t nbig, const int32_t *__restrict__ big,
+                                                   const int32_t *__restrict__ soc_off,
+                                                   const double *__restrict__ wbar, const double *__restrict__ beta,
+                                                   const double *__restrict__ u, const double *__restrict__ v,
+                                                   double *__restrict__ out) {
+    const int32_t gw = big_wave();
+    if (gw >= nbig) return;
+    const int lane = threadIdx.x & 63;
+    const int32_t k = big[gw];
+    const int32_t off = soc_off[k], q = soc_off[k + 1] - off;
+    const double *uk = u + off;
+    double *ok = out + off;
+    const double *wb = wbar + (off - l);
+    if (op == 0 || op == 1) {
+        const double sg = op ? -1.0 : 1.0;
+        double w1u1 = 0.0;
+        for (int32_t a = 1 + lane; a < q; a += 64) w1u1 += wb[a] * (sg * uk[a]);
+        w1u1 = wave_sum(w1u1);
+        const double u0 = uk[0];
+        const double coef = u0 + w1u1 / (1.0 + wb[0]);
+        const double scale = op ? 1.0 / beta[k] : beta[k];
+        if (lane == 0) ok[0] = scale * (wb[0] * u0 + w1u1);
+        for (int32_t a = 1 + lane; a < q; a += 64) ok[a] = scale * sg * (sg * uk[a] + wb[a] * coef);
+    } else if (op == 2) {
+        double wu = 0.0;
+        for (int32_t a = lane; a < q; a += 64) wu += wb[a] * uk[a];
+        wu = wave_sum(wu);
+        const double b2 = beta[k] * beta[k];
+        for (int32_t a = lane; a < q; a += 64) ok[a] = b2 * (2.0 * wb[a] * wu - (a == 0 ? uk[a] : -uk[a]));
+    } else if (op == 3) {
+        const double *vk = v + off;
+        double dot = 0.0;
+        for (int32_t a = lane; a < q; a += 64) dot += uk[a] * vk[a];
+        dot = wave_sum(dot);
+        const double u0 = uk[0], v0 = vk[0];
+        for (int32_t a = 1 + lane; a < q; a += 64) ok[a] = u0 * vk[a] + v0 * uk[a];
+        if (lane == 0) ok[0] = dot;
+    } else {
+        const double *vk = v + off;
+        double l1l1 = 0.0, l1v1 = 0.0;
+        for (int32_t a = 1 + lane; a < q; a += 64) { l1l1 += uk[a] * uk[a]; l1v1 += uk[a] * vk[a]; }
+        l1l1 = wave_sum(l1l1);
+        l1v1 = wave_sum(l1v1);
+        const double rho = uk[0] * uk[0] - l1l1;
+        const double x0 = (uk[0] * vk[0] - l1v1) / rho;
+        for (int32_t a = 1 + lane; a < q; a += 64) ok[a] = (vk[a] - x0 * uk[a]) / uk[0];
+        if (lane == 0) ok[0] = x0;
+    }
+}
+
+// ds = tsign * tvec - W'W dz
+__global__ void __launch_bounds__(256) ds_big(int32_t l, int32_t nbig, const int32_t *__restrict__ big,
+                                              const int32_t *__restrict__ soc_off, const double *__restrict__ wbar,
+                                              const double *__restrict__ beta, const double *__restrict__ tvec,
+                                              double tsign, const double *__restrict__ dz, double *__restrict__ ds) {
+    const int32_t gw = big_wave();
+    if (gw >= nbig) return;
+    const int lane = threadIdx.x & 63;
+    const int32_t k = big[gw];
+    const int32_t off = soc_off[k], q = soc_off[k + 1] - off;
+    const double *wb = wbar + (off - l);
+    double wu = 0.0;
+    for (int32_t a = lane; a < q; a += 64) wu += wb[a] * dz[off + a];
+    wu = wave_sum(wu);
+    const double b2 = beta[k] * beta[k];
+    for (int32_t a = lane; a < q; a += 64) {
+        const double whw = b2 * (2.0 * wb[a] * wu - (a == 0 ? dz[off + a] : -dz[off + a]));
+        ds[off + a] = tsign * tvec[off + a] - whw;
+    }
+}
+
+// t = W'(lam \ d), d = -lam o lam - (W^-1 ds_a) o (W dz_a) + sigma mu e (see corrector_kernel)
+__global__ void __launch_bounds__(256) corrector_big(int32_t l, int32_t nbig, const int32_t *__restrict__ big,
+                                                     const int32_t *__restrict__ soc_off,
+                                                     const double *__restrict__ wbar,
+                                                     const double *__restrict__ beta, const double *__restrict__ lam,
+                                                     const double *__restrict__ dsa, const double *__restrict__ dza,
+                                                     const unsigned long long *__restrict__ amin, double mu,
+                                                     double sigma_mu_fixed, double *__restrict__ tout) {
+    const int32_t gw = big_wave();
+    if (gw >= nbig) return;
+    double smu;
+    if (sigma_mu_fixed >= 0.0) {
+        smu = sigma_mu_fixed;
+    } else {
+        const double aa = fmin(1.0, fmin(__longlong_as_double((long long)amin[0]),
+                                         __longlong_as_double((long long)amin[1])));
+        const double om = 1.0 - aa;
+        smu = fmin(1.0, fmax(0.0, om * om * om)) * mu;
+    }
+    const int lane = threadIdx.x & 63;
+    const int32_t k = big[gw];
+    const int32_t off = soc_off[k], q = soc_off[k + 1] - off;
+    const double *wb = wbar + (off - l);
+    const double bt = beta[k];
+    const double *lk = lam + off;
+    const double *ua = dsa + off, *ub = dza + off;
+    double wu = 0.0, wv = 0.0, l1l1 = 0.0;
+    for (int32_t a = 1 + lane; a < q; a += 64) {
+        wu += wb[a] * ua[a];
+        wv += wb[a] * ub[a];
+        l1l1 += lk[a] * lk[a];
+    }
+    wu = wave_sum(wu);
+    wv = wave_sum(wv);
+    l1l1 = wave_sum(l1l1);
+    const double w0 = wb[0], l0 = lk[0];
+    const double ca = ua[0] - wu / (1.0 + w0);
+    const double cb = ub[0] + wv / (1.0 + w0);
+    const double A0 = (w0 * ua[0] - wu) / bt;
+    const double B0 = bt * (w0 * ub[0] + wv);
+    // tail entries of A = W^-1 ds_a, B = W dz_a and d
+    auto da_of = [&](int32_t a) {
+        const double Aa = (ua[a] - wb[a] * ca) / bt, Ba = bt * (ub[a] + wb[a] * cb);
+        return -(2.0 * l0 * lk[a]) - (A0 * Ba + B0 * Aa);
+    };
+    double ab = 0.0, l1d1 = 0.0;
+    for (int32_t a = 1 + lane; a < q; a += 64) {
+        ab += ((ua[a] - wb[a] * ca) / bt) * (bt * (ub[a] + wb[a] * cb));
+        l1d1 += lk[a] * da_of(a);
+    }
+    ab = A0 * B0 + wave_sum(ab);
+    l1d1 = wave_sum(l1d1);
+    const double d0 = -(l0 * l0 + l1l1) - ab + smu;
+    const double rho = l0 * l0 - l1l1;
+    const double x0 = (l0 * d0 - l1d1) / rho;
+    double wx = 0.0;
+    for (int32_t a = 1 + lane; a < q; a += 64) wx += wb[a] * ((da_of(a) - x0 * lk[a]) / l0);
+    wx = wave_sum(wx);
+    const double cx = x0 + wx / (1.0 + w0);
+    double *to = tout + off;
+    for (int32_t a = 1 + lane; a < q; a += 64) to[a] = bt * ((da_of(a) - x0 * lk[a]) / l0 + wb[a] * cx);
+    if (lane == 0) to[0] = bt * (w0 * x0 + wx);
+}
+
+// per-cone maximum step, min-reduced into amin (see step_kernel)
+__global__ void __launch_bounds__(256) step_big(int32_t nbig, const int32_t *__restrict__ big,
+                                                const int32_t *__restrict__ soc_off, const double *__restrict__ u,
+                                                const double *__restrict__ du, unsigned long long *__restrict__ amin) {
+    const int32_t gw = big_wave();
+    if (gw >= nbig) return;
+    const int lane = threadIdx.x & 63;
+    const int32_t k = big[gw];
+    const int32_t off = soc_off[k], q = soc_off[k + 1] - off;
+    const double *uk = u + off, *dk = du + off;
+    const double uJ = wave_jnorm(uk, q, lane);
+    double r1 = 0.0;
+    for (int32_t c = 1 + lane; c < q; c += 64) r1 += uk[c] / uJ * dk[c];
+    const double r0 = (uk[0] / uJ * dk[0] - wave_sum(r1)) / uJ;
+    const double coef = (r0 * uJ + dk[0]) / (1.0 + uk[0] / uJ);
+    double n1 = 0.0;
+    for (int32_t c = 1 + lane; c < q; c += 64) {
+        const double v = (dk[c] - coef * (uk[c] / uJ)) / uJ;
+        n1 += v * v;
+    }
+    const double den = sqrt(wave_sum(n1)) - r0;
+    if (lane == 0 && den > 0.0) atomicMin(amin, (unsigned long long)__double_as_longlong(1.0 / den));
+}
+
+// -lambda_min = |u1| - u0 per big cone, max-reduced per block into partials[blockIdx.x]
+__global__ void __launch_bounds__(256) lmin_big(int32_t nbig, const int32_t *__restrict__ big,
+                                                const int32_t *__restrict__ soc_off, const double *__restrict__ u,
+                                                double *__restrict__ partials) {
+    const int32_t gw = big_wave();
+    const int lane = threadIdx.x & 63;
+    double v = -INFINITY;
+    if (gw < nbig) {
+        const int32_t k = big[gw];
+        const int32_t off = soc_off[k], q = soc_off[k + 1] - off;
+        double n1 = 0.0;
+        for (int32_t a = 1 + lane; a < q; a += 64) n1 += u[off + a] * u[off + a];
+        v = -(u[off] - sqrt(wave_sum(n1)));
+    }
+    __shared__ double sh[4];
+    if (lane == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) partials[blockIdx.x] = nan_max(nan_max(sh[0], sh[1]), nan_max(sh[2], sh[3]));
+}
+
+static inline unsigned big_grid(qg_handle *h) { return (unsigned)((h->nbig + 3) / 4); }
+
 static inline unsigned cone_grid(qg_handle *h) {
     const int64_t units = (int64_t)h->pp.l + h->pp.nsoc;
     return (unsigned)std::max<int64_t>(1, (units + 255) / 256);
@@ -340,6 +648,16 @@ int launch_scaling(qg_handle *h, const double *s, const double *z, double *lam, 
                                                          d.blk33.p, s, z, d.w.p, d.wbar.p, d.beta.p, lam,
                                                          d.kval.p, block);
     QG_HIP(h, hipGetLastError());
+    if (h->nbig) {
+        scaling_big<<<big_grid(h), 256, 0, h->stream>>>(h->pp.l, h->nbig, d.big_cones.p, d.soc_off.p, s, z,
+                                                         d.wbar.p, d.beta.p, lam, d.bigsc.p, block);
+        QG_HIP(h, hipGetLastError());
+        block_big<<<(unsigned)h->nbigchunk, 256, 0, h->stream>>>(h->pp.l, d.big_cones.p, d.big_chunk_cone.p,
+                                                                  d.big_chunk_start.p, d.soc_off.p, d.blk_off.p,
+                                                                  d.blk33.p, s, z, d.wbar.p, d.beta.p, d.bigsc.p,
+                                                                  d.kval.p, block);
+        QG_HIP(h, hipGetLastError());
+    }
     return QG_OK;
 }
 
@@ -348,6 +666,11 @@ int launch_cone_op(qg_handle *h, int op, const double *u, const double *v, doubl
     cone_op_kernel<<<cone_grid(h), 256, 0, h->stream>>>(op, h->pp.l, h->pp.nsoc, d.soc_off.p, d.w.p, d.wbar.p,
                                                          d.beta.p, u, v, out);
     QG_HIP(h, hipGetLastError());
+    if (h->nbig) {
+        cone_op_big<<<big_grid(h), 256, 0, h->stream>>>(op, h->pp.l, h->nbig, d.big_cones.p, d.soc_off.p, d.wbar.p,
+                                                         d.beta.p, u, v, out);
+        QG_HIP(h, hipGetLastError());
+    }
     return QG_OK;
 }
 
@@ -356,6 +679,11 @@ int launch_ds_from_dz(qg_handle *h, const double *tvec, double tsign, const doub
     ds_kernel<<<cone_grid(h), 256, 0, h->stream>>>(h->pp.l, h->pp.nsoc, d.soc_off.p, d.w.p, d.wbar.p, d.beta.p,
                                                     tvec, tsign, dz, ds);
     QG_HIP(h, hipGetLastError());
+    if (h->nbig) {
+        ds_big<<<big_grid(h), 256, 0, h->stream>>>(h->pp.l, h->nbig, d.big_cones.p, d.soc_off.p, d.wbar.p, d.beta.p,
+                                                    tvec, tsign, dz, ds);
+        QG_HIP(h, hipGetLastError());
+    }
     return QG_OK;
 }
 
@@ -367,6 +695,11 @@ int launch_corrector(qg_handle *h, const double *dsa, const double *dza, double 
                                                            d.beta.p, d.lam.p, dsa, dza, d.amin.p, mu, sigma_mu,
                                                            t, d.alpha.p);
     QG_HIP(h, hipGetLastError());
+    if (h->nbig) {
+        corrector_big<<<big_grid(h), 256, 0, h->stream>>>(h->pp.l, h->nbig, d.big_cones.p, d.soc_off.p, d.wbar.p,
+                                                           d.beta.p, d.lam.p, dsa, dza, d.amin.p, mu, sigma_mu, t);
+        QG_HIP(h, hipGetLastError());
+    }
     return QG_OK;
 }
 
@@ -375,7 +708,9 @@ int launch_shift_interior(qg_handle *h, double *u) {
     Device &d = h->d;
     const unsigned g = cone_grid(h);
     lmin_kernel<<<g, 256, 0, h->stream>>>(h->pp.l, h->pp.nsoc, d.soc_off.p, u, d.partials.p);
-    finish_max<<<1, 1, 0, h->stream>>>(d.partials.p, (int32_t)g, d.scal.p + NSCAL + 2);
+    const unsigned gb = big_grid(h);
+    if (gb) lmin_big<<<gb, 256, 0, h->stream>>>(h->nbig, d.big_cones.p, d.soc_off.p, u, d.partials.p + g);
+    finish_max<<<1, 1, 0, h->stream>>>(d.partials.p, (int32_t)(g + gb), d.scal.p + NSCAL + 2);
     double a = 0.0;
     QG_HIP(h, hipMemcpyAsync(&a, d.scal.p + NSCAL + 2, sizeof(double), hipMemcpyDeviceToHost, h->stream));
     QG_HIP(h, hipStreamSynchronize(h->stream));
@@ -404,6 +739,10 @@ int launch_step_min(qg_handle *h, const double *u, const double *du, int slot) {
     Device &d = h->d;
     step_kernel<<<cone_grid(h), 256, 0, h->stream>>>(h->pp.l, h->pp.nsoc, d.soc_off.p, u, du, d.amin.p + slot);
     QG_HIP(h, hipGetLastError());
+    if (h->nbig) {
+        step_big<<<big_grid(h), 256, 0, h->stream>>>(h->nbig, d.big_cones.p, d.soc_off.p, u, du, d.amin.p + slot);
+        QG_HIP(h, hipGetLastError());
+    }
     return QG_OK;
 }
 

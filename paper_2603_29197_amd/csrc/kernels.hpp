@@ -18,6 +18,11 @@ constexpr int SB = 256;
 // Lanes per matrix row in the sparse matrix-vector products (16 rows per
 // 256-thread block).
 constexpr int RL = 16;
+// Second-order cones with q >= QBIG entries are handled one wavefront per
+// cone (lane-strided entries, butterfly sums); smaller cones one thread each.
+constexpr int QBIG = 32;
+// (3,3)-block entries of a big cone written per workgroup.
+constexpr int BIG_CHUNK = 2048;
 
 // Kind of a permuted KKT column: primal x, equality y, cone z.  Pivot signs
 // of the quasi-definite matrix: + for x, - for y and z; static

@@ -54,7 +54,7 @@ static void dfree(DBuf<T> &b) {
 
 void dfree_all(qg_handle *h) {
     Device &d = h->d;
-    dfree(d.kval); dfree(d.blk33); dfree(d.blk_off); dfree(d.soc_off); dfree(d.kr_ptr);
+    dfree(d.kval); dfree(d.blk33); dfree(d.blk_off); dfree(d.soc_off); dfree(d.big_cones); dfree(d.big_chunk_cone); dfree(d.big_chunk_start); dfree(d.bigsc); dfree(d.kr_ptr);
     dfree(d.kr_col); dfree(d.kr_val); dfree(d.c); dfree(d.b); dfree(d.h); dfree(d.Pp); dfree(d.Pi);
     dfree(d.Ap); dfree(d.Ai); dfree(d.Gp); dfree(d.Gi); dfree(d.posG);
     dfree(d.perm); dfree(d.iperm);

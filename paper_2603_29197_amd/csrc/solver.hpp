@@ -84,6 +84,10 @@ struct Device {
     DBuf<int64_t> blk33;        // positions of (3,3) entries in kval
     DBuf<int64_t> blk_off;      // per SOC: offset of its entries in blk33 (after the orthant)
     DBuf<int32_t> soc_off;      // nsoc + 1 row offsets in z
+    DBuf<int32_t> big_cones;    // indices of the SOCs with q >= QBIG (one wavefront each)
+    DBuf<int32_t> big_chunk_cone;   // per BIG_CHUNK chunk of a big cone's block: position in big_cones
+    DBuf<int64_t> big_chunk_start;  //   and first entry of the chunk within that cone's block
+    DBuf<double> bigsc;         // 2 per big cone: z1'z1, z1's1 (derivative block)
     DBuf<int64_t> kr_ptr;       // full symmetric CSR of K without the (3,3) block
     DBuf<int32_t> kr_col;
     DBuf<double> kr_val;
@@ -155,6 +159,8 @@ struct qg_handle {
     std::vector<double> hc, hb, hh;    // c, b, h on the host
     int64_t nnzK = 0;
     int32_t n = 0, m = 0, p = 0, N = 0;
+    int32_t nbig = 0;                  // SOCs handled one wavefront per cone
+    int64_t nbigchunk = 0;             // workgroups of the big cones' block writes
     bool solved = false;               // a solve finished (x, s, y, z valid)
     bool final_factor = false;         // the derivative system is factored (FP64)
     int last_precision = -1;           // precision of the current factor

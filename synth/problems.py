@@ -151,18 +151,24 @@ def lasso(rows: int = 20000, cols: int = 10000, density: float = 0.005,
 # --------------------------------------------------------------------------------------
 # Workload 3: many small second-order cones ||F_i x + g_i|| <= d_i'x + e_i, plus bounds
 # --------------------------------------------------------------------------------------
-def many_soc(n: int = 300000, ncones: int = 100000, q: int = 4, nbounds: int = 100000,
+def many_soc(n: int = 300000, ncones: int = 100000, q=4, nbounds: int = 100000,
              seed: int = BASE_SEED + 3, windowed: bool = True, per_row: int = 2,
              window: int = 12) -> Problem:
+    """``q`` is one cone dimension for all ``ncones`` cones, or a list of
+    dimensions (one per cone; ``ncones`` is then ignored)."""
+    qs = [int(q)] * ncones if np.isscalar(q) else [int(v) for v in q]
+    ncones = len(qs)
+    offs = np.concatenate([[0], np.cumsum(qs)]).astype(np.int64)
     rng = np.random.default_rng(seed)
     x0 = rng.standard_normal(n)
     Pdiag = rng.uniform(0.1, 1.0, n)
     c = rng.standard_normal(n)
     rows_i, cols_i, vals_i = [], [], []
-    h_soc = np.empty(ncones * q)
-    nf = q - 1
+    h_soc = np.empty(int(offs[-1]))
     for i in range(ncones):
-        base = q * i
+        q_i = qs[i]
+        nf = q_i - 1
+        base = int(offs[i])
         if windowed:
             pool = (3 * i + np.arange(window)) % n
         else:
@@ -185,9 +191,9 @@ def many_soc(n: int = 300000, ncones: int = 100000, q: int = 4, nbounds: int = 1
         for r in range(nf):
             rows_i.append(np.full(per_row, base + 1 + r)); cols_i.append(Fcols[r]); vals_i.append(-Fvals[r])
         h_soc[base] = ei
-        h_soc[base + 1:base + q] = gi
+        h_soc[base + 1:base + q_i] = gi
     Gsoc = sp.coo_matrix((np.concatenate(vals_i), (np.concatenate(rows_i), np.concatenate(cols_i))),
-                         shape=(ncones * q, n))
+                         shape=(int(offs[-1]), n))
     bidx = np.sort(rng.choice(n, size=nbounds, replace=False))
     slack = rng.uniform(0.1, 1.0, nbounds)
     Gb = sp.coo_matrix((-np.ones(nbounds), (np.arange(nbounds), bidx)), shape=(nbounds, n))
@@ -195,10 +201,11 @@ def many_soc(n: int = 300000, ncones: int = 100000, q: int = 4, nbounds: int = 1
     G = sp.vstack([Gb, Gsoc], format="csc")
     h = np.concatenate([hb, h_soc])
     P = sp.diags(Pdiag, format="csc")
-    prob = Problem(n=n, m=nbounds + ncones * q, p=0, P=_csc(P), c=c,
+    qname = f"q{qs[0]}" if np.isscalar(q) else f"qmix{max(qs)}"
+    prob = Problem(n=n, m=nbounds + int(offs[-1]), p=0, P=_csc(P), c=c,
                    A=_csc(sp.csc_matrix((0, n))), b=np.zeros(0), G=_csc(G), h=h,
-                   l=nbounds, q=[q] * ncones,
-                   name=f"many_soc_n{n}_k{ncones}_q{q}{'' if windowed else '_random'}",
+                   l=nbounds, q=list(qs),
+                   name=f"many_soc_n{n}_k{ncones}_{qname}{'' if windowed else '_random'}",
                    meta=dict(seed=seed, windowed=windowed))
     prob.check()
     return prob
@@ -251,6 +258,9 @@ def workload(name: str) -> Problem:
         "many_soc_s": lambda: many_soc(3000, 1000, 4, 1000, seed=BASE_SEED + 13),
         "huber_s": lambda: huber(10000, 4000, 40, seed=BASE_SEED + 14),
         "lasso_diff_s": lambda: lasso(2500, 1000, 0.016, seed=BASE_SEED + 15),
+        # large second-order cones: 3000 of 64 entries, 300 of 256, 30 of 1024 (m = 304520)
+        "big_cones": lambda: many_soc(20000, q=[64] * 3000 + [256] * 300 + [1024] * 30, nbounds=5000,
+                                      seed=BASE_SEED + 16),
     }
     return table[name]()
 

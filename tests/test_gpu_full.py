@@ -8,6 +8,9 @@ any size and through sampled outputs the oracle computes itself.
   up-looking factorization stops after a prefix of rows) to 1e-10.
 - many_soc (n = 300000, 1e5 cones of dimension 4, N_K = 800000): residuals,
   gap, cone interiority, modes agreeing.
+- big_cones (3000 cones of dimension 64, 300 of 256, 30 of 1024, 5000 bounds,
+  n = 20000): as above; cones of 32 entries and more run one wavefront per
+  cone.
 - huber_m (the Huber generator at F 50000 x 20000, 40 entries per row,
   N_K = 320000; the full 500000 x 200000 instance would need a dense root
   front of about 2e5 columns, more than one GPU's memory): as above.
@@ -74,7 +77,9 @@ def solve_both(prob):
         S.set_settings(precision=prec)
         x, s, y, z, info = S.solve()
         print(f"[gpu] {prob.name} {name}: {info['status_name']} iters {info['iters']} switch "
-              f"{info['switch_iter']} ir {info['ir_steps']} step {info['ms_step_median']:.2f} ms", flush=True)
+              f"{info['switch_iter']} ir {info['ir_steps']} step {info['ms_step_median']:.2f} ms (cone phase "
+              f"{info['ms_cone']:.1f}, factor {info['ms_factor']:.1f}, solves {info['ms_trisolve']:.1f} ms "
+              f"over the solve)", flush=True)
         assert info["status"] == 1
         out[name] = [host(t) for t in (x, s, y, z)]
     S.close()
@@ -82,7 +87,7 @@ def solve_both(prob):
 
 
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("name", ["lasso", "many_soc", "huber_m"])
+@pytest.mark.parametrize("name", ["lasso", "many_soc", "huber_m", "big_cones"])
 def test_full_size_solution_properties(name):
     prob = problems.workload(name)
     out = solve_both(prob)

@@ -27,6 +27,10 @@ SMALL = {
     "lasso_s": lambda: problems.workload("lasso_s"),
     "many_soc_s": lambda: problems.workload("many_soc_s"),
     "mixed_soc": lambda: problems.many_soc(n=400, ncones=60, q=7, nbounds=50, seed=77, windowed=False),
+    # cone sizes on both sides of the thread-per-cone / wavefront-per-cone switch at 32 entries,
+    # and past one, two, four and ten lane strides
+    "big_soc": lambda: problems.many_soc(n=400, q=[3, 64, 31, 257, 32, 5, 100, 33, 700, 2, 65, 4, 129],
+                                         nbounds=100, seed=78, windowed=False),
 }
 
 
@@ -51,7 +55,7 @@ def relerr(a, b):
 # ---------------------------------------------------------------------------
 # a1 + a6: NT scaling and the (3,3) block
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("name", ["small_qp", "many_soc_s", "mixed_soc"])
+@pytest.mark.parametrize("name", ["small_qp", "many_soc_s", "mixed_soc", "big_soc"])
 def test_scaling_and_kkt_block(name):
     prob = SMALL[name]()
     S = solver(prob)
@@ -68,7 +72,7 @@ def test_scaling_and_kkt_block(name):
     S.close()
 
 
-@pytest.mark.parametrize("name", ["many_soc_s", "mixed_soc"])
+@pytest.mark.parametrize("name", ["many_soc_s", "mixed_soc", "big_soc"])
 def test_derivative_block(name):
     prob = SMALL[name]()
     S = solver(prob)
@@ -83,7 +87,7 @@ def test_derivative_block(name):
 # ---------------------------------------------------------------------------
 # a7, a8, a9: cone algebra, corrector, max step
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("name", ["small_qp", "many_soc_s", "mixed_soc"])
+@pytest.mark.parametrize("name", ["small_qp", "many_soc_s", "mixed_soc", "big_soc"])
 def test_cone_ops_corrector_and_step(name):
     prob = SMALL[name]()
     S = solver(prob)
@@ -115,7 +119,7 @@ def test_cone_ops_corrector_and_step(name):
 # ---------------------------------------------------------------------------
 # a2 + a3 + a4: factor, solves, refinement
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("name", ["small_qp", "lasso_s", "many_soc_s", "mixed_soc"])
+@pytest.mark.parametrize("name", ["small_qp", "lasso_s", "many_soc_s", "mixed_soc", "big_soc"])
 def test_factor_entries_fp64(name):
     import paper_2603_29197_amd as qg
     prob = SMALL[name]()
@@ -134,7 +138,7 @@ def test_factor_entries_fp64(name):
     S.close()
 
 
-@pytest.mark.parametrize("name", ["small_qp", "lasso_s", "many_soc_s", "mixed_soc"])
+@pytest.mark.parametrize("name", ["small_qp", "lasso_s", "many_soc_s", "mixed_soc", "big_soc"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_refined_solve(name, prec):
     import paper_2603_29197_amd as qg
@@ -170,7 +174,7 @@ def oracle_solution(name):
     return ORACLE_CACHE[name]
 
 
-@pytest.mark.parametrize("name", ["small_qp", "lasso_s", "many_soc_s", "mixed_soc"])
+@pytest.mark.parametrize("name", ["small_qp", "lasso_s", "many_soc_s", "mixed_soc", "big_soc"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_solve_matches_oracle(name, prec):
     import paper_2603_29197_amd as qg
@@ -196,7 +200,15 @@ def test_solve_matches_oracle(name, prec):
     S.close()
 
 
-@pytest.mark.parametrize("name", ["small_qp", "lasso_s", "mixed_soc"])
+# Tolerance against the gradients at the oracle's own final iterate.  The two solves stop at
+# different points that both meet the stopping rule; where their trajectories coincide closely the
+# gradients agree to 1e-5.  On big_soc they part earlier, and the gradient there is no sharper than
+# the stopping rule fixes it: tightening the oracle's rule from 1e-8 to 1e-10 moves its own dL/dc
+# by 9e-3 and dL/dG by 3e-2 (mixed_soc: 5e-2), so the bound is 1e-3.
+TRAJ_TOL = {"big_soc": 1e-3}
+
+
+@pytest.mark.parametrize("name", ["small_qp", "lasso_s", "mixed_soc", "big_soc"])
 def test_backward_matches_oracle(name):
     prob = SMALL[name]()
     S = solver(prob, differentiable=1)
@@ -205,15 +217,32 @@ def test_backward_matches_oracle(name):
     ref = oracle_solution(name)
     g = np.random.default_rng(11).standard_normal(prob.n)
     gr = S.backward(dev(g), want_A=True, want_G=True)
+    # The adjoint solve itself, at the device's final iterate: u = [-dL/dc; dL/db; dL/dh] must solve
+    # the oracle's K_fin there to a normwise backward error near FP64 rounding (a test of the solve
+    # that does not depend on how well K_fin is conditioned), and the gradients of the matrix values
+    # must be the oracle's formulas applied to that u.
+    xs, ss, ys, zs = host(x), host(s), host(y), host(z)
+    orth, blocks = oadj.final_block(prob, ss, zs)
+    K = okkt.full_from_upper(okkt.kkt_upper(prob, orth, blocks)).tocsr()
+    u = np.concatenate([-host(gr["dc"]), host(gr["db"]), host(gr["dh"])])
+    rhs = np.concatenate([g, np.zeros(prob.p + prob.m)])
+    knorm = float(np.max(np.asarray(abs(K).sum(axis=1)).ravel()))
+    bwd = float(np.max(np.abs(rhs - K @ u)) / (knorm * np.max(np.abs(u)) + np.max(np.abs(rhs))))
+    print(f"[gpu] {name} adjoint backward error {bwd:.2e}", flush=True)
+    assert bwd <= 1e-13, bwd
+    same = oadj._grads(prob, xs, ys, zs, u)
     want = oadj.backward_dense(prob, ref, g)
     for k in ("dc", "dh", "db", "dP", "dA", "dG"):
         if k in ("dP", "dA", "dG") and not getattr(prob, k[1]).nnz:
             continue
-        a, b = host(gr[k]), want[k]
-        if b.size:
-            e = float(np.max(np.abs(a - b)) / max(1.0, np.max(np.abs(b))))
-            print(f"[gpu] {name} {k} rel err {e:.2e}", flush=True)
-            assert e <= 1e-5, (k, e)
+        a = host(gr[k])
+        if not a.size:
+            continue
+        e1 = float(np.max(np.abs(a - same[k])) / max(1.0, np.max(np.abs(same[k]))))
+        e2 = float(np.max(np.abs(a - want[k])) / max(1.0, np.max(np.abs(want[k]))))
+        print(f"[gpu] {name} {k} rel err {e1:.2e} from the same u, {e2:.2e} at the oracle's iterate", flush=True)
+        assert e1 <= 1e-13, (k, e1)
+        assert e2 <= TRAJ_TOL.get(name, 1e-5), (k, e2)
     S.close()
 
 

@@ -122,9 +122,9 @@ def _soc_pair(q, seed):
     return C.Cones(0, [q]), s, z
 
 
-def _mixed(seed):
+def _mixed(seed, qs=(5, 3, 5, 2, 6, 9)):
     prob = problems.many_soc(n=40, ncones=6, q=5, nbounds=7, seed=seed)
-    prob.q = [5, 3, 5, 2, 6, 9]
+    prob.q = list(qs)
     prob.m = prob.l + sum(prob.q)
     _, s, _, z = problems.random_point(prob, seed)
     return C.Cones(prob.l, prob.q), s, z
@@ -135,9 +135,10 @@ def _dense_W(sc, cn):
     return np.column_stack([sc.W(np.eye(m)[:, k]) for k in range(m)])
 
 
-@pytest.mark.parametrize("seed", range(6))
-def test_nt_scaling_identities(seed):
-    cn, s, z = _mixed(seed)
+@pytest.mark.parametrize("seed,qs", [(k, (5, 3, 5, 2, 6, 9)) for k in range(6)] +
+                         [(k, (33, 2, 130, 64)) for k in range(2)])
+def test_nt_scaling_identities(seed, qs):
+    cn, s, z = _mixed(seed, qs)
     sc = C.nt_scaling(cn, s, z)
     W = _dense_W(sc, cn)
     assert np.allclose(W, W.T, atol=1e-13)

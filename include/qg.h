@@ -230,6 +230,21 @@ int qg_backward_full(qg_handle *h, const double *dl_dx, const double *dl_dy, con
                      const double *dl_ds, double *dl_dc, double *dl_dh, double *dl_db,
                      double *dl_dPval, double *dl_dAval, double *dl_dGval);
 
+/*
+ * Gradients of k losses through the same solve.  The k adjoint systems
+ * share the one stored final factorization and run one after another on the
+ * handle's stream.  Each input and output holds k blocks stored one after
+ * another: dl_dx (k x n), dl_dy (k x p), dl_dz and dl_ds (k x m), dl_dc
+ * (k x n), dl_dh (k x m), dl_db (k x p), dl_dPval (k x nnz(P)), dl_dAval
+ * (k x nnz(A)), dl_dGval (k x nnz(G)).  Block j is what qg_backward_full
+ * gives for the j-th blocks of the inputs.  NULL inputs mean zero and NULL
+ * outputs are not written.  k = 0 does nothing.  k < 0 gives QG_ERR_ARG;
+ * other errors are as for qg_backward.
+ */
+int qg_backward_batch(qg_handle *h, int32_t k, const double *dl_dx, const double *dl_dy,
+                      const double *dl_dz, const double *dl_ds, double *dl_dc, double *dl_dh,
+                      double *dl_db, double *dl_dPval, double *dl_dAval, double *dl_dGval);
+
 /* Host copies of the analysis; valid until qg_cleanup. */
 int qg_get_pattern(const qg_handle *h, qg_pattern *out);
 

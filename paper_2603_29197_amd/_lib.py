@@ -76,7 +76,7 @@ class qg_pattern(ctypes.Structure):
 
 EXPORTS = [
     "qg_default_settings", "qg_analyze", "qg_symbolic_pattern", "qg_symbolic_free", "qg_setup", "qg_update",
-    "qg_set_settings", "qg_solve", "qg_backward", "qg_backward_full", "qg_get_pattern", "qg_last_hip_error", "qg_cleanup",
+    "qg_set_settings", "qg_solve", "qg_backward", "qg_backward_full", "qg_backward_batch", "qg_get_pattern", "qg_last_hip_error", "qg_cleanup",
     "qg_strerror", "qg_step_scaling", "qg_step_get_kkt", "qg_step_factor", "qg_step_get_factor",
     "qg_step_solve", "qg_step_max_step", "qg_step_cone_op", "qg_step_corrector",
 ]
@@ -109,6 +109,7 @@ def lib():
     L.qg_solve.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(qg_info)]
     L.qg_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     L.qg_backward_full.argtypes = [vp] * 11
+    L.qg_backward_batch.argtypes = [vp, ctypes.c_int32] + [vp] * 10
     L.qg_get_pattern.argtypes = [vp, ctypes.POINTER(qg_pattern)]
     L.qg_last_hip_error.argtypes = [vp]
     L.qg_cleanup.argtypes = [vp]

@@ -179,6 +179,31 @@ class Solver:
             res["d" + k] = None if out[k] is None else out[k][:nnz[k]]
         return res
 
+    def backward_batch(self, dl_dx, want_P: bool = True, want_A: bool = False, want_G: bool = False,
+                       dl_dy=None, dl_dz=None, dl_ds=None):
+        """k losses at once: dl_dx is (k, n), the optional dl_dy, dl_dz, dl_ds are (k, p), (k, m),
+        (k, m); returns the gradients of backward() stacked along a leading axis of length k."""
+        t = self.torch
+        dl_dx = dl_dx.to(device="cuda", dtype=t.float64).contiguous()
+        k = int(dl_dx.shape[0])
+        assert dl_dx.shape == (k, self.n)
+        extra = [None if v is None else v.to(device="cuda", dtype=t.float64).contiguous()
+                 for v in (dl_dy, dl_dz, dl_ds)]
+        for v, w in zip(extra, (self.p, self.m, self.m)):
+            assert v is None or v.shape == (k, w)
+        nnz = {key: int(getattr(self.prob, key).nnz) for key in ("P", "A", "G")}
+        want = {"P": want_P, "A": want_A, "G": want_G}
+        new = lambda w: t.empty((k, w), dtype=t.float64, device="cuda")
+        dc, dh, db = new(self.n), new(self.m), new(self.p)
+        out = {key: (new(nnz[key]) if (want[key] and nnz[key] > 0) else None) for key in ("P", "A", "G")}
+        vp = lambda v: None if v is None or v.numel() == 0 else ctypes.c_void_p(v.data_ptr())
+        check(lib().qg_backward_batch(self.handle, k, vp(dl_dx), *[vp(v) for v in extra], vp(dc), vp(dh),
+                                      vp(db), vp(out["P"]), vp(out["A"]), vp(out["G"])), "qg_backward_batch")
+        res = dict(dc=dc, dh=dh, db=db)
+        for key in ("P", "A", "G"):
+            res["d" + key] = out[key]
+        return res
+
     def pattern(self) -> dict:
         pt = qg_pattern()
         check(lib().qg_get_pattern(self.handle, ctypes.byref(pt)), "qg_get_pattern")

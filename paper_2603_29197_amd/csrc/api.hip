@@ -326,22 +326,18 @@ void qg_cleanup(qg_handle *h) {
     if (!h) return;
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     if (h->bulk) (void)hipStreamSynchronize(h->bulk);
-    if (h->prep) (void)hipStreamSynchronize(h->prep);
     dfree_all(h);
-    for (hipEvent_t e : {h->ev_panel, h->ev_bulk, h->ev_prep})
+    for (hipEvent_t e : {h->ev_panel, h->ev_bulk})
         if (e) (void)hipEventDestroy(e);
     if (h->bulk) (void)hipStreamDestroy(h->bulk);
-    if (h->prep) (void)hipStreamDestroy(h->prep);
     delete h;
 }
 
-// Side streams and ordering events of the factorization.
+// Side stream and ordering events of the factorization.
 static int create_streams(qg_handle *h) {
     QG_HIP(h, hipStreamCreateWithFlags(&h->bulk, hipStreamNonBlocking));
-    QG_HIP(h, hipStreamCreateWithFlags(&h->prep, hipStreamNonBlocking));
     QG_HIP(h, hipEventCreateWithFlags(&h->ev_panel, hipEventDisableTiming));
     QG_HIP(h, hipEventCreateWithFlags(&h->ev_bulk, hipEventDisableTiming));
-    QG_HIP(h, hipEventCreateWithFlags(&h->ev_prep, hipEventDisableTiming));
     return QG_OK;
 }
 
@@ -434,6 +430,24 @@ int qg_backward_full(qg_handle *h, const double *dl_dx, const double *dl_dy, con
     if (!h || !dl_dx) return QG_ERR_ARG;
     if (!h->solved || !h->final_factor) return QG_ERR_STATE;
     return adjoint_backward(h, dl_dx, dl_dy, dl_dz, dl_ds, dl_dc, dl_dh, dl_db, dl_dPval, dl_dAval, dl_dGval);
+}
+
+int qg_backward_batch(qg_handle *h, int32_t k, const double *dl_dx, const double *dl_dy, const double *dl_dz,
+                      const double *dl_ds, double *dl_dc, double *dl_dh, double *dl_db, double *dl_dPval,
+                      double *dl_dAval, double *dl_dGval) {
+    if (!h || k < 0 || (k > 0 && !dl_dx)) return QG_ERR_ARG;
+    if (!h->solved || !h->final_factor) return QG_ERR_STATE;
+    const size_t n = (size_t)h->n, p = (size_t)h->p, m = (size_t)h->m;
+    const size_t nP = (size_t)h->pp.P.rowind.size(), nA = (size_t)h->pp.A.rowind.size(),
+                 nG = (size_t)h->pp.G.rowind.size();
+    auto at = [](auto *base, size_t len, int32_t j) { return base ? base + len * (size_t)j : base; };
+    for (int32_t j = 0; j < k; ++j) {
+        const int rc = adjoint_backward(h, at(dl_dx, n, j), at(dl_dy, p, j), at(dl_dz, m, j), at(dl_ds, m, j),
+                                        at(dl_dc, n, j), at(dl_dh, m, j), at(dl_db, p, j), at(dl_dPval, nP, j),
+                                        at(dl_dAval, nA, j), at(dl_dGval, nG, j));
+        if (rc) return rc;
+    }
+    return QG_OK;
 }
 
 int qg_get_pattern(const qg_handle *h, qg_pattern *out) {

@@ -326,18 +326,22 @@ void qg_cleanup(qg_handle *h) {
     if (!h) return;
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     if (h->bulk) (void)hipStreamSynchronize(h->bulk);
+    if (h->prep) (void)hipStreamSynchronize(h->prep);
     dfree_all(h);
-    for (hipEvent_t e : {h->ev_panel, h->ev_bulk})
+    for (hipEvent_t e : {h->ev_panel, h->ev_bulk, h->ev_prep})
         if (e) (void)hipEventDestroy(e);
     if (h->bulk) (void)hipStreamDestroy(h->bulk);
+    if (h->prep) (void)hipStreamDestroy(h->prep);
     delete h;
 }
 
-// Side stream and ordering events of the factorization.
+// Side streams and ordering events of the factorization.
 static int create_streams(qg_handle *h) {
     QG_HIP(h, hipStreamCreateWithFlags(&h->bulk, hipStreamNonBlocking));
+    QG_HIP(h, hipStreamCreateWithFlags(&h->prep, hipStreamNonBlocking));
     QG_HIP(h, hipEventCreateWithFlags(&h->ev_panel, hipEventDisableTiming));
     QG_HIP(h, hipEventCreateWithFlags(&h->ev_bulk, hipEventDisableTiming));
+    QG_HIP(h, hipEventCreateWithFlags(&h->ev_prep, hipEventDisableTiming));
     return QG_OK;
 }
 

@@ -374,6 +374,9 @@ __global__ void __launch_bounds__(256) sblock_inverse(const T *__restrict__ F, i
         XTs[(int64_t)(j * NB + rr) * ld + j * NB + cc] = v;
     }
     for (int32_t i = j + 1; i < nsub; ++i) {
+        // X_jj, and the X_{i-1,j} stored at the end of the previous pass, were written by other
+        // wavefronts of this workgroup and are read below
+        __syncthreads();
         const int32_t bi = min(NB, kb - i * NB);
         V acc[4];
 #pragma unroll
@@ -731,9 +734,8 @@ static void launch_update(qg_handle *h, hipStream_t st, T *F, int32_t r, int32_t
 // update of super-panel J runs while super-panel J+1 is factored.  The bulk
 // update of J and the next-columns update of J+1 touch the same columns, so
 // the latter waits for the former.  The inverses and W blocks that only the
-// solves need are formed on the main stream after each super-panel (formed on
-// a third stream instead, they made the factorization differ from run to run
-// on fronts with a contribution block).  The bulk stream is joined at the end.
+// solves need are formed on the prep stream.  Both side streams are joined at
+// the end.
 template <typename T>
 static int factor_large(qg_handle *h, int32_t s, T *front, T *dinv, T *sinv, T *wb, const RegParams &rp) {
     const Plan &pl = h->plan;
@@ -743,9 +745,10 @@ static int factor_large(qg_handle *h, int32_t s, T *front, T *dinv, T *sinv, T *
     const int8_t *kinds = h->d.reg_sign.p + pl.sn_first[s];
     hipStream_t ms = h->stream;
     bool bulk_pending = false;
-    // everything before this front on the main stream is visible to the bulk stream
+    // everything before this front on the main stream is visible to the side streams
     QG_HIP(h, hipEventRecord(h->ev_panel, ms));
     QG_HIP(h, hipStreamWaitEvent(h->bulk, h->ev_panel, 0));
+    QG_HIP(h, hipStreamWaitEvent(h->prep, h->ev_panel, 0));
     for (int32_t J0 = 0; J0 < k; J0 += SB) {
         const int32_t J1 = std::min(k, J0 + SB);
         for (int32_t j0 = J0; j0 < J1; j0 += NB) {
@@ -759,14 +762,14 @@ static int factor_large(qg_handle *h, int32_t s, T *front, T *dinv, T *sinv, T *
         }
         QG_HIP(h, hipEventRecord(h->ev_panel, ms));
         {
-            // solve-only data of this super-panel on the main stream, while the previous bulk
-            // update (which the next-columns update below waits for) may still run
+            // solve-only data of this super-panel
+            QG_HIP(h, hipStreamWaitEvent(h->prep, h->ev_panel, 0));
             const int32_t nsub = (J1 - J0 + NB - 1) / NB, ld = nsub * NB;
             T *Xs = sinv + pl.sinv_off[s] + (int64_t)(J0 / SB) * 2 * SB * SB;
-            sblock_inverse<T><<<nsub, 256, 0, ms>>>(F, r, J0, J1 - J0, dinv + pl.dinv_off[s], ld, Xs,
-                                                    Xs + (int64_t)ld * ld);
+            sblock_inverse<T><<<nsub, 256, 0, h->prep>>>(F, r, J0, J1 - J0, dinv + pl.dinv_off[s], ld, Xs,
+                                                         Xs + (int64_t)ld * ld);
             if (J1 < r)
-                wblock<T><<<dim3((unsigned)((r - J1 + 63) / 64), (unsigned)nsub), 256, 0, ms>>>(
+                wblock<T><<<dim3((unsigned)((r - J1 + 63) / 64), (unsigned)nsub), 256, 0, h->prep>>>(
                     F, r, J0, J1 - J0, Xs, ld, wb + pl.w_off[s] + w_block_offset(r, J0));
         }
         if (J1 < r) {
@@ -789,6 +792,8 @@ static int factor_large(qg_handle *h, int32_t s, T *front, T *dinv, T *sinv, T *
     }
     // join
     if (bulk_pending) QG_HIP(h, hipStreamWaitEvent(ms, h->ev_bulk, 0));
+    QG_HIP(h, hipEventRecord(h->ev_prep, h->prep));
+    QG_HIP(h, hipStreamWaitEvent(ms, h->ev_prep, 0));
     QG_HIP(h, hipEventRecord(h->ev_bulk, h->bulk));
     QG_HIP(h, hipStreamWaitEvent(ms, h->ev_bulk, 0));
     return QG_OK;

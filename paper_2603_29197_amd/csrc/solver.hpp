@@ -142,11 +142,11 @@ struct Timer {
 struct qg_handle {
     qg_settings st;
     hipStream_t stream = nullptr;
-    // Side stream of the large-front factorization (default priority, non-blocking):
-    // bulk = trailing updates beyond the next super-panel; ordered against `stream`
-    // with the events below.
-    hipStream_t bulk = nullptr;
-    hipEvent_t ev_panel = nullptr, ev_bulk = nullptr;
+    // Side streams of the large-front factorization (default priority, non-blocking):
+    // bulk = trailing updates beyond the next super-panel, prep = inverses and W blocks
+    // for the solves; ordered against `stream` with the events below.
+    hipStream_t bulk = nullptr, prep = nullptr;
+    hipEvent_t ev_panel = nullptr, ev_bulk = nullptr, ev_prep = nullptr;
     int last_hip = 0;
     int device = 0;
     qg::ProblemPattern pp;

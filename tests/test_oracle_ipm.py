@@ -344,3 +344,55 @@ def test_adjoint_through_the_whole_solution_vs_central_finite_differences():
             checks.append((mat, t, gr[key][t], loss_diff(*res) / (2 * hstep)))
     for what, j, adj, fd in checks:
         assert abs(adj - fd) <= 1e-3 * max(abs(fd), 1e-3), (what, j, adj, fd)
+
+
+def test_box_qp_gradient_of_the_quadratic_closed_form():
+    """dL/dP on the box QP (P = diag(d)): x*_i = -c_i/d_i on free coordinates, so
+    dx*_i/dd_i = c_i/d_i^2 there, and 0 for clipped coordinates and for every other d_j."""
+    prob, d, c, lo, hi = box_qp(7)
+    r = ipm.solve(prob, tight())
+    xs = r.x
+    free = (xs > lo + 1e-6) & (xs < hi - 1e-6)
+    assert free.sum() >= 3 and (~free).sum() >= 3
+    Pu = prob.P.tocoo()
+    assert np.array_equal(Pu.row, Pu.col)              # only the diagonal is stored
+    for i in range(prob.n):
+        g = np.zeros(prob.n); g[i] = 1.0                # L = x_i
+        gr = adjoint.backward(prob, r, g)
+        want = np.zeros(prob.n)
+        want[i] = c[i] / d[i] ** 2 if free[i] else 0.0
+        assert np.allclose(gr["dP"][np.argsort(Pu.row)], want, atol=1e-5), (i, gr["dP"], want)
+
+
+def test_adjoint_of_the_quadratic_vs_central_finite_differences():
+    """dL/dP on P's stored upper pattern against central differences of the stored values: a
+    stored off-diagonal value P_ij enters the symmetric P twice (P_ij = P_ji), a diagonal value
+    once.  Seeded diagonal and off-diagonal entries plus the largest-gradient ones."""
+    prob = problems.small_qp(n=30, p=8, m=30, mrows=20, density=0.2, seed=31)
+    st = tight()
+    base = ipm.solve(prob, st)
+    rng = np.random.default_rng(32)
+    xref = rng.standard_normal(prob.n)
+    gr = adjoint.backward(prob, base, base.x - xref)     # L = 1/2 |x* - xref|^2
+    Pu = prob.P.tocoo()
+    diag = np.flatnonzero(Pu.row == Pu.col)
+    off = np.flatnonzero(Pu.row != Pu.col)
+    assert len(off) > 10
+    top_d = diag[np.argsort(-np.abs(gr["dP"][diag]))[:2]]
+    top_o = off[np.argsort(-np.abs(gr["dP"][off]))[:3]]
+    picks = np.unique(np.concatenate([rng.choice(diag, 3, replace=False), rng.choice(off, 4, replace=False),
+                                      top_d, top_o]))
+    hstep = 1e-6
+    nchecked = {"diag": 0, "off": 0}
+    for t in picks:
+        xs = []
+        for sgn in (+1, -1):
+            pr = problems.Problem(**{**prob.__dict__})
+            P2 = prob.P.copy(); P2.data[t] += sgn * hstep
+            pr.P = P2
+            xs.append(ipm.solve(pr, st).x)
+        xp, xm = xs
+        fd = 0.5 * (xp - xm) @ (xp + xm - 2 * xref) / (2 * hstep)
+        assert abs(gr["dP"][t] - fd) <= 1e-3 * max(abs(fd), 1e-3), (t, Pu.row[t], Pu.col[t], gr["dP"][t], fd)
+        nchecked["diag" if Pu.row[t] == Pu.col[t] else "off"] += 1
+    assert nchecked["diag"] >= 3 and nchecked["off"] >= 4

@@ -214,3 +214,51 @@ def test_dense_nodes_are_ordered_last():
     assert symbolic.dense_cut(N) < N - 1
     perm = symbolic.order(U)
     assert perm[-1] == 0
+
+
+def _relax_ok(rows_of_group, cols, colcount):
+    """The relaxation test on a candidate block: explicit zeros of its stored lower trapezoid,
+    counted from the union of the columns' row sets (brute force, not the colcount formula)."""
+    w = len(cols)
+    r = len(rows_of_group)
+    stored = w * r - w * (w - 1) // 2
+    zeros = stored - int(sum(colcount[c] for c in cols))
+    return zeros <= symbolic.ZREL * stored or (w <= symbolic.RELAX_W and zeros <= symbolic.RELAX_Z)
+
+
+@pytest.mark.parametrize("name", ["small_qp", "lasso_s", "many_soc_s", "rand"])
+def test_relaxed_supernodes_are_the_greedy_partition(name):
+    """The relaxed partition is pinned by two properties that determine a greedy left-to-right
+    grouping uniquely: every extension of a group's prefix by its next fundamental supernode
+    passes the test (T holds the parent of the prefix's last column, zeros within bounds), and
+    every group boundary fails it.  Row sets come from the explicit L pattern."""
+    if name == "rand":
+        Ku = random_sym_upper(150, 0.03, 5)
+    else:
+        Ku = kkt.kkt_pattern(problems.workload(name))
+    pat = symbolic.analyze(Ku)
+    cc, par = pat.colcount, pat.parent
+    struct = [set([j]) | set(pat.Li[pat.Lp[j]:pat.Lp[j + 1]].tolist()) for j in range(pat.N)]
+
+    def extends(group_cols, t_cols):
+        if par[group_cols[-1]] != t_cols[0]:
+            return False
+        cols = list(group_cols) + list(t_cols)
+        rows = set().union(*(struct[c] for c in cols))
+        return _relax_ok(rows, cols, cc)
+
+    sf = pat.super_fund.tolist()
+    fund = [list(range(sf[s], sf[s + 1])) for s in range(len(sf) - 1)]
+    start_of = {f[0]: k for k, f in enumerate(fund)}
+    sp_ = pat.super_ptr.tolist()
+    merges = 0
+    for g in range(len(sp_) - 1):
+        k0, k1 = start_of[sp_[g]], start_of.get(sp_[g + 1], len(fund))
+        group = list(fund[k0])
+        for k in range(k0 + 1, k1):
+            assert extends(group, fund[k]), (g, k)
+            group += fund[k]
+            merges += 1
+        if k1 < len(fund):
+            assert not extends(group, fund[k1]), (g, k1)
+    assert merges > 0

@@ -148,6 +148,17 @@ typedef struct {
 typedef struct qg_handle qg_handle;      /* device solver state */
 typedef struct qg_symbolic qg_symbolic;  /* host-only analysis result */
 
+/*
+ * Device-memory hooks of qg_setup.  alloc(ctx, bytes) returns device memory
+ * of at least `bytes` bytes, aligned to 256 bytes, usable on the handle's
+ * stream, or NULL when it refuses (qg_setup then fails with QG_ERR_OOM after
+ * returning everything it obtained through free).  free(ctx, ptr) gives back
+ * one pointer alloc returned.  The hooks are called from the thread that
+ * calls qg_setup, qg_update and qg_cleanup only, never from device work.
+ */
+typedef void *(*qg_alloc_fn)(void *ctx, size_t bytes);
+typedef void (*qg_free_fn)(void *ctx, void *ptr);
+
 /* Fill *s with the defaults listed in qg_settings. */
 int qg_default_settings(qg_settings *s);
 
@@ -167,20 +178,26 @@ void qg_symbolic_free(qg_symbolic *sym);
 /*
  * Setup (paper Sec. 2.1 Listing 1, Sec. 2.3): validates and copies the
  * problem data (host pointers, read before return), runs the analysis and
- * uploads everything to device 0 of the current HIP device context.
+ * uploads everything to the current HIP device.
  * P: n x n upper triangle incl. diagonal, or NULL for P = 0.  A: p x n, may
  * be NULL iff p == 0.  G: m x n, may be NULL iff m == 0.  q: nsoc cone
  * dimensions (host).  s: NULL for defaults.  hip_stream: the stream all
  * work is ordered on (NULL = the default stream).
- * Errors: QG_ERR_ARG, QG_ERR_PATTERN, QG_ERR_NONFINITE, QG_ERR_OOM,
- * QG_ERR_HIP, QG_ERR_DEVICE.  On error *out is NULL.
+ * alloc, free, alloc_ctx: where the handle's device memory comes from (all
+ * of it: data, analysis maps, factor storage, work vectors); both NULL means
+ * hipMalloc / hipFree, exactly one NULL is QG_ERR_ARG.  The handle owns what
+ * it obtained and returns it through free in qg_cleanup.
+ * Errors: QG_ERR_ARG, QG_ERR_PATTERN, QG_ERR_NONFINITE (checked before any
+ * device call), QG_ERR_OOM (including a refusing alloc), QG_ERR_HIP,
+ * QG_ERR_DEVICE.  On error *out is NULL and nothing is left allocated.
  */
 int qg_setup(qg_handle **out, qg_int n, qg_int m, qg_int p,
              const qg_csc *P, const double *c,
              const qg_csc *A, const double *b,
              const qg_csc *G, const double *h,
              qg_int l, qg_int nsoc, const qg_int *q,
-             const qg_settings *s, void *hip_stream);
+             const qg_settings *s, void *hip_stream,
+             qg_alloc_fn alloc, qg_free_fn free, void *alloc_ctx);
 
 /*
  * Replace values on the fixed pattern (host pointers, NULL = unchanged);
@@ -190,6 +207,14 @@ int qg_setup(qg_handle **out, qg_int n, qg_int m, qg_int p,
  */
 int qg_update(qg_handle *h, const double *Pval, const double *c, const double *Aval,
               const double *b, const double *Gval, const double *hvec);
+
+/*
+ * The same for the vectors only, from device memory (e.g. float64 torch
+ * tensors): c (n), b (p), hvec (m), NULL = unchanged.  Copied on the handle's
+ * stream before return; no host round trip.  QG_ERR_NONFINITE (values left
+ * unchanged) if any given entry is NaN or Inf.
+ */
+int qg_update_vectors(qg_handle *h, const double *c, const double *b, const double *hvec);
 
 /* Replace the settings (the analysis is kept). */
 int qg_set_settings(qg_handle *h, const qg_settings *s);
@@ -265,7 +290,7 @@ const char *qg_strerror(int code);
 
 /*
  * Nesterov-Todd scaling of (s, z) (both strictly inside K; paper Sec. 2.1,
- * Sec. 2.2 eq. 2 "W_k is the Nesterov-Todd scaling matrix"): stores W in
+ * the scaling W of the (3,3) block of eq. 2, Sec. 2.2): stores W in
  * the handle, writes lambda = W z (m) if lam != NULL, and writes the (3,3)
  * block -W'W into the handle's KKT values.  block = 1 instead writes the
  * derivative-system block -sym(Arw(z)^-1 Arw(s)) (see qg_backward).
@@ -282,7 +307,7 @@ int qg_step_get_kkt(const qg_handle *h, double *kval, int64_t *nnz);
 int qg_step_factor(qg_handle *h, int precision, int *nreg);
 
 /*
- * Factor values on the oracle-style column pattern: for the permuted
+ * Factor values on the analysis' column pattern: for the permuted
  * strictly-lower pattern (Lp: N+1, Li: Lp[N]; host) writes L's values
  * (Lx, host, Lp[N]) and D (host, N) from the last factor (FP32 factors are
  * widened).  Host-side extraction: meant for small test sizes.

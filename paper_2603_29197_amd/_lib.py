@@ -74,9 +74,13 @@ class qg_pattern(ctypes.Structure):
                 ("front_ptr", c_int32_p), ("front_rows_ptr", c_int64_p), ("front_rows", c_int32_p)]
 
 
+# Device-memory hooks of qg_setup (include/qg.h: qg_alloc_fn, qg_free_fn).
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
 EXPORTS = [
     "qg_default_settings", "qg_analyze", "qg_symbolic_pattern", "qg_symbolic_free", "qg_setup", "qg_update",
-    "qg_set_settings", "qg_solve", "qg_backward", "qg_backward_full", "qg_backward_batch", "qg_get_pattern", "qg_last_hip_error", "qg_cleanup",
+    "qg_update_vectors", "qg_set_settings", "qg_solve", "qg_backward", "qg_backward_full", "qg_backward_batch", "qg_get_pattern", "qg_last_hip_error", "qg_cleanup",
     "qg_strerror", "qg_step_scaling", "qg_step_get_kkt", "qg_step_factor", "qg_step_get_factor",
     "qg_step_solve", "qg_step_max_step", "qg_step_cone_op", "qg_step_corrector",
 ]
@@ -103,8 +107,9 @@ def lib():
     L.qg_setup.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                            ctypes.POINTER(qg_csc), c_double_p, ctypes.POINTER(qg_csc), c_double_p,
                            ctypes.POINTER(qg_csc), c_double_p, ctypes.c_int32, ctypes.c_int32, c_int32_p,
-                           ctypes.POINTER(qg_settings), vp]
+                           ctypes.POINTER(qg_settings), vp, ALLOC_FN, FREE_FN, vp]
     L.qg_update.argtypes = [vp, c_double_p, c_double_p, c_double_p, c_double_p, c_double_p, c_double_p]
+    L.qg_update_vectors.argtypes = [vp, vp, vp, vp]
     L.qg_set_settings.argtypes = [vp, ctypes.POINTER(qg_settings)]
     L.qg_solve.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(qg_info)]
     L.qg_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
@@ -124,10 +129,6 @@ def lib():
     L.qg_step_max_step.argtypes = [vp, vp, vp, c_double_p]
     L.qg_step_cone_op.argtypes = [vp, ctypes.c_int, vp, vp, vp]
     L.qg_step_corrector.argtypes = [vp, vp, vp, ctypes.c_double, vp]
-    for name in EXPORTS:
-        f = getattr(L, name)
-        if f.restype is ctypes.c_int and name not in ("qg_strerror",):
-            pass
     _lib = L
     return L
 

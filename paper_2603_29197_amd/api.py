@@ -92,10 +92,55 @@ def analyze(prob) -> dict:
         lib().qg_symbolic_free(h)
 
 
-class Solver:
-    """One device handle (qg_setup ... qg_cleanup) for a fixed sparsity pattern."""
+class TorchDeviceMemory:
+    """Device memory for a handle from PyTorch's caching allocator: every block
+    the library asks for is a uint8 tensor kept alive here until the library
+    gives it back, so torch's memory counters see the handle's footprint.
+    ``source(nbytes)`` may replace the default tensor factory (it returns a
+    tensor of at least ``nbytes`` bytes, or None to refuse)."""
 
-    def __init__(self, prob, settings: Optional[qg_settings] = None, stream=None, **kw):
+    ALIGN = 256
+
+    def __init__(self, torch, source=None):
+        self.torch = torch
+        self.source = source
+        self.live = {}
+        self.calls = 0
+        self.c_alloc = _lib.ALLOC_FN(self._alloc)
+        self.c_free = _lib.FREE_FN(self._free)
+
+    def _alloc(self, ctx, nbytes):
+        self.calls += 1
+        try:
+            t = self.source(int(nbytes)) if self.source is not None else \
+                self.torch.empty(int(nbytes), dtype=self.torch.uint8, device="cuda")
+        except Exception:      # an allocator failure becomes QG_ERR_OOM in the library
+            return None
+        if t is None:
+            return None
+        ptr = int(t.data_ptr())
+        if ptr % self.ALIGN:
+            return None
+        self.live[ptr] = t
+        return ptr
+
+    def _free(self, ctx, ptr):
+        if ptr:
+            self.live.pop(int(ptr), None)
+
+    @property
+    def nbytes(self) -> int:
+        return sum(int(t.numel()) for t in self.live.values())
+
+
+class Solver:
+    """One device handle (qg_setup ... qg_cleanup) for a fixed sparsity pattern.
+
+    ``memory``: "torch" (default) routes every device allocation of the handle
+    through PyTorch's caching allocator; "hip" lets the library call hipMalloc;
+    a callable ``f(nbytes) -> tensor | None`` supplies the blocks itself."""
+
+    def __init__(self, prob, settings: Optional[qg_settings] = None, stream=None, memory="torch", **kw):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("a HIP device is required")
@@ -105,9 +150,16 @@ class Solver:
         self.N = self.n + self.m + self.p
         self.settings = settings if settings is not None else default_settings(**kw)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.nsolve = 0          # solves run on this handle (checked by the autograd functions)
         P, A, G, q = _args(prob)
         self._keep = (P, A, G, q)
         self.handle = ctypes.c_void_p()
+        if memory == "hip":
+            self.memory = None
+            hooks = (_lib.ALLOC_FN(), _lib.FREE_FN(), None)
+        else:
+            self.memory = TorchDeviceMemory(torch, None if memory == "torch" else memory)
+            hooks = (self.memory.c_alloc, self.memory.c_free, None)
         c = np.ascontiguousarray(prob.c, dtype=np.float64)
         b = np.ascontiguousarray(prob.b, dtype=np.float64)
         hv = np.ascontiguousarray(prob.h, dtype=np.float64)
@@ -116,7 +168,7 @@ class Solver:
                              b.ctypes.data_as(_lib.c_double_p) if prob.p else None, G.ptr(),
                              hv.ctypes.data_as(_lib.c_double_p) if prob.m else None, prob.l, len(prob.q),
                              q.ctypes.data_as(_lib.c_int32_p), ctypes.byref(self.settings),
-                             ctypes.c_void_p(self.stream.cuda_stream)), "qg_setup")
+                             ctypes.c_void_p(self.stream.cuda_stream), *hooks), "qg_setup")
         self.info = None
 
     # -- lifecycle ------------------------------------------------------------
@@ -148,11 +200,23 @@ class Solver:
 
     def update(self, Pval=None, c=None, Aval=None, b=None, Gval=None, h=None):
         keep = [None if v is None else np.ascontiguousarray(v, dtype=np.float64) for v in (Pval, c, Aval, b, Gval, h)]
+        self._matrix_tokens = {}
         check(lib().qg_update(self.handle, *[_dptr(v) for v in keep]), "qg_update")
+
+    def update_vectors(self, c=None, b=None, h=None):
+        """c, b, h from device tensors (float64 on the handle's device), no host round trip."""
+        t = self.torch
+        keep = [None if v is None else v.detach().to(device="cuda", dtype=t.float64).contiguous()
+                for v in (c, b, h)]
+        for v, w in zip(keep, (self.n, self.p, self.m)):
+            if v is not None and v.numel() != w:
+                raise ValueError("vector length does not match the problem")
+        check(lib().qg_update_vectors(self.handle, *[self._vp(v) for v in keep]), "qg_update_vectors")
 
     def solve(self):
         x, s, y, z = self._empty(self.n), self._empty(self.m), self._empty(self.p), self._empty(self.m)
         info = qg_info()
+        self.nsolve += 1
         check(lib().qg_solve(self.handle, self._vp(x), self._vp(s), self._vp(y), self._vp(z),
                              ctypes.byref(info)), "qg_solve")
         self.info = info.as_dict()
@@ -264,6 +328,38 @@ class Solver:
 def _autograd_function():
     import torch
 
+    def _forward(ctx, c, h, b, Pval, solver, AG):
+        Aval = AG[0] if len(AG) > 0 else None
+        Gval = AG[1] if len(AG) > 1 else None
+        ctx.n_extra = len(AG)
+        # matrix values (fixed pattern) go through the host only when they differ from the values
+        # the handle holds; the vectors are copied device to device
+        token = lambda v: None if v is None else (v.data_ptr(), v._version, tuple(v.shape))
+        mats = {"Pval": Pval, "Aval": Aval, "Gval": Gval}
+        held = getattr(solver, "_matrix_tokens", {})
+        changed = {k: v.detach().cpu().numpy() for k, v in mats.items() if v is not None and held.get(k) != token(v)}
+        if changed:
+            solver.update(**changed)
+            solver._matrix_tokens = {**held, **{k: token(mats[k]) for k in changed}}
+        solver.update_vectors(c=c, b=b, h=h)
+        if not solver.settings.differentiable:
+            solver.set_settings(differentiable=1)
+        x, s, y, z, info = solver.solve()
+        if info["status"] not in (1, 2):
+            raise RuntimeError(f"QGSolve: the solve ended with status {info['status_name']}; there is no "
+                               "solution to differentiate")
+        solver.last = (x, s, y, z, info)
+        ctx.solver = solver
+        ctx.solve_id = solver.nsolve
+        ctx.has = (Pval is not None, Aval is not None, Gval is not None)
+        return x
+
+    def _check_state(ctx):
+        if ctx.solver.nsolve != ctx.solve_id:
+            raise RuntimeError("QGSolve backward: the solver has run another solve since this forward, so its "
+                               "stored factorization and iterate belong to that solve; use one Solver per "
+                               "differentiated solve, or call backward before solving again")
+
     class QGSolve(torch.autograd.Function):
         """x* = QGSolve.apply(c, h, b, Pval, solver[, Aval, Gval]): forward
         updates the values (fixed pattern) and solves; backward returns
@@ -272,21 +368,11 @@ def _autograd_function():
 
         @staticmethod
         def forward(ctx, c, h, b, Pval, solver, *AG):
-            Aval = AG[0] if len(AG) > 0 else None
-            Gval = AG[1] if len(AG) > 1 else None
-            ctx.n_extra = len(AG)
-            host = lambda v: None if v is None else v.detach().cpu().numpy()
-            solver.update(Pval=host(Pval), c=host(c), b=host(b), h=host(h), Aval=host(Aval), Gval=host(Gval))
-            if not solver.settings.differentiable:
-                solver.set_settings(differentiable=1)
-            x, s, y, z, info = solver.solve()
-            solver.last = (x, s, y, z, info)
-            ctx.solver = solver
-            ctx.has = (Pval is not None, Aval is not None, Gval is not None)
-            return x.clone()
+            return _forward(ctx, c, h, b, Pval, solver, AG).clone()
 
         @staticmethod
         def backward(ctx, gx):
+            _check_state(ctx)
             hP, hA, hG = ctx.has
             g = ctx.solver.backward(gx, want_P=hP, want_A=hA, want_G=hG)
             clone = lambda v, has: v.clone() if (has and v is not None) else None
@@ -299,12 +385,13 @@ def _autograd_function():
 
         @staticmethod
         def forward(ctx, c, h, b, Pval, solver, *AG):
-            x = QGSolve.forward(ctx, c, h, b, Pval, solver, *AG)
+            x = _forward(ctx, c, h, b, Pval, solver, AG)
             _, s, y, z, _ = solver.last
-            return x, y.clone(), z.clone(), s.clone()
+            return x.clone(), y.clone(), z.clone(), s.clone()
 
         @staticmethod
         def backward(ctx, gx, gy, gz, gs):
+            _check_state(ctx)
             hP, hA, hG = ctx.has
             g = ctx.solver.backward(gx, want_P=hP, want_A=hA, want_G=hG, dl_dy=gy, dl_dz=gz, dl_ds=gs)
             clone = lambda v, has: v.clone() if (has and v is not None) else None

@@ -111,6 +111,33 @@ static bool finite_all(const double *v, int64_t len) {
     return true;
 }
 
+// Number of non-finite entries over up to three device vectors (NULL skipped), into *bad.
+__global__ void count_nonfinite_kernel(const double *__restrict__ a, int32_t na, const double *__restrict__ b,
+                                       int32_t nb, const double *__restrict__ c, int32_t nc, int32_t *bad) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    int f = 0;
+    if (a && i < na && !isfinite(a[i])) f = 1;
+    if (b && i < nb && !isfinite(b[i])) f = 1;
+    if (c && i < nc && !isfinite(c[i])) f = 1;
+    if (f) atomicAdd(bad, 1);
+}
+
+static int count_nonfinite(qg_handle *h, const double *a, int32_t na, const double *b, int32_t nb,
+                           const double *c, int32_t nc, int *bad) {
+    const int32_t len = std::max({a ? na : 0, b ? nb : 0, c ? nc : 0});
+    *bad = 0;
+    if (len <= 0) return QG_OK;
+    int32_t *cnt = h->d.flag.p;
+    QG_HIP(h, hipMemsetAsync(cnt, 0, sizeof(int32_t), h->stream));
+    count_nonfinite_kernel<<<(len + 255) / 256, 256, 0, h->stream>>>(a, na, b, nb, c, nc, cnt);
+    QG_HIP(h, hipGetLastError());
+    int32_t v = 0;
+    QG_HIP(h, hipMemcpyAsync(&v, cnt, sizeof(v), hipMemcpyDeviceToHost, h->stream));
+    QG_HIP(h, hipStreamSynchronize(h->stream));
+    *bad = v;
+    return QG_OK;
+}
+
 static int allocate_device(qg_handle *h) {
     Device &d = h->d;
     const Plan &pl = h->plan;
@@ -175,16 +202,20 @@ static int allocate_device(qg_handle *h) {
     UP(posG, kp.posG);
 #undef UP
     const size_t N = (size_t)h->N, m = (size_t)h->m;
+    // One factor exists at a time (FP32 while the FP32+IR mode is on, FP64 from the switch on),
+    // so the FP32 fronts, inverses and W blocks are views into the FP64 buffers: 8 bytes per
+    // stored entry instead of 12.
     if ((rc = dalloc(h, d.front64, (size_t)pl.front_total))) return rc;
-    if ((rc = dalloc(h, d.front32, (size_t)pl.front_total))) return rc;
     if ((rc = dalloc(h, d.uvec, (size_t)pl.uv_total))) return rc;
     if ((rc = dalloc(h, d.vwork, (size_t)pl.task_sn.size()))) return rc;
     if ((rc = dalloc(h, d.dinv64, (size_t)pl.dinv_total))) return rc;
-    if ((rc = dalloc(h, d.dinv32, (size_t)pl.dinv_total))) return rc;
     if ((rc = dalloc(h, d.sinv64, (size_t)pl.sinv_total))) return rc;
-    if ((rc = dalloc(h, d.sinv32, (size_t)pl.sinv_total))) return rc;
     if ((rc = dalloc(h, d.w64, (size_t)pl.w_total))) return rc;
-    if ((rc = dalloc(h, d.w32, (size_t)pl.w_total))) return rc;
+    auto view32 = [](DBuf<float> &v, const DBuf<double> &b) { v.p = reinterpret_cast<float *>(b.p); v.n = b.n; };
+    view32(d.front32, d.front64);
+    view32(d.dinv32, d.dinv64);
+    view32(d.sinv32, d.sinv64);
+    view32(d.w32, d.w64);
     if ((rc = dalloc(h, d.ubuf, (size_t)pl.max_r))) return rc;
     if ((rc = dalloc(h, d.vbuf, (size_t)pl.max_r))) return rc;
     if ((rc = dalloc(h, d.nreg, 1))) return rc;
@@ -210,6 +241,7 @@ static int allocate_device(qg_handle *h) {
     if ((rc = dalloc(h, d.scal, 64))) return rc;
     if ((rc = dalloc(h, d.alpha, 4))) return rc;
     if ((rc = dalloc(h, d.amin, 4))) return rc;
+    if ((rc = dalloc(h, d.flag, 1))) return rc;
     // per-block partials: the sparse residual kernels use 256 / RL rows per block
     const size_t nblk = (N + 256 / RL - 1) / (256 / RL) + (size_t)((h->pp.l + h->pp.nsoc + 255) / 256) +
                         (size_t)((h->nbig + 3) / 4) + 1;
@@ -347,14 +379,19 @@ static int create_streams(qg_handle *h) {
 
 int qg_setup(qg_handle **out, qg_int n, qg_int m, qg_int p, const qg_csc *P, const double *c,
              const qg_csc *A, const double *b, const qg_csc *G, const double *hv, qg_int l, qg_int nsoc,
-             const qg_int *q, const qg_settings *s, void *hip_stream) {
+             const qg_int *q, const qg_settings *s, void *hip_stream, qg_alloc_fn alloc, qg_free_fn free_fn,
+             void *alloc_ctx) {
     if (!out) return QG_ERR_ARG;
     *out = nullptr;
+    if ((alloc == nullptr) != (free_fn == nullptr)) return QG_ERR_ARG;
     const auto t0 = std::chrono::steady_clock::now();
     qg_handle *h = new (std::nothrow) qg_handle();
     if (!h) return QG_ERR_OOM;
     if (s) h->st = *s; else qg_default_settings(&h->st);
     h->stream = (hipStream_t)hip_stream;
+    h->alloc = alloc;
+    h->free_fn = free_fn;
+    h->alloc_ctx = alloc_ctx;
     int rc = QG_OK;
     try {
         rc = build_problem_pattern(h->pp, n, m, p, P, A, G, l, nsoc, q, true);
@@ -376,7 +413,7 @@ int qg_setup(qg_handle **out, qg_int n, qg_int m, qg_int p, const qg_csc *P, con
         if ((rc = create_streams(h))) { qg_cleanup(h); return rc; }
         if ((rc = allocate_device(h))) { qg_cleanup(h); return rc; }
         if ((rc = factor_init_attributes(h))) { qg_cleanup(h); return rc; }
-        if ((rc = upload_static_values(h))) { qg_cleanup(h); return rc; }
+        if ((rc = upload_static_values(h, true))) { qg_cleanup(h); return rc; }
         if (hipStreamSynchronize(h->stream) != hipSuccess) { qg_cleanup(h); return QG_ERR_HIP; }
     } catch (const std::bad_alloc &) {
         qg_cleanup(h);
@@ -400,13 +437,31 @@ int qg_update(qg_handle *h, const double *Pval, const double *c, const double *A
     if (Pval) h->pp.P.val.assign(Pval, Pval + h->pp.P.val.size());
     if (Aval) h->pp.A.val.assign(Aval, Aval + h->pp.A.val.size());
     if (Gval) h->pp.G.val.assign(Gval, Gval + h->pp.G.val.size());
-    if (c) h->hc.assign(c, c + h->n);
-    if (b) h->hb.assign(b, b + h->p);
-    if (hv) h->hh.assign(hv, hv + h->m);
     h->solved = false;
     h->final_factor = false;
-    int rc = upload_static_values(h);
+    if (Pval || Aval || Gval) {
+        const int rc = upload_static_values(h, false);
+        if (rc) return rc;
+    }
+    // vectors go straight into the device copies (the host copies only serve setup)
+    if (c && h->n > 0) QG_HIP(h, hipMemcpyAsync(h->d.c.p, c, sizeof(double) * h->n, hipMemcpyHostToDevice, h->stream));
+    if (b && h->p > 0) QG_HIP(h, hipMemcpyAsync(h->d.b.p, b, sizeof(double) * h->p, hipMemcpyHostToDevice, h->stream));
+    if (hv && h->m > 0) QG_HIP(h, hipMemcpyAsync(h->d.h.p, hv, sizeof(double) * h->m, hipMemcpyHostToDevice, h->stream));
+    QG_HIP(h, hipStreamSynchronize(h->stream));
+    return QG_OK;
+}
+
+int qg_update_vectors(qg_handle *h, const double *c, const double *b, const double *hv) {
+    if (!h) return QG_ERR_ARG;
+    int bad = 0;
+    int rc = count_nonfinite(h, c, h->n, b, h->p, hv, h->m, &bad);
     if (rc) return rc;
+    if (bad) return QG_ERR_NONFINITE;
+    h->solved = false;
+    h->final_factor = false;
+    if (c && h->n > 0) QG_HIP(h, hipMemcpyAsync(h->d.c.p, c, sizeof(double) * h->n, hipMemcpyDeviceToDevice, h->stream));
+    if (b && h->p > 0) QG_HIP(h, hipMemcpyAsync(h->d.b.p, b, sizeof(double) * h->p, hipMemcpyDeviceToDevice, h->stream));
+    if (hv && h->m > 0) QG_HIP(h, hipMemcpyAsync(h->d.h.p, hv, sizeof(double) * h->m, hipMemcpyDeviceToDevice, h->stream));
     QG_HIP(h, hipStreamSynchronize(h->stream));
     return QG_OK;
 }

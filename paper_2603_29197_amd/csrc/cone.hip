@@ -17,16 +17,10 @@
 //   Max step (u interior): orthant -u/du for du < 0; SOC with uJ = sqrt(u'Ju),
 //   ub = u/uJ, rho0 = ub'J du/uJ, rho1 = (du1 - ((rho0 uJ + du0)/(1+ub0)) ub1)/uJ:
 //   1/max(0, |rho1| - rho0).
+#include "cone_math.hpp"
 #include "vec.hpp"
 
 namespace qg {
-
-__device__ inline double jnorm(const double *u, int32_t q) {
-    double n1 = 0.0;
-    for (int32_t a = 1; a < q; ++a) n1 += u[a] * u[a];
-    n1 = sqrt(n1);
-    return sqrt((u[0] - n1) * (u[0] + n1));
-}
 
 // out = beta * Wb u  (inv = 0)   or   (1/beta) J Wb J u  (inv = 1)
 __device__ inline void soc_w_apply(const double *wb, double beta, const double *u, double *out, int32_t q,
@@ -276,19 +270,7 @@ __global__ void step_kernel(int32_t l, int32_t nsoc, const int32_t *__restrict__
     } else if (t - l < nsoc && soc_off[t - l + 1] - soc_off[t - l] < QBIG) {
         const int32_t k = t - l;
         const int32_t off = soc_off[k], q = soc_off[k + 1] - off;
-        const double *uk = u + off, *dk = du + off;
-        const double uJ = jnorm(uk, q);
-        double r0 = uk[0] / uJ * dk[0];
-        for (int32_t c = 1; c < q; ++c) r0 -= uk[c] / uJ * dk[c];
-        r0 /= uJ;
-        const double coef = (r0 * uJ + dk[0]) / (1.0 + uk[0] / uJ);
-        double n1 = 0.0;
-        for (int32_t c = 1; c < q; ++c) {
-            const double v = (dk[c] - coef * (uk[c] / uJ)) / uJ;
-            n1 += v * v;
-        }
-        const double den = sqrt(n1) - r0;
-        if (den > 0.0) a = 1.0 / den;
+        a = soc_max_step(u + off, du + off, q);
     }
     // wave min, then one atomic per wave
     for (int off = 32; off > 0; off >>= 1) a = fmin(a, __shfl_xor(a, off));

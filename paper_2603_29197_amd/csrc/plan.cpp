@@ -15,12 +15,34 @@ int hip_fail(qg_handle *h, hipError_t e) {
     return e == hipErrorOutOfMemory ? QG_ERR_OOM : QG_ERR_HIP;
 }
 
+// Device memory of the handle: through the caller's allocator when one was
+// given to qg_setup, else hipMalloc.  A buffer that already has the requested
+// length is kept (value updates re-upload into the same memory).
+void *dmem_alloc(qg_handle *h, size_t bytes) {
+    if (h->alloc) {
+        void *p = h->alloc(h->alloc_ctx, bytes);
+        h->alloc_refused = (p == nullptr);
+        return p;
+    }
+    void *p = nullptr;
+    const hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) { h->last_hip = (int)e; (void)hipGetLastError(); return nullptr; }
+    return p;
+}
+
+void dmem_free(qg_handle *h, void *p) {
+    if (!p) return;
+    if (h->alloc) { if (h->free_fn) h->free_fn(h->alloc_ctx, p); }
+    else (void)hipFree(p);
+}
+
 template <typename T>
 int dalloc(qg_handle *h, DBuf<T> &b, size_t n) {
-    if (b.p) { (void)hipFree(b.p); b.p = nullptr; b.n = 0; }
     if (n == 0) n = 1;
-    hipError_t e = hipMalloc((void **)&b.p, n * sizeof(T));
-    if (e != hipSuccess) { b.p = nullptr; return hip_fail(h, e); }
+    if (b.p && b.n == n) return QG_OK;
+    if (b.p) { dmem_free(h, b.p); b.p = nullptr; b.n = 0; }
+    b.p = (T *)dmem_alloc(h, n * sizeof(T));
+    if (!b.p) return QG_ERR_OOM;
     b.n = n;
     return QG_OK;
 }
@@ -46,31 +68,33 @@ template int dupload<int64_t>(qg_handle *, DBuf<int64_t> &, const std::vector<in
 template int dupload<int8_t>(qg_handle *, DBuf<int8_t> &, const std::vector<int8_t> &);
 
 template <typename T>
-static void dfree(DBuf<T> &b) {
-    if (b.p) (void)hipFree(b.p);
+static void dfree_(qg_handle *h, DBuf<T> &b) {
+    dmem_free(h, b.p);
     b.p = nullptr;
     b.n = 0;
 }
 
 void dfree_all(qg_handle *h) {
     Device &d = h->d;
-    dfree(d.kval); dfree(d.blk33); dfree(d.blk_off); dfree(d.soc_off); dfree(d.big_cones); dfree(d.big_chunk_cone); dfree(d.big_chunk_start); dfree(d.bigsc); dfree(d.kr_ptr);
-    dfree(d.kr_col); dfree(d.kr_val); dfree(d.c); dfree(d.b); dfree(d.h); dfree(d.Pp); dfree(d.Pi);
-    dfree(d.Ap); dfree(d.Ai); dfree(d.Gp); dfree(d.Gi); dfree(d.posG);
-    dfree(d.perm); dfree(d.iperm);
-    dfree(d.sn_first); dfree(d.sn_rows); dfree(d.task_sn); dfree(d.task_col);
-    dfree(d.ctb_src); dfree(d.ch_ptr); dfree(d.ch_list);
-    dfree(d.lvl_small_sn); dfree(d.sn_rptr); dfree(d.fr_off); dfree(d.task_ptr);
-    dfree(d.ctb_ptr); dfree(d.uv_off); dfree(d.reg_sign);
-    dfree(d.ent_dst); dfree(d.ent_sptr); dfree(d.ent_src); dfree(d.ent_reg); dfree(d.zseg_off);
-    dfree(d.zseg_len);
-    dfree(d.front64); dfree(d.front32); dfree(d.uvec); dfree(d.dinv64); dfree(d.dinv32);
-    dfree(d.sinv64); dfree(d.sinv32); dfree(d.w64); dfree(d.w32); dfree(d.ubuf);
-    dfree(d.vbuf); dfree(d.col2sn); dfree(d.nreg); dfree(d.vwork); dfree(d.task0);
-    dfree(d.x); dfree(d.y); dfree(d.s); dfree(d.z); dfree(d.rx); dfree(d.ry); dfree(d.rz);
-    dfree(d.kx); dfree(d.rhs); dfree(d.sol); dfree(d.res); dfree(d.corr); dfree(d.xp);
-    dfree(d.dsa); dfree(d.ds); dfree(d.t); dfree(d.lam); dfree(d.w); dfree(d.wbar); dfree(d.beta);
-    dfree(d.scal); dfree(d.amin); dfree(d.partials); dfree(d.zcone); dfree(d.alpha);
+    // FP32 factor buffers are views into the FP64 ones (a factor is in one precision at a time)
+    d.front32 = {}; d.dinv32 = {}; d.sinv32 = {}; d.w32 = {};
+    dfree_(h, d.kval); dfree_(h, d.blk33); dfree_(h, d.blk_off); dfree_(h, d.soc_off); dfree_(h, d.big_cones); dfree_(h, d.big_chunk_cone); dfree_(h, d.big_chunk_start); dfree_(h, d.bigsc); dfree_(h, d.kr_ptr);
+    dfree_(h, d.kr_col); dfree_(h, d.kr_val); dfree_(h, d.c); dfree_(h, d.b); dfree_(h, d.h); dfree_(h, d.Pp); dfree_(h, d.Pi);
+    dfree_(h, d.Ap); dfree_(h, d.Ai); dfree_(h, d.Gp); dfree_(h, d.Gi); dfree_(h, d.posG);
+    dfree_(h, d.perm); dfree_(h, d.iperm);
+    dfree_(h, d.sn_first); dfree_(h, d.sn_rows); dfree_(h, d.task_sn); dfree_(h, d.task_col);
+    dfree_(h, d.ctb_src); dfree_(h, d.ch_ptr); dfree_(h, d.ch_list);
+    dfree_(h, d.lvl_small_sn); dfree_(h, d.sn_rptr); dfree_(h, d.fr_off); dfree_(h, d.task_ptr);
+    dfree_(h, d.ctb_ptr); dfree_(h, d.uv_off); dfree_(h, d.reg_sign);
+    dfree_(h, d.ent_dst); dfree_(h, d.ent_sptr); dfree_(h, d.ent_src); dfree_(h, d.ent_reg); dfree_(h, d.zseg_off);
+    dfree_(h, d.zseg_len);
+    dfree_(h, d.front64); dfree_(h, d.uvec); dfree_(h, d.dinv64);
+    dfree_(h, d.sinv64); dfree_(h, d.w64); dfree_(h, d.ubuf);
+    dfree_(h, d.vbuf); dfree_(h, d.col2sn); dfree_(h, d.nreg); dfree_(h, d.vwork); dfree_(h, d.task0);
+    dfree_(h, d.x); dfree_(h, d.y); dfree_(h, d.s); dfree_(h, d.z); dfree_(h, d.rx); dfree_(h, d.ry); dfree_(h, d.rz);
+    dfree_(h, d.kx); dfree_(h, d.rhs); dfree_(h, d.sol); dfree_(h, d.res); dfree_(h, d.corr); dfree_(h, d.xp);
+    dfree_(h, d.dsa); dfree_(h, d.ds); dfree_(h, d.t); dfree_(h, d.lam); dfree_(h, d.w); dfree_(h, d.wbar); dfree_(h, d.beta);
+    dfree_(h, d.scal); dfree_(h, d.amin); dfree_(h, d.partials); dfree_(h, d.zcone); dfree_(h, d.alpha); dfree_(h, d.flag);
 }
 
 // Fronts of the device factorization.  The analysis' supernodes are kept,
@@ -446,7 +470,7 @@ int build_plan(qg_handle *h) {
     return QG_OK;
 }
 
-int upload_static_values(qg_handle *h) {
+int upload_static_values(qg_handle *h, bool vectors) {
     const ProblemPattern &pp = h->pp;
     const KktPattern &kp = h->kp;
     const int32_t n = h->n, p = h->p, N = h->N;
@@ -494,6 +518,7 @@ int upload_static_values(qg_handle *h) {
     if ((rc = dupload(h, h->d.kr_ptr, rp))) return rc;
     if ((rc = dupload(h, h->d.kr_col, rc_))) return rc;
     if ((rc = dupload(h, h->d.kr_val, rv))) return rc;
+    if (!vectors) return QG_OK;
     if ((rc = dupload(h, h->d.c, h->hc))) return rc;
     if ((rc = dupload(h, h->d.b, h->hb))) return rc;
     if ((rc = dupload(h, h->d.h, h->hh))) return rc;

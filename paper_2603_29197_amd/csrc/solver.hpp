@@ -130,6 +130,7 @@ struct Device {
     DBuf<int32_t> zcone;        // per z row: SOC index (-1 on the orthant)
     DBuf<double> alpha;         // step lengths of the last iteration (affine, combined)
     DBuf<unsigned long long> amin;          // step-length minima (ordered bits)
+    DBuf<int32_t> flag;         // count of non-finite entries (qg_update_vectors)
 };
 
 // Timing helper around HIP events on the handle's stream.
@@ -149,6 +150,11 @@ struct qg_handle {
     hipEvent_t ev_panel = nullptr, ev_bulk = nullptr, ev_prep = nullptr;
     int last_hip = 0;
     int device = 0;
+    // device memory of the handle: the caller's allocator (qg_setup), or hipMalloc when NULL
+    qg_alloc_fn alloc = nullptr;
+    qg_free_fn free_fn = nullptr;
+    void *alloc_ctx = nullptr;
+    bool alloc_refused = false;
     qg::ProblemPattern pp;
     qg::KktPattern kp;
     qg::Symbolic sym;                  // the analysis (supernodes, permutation)
@@ -181,6 +187,8 @@ int hip_fail(qg_handle *h, hipError_t e);
         if (e_ != hipSuccess) return qg::hip_fail(h, e_); \
     } while (0)
 
+void *dmem_alloc(qg_handle *h, size_t bytes);
+void dmem_free(qg_handle *h, void *p);
 template <typename T>
 int dalloc(qg_handle *h, DBuf<T> &b, size_t n);
 template <typename T>
@@ -189,7 +197,7 @@ void dfree_all(qg_handle *h);
 
 int group_fronts(const Symbolic &sym, Symbolic &fronts);
 int build_plan(qg_handle *h);
-int upload_static_values(qg_handle *h);
+int upload_static_values(qg_handle *h, bool vectors);
 
 // device phases (all enqueue on h->stream)
 int launch_scaling(qg_handle *h, const double *s, const double *z, double *lam, int block);

@@ -257,6 +257,7 @@ def workload(name: str) -> Problem:
         "lasso_s": lambda: lasso(2000, 1000, 0.02, seed=BASE_SEED + 12),
         "many_soc_s": lambda: many_soc(3000, 1000, 4, 1000, seed=BASE_SEED + 13),
         "huber_s": lambda: huber(10000, 4000, 40, seed=BASE_SEED + 14),
+        "huber_t": lambda: huber(2500, 1000, 40, seed=BASE_SEED + 17),
         "lasso_diff_s": lambda: lasso(2500, 1000, 0.016, seed=BASE_SEED + 15),
         # large second-order cones: 3000 of 64 entries, 300 of 256, 30 of 1024 (m = 304520)
         "big_cones": lambda: many_soc(20000, q=[64] * 3000 + [256] * 300 + [1024] * 30, nbounds=5000,

@@ -1,0 +1,290 @@
+"""The boundary and the failure paths on the device, through the C ABI:
+
+- device memory of a handle through the caller's allocator (PyTorch's caching
+  allocator by default), a refusing allocator giving QG_ERR_OOM with nothing
+  left allocated, and the hipMalloc path giving the same bits;
+- vector updates from device memory, non-finite updates rejected;
+- the autograd function refusing gradients of a solve that was replaced, and
+  solves that did not converge;
+- failure modes of the method: an infeasible and an unbounded problem end
+  in MAX_ITER or NUMERICAL_ERROR, an FP32 refinement that cannot pass its
+  test switches the step to FP64, and the phase counts of the iteration
+  (one factorization and two solves per Newton step, paper Sec. 2.2).
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+torch = pytest.importorskip("torch")
+
+from oracle import ipm as oipm  # noqa: E402
+from synth import problems  # noqa: E402
+from synth.problems import Problem, _csc  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def solver(prob, **kw):
+    import paper_2603_29197_amd as qg
+    print(f"[gpu] setup {prob.name} n={prob.n} m={prob.m} p={prob.p} {kw}", flush=True)
+    return qg.Solver(prob, **kw)
+
+
+def lp(c, G, h, A=None, b=None, name="lp"):
+    n = len(c)
+    A = np.zeros((0, n)) if A is None else np.asarray(A, float)
+    G = np.asarray(G, float)
+    return Problem(n=n, m=G.shape[0], p=A.shape[0], P=_csc(sp.csc_matrix((n, n))), c=np.asarray(c, float),
+                   A=_csc(sp.csc_matrix(A)), b=np.zeros(A.shape[0]) if b is None else np.asarray(b, float),
+                   G=_csc(sp.csc_matrix(G)), h=np.asarray(h, float), l=G.shape[0], q=[], name=name)
+
+
+# ---------------------------------------------------------------------------
+# device memory through the caller's allocator
+# ---------------------------------------------------------------------------
+def test_torch_allocator_holds_the_handles_memory():
+    prob = problems.workload("lasso_s")
+    torch.cuda.synchronize()
+    before = torch.cuda.memory_allocated()
+    S = solver(prob)
+    held = S.memory.nbytes
+    grown = torch.cuda.memory_allocated() - before
+    print(f"[gpu] handle holds {held} bytes in {len(S.memory.live)} torch blocks; torch counter grew {grown}",
+          flush=True)
+    assert held > 0 and len(S.memory.live) > 20
+    assert grown >= held
+    x, s, y, z, info = S.solve()
+    assert info["status"] == 1
+    S.close()
+    assert not S.memory.live
+    del x, s, y, z
+    torch.cuda.synchronize()
+    assert torch.cuda.memory_allocated() <= before
+
+
+@pytest.mark.parametrize("refuse_at", [1, 7, 40])
+def test_refusing_allocator_gives_oom_and_returns_everything(refuse_at):
+    import paper_2603_29197_amd as qg
+    from paper_2603_29197_amd._lib import QGError
+    prob = problems.workload("small_qp")
+    calls = {"n": 0}
+
+    def source(nbytes):
+        calls["n"] += 1
+        if calls["n"] >= refuse_at:
+            return None
+        return torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+
+    with pytest.raises(QGError) as e:
+        qg.Solver(prob, memory=source)
+    assert e.value.code == -4
+    assert calls["n"] == refuse_at
+    # a fresh solver on the same source state would refuse at once; a normal one still works
+    S = solver(prob)
+    assert S.solve()[4]["status"] == 1
+    S.close()
+
+
+def test_refusing_allocator_leaves_nothing_held():
+    import paper_2603_29197_amd as qg
+    from paper_2603_29197_amd._lib import QGError
+    from paper_2603_29197_amd.api import TorchDeviceMemory
+    prob = problems.workload("small_qp")
+    state = {"n": 0}
+
+    def source(nbytes):
+        state["n"] += 1
+        return None if state["n"] > 25 else torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+
+    mem = {}
+    orig = TorchDeviceMemory.__init__
+
+    def spy(self, *a, **k):
+        orig(self, *a, **k)
+        mem["m"] = self
+
+    TorchDeviceMemory.__init__ = spy
+    try:
+        with pytest.raises(QGError):
+            qg.Solver(prob, memory=source)
+    finally:
+        TorchDeviceMemory.__init__ = orig
+    assert state["n"] == 26 and not mem["m"].live
+
+
+def test_hip_allocator_gives_the_same_bits():
+    import paper_2603_29197_amd as qg
+    prob = problems.workload("huber_t")
+    out = []
+    for memory in ("torch", "hip"):
+        S = solver(prob, memory=memory, precision=qg.QG_FP32_IR)
+        x, s, y, z, info = S.solve()
+        out.append((host(x).copy(), info["iters"], info["ir_steps"]))
+        S.close()
+    assert out[0][1:] == out[1][1:]
+    assert np.array_equal(out[0][0], out[1][0])
+
+
+# ---------------------------------------------------------------------------
+# value updates from device memory
+# ---------------------------------------------------------------------------
+def test_device_vector_update_matches_host_update():
+    prob = problems.workload("small_qp")
+    rng = np.random.default_rng(40)
+    c2 = prob.c + 0.1 * rng.standard_normal(prob.n)
+    b2 = prob.b + 0.01 * rng.standard_normal(prob.p)
+    h2 = prob.h + 0.05 * rng.uniform(0, 1, prob.m)
+    S1, S2 = solver(prob), solver(prob)
+    S1.update(c=c2, b=b2, h=h2)
+    S2.update_vectors(c=dev(c2), b=dev(b2), h=dev(h2))
+    x1 = host(S1.solve()[0])
+    x2 = host(S2.solve()[0])
+    assert np.array_equal(x1, x2)
+    pr2 = Problem(**{**prob.__dict__})
+    pr2.c, pr2.b, pr2.h = c2, b2, h2
+    ref = oipm.solve(pr2)
+    assert np.max(np.abs(x2 - ref.x)) <= 1e-6 * max(1.0, np.max(np.abs(ref.x)))
+    S1.close()
+    S2.close()
+
+
+def test_nonfinite_device_update_is_rejected():
+    from paper_2603_29197_amd._lib import QGError
+    prob = problems.workload("small_qp")
+    S = solver(prob)
+    x0 = host(S.solve()[0]).copy()
+    bad = prob.c.copy()
+    bad[5] = np.nan
+    with pytest.raises(QGError) as e:
+        S.update_vectors(c=dev(bad))
+    assert e.value.code == -3
+    bad = prob.h.copy()
+    bad[-1] = -np.inf
+    with pytest.raises(QGError) as e:
+        S.update_vectors(h=dev(bad))
+    assert e.value.code == -3
+    assert np.array_equal(host(S.solve()[0]), x0)      # values unchanged
+    S.close()
+
+
+# ---------------------------------------------------------------------------
+# the autograd function's state checks
+# ---------------------------------------------------------------------------
+def test_backward_after_another_solve_is_refused():
+    import paper_2603_29197_amd as qg
+    prob = problems.lasso(rows=120, cols=60, density=0.1, seed=9)
+    S = solver(prob, differentiable=1)
+    c = torch.tensor(prob.c, device="cuda", requires_grad=True)
+    h = torch.tensor(prob.h, device="cuda", requires_grad=True)
+    b = torch.tensor(prob.b, device="cuda", requires_grad=True)
+    x1 = qg.QGSolve.apply(c, h, b, None, S)
+    x2 = qg.QGSolve.apply(c * 1.01, h, b, None, S)        # the same Solver again
+    with pytest.raises(RuntimeError, match="another solve"):
+        (x1.sum() + x2.sum()).backward()
+    # the last solve's node is still differentiable on its own
+    c.grad = None
+    x3 = qg.QGSolve.apply(c, h, b, None, S)
+    x3.sum().backward()
+    assert c.grad is not None and torch.isfinite(c.grad).all()
+    S.close()
+
+
+def test_unchanged_matrix_values_skip_the_host_update():
+    import paper_2603_29197_amd as qg
+    prob = problems.small_qp(n=40, p=10, m=40, mrows=20, density=0.2, seed=41)
+    S = solver(prob, differentiable=1)
+    calls = {"n": 0}
+    orig = S.update
+
+    def counting_update(**kw):
+        calls["n"] += 1
+        return orig(**kw)
+
+    S.update = counting_update
+    c = torch.tensor(prob.c, device="cuda", requires_grad=True)
+    h = torch.tensor(prob.h, device="cuda")
+    b = torch.tensor(prob.b, device="cuda")
+    Pv = torch.tensor(prob.P.data, device="cuda", requires_grad=True)
+    for _ in range(3):
+        x = qg.QGSolve.apply(c, h, b, Pv, S)
+        x.sum().backward()
+    assert calls["n"] == 1
+    with torch.no_grad():
+        Pv.mul_(1.0)                                      # in place: a new version of the values
+    qg.QGSolve.apply(c, h, b, Pv, S)
+    assert calls["n"] == 2
+    S.close()
+
+
+def test_forward_refuses_an_unsolved_problem():
+    import paper_2603_29197_amd as qg
+    prob = lp([1.0], [[-1.0], [1.0]], [-1.0, 0.0], name="infeasible_1d")    # x >= 1 and x <= 0
+    S = solver(prob, max_iter=25)
+    c = torch.tensor(prob.c, device="cuda", requires_grad=True)
+    with pytest.raises(RuntimeError, match="status"):
+        qg.QGSolve.apply(c, dev(prob.h), dev(prob.b), None, S)
+    S.close()
+
+
+# ---------------------------------------------------------------------------
+# failure modes and phase counts of the iteration
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("case", ["infeasible", "unbounded"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_infeasible_and_unbounded_problems_end_unsolved(case, prec):
+    import paper_2603_29197_amd as qg
+    if case == "infeasible":     # x1 + x2 >= 2, x1 <= 0, x2 <= 0
+        prob = lp([1.0, 1.0], [[-1.0, -1.0], [1.0, 0.0], [0.0, 1.0]], [-2.0, 0.0, 0.0], name="infeasible")
+    else:                        # minimize -x1 with x1 >= 0, x2 free in 0 <= x2 <= 1
+        prob = lp([-1.0, 0.0], [[-1.0, 0.0], [0.0, -1.0], [0.0, 1.0]], [0.0, 0.0, 1.0], name="unbounded")
+    S = solver(prob, max_iter=40, precision=qg.QG_FP64 if prec == "fp64" else qg.QG_FP32_IR)
+    _, _, _, _, info = S.solve()
+    print(f"[gpu] {case} {prec}: {info['status_name']} after {info['iters']} iterations", flush=True)
+    assert info["status"] in (-1, -2), info["status_name"]
+    S.close()
+
+
+def test_fp32_refinement_failure_switches_to_fp64():
+    """One correction per solve with an FP32 factor cannot reach the refinement test: the first
+    Newton step runs again with an FP64 factor and FP64 stays; the solution is the oracle's."""
+    import paper_2603_29197_amd as qg
+    prob = problems.workload("small_qp")
+    S = solver(prob, precision=qg.QG_FP32_IR, ir_max32=1)
+    x, s, y, z, info = S.solve()
+    print(f"[gpu] ir_max32=1: status {info['status_name']} switch {info['switch_iter']} iters {info['iters']} "
+          f"factorizations {info['nfactor']} fp32/fp64 triangular solves {info['ntrisolve'][1]}/"
+          f"{info['ntrisolve'][0]}", flush=True)
+    assert info["status"] == 1
+    assert info["switch_iter"] == 0
+    ref = oipm.solve(prob)
+    assert np.max(np.abs(host(x) - ref.x)) <= 1e-6 * max(1.0, np.max(np.abs(ref.x)))
+    # the initial solve with the FP32 factor failed too and was redone in FP64: every Newton step
+    # factors in FP64 (plus the initial FP32 + FP64 pair and the repeated first step)
+    assert info["nfactor"] >= info["iters"] + 2
+    S.close()
+
+
+@pytest.mark.parametrize("name", ["small_qp", "many_soc_s"])
+@pytest.mark.parametrize("differentiable", [0, 1])
+def test_phase_counts_one_factor_two_solves_per_step(name, differentiable):
+    """FP64 mode: the initial point costs one factorization and one solve, every Newton step one
+    factorization and two solves (paper Sec. 2.2); a differentiable solve adds the one FP64
+    factorization of the derivative system."""
+    import paper_2603_29197_amd as qg
+    prob = problems.workload(name)
+    S = solver(prob, precision=qg.QG_FP64, differentiable=differentiable)
+    _, _, _, _, info = S.solve()
+    assert info["status"] == 1
+    k = info["iters"]
+    assert info["nfactor"] == k + 1 + differentiable, (info["nfactor"], k)
+    assert info["nsolve"] == 2 * k + 1, (info["nsolve"], k)
+    assert info["switch_iter"] == -1 and info["ntrisolve"][1] == 0
+    S.close()

@@ -144,3 +144,44 @@ def test_invalid_inputs_are_rejected():
     with pytest.raises(QGError) as e:
         qg.analyze(bad)
     assert e.value.code == -1
+
+
+def _raw_setup(prob, hooks=None):
+    """qg_setup through the C ABI with host data only; returns the code.  Every case below is
+    rejected by validation, which runs before any device call."""
+    import ctypes
+    from paper_2603_29197_amd import _lib, api
+    P, A, G, q = api._args(prob)
+    c = np.ascontiguousarray(prob.c, dtype=np.float64)
+    b = np.ascontiguousarray(prob.b, dtype=np.float64)
+    hv = np.ascontiguousarray(prob.h, dtype=np.float64)
+    h = ctypes.c_void_p()
+    hooks = hooks or (_lib.ALLOC_FN(), _lib.FREE_FN(), None)
+    rc = _lib.lib().qg_setup(ctypes.byref(h), prob.n, prob.m, prob.p, P.ptr(), c.ctypes.data_as(_lib.c_double_p),
+                             A.ptr(), b.ctypes.data_as(_lib.c_double_p), G.ptr(),
+                             hv.ctypes.data_as(_lib.c_double_p), prob.l, len(prob.q),
+                             q.ctypes.data_as(_lib.c_int32_p), None, None, *hooks)
+    assert not h.value
+    return rc
+
+
+@pytest.mark.parametrize("where", ["c", "b", "h", "P", "A", "G"])
+def test_nonfinite_data_is_rejected_before_the_device(where):
+    """NaN or Inf anywhere in the data gives QG_ERR_NONFINITE from qg_setup."""
+    prob = problems.small_qp(n=20, p=4, m=10, mrows=10)
+    for bad_value in (np.nan, np.inf):
+        bad = problems.Problem(**{**prob.__dict__})
+        if where in ("c", "b", "h"):
+            v = getattr(prob, where).copy(); v[3] = bad_value
+            setattr(bad, where, v)
+        else:
+            M = getattr(prob, where).copy(); M.data[2] = bad_value
+            setattr(bad, where, M)
+        assert _raw_setup(bad) == -3, (where, bad_value)
+
+
+def test_allocator_hooks_must_come_in_pairs():
+    from paper_2603_29197_amd import _lib
+    prob = problems.small_qp(n=20, p=4, m=10, mrows=10)
+    only_alloc = (_lib.ALLOC_FN(lambda ctx, nbytes: None), _lib.FREE_FN(), None)
+    assert _raw_setup(prob, only_alloc) == -1

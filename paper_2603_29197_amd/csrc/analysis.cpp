@@ -22,10 +22,12 @@
 //     r = width(G) + colcount[first(T)];
 //  8. row list of a supernode = its columns followed by the rows below it.
 #include "analysis.hpp"
+#include "workpool.hpp"
 
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <set>
 #include <stdexcept>
@@ -192,7 +194,6 @@ struct QuotientGraph {
     int32_t N;
     std::vector<std::vector<int32_t>> A, E, Lel;
     std::vector<int64_t> nv, deg, wtot, wcur;
-    std::vector<int64_t> wstamp;
     std::vector<int8_t> status;
     std::vector<int32_t> head, next, tail;  // member chains
     std::vector<int64_t> mark;
@@ -241,6 +242,34 @@ struct DegreeHeap {
         place(k, v);
     }
     void push(int32_t v) { heap.push_back(v); up(heap.size() - 1); }
+    // Remove every variable of vs that is in the heap (in bulk: filter and
+    // rebuild when vs is a large part of the heap, one by one otherwise).
+    void remove_many(const std::vector<int32_t> &vs) {
+        if (vs.size() * 8 < heap.size()) {
+            for (int32_t v : vs) if (contains(v)) remove(v);
+            return;
+        }
+        for (int32_t v : vs) if (contains(v)) pos[v] = -2;     // marked for removal
+        size_t k = 0;
+        for (int32_t v : heap) if (pos[v] != -2) heap[k++] = v;
+        heap.resize(k);
+        for (int32_t v : vs) if (pos[v] == -2) pos[v] = -1;
+        rebuild();
+    }
+    // Insert every variable of vs with its current key.
+    void push_many(const std::vector<int32_t> &vs) {
+        if (vs.size() * 8 < heap.size()) {
+            for (int32_t v : vs) push(v);
+            return;
+        }
+        heap.insert(heap.end(), vs.begin(), vs.end());
+        rebuild();
+    }
+    // Restore the heap order over the whole array (Floyd), positions included.
+    void rebuild() {
+        for (size_t k = 0; k < heap.size(); ++k) pos[heap[k]] = (int32_t)k;
+        for (size_t k = heap.size() / 2; k-- > 0;) down(k);
+    }
     bool contains(int32_t v) const { return pos[v] >= 0; }
     void remove(int32_t v) {
         const size_t k = (size_t)pos[v];
@@ -267,7 +296,6 @@ void min_degree_order(int32_t N, const std::vector<int64_t> &Gp, const std::vect
     g.N = N;
     g.A.resize(N); g.E.resize(N); g.Lel.resize(N);
     g.nv.assign(N, 1); g.deg.assign(N, 0); g.wtot.assign(N, 0); g.wcur.assign(N, 0);
-    g.wstamp.assign(N, -1);
     g.status.assign(N, VAR);
     g.head.resize(N); g.next.assign(N, -1); g.tail.resize(N);
     g.mark.assign(N, 0);
@@ -287,30 +315,62 @@ void min_degree_order(int32_t N, const std::vector<int64_t> &Gp, const std::vect
     order.clear();
     order.reserve(N);
     int64_t rem = N;
-    int64_t pivot_id = 0;
-    std::vector<int32_t> Lp, members;
+    std::vector<int32_t> Lp, members, rest, merged_buf;
     std::vector<std::pair<uint64_t, int32_t>> keyed;
     std::vector<uint64_t> hslot, hashes;     // hash count table (open addressing) and Lp's hashes
     std::vector<int32_t> hcount;
+    std::vector<size_t> run_end;
+    std::vector<int32_t> elist;              // live elements adjacent to Lp (degree update)
+    std::vector<int64_t> estamp((size_t)N, 0);
+    int64_t estamp_id = 0;
+    std::mutex elist_mu;
+    // Loops over Lp whose iterations are independent run on the pool when Lp is long (the
+    // dense final phase, where Lp holds most of the remaining variables).
+    WorkPool pool(WorkPool::default_threads());
+    constexpr size_t PAR_MIN = 2048;
+    auto for_lp = [&](const std::function<void(int64_t, int64_t)> &fn) {
+        if (Lp.size() >= PAR_MIN) pool.run((int64_t)Lp.size(), fn);
+        else fn(0, (int64_t)Lp.size());
+    };
     while (!pq.heap.empty()) {
         const int32_t p = pq.pop();
-        ++pivot_id;
         // members of p in increasing order
         members.clear();
         for (int32_t v = g.head[p]; v != -1; v = g.next[v]) members.push_back(v);
         std::sort(members.begin(), members.end());
         order.insert(order.end(), members.begin(), members.end());
-        // Lp = (A_p U union L_e) \ {p}
+        // Lp = (A_p U union L_e) \ {p}, sorted: A_p and every L_e are sorted lists, so Lp is
+        // formed as sorted runs and merged (the longest run with the sorted rest)
         ++g.stamp;
         const int64_t lpmark = g.stamp;
         g.mark[p] = lpmark;
         Lp.clear();
+        run_end.clear();
         for (int32_t v : g.A[p])
             if (g.status[v] == VAR && g.mark[v] != lpmark) { g.mark[v] = lpmark; Lp.push_back(v); }
-        for (int32_t e : g.E[p])
+        run_end.push_back(Lp.size());
+        for (int32_t e : g.E[p]) {
             for (int32_t v : g.Lel[e])
                 if (g.status[v] == VAR && g.mark[v] != lpmark) { g.mark[v] = lpmark; Lp.push_back(v); }
-        std::sort(Lp.begin(), Lp.end());
+            run_end.push_back(Lp.size());
+        }
+        {
+            size_t b0 = 0, e0 = 0, prev = 0;
+            for (size_t r : run_end) {
+                if (r - prev > e0 - b0) { b0 = prev; e0 = r; }
+                prev = r;
+            }
+            if (e0 - b0 < Lp.size()) {
+                rest.clear();
+                rest.insert(rest.end(), Lp.begin(), Lp.begin() + (std::ptrdiff_t)b0);
+                rest.insert(rest.end(), Lp.begin() + (std::ptrdiff_t)e0, Lp.end());
+                std::sort(rest.begin(), rest.end());
+                merged_buf.resize(Lp.size());
+                std::merge(Lp.begin() + (std::ptrdiff_t)b0, Lp.begin() + (std::ptrdiff_t)e0, rest.begin(),
+                           rest.end(), merged_buf.begin());
+                Lp.swap(merged_buf);
+            }
+        }
         for (int32_t e : g.E[p]) {
             g.status[e] = ABSORBED;
             std::vector<int32_t>().swap(g.Lel[e]);
@@ -323,22 +383,36 @@ void min_degree_order(int32_t N, const std::vector<int64_t> &Gp, const std::vect
         for (int32_t i : Lp) wlp += g.nv[i];
         g.Lel[p] = Lp;
         g.wtot[p] = wlp;
-        for (int32_t i : Lp) if (pq.contains(i)) pq.remove(i);
-        // list updates
-        for (int32_t i : Lp) {
-            auto &Ei = g.E[i];
-            size_t k = 0;
-            for (int32_t e : Ei) if (g.status[e] == ELEMENT) Ei[k++] = e;
-            Ei.erase(Ei.begin() + (std::ptrdiff_t)k, Ei.end());
-            Ei.insert(std::lower_bound(Ei.begin(), Ei.end(), p), p);
-            auto &Ai = g.A[i];
-            k = 0;
-            for (int32_t v : Ai) if (g.mark[v] != lpmark) Ai[k++] = v;
-            Ai.erase(Ai.begin() + (std::ptrdiff_t)k, Ai.end());
-        }
+        pq.remove_many(Lp);
+        // list updates: each variable's own lists, from shared read-only marks and states
+        for_lp([&](int64_t t0, int64_t t1) {
+            for (int64_t t = t0; t < t1; ++t) {
+                const int32_t i = Lp[(size_t)t];
+                auto &Ei = g.E[i];
+                size_t k = 0;
+                for (int32_t e : Ei) if (g.status[e] == ELEMENT) Ei[k++] = e;
+                Ei.erase(Ei.begin() + (std::ptrdiff_t)k, Ei.end());
+                Ei.insert(std::lower_bound(Ei.begin(), Ei.end(), p), p);
+                auto &Ai = g.A[i];
+                k = 0;
+                for (int32_t v : Ai) if (g.mark[v] != lpmark) Ai[k++] = v;
+                Ai.erase(Ai.begin() + (std::ptrdiff_t)k, Ai.end());
+            }
+        });
         // supervariable detection among Lp: hash, then confirm by full equality.  Only a hash
         // shared by two or more variables can lead to a merge: those are found with an
         // open-addressing count table, and only they are sorted by (hash, index)
+        hashes.resize(Lp.size());
+        for_lp([&](int64_t t0, int64_t t1) {
+            for (int64_t t = t0; t < t1; ++t) {
+                const int32_t i = Lp[(size_t)t];
+                uint64_t h = mix(mix(0, g.A[i].size()), g.E[i].size());
+                for (int32_t v : g.A[i]) h = mix(h, (uint64_t)v);
+                h = mix(h, 0xabcdefULL);
+                for (int32_t e : g.E[i]) h = mix(h, (uint64_t)e);
+                hashes[(size_t)t] = h;
+            }
+        });
         keyed.clear();
         size_t cap = 16;
         while (cap < 2 * Lp.size()) cap <<= 1;
@@ -349,15 +423,9 @@ void min_degree_order(int32_t N, const std::vector<int64_t> &Gp, const std::vect
             while (hcount[k] != 0 && hslot[k] != h) k = (k + 1) & (cap - 1);
             return k;
         };
-        hashes.clear();
-        for (int32_t i : Lp) {
-            uint64_t h = mix(mix(0, g.A[i].size()), g.E[i].size());
-            for (int32_t v : g.A[i]) h = mix(h, (uint64_t)v);
-            h = mix(h, 0xabcdefULL);
-            for (int32_t e : g.E[i]) h = mix(h, (uint64_t)e);
-            hashes.push_back(h);
-            const size_t k = slot_of(h);
-            hslot[k] = h;
+        for (size_t t = 0; t < Lp.size(); ++t) {
+            const size_t k = slot_of(hashes[t]);
+            hslot[k] = hashes[t];
             ++hcount[k];
         }
         for (size_t t = 0; t < Lp.size(); ++t)
@@ -393,26 +461,75 @@ void min_degree_order(int32_t N, const std::vector<int64_t> &Gp, const std::vect
             }
             a = b;
         }
-        // approximate degrees: w_e = W(L_e \ Lp) from the element totals
-        for (int32_t i : Lp) {
-            if (g.status[i] != VAR) continue;
-            for (int32_t e : g.E[i]) {
-                if (e == p) continue;
-                if (g.wstamp[e] != pivot_id) { g.wstamp[e] = pivot_id; g.wcur[e] = g.wtot[e]; }
-                g.wcur[e] -= g.nv[i];
+        // approximate degrees: w_e = W(L_e \ Lp) = total weight of e minus the weight of its
+        // variables in Lp, for every live element e != p of a variable of Lp (integer sums: the
+        // same whichever way they are formed)
+        ++estamp_id;
+        if (Lp.size() < PAR_MIN) {
+            // from the variables' side: each element starts from its total at its first visit
+            for (int32_t i : Lp) {
+                if (g.status[i] != VAR) continue;
+                for (int32_t e : g.E[i]) {
+                    if (e == p) continue;
+                    if (estamp[e] != estamp_id) { estamp[e] = estamp_id; g.wcur[e] = g.wtot[e]; }
+                    g.wcur[e] -= g.nv[i];
+                }
             }
+        } else {
+            // from the elements' side, in parallel: the elements are collected once each (the
+            // per-pivot stamp), then each sum is formed by one thread from the element's own
+            // list (the incidence of live elements and variables is symmetric: e is in E_i
+            // exactly when i is in L_e)
+            elist.clear();
+            for_lp([&](int64_t t0, int64_t t1) {
+                std::vector<int32_t> mine;
+                for (int64_t t = t0; t < t1; ++t) {
+                    const int32_t i = Lp[(size_t)t];
+                    if (g.status[i] != VAR) continue;
+                    for (int32_t e : g.E[i]) {
+                        if (e == p || __atomic_load_n(&estamp[e], __ATOMIC_RELAXED) == estamp_id) continue;
+                        if (__atomic_exchange_n(&estamp[e], estamp_id, __ATOMIC_RELAXED) != estamp_id)
+                            mine.push_back(e);
+                    }
+                }
+                std::lock_guard<std::mutex> lk(elist_mu);
+                elist.insert(elist.end(), mine.begin(), mine.end());
+            });
+            pool.run((int64_t)elist.size(), [&](int64_t t0, int64_t t1) {
+                for (int64_t t = t0; t < t1; ++t) {
+                    const int32_t e = elist[(size_t)t];
+                    int64_t w = g.wtot[e];
+                    // eliminated variables are dropped from the list on the way (every reader
+                    // of element lists skips them)
+                    auto &Le = g.Lel[e];
+                    size_t k = 0;
+                    for (int32_t v : Le) {
+                        if (g.status[v] != VAR) continue;
+                        if (g.mark[v] == lpmark) w -= g.nv[v];
+                        Le[k++] = v;
+                    }
+                    Le.resize(k);
+                    g.wcur[e] = w;
+                }
+            });
         }
-        for (int32_t i : Lp) {
-            if (g.status[i] != VAR) continue;
-            int64_t wa = 0, we = 0;
-            for (int32_t v : g.A[i]) wa += g.nv[v];
-            for (int32_t e : g.E[i]) if (e != p) we += g.wcur[e];
-            const int64_t lpi = wlp - g.nv[i];
-            int64_t d = std::min(rem - g.nv[i], g.deg[i] + lpi);
-            d = std::min(d, wa + lpi + we);
-            g.deg[i] = d;
-            pq.push(i);
-        }
+        for_lp([&](int64_t t0, int64_t t1) {
+            for (int64_t t = t0; t < t1; ++t) {
+                const int32_t i = Lp[(size_t)t];
+                if (g.status[i] != VAR) continue;
+                int64_t wa = 0, we = 0;
+                for (int32_t v : g.A[i]) wa += g.nv[v];
+                for (int32_t e : g.E[i]) if (e != p) we += g.wcur[e];
+                const int64_t lpi = wlp - g.nv[i];
+                int64_t d = std::min(rem - g.nv[i], g.deg[i] + lpi);
+                d = std::min(d, wa + lpi + we);
+                g.deg[i] = d;
+            }
+        });
+        size_t k = 0;
+        for (int32_t i : Lp) if (g.status[i] == VAR) Lp[k++] = i;
+        Lp.resize(k);
+        pq.push_many(Lp);
     }
 }
 

@@ -129,6 +129,20 @@ def test_analysis_matches_oracle_digest_full_size(name):
         assert hashlib.sha256(np.ascontiguousarray(a[k], dtype=dt).tobytes()).hexdigest() == gold[k], k
 
 
+@pytest.mark.parametrize("threads", ["1", "3"])
+def test_analysis_does_not_depend_on_the_thread_count(threads, monkeypatch):
+    """The ordering's long pivot steps (huber_s ends in a ~4000-wide dense phase) run on a pool of
+    host threads; with 1 or 3 threads the result is the oracle's digest, as with the default."""
+    import paper_2603_29197_amd as qg
+    monkeypatch.setenv("QG_ANALYSIS_THREADS", threads)
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "patterns.json")))["huber_s"]
+    a = qg.analyze(problems.workload("huber_s"))
+    for k, dt in KEYS:
+        if k == "iperm":
+            continue
+        assert hashlib.sha256(np.ascontiguousarray(a[k], dtype=dt).tobytes()).hexdigest() == gold[k], k
+
+
 def test_invalid_inputs_are_rejected():
     import scipy.sparse as sp
     import paper_2603_29197_amd as qg

@@ -55,6 +55,7 @@ typedef int64_t qg_nnz;
 #define QG_ERR_HIP (-5)        /* a HIP call failed (code kept in the handle) */
 #define QG_ERR_STATE (-6)      /* call out of order (e.g. backward before a solve) */
 #define QG_ERR_DEVICE (-7)     /* no usable gfx950 device */
+#define QG_ERR_SIZE (-8)       /* input larger than a fixed capacity (qg_max_step_noalloc) */
 
 /* qg_info.status */
 #define QG_UNSOLVED 0
@@ -334,6 +335,37 @@ int qg_step_cone_op(qg_handle *h, int op, const double *u, const double *v, doub
  * t = W'(lambda \ d),  d = -lambda o lambda - (W^-T ds_a) o (W dz_a) + sigma_mu e. */
 int qg_step_corrector(qg_handle *h, const double *ds_a, const double *dz_a, double sigma_mu,
                       double *t);
+
+/* ---------------------------------------------------------------------
+ * Entry point that allocates nothing.
+ * --------------------------------------------------------------------- */
+
+/* Capacity of qg_max_step_noalloc: at most this many cone units (l + nsoc). */
+#define QG_NOALLOC_MAX_UNITS 4194304
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * maximum step of qg_step_max_step without a handle and without any
+ * allocation.  alpha = sup{a >= 0 : u + a du in K} (+inf if unbounded) for
+ * K = the orthant of dimension l times nsoc second-order cones.
+ * soc_off: device, nsoc + 1 increasing row offsets of the cones in u
+ * (soc_off[0] = l, cone k is rows soc_off[k] .. soc_off[k+1]-1, each of at
+ * least one row); may be NULL when nsoc == 0.  u (strictly inside K), du:
+ * device, soc_off[nsoc] entries (l when nsoc == 0).  alpha: host.
+ * hip_stream: the stream the work is ordered on (NULL = default stream);
+ * returns after it completed.
+ * Its only device memory is a fixed array in the library, one per device
+ * for the life of the process (QG_NOALLOC_MAX_UNITS / 256 + 1 doubles,
+ * 128 KiB); every call on a device shares it, so calls that overlap on one
+ * device (other host threads, or streams running concurrently) race and
+ * must be serialized by the caller.  No state carries over between calls.
+ * Errors: QG_ERR_ARG (negative sizes, NULL alpha, NULL soc_off with
+ * nsoc > 0, NULL u or du with l + nsoc > 0), QG_ERR_SIZE
+ * (l + nsoc > QG_NOALLOC_MAX_UNITS), QG_ERR_DEVICE, QG_ERR_HIP.
+ */
+int qg_max_step_noalloc(qg_int l, qg_int nsoc, const qg_int *soc_off, const double *u,
+                        const double *du, double *alpha, void *hip_stream);
 
 #ifdef __cplusplus
 }

@@ -18,7 +18,7 @@ c_double_p = ctypes.POINTER(ctypes.c_double)
 
 QG_OK = 0
 ERRORS = {-1: "QG_ERR_ARG", -2: "QG_ERR_PATTERN", -3: "QG_ERR_NONFINITE", -4: "QG_ERR_OOM",
-          -5: "QG_ERR_HIP", -6: "QG_ERR_STATE", -7: "QG_ERR_DEVICE"}
+          -5: "QG_ERR_HIP", -6: "QG_ERR_STATE", -7: "QG_ERR_DEVICE", -8: "QG_ERR_SIZE"}
 STATUS = {0: "unsolved", 1: "solved", 2: "solved_inaccurate", -1: "max_iter", -2: "numerical_error"}
 QG_FP64 = 0
 QG_FP32_IR = 1
@@ -82,8 +82,9 @@ EXPORTS = [
     "qg_default_settings", "qg_analyze", "qg_symbolic_pattern", "qg_symbolic_free", "qg_setup", "qg_update",
     "qg_update_vectors", "qg_set_settings", "qg_solve", "qg_backward", "qg_backward_full", "qg_backward_batch", "qg_get_pattern", "qg_last_hip_error", "qg_cleanup",
     "qg_strerror", "qg_step_scaling", "qg_step_get_kkt", "qg_step_factor", "qg_step_get_factor",
-    "qg_step_solve", "qg_step_max_step", "qg_step_cone_op", "qg_step_corrector",
+    "qg_step_solve", "qg_step_max_step", "qg_step_cone_op", "qg_step_corrector", "qg_max_step_noalloc",
 ]
+QG_NOALLOC_MAX_UNITS = 4194304
 
 _lib = None
 
@@ -129,6 +130,7 @@ def lib():
     L.qg_step_max_step.argtypes = [vp, vp, vp, c_double_p]
     L.qg_step_cone_op.argtypes = [vp, ctypes.c_int, vp, vp, vp]
     L.qg_step_corrector.argtypes = [vp, vp, vp, ctypes.c_double, vp]
+    L.qg_max_step_noalloc.argtypes = [ctypes.c_int32, ctypes.c_int32, vp, vp, vp, c_double_p, vp]
     _lib = L
     return L
 

@@ -300,6 +300,7 @@ const char *qg_strerror(int code) {
         case QG_ERR_HIP: return "HIP runtime error";
         case QG_ERR_STATE: return "call out of order";
         case QG_ERR_DEVICE: return "no gfx950 device";
+        case QG_ERR_SIZE: return "input exceeds a fixed capacity";
         default: return "unknown error";
     }
 }

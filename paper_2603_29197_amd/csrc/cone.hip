@@ -321,22 +321,8 @@ __global__ void add_e_kernel(int32_t l, int32_t nsoc, const int32_t *__restrict_
 // a + 64, ...; every inner product is a butterfly sum, after which all lanes
 // hold the same value.  Same formulas as the per-thread kernels above.
 // ---------------------------------------------------------------------------
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
-
 // wavefront index among the big cones (4 wavefronts per 256-thread block)
 __device__ inline int32_t big_wave() { return (int32_t)(blockIdx.x * 4 + (threadIdx.x >> 6)); }
-
-// s'Js over the tail as sqrt((u0 - |u1|)(u0 + |u1|))
-__device__ inline double wave_jnorm(const double *u, int32_t q, int lane) {
-    double t = 0.0;
-    for (int32_t a = 1 + lane; a < q; a += 64) t += u[a] * u[a];
-    const double n1 = sqrt(wave_sum(t));
-    return sqrt((u[0] - n1) * (u[0] + n1));
-}
 
 // NT scaling of a big cone (wb, beta, lam); its (3,3) block is written by block_big.
 // block == 1 stores the two sums block_big needs for -sym(Arw(z)^-1 Arw(s)) instead.
@@ -582,19 +568,8 @@ __global__ void __launch_bounds__(256) step_big(int32_t nbig, const int32_t *__r
     const int lane = threadIdx.x & 63;
     const int32_t k = big[gw];
     const int32_t off = soc_off[k], q = soc_off[k + 1] - off;
-    const double *uk = u + off, *dk = du + off;
-    const double uJ = wave_jnorm(uk, q, lane);
-    double r1 = 0.0;
-    for (int32_t c = 1 + lane; c < q; c += 64) r1 += uk[c] / uJ * dk[c];
-    const double r0 = (uk[0] / uJ * dk[0] - wave_sum(r1)) / uJ;
-    const double coef = (r0 * uJ + dk[0]) / (1.0 + uk[0] / uJ);
-    double n1 = 0.0;
-    for (int32_t c = 1 + lane; c < q; c += 64) {
-        const double v = (dk[c] - coef * (uk[c] / uJ)) / uJ;
-        n1 += v * v;
-    }
-    const double den = sqrt(wave_sum(n1)) - r0;
-    if (lane == 0 && den > 0.0) atomicMin(amin, (unsigned long long)__double_as_longlong(1.0 / den));
+    const double a = wave_soc_max_step(u + off, du + off, q, lane);
+    if (lane == 0 && a < INFINITY) atomicMin(amin, (unsigned long long)__double_as_longlong(a));
 }
 
 // -lambda_min = |u1| - u0 per big cone, max-reduced per block into partials[blockIdx.x]

@@ -43,6 +43,12 @@ def lib():
     L.or_etree.restype = ctypes.c_int
     L.or_lpattern.argtypes = [ctypes.c_int32, i64p, i32p, i32p, ctypes.c_void_p, i64p, ctypes.c_void_p]
     L.or_lpattern.restype = ctypes.c_int
+    L.or_row_work.argtypes = [ctypes.c_int32, i64p, i32p, i32p, i64p, f64p]
+    L.or_ldl_numeric_rows_marked.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, i64p, i32p, f64p,
+                                             i32p, i64p, i32p, i8p, ctypes.c_double, ctypes.c_double, f64p,
+                                             f64p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]
+    L.or_ldl_numeric_rows_marked.restype = ctypes.c_int
+    L.or_row_work.restype = ctypes.c_int
     L.or_ldl_numeric.argtypes = [ctypes.c_int32, i64p, i32p, f64p, i32p, i64p, i32p, i8p,
                                  ctypes.c_double, ctypes.c_double, f64p, f64p,
                                  ctypes.POINTER(ctypes.c_int64)]

@@ -16,8 +16,10 @@
  * Everything is deliberately simple: dynamic arrays, linear scans, sorting
  * with qsort, scalar loops.  Speed is not a goal.
  */
+#define _POSIX_C_SOURCE 200809L  /* clock_gettime */
 #include <stdint.h>
 #include <stdlib.h>
+#include <time.h>
 #include <string.h>
 #include <math.h>
 
@@ -380,6 +382,44 @@ int or_lpattern(int32_t N, const int64_t *Up, const int32_t *Ui, const int32_t *
     return 0;
 }
 
+/*
+ * Work of each row of the up-looking factorization below, from the same row
+ * subtrees: row k has an entry in column i for each i on those paths, and
+ * that entry is the t-th of column i (t = entries of column i in rows < k),
+ * whose update costs t multiply-adds; with one division per entry and one
+ * for the pivot, rowops[k] = 1 + sum over the row's entries of (t + 1).
+ * rowcnt[k] = entries of row k.  Used to time a bounded prefix of a large
+ * factorization and scale it to the whole.
+ */
+int or_row_work(int32_t N, const int64_t *Up, const int32_t *Ui, const int32_t *parent,
+                int64_t *rowcnt, double *rowops)
+{
+    int32_t *flag = (int32_t *)malloc((size_t)(N > 0 ? N : 1) * sizeof(int32_t));
+    int64_t *cnt = (int64_t *)calloc((size_t)(N > 0 ? N : 1), sizeof(int64_t));
+    if (!flag || !cnt) { free(flag); free(cnt); return -1; }
+    for (int32_t j = 0; j < N; ++j) flag[j] = -1;
+    for (int32_t k = 0; k < N; ++k) {
+        double ops = 1.0;
+        int64_t nk = 0;
+        flag[k] = k;
+        for (int64_t t = Up[k]; t < Up[k + 1]; ++t) {
+            int32_t i = Ui[t];
+            if (i >= k) continue;
+            while (flag[i] != k) {
+                flag[i] = k;
+                ops += (double)cnt[i] + 1.0;
+                cnt[i] += 1;
+                nk += 1;
+                i = parent[i];
+            }
+        }
+        rowcnt[k] = nk;
+        rowops[k] = ops;
+    }
+    free(flag); free(cnt);
+    return 0;
+}
+
 /* ------------------------------------------------------------------ */
 /* Up-looking numeric LDL' on a known pattern                          */
 /* ------------------------------------------------------------------ */
@@ -411,6 +451,11 @@ int or_ldl_numeric(int32_t N, const int64_t *Up, const int32_t *Ui, const double
     return or_ldl_numeric_rows(N, N, Up, Ui, Ux, parent, Lp, Li, sign, eps, delta, Lx, D, nreg);
 }
 
+int or_ldl_numeric_rows_marked(int32_t N, int32_t k_end, int32_t k_mark, const int64_t *Up,
+                               const int32_t *Ui, const double *Ux, const int32_t *parent,
+                               const int64_t *Lp, const int32_t *Li, const int8_t *sign, double eps,
+                               double delta, double *Lx, double *D, int64_t *nreg, double *t_mark);
+
 /* The same factorization stopped after rows 0..k_end-1 (used to time a
  * bounded sample of a large factorization). */
 int or_ldl_numeric_rows(int32_t N, int32_t k_end, const int64_t *Up, const int32_t *Ui,
@@ -418,6 +463,27 @@ int or_ldl_numeric_rows(int32_t N, int32_t k_end, const int64_t *Up, const int32
                         const int32_t *Li, const int8_t *sign, double eps, double delta,
                         double *Lx, double *D, int64_t *nreg)
 {
+    return or_ldl_numeric_rows_marked(N, k_end, -1, Up, Ui, Ux, parent, Lp, Li, sign, eps, delta, Lx, D,
+                                      nreg, NULL);
+}
+
+/* Seconds of a monotonic clock. */
+static double or_now(void)
+{
+    struct timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    return (double)ts.tv_sec + 1e-9 * (double)ts.tv_nsec;
+}
+
+/* The same, with the clock read when row k_mark starts (*t_mark, seconds
+ * since the call started; untouched when k_mark is outside 0..k_end-1): the
+ * work of a stretch of rows can then be timed inside one run. */
+int or_ldl_numeric_rows_marked(int32_t N, int32_t k_end, int32_t k_mark, const int64_t *Up,
+                               const int32_t *Ui, const double *Ux, const int32_t *parent,
+                               const int64_t *Lp, const int32_t *Li, const int8_t *sign, double eps,
+                               double delta, double *Lx, double *D, int64_t *nreg, double *t_mark)
+{
+    const double t0 = or_now();
     double *y = (double *)calloc((size_t)(N > 0 ? N : 1), sizeof(double));
     int32_t *flag = (int32_t *)malloc((size_t)(N > 0 ? N : 1) * sizeof(int32_t));
     int32_t *patt = (int32_t *)malloc((size_t)(N > 0 ? N : 1) * sizeof(int32_t));
@@ -427,6 +493,7 @@ int or_ldl_numeric_rows(int32_t N, int32_t k_end, const int64_t *Up, const int32
     *nreg = 0;
     for (int32_t j = 0; j < N; ++j) flag[j] = -1;
     for (int32_t k = 0; k < k_end; ++k) {
+        if (k == k_mark && t_mark) *t_mark = or_now() - t0;
         /* scatter column k of the upper triangle; collect the row-k pattern */
         int32_t np = 0;
         double akk = 0.0;

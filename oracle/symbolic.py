@@ -172,6 +172,34 @@ def l_pattern(Up: sp.csc_matrix, parent: np.ndarray):
     return Lp, Li, (cnt + 1).astype(np.int64)
 
 
+def row_work(Up: sp.csc_matrix, parent: np.ndarray, nrows: int | None = None):
+    """Per row k of the up-looking factorization: entries of row k of L (strictly lower) and its
+    multiply-add count (see or_row_work); only rows < nrows (default all)."""
+    N = Up.shape[0] if nrows is None else int(nrows)
+    rowcnt = np.zeros(N, dtype=np.int64)
+    rowops = np.zeros(N, dtype=np.float64)
+    lib().or_row_work(N, Up.indptr.astype(np.int64), Up.indices.astype(np.int32),
+                      np.ascontiguousarray(parent, dtype=np.int32), rowcnt, rowops)
+    return rowcnt, rowops
+
+
+def l_pattern_rows(Up: sp.csc_matrix, parent: np.ndarray, nrows: int):
+    """Strictly lower pattern of the leading nrows x nrows block of L (columns and rows < nrows):
+    the rows of the row subtrees of rows 0..nrows-1 only; returns (Lp, Li)."""
+    Upp = Up.indptr.astype(np.int64)
+    Upi = Up.indices.astype(np.int32)
+    cnt = np.zeros(nrows, dtype=np.int64)
+    L = lib()
+    L.or_lpattern(nrows, Upp, Upi, np.ascontiguousarray(parent, dtype=np.int32), None, cnt, None)
+    Lp = np.zeros(nrows + 1, dtype=np.int64)
+    np.cumsum(cnt, out=Lp[1:])
+    Li = np.empty(int(Lp[-1]), dtype=np.int32)
+    cnt2 = np.zeros(nrows, dtype=np.int64)
+    L.or_lpattern(nrows, Upp, Upi, np.ascontiguousarray(parent, dtype=np.int32),
+                  Lp.ctypes.data_as(ctypes.c_void_p), cnt2, Li.ctypes.data_as(ctypes.c_void_p))
+    return Lp, Li
+
+
 def fundamental_supernodes(parent: np.ndarray, colcount: np.ndarray) -> np.ndarray:
     N = len(parent)
     nchild = np.zeros(N, dtype=np.int64)

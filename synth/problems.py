@@ -253,6 +253,8 @@ def workload(name: str) -> Problem:
         # the largest Huber instance of the same generator used in the device tests (the full one
         # needs a ~2e5-wide dense root front: more than one GPU's memory)
         "huber_m": lambda: huber(50000, 20000, 40, seed=BASE_SEED + 4),
+        # the benchmark's Huber instance: the same generator at F 100000 x 40000 (40 entries per row)
+        "huber_l": lambda: huber(100000, 40000, 40, seed=BASE_SEED + 4),
         # oracle-scaled variants drawn from the same generators
         "lasso_s": lambda: lasso(2000, 1000, 0.02, seed=BASE_SEED + 12),
         "many_soc_s": lambda: many_soc(3000, 1000, 4, 1000, seed=BASE_SEED + 13),
@@ -264,6 +266,36 @@ def workload(name: str) -> Problem:
                                       seed=BASE_SEED + 16),
     }
     return table[name]()
+
+
+def family(prob: Problem, k: int, seed: int) -> List[Problem]:
+    """k problems on the sparsity pattern of ``prob`` with drawn values (a parametric family):
+    P scaled by U(0.5, 1.5) (stays positive semidefinite), every entry of A and G multiplied by
+    1 + 0.05 N(0,1), c + 0.1 N(0,1); b and h from a fresh point x0 ~ N(0,1) and slack s0 strictly
+    inside the cones (orthant U(0.1, 1); each SOC (|u| + U(0.1, 1), u), u ~ N(0,1)), so each
+    problem is feasible.  Problem 0 is drawn like the others (it is not ``prob`` itself)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(k):
+        P = prob.P.copy()
+        P.data = P.data * rng.uniform(0.5, 1.5)
+        A = prob.A.copy()
+        A.data = A.data * (1.0 + 0.05 * rng.standard_normal(A.nnz))
+        G = prob.G.copy()
+        G.data = G.data * (1.0 + 0.05 * rng.standard_normal(G.nnz))
+        c = prob.c + 0.1 * rng.standard_normal(prob.n)
+        x0 = rng.standard_normal(prob.n)
+        s0 = np.empty(prob.m)
+        s0[:prob.l] = rng.uniform(0.1, 1.0, prob.l)
+        off = prob.l
+        for qk in prob.q:
+            u = rng.standard_normal(qk - 1)
+            s0[off] = np.linalg.norm(u) + rng.uniform(0.1, 1.0)
+            s0[off + 1:off + qk] = u
+            off += qk
+        out.append(Problem(n=prob.n, m=prob.m, p=prob.p, P=P, c=c, A=A, b=A @ x0, G=G, h=G @ x0 + s0,
+                           l=prob.l, q=list(prob.q), name=f"{prob.name}_family{i}", meta=dict(seed=seed, index=i)))
+    return out
 
 
 def random_point(prob: Problem, seed: int):

@@ -31,10 +31,10 @@ def pattern_record(name):
     prob = problems.workload(name)
     t = time.time()
     pat = symbolic.analyze(kkt.kkt_pattern(prob))
-    if name == "lasso":
-        # the oracle's ordering of the benchmark workload, for the CPU-baseline
+    if name in ("lasso", "huber_l"):
+        # the oracle's ordering of a benchmark workload, for the CPU-baseline
         # leg of the benchmark (which then needs only the fast symbolic steps)
-        np.save(os.path.join(os.path.dirname(OUT), "lasso_perm.npy"), pat.perm.astype(np.int32))
+        np.save(os.path.join(os.path.dirname(OUT), f"{name}_perm.npy"), pat.perm.astype(np.int32))
     return dict(
         N=int(pat.N), nnz_L=int(pat.nnz_L), nsuper_fund=int(len(pat.super_fund) - 1),
         nsuper=int(len(pat.super_ptr) - 1), rows_total=int(len(pat.rows)),

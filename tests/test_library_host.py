@@ -116,7 +116,7 @@ def test_device_fronts_random(seed):
     _check_fronts(prob, qg.analyze(prob))
 
 
-@pytest.mark.parametrize("name", ["huber_s", "many_soc", "lasso"])
+@pytest.mark.parametrize("name", ["huber_s", "many_soc", "lasso", "huber_l"])
 def test_analysis_matches_oracle_digest_full_size(name):
     """Digests written by tests/golden/make_golden.py from the oracle."""
     import paper_2603_29197_amd as qg

@@ -232,3 +232,49 @@ def test_shift_interior():
     v[0] = -3.0
     w = cn.shift_interior(v)
     assert np.all(cn.lambda_min(w) >= 1.0 - 1e-12)
+
+
+@pytest.mark.parametrize("name", ["small_qp", "lasso_s", "many_soc_s"])
+def test_row_work_and_leading_block_factor(name):
+    """The bounded-prefix timing of the oracle's factorization rests on three facts, each checked
+    against the full pattern and the full factorization: (1) or_row_work's row counts are the row
+    counts of L's pattern and its per-row work is the sum over the row's entries of (position in
+    the column + 1), plus one; in total sum_j c_j (c_j + 1) / 2 + N with c_j the column counts
+    (closed form); (2) the pattern of the leading block is the full pattern restricted to rows
+    and columns below the cut; (3) factoring only the rows below the cut on that pattern gives the
+    same L rows and pivots as the full factorization."""
+    import ctypes
+    prob = problems.workload(name)
+    F = ldl.KKTFactor(prob)
+    _, s, _, z = problems.random_point(prob, 3)
+    F.factor(*C.nt_scaling(C.Cones(prob.l, prob.q), s, z).block33())
+    Kp = kkt.kkt_pattern(prob)
+    Up = symbolic.permute_upper(Kp, F.pat.perm)
+    parent = F.pat.parent
+    N = F.N
+    rowcnt, rowops = symbolic.row_work(Up, parent)
+    Lp, Li = F.pat.Lp, F.pat.Li
+    assert np.array_equal(rowcnt, np.bincount(Li, minlength=N))
+    tpos = np.arange(len(Li)) - np.repeat(Lp[:-1], np.diff(Lp))
+    assert np.allclose(rowops, np.bincount(Li, weights=tpos + 1.0, minlength=N) + 1.0, rtol=0, atol=0)
+    c = np.diff(Lp).astype(np.float64)
+    assert rowops.sum() == float(np.sum(c * (c + 1) / 2) + N)
+    cut = N // 2 + 7
+    Lp2, Li2 = symbolic.l_pattern_rows(Up, parent, cut)
+    for j in range(cut):
+        col = Li[Lp[j]:Lp[j + 1]]
+        assert np.array_equal(Li2[Lp2[j]:Lp2[j + 1]], col[col < cut])
+    ip, ii, pos = symbolic.permute_map(Kp, F.pat.perm)
+    Kreg = F.asm.upper(*C.nt_scaling(C.Cones(prob.l, prob.q), s, z).block33(), F.reg.static_reg,
+                       F.reg.static_reg)
+    Ux = np.empty(len(ii)); Ux[pos] = Kreg.data
+    Lx2 = np.zeros(len(Li2)); D2 = np.zeros(cut)
+    nreg = ctypes.c_int64(0)
+    from oracle._clib import lib
+    rc = lib().or_ldl_numeric_rows(cut, cut, ip, ii, Ux, parent, Lp2, Li2, F.sign_perm, F.reg.dyn_eps,
+                                   F.reg.dyn_delta, Lx2, D2, ctypes.byref(nreg))
+    assert rc == 0
+    assert np.array_equal(D2, F.D[:cut])
+    for j in range(cut):
+        col = Li[Lp[j]:Lp[j + 1]]
+        assert np.array_equal(Lx2[Lp2[j]:Lp2[j + 1]], F.Lx[Lp[j]:Lp[j + 1]][col < cut])

@@ -91,7 +91,17 @@ typedef struct {
     int differentiable;        /* 1: factor the derivative system after convergence (qg_backward) */
     int verbose;               /* 1: one line per iteration on stderr */
     int profile;               /* 1: time every launch of the trailing-update kernel (qg_info.kern_*) */
+    int chains;                /* 1: the narrow upper levels of deep elimination trees are factored and
+                                  solved by one workgroup per tree instead of one launch per level (1);
+                                  read by qg_setup only, the arithmetic is the same either way */
+    double fp32_min_flops;     /* QG_FP32_IR: FP32 factors only when the fronts factored on the matrix
+                                  cores (more than 128 rows) take at least this many flops per
+                                  factorization (1e10); below it the factorization is latency-bound,
+                                  FP32 saves nothing and its refinement corrections cost extra solves, so
+                                  every factor is FP64 (qg_info.switch_iter = 0) */
 } qg_settings;
+
+#define QG_STEP_MS_MAX 256
 
 typedef struct {
     int status;                /* QG_SOLVED, ... */
@@ -110,15 +120,19 @@ typedef struct {
     int64_t nnz_L;                           /* entries of L incl. diagonal (exact symbolic count) */
     double factor_flops;                     /* sum_j (c_j - 1)^2 + 3 (c_j - 1), c_j column counts */
     /* with settings.profile: the trailing-update kernel of large fronts (MFMA), HIP events per
-     * launch; index 0 = FP64 launches, 1 = FP32 launches */
-    int64_t kern_launches[2];
-    double kern_ms[2];                       /* summed launch durations */
-    double kern_flops[2];                    /* algorithmic flops: 2 b (C M - C (C - 1) / 2) per launch
+     * launch; index 0 = FP64 launches, 1 = FP32 launches on 64 x 64 tiles, 2 and 3 the same
+     * on 128 x 128 tiles */
+    int64_t kern_launches[4];
+    double kern_ms[4];                       /* summed launch durations */
+    double kern_flops[4];                    /* algorithmic flops: 2 b (C M - C (C - 1) / 2) per launch
                                                 (rank b, M rows by C columns of the lower part) */
     double ms_step_p90;                      /* 90th percentile of the Newton-step times */
     int64_t ntrisolve[2];                    /* triangular solves incl. refinement corrections:
                                                 [0] with an FP64 factor, [1] with an FP32 factor */
     int64_t nresidual;                       /* refinement residuals r - K x (FP64, unregularized K) */
+    int32_t nstep_ms;                        /* entries of step_ms: min(iters, QG_STEP_MS_MAX) */
+    int32_t step_fp32[QG_STEP_MS_MAX];       /* 1 where that step's factor was FP32, 0 for FP64 */
+    double step_ms[QG_STEP_MS_MAX];          /* Newton-step times of the first iterations (HIP events) */
 } qg_info;
 
 /* Integer pattern of the analysis; pointers stay valid until the object
@@ -270,6 +284,39 @@ int qg_backward_full(qg_handle *h, const double *dl_dx, const double *dl_dy, con
 int qg_backward_batch(qg_handle *h, int32_t k, const double *dl_dx, const double *dl_dy,
                       const double *dl_dz, const double *dl_ds, double *dl_dc, double *dl_dh,
                       double *dl_db, double *dl_dPval, double *dl_dAval, double *dl_dGval);
+
+/*
+ * Batches of problems on one pattern (paper Sec. 3.2: the analysis is reused
+ * when only the values change, for parametric problems).  The k problems
+ * share n, m, p, the patterns of P, A, G and the cones; their values differ.
+ * P, A, G: the shared pattern (as in qg_setup) whose val arrays hold k value
+ * sets one after another (k x nnz, problem 0 first; P may be NULL for P = 0).
+ * c (k x n), b (k x p), hvec (k x m): host, problem by problem.  The analysis
+ * of one problem runs once and is replicated; the problems are solved
+ * together as one separable problem (the block-diagonal KKT matrix of the
+ * stack: every factorization and triangular solve of an iteration covers all
+ * k, identical fronts of the k problems in one launch), so they share one
+ * step length and one centering parameter per iteration, and the stopping
+ * test of qg_solve applies to the stack (residual norms over all k problems,
+ * the sum of the complementarity gaps against the summed objectives).  The
+ * stack's optimum is the k problems' optima.  The handle takes qg_solve_batch
+ * and the step-level calls; qg_solve, qg_update, qg_update_vectors and the
+ * backward calls return QG_ERR_STATE on it.  Other arguments, ownership and
+ * errors as for qg_setup; QG_ERR_ARG also for k < 1 or k (n + m + p) beyond
+ * 32-bit indices.
+ */
+int qg_setup_batch(qg_handle **out, qg_int k, qg_int n, qg_int m, qg_int p,
+                   const qg_csc *P, const double *c, const qg_csc *A, const double *b,
+                   const qg_csc *G, const double *hvec, qg_int l, qg_int nsoc, const qg_int *q,
+                   const qg_settings *s, void *hip_stream, qg_alloc_fn alloc, qg_free_fn free,
+                   void *alloc_ctx);
+
+/*
+ * Solve the batch of qg_setup_batch.  x (k x n), s (k x m), y (k x p),
+ * z (k x m): device outputs, problem by problem (any may be NULL).  info
+ * (host, may be NULL) describes the stacked solve.
+ */
+int qg_solve_batch(qg_handle *h, double *x, double *s, double *y, double *z, qg_info *info);
 
 /* Host copies of the analysis; valid until qg_cleanup. */
 int qg_get_pattern(const qg_handle *h, qg_pattern *out);

@@ -22,6 +22,7 @@ ERRORS = {-1: "QG_ERR_ARG", -2: "QG_ERR_PATTERN", -3: "QG_ERR_NONFINITE", -4: "Q
 STATUS = {0: "unsolved", 1: "solved", 2: "solved_inaccurate", -1: "max_iter", -2: "numerical_error"}
 QG_FP64 = 0
 QG_FP32_IR = 1
+QG_STEP_MS_MAX = 256
 
 
 class QGError(RuntimeError):
@@ -42,7 +43,8 @@ class qg_settings(ctypes.Structure):
                 ("static_reg32", ctypes.c_double), ("dyn_eps32", ctypes.c_double),
                 ("dyn_delta32", ctypes.c_double), ("ir_max", ctypes.c_int), ("ir_max32", ctypes.c_int),
                 ("ir_tol", ctypes.c_double), ("step_frac", ctypes.c_double), ("differentiable", ctypes.c_int),
-                ("verbose", ctypes.c_int), ("profile", ctypes.c_int)]
+                ("verbose", ctypes.c_int), ("profile", ctypes.c_int), ("chains", ctypes.c_int),
+                ("fp32_min_flops", ctypes.c_double)]
 
 
 class qg_info(ctypes.Structure):
@@ -54,14 +56,18 @@ class qg_info(ctypes.Structure):
                 ("ms_factor", ctypes.c_double), ("ms_trisolve", ctypes.c_double), ("ms_cone", ctypes.c_double),
                 ("ms_step_median", ctypes.c_double), ("ms_step_median_fp32", ctypes.c_double),
                 ("ms_step_median_fp64", ctypes.c_double), ("nnz_L", ctypes.c_int64),
-                ("factor_flops", ctypes.c_double), ("kern_launches", ctypes.c_int64 * 2),
-                ("kern_ms", ctypes.c_double * 2), ("kern_flops", ctypes.c_double * 2),
-                ("ms_step_p90", ctypes.c_double), ("ntrisolve", ctypes.c_int64 * 2), ("nresidual", ctypes.c_int64)]
+                ("factor_flops", ctypes.c_double), ("kern_launches", ctypes.c_int64 * 4),
+                ("kern_ms", ctypes.c_double * 4), ("kern_flops", ctypes.c_double * 4),
+                ("ms_step_p90", ctypes.c_double), ("ntrisolve", ctypes.c_int64 * 2), ("nresidual", ctypes.c_int64),
+                ("nstep_ms", ctypes.c_int32), ("step_fp32", ctypes.c_int32 * QG_STEP_MS_MAX),
+                ("step_ms", ctypes.c_double * QG_STEP_MS_MAX)]
 
     def as_dict(self):
         d = {name: getattr(self, name) for name, _ in self._fields_}
         for k in ("kern_launches", "kern_ms", "kern_flops", "ntrisolve"):
             d[k] = list(d[k])
+        d["step_ms"] = list(d["step_ms"])[:self.nstep_ms]
+        d["step_fp32"] = list(d["step_fp32"])[:self.nstep_ms]
         d["status_name"] = STATUS.get(self.status, str(self.status))
         return d
 
@@ -83,6 +89,7 @@ EXPORTS = [
     "qg_update_vectors", "qg_set_settings", "qg_solve", "qg_backward", "qg_backward_full", "qg_backward_batch", "qg_get_pattern", "qg_last_hip_error", "qg_cleanup",
     "qg_strerror", "qg_step_scaling", "qg_step_get_kkt", "qg_step_factor", "qg_step_get_factor",
     "qg_step_solve", "qg_step_max_step", "qg_step_cone_op", "qg_step_corrector", "qg_max_step_noalloc",
+    "qg_setup_batch", "qg_solve_batch",
 ]
 QG_NOALLOC_MAX_UNITS = 4194304
 
@@ -109,6 +116,11 @@ def lib():
                            ctypes.POINTER(qg_csc), c_double_p, ctypes.POINTER(qg_csc), c_double_p,
                            ctypes.POINTER(qg_csc), c_double_p, ctypes.c_int32, ctypes.c_int32, c_int32_p,
                            ctypes.POINTER(qg_settings), vp, ALLOC_FN, FREE_FN, vp]
+    L.qg_setup_batch.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                 ctypes.c_int32, ctypes.POINTER(qg_csc), c_double_p, ctypes.POINTER(qg_csc),
+                                 c_double_p, ctypes.POINTER(qg_csc), c_double_p, ctypes.c_int32, ctypes.c_int32,
+                                 c_int32_p, ctypes.POINTER(qg_settings), vp, ALLOC_FN, FREE_FN, vp]
+    L.qg_solve_batch.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(qg_info)]
     L.qg_update.argtypes = [vp, c_double_p, c_double_p, c_double_p, c_double_p, c_double_p, c_double_p]
     L.qg_update_vectors.argtypes = [vp, vp, vp, vp]
     L.qg_set_settings.argtypes = [vp, ctypes.POINTER(qg_settings)]

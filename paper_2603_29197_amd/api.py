@@ -325,6 +325,85 @@ class Solver:
         return t[:self.m]
 
 
+class BatchSolver:
+    """k problems on one sparsity pattern solved together (qg_setup_batch / qg_solve_batch):
+    the analysis of one problem is replicated, each iteration factors and solves all k at once.
+    ``probs``: problems with identical n, m, p, cones and patterns of P, A, G."""
+
+    def __init__(self, probs, settings: Optional[qg_settings] = None, stream=None, memory="torch", **kw):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("a HIP device is required")
+        if not probs:
+            raise ValueError("empty batch")
+        p0 = probs[0]
+        for q in probs[1:]:
+            same = (q.n, q.m, q.p, q.l, list(q.q)) == (p0.n, p0.m, p0.p, p0.l, list(p0.q))
+            for M0, M1 in ((p0.P, q.P), (p0.A, q.A), (p0.G, q.G)):
+                same = same and np.array_equal(M0.indptr, M1.indptr) and np.array_equal(M0.indices, M1.indices)
+            if not same:
+                raise ValueError("the problems of a batch must share sizes, cones and sparsity patterns")
+        self.torch = torch
+        self.k, self.n, self.m, self.p = len(probs), p0.n, p0.m, p0.p
+        self.settings = settings if settings is not None else default_settings(**kw)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        P, A, G, q = _args(p0)
+        # value sets back to back on the shared pattern
+        for csc, name in ((P, "P"), (A, "A"), (G, "G")):
+            if csc.s is not None:
+                csc.val = np.ascontiguousarray(np.concatenate([getattr(pr, name).tocsc().data for pr in probs]),
+                                               dtype=np.float64)
+                csc.s.val = csc.val.ctypes.data_as(_lib.c_double_p)
+        c = np.ascontiguousarray(np.concatenate([pr.c for pr in probs]), dtype=np.float64)
+        b = np.ascontiguousarray(np.concatenate([pr.b for pr in probs]), dtype=np.float64)
+        hv = np.ascontiguousarray(np.concatenate([pr.h for pr in probs]), dtype=np.float64)
+        self._keep = (P, A, G, q, c, b, hv)
+        self.handle = ctypes.c_void_p()
+        if memory == "hip":
+            self.memory = None
+            hooks = (_lib.ALLOC_FN(), _lib.FREE_FN(), None)
+        else:
+            self.memory = TorchDeviceMemory(torch, None if memory == "torch" else memory)
+            hooks = (self.memory.c_alloc, self.memory.c_free, None)
+        check(lib().qg_setup_batch(ctypes.byref(self.handle), self.k, p0.n, p0.m, p0.p, P.ptr(),
+                                   c.ctypes.data_as(_lib.c_double_p), A.ptr(),
+                                   b.ctypes.data_as(_lib.c_double_p) if p0.p else None, G.ptr(),
+                                   hv.ctypes.data_as(_lib.c_double_p) if p0.m else None, p0.l, len(p0.q),
+                                   q.ctypes.data_as(_lib.c_int32_p), ctypes.byref(self.settings),
+                                   ctypes.c_void_p(self.stream.cuda_stream), *hooks), "qg_setup_batch")
+        self.info = None
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            lib().qg_cleanup(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_settings(self, **kw):
+        for key, v in kw.items():
+            if not hasattr(self.settings, key):
+                raise KeyError(key)
+            setattr(self.settings, key, v)
+        check(lib().qg_set_settings(self.handle, ctypes.byref(self.settings)), "qg_set_settings")
+
+    def solve(self):
+        """Returns x (k x n), s (k x m), y (k x p), z (k x m) as device tensors and the info dict."""
+        t = self.torch
+        mk = lambda w: t.empty(max(self.k * w, 1), dtype=t.float64, device="cuda")
+        x, s, y, z = mk(self.n), mk(self.m), mk(self.p), mk(self.m)
+        info = qg_info()
+        vp = lambda a: ctypes.c_void_p(a.data_ptr())
+        check(lib().qg_solve_batch(self.handle, vp(x), vp(s), vp(y), vp(z), ctypes.byref(info)), "qg_solve_batch")
+        self.info = info.as_dict()
+        shape = lambda a, w: a[:self.k * w].reshape(self.k, w)
+        return shape(x, self.n), shape(s, self.m), shape(y, self.p), shape(z, self.m), self.info
+
+
 def _autograd_function():
     import torch
 

@@ -7,6 +7,7 @@
 #include <new>
 #include <string>
 
+#include "batch.hpp"
 #include "vec.hpp"
 
 struct qg_symbolic {
@@ -189,6 +190,10 @@ static int allocate_device(qg_handle *h) {
     UP(zseg_len, pl.zseg_len);
     UP(task0, pl.task0);
     UP(reg_sign, pl.reg_sign);
+    UP(chain_comp_ptr, pl.chain_comp_ptr);
+    UP(chain_grp_ptr, pl.chain_grp_ptr);
+    UP(chain_sn, pl.chain_sn);
+    UP(ent_front, pl.ent_front);
     std::vector<int32_t> zc((size_t)h->m, -1);
     for (int32_t k = 0; k < h->pp.nsoc; ++k)
         for (int32_t r = h->pp.soc_off[k]; r < h->pp.soc_off[k + 1]; ++r) zc[r] = k;
@@ -216,8 +221,8 @@ static int allocate_device(qg_handle *h) {
     view32(d.dinv32, d.dinv64);
     view32(d.sinv32, d.sinv64);
     view32(d.w32, d.w64);
-    if ((rc = dalloc(h, d.ubuf, (size_t)pl.max_r))) return rc;
-    if ((rc = dalloc(h, d.vbuf, (size_t)pl.max_r))) return rc;
+    if ((rc = dalloc(h, d.ubuf, (size_t)pl.max_r * pl.ncopy))) return rc;
+    if ((rc = dalloc(h, d.vbuf, (size_t)pl.max_r * pl.ncopy))) return rc;
     if ((rc = dalloc(h, d.nreg, 1))) return rc;
     if ((rc = dalloc(h, d.x, (size_t)h->n))) return rc;
     if ((rc = dalloc(h, d.y, (size_t)h->p))) return rc;
@@ -239,12 +244,14 @@ static int allocate_device(qg_handle *h) {
     if ((rc = dalloc(h, d.wbar, m))) return rc;
     if ((rc = dalloc(h, d.beta, (size_t)h->pp.nsoc))) return rc;
     if ((rc = dalloc(h, d.scal, 64))) return rc;
+    if ((rc = dalloc(h, d.scal_inst, (size_t)h->ncopy * NSCAL))) return rc;
     if ((rc = dalloc(h, d.alpha, 4))) return rc;
-    if ((rc = dalloc(h, d.amin, 4))) return rc;
+    if ((rc = dalloc(h, d.amin, 4 * (size_t)h->ncopy))) return rc;
+    if ((rc = dalloc(h, d.mu, (size_t)h->ncopy))) return rc;
     if ((rc = dalloc(h, d.flag, 1))) return rc;
     // per-block partials: the sparse residual kernels use 256 / RL rows per block
     const size_t nblk = (N + 256 / RL - 1) / (256 / RL) + (size_t)((h->pp.l + h->pp.nsoc + 255) / 256) +
-                        (size_t)((h->nbig + 3) / 4) + 1;
+                        (size_t)((h->nbig + 3) / 4) + 1 + (size_t)h->ncopy;
     if ((rc = dalloc(h, d.partials, nblk * NSCAL))) return rc;
     return QG_OK;
 }
@@ -287,6 +294,8 @@ int qg_default_settings(qg_settings *s) {
     s->differentiable = 0;
     s->verbose = 0;
     s->profile = 0;
+    s->chains = 1;
+    s->fp32_min_flops = 1e10;
     return QG_OK;
 }
 
@@ -428,9 +437,115 @@ int qg_setup(qg_handle **out, qg_int n, qg_int m, qg_int p, const qg_csc *P, con
     return QG_OK;
 }
 
+// Cone-ordered rows of the stack -> problem-major rows: out[i m + w] = in[zrow(i, w)].
+__global__ void unstack_cone_rows(const double *__restrict__ in, double *__restrict__ out, int32_t k, int32_t m,
+                                  int32_t l) {
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= (int64_t)k * m) return;
+    const int32_t i = (int32_t)(t / m), w = (int32_t)(t % m);
+    const int64_t src = w < l ? (int64_t)i * l + w : (int64_t)k * l + (int64_t)i * (m - l) + (w - l);
+    out[t] = in[src];
+}
+
+int qg_setup_batch(qg_handle **out, qg_int k, qg_int n, qg_int m, qg_int p, const qg_csc *P, const double *c,
+                   const qg_csc *A, const double *b, const qg_csc *G, const double *hv, qg_int l, qg_int nsoc,
+                   const qg_int *q, const qg_settings *s, void *hip_stream, qg_alloc_fn alloc, qg_free_fn free_fn,
+                   void *alloc_ctx) {
+    if (!out) return QG_ERR_ARG;
+    *out = nullptr;
+    if (k < 1 || n < 0 || m < 0 || p < 0 || l < 0 || nsoc < 0) return QG_ERR_ARG;
+    if ((alloc == nullptr) != (free_fn == nullptr)) return QG_ERR_ARG;
+    if ((int64_t)k * (n + m + p) > INT32_MAX) return QG_ERR_ARG;
+    const auto t0 = std::chrono::steady_clock::now();
+    qg_handle *h = new (std::nothrow) qg_handle();
+    if (!h) return QG_ERR_OOM;
+    if (s) h->st = *s; else qg_default_settings(&h->st);
+    h->st.differentiable = 0;
+    h->stream = (hipStream_t)hip_stream;
+    h->alloc = alloc;
+    h->free_fn = free_fn;
+    h->alloc_ctx = alloc_ctx;
+    int rc = QG_OK;
+    try {
+        // one problem's pattern: validated, analysed once
+        ProblemPattern pp1;
+        rc = build_problem_pattern(pp1, n, m, p, P, A, G, l, nsoc, q, false);
+        if (!rc && (!c || (p > 0 && !b) || (m > 0 && !hv))) rc = QG_ERR_ARG;
+        if (!rc && ((P && !P->val) || (A && !A->val) || (G && !G->val))) rc = QG_ERR_ARG;
+        if (rc) { delete h; return rc; }
+        auto nnz = [](const qg_csc *M) { return M ? (int64_t)M->colptr[M->ncol] : 0; };
+        if ((P && !finite_all(P->val, k * nnz(P))) || (A && !finite_all(A->val, k * nnz(A))) ||
+            (G && !finite_all(G->val, k * nnz(G))) || !finite_all(c, (int64_t)k * n) ||
+            (p > 0 && !finite_all(b, (int64_t)k * p)) || (m > 0 && !finite_all(hv, (int64_t)k * m))) {
+            delete h;
+            return QG_ERR_NONFINITE;
+        }
+        StackMap mp;
+        mp.k = k; mp.n = n; mp.p = p; mp.m = m; mp.l = l;
+        StackedCsc Ps, As, Gs;
+        stack_problem(mp, P, A, G, Ps, As, Gs);
+        std::vector<int32_t> qs;
+        for (int32_t i = 0; i < k; ++i) qs.insert(qs.end(), q, q + nsoc);
+        rc = build_problem_pattern(h->pp, k * n, k * m, k * p, P ? &Ps.csc : nullptr, A ? &As.csc : nullptr,
+                                   G ? &Gs.csc : nullptr, k * l, k * nsoc, qs.data(), true);
+        if (rc) { delete h; return rc; }
+        h->ncopy = k;
+        h->n1 = n; h->m1 = m; h->p1 = p; h->l1 = l;
+        h->n = k * n; h->m = k * m; h->p = k * p; h->N = h->n + h->m + h->p;
+        h->hc.assign(c, c + (size_t)k * n);
+        h->hb.assign(b ? b : c, b ? b + (size_t)k * p : c);
+        h->hh.assign((size_t)k * m, 0.0);
+        for (int32_t i = 0; i < k; ++i)
+            for (int32_t w = 0; w < m; ++w) h->hh[(size_t)mp.zrow(i, w)] = hv[(size_t)i * m + w];
+        if ((rc = check_device(h))) { delete h; return rc; }
+        build_kkt_pattern(h->pp, h->kp);
+        h->nnzK = (int64_t)h->kp.Ki.size();
+        const auto ta = std::chrono::steady_clock::now();
+        KktPattern kp1;
+        build_kkt_pattern(pp1, kp1);
+        Symbolic sym1, fronts1;
+        analyze_pattern(kp1, sym1);
+        if ((rc = group_fronts(sym1, fronts1))) { qg_cleanup(h); return rc; }
+        replicate_symbolic(sym1, mp, h->sym);
+        replicate_symbolic(fronts1, mp, h->fronts);
+        h->ms_analyze = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - ta).count();
+        if ((rc = build_plan(h))) { qg_cleanup(h); return rc; }
+        if ((rc = create_streams(h))) { qg_cleanup(h); return rc; }
+        if ((rc = allocate_device(h))) { qg_cleanup(h); return rc; }
+        if ((rc = factor_init_attributes(h))) { qg_cleanup(h); return rc; }
+        if ((rc = upload_static_values(h, true))) { qg_cleanup(h); return rc; }
+        if (hipStreamSynchronize(h->stream) != hipSuccess) { qg_cleanup(h); return QG_ERR_HIP; }
+    } catch (const std::bad_alloc &) {
+        qg_cleanup(h);
+        return QG_ERR_OOM;
+    } catch (...) {
+        qg_cleanup(h);
+        return QG_ERR_PATTERN;
+    }
+    h->ms_setup = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    *out = h;
+    return QG_OK;
+}
+
+int qg_solve_batch(qg_handle *h, double *x, double *s, double *y, double *z, qg_info *info) {
+    if (!h) return QG_ERR_ARG;
+    int rc = ipm_solve(h, x, nullptr, y, nullptr, info);
+    if (rc) return rc;
+    const int64_t tot = (int64_t)h->ncopy * h->m1;
+    if (tot > 0) {
+        const unsigned g = (unsigned)((tot + 255) / 256);
+        if (s) unstack_cone_rows<<<g, 256, 0, h->stream>>>(h->d.s.p, s, h->ncopy, h->m1, h->l1);
+        if (z) unstack_cone_rows<<<g, 256, 0, h->stream>>>(h->d.z.p, z, h->ncopy, h->m1, h->l1);
+        QG_HIP(h, hipGetLastError());
+        QG_HIP(h, hipStreamSynchronize(h->stream));
+    }
+    return QG_OK;
+}
+
 int qg_update(qg_handle *h, const double *Pval, const double *c, const double *Aval, const double *b,
               const double *Gval, const double *hv) {
     if (!h) return QG_ERR_ARG;
+    if (h->ncopy > 1) return QG_ERR_STATE;
     auto chk = [](const double *v, size_t len) { return v == nullptr || finite_all(v, (int64_t)len); };
     if (!chk(Pval, h->pp.P.val.size()) || !chk(c, h->n) || !chk(Aval, h->pp.A.val.size()) ||
         !chk(b, h->p) || !chk(Gval, h->pp.G.val.size()) || !chk(hv, h->m))
@@ -454,6 +569,7 @@ int qg_update(qg_handle *h, const double *Pval, const double *c, const double *A
 
 int qg_update_vectors(qg_handle *h, const double *c, const double *b, const double *hv) {
     if (!h) return QG_ERR_ARG;
+    if (h->ncopy > 1) return QG_ERR_STATE;
     int bad = 0;
     int rc = count_nonfinite(h, c, h->n, b, h->p, hv, h->m, &bad);
     if (rc) return rc;
@@ -475,6 +591,7 @@ int qg_set_settings(qg_handle *h, const qg_settings *s) {
 
 int qg_solve(qg_handle *h, double *x, double *s, double *y, double *z, qg_info *info) {
     if (!h) return QG_ERR_ARG;
+    if (h->ncopy > 1) return QG_ERR_STATE;
     return ipm_solve(h, x, s, y, z, info);
 }
 
@@ -618,7 +735,7 @@ int qg_step_cone_op(qg_handle *h, int op, const double *u, const double *v, doub
 
 int qg_step_corrector(qg_handle *h, const double *ds_a, const double *dz_a, double sigma_mu, double *t) {
     if (!h || !ds_a || !dz_a || !t || !(sigma_mu >= 0.0)) return QG_ERR_ARG;
-    int rc = launch_corrector(h, ds_a, dz_a, sigma_mu, nullptr, 0.0, t);
+    int rc = launch_corrector(h, ds_a, dz_a, sigma_mu, h->d.mu.p, t);
     if (rc) return rc;
     QG_HIP(h, hipStreamSynchronize(h->stream));
     return QG_OK;

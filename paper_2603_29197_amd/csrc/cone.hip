@@ -190,20 +190,23 @@ __global__ void corrector_kernel(int32_t l, int32_t nsoc, const int32_t *__restr
                                  const double *__restrict__ w, const double *__restrict__ wbar,
                                  const double *__restrict__ beta, const double *__restrict__ lam,
                                  const double *__restrict__ dsa, const double *__restrict__ dza,
-                                 const unsigned long long *__restrict__ amin, double mu, double sigma_mu_fixed,
-                                 double *__restrict__ tout, double *__restrict__ alpha_rec) {
+                                 const unsigned long long *__restrict__ amin, const double *__restrict__ mu,
+                                 double sigma_mu_fixed, double *__restrict__ tout, double *__restrict__ alpha_rec,
+                                 int32_t l1, int32_t nsoc1, int32_t kb) {
+    const int32_t t = blockIdx.x * 256 + threadIdx.x;
+    const int32_t inst = cone_problem(t, l, l1, nsoc1, kb);
     double smu;
     if (sigma_mu_fixed >= 0.0) {
         smu = sigma_mu_fixed;
     } else {
-        const double aa = fmin(1.0, fmin(__longlong_as_double((long long)amin[0]),
-                                         __longlong_as_double((long long)amin[1])));
+        const unsigned long long *am = amin + 4 * inst;
+        const double aa = fmin(1.0, fmin(__longlong_as_double((long long)am[0]),
+                                         __longlong_as_double((long long)am[1])));
         const double om = 1.0 - aa;
         const double sigma = fmin(1.0, fmax(0.0, om * om * om));
-        smu = sigma * mu;
-        if (blockIdx.x == 0 && threadIdx.x == 0 && alpha_rec) alpha_rec[0] = aa;
+        smu = sigma * mu[inst];
+        if (t == 0 && alpha_rec) alpha_rec[0] = aa;
     }
-    const int32_t t = blockIdx.x * 256 + threadIdx.x;
     if (t < l) {
         const double li = lam[t], wi = w[t];
         const double d = -li * li - (dsa[t] / wi) * (wi * dza[t]) + smu;
@@ -262,7 +265,7 @@ __global__ void corrector_kernel(int32_t l, int32_t nsoc, const int32_t *__restr
 // nonnegative double)
 __global__ void step_kernel(int32_t l, int32_t nsoc, const int32_t *__restrict__ soc_off,
                             const double *__restrict__ u, const double *__restrict__ du,
-                            unsigned long long *__restrict__ amin) {
+                            unsigned long long *__restrict__ amin, int32_t l1, int32_t nsoc1, int32_t kb) {
     const int32_t t = blockIdx.x * 256 + threadIdx.x;
     double a = INFINITY;
     if (t < l) {
@@ -272,13 +275,20 @@ __global__ void step_kernel(int32_t l, int32_t nsoc, const int32_t *__restrict__
         const int32_t off = soc_off[k], q = soc_off[k + 1] - off;
         a = soc_max_step(u + off, du + off, q);
     }
-    // wave min, then one atomic per wave
-    for (int off = 32; off > 0; off >>= 1) a = fmin(a, __shfl_xor(a, off));
-    if ((threadIdx.x & 63) == 0) atomicMin(amin + 0, (unsigned long long)__double_as_longlong(a));
+    // the minimum of each problem: a wave min and one atomic per wave when the wave's cones belong to
+    // one problem (always for a single problem), else one atomic per cone
+    const int32_t inst = cone_problem(t, l, l1, nsoc1, kb);
+    if (__all(inst == __shfl(inst, 0))) {
+        for (int off = 32; off > 0; off >>= 1) a = fmin(a, __shfl_xor(a, off));
+        if ((threadIdx.x & 63) == 0) atomicMin(amin + 4 * inst, (unsigned long long)__double_as_longlong(a));
+    } else if (a < INFINITY) {
+        atomicMin(amin + 4 * inst, (unsigned long long)__double_as_longlong(a));
+    }
 }
 
-__global__ void reset_steps_kernel(unsigned long long *amin) {
-    if (threadIdx.x < 4) amin[threadIdx.x] = (unsigned long long)__double_as_longlong(INFINITY);
+__global__ void reset_steps_kernel(unsigned long long *amin, int32_t n) {
+    const int32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) amin[i] = (unsigned long long)__double_as_longlong(INFINITY);
 }
 
 // lambda_min per cone (orthant u_i, SOC u0 - |u1|), reduced as max(-lambda_min)
@@ -501,18 +511,21 @@ __global__ void __launch_bounds__(256) corrector_big(int32_t l, int32_t nbig, co
                                                      const double *__restrict__ wbar,
                                                      const double *__restrict__ beta, const double *__restrict__ lam,
                                                      const double *__restrict__ dsa, const double *__restrict__ dza,
-                                                     const unsigned long long *__restrict__ amin, double mu,
-                                                     double sigma_mu_fixed, double *__restrict__ tout) {
+                                                     const unsigned long long *__restrict__ amin,
+                                                     const double *__restrict__ mu, double sigma_mu_fixed,
+                                                     double *__restrict__ tout, int32_t nsoc1) {
     const int32_t gw = big_wave();
     if (gw >= nbig) return;
     double smu;
     if (sigma_mu_fixed >= 0.0) {
         smu = sigma_mu_fixed;
     } else {
-        const double aa = fmin(1.0, fmin(__longlong_as_double((long long)amin[0]),
-                                         __longlong_as_double((long long)amin[1])));
+        const int32_t inst = big[gw] / nsoc1;
+        const unsigned long long *am = amin + 4 * inst;
+        const double aa = fmin(1.0, fmin(__longlong_as_double((long long)am[0]),
+                                         __longlong_as_double((long long)am[1])));
         const double om = 1.0 - aa;
-        smu = fmin(1.0, fmax(0.0, om * om * om)) * mu;
+        smu = fmin(1.0, fmax(0.0, om * om * om)) * mu[inst];
     }
     const int lane = threadIdx.x & 63;
     const int32_t k = big[gw];
@@ -562,14 +575,15 @@ __global__ void __launch_bounds__(256) corrector_big(int32_t l, int32_t nbig, co
 // per-cone maximum step, min-reduced into amin (see step_kernel)
 __global__ void __launch_bounds__(256) step_big(int32_t nbig, const int32_t *__restrict__ big,
                                                 const int32_t *__restrict__ soc_off, const double *__restrict__ u,
-                                                const double *__restrict__ du, unsigned long long *__restrict__ amin) {
+                                                const double *__restrict__ du, unsigned long long *__restrict__ amin,
+                                                int32_t nsoc1) {
     const int32_t gw = big_wave();
     if (gw >= nbig) return;
     const int lane = threadIdx.x & 63;
     const int32_t k = big[gw];
     const int32_t off = soc_off[k], q = soc_off[k + 1] - off;
     const double a = wave_soc_max_step(u + off, du + off, q, lane);
-    if (lane == 0 && a < INFINITY) atomicMin(amin, (unsigned long long)__double_as_longlong(a));
+    if (lane == 0 && a < INFINITY) atomicMin(amin + 4 * (k / nsoc1), (unsigned long long)__double_as_longlong(a));
 }
 
 // -lambda_min = |u1| - u0 per big cone, max-reduced per block into partials[blockIdx.x]
@@ -645,16 +659,17 @@ int launch_ds_from_dz(qg_handle *h, const double *tvec, double tsign, const doub
 }
 
 int launch_corrector(qg_handle *h, const double *dsa, const double *dza, double sigma_mu,
-                     const double *alpha_aff_dev, double mu, double *t) {
-    (void)alpha_aff_dev;
+                     const double *mu_dev, double *t) {
     Device &d = h->d;
+    const int32_t kb = h->ncopy;
     corrector_kernel<<<cone_grid(h), 256, 0, h->stream>>>(h->pp.l, h->pp.nsoc, d.soc_off.p, d.w.p, d.wbar.p,
-                                                           d.beta.p, d.lam.p, dsa, dza, d.amin.p, mu, sigma_mu,
-                                                           t, d.alpha.p);
+                                                           d.beta.p, d.lam.p, dsa, dza, d.amin.p, mu_dev, sigma_mu,
+                                                           t, d.alpha.p, h->pp.l / kb, h->pp.nsoc / kb, kb);
     QG_HIP(h, hipGetLastError());
     if (h->nbig) {
         corrector_big<<<big_grid(h), 256, 0, h->stream>>>(h->pp.l, h->nbig, d.big_cones.p, d.soc_off.p, d.wbar.p,
-                                                           d.beta.p, d.lam.p, dsa, dza, d.amin.p, mu, sigma_mu, t);
+                                                           d.beta.p, d.lam.p, dsa, dza, d.amin.p, mu_dev, sigma_mu, t,
+                                                           h->pp.nsoc / kb);
         QG_HIP(h, hipGetLastError());
     }
     return QG_OK;
@@ -687,17 +702,21 @@ int launch_identity_vec(qg_handle *h, double *u) {
 }
 
 int launch_reset_steps(qg_handle *h) {
-    reset_steps_kernel<<<1, 64, 0, h->stream>>>(h->d.amin.p);
+    const int32_t n = 4 * h->ncopy;
+    reset_steps_kernel<<<(n + 255) / 256, 256, 0, h->stream>>>(h->d.amin.p, n);
     QG_HIP(h, hipGetLastError());
     return QG_OK;
 }
 
 int launch_step_min(qg_handle *h, const double *u, const double *du, int slot) {
     Device &d = h->d;
-    step_kernel<<<cone_grid(h), 256, 0, h->stream>>>(h->pp.l, h->pp.nsoc, d.soc_off.p, u, du, d.amin.p + slot);
+    const int32_t kb = h->ncopy;
+    step_kernel<<<cone_grid(h), 256, 0, h->stream>>>(h->pp.l, h->pp.nsoc, d.soc_off.p, u, du, d.amin.p + slot,
+                                                      h->pp.l / kb, h->pp.nsoc / kb, kb);
     QG_HIP(h, hipGetLastError());
     if (h->nbig) {
-        step_big<<<big_grid(h), 256, 0, h->stream>>>(h->nbig, d.big_cones.p, d.soc_off.p, u, du, d.amin.p + slot);
+        step_big<<<big_grid(h), 256, 0, h->stream>>>(h->nbig, d.big_cones.p, d.soc_off.p, u, du, d.amin.p + slot,
+                                                      h->pp.nsoc / kb);
         QG_HIP(h, hipGetLastError());
     }
     return QG_OK;

@@ -94,6 +94,37 @@ __device__ inline T regularize(T d, int8_t kind_j, double eps, double dyn, int32
 // ---------------------------------------------------------------------------
 // small fronts: one 256-thread workgroup per front, front in LDS
 // ---------------------------------------------------------------------------
+// The k pivot steps of one assembled front F (r x r, column-major, in LDS;
+// lower part) by the whole 256-thread workgroup, then F's lower part back to
+// the front storage G: L in the first k columns, the update block after them.
+template <typename T>
+__device__ inline void factor_front_lds(T *F, T *__restrict__ G, int32_t r, int32_t k,
+                                        const int8_t *__restrict__ kind, double eps, double dyn, int32_t *nreg,
+                                        T &dsh) {
+    const int tid = threadIdx.x;
+    for (int32_t jj = 0; jj < k; ++jj) {
+        if (tid == 0) {
+            T d = regularize(F[jj * r + jj], kind[jj], eps, dyn, nreg);
+            F[jj * r + jj] = d;
+            dsh = d;
+        }
+        __syncthreads();
+        const T d = dsh;
+        const int32_t R = r - jj - 1;
+        for (int32_t idx = tid; idx < R * R; idx += 256) {
+            const int32_t i = jj + 1 + idx % R, c = jj + 1 + idx / R;
+            if (i >= c) F[c * r + i] -= F[jj * r + i] * F[jj * r + c] / d;
+        }
+        __syncthreads();
+        for (int32_t i = jj + 1 + tid; i < r; i += 256) F[jj * r + i] /= d;
+        __syncthreads();
+    }
+    for (int32_t idx = tid; idx < r * r; idx += 256) {
+        const int32_t i = idx % r, c = idx / r;
+        if (i >= c) G[idx] = F[idx];
+    }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) factor_small(
     const int32_t *__restrict__ sn_list, const int32_t *__restrict__ sn_first,
@@ -119,26 +150,82 @@ __global__ void __launch_bounds__(256) factor_small(
         }
     }
     __syncthreads();
-    for (int32_t jj = 0; jj < k; ++jj) {
-        if (tid == 0) {
-            T d = regularize(F[jj * r + jj], kind[sn_first[s] + jj], eps, dyn, nreg);
-            F[jj * r + jj] = d;
-            dsh = d;
+    factor_front_lds(F, G, r, k, kind + sn_first[s], eps, dyn, nreg, dsh);
+}
+
+// Chains (the narrow upper levels of deep elimination trees): one workgroup
+// per component walks the component's levels; the fronts of a level are
+// factored one per wavefront, each in its own LDS tile, with the same
+// arithmetic as factor_small (pivot, rank-1 update of the trailing lower
+// part, column scaling), the steps separated by wavefront barriers only (the
+// LDS operations of one wavefront complete in order).  A front is assembled
+// in its tile from the entries of the numeric assembly map (the same sources
+// in the same order as gather_entries: the K entry, the static regularization
+// of a pivot diagonal, then the children's update entries).  Children below
+// the chain levels were factored by the level kernels before this launch;
+// children inside the component by this workgroup, before the workgroup
+// barrier that ends their level.
+template <typename T>
+__global__ void __launch_bounds__(256) factor_chain(
+    const int32_t *__restrict__ comp_ptr, const int32_t *__restrict__ grp_ptr, const int32_t *__restrict__ chain_sn,
+    const int64_t *__restrict__ ent_front, const int64_t *__restrict__ dst, const int64_t *__restrict__ sptr,
+    const int8_t *__restrict__ reg, const int64_t *__restrict__ src, const double *__restrict__ kval,
+    double delta, const int32_t *__restrict__ sn_first, const int64_t *__restrict__ sn_rptr,
+    const int64_t *__restrict__ fr_off, T *__restrict__ front, const int8_t *__restrict__ kind, double eps,
+    double dyn, int32_t *nreg) {
+    __shared__ T tile[4][CHAIN_R * CHAIN_R];
+    __shared__ T dsh[4];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    T *F = tile[w];
+    const int32_t c = blockIdx.x;
+    for (int32_t g = comp_ptr[c]; g < comp_ptr[c + 1]; ++g) {
+        for (int32_t t = grp_ptr[g] + w; t < grp_ptr[g + 1]; t += 4) {
+            const int32_t s = chain_sn[t];
+            const int32_t r = (int32_t)(sn_rptr[s + 1] - sn_rptr[s]);
+            const int32_t k = sn_first[s + 1] - sn_first[s];
+            const int64_t base = fr_off[s];
+            const int8_t *kd_s = kind + sn_first[s];
+            for (int32_t idx = lane; idx < r * r; idx += 64) F[idx] = T(0);
+            __builtin_amdgcn_wave_barrier();
+            for (int64_t e = ent_front[2 * s] + lane; e < ent_front[2 * s + 1]; e += 64) {
+                int64_t u = sptr[e];
+                const int64_t u1 = sptr[e + 1];
+                T v = T(0);
+                if (u < u1) {
+                    const int64_t s0 = src[u];
+                    if (s0 < 0) { v = (T)kval[-s0 - 1]; ++u; }
+                }
+                const int8_t kd = reg[e];
+                if (kd >= 0) v = (T)((double)v + static_reg(kd, delta));
+                for (; u < u1; ++u) v += front[src[u]];
+                F[dst[e] - base] = v;
+            }
+            __builtin_amdgcn_wave_barrier();
+            for (int32_t jj = 0; jj < k; ++jj) {
+                if (lane == 0) {
+                    const T d = regularize(F[jj * r + jj], kd_s[jj], eps, dyn, nreg);
+                    F[jj * r + jj] = d;
+                    dsh[w] = d;
+                }
+                __builtin_amdgcn_wave_barrier();
+                const T d = dsh[w];
+                const int32_t R = r - jj - 1;
+                for (int32_t idx = lane; idx < R * R; idx += 64) {
+                    const int32_t i = jj + 1 + idx % R, cc = jj + 1 + idx / R;
+                    if (i >= cc) F[cc * r + i] -= F[jj * r + i] * F[jj * r + cc] / d;
+                }
+                __builtin_amdgcn_wave_barrier();
+                for (int32_t i = jj + 1 + lane; i < r; i += 64) F[jj * r + i] /= d;
+                __builtin_amdgcn_wave_barrier();
+            }
+            T *G = front + base;
+            for (int32_t idx = lane; idx < r * r; idx += 64) {
+                const int32_t i = idx % r, cc = idx / r;
+                if (i >= cc) G[idx] = F[idx];
+            }
+            __builtin_amdgcn_wave_barrier();
         }
         __syncthreads();
-        const T d = dsh;
-        const int32_t R = r - jj - 1;
-        for (int32_t idx = tid; idx < R * R; idx += 256) {
-            const int32_t i = jj + 1 + idx % R, c = jj + 1 + idx / R;
-            if (i >= c) F[c * r + i] -= F[jj * r + i] * F[jj * r + c] / d;
-        }
-        __syncthreads();
-        for (int32_t i = jj + 1 + tid; i < r; i += 256) F[jj * r + i] /= d;
-        __syncthreads();
-    }
-    for (int32_t idx = tid; idx < r * r; idx += 256) {
-        const int32_t i = idx % r, c = idx / r;
-        if (i >= c) G[idx] = F[idx];
     }
 }
 
@@ -189,7 +276,10 @@ __device__ inline typename Acc4<T>::type tile16(FA a, FB b) {
 template <typename T>
 __global__ void __launch_bounds__(256) diag_block(T *__restrict__ F, int32_t r, int32_t j0, int32_t b,
                                                   const int8_t *__restrict__ kind_cols, double eps,
-                                                  double dyn, int32_t *nreg, T *__restrict__ Xg) {
+                                                  double dyn, int32_t *nreg, T *__restrict__ Xg, CopyStride cs) {
+    F += blockIdx.z * cs.f;
+    kind_cols += blockIdx.z * cs.col;
+    Xg += blockIdx.z * cs.dinv;
     // the panel chain is the critical path of a large front: its waves win issue
     // arbitration against the concurrent bulk update on a shared compute unit
     __builtin_amdgcn_s_setprio(3);
@@ -354,7 +444,11 @@ __global__ void __launch_bounds__(256) diag_block(T *__restrict__ F, int32_t r, 
 template <typename T>
 __global__ void __launch_bounds__(256) sblock_inverse(const T *__restrict__ F, int32_t r, int32_t J0, int32_t kb,
                                                       const T *__restrict__ dinv_s, int32_t ld,
-                                                      T *__restrict__ Xs, T *__restrict__ XTs) {
+                                                      T *__restrict__ Xs, T *__restrict__ XTs, CopyStride cs) {
+    F += blockIdx.z * cs.f;
+    dinv_s += blockIdx.z * cs.dinv;
+    Xs += blockIdx.z * cs.sinv;
+    XTs += blockIdx.z * cs.sinv;
     constexpr int LD = NB + 1;
     __shared__ T A[NB * LD];         // A[k * LD + i] = operand A(i, k)
     __shared__ T B[NB * LD];         // B[j * LD + k] = operand B(k, j)
@@ -446,7 +540,9 @@ __global__ void __launch_bounds__(256) sblock_inverse(const T *__restrict__ F, i
 // run along the contiguous rows of the front in the store.
 template <typename T>
 __global__ void __launch_bounds__(256) panel_solve(T *__restrict__ F, int32_t r, int32_t j0, int32_t b,
-                                                   const T *__restrict__ Xg) {
+                                                   const T *__restrict__ Xg, CopyStride cs) {
+    F += blockIdx.z * cs.f;
+    Xg += blockIdx.z * cs.dinv;
     __builtin_amdgcn_s_setprio(3);                      // panel chain: see diag_block
     constexpr int XP = sizeof(T) == 4 ? NB + 16 : NB;   // pitch: MFMA operand rows on disjoint banks
     __shared__ T Xs[NB * XP];        // Xs[t * XP + c] = X(c, t)
@@ -503,7 +599,8 @@ __global__ void __launch_bounds__(256) panel_solve(T *__restrict__ F, int32_t r,
 // along a column of the column-major front.
 template <typename T>
 __global__ void __launch_bounds__(256) trail_update(T *__restrict__ F, int32_t r, int32_t k0, int32_t kb,
-                                                   int32_t r_lo, int32_t c_hi, int32_t urgent) {
+                                                   int32_t r_lo, int32_t c_hi, int32_t urgent, int64_t zstride) {
+    F += blockIdx.z * zstride;
     constexpr int KC = 32;
     constexpr int PER = KC / 4;                    // rank columns staged per thread and chunk
     // row pitch of the LDS tiles: the four 16-lane groups of an MFMA operand read rows kk .. kk+3;
@@ -560,12 +657,18 @@ __global__ void __launch_bounds__(256) trail_update(T *__restrict__ F, int32_t r
             vb |= (uint32_t)okb << u;
         }
     };
+    // branch-free: the pivots are read for every staged entry (the index clamped into Dk) and the
+    // invalid entries replaced by zeros with selects
     auto lstore = [&](int buf, int32_t kc) {
+        T dk[PER];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) dk[u] = Dk[min(kc + (tid >> 6) + 4 * u, SB - 1)];
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
             const int32_t kk = (tid >> 6) + 4 * u;
+            const T b = rb[u] * dk[u];
             As[buf][kk * LDT + i] = ((va >> u) & 1u) ? ra[u] : T(0);
-            Bs[buf][kk * LDT + i] = ((vb >> u) & 1u) ? rb[u] * Dk[kc + kk] : T(0);
+            Bs[buf][kk * LDT + i] = ((vb >> u) & 1u) ? b : T(0);
         }
     };
     V acc[2][2];
@@ -611,6 +714,132 @@ __global__ void __launch_bounds__(256) trail_update(T *__restrict__ F, int32_t r
             }
 }
 
+// The same update on 128 x 128 tiles, for the large launches (the rank-SB
+// updates of a super-panel across the rest of the front).  Each wavefront owns
+// a 64 x 64 quarter as 4 x 4 MFMA 16x16x4 blocks, so every operand read from
+// LDS feeds four MFMAs (twice the reuse of the 64 x 64 tiles) and every entry
+// of the two panel blocks staged per chunk serves 128 rows or columns.  The
+// rank is consumed in chunks of KC columns through double-buffered LDS, the
+// global loads of the next chunk in flight during the MFMAs of the current
+// one; C is read once, after the last chunk.  On a diagonal tile the quarter
+// strictly above the diagonal does no MFMA work.
+template <typename T>
+__global__ void __launch_bounds__(256) trail_update_big(T *__restrict__ F, int32_t r, int32_t k0, int32_t kb,
+                                                       int32_t r_lo, int32_t c_hi, int32_t urgent,
+                                                       int64_t zstride) {
+    F += blockIdx.z * zstride;
+    constexpr int TILE = 128;
+    constexpr int KC = 32;
+    constexpr int PER = KC * TILE / 256;           // rank columns staged per thread and chunk (16)
+    // row pitch of the LDS tiles: the four 16-lane groups of an MFMA operand read rows kk .. kk+3;
+    // for 4-byte entries a pitch of 144 (16 mod 32 banks) puts each half-wavefront on disjoint banks
+    constexpr int LDT = sizeof(T) == 4 ? TILE + 16 : TILE;
+    __shared__ T As[2][KC * LDT];                  // As[kk * LDT + i] = L(r0 + i, k)
+    __shared__ T Bs[2][KC * LDT];                  // Bs[kk * LDT + j] = L(c0 + j, k) * D(k)
+    __shared__ T Dk[SB];
+    // XCD-aware order as in trail_update: XCD x takes the tile rows ti = x (mod 8)
+    const int32_t TR = (r - r_lo + TILE - 1) / TILE, TC = (c_hi - r_lo + TILE - 1) / TILE, NR = (TR + 7) / 8;
+    const int32_t xcd = blockIdx.x % 8, sq = blockIdx.x / 8;
+    const int32_t tj = sq / NR, ti = (sq % NR) * 8 + xcd;
+    if (ti >= TR || tj >= TC || ti < tj) return;
+    if (urgent) __builtin_amdgcn_s_setprio(2);     // on the panel chain: ahead of the bulk update's waves
+    const int32_t r0 = r_lo + TILE * ti, c0 = r_lo + TILE * tj;
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
+    const int lr = lane & 15, lk = lane >> 4;
+    // this quarter stores results unless it lies beyond the last row or column, or strictly above the diagonal
+    const bool active = r0 + wr < r && c0 + wc < c_hi && r0 + wr + 63 >= c0 + wc;
+    typedef typename Acc4<T>::type V;
+    const int32_t i = tid & (TILE - 1);
+    const int kk0 = tid >> 7;                      // 0 or 1
+    T ra[PER], rb[PER];
+    uint32_t va = 0, vb = 0;
+    auto gload = [&](int32_t kc) {
+        va = vb = 0;
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int32_t kk = kk0 + 2 * u;
+            const bool okk = kc + kk < kb;
+            const int32_t kcol = k0 + kc + (okk ? kk : 0);
+            const T *colp = F + (int64_t)kcol * r;
+            const bool oka = okk && r0 + i < r, okb = okk && c0 + i < c_hi;
+            ra[u] = colp[oka ? r0 + i : 0];
+            rb[u] = colp[okb ? c0 + i : 0];
+            va |= (uint32_t)oka << u;
+            vb |= (uint32_t)okb << u;
+        }
+    };
+    auto lstore = [&](int buf, int32_t kc) {
+        T dk[PER];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) dk[u] = Dk[min(kc + kk0 + 2 * u, SB - 1)];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int32_t kk = kk0 + 2 * u;
+            const T b = rb[u] * dk[u];
+            As[buf][kk * LDT + i] = ((va >> u) & 1u) ? ra[u] : T(0);
+            Bs[buf][kk * LDT + i] = ((vb >> u) & 1u) ? b : T(0);
+        }
+    };
+    V acc[4][4];
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = V{0, 0, 0, 0};
+    const int32_t nch = (kb + KC - 1) / KC;
+    if (tid < kb) Dk[tid] = F[(int64_t)(k0 + tid) * r + k0 + tid];
+    gload(0);
+    __syncthreads();
+    lstore(0, 0);
+    __syncthreads();
+    for (int32_t c = 0; c < nch; ++c) {
+        const int buf = c & 1;
+        if (c + 1 < nch) gload((c + 1) * KC);
+        // every quarter runs the MFMAs (a quarter without entries to update, on the edges or above the
+        // diagonal, computes products it never stores): no branch around them, so the accumulators stay
+        // in the accumulation registers for the whole loop
+#pragma unroll
+        for (int32_t kk = 0; kk < KC; kk += 4) {       // zero-padded past the rank
+            const int32_t kq = kk + lk;
+            T a_op[4], b_op[4];
+#pragma unroll
+            for (int bj = 0; bj < 4; ++bj) a_op[bj] = Bs[buf][kq * LDT + wc + 16 * bj + lr];
+#pragma unroll
+            for (int bi = 0; bi < 4; ++bi) b_op[bi] = As[buf][kq * LDT + wr + 16 * bi + lr];
+#pragma unroll
+            for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = mfma16x16x4(a_op[bj], b_op[bi], acc[bi][bj]);
+        }
+        if (c + 1 < nch) lstore(buf ^ 1, (c + 1) * KC);
+        __syncthreads();
+    }
+    if (!active) return;
+    // lane holds C(row = wr + 16 bi + lr, col = wc + 16 bj + mfma_out_row(lk, v)); 16 lanes store 16
+    // consecutive rows of one column
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi) {
+        const int32_t row = r0 + wr + 16 * bi + lr;
+        T cold[4][4];
+#pragma unroll
+        for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int32_t col = c0 + wc + 16 * bj + mfma_out_row<T>(lk, v);
+                const bool ok = row < r && col < c_hi && row >= col;
+                cold[bj][v] = F[ok ? (int64_t)col * r + row : 0];
+            }
+#pragma unroll
+        for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int32_t col = c0 + wc + 16 * bj + mfma_out_row<T>(lk, v);
+                if (row < r && col < c_hi && row >= col) F[(int64_t)col * r + row] = cold[bj][v] - acc[bi][bj][v];
+            }
+    }
+}
+
 // W_J = L(J1:r, J0:J1) X_J for a super-panel [J0, J1) (X_J the inverse of its
 // unit-lower diagonal block, column-major with leading dimension ld), written
 // column-major with leading dimension r - J1.  The solves use W_J: the forward
@@ -621,7 +850,11 @@ __global__ void __launch_bounds__(256) trail_update(T *__restrict__ F, int32_t r
 // transposed so that lanes run along the rows of W in the store.
 template <typename T>
 __global__ void __launch_bounds__(256) wblock(const T *__restrict__ F, int32_t r, int32_t J0, int32_t kb,
-                                             const T *__restrict__ Xs, int32_t ld, T *__restrict__ W) {
+                                             const T *__restrict__ Xs, int32_t ld, T *__restrict__ W,
+                                             CopyStride cs) {
+    F += blockIdx.z * cs.f;
+    Xs += blockIdx.z * cs.sinv;
+    W += blockIdx.z * cs.w;
     constexpr int KC = 32, PER = KC * 64 / 256;
     constexpr int AP = sizeof(T) == 4 ? 80 : 64;   // pitch: MFMA operand rows on disjoint banks
     __shared__ T As[KC * AP];          // As[kk * AP + i] = L(J1 + 64 ti + i, J0 + kc + kk)
@@ -687,15 +920,16 @@ static void prof_begin(hipStream_t st, hipEvent_t *e0, hipEvent_t *e1) {
     if (hipEventCreate(e0) != hipSuccess || hipEventCreate(e1) != hipSuccess) { *e0 = *e1 = nullptr; return; }
     (void)hipEventRecord(*e0, st);
 }
-static void prof_end(qg_handle *h, hipStream_t st, hipEvent_t e0, hipEvent_t e1, double flops, int fp32) {
+// slot = (128 x 128 tiles ? 2 : 0) + (FP32 ? 1 : 0)
+static void prof_end(qg_handle *h, hipStream_t st, hipEvent_t e0, hipEvent_t e1, double flops, int slot) {
     if (!e0) return;
     (void)hipEventRecord(e1, st);
-    h->prof_events.push_back({{e0, e1}, fp32});
-    h->prof_flops[fp32] += flops;
+    h->prof_events.push_back({{e0, e1}, slot});
+    h->prof_flops[slot] += flops;
 }
 
 void prof_collect(qg_handle *h, int64_t *launches, double *ms, double *flops) {
-    for (int q = 0; q < 2; ++q) { launches[q] = 0; ms[q] = 0.0; flops[q] = h->prof_flops[q]; }
+    for (int q = 0; q < 4; ++q) { launches[q] = 0; ms[q] = 0.0; flops[q] = h->prof_flops[q]; }
     for (auto &pr : h->prof_events) {
         float t = 0.f;
         if (hipEventSynchronize(pr.first.second) == hipSuccess &&
@@ -706,23 +940,34 @@ void prof_collect(qg_handle *h, int64_t *launches, double *ms, double *flops) {
         (void)hipEventDestroy(pr.first.second);
     }
     h->prof_events.clear();
-    h->prof_flops[0] = h->prof_flops[1] = 0.0;
+    for (double &f : h->prof_flops) f = 0.0;
 }
 
 template <typename T>
 static void launch_update(qg_handle *h, hipStream_t st, T *F, int32_t r, int32_t k0, int32_t kb, int32_t r_lo,
-                          int32_t c_hi) {
+                          int32_t c_hi, const CopyStride &cs, int32_t ncopy) {
     const int32_t TR = (r - r_lo + 63) / 64, TC = (c_hi - r_lo + 63) / 64;
     if (TR <= 0 || TC <= 0 || kb <= 0) return;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (h->st.profile) prof_begin(st, &e0, &e1);
-    trail_update<T><<<(unsigned)(8 * TC * ((TR + 7) / 8)), 256, 0, st>>>(F, r, k0, kb, r_lo, c_hi,
-                                                                         st == h->stream ? 1 : 0);
+    // large launches (at least one 128 x 128 lower tile per compute unit) on the big tiles
+    const int64_t TR2 = (r - r_lo + 127) / 128, TC2 = (c_hi - r_lo + 127) / 128;
+    const int64_t lower2 = TC2 * TR2 - TC2 * (TC2 - 1) / 2;
+    const int urgent = st == h->stream ? 1 : 0;
+    // FP32 only: the FP64 variant needs more registers than two wavefronts per SIMD allow and was
+    // measured slower than the 64 x 64 tiles (one wavefront per SIMD leaves the loads unhidden)
+    const bool big = sizeof(T) == 4 && lower2 * ncopy >= 256 && kb > 64;
+    if (big)
+        trail_update_big<T><<<dim3((unsigned)(8 * TC2 * ((TR2 + 7) / 8)), 1, (unsigned)ncopy), 256, 0, st>>>(
+            F, r, k0, kb, r_lo, c_hi, urgent, cs.f);
+    else
+        trail_update<T><<<dim3((unsigned)(8 * TC * ((TR + 7) / 8)), 1, (unsigned)ncopy), 256, 0, st>>>(
+            F, r, k0, kb, r_lo, c_hi, urgent, cs.f);
     if (h->st.profile) {
         // lower part of rows [r_lo, r) x cols [r_lo, c_hi): sum over columns of (r - col)
         const double M = (double)(r - r_lo), C = (double)(c_hi - r_lo);
         const double entries = C * M - C * (C - 1.0) / 2.0;
-        prof_end(h, st, e0, e1, 2.0 * (double)kb * entries, sizeof(T) == 4);
+        prof_end(h, st, e0, e1, 2.0 * (double)kb * entries * ncopy, (big ? 2 : 0) + (sizeof(T) == 4 ? 1 : 0));
     }
 }
 
@@ -737,7 +982,8 @@ static void launch_update(qg_handle *h, hipStream_t st, T *F, int32_t r, int32_t
 // solves need are formed on the prep stream.  Both side streams are joined at
 // the end.
 template <typename T>
-static int factor_large(qg_handle *h, int32_t s, T *front, T *dinv, T *sinv, T *wb, const RegParams &rp) {
+static int factor_large(qg_handle *h, int32_t s, T *front, T *dinv, T *sinv, T *wb, const RegParams &rp,
+                        const CopyStride &cs, int32_t ncopy) {
     const Plan &pl = h->plan;
     const int32_t r = (int32_t)(pl.sn_rptr[s + 1] - pl.sn_rptr[s]);
     const int32_t k = pl.sn_first[s + 1] - pl.sn_first[s];
@@ -754,11 +1000,11 @@ static int factor_large(qg_handle *h, int32_t s, T *front, T *dinv, T *sinv, T *
         for (int32_t j0 = J0; j0 < J1; j0 += NB) {
             const int32_t b = std::min(NB, J1 - j0);
             T *ws = dinv + pl.dinv_off[s] + (int64_t)(j0 / NB) * NB * NB;
-            diag_block<T><<<1, 256, 0, ms>>>(F, r, j0, b, kinds, rp.eps, rp.dyn, h->d.nreg.p, ws);
+            diag_block<T><<<dim3(1, 1, ncopy), 256, 0, ms>>>(F, r, j0, b, kinds, rp.eps, rp.dyn, h->d.nreg.p, ws, cs);
             const int32_t mb = r - j0 - b;
-            if (mb > 0) panel_solve<T><<<(mb + 63) / 64, 256, 0, ms>>>(F, r, j0, b, ws);
+            if (mb > 0) panel_solve<T><<<dim3((mb + 63) / 64, 1, ncopy), 256, 0, ms>>>(F, r, j0, b, ws, cs);
             // rest of this super-panel's columns (rank b)
-            if (j0 + b < J1) launch_update<T>(h, ms, F, r, j0, b, j0 + b, J1);
+            if (j0 + b < J1) launch_update<T>(h, ms, F, r, j0, b, j0 + b, J1, cs, ncopy);
         }
         QG_HIP(h, hipEventRecord(h->ev_panel, ms));
         {
@@ -766,22 +1012,22 @@ static int factor_large(qg_handle *h, int32_t s, T *front, T *dinv, T *sinv, T *
             QG_HIP(h, hipStreamWaitEvent(h->prep, h->ev_panel, 0));
             const int32_t nsub = (J1 - J0 + NB - 1) / NB, ld = nsub * NB;
             T *Xs = sinv + pl.sinv_off[s] + (int64_t)(J0 / SB) * 2 * SB * SB;
-            sblock_inverse<T><<<nsub, 256, 0, h->prep>>>(F, r, J0, J1 - J0, dinv + pl.dinv_off[s], ld, Xs,
-                                                         Xs + (int64_t)ld * ld);
+            sblock_inverse<T><<<dim3(nsub, 1, ncopy), 256, 0, h->prep>>>(F, r, J0, J1 - J0, dinv + pl.dinv_off[s],
+                                                                        ld, Xs, Xs + (int64_t)ld * ld, cs);
             if (J1 < r)
-                wblock<T><<<dim3((unsigned)((r - J1 + 63) / 64), (unsigned)nsub), 256, 0, h->prep>>>(
-                    F, r, J0, J1 - J0, Xs, ld, wb + pl.w_off[s] + w_block_offset(r, J0));
+                wblock<T><<<dim3((unsigned)((r - J1 + 63) / 64), (unsigned)nsub, ncopy), 256, 0, h->prep>>>(
+                    F, r, J0, J1 - J0, Xs, ld, wb + pl.w_off[s] + w_block_offset(r, J0), cs);
         }
         if (J1 < r) {
             const int32_t J2 = std::min(r, J1 + SB);
             // bulk: columns [J2, r), after this super-panel's panels
             if (J2 < r) {
                 QG_HIP(h, hipStreamWaitEvent(h->bulk, h->ev_panel, 0));
-                launch_update<T>(h, h->bulk, F, r, J0, J1 - J0, J2, r);
+                launch_update<T>(h, h->bulk, F, r, J0, J1 - J0, J2, r, cs, ncopy);
             }
             // next super-panel's columns [J1, J2): after the previous bulk update, which also wrote them
             if (bulk_pending) QG_HIP(h, hipStreamWaitEvent(ms, h->ev_bulk, 0));
-            launch_update<T>(h, ms, F, r, J0, J1 - J0, J1, J2);
+            launch_update<T>(h, ms, F, r, J0, J1 - J0, J1, J2, cs, ncopy);
             if (J2 < r) {
                 QG_HIP(h, hipEventRecord(h->ev_bulk, h->bulk));
                 bulk_pending = true;
@@ -803,10 +1049,19 @@ template <typename T>
 static int factor_all(qg_handle *h, T *front, T *dinv, T *sinv, T *wb, const RegParams &rp) {
     const Plan &pl = h->plan;
     Device &d = h->d;
+    const int32_t nchain = (int32_t)pl.chain_comp_ptr.size() - 1;
     for (int32_t L = 0; L < pl.nlevels; ++L) {
-        const int64_t z0 = pl.zseg_lvl_ptr[L], nz = pl.zseg_lvl_ptr[L + 1] - z0;
+        if (L == pl.chain_L0 && nchain > 0) {
+            // every level below the chains is factored: the components run now, beside the rest
+            factor_chain<T><<<(unsigned)nchain, 256, 0, h->stream>>>(
+                d.chain_comp_ptr.p, d.chain_grp_ptr.p, d.chain_sn.p, d.ent_front.p, d.ent_dst.p, d.ent_sptr.p,
+                d.ent_reg.p, d.ent_src.p, d.kval.p, rp.delta, d.sn_first.p, d.sn_rptr.p, d.fr_off.p, front,
+                d.reg_sign.p, rp.eps, rp.dyn, d.nreg.p);
+        }
+        // the level's other fronts (its chain fronts come last in its ranges)
+        const int64_t z0 = pl.zseg_lvl_ptr[L], nz = pl.zseg_lvl_mid[L] - z0;
         if (nz > 0) zero_segments<T><<<(unsigned)nz, 256, 0, h->stream>>>(d.zseg_off.p + z0, d.zseg_len.p + z0, front);
-        const int64_t e0 = pl.ent_lvl_ptr[L], ne = pl.ent_lvl_ptr[L + 1] - e0;
+        const int64_t e0 = pl.ent_lvl_ptr[L], ne = pl.ent_lvl_mid[L] - e0;
         if (ne > 0)
             gather_entries<T><<<(unsigned)((ne + 255) / 256), 256, 0, h->stream>>>(
                 e0, ne, d.ent_dst.p, d.ent_sptr.p, d.ent_reg.p, d.ent_src.p, d.kval.p, rp.delta, front);
@@ -817,8 +1072,11 @@ static int factor_all(qg_handle *h, T *front, T *dinv, T *sinv, T *wb, const Reg
                                                                d.sn_rptr.p, d.fr_off.p, front,
                                                                d.reg_sign.p, rp.eps, rp.dyn, d.nreg.p);
         }
+        // large fronts; in a batch, the copies of a front run in one launch sequence
         for (int32_t u = pl.lvl_large_ptr[L]; u < pl.lvl_large_ptr[L + 1]; ++u) {
-            const int rc = factor_large<T>(h, pl.lvl_large_sn[u], front, dinv, sinv, wb, rp);
+            const int32_t s = pl.lvl_large_sn[u];
+            if (s >= pl.ns1) continue;
+            const int rc = factor_large<T>(h, s, front, dinv, sinv, wb, rp, pl.copy_stride[s], pl.ncopy);
             if (rc) return rc;
         }
     }

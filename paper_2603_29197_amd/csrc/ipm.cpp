@@ -121,11 +121,34 @@ int ipm_solve(qg_handle *h, double *xo, double *so, double *yo, double *zo, qg_i
     ev.create();
     int rc = QG_OK;
     int ir_total = 0, nreg_total = 0, nfactor = 0, nsolve = 0, switch_iter = -1;
+    if (st.precision == QG_FP32_IR && h->plan.large_flops < st.fp32_min_flops) switch_iter = 0;
     double ms_factor = 0, ms_solve = 0, ms_cone = 0;
     SolveWork work;
     std::vector<double> step_ms, step32, step64;
-    bool fp64_only = st.precision != QG_FP32_IR;
+    std::vector<int32_t> step_is32;
+    // FP32 factors only where the matrix-core work of the factorization is large enough to pay for
+    // the extra refinement corrections (settings.fp32_min_flops)
+    bool fp64_only = st.precision != QG_FP32_IR || h->plan.large_flops < st.fp32_min_flops;
+    // residual scalars of each problem of a batch (one problem: kb = 1) and of the whole stack
+    const int32_t kb = h->ncopy;
+    std::vector<double> scal_all((size_t)kb * NSCAL), mu_host((size_t)kb);
     double scal[NSCAL];
+    auto combine = [&]() {
+        for (int q = 0; q < NSCAL; ++q) {
+            double v = scal_all[(size_t)q];
+            for (int32_t i = 1; i < kb; ++i) {
+                const double w = scal_all[(size_t)i * NSCAL + q];
+                v = ((SCAL_MAXMASK >> q) & 1u) ? nan_max(v, w) : v + w;
+            }
+            scal[q] = v;
+        }
+    };
+    // every problem of the batch meets the test (its own residuals, scales and gap)
+    auto all_pass = [&](double ea, double er) {
+        for (int32_t i = 0; i < kb; ++i)
+            if (!stop_test(h, scal_all.data() + (size_t)i * NSCAL, ea, er).ok) return false;
+        return true;
+    };
     Scalars sr{};
     int status = QG_MAX_ITER, it = 0;
     h->solved = false;
@@ -160,7 +183,7 @@ int ipm_solve(qg_handle *h, double *xo, double *so, double *yo, double *zo, qg_i
         QG_HIP(h, hipMemcpyAsync(d.z.p, d.sol.p + n + p, sizeof(double) * m, hipMemcpyDeviceToDevice, h->stream));
         // s = h - G x: residual with s = 0 gives rz = Gx - h
         if ((rc = launch_fill(h, m, 0.0, d.s.p))) return fail(rc);
-        if ((rc = launch_residual(h, d.x.p, d.y.p, d.z.p, d.s.p, scal))) return fail(rc);
+        if ((rc = launch_residual(h, d.x.p, d.y.p, d.z.p, d.s.p, scal_all.data()))) return fail(rc);
         if ((rc = launch_scale_copy(h, m, -1.0, d.rz.p, d.s.p))) return fail(rc);
         if ((rc = launch_shift_interior(h, d.s.p))) return fail(rc);
         if ((rc = launch_shift_interior(h, d.z.p))) return fail(rc);
@@ -169,8 +192,10 @@ int ipm_solve(qg_handle *h, double *xo, double *so, double *yo, double *zo, qg_i
     const double *dz_of = dvec + n + p;
     while (true) {
         (void)hipEventRecord(ev.e[0], h->stream);
-        if ((rc = launch_residual(h, d.x.p, d.y.p, d.z.p, d.s.p, scal))) return fail(rc);
+        if ((rc = launch_residual(h, d.x.p, d.y.p, d.z.p, d.s.p, scal_all.data()))) return fail(rc);
+        combine();
         sr = stop_test(h, scal, st.eps_abs, st.eps_rel);
+        if (kb > 1) sr.ok = all_pass(st.eps_abs, st.eps_rel);
         if (st.verbose)
             fprintf(stderr, "it %3d pobj %+.8e dobj %+.8e pres %.2e dres %.2e gap %.2e %s\n", it, sr.pobj,
                     sr.dobj, sr.pres, sr.dres, sr.gap, prec == QG_FP32_IR ? "fp32" : "fp64");
@@ -180,11 +205,15 @@ int ipm_solve(qg_handle *h, double *xo, double *so, double *yo, double *zo, qg_i
         }
         if (sr.ok) { status = QG_SOLVED; break; }
         if (it >= st.max_iter) {
-            Scalars s5 = stop_test(h, scal, st.eps_inacc, st.eps_inacc);
-            status = s5.ok ? QG_SOLVED_INACCURATE : QG_MAX_ITER;
+            const bool ok5 = kb > 1 ? all_pass(st.eps_inacc, st.eps_inacc)
+                                    : stop_test(h, scal, st.eps_inacc, st.eps_inacc).ok;
+            status = ok5 ? QG_SOLVED_INACCURATE : QG_MAX_ITER;
             break;
         }
         const double mu = nu > 0 ? sr.sz / nu : 0.0;
+        // each problem's own complementarity measure for its centering (a batch: nu / kb cone units each)
+        for (int32_t i = 0; i < kb; ++i) mu_host[(size_t)i] = nu > 0 ? scal_all[(size_t)i * NSCAL + S_SZ] / (nu / kb) : 0.0;
+        QG_HIP(h, hipMemcpyAsync(d.mu.p, mu_host.data(), sizeof(double) * kb, hipMemcpyHostToDevice, h->stream));
         const double gscaled = sr.gap / std::max(1.0, std::min(std::fabs(sr.pobj), std::fabs(sr.dobj)));
         if (!fp64_only && gscaled < st.switch_gap) fp64_only = true;
         prec = fp64_only ? QG_FP64 : QG_FP32_IR;
@@ -218,7 +247,7 @@ int ipm_solve(qg_handle *h, double *xo, double *so, double *yo, double *zo, qg_i
                 if ((rc = launch_step_min(h, d.s.p, d.dsa.p, 0))) return fail(rc);
                 if ((rc = launch_step_min(h, d.z.p, dz_of, 1))) return fail(rc);
                 // corrector (sigma from the affine step length on the device)
-                if ((rc = launch_corrector(h, d.dsa.p, dz_of, -1.0, nullptr, mu, d.t.p))) return fail(rc);
+                if ((rc = launch_corrector(h, d.dsa.p, dz_of, -1.0, d.mu.p, d.t.p))) return fail(rc);
                 if ((rc = launch_build_rhs(h, d.t.p, -1.0, d.rhs.p))) return fail(rc);
                 (void)hipEventRecord(ev.e[7], h->stream);
                 if ((rc = solve_with(h, d.rhs.p, dvec, prec, &ir_total, &failed2, ev, &ms_solve, work))) return fail(rc);
@@ -243,6 +272,7 @@ int ipm_solve(qg_handle *h, double *xo, double *so, double *yo, double *zo, qg_i
         ms_cone += elapsed(ev.e[6], ev.e[1]);
         const double sm = elapsed(ev.e[0], ev.e[1]);
         step_ms.push_back(sm);
+        step_is32.push_back(prec == QG_FP32_IR ? 1 : 0);
         (prec == QG_FP32_IR ? step32 : step64).push_back(sm);
         ++it;
     }
@@ -285,11 +315,16 @@ int ipm_solve(qg_handle *h, double *xo, double *so, double *yo, double *zo, qg_i
         info->ntrisolve[0] = work.tri[0];
         info->ntrisolve[1] = work.tri[1];
         info->nresidual = work.residuals;
+        info->nstep_ms = (int32_t)std::min<size_t>(step_ms.size(), QG_STEP_MS_MAX);
+        for (int32_t k = 0; k < info->nstep_ms; ++k) {
+            info->step_ms[k] = step_ms[(size_t)k];
+            info->step_fp32[k] = step_is32[(size_t)k];
+        }
         info->nnz_L = h->sym.nnz_L;
         info->factor_flops = h->sym.flops;
         prof_collect(h, info->kern_launches, info->kern_ms, info->kern_flops);
     } else {
-        int64_t a[2]; double b_[2], c_[2];
+        int64_t a[4]; double b_[4], c_[4];
         prof_collect(h, a, b_, c_);
     }
     return QG_OK;

@@ -15,6 +15,11 @@ namespace qg {
 constexpr int SMALL_R = 128;
 constexpr int NB = 64;
 constexpr int SB = 256;
+// Chains of small fronts on the narrow upper levels of deep elimination trees
+// (one workgroup per component): levels with fewer than CHAIN_LEVEL_MIN
+// fronts, fronts of at most CHAIN_R rows.
+constexpr int CHAIN_LEVEL_MIN = 1024;
+constexpr int CHAIN_R = 32;
 // Lanes per matrix row in the sparse matrix-vector products (16 rows per
 // 256-thread block).
 constexpr int RL = 16;
@@ -51,6 +56,28 @@ __device__ inline T ld_or0(const T *__restrict__ p, int64_t i, bool ok) {
 __host__ __device__ inline int64_t w_block_offset(int64_t r, int64_t J0) {
     const int64_t n = J0 / SB;
     return SB * (n * r - SB * n * (n + 1) / 2);
+}
+
+// Identical copies of a large front in a batch of problems on one pattern
+// (qg_setup_batch) are factored and solved by one launch, copy z on
+// blockIdx.z: the element distances between consecutive copies in each
+// buffer (all zero for a single problem).
+struct CopyStride {
+    int64_t f = 0;       // front storage
+    int64_t dinv = 0;    // inverses of the NB x NB diagonal blocks
+    int64_t sinv = 0;    // inverses of the SB x SB diagonal blocks
+    int64_t w = 0;       // W_J blocks
+    int64_t task = 0;    // solve work vector (task slots)
+    int32_t col = 0;     // permuted columns
+    int32_t front = 0;   // front index
+};
+
+// Problem of cone unit t in a batch of kb problems (units: the l = kb l1 orthant
+// entries, then the kb nsoc1 second-order cones, problem by problem in each
+// part); units past the end count for the last problem.  kb = 1: always 0.
+__host__ __device__ inline int32_t cone_problem(int32_t t, int32_t l, int32_t l1, int32_t nsoc1, int32_t kb) {
+    const int32_t i = t < l ? t / l1 : (nsoc1 > 0 ? (t - l) / nsoc1 : 0);
+    return i < kb ? i : kb - 1;
 }
 
 struct RegParams {

@@ -87,14 +87,15 @@ void dfree_all(qg_handle *h) {
     dfree_(h, d.lvl_small_sn); dfree_(h, d.sn_rptr); dfree_(h, d.fr_off); dfree_(h, d.task_ptr);
     dfree_(h, d.ctb_ptr); dfree_(h, d.uv_off); dfree_(h, d.reg_sign);
     dfree_(h, d.ent_dst); dfree_(h, d.ent_sptr); dfree_(h, d.ent_src); dfree_(h, d.ent_reg); dfree_(h, d.zseg_off);
-    dfree_(h, d.zseg_len);
+    dfree_(h, d.zseg_len); dfree_(h, d.chain_comp_ptr); dfree_(h, d.chain_grp_ptr); dfree_(h, d.chain_sn);
+    dfree_(h, d.ent_front);
     dfree_(h, d.front64); dfree_(h, d.uvec); dfree_(h, d.dinv64);
     dfree_(h, d.sinv64); dfree_(h, d.w64); dfree_(h, d.ubuf);
     dfree_(h, d.vbuf); dfree_(h, d.col2sn); dfree_(h, d.nreg); dfree_(h, d.vwork); dfree_(h, d.task0);
     dfree_(h, d.x); dfree_(h, d.y); dfree_(h, d.s); dfree_(h, d.z); dfree_(h, d.rx); dfree_(h, d.ry); dfree_(h, d.rz);
     dfree_(h, d.kx); dfree_(h, d.rhs); dfree_(h, d.sol); dfree_(h, d.res); dfree_(h, d.corr); dfree_(h, d.xp);
     dfree_(h, d.dsa); dfree_(h, d.ds); dfree_(h, d.t); dfree_(h, d.lam); dfree_(h, d.w); dfree_(h, d.wbar); dfree_(h, d.beta);
-    dfree_(h, d.scal); dfree_(h, d.amin); dfree_(h, d.partials); dfree_(h, d.zcone); dfree_(h, d.alpha); dfree_(h, d.flag);
+    dfree_(h, d.scal); dfree_(h, d.scal_inst); dfree_(h, d.amin); dfree_(h, d.mu); dfree_(h, d.partials); dfree_(h, d.zcone); dfree_(h, d.alpha); dfree_(h, d.flag);
 }
 
 // Fronts of the device factorization.  The analysis' supernodes are kept,
@@ -188,6 +189,108 @@ int group_fronts(const Symbolic &sym, Symbolic &g) {
     return QG_OK;
 }
 
+// Chains: the narrow upper levels of deep elimination trees.  From the first
+// level L0 with fewer than CHAIN_LEVEL_MIN fronts on, each tree's fronts at
+// levels >= L0 form one component; when all of them have at most CHAIN_R
+// rows, the component is factored and solved by one workgroup that walks its
+// levels with workgroup barriers, instead of one launch per level (the
+// levels below L0, wide enough to fill the device, keep the level launches).
+// A component depends only on fronts below L0 (its own tree), and nothing
+// else depends on it except those fronts, in the backward solve.  Each level
+// lists its chain fronts after the others, so that the level kernels' entry
+// and segment ranges can stop before them.
+static void select_chains(Plan &pl, const Symbolic &sym, bool enabled) {
+    const int32_t ns = pl.ns;
+    pl.in_chain.assign((size_t)ns, 0);
+    pl.chain_comp_ptr.assign(1, 0);
+    pl.chain_grp_ptr.assign(1, 0);
+    pl.chain_sn.clear();
+    pl.chain_maxr = 0;
+    pl.chain_L0 = pl.nlevels;
+    if (!enabled) return;
+    for (int32_t L = 0; L < pl.nlevels; ++L)
+        if (pl.lvl_ptr[L + 1] - pl.lvl_ptr[L] < CHAIN_LEVEL_MIN) { pl.chain_L0 = L; break; }
+    if (pl.chain_L0 >= pl.nlevels) return;
+    // root of each front's tree; component eligibility per root
+    std::vector<int32_t> root((size_t)ns);
+    for (int32_t f = ns - 1; f >= 0; --f) {       // parents have larger indices
+        const int32_t P = sym.sn_parent[f];
+        root[f] = P < 0 ? f : root[P];
+    }
+    std::vector<int8_t> ok((size_t)ns, 1);
+    std::vector<int32_t> members((size_t)ns, 0);
+    for (int32_t f = 0; f < ns; ++f) {
+        if (sym.sn_level[f] < pl.chain_L0) continue;
+        const int64_t r = pl.sn_rptr[f + 1] - pl.sn_rptr[f];
+        if (r > CHAIN_R) ok[root[f]] = 0;
+        members[root[f]]++;
+    }
+    // components in root order; inside, fronts by level then index
+    std::vector<std::vector<int32_t>> comp_of((size_t)ns);
+    for (int32_t t = pl.lvl_ptr[pl.chain_L0]; t < pl.lvl_ptr[pl.nlevels]; ++t) {
+        const int32_t f = pl.lvl_sn[t];
+        if (ok[root[f]] && members[root[f]] > 0) comp_of[root[f]].push_back(f);
+    }
+    for (int32_t R = 0; R < ns; ++R) {
+        if (comp_of[R].empty()) continue;
+        int32_t prev = -1;
+        for (int32_t f : comp_of[R]) {
+            if (sym.sn_level[f] != prev && prev >= 0) pl.chain_grp_ptr.push_back((int32_t)pl.chain_sn.size());
+            prev = sym.sn_level[f];
+            pl.chain_sn.push_back(f);
+            pl.in_chain[f] = 1;
+            pl.chain_maxr = std::max<int32_t>(pl.chain_maxr, (int32_t)(pl.sn_rptr[f + 1] - pl.sn_rptr[f]));
+        }
+        pl.chain_grp_ptr.push_back((int32_t)pl.chain_sn.size());
+        pl.chain_comp_ptr.push_back((int32_t)pl.chain_grp_ptr.size() - 1);
+    }
+    // each level: its other fronts first, then its chain fronts
+    for (int32_t L = pl.chain_L0; L < pl.nlevels; ++L)
+        std::stable_partition(pl.lvl_sn.begin() + pl.lvl_ptr[L], pl.lvl_sn.begin() + pl.lvl_ptr[L + 1],
+                              [&](int32_t f) { return !pl.in_chain[f]; });
+}
+
+// The chain partition as the kernels rely on it: every front is handled once
+// (level lists or a chain); a chain front's children are earlier fronts of its
+// own component or fronts below the chain levels; no other front has a chain
+// child; the level kernels' entry ranges stop before the chain fronts' entries.
+static bool check_chains(const Plan &pl, const Symbolic &sym) {
+    const int32_t ns = pl.ns;
+    std::vector<int32_t> seen((size_t)ns, 0), comp((size_t)ns, -1), grp((size_t)ns, -1);
+    for (int32_t s : pl.lvl_small_sn) seen[s]++;
+    for (int32_t s : pl.lvl_large_sn) seen[s]++;
+    const int32_t nc = (int32_t)pl.chain_comp_ptr.size() - 1;
+    for (int32_t c = 0; c < nc; ++c)
+        for (int32_t g = pl.chain_comp_ptr[c]; g < pl.chain_comp_ptr[c + 1]; ++g)
+            for (int32_t t = pl.chain_grp_ptr[g]; t < pl.chain_grp_ptr[g + 1]; ++t) {
+                const int32_t s = pl.chain_sn[t];
+                seen[s]++;
+                comp[s] = c;
+                grp[s] = g;
+                if (!pl.in_chain[s] || pl.sn_rptr[s + 1] - pl.sn_rptr[s] > CHAIN_R) return false;
+            }
+    for (int32_t s = 0; s < ns; ++s) {
+        if (seen[s] != 1) return false;
+        const int32_t L = sym.sn_level[s];
+        for (int32_t u = pl.ch_ptr[s]; u < pl.ch_ptr[s + 1]; ++u) {
+            const int32_t c = pl.ch_list[u];
+            if (pl.in_chain[s]) {
+                if (pl.in_chain[c] ? (comp[c] != comp[s] || grp[c] >= grp[s]) : sym.sn_level[c] >= pl.chain_L0)
+                    return false;
+            } else if (pl.in_chain[c]) {
+                return false;
+            }
+        }
+        if (pl.in_chain[s]) {
+            if (pl.ent_front[2 * (size_t)s] < pl.ent_lvl_mid[L] || pl.ent_front[2 * (size_t)s + 1] > pl.ent_lvl_ptr[L + 1])
+                return false;
+        } else if (pl.ent_front[2 * (size_t)s + 1] > pl.ent_lvl_mid[L]) {
+            return false;
+        }
+    }
+    return true;
+}
+
 // Assembly map of the numeric factorization (the extend-add of the paper's
 // multifrontal factorization, Sec. 2.2): per level, the front entries that
 // receive a value, each with its sources in the order the sum is formed -- the
@@ -200,6 +303,9 @@ static bool build_assembly_map(Plan &pl, const std::vector<int64_t> &task_base, 
     constexpr int64_t ZCHUNK = 8192;
     pl.ent_lvl_ptr.assign((size_t)pl.nlevels + 1, 0);
     pl.zseg_lvl_ptr.assign((size_t)pl.nlevels + 1, 0);
+    pl.ent_lvl_mid.assign((size_t)pl.nlevels, 0);
+    pl.zseg_lvl_mid.assign((size_t)pl.nlevels, 0);
+    pl.ent_front.assign(2 * (size_t)pl.ns, 0);
     pl.ent_dst.clear(); pl.ent_reg.clear(); pl.ent_src.clear(); pl.zseg_off.clear(); pl.zseg_len.clear();
     pl.ent_sptr.assign(1, 0);
     std::vector<int32_t> cnt((size_t)pl.max_r + 1, 0);
@@ -213,13 +319,23 @@ static bool build_assembly_map(Plan &pl, const std::vector<int64_t> &task_base, 
         }
     };
     for (int32_t L = 0; L < pl.nlevels; ++L) {
+        pl.ent_lvl_mid[L] = -1;
         for (int32_t t = pl.lvl_ptr[L]; t < pl.lvl_ptr[L + 1]; ++t) {
             const int32_t s = pl.lvl_sn[t];
             const int64_t r = pl.sn_rptr[s + 1] - pl.sn_rptr[s];
             const int32_t k = pl.sn_first[s + 1] - pl.sn_first[s];
-            if (r <= SMALL_R) zseg(pl.fr_off[s], r * r);
-            else
+            if (pl.in_chain[s] && pl.ent_lvl_mid[L] < 0) {   // the level's chain fronts start here
+                pl.ent_lvl_mid[L] = (int64_t)pl.ent_dst.size();
+                pl.zseg_lvl_mid[L] = (int64_t)pl.zseg_off.size();
+            }
+            pl.ent_front[2 * (size_t)s] = (int64_t)pl.ent_dst.size();
+            if (pl.in_chain[s]) {
+                // assembled in LDS: no segments to clear
+            } else if (r <= SMALL_R) {
+                zseg(pl.fr_off[s], r * r);
+            } else {
                 for (int64_t j = 0; j < r; ++j) zseg(pl.fr_off[s] + j * r + j, r - j);
+            }
             for (int32_t j = 0; j < (int32_t)r; ++j) {
                 const int64_t task = task_base[s] + j;
                 touched.clear();
@@ -256,9 +372,14 @@ static bool build_assembly_map(Plan &pl, const std::vector<int64_t> &task_base, 
                 }
                 for (int32_t row : touched) { live[row] = 0; cnt[row] = 0; }
             }
+            pl.ent_front[2 * (size_t)s + 1] = (int64_t)pl.ent_dst.size();
         }
         pl.ent_lvl_ptr[L + 1] = (int64_t)pl.ent_dst.size();
         pl.zseg_lvl_ptr[L + 1] = (int64_t)pl.zseg_off.size();
+        if (pl.ent_lvl_mid[L] < 0) {
+            pl.ent_lvl_mid[L] = pl.ent_lvl_ptr[L + 1];
+            pl.zseg_lvl_mid[L] = pl.zseg_lvl_ptr[L + 1];
+        }
     }
     // every index the device will follow stays inside the front buffer / the K values
     for (int64_t d : pl.ent_dst) if (d < 0 || d >= pl.front_total) return false;
@@ -269,8 +390,11 @@ static bool build_assembly_map(Plan &pl, const std::vector<int64_t> &task_base, 
 }
 
 int build_plan(qg_handle *h) {
-    int rc0 = group_fronts(h->sym, h->fronts);
-    if (rc0) return rc0;
+    // a batch arrives with its device fronts formed copy by copy (qg_setup_batch)
+    if (h->ncopy == 1) {
+        int rc0 = group_fronts(h->sym, h->fronts);
+        if (rc0) return rc0;
+    }
     const Symbolic &sym = h->fronts;
     const KktPattern &kp = h->kp;
     Plan &pl = h->plan;
@@ -336,20 +460,26 @@ int build_plan(qg_handle *h) {
         std::vector<int32_t> fill(pl.lvl_ptr.begin(), pl.lvl_ptr.end() - 1);
         for (int32_t s = 0; s < ns; ++s) pl.lvl_sn[fill[sym.sn_level[s]]++] = s;
     }
+    select_chains(pl, sym, h->st.chains != 0);
     pl.lvl_small_maxr.assign((size_t)pl.nlevels, 0);
     pl.lvl_small_ptr.assign((size_t)pl.nlevels + 1, 0);
     pl.lvl_large_ptr.assign((size_t)pl.nlevels + 1, 0);
     pl.lvl_small_sn.clear();
     pl.lvl_large_sn.clear();
+    pl.large_flops = 0.0;
     for (int32_t L = 0; L < pl.nlevels; ++L) {
         for (int32_t t = pl.lvl_ptr[L]; t < pl.lvl_ptr[L + 1]; ++t) {
             const int32_t s = pl.lvl_sn[t];
             const int64_t r = pl.sn_rptr[s + 1] - pl.sn_rptr[s];
+            if (pl.in_chain[s]) continue;          // factored and solved by the chain kernels
             if (r <= SMALL_R) {
                 pl.lvl_small_sn.push_back(s);
                 pl.lvl_small_maxr[L] = std::max<int32_t>(pl.lvl_small_maxr[L], (int32_t)r);
             } else {
                 pl.lvl_large_sn.push_back(s);
+                const double rr = (double)r, kk = (double)(pl.sn_first[s + 1] - pl.sn_first[s]);
+                // sum over the k pivots j of (r - j - 1)^2
+                pl.large_flops += kk * (rr - 1) * (rr - 1) - (rr - 1) * kk * (kk - 1) + (kk - 1) * kk * (2 * kk - 1) / 6;
             }
         }
         pl.lvl_small_ptr[L + 1] = (int32_t)pl.lvl_small_sn.size();
@@ -467,6 +597,34 @@ int build_plan(qg_handle *h) {
         pl.reg_sign[c] = (int8_t)(o < h->n ? 0 : (o < h->n + h->p ? 1 : 2));
     }
     if (!build_assembly_map(pl, task_base, nnzK)) return QG_ERR_PATTERN;
+    if (!check_chains(pl, sym)) return QG_ERR_PATTERN;
+    // copies of a batch: every offset of copy z is copy 0's plus z times a fixed distance per front
+    pl.ncopy = h->ncopy;
+    if (ns % pl.ncopy) return QG_ERR_PATTERN;
+    pl.ns1 = ns / pl.ncopy;
+    pl.copy_stride.assign((size_t)pl.ns1, CopyStride());
+    if (pl.ncopy > 1) {
+        for (int32_t s = 0; s < pl.ns1; ++s) {
+            CopyStride &c = pl.copy_stride[s];
+            const int32_t t = s + pl.ns1;
+            c.f = pl.fr_off[t] - pl.fr_off[s];
+            c.dinv = pl.dinv_off[t] - pl.dinv_off[s];
+            c.sinv = pl.sinv_off[t] - pl.sinv_off[s];
+            c.w = pl.w_off[t] - pl.w_off[s];
+            c.task = pl.task0[t] - pl.task0[s];
+            c.col = pl.sn_first[t] - pl.sn_first[s];
+            c.front = pl.ns1;
+            for (int32_t z = 1; z < pl.ncopy; ++z) {
+                const int32_t u = s + z * pl.ns1;
+                if (pl.fr_off[u] != pl.fr_off[s] + z * c.f || pl.dinv_off[u] != pl.dinv_off[s] + z * c.dinv ||
+                    pl.sinv_off[u] != pl.sinv_off[s] + z * c.sinv || pl.w_off[u] != pl.w_off[s] + z * c.w ||
+                    pl.task0[u] != pl.task0[s] + z * c.task || pl.sn_first[u] != pl.sn_first[s] + z * c.col ||
+                    pl.sn_rptr[u + 1] - pl.sn_rptr[u] != pl.sn_rptr[s + 1] - pl.sn_rptr[s] ||
+                    pl.sn_first[u + 1] - pl.sn_first[u] != pl.sn_first[s + 1] - pl.sn_first[s])
+                    return QG_ERR_PATTERN;
+            }
+        }
+    }
     return QG_OK;
 }
 

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "analysis.hpp"
+#include "kernels.hpp"
 #include "qg.h"
 
 namespace qg {
@@ -76,6 +77,22 @@ struct Plan {
     std::vector<int8_t> reg_sign;         // per permuted column: +1 x, -1 y, 0 z
     int64_t front_total = 0, uv_total = 0;
     int32_t max_r = 0;
+    double large_flops = 0.0;             // dense flops of the large fronts per factorization
+    // batch of ncopy identical problems (qg_setup_batch): fronts [z ns1, (z + 1) ns1) are copy z of
+    // fronts [0, ns1); a large front's copies are factored and solved together with the distances
+    // copy_stride[s] (s < ns1).  A single problem has ncopy = 1, ns1 = ns.
+    int32_t ncopy = 1, ns1 = 0;
+    std::vector<CopyStride> copy_stride;
+    // chains (see select_chains in plan.cpp): components of small fronts on the narrow upper levels
+    // of deep trees, one workgroup each; levels >= chain_L0 list their chain fronts last, and the
+    // level kernels stop at ent_lvl_mid / zseg_lvl_mid
+    int32_t chain_L0 = 0, chain_maxr = 0;
+    std::vector<int8_t> in_chain;
+    std::vector<int32_t> chain_comp_ptr;  // components -> groups
+    std::vector<int32_t> chain_grp_ptr;   // groups (one level of a component) -> fronts
+    std::vector<int32_t> chain_sn;
+    std::vector<int64_t> ent_lvl_mid, zseg_lvl_mid;
+    std::vector<int64_t> ent_front;       // 2 per front: its range of assembly entries
 };
 
 struct Device {
@@ -103,6 +120,8 @@ struct Device {
     DBuf<int64_t> ent_dst, ent_sptr, ent_src, zseg_off;   // numeric assembly map (see Plan)
     DBuf<int8_t> ent_reg;
     DBuf<int32_t> zseg_len;
+    DBuf<int32_t> chain_comp_ptr, chain_grp_ptr, chain_sn;   // chains (Plan)
+    DBuf<int64_t> ent_front;
     DBuf<double> front64;
     DBuf<float> front32;
     DBuf<double> uvec;          // update vectors of the triangular solves
@@ -126,10 +145,12 @@ struct Device {
     DBuf<double> dsa, ds, t, lam, w;        // m
     DBuf<double> wbar, beta;                // SOC scaling
     DBuf<double> scal;          // reduction scalars
+    DBuf<double> scal_inst;     // residual scalars of each problem of a batch (NSCAL each)
     DBuf<double> partials;      // per-block reduction partials
     DBuf<int32_t> zcone;        // per z row: SOC index (-1 on the orthant)
     DBuf<double> alpha;         // step lengths of the last iteration (affine, combined)
-    DBuf<unsigned long long> amin;          // step-length minima (ordered bits)
+    DBuf<unsigned long long> amin;          // step-length minima (ordered bits), 4 per problem of a batch
+    DBuf<double> mu;            // complementarity measure of each problem of a batch
     DBuf<int32_t> flag;         // count of non-finite entries (qg_update_vectors)
 };
 
@@ -165,6 +186,8 @@ struct qg_handle {
     std::vector<double> hc, hb, hh;    // c, b, h on the host
     int64_t nnzK = 0;
     int32_t n = 0, m = 0, p = 0, N = 0;
+    int32_t ncopy = 1;                 // problems in the batch (qg_setup_batch), 1 for qg_setup
+    int32_t n1 = 0, m1 = 0, p1 = 0, l1 = 0;   // sizes of one problem of the batch
     int32_t nbig = 0;                  // SOCs handled one wavefront per cone
     int64_t nbigchunk = 0;             // workgroups of the big cones' block writes
     bool solved = false;               // a solve finished (x, s, y, z valid)
@@ -174,7 +197,7 @@ struct qg_handle {
     double ms_setup = 0, ms_analyze = 0;
     int64_t small_lds_bytes = 0;
     std::vector<std::pair<std::pair<hipEvent_t, hipEvent_t>, int>> prof_events;   // settings.profile
-    double prof_flops[2] = {0.0, 0.0};
+    double prof_flops[4] = {0.0, 0.0, 0.0, 0.0};
 };
 
 namespace qg {
@@ -209,7 +232,7 @@ int launch_kkt_residual(qg_handle *h, const double *rhs, const double *x, double
 int launch_max_step(qg_handle *h, const double *u, const double *du, int slot);
 int launch_cone_op(qg_handle *h, int op, const double *u, const double *v, double *out);
 int launch_corrector(qg_handle *h, const double *dsa, const double *dza, double sigma_mu,
-                     const double *alpha_aff_dev, double mu, double *t);
+                     const double *mu_dev, double *t);
 int read_nreg(qg_handle *h, int *nreg);
 int factor_init_attributes(qg_handle *h);
 void prof_collect(qg_handle *h, int64_t *launches, double *ms, double *flops);

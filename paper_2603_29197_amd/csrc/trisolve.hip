@@ -31,7 +31,9 @@ namespace qg {
 __global__ void __launch_bounds__(256) fwd_gather_level(
     int64_t t0, int64_t nt, const int32_t *__restrict__ task_sn, const int32_t *__restrict__ task_col,
     const int32_t *__restrict__ sn_first, const int64_t *__restrict__ ctb_ptr,
-    const int64_t *__restrict__ ctb_src, const double *__restrict__ xp, double *__restrict__ vwork) {
+    const int64_t *__restrict__ ctb_src, const double *__restrict__ xp, double *__restrict__ vwork,
+    int64_t tstride) {
+    t0 += blockIdx.z * tstride;                      // copy z of a batched front: its own task slots
     const int sub = threadIdx.x & (RL - 1);
     const int64_t t = t0 + (int64_t)blockIdx.x * (256 / RL) + (threadIdx.x / RL);
     const bool live = t < t0 + nt;
@@ -68,17 +70,12 @@ constexpr int SW = 4;                       // fronts (wavefronts) per workgroup
 // elimination steps with L columns read from the front, and the update vector
 // is left in the front's own slots for the parent.
 template <typename T>
-__global__ void __launch_bounds__(64 * SW) fwd_small(
-    int32_t nfront, const int32_t *__restrict__ sn_list, const int32_t *__restrict__ sn_first,
-    const int64_t *__restrict__ sn_rptr, const int64_t *__restrict__ fr_off, const T *__restrict__ front,
-    const int64_t *__restrict__ task0, const int64_t *__restrict__ ctb_ptr, const int64_t *__restrict__ ctb_src,
-    double *__restrict__ vwork, double *__restrict__ xp) {
-    __shared__ double vsh[SW][SMALL_R];
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int32_t q = blockIdx.x * SW + w;
-    if (q >= nfront) return;                   // whole wavefront
-    double *v = vsh[w];
-    const int32_t s = sn_list[q];
+__device__ inline void fwd_front(int32_t s, const int32_t *__restrict__ sn_first,
+                                 const int64_t *__restrict__ sn_rptr, const int64_t *__restrict__ fr_off,
+                                 const T *__restrict__ front, const int64_t *__restrict__ task0,
+                                 const int64_t *__restrict__ ctb_ptr, const int64_t *__restrict__ ctb_src,
+                                 double *__restrict__ vwork, double *__restrict__ xp, double *v) {
+    const int lane = threadIdx.x & 63;
     const int32_t f = sn_first[s];
     const int32_t r = (int32_t)(sn_rptr[s + 1] - sn_rptr[s]);
     const int32_t k = sn_first[s + 1] - f;
@@ -112,22 +109,31 @@ __global__ void __launch_bounds__(64 * SW) fwd_small(
         if (row < k) xp[f + row] = v[row];
         else if (row < r) vs[row] = v[row];
     }
+    __builtin_amdgcn_wave_barrier();
+}
+
+template <typename T>
+__global__ void __launch_bounds__(64 * SW) fwd_small(
+    int32_t nfront, const int32_t *__restrict__ sn_list, const int32_t *__restrict__ sn_first,
+    const int64_t *__restrict__ sn_rptr, const int64_t *__restrict__ fr_off, const T *__restrict__ front,
+    const int64_t *__restrict__ task0, const int64_t *__restrict__ ctb_ptr, const int64_t *__restrict__ ctb_src,
+    double *__restrict__ vwork, double *__restrict__ xp) {
+    __shared__ double vsh[SW][SMALL_R];
+    const int w = threadIdx.x >> 6;
+    const int32_t q = blockIdx.x * SW + w;
+    if (q >= nfront) return;                   // whole wavefront
+    fwd_front<T>(sn_list[q], sn_first, sn_rptr, fr_off, front, task0, ctb_ptr, ctb_src, vwork, xp, vsh[w]);
 }
 
 // Backward: v = D^-1 x_own - L21' g (g = solution at the update rows; the
 // products with L21' are summed per column over the wavefront with a
 // butterfly), then the unit-upper solve with L11'.
 template <typename T>
-__global__ void __launch_bounds__(64 * SW) bwd_small(
-    int32_t nfront, const int32_t *__restrict__ sn_list, const int32_t *__restrict__ sn_first,
-    const int64_t *__restrict__ sn_rptr, const int32_t *__restrict__ sn_rows,
-    const int64_t *__restrict__ fr_off, const T *__restrict__ front, double *__restrict__ xp) {
-    __shared__ double vsh[SW][SMALL_R];
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int32_t q = blockIdx.x * SW + w;
-    if (q >= nfront) return;                   // whole wavefront
-    double *v = vsh[w];
-    const int32_t s = sn_list[q];
+__device__ inline void bwd_front(int32_t s, const int32_t *__restrict__ sn_first,
+                                 const int64_t *__restrict__ sn_rptr, const int32_t *__restrict__ sn_rows,
+                                 const int64_t *__restrict__ fr_off, const T *__restrict__ front,
+                                 double *__restrict__ xp, double *v) {
+    const int lane = threadIdx.x & 63;
     const int32_t f = sn_first[s];
     const int32_t r = (int32_t)(sn_rptr[s + 1] - sn_rptr[s]);
     const int32_t k = sn_first[s + 1] - f;
@@ -167,6 +173,53 @@ __global__ void __launch_bounds__(64 * SW) bwd_small(
         const int32_t row = lane + 64 * h;
         if (row < k) xp[f + row] = v[row];
     }
+    __builtin_amdgcn_wave_barrier();
+}
+
+template <typename T>
+__global__ void __launch_bounds__(64 * SW) bwd_small(
+    int32_t nfront, const int32_t *__restrict__ sn_list, const int32_t *__restrict__ sn_first,
+    const int64_t *__restrict__ sn_rptr, const int32_t *__restrict__ sn_rows,
+    const int64_t *__restrict__ fr_off, const T *__restrict__ front, double *__restrict__ xp) {
+    __shared__ double vsh[SW][SMALL_R];
+    const int w = threadIdx.x >> 6;
+    const int32_t q = blockIdx.x * SW + w;
+    if (q >= nfront) return;                   // whole wavefront
+    bwd_front<T>(sn_list[q], sn_first, sn_rptr, sn_rows, fr_off, front, xp, vsh[w]);
+}
+
+// Chains (see factor_chain): one workgroup per component, its levels in
+// order (forward: lowest first; backward: highest first), the fronts of a
+// level one per wavefront, a workgroup barrier between levels.
+template <typename T>
+__global__ void __launch_bounds__(64 * SW) fwd_chain(
+    const int32_t *__restrict__ comp_ptr, const int32_t *__restrict__ grp_ptr, const int32_t *__restrict__ chain_sn,
+    const int32_t *__restrict__ sn_first, const int64_t *__restrict__ sn_rptr, const int64_t *__restrict__ fr_off,
+    const T *__restrict__ front, const int64_t *__restrict__ task0, const int64_t *__restrict__ ctb_ptr,
+    const int64_t *__restrict__ ctb_src, double *__restrict__ vwork, double *__restrict__ xp) {
+    __shared__ double vsh[SW][SMALL_R];
+    const int w = threadIdx.x >> 6;
+    const int32_t c = blockIdx.x;
+    for (int32_t g = comp_ptr[c]; g < comp_ptr[c + 1]; ++g) {
+        for (int32_t t = grp_ptr[g] + w; t < grp_ptr[g + 1]; t += SW)
+            fwd_front<T>(chain_sn[t], sn_first, sn_rptr, fr_off, front, task0, ctb_ptr, ctb_src, vwork, xp, vsh[w]);
+        __syncthreads();
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(64 * SW) bwd_chain(
+    const int32_t *__restrict__ comp_ptr, const int32_t *__restrict__ grp_ptr, const int32_t *__restrict__ chain_sn,
+    const int32_t *__restrict__ sn_first, const int64_t *__restrict__ sn_rptr, const int32_t *__restrict__ sn_rows,
+    const int64_t *__restrict__ fr_off, const T *__restrict__ front, double *__restrict__ xp) {
+    __shared__ double vsh[SW][SMALL_R];
+    const int w = threadIdx.x >> 6;
+    const int32_t c = blockIdx.x;
+    for (int32_t g = comp_ptr[c + 1] - 1; g >= comp_ptr[c]; --g) {
+        for (int32_t t = grp_ptr[g] + w; t < grp_ptr[g + 1]; t += SW)
+            bwd_front<T>(chain_sn[t], sn_first, sn_rptr, sn_rows, fr_off, front, xp, vsh[w]);
+        __syncthreads();
+    }
 }
 
 // ------------------------------- large -------------------------------------
@@ -196,7 +249,12 @@ __device__ inline double quarter_gemv(const T *__restrict__ Mt, int64_t ldm, con
 template <typename T>
 __global__ void __launch_bounds__(256) fwd_block(const T *__restrict__ X, int32_t ld, int32_t kb,
                                                  const T *__restrict__ W, int32_t m, int32_t J0,
-                                                 double *__restrict__ vs, double *__restrict__ xp_own) {
+                                                 double *__restrict__ vs, double *__restrict__ xp_own,
+                                                 CopyStride cs) {
+    X += blockIdx.z * cs.sinv;
+    W += blockIdx.z * cs.w;
+    vs += blockIdx.z * cs.task;
+    xp_own += blockIdx.z * cs.col;
     __shared__ double vj[SB];
     __shared__ double red[4][64];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -220,7 +278,11 @@ __global__ void __launch_bounds__(256) fwd_block(const T *__restrict__ X, int32_
 // (grid (4, super-blocks); X_J' stored column-major, upper triangular).
 template <typename T>
 __global__ void __launch_bounds__(256) bwd_apply_all(const T *__restrict__ sinv_s, int32_t k,
-                                                     const double *__restrict__ v, double *__restrict__ u) {
+                                                     const double *__restrict__ v, double *__restrict__ u,
+                                                     CopyStride cs, int32_t max_r) {
+    sinv_s += blockIdx.z * cs.sinv;
+    v += (int64_t)blockIdx.z * max_r;
+    u += (int64_t)blockIdx.z * max_r;
     __shared__ double vj[SB];
     __shared__ double red[4][64];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -242,7 +304,10 @@ __global__ void __launch_bounds__(256) bwd_init(int32_t s, const int32_t *__rest
                                                 const int64_t *__restrict__ sn_rptr,
                                                 const int32_t *__restrict__ sn_rows,
                                                 const T *__restrict__ F, const double *__restrict__ xp,
-                                                double *__restrict__ vbuf) {
+                                                double *__restrict__ vbuf, CopyStride cs, int32_t max_r) {
+    s += blockIdx.z * cs.front;
+    F += blockIdx.z * cs.f;
+    vbuf += (int64_t)blockIdx.z * max_r;
     const int32_t f = sn_first[s];
     const int32_t r = (int32_t)(sn_rptr[s + 1] - sn_rptr[s]);
     const int32_t k = sn_first[s + 1] - f;
@@ -267,7 +332,11 @@ __global__ void __launch_bounds__(256) bwd_init(int32_t s, const int32_t *__rest
 // combine the four lanes of each column.  No workgroup barrier.
 template <typename T>
 __global__ void __launch_bounds__(256) bwd_push(const T *__restrict__ W_s, int32_t r, int32_t K0, int32_t kb,
-                                                double *__restrict__ u, double *__restrict__ xp_own) {
+                                                double *__restrict__ u, double *__restrict__ xp_own,
+                                                CopyStride cs, int32_t max_r) {
+    W_s += blockIdx.z * cs.w;
+    u += (int64_t)blockIdx.z * max_r;
+    xp_own += blockIdx.z * cs.col;
     __shared__ double red[4][16][65];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const bool pushes = blockIdx.x * NB < K0;        // uniform over the workgroup
@@ -322,7 +391,12 @@ static int solve_perm(qg_handle *h, const T *front, const T *sinv, const T *wbuf
     const Plan &pl = h->plan;
     Device &d = h->d;
     double *xp = d.xp.p;
+    const int32_t nchain = (int32_t)pl.chain_comp_ptr.size() - 1;
     for (int32_t L = 0; L < pl.nlevels; ++L) {
+        if (L == pl.chain_L0 && nchain > 0)
+            fwd_chain<T><<<(unsigned)nchain, 64 * SW, 0, h->stream>>>(
+                d.chain_comp_ptr.p, d.chain_grp_ptr.p, d.chain_sn.p, d.sn_first.p, d.sn_rptr.p, d.fr_off.p, front,
+                d.task0.p, d.ctb_ptr.p, d.ctb_src.p, d.vwork.p, xp);
         const int32_t s0 = pl.lvl_small_ptr[L], s1 = pl.lvl_small_ptr[L + 1];
         if (s1 > s0)
             fwd_small<T><<<(s1 - s0 + SW - 1) / SW, 64 * SW, 0, h->stream>>>(s1 - s0, d.lvl_small_sn.p + s0, d.sn_first.p, d.sn_rptr.p,
@@ -330,13 +404,16 @@ static int solve_perm(qg_handle *h, const T *front, const T *sinv, const T *wbuf
                                                                d.ctb_src.p, d.vwork.p, xp);
         for (int32_t u = pl.lvl_large_ptr[L]; u < pl.lvl_large_ptr[L + 1]; ++u) {
             const int32_t s = pl.lvl_large_sn[u];
+            if (s >= pl.ns1) continue;                 // copies of a batch run with copy 0 (blockIdx.z)
+            const CopyStride &cs = pl.copy_stride[s];
+            const unsigned nc = (unsigned)pl.ncopy;
             const int32_t r = (int32_t)(pl.sn_rptr[s + 1] - pl.sn_rptr[s]);
             const int32_t k = pl.sn_first[s + 1] - pl.sn_first[s];
-            const T *F = front + pl.fr_off[s];
             double *vs = d.vwork.p + pl.task0[s];
             // gather of this front's rows (its tasks are contiguous)
-            fwd_gather_level<<<(unsigned)((r + 256 / RL - 1) / (256 / RL)), 256, 0, h->stream>>>(
-                pl.task0[s], r, d.task_sn.p, d.task_col.p, d.sn_first.p, d.ctb_ptr.p, d.ctb_src.p, xp, d.vwork.p);
+            fwd_gather_level<<<dim3((unsigned)((r + 256 / RL - 1) / (256 / RL)), 1, nc), 256, 0, h->stream>>>(
+                pl.task0[s], r, d.task_sn.p, d.task_col.p, d.sn_first.p, d.ctb_ptr.p, d.ctb_src.p, xp, d.vwork.p,
+                cs.task);
             for (int32_t J0 = 0; J0 < k; J0 += SB) {
                 const int32_t kb = std::min(SB, k - J0);
                 const int32_t ld = (kb + NB - 1) / NB * NB;
@@ -344,28 +421,37 @@ static int solve_perm(qg_handle *h, const T *front, const T *sinv, const T *wbuf
                 const T *Xsb = sinv + pl.sinv_off[s] + (int64_t)(J0 / SB) * 2 * SB * SB;
                 const T *Wj = wbuf + pl.w_off[s] + w_block_offset(r, J0);
                 const unsigned grid = (unsigned)((kb + 63) / 64 + (m + 63) / 64);
-                fwd_block<T><<<grid, 256, 0, h->stream>>>(Xsb, ld, kb, Wj, m, J0, vs, xp + pl.sn_first[s]);
+                fwd_block<T><<<dim3(grid, 1, nc), 256, 0, h->stream>>>(Xsb, ld, kb, Wj, m, J0, vs,
+                                                                      xp + pl.sn_first[s], cs);
             }
         }
     }
     for (int32_t L = pl.nlevels - 1; L >= 0; --L) {
         for (int32_t u = pl.lvl_large_ptr[L + 1] - 1; u >= pl.lvl_large_ptr[L]; --u) {
             const int32_t s = pl.lvl_large_sn[u];
+            if (s >= pl.ns1) continue;
+            const CopyStride &cs = pl.copy_stride[s];
+            const unsigned nc = (unsigned)pl.ncopy;
             const int32_t r = (int32_t)(pl.sn_rptr[s + 1] - pl.sn_rptr[s]);
             const int32_t k = pl.sn_first[s + 1] - pl.sn_first[s];
             const T *F = front + pl.fr_off[s];
-            bwd_init<T><<<(k + 3) / 4, 256, 0, h->stream>>>(s, d.sn_first.p, d.sn_rptr.p, d.sn_rows.p, F, xp,
-                                                            d.vbuf.p);
+            bwd_init<T><<<dim3((k + 3) / 4, 1, nc), 256, 0, h->stream>>>(s, d.sn_first.p, d.sn_rptr.p, d.sn_rows.p,
+                                                                         F, xp, d.vbuf.p, cs, pl.max_r);
             const int32_t nsb = (k + SB - 1) / SB;
-            bwd_apply_all<T><<<dim3(SB / 64, (unsigned)nsb), 256, 0, h->stream>>>(sinv + pl.sinv_off[s], k, d.vbuf.p,
-                                                                             d.ubuf.p);
+            bwd_apply_all<T><<<dim3(SB / 64, (unsigned)nsb, nc), 256, 0, h->stream>>>(sinv + pl.sinv_off[s], k,
+                                                                                 d.vbuf.p, d.ubuf.p, cs, pl.max_r);
             for (int32_t bi = nsb - 1; bi >= 0; --bi) {
                 const int32_t K0 = bi * SB;
                 const int32_t kb = std::min(SB, k - K0);
                 const unsigned grid = (unsigned)std::max(1, (K0 + NB - 1) / NB);
-                bwd_push<T><<<grid, 256, 0, h->stream>>>(wbuf + pl.w_off[s], r, K0, kb, d.ubuf.p, xp + pl.sn_first[s]);
+                bwd_push<T><<<dim3(grid, 1, nc), 256, 0, h->stream>>>(wbuf + pl.w_off[s], r, K0, kb, d.ubuf.p,
+                                                                     xp + pl.sn_first[s], cs, pl.max_r);
             }
         }
+        if (L == pl.chain_L0 && nchain > 0)
+            bwd_chain<T><<<(unsigned)nchain, 64 * SW, 0, h->stream>>>(
+                d.chain_comp_ptr.p, d.chain_grp_ptr.p, d.chain_sn.p, d.sn_first.p, d.sn_rptr.p, d.sn_rows.p,
+                d.fr_off.p, front, xp);
         const int32_t s0 = pl.lvl_small_ptr[L], s1 = pl.lvl_small_ptr[L + 1];
         if (s1 > s0)
             bwd_small<T><<<(s1 - s0 + SW - 1) / SW, 64 * SW, 0, h->stream>>>(s1 - s0, d.lvl_small_sn.p + s0, d.sn_first.p, d.sn_rptr.p,

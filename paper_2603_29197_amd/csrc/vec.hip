@@ -11,7 +11,8 @@ namespace qg {
 
 // Per-block reduction helper: NS slots, each either a sum or a max-abs.
 template <int NS>
-__device__ inline void block_reduce_store(double (&val)[NS], const uint32_t maxmask, double *partials) {
+__device__ inline void block_reduce_store(double (&val)[NS], const uint32_t maxmask, double *partials,
+                                          int64_t block) {
     __shared__ double sh[NS][4];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -30,14 +31,18 @@ __device__ inline void block_reduce_store(double (&val)[NS], const uint32_t maxm
         const bool ismax = (maxmask >> q) & 1u;
         double v = sh[q][0];
         for (int w = 1; w < 4; ++w) v = ismax ? nan_max(v, sh[q][w]) : v + sh[q][w];
-        partials[(int64_t)blockIdx.x * NS + q] = v;
+        partials[block * NS + q] = v;
     }
 }
 
 // Second pass: 256 threads, each folds a fixed strided subset of the block
-// partials, then a fixed tree over the threads (deterministic).
+// partials, then a fixed tree over the threads (deterministic).  Workgroup g
+// reduces the g-th run of nblk partials into out[g ns ..] (one run per
+// problem of a batch).
 __global__ void __launch_bounds__(256) finish_reduce(const double *__restrict__ partials, int32_t nblk,
                                                      int32_t ns, uint32_t maxmask, double *__restrict__ out) {
+    partials += (int64_t)blockIdx.x * nblk * ns;
+    out += (int64_t)blockIdx.x * ns;
     __shared__ double sh[4];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     for (int q = 0; q < ns; ++q) {
@@ -73,18 +78,33 @@ __global__ void __launch_bounds__(256) finish_reduce(const double *__restrict__ 
 
 // Residuals of problem (1): rx = Px + A'y + G'z + c, ry = Ax - b,
 // rz = Gx + s - h, and the scalars of the stopping test (slots in vec.hpp).
+// A batch of kb problems (sizes n1, p1, m1, l1 each; n = kb n1, ...) is one
+// stacked problem: blockIdx.y is the problem, whose rows (its x, y and cone
+// rows, see batch.cpp) the x-blocks walk, so that every block's partial
+// scalars belong to one problem.  kb = 1 is the plain problem.
+__device__ inline int32_t stacked_row(int32_t kb, int32_t n1, int32_t p1, int32_t m1, int32_t l1, int32_t inst,
+                                      int32_t loc) {
+    if (loc < n1) return inst * n1 + loc;
+    if (loc < n1 + p1) return kb * n1 + inst * p1 + (loc - n1);
+    const int32_t w = loc - n1 - p1;
+    return kb * (n1 + p1) + (w < l1 ? inst * l1 + w : kb * l1 + inst * (m1 - l1) + (w - l1));
+}
+
 __global__ void __launch_bounds__(256) residual_kernel(
     int32_t n, int32_t p, int32_t m, const int64_t *__restrict__ kr_ptr, const int32_t *__restrict__ kr_col,
     const double *__restrict__ kr_val, const double *__restrict__ x, const double *__restrict__ y,
     const double *__restrict__ z, const double *__restrict__ s, const double *__restrict__ c,
     const double *__restrict__ b, const double *__restrict__ hv, double *__restrict__ rx,
-    double *__restrict__ ry, double *__restrict__ rz, double *__restrict__ partials) {
+    double *__restrict__ ry, double *__restrict__ rz, double *__restrict__ partials, int32_t kb, int32_t n1,
+    int32_t p1, int32_t m1, int32_t l1) {
     double val[NSCAL];
 #pragma unroll
     for (int q = 0; q < NSCAL; ++q) val[q] = 0.0;
-    const int32_t N = n + p + m;
     const int sub = threadIdx.x & (RL - 1);
-    const int32_t i = blockIdx.x * (256 / RL) + (threadIdx.x / RL);
+    const int32_t loc = blockIdx.x * (256 / RL) + (threadIdx.x / RL);
+    const bool live = loc < n1 + p1 + m1;
+    const int32_t i = live ? stacked_row(kb, n1, p1, m1, l1, blockIdx.y, loc) : n + p + m;
+    const int32_t N = n + p + m;
     double a0 = 0.0, a1 = 0.0, a2 = 0.0;
     if (i < N) {
         for (int64_t t = kr_ptr[i] + sub; t < kr_ptr[i + 1]; t += RL) {
@@ -120,7 +140,7 @@ __global__ void __launch_bounds__(256) residual_kernel(
             val[S_S] = fabs(s[e]); val[S_H] = fabs(hv[e]);
         }
     }
-    block_reduce_store<NSCAL>(val, SCAL_MAXMASK, partials);
+    block_reduce_store<NSCAL>(val, SCAL_MAXMASK, partials, (int64_t)blockIdx.y * gridDim.x + blockIdx.x);
 }
 
 // res = rhs - K sol, K = static part + (3,3) block from kval; slot 0 of the
@@ -163,7 +183,7 @@ __global__ void __launch_bounds__(256) kkt_residual_kernel(
         val[0] = fabs(r_);
         val[1] = fabs(rhs[i]);
     }
-    block_reduce_store<2>(val, 3u, partials);
+    block_reduce_store<2>(val, 3u, partials, blockIdx.x);
 }
 
 __global__ void build_rhs_kernel(int32_t n, int32_t p, int32_t m, const double *__restrict__ rx,
@@ -182,15 +202,27 @@ __global__ void axpy_kernel(int32_t len, double a, const double *__restrict__ xv
     if (i < len) yv[i] += a * xv[i];
 }
 
-// (x, y, z, s) += alpha (dx, dy, dz, ds), alpha = min(1, frac * min(a_s, a_z))
+// (x, y, z, s) += alpha (dx, dy, dz, ds), alpha = min(1, frac * min(a_s, a_z)); in a batch of kb
+// problems (sizes n1, p1, m1, l1 each; the stacked layout of batch.cpp) each row takes its problem's alpha
 __global__ void update_kernel(int32_t n, int32_t p, int32_t m, const double *__restrict__ d,
                               const double *__restrict__ ds, const unsigned long long *__restrict__ amin,
                               double frac, double *__restrict__ x, double *__restrict__ y,
-                              double *__restrict__ z, double *__restrict__ s, double *__restrict__ alpha_out) {
-    const double as = __longlong_as_double((long long)amin[2]);
-    const double az = __longlong_as_double((long long)amin[3]);
-    const double alpha = fmin(1.0, frac * fmin(as, az));
+                              double *__restrict__ z, double *__restrict__ s, double *__restrict__ alpha_out,
+                              int32_t kb, int32_t n1, int32_t p1, int32_t m1, int32_t l1) {
     const int32_t i = blockIdx.x * 256 + threadIdx.x;
+    int32_t inst = 0;
+    if (kb > 1) {
+        if (i < n) inst = i / n1;
+        else if (i < n + p) inst = (i - n) / p1;
+        else {
+            const int32_t e = i - n - p, l = kb * l1;
+            inst = e < l ? e / l1 : (m1 > l1 ? (e - l) / (m1 - l1) : 0);
+        }
+        inst = inst < kb ? inst : kb - 1;
+    }
+    const double as = __longlong_as_double((long long)amin[4 * inst + 2]);
+    const double az = __longlong_as_double((long long)amin[4 * inst + 3]);
+    const double alpha = fmin(1.0, frac * fmin(as, az));
     if (i == 0 && alpha_out) *alpha_out = alpha;
     if (i < n) x[i] += alpha * d[i];
     else if (i < n + p) y[i - n] += alpha * d[i];
@@ -226,14 +258,16 @@ int launch_scale_copy(qg_handle *h, int32_t len, double a, const double *xv, dou
 int launch_residual(qg_handle *h, const double *x, const double *y, const double *z, const double *s,
                     double *scal_host) {
     Device &d = h->d;
-    const int32_t N = h->N;
-    const int32_t nblk = (N + 256 / RL - 1) / (256 / RL);
-    residual_kernel<<<nblk, 256, 0, h->stream>>>(h->n, h->p, h->m, d.kr_ptr.p, d.kr_col.p, d.kr_val.p, x, y,
-                                                  z, s, d.c.p, d.b.p, d.h.p, d.rx.p, d.ry.p, d.rz.p,
-                                                  d.partials.p);
-    finish_reduce<<<1, 256, 0, h->stream>>>(d.partials.p, nblk, NSCAL, SCAL_MAXMASK, d.scal.p);
+    const int32_t kb = h->ncopy;
+    const int32_t n1 = h->n / kb, p1 = h->p / kb, m1 = h->m / kb, l1 = h->pp.l / kb;
+    const int32_t nblk = (n1 + p1 + m1 + 256 / RL - 1) / (256 / RL);
+    residual_kernel<<<dim3((unsigned)nblk, (unsigned)kb), 256, 0, h->stream>>>(
+        h->n, h->p, h->m, d.kr_ptr.p, d.kr_col.p, d.kr_val.p, x, y, z, s, d.c.p, d.b.p, d.h.p, d.rx.p, d.ry.p,
+        d.rz.p, d.partials.p, kb, n1, p1, m1, l1);
+    finish_reduce<<<(unsigned)kb, 256, 0, h->stream>>>(d.partials.p, nblk, NSCAL, SCAL_MAXMASK, d.scal_inst.p);
     QG_HIP(h, hipGetLastError());
-    QG_HIP(h, hipMemcpyAsync(scal_host, d.scal.p, NSCAL * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    QG_HIP(h, hipMemcpyAsync(scal_host, d.scal_inst.p, (size_t)kb * NSCAL * sizeof(double),
+                             hipMemcpyDeviceToHost, h->stream));
     QG_HIP(h, hipStreamSynchronize(h->stream));
     return QG_OK;
 }
@@ -270,8 +304,10 @@ int launch_axpy(qg_handle *h, int32_t len, double a, const double *xv, double *y
 int launch_update(qg_handle *h, const double *dvec, const double *ds, double frac, double *alpha_dev) {
     Device &d = h->d;
     const int32_t N = h->N;
+    const int32_t kb = h->ncopy;
     update_kernel<<<(N + 255) / 256, 256, 0, h->stream>>>(h->n, h->p, h->m, dvec, ds, d.amin.p, frac, d.x.p,
-                                                          d.y.p, d.z.p, d.s.p, alpha_dev);
+                                                          d.y.p, d.z.p, d.s.p, alpha_dev, kb, h->n / kb,
+                                                          h->p / kb, h->m / kb, h->pp.l / kb);
     QG_HIP(h, hipGetLastError());
     return QG_OK;
 }

@@ -34,6 +34,9 @@ def host(t):
 
 def solver(prob, **kw):
     import paper_2603_29197_amd as qg
+    # FP32+IR solves use FP32 factors at every size here (the library's default keeps FP64 factors
+    # below 1e10 matrix-core flops per factorization, where FP32 saves nothing)
+    kw.setdefault("fp32_min_flops", 0.0)
     print(f"[gpu] setup {prob.name} n={prob.n} m={prob.m} p={prob.p} {kw}", flush=True)
     return qg.Solver(prob, **kw)
 
@@ -288,3 +291,20 @@ def test_phase_counts_one_factor_two_solves_per_step(name, differentiable):
     assert info["nsolve"] == 2 * k + 1, (info["nsolve"], k)
     assert info["switch_iter"] == -1 and info["ntrisolve"][1] == 0
     S.close()
+
+
+def test_fp32_factors_only_where_the_matrix_cores_pay():
+    """FP32+IR mode with the default threshold: a problem whose fronts all stay small (many_soc_s:
+    no front on the matrix-core path) is factored in FP64 from the start (switch_iter 0, no FP32
+    triangular solve); the lasso_s root (1000 columns, 3e8 flops) likewise below 1e10; with the
+    threshold at 0 the same solve uses FP32 factors."""
+    import paper_2603_29197_amd as qg
+    for name in ("many_soc_s", "lasso_s"):
+        prob = problems.workload(name)
+        S = qg.Solver(prob, precision=qg.QG_FP32_IR)
+        _, _, _, _, info = S.solve()
+        assert info["status"] == 1 and info["switch_iter"] == 0 and info["ntrisolve"][1] == 0, info
+        S.set_settings(fp32_min_flops=0.0)
+        _, _, _, _, info = S.solve()
+        assert info["status"] == 1 and info["switch_iter"] != 0 and info["ntrisolve"][1] > 0, info
+        S.close()

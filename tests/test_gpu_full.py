@@ -44,6 +44,9 @@ def host(t):
 
 def solver(prob, **kw):
     import paper_2603_29197_amd as qg
+    # FP32+IR solves use FP32 factors at every size here (the library's default keeps FP64 factors
+    # below 1e10 matrix-core flops per factorization, where FP32 saves nothing)
+    kw.setdefault("fp32_min_flops", 0.0)
     print(f"[gpu] setup {prob.name} n={prob.n} m={prob.m} p={prob.p}", flush=True)
     return qg.Solver(prob, **kw)
 

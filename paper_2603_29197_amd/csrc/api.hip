@@ -247,7 +247,7 @@ static int allocate_device(qg_handle *h) {
     if ((rc = dalloc(h, d.scal_inst, (size_t)h->ncopy * NSCAL))) return rc;
     if ((rc = dalloc(h, d.alpha, 4))) return rc;
     if ((rc = dalloc(h, d.amin, 4 * (size_t)h->ncopy))) return rc;
-    if ((rc = dalloc(h, d.mu, (size_t)h->ncopy))) return rc;
+    if ((rc = dalloc(h, d.mu, 2 * (size_t)h->ncopy))) return rc;
     if ((rc = dalloc(h, d.flag, 1))) return rc;
     // per-block partials: the sparse residual kernels use 256 / RL rows per block
     const size_t nblk = (N + 256 / RL - 1) / (256 / RL) + (size_t)((h->pp.l + h->pp.nsoc + 255) / 256) +

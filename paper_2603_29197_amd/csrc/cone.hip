@@ -318,6 +318,54 @@ __global__ void finish_max(const double *__restrict__ partials, int32_t nblk, do
     *out = v;
 }
 
+// Batches: the shift of the initial point is each problem's own.  Key of a
+// double whose unsigned integer order is the numeric order (a NaN above +inf),
+// for one atomicMax per cone into the problem's slot.
+__device__ inline unsigned long long ordered_key(double v) {
+    if (v != v) v = __longlong_as_double(0x7ff8000000000000LL);
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ULL);
+}
+__device__ inline double ordered_value(unsigned long long k) {
+    return __longlong_as_double((long long)((k >> 63) ? (k & 0x7fffffffffffffffULL) : ~k));
+}
+
+__global__ void init_keys_kernel(unsigned long long *__restrict__ keys, int32_t kb) {
+    const int32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i < kb) keys[4 * i] = ordered_key(-INFINITY);
+}
+
+// max over each problem's cones of -lambda_min (one thread per cone, any size: the initial point only)
+__global__ void lmin_inst_kernel(int32_t l, int32_t nsoc, const int32_t *__restrict__ soc_off,
+                                 const double *__restrict__ u, unsigned long long *__restrict__ keys, int32_t l1,
+                                 int32_t nsoc1, int32_t kb) {
+    const int32_t t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= l + nsoc) return;
+    double v;
+    if (t < l) {
+        v = -u[t];
+    } else {
+        const int32_t k = t - l;
+        const int32_t off = soc_off[k], q = soc_off[k + 1] - off;
+        double n1 = 0.0;
+        for (int32_t a = 1; a < q; ++a) n1 += u[off + a] * u[off + a];
+        v = -(u[off] - sqrt(n1));
+    }
+    atomicMax(keys + 4 * cone_problem(t, l, l1, nsoc1, kb), ordered_key(v));
+}
+
+// u += (1 + a_i) e on the cones of every problem i with a_i = max(-lambda_min) >= 0
+__global__ void add_e_inst_kernel(int32_t l, int32_t nsoc, const int32_t *__restrict__ soc_off,
+                                  const unsigned long long *__restrict__ keys, double *__restrict__ u, int32_t l1,
+                                  int32_t nsoc1, int32_t kb) {
+    const int32_t t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= l + nsoc) return;
+    const double a = ordered_value(keys[4 * cone_problem(t, l, l1, nsoc1, kb)]);
+    if (a < 0.0) return;
+    if (t < l) u[t] += 1.0 + a;
+    else u[soc_off[t - l]] += 1.0 + a;
+}
+
 // u += c e
 __global__ void add_e_kernel(int32_t l, int32_t nsoc, const int32_t *__restrict__ soc_off, double c,
                              double *__restrict__ u) {
@@ -679,6 +727,17 @@ int launch_corrector(qg_handle *h, const double *dsa, const double *dza, double 
 int launch_shift_interior(qg_handle *h, double *u) {
     Device &d = h->d;
     const unsigned g = cone_grid(h);
+    const int32_t kb = h->ncopy;
+    if (kb > 1) {
+        // the amin slots serve as scratch here; the step kernels reset them before use
+        init_keys_kernel<<<(kb + 255) / 256, 256, 0, h->stream>>>(d.amin.p, kb);
+        lmin_inst_kernel<<<g, 256, 0, h->stream>>>(h->pp.l, h->pp.nsoc, d.soc_off.p, u, d.amin.p, h->pp.l / kb,
+                                                   h->pp.nsoc / kb, kb);
+        add_e_inst_kernel<<<g, 256, 0, h->stream>>>(h->pp.l, h->pp.nsoc, d.soc_off.p, d.amin.p, u, h->pp.l / kb,
+                                                    h->pp.nsoc / kb, kb);
+        QG_HIP(h, hipGetLastError());
+        return QG_OK;
+    }
     lmin_kernel<<<g, 256, 0, h->stream>>>(h->pp.l, h->pp.nsoc, d.soc_off.p, u, d.partials.p);
     const unsigned gb = big_grid(h);
     if (gb) lmin_big<<<gb, 256, 0, h->stream>>>(h->nbig, d.big_cones.p, d.soc_off.p, u, d.partials.p + g);

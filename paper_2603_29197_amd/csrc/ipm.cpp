@@ -131,7 +131,7 @@ int ipm_solve(qg_handle *h, double *xo, double *so, double *yo, double *zo, qg_i
     bool fp64_only = st.precision != QG_FP32_IR || h->plan.large_flops < st.fp32_min_flops;
     // residual scalars of each problem of a batch (one problem: kb = 1) and of the whole stack
     const int32_t kb = h->ncopy;
-    std::vector<double> scal_all((size_t)kb * NSCAL), mu_host((size_t)kb);
+    std::vector<double> scal_all((size_t)kb * NSCAL), mu_host(2 * (size_t)kb, 1.0);
     double scal[NSCAL];
     auto combine = [&]() {
         for (int q = 0; q < NSCAL; ++q) {
@@ -143,11 +143,17 @@ int ipm_solve(qg_handle *h, double *xo, double *so, double *yo, double *zo, qg_i
             scal[q] = v;
         }
     };
-    // every problem of the batch meets the test (its own residuals, scales and gap)
+    // every problem of the batch meets the test (its own residuals, scales and gap); a problem that
+    // meets it stops moving (its gate, mu_host[kb + i], drops to 0), so each problem ends at the
+    // first iterate that passes its own test, as when it is solved alone
     auto all_pass = [&](double ea, double er) {
-        for (int32_t i = 0; i < kb; ++i)
-            if (!stop_test(h, scal_all.data() + (size_t)i * NSCAL, ea, er).ok) return false;
-        return true;
+        bool all = true;
+        for (int32_t i = 0; i < kb; ++i) {
+            if (mu_host[(size_t)kb + i] == 0.0) continue;
+            if (stop_test(h, scal_all.data() + (size_t)i * NSCAL, ea, er).ok) mu_host[(size_t)kb + i] = 0.0;
+            else all = false;
+        }
+        return all;
     };
     Scalars sr{};
     int status = QG_MAX_ITER, it = 0;
@@ -213,7 +219,7 @@ int ipm_solve(qg_handle *h, double *xo, double *so, double *yo, double *zo, qg_i
         const double mu = nu > 0 ? sr.sz / nu : 0.0;
         // each problem's own complementarity measure for its centering (a batch: nu / kb cone units each)
         for (int32_t i = 0; i < kb; ++i) mu_host[(size_t)i] = nu > 0 ? scal_all[(size_t)i * NSCAL + S_SZ] / (nu / kb) : 0.0;
-        QG_HIP(h, hipMemcpyAsync(d.mu.p, mu_host.data(), sizeof(double) * kb, hipMemcpyHostToDevice, h->stream));
+        QG_HIP(h, hipMemcpyAsync(d.mu.p, mu_host.data(), sizeof(double) * 2 * kb, hipMemcpyHostToDevice, h->stream));
         const double gscaled = sr.gap / std::max(1.0, std::min(std::fabs(sr.pobj), std::fabs(sr.dobj)));
         if (!fp64_only && gscaled < st.switch_gap) fp64_only = true;
         prec = fp64_only ? QG_FP64 : QG_FP32_IR;

@@ -150,7 +150,8 @@ struct Device {
     DBuf<int32_t> zcone;        // per z row: SOC index (-1 on the orthant)
     DBuf<double> alpha;         // step lengths of the last iteration (affine, combined)
     DBuf<unsigned long long> amin;          // step-length minima (ordered bits), 4 per problem of a batch
-    DBuf<double> mu;            // complementarity measure of each problem of a batch
+    DBuf<double> mu;            // complementarity measure of each problem of a batch, then its step gate
+                                // (1 while it iterates, 0 once its own stopping test has passed)
     DBuf<int32_t> flag;         // count of non-finite entries (qg_update_vectors)
 };
 

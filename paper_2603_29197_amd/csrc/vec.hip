@@ -208,7 +208,8 @@ __global__ void update_kernel(int32_t n, int32_t p, int32_t m, const double *__r
                               const double *__restrict__ ds, const unsigned long long *__restrict__ amin,
                               double frac, double *__restrict__ x, double *__restrict__ y,
                               double *__restrict__ z, double *__restrict__ s, double *__restrict__ alpha_out,
-                              int32_t kb, int32_t n1, int32_t p1, int32_t m1, int32_t l1) {
+                              int32_t kb, int32_t n1, int32_t p1, int32_t m1, int32_t l1,
+                              const double *__restrict__ gate) {
     const int32_t i = blockIdx.x * 256 + threadIdx.x;
     int32_t inst = 0;
     if (kb > 1) {
@@ -222,8 +223,11 @@ __global__ void update_kernel(int32_t n, int32_t p, int32_t m, const double *__r
     }
     const double as = __longlong_as_double((long long)amin[4 * inst + 2]);
     const double az = __longlong_as_double((long long)amin[4 * inst + 3]);
-    const double alpha = fmin(1.0, frac * fmin(as, az));
+    // a problem of a batch whose own stopping test has passed keeps its iterate (gate 0)
+    const double g = kb > 1 ? gate[inst] : 1.0;
+    const double alpha = g * fmin(1.0, frac * fmin(as, az));
     if (i == 0 && alpha_out) *alpha_out = alpha;
+    if (g == 0.0) return;
     if (i < n) x[i] += alpha * d[i];
     else if (i < n + p) y[i - n] += alpha * d[i];
     else if (i < n + p + m) {
@@ -307,7 +311,7 @@ int launch_update(qg_handle *h, const double *dvec, const double *ds, double fra
     const int32_t kb = h->ncopy;
     update_kernel<<<(N + 255) / 256, 256, 0, h->stream>>>(h->n, h->p, h->m, dvec, ds, d.amin.p, frac, d.x.p,
                                                           d.y.p, d.z.p, d.s.p, alpha_dev, kb, h->n / kb,
-                                                          h->p / kb, h->m / kb, h->pp.l / kb);
+                                                          h->p / kb, h->m / kb, h->pp.l / kb, d.mu.p + kb);
     QG_HIP(h, hipGetLastError());
     return QG_OK;
 }

@@ -1,9 +1,13 @@
 """Batches of problems on one pattern (qg_setup_batch / qg_solve_batch): every
-problem of the batch against the oracle's solve of that problem alone, in
-both precisions; the batch covers small fronts (lasso_s: thousands of small
-fronts and a 1000-wide root), a single large front per problem (small_qp:
-its copies factored and solved by one launch sequence) and second-order cones
-(mixed_soc: the cone rows come back problem by problem).
+problem of the batch against the oracle's solve of that problem alone, and
+against the library's own solve of it alone, in both precisions; the batch
+covers small fronts (lasso_s: thousands of small fronts and a 1000-wide
+root), a single large front per problem (small_qp: its copies factored and
+solved by one launch sequence) and second-order cones (mixed_soc: the cone
+rows come back problem by problem).  Each problem stops moving at the first
+iterate that passes its own test, so it ends where its own solve ends; the
+shared parts (the factorization's precision, the number of refinement
+corrections) change its iterates by rounding only.
 """
 import numpy as np
 import pytest
@@ -50,6 +54,13 @@ def test_batch_matches_single_oracle_solves(name, k, prec):
         assert ex <= 1e-6 and eo <= 1e-6, (i, ex, eo)
         assert np.max(np.abs(rz), initial=0.0) <= 1e-6 * (1 + np.max(np.abs(pr.h), initial=0.0))
         assert np.max(np.abs(ry), initial=0.0) <= 1e-6 * (1 + np.max(np.abs(pr.b), initial=0.0))
+        S = qg.Solver(pr, precision=qg.QG_FP64 if prec == "fp64" else qg.QG_FP32_IR, fp32_min_flops=0.0)
+        xs, _, _, _, info1 = S.solve()
+        S.close()
+        assert info1["status"] == 1
+        e1 = relerr(x[i], xs.cpu().numpy())
+        print(f"[gpu]   problem {i}: against its own solve {e1:.1e} ({info1['iters']} iterations)", flush=True)
+        assert e1 <= 1e-8, (i, e1)
     B.close()
 
 

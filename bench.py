@@ -317,14 +317,14 @@ def main():
         def kern(info, slot):
             l, ms, fl = info["kern_launches"][slot], info["kern_ms"][slot], info["kern_flops"][slot]
             return (int(l), ms, fl, fl / (ms * 1e-3) / 1e12 if ms > 0 else 0.0)
-        # slot 3 = FP32 on 128 x 128 tiles (trail_update_big<float>), the kernel with the most flops;
-        # slot 1 = FP32 on 64 x 64 tiles (trail_update<float>: the rank-64 updates inside a super-panel)
+        # slot 3 = FP32 on 128 x 128 tiles (trail_update_big), the kernel with the most flops;
+        # slot 1 = FP32 on 64 x 64 tiles (trail_update<float>: the rank-64 updates inside a super-panel);
+        # slot 0 = FP64 (trail_update<double>, 64 x 64 tiles: the FP64 mode has no 128 x 128 kernel)
         lb, msb, flb, ab = kern(p32, 3)
         ls, mss, fls, as_ = kern(p32, 1)
-        l64, ms64, fl64, a64 = kern(p64, 2)
-        l64s, ms64s, fl64s, a64s = kern(p64, 0)
+        l64, ms64, fl64, a64 = kern(p64, 0)
         if lb > 0 and msb > 0:
-            roof = {"kernel": "trail_update_big<float> (MFMA f32 16x16x4, 128x128 tiles: the rank-256 trailing "
+            roof = {"kernel": "trail_update_big (FP32, MFMA f32 16x16x4, 128x128 tiles: the rank-256 trailing "
                               "updates of large fronts)",
                     "bound": "mfma", "achieved": round(ab, 2), "peak": PEAK_TFLOPS["fp32"],
                     "unit": "TFLOP/s", "frac": round(ab / PEAK_TFLOPS["fp32"], 4),
@@ -338,12 +338,11 @@ def main():
                                                   "frac": round((flb + fls) / ((msb + mss) * 1e-3) / 1e12
                                                                 / PEAK_TFLOPS["fp32"], 4)}}
             if l64 > 0 and ms64 > 0:
-                roof["fp64_kernel"] = {"kernel": "trail_update_big<double>", "achieved": round(a64, 2),
-                                       "peak": PEAK_TFLOPS["fp64"], "frac": round(a64 / PEAK_TFLOPS["fp64"], 4),
+                roof["fp64_kernel"] = {"kernel": "trail_update<double> (all FP64 trailing updates)",
+                                       "achieved": round(a64, 2), "peak": PEAK_TFLOPS["fp64"],
+                                       "frac": round(a64 / PEAK_TFLOPS["fp64"], 4),
                                        "traffic": TRAFFIC_BYTES_PER_LAUNCH["fp64"],
-                                       "launches": l64, "avg_launch_us": round(1e3 * ms64 / l64, 2),
-                                       "all_trailing_updates_fp64": round((fl64 + fl64s) / ((ms64 + ms64s) * 1e-3)
-                                                                          / 1e12, 2)}
+                                       "launches": l64, "avg_launch_us": round(1e3 * ms64 / l64, 2)}
     # the solve phase of the full FP32+IR solve against HBM: per triangular solve 2 nnz(L) s_L + 4 N 8
     # bytes (s_L = 4 with an FP32 factor, 8 with FP64), per residual nnz(K upper) (8 + 4) + 3 N 8 bytes
     last = full["fp32_ir"][1]

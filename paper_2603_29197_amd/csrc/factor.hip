@@ -714,29 +714,52 @@ __global__ void __launch_bounds__(256) trail_update(T *__restrict__ F, int32_t r
             }
 }
 
-// The same update on 128 x 128 tiles, for the large launches (the rank-SB
-// updates of a super-panel across the rest of the front).  Each wavefront owns
-// a 64 x 64 quarter as 4 x 4 MFMA 16x16x4 blocks, so every operand read from
-// LDS feeds four MFMAs (twice the reuse of the 64 x 64 tiles) and every entry
-// of the two panel blocks staged per chunk serves 128 rows or columns.  The
-// rank is consumed in chunks of KC columns through double-buffered LDS, the
-// global loads of the next chunk in flight during the MFMAs of the current
-// one; C is read once, after the last chunk.  On a diagonal tile the quarter
-// strictly above the diagonal does no MFMA work.
-template <typename T>
-__global__ void __launch_bounds__(256) trail_update_big(T *__restrict__ F, int32_t r, int32_t k0, int32_t kb,
-                                                       int32_t r_lo, int32_t c_hi, int32_t urgent,
-                                                       int64_t zstride) {
+// Raw buffer resource over nbytes from p, built from wave-uniform values (so
+// it lives in scalar registers and every access is a single instruction): a
+// load at a byte offset >= nbytes returns 0 and a store there is dropped by the
+// hardware range check.  Word 3 selects the 32-bit data format (4 in bits
+// 15..18 of a gfx9-family descriptor).
+__device__ inline __amdgpu_buffer_rsrc_t uniform_rsrc(const void *p, int32_t nbytes) {
+    const uint64_t a = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+    return __builtin_amdgcn_make_buffer_rsrc((void *)(((uint64_t)hi << 32) | lo), (short)0,
+                                             __builtin_amdgcn_readfirstlane(nbytes), 0x00020000);
+}
+// byte offset past every range: marks a lane or entry whose access must read 0 / store nothing
+constexpr uint32_t OFF_NONE = 0x80000000u;
+// rows of the largest front the 128 x 128 kernel takes: its ranges (at most 64 columns of r
+// 4-byte rows) and offsets stay below OFF_NONE
+constexpr int32_t BIG_MAX_R = (1 << 23) - 1;
+
+// The same update (FP32) on 128 x 128 tiles, for the large launches (the
+// rank-SB updates of a super-panel across the rest of the front).  Each
+// wavefront owns a 64 x 64 quarter as 4 x 4 MFMA 16x16x4 blocks, so every
+// operand read from LDS feeds four MFMAs and every entry of the two panel
+// blocks staged per chunk serves 128 rows or columns.  The rank is consumed in
+// chunks of KC = 16 columns through double-buffered LDS (38 KB per workgroup,
+// four workgroups per compute unit), the global loads of the next chunk in
+// flight during the MFMAs of the current one; C is read once, after the last
+// chunk.  All global accesses are buffer instructions on a resource in scalar
+// registers: a chunk's resource spans exactly its valid rank columns, so
+// columns past the rank read 0, and lanes on rows past the end point beyond
+// every range (OFF_NONE), so no address arithmetic or select sits in the loop.
+// On a diagonal tile the quarter strictly above the diagonal computes products
+// it never stores.
+__global__ void __launch_bounds__(256, 3) trail_update_big(float *__restrict__ F, int32_t r, int32_t k0, int32_t kb,
+                                                          int32_t r_lo, int32_t c_hi, int32_t urgent,
+                                                          int64_t zstride) {
     F += blockIdx.z * zstride;
     constexpr int TILE = 128;
-    constexpr int KC = 32;
-    constexpr int PER = KC * TILE / 256;           // rank columns staged per thread and chunk (16)
+    constexpr int KC = 16;
+    constexpr int PER = KC * TILE / 256;           // rank columns staged per thread and chunk (8)
     // row pitch of the LDS tiles: the four 16-lane groups of an MFMA operand read rows kk .. kk+3;
-    // for 4-byte entries a pitch of 144 (16 mod 32 banks) puts each half-wavefront on disjoint banks
-    constexpr int LDT = sizeof(T) == 4 ? TILE + 16 : TILE;
-    __shared__ T As[2][KC * LDT];                  // As[kk * LDT + i] = L(r0 + i, k)
-    __shared__ T Bs[2][KC * LDT];                  // Bs[kk * LDT + j] = L(c0 + j, k) * D(k)
-    __shared__ T Dk[SB];
+    // a pitch of 144 (16 mod 32 banks) puts each half-wavefront on disjoint banks
+    constexpr int LDT = TILE + 16;
+    static_assert(SB == 256, "one pivot per thread of the 256-thread workgroup");
+    __shared__ float As[2][KC * LDT];              // As[kk * LDT + i] = L(r0 + i, k)
+    __shared__ float Bs[2][KC * LDT];              // Bs[kk * LDT + j] = L(c0 + j, k) * D(k)
+    __shared__ float Dk[SB];                       // D(k0 .. k0 + kb - 1), zero past the rank
     // XCD-aware order as in trail_update: XCD x takes the tile rows ti = x (mod 8)
     const int32_t TR = (r - r_lo + TILE - 1) / TILE, TC = (c_hi - r_lo + TILE - 1) / TILE, NR = (TR + 7) / 8;
     const int32_t xcd = blockIdx.x % 8, sq = blockIdx.x / 8;
@@ -750,36 +773,28 @@ __global__ void __launch_bounds__(256) trail_update_big(T *__restrict__ F, int32
     const int lr = lane & 15, lk = lane >> 4;
     // this quarter stores results unless it lies beyond the last row or column, or strictly above the diagonal
     const bool active = r0 + wr < r && c0 + wc < c_hi && r0 + wr + 63 >= c0 + wc;
-    typedef typename Acc4<T>::type V;
+    typedef typename Acc4<float>::type V;
     const int32_t i = tid & (TILE - 1);
-    const int kk0 = tid >> 7;                      // 0 or 1
-    T ra[PER], rb[PER];
-    uint32_t va = 0, vb = 0;
+    const int kk0 = tid >> 7;                      // 0 or 1: this thread stages rank columns kk0, kk0 + 2, ...
+    // byte offsets of this thread's first staged entries within a chunk (column kk0 of the chunk)
+    const uint32_t offa = r0 + i < r ? (uint32_t)(kk0 * r + r0 + i) * 4u : OFF_NONE;
+    const uint32_t offb = c0 + i < c_hi ? (uint32_t)(kk0 * r + c0 + i) * 4u : OFF_NONE;
+    const uint32_t ustep = 8u * (uint32_t)r;       // two columns
+    float ra[PER], rb[PER];
     auto gload = [&](int32_t kc) {
-        va = vb = 0;
+        const __amdgpu_buffer_rsrc_t rs = uniform_rsrc(F + (int64_t)(k0 + kc) * r, min(KC, kb - kc) * r * 4);
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
-            const int32_t kk = kk0 + 2 * u;
-            const bool okk = kc + kk < kb;
-            const int32_t kcol = k0 + kc + (okk ? kk : 0);
-            const T *colp = F + (int64_t)kcol * r;
-            const bool oka = okk && r0 + i < r, okb = okk && c0 + i < c_hi;
-            ra[u] = colp[oka ? r0 + i : 0];
-            rb[u] = colp[okb ? c0 + i : 0];
-            va |= (uint32_t)oka << u;
-            vb |= (uint32_t)okb << u;
+            ra[u] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, (int)(offa + u * ustep), 0, 0));
+            rb[u] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, (int)(offb + u * ustep), 0, 0));
         }
     };
     auto lstore = [&](int buf, int32_t kc) {
-        T dk[PER];
-#pragma unroll
-        for (int u = 0; u < PER; ++u) dk[u] = Dk[min(kc + kk0 + 2 * u, SB - 1)];
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
             const int32_t kk = kk0 + 2 * u;
-            const T b = rb[u] * dk[u];
-            As[buf][kk * LDT + i] = ((va >> u) & 1u) ? ra[u] : T(0);
-            Bs[buf][kk * LDT + i] = ((vb >> u) & 1u) ? b : T(0);
+            As[buf][kk * LDT + i] = ra[u];
+            Bs[buf][kk * LDT + i] = rb[u] * Dk[kc + kk];
         }
     };
     V acc[4][4];
@@ -788,7 +803,7 @@ __global__ void __launch_bounds__(256) trail_update_big(T *__restrict__ F, int32
 #pragma unroll
         for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = V{0, 0, 0, 0};
     const int32_t nch = (kb + KC - 1) / KC;
-    if (tid < kb) Dk[tid] = F[(int64_t)(k0 + tid) * r + k0 + tid];
+    Dk[tid] = tid < kb ? F[(int64_t)(k0 + tid) * r + k0 + tid] : 0.f;   // blockDim == SB
     gload(0);
     __syncthreads();
     lstore(0, 0);
@@ -796,13 +811,10 @@ __global__ void __launch_bounds__(256) trail_update_big(T *__restrict__ F, int32
     for (int32_t c = 0; c < nch; ++c) {
         const int buf = c & 1;
         if (c + 1 < nch) gload((c + 1) * KC);
-        // every quarter runs the MFMAs (a quarter without entries to update, on the edges or above the
-        // diagonal, computes products it never stores): no branch around them, so the accumulators stay
-        // in the accumulation registers for the whole loop
 #pragma unroll
         for (int32_t kk = 0; kk < KC; kk += 4) {       // zero-padded past the rank
             const int32_t kq = kk + lk;
-            T a_op[4], b_op[4];
+            float a_op[4], b_op[4];
 #pragma unroll
             for (int bj = 0; bj < 4; ++bj) a_op[bj] = Bs[buf][kq * LDT + wc + 16 * bj + lr];
 #pragma unroll
@@ -816,27 +828,30 @@ __global__ void __launch_bounds__(256) trail_update_big(T *__restrict__ F, int32
         __syncthreads();
     }
     if (!active) return;
-    // lane holds C(row = wr + 16 bi + lr, col = wc + 16 bj + mfma_out_row(lk, v)); 16 lanes store 16
-    // consecutive rows of one column
+    // lane holds C(row = wr + 16 bi + lr, col = wc + 16 bj + mfma_out_row(lk, v)); 16 lanes load and store
+    // 16 consecutive rows of one column.  The resource spans this quarter's valid columns; entries below
+    // the last row or above the diagonal point past it.
+    const int32_t cq = c0 + wc;
+    const __amdgpu_buffer_rsrc_t rc = uniform_rsrc(F + (int64_t)cq * r, min(64, c_hi - cq) * r * 4);
 #pragma unroll
     for (int bi = 0; bi < 4; ++bi) {
         const int32_t row = r0 + wr + 16 * bi + lr;
-        T cold[4][4];
+        uint32_t off[4][4];
+        float cold[4][4];
 #pragma unroll
         for (int bj = 0; bj < 4; ++bj)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int32_t col = c0 + wc + 16 * bj + mfma_out_row<T>(lk, v);
-                const bool ok = row < r && col < c_hi && row >= col;
-                cold[bj][v] = F[ok ? (int64_t)col * r + row : 0];
+                const int32_t cl = 16 * bj + mfma_out_row<float>(lk, v);
+                off[bj][v] = (row < r && row >= cq + cl) ? (uint32_t)(cl * r + row) * 4u : OFF_NONE;
+                cold[bj][v] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rc, (int)off[bj][v], 0, 0));
             }
 #pragma unroll
         for (int bj = 0; bj < 4; ++bj)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int32_t col = c0 + wc + 16 * bj + mfma_out_row<T>(lk, v);
-                if (row < r && col < c_hi && row >= col) F[(int64_t)col * r + row] = cold[bj][v] - acc[bi][bj][v];
-            }
+            for (int v = 0; v < 4; ++v)
+                __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, cold[bj][v] - acc[bi][bj][v]), rc,
+                                                      (int)off[bj][v], 0, 0);
     }
 }
 
@@ -956,11 +971,13 @@ static void launch_update(qg_handle *h, hipStream_t st, T *F, int32_t r, int32_t
     const int urgent = st == h->stream ? 1 : 0;
     // FP32 only: the FP64 variant needs more registers than two wavefronts per SIMD allow and was
     // measured slower than the 64 x 64 tiles (one wavefront per SIMD leaves the loads unhidden)
-    const bool big = sizeof(T) == 4 && lower2 * ncopy >= 256 && kb > 64;
-    if (big)
-        trail_update_big<T><<<dim3((unsigned)(8 * TC2 * ((TR2 + 7) / 8)), 1, (unsigned)ncopy), 256, 0, st>>>(
-            F, r, k0, kb, r_lo, c_hi, urgent, cs.f);
-    else
+    const bool big = sizeof(T) == 4 && lower2 * ncopy >= 256 && kb > 64 && r <= BIG_MAX_R;
+    if constexpr (sizeof(T) == 4) {
+        if (big)
+            trail_update_big<<<dim3((unsigned)(8 * TC2 * ((TR2 + 7) / 8)), 1, (unsigned)ncopy), 256, 0, st>>>(
+                F, r, k0, kb, r_lo, c_hi, urgent, cs.f);
+    }
+    if (!big)
         trail_update<T><<<dim3((unsigned)(8 * TC * ((TR + 7) / 8)), 1, (unsigned)ncopy), 256, 0, st>>>(
             F, r, k0, kb, r_lo, c_hi, urgent, cs.f);
     if (h->st.profile) {

@@ -252,6 +252,8 @@ def main():
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the other configurations")
     ap.add_argument("--workload", default=WORKLOAD, help=argparse.SUPPRESS)
+    ap.add_argument("--fp32-steps-only", action="store_true",
+                    help="setup and the timed FP32+IR Newton steps only, for runs under a profiler; prints no JSON line")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device copy of 256 MiB three times (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -293,6 +295,9 @@ def main():
         return times, is32, infos, wall
 
     t32, f32, i32, wall32 = timed(qg.QG_FP32_IR, "fp32+ir")
+    if args.fp32_steps_only:
+        S.close()
+        return
     t64, _, i64, wall64 = timed(qg.QG_FP64, "fp64")
     step32, step64 = med(t32), med(t64)
 

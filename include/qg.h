@@ -55,7 +55,8 @@ typedef int64_t qg_nnz;
 #define QG_ERR_HIP (-5)        /* a HIP call failed (code kept in the handle) */
 #define QG_ERR_STATE (-6)      /* call out of order (e.g. backward before a solve) */
 #define QG_ERR_DEVICE (-7)     /* no usable gfx950 device */
-#define QG_ERR_SIZE (-8)       /* input larger than a fixed capacity (qg_max_step_noalloc) */
+#define QG_ERR_SIZE (-8)       /* input larger than a fixed capacity (qg_max_step_noalloc; at setup,
+                                  a front of more than 8388607 rows) */
 
 /* qg_info.status */
 #define QG_UNSOLVED 0

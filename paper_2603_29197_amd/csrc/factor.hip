@@ -155,16 +155,18 @@ __global__ void __launch_bounds__(256) factor_small(
 
 // Chains (the narrow upper levels of deep elimination trees): one workgroup
 // per component walks the component's levels; the fronts of a level are
-// factored one per wavefront, each in its own LDS tile, with the same
-// arithmetic as factor_small (pivot, rank-1 update of the trailing lower
-// part, column scaling), the steps separated by wavefront barriers only (the
-// LDS operations of one wavefront complete in order).  A front is assembled
-// in its tile from the entries of the numeric assembly map (the same sources
-// in the same order as gather_entries: the K entry, the static regularization
-// of a pivot diagonal, then the children's update entries).  Children below
-// the chain levels were factored by the level kernels before this launch;
-// children inside the component by this workgroup, before the workgroup
-// barrier that ends their level.
+// factored one per wavefront with the same arithmetic as factor_small (pivot,
+// rank-1 update of the trailing lower part, column scaling).  A front is
+// assembled in the wavefront's LDS tile from the entries of the numeric
+// assembly map (the same sources in the same order as gather_entries: the K
+// entry, the static regularization of a pivot diagonal, then the children's
+// update entries); then each lane takes one row (a chain front has at most
+// CHAIN_R = 32 rows) into registers and the pivot steps run there, with the
+// pivot column broadcast by readlane, so a step costs a few instructions
+// instead of LDS round trips and barriers.  Children below the chain levels
+// were factored by the level kernels before this launch; children inside the
+// component by this workgroup, before the workgroup barrier that ends their
+// level.
 template <typename T>
 __global__ void __launch_bounds__(256) factor_chain(
     const int32_t *__restrict__ comp_ptr, const int32_t *__restrict__ grp_ptr, const int32_t *__restrict__ chain_sn,
@@ -174,8 +176,8 @@ __global__ void __launch_bounds__(256) factor_chain(
     const int64_t *__restrict__ fr_off, T *__restrict__ front, const int8_t *__restrict__ kind, double eps,
     double dyn, int32_t *nreg) {
     __shared__ T tile[4][CHAIN_R * CHAIN_R];
-    __shared__ T dsh[4];
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform: the front indices below too
+    const int lane = threadIdx.x & 63;
     T *F = tile[w];
     const int32_t c = blockIdx.x;
     for (int32_t g = comp_ptr[c]; g < comp_ptr[c + 1]; ++g) {
@@ -201,29 +203,39 @@ __global__ void __launch_bounds__(256) factor_chain(
                 F[dst[e] - base] = v;
             }
             __builtin_amdgcn_wave_barrier();
-            for (int32_t jj = 0; jj < k; ++jj) {
-                if (lane == 0) {
-                    const T d = regularize(F[jj * r + jj], kd_s[jj], eps, dyn, nreg);
-                    F[jj * r + jj] = d;
-                    dsh[w] = d;
+            // lane l holds row l of the assembled front (columns 0 .. CHAIN_R - 1, clamped reads; lanes
+            // and columns past r hold values that are never used) and runs the k pivot steps in registers,
+            // the pivot column's entries broadcast with readlane: the same operations in the same order as
+            // factor_front_lds (pivot, rank-1 update of the trailing lower part, column scaling)
+            const int row = lane;
+            const int32_t rowc = min(row, r - 1);
+            const bool live = row < r;
+            T a[CHAIN_R];
+#pragma unroll
+            for (int c = 0; c < CHAIN_R; ++c) a[c] = F[min(c, r - 1) * r + rowc];
+#pragma unroll
+            for (int jj = 0; jj < CHAIN_R; ++jj) {
+                if (jj < k) {                               // uniform
+                    const T raw = lane_bcast(a[jj], jj);
+                    const double sg = pivot_sign(kd_s[jj]);
+                    const bool fix = !(sg * (double)raw > eps);  // also catches NaN
+                    const T d = fix ? (T)(sg * dyn) : raw;
+                    if (fix && lane == 0) atomicAdd(nreg, 1);
+                    if (row == jj) a[jj] = d;
+#pragma unroll
+                    for (int c = jj + 1; c < CHAIN_R; ++c) {
+                        if (c < r) {                        // uniform
+                            const T b = lane_bcast(a[jj], c);
+                            if (row >= c && live) a[c] -= a[jj] * b / d;
+                        }
+                    }
+                    if (row > jj && live) a[jj] /= d;
                 }
-                __builtin_amdgcn_wave_barrier();
-                const T d = dsh[w];
-                const int32_t R = r - jj - 1;
-                for (int32_t idx = lane; idx < R * R; idx += 64) {
-                    const int32_t i = jj + 1 + idx % R, cc = jj + 1 + idx / R;
-                    if (i >= cc) F[cc * r + i] -= F[jj * r + i] * F[jj * r + cc] / d;
-                }
-                __builtin_amdgcn_wave_barrier();
-                for (int32_t i = jj + 1 + lane; i < r; i += 64) F[jj * r + i] /= d;
-                __builtin_amdgcn_wave_barrier();
             }
             T *G = front + base;
-            for (int32_t idx = lane; idx < r * r; idx += 64) {
-                const int32_t i = idx % r, cc = idx / r;
-                if (i >= cc) G[idx] = F[idx];
-            }
-            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int c = 0; c < CHAIN_R; ++c)
+                if (c < r && row >= c && live) G[(int64_t)c * r + row] = a[c];
         }
         __syncthreads();
     }
@@ -237,15 +249,6 @@ __global__ void __launch_bounds__(256) factor_chain(
 __device__ inline float recip(float d) { return __builtin_amdgcn_rcpf(d); }
 __device__ inline double recip(double d) { return 1.0 / d; }
 
-// Value of lane `src` (uniform over the wavefront) of v, for every lane.
-__device__ inline float lane_bcast(float v, int src) {
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
-}
-__device__ inline double lane_bcast(double v, int src) {
-    const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
-    return __hiloint2double(hi, lo);
-}
 
 // One 16 x 16 tile of C = sum_k A(i, k) B(k, j), k = 0..15, on MFMA 16x16x4:
 // a(i, k) and b(k, j) return the operands; the result is in the lane layout
@@ -588,27 +591,64 @@ __global__ void __launch_bounds__(256) panel_solve(T *__restrict__ F, int32_t r,
         }
 }
 
+// Raw buffer resource over nbytes from p, built from wave-uniform values (so
+// it lives in scalar registers and every access is a single instruction): a
+// load at a byte offset >= nbytes returns 0 and a store there is dropped by the
+// hardware range check.  Word 3 selects the 32-bit data format (4 in bits
+// 15..18 of a gfx9-family descriptor).
+__device__ inline __amdgpu_buffer_rsrc_t uniform_rsrc(const void *p, int32_t nbytes) {
+    const uint64_t a = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+    return __builtin_amdgcn_make_buffer_rsrc((void *)(((uint64_t)hi << 32) | lo), (short)0,
+                                             __builtin_amdgcn_readfirstlane(nbytes), 0x00020000);
+}
+// byte offset past every range: marks a lane or entry whose access must read 0 / store nothing.  With
+// fronts of at most MAX_FRONT_R rows the ranges (at most 32 columns of 8-byte or 64 columns of 4-byte
+// entries) and every valid offset stay below it, and it plus the largest in-chunk step stays below 2^32.
+constexpr uint32_t OFF_NONE = 0x80000000u;
+template <typename T> __device__ inline T buffer_load(__amdgpu_buffer_rsrc_t rs, uint32_t off);
+template <> __device__ inline float buffer_load<float>(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, (int)off, 0, 0));
+}
+template <> __device__ inline double buffer_load<double>(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)off, 0, 0));
+}
+template <typename T> __device__ inline void buffer_store(__amdgpu_buffer_rsrc_t rs, uint32_t off, T v);
+template <> __device__ inline void buffer_store<float>(__amdgpu_buffer_rsrc_t rs, uint32_t off, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), rs, (int)off, 0, 0);
+}
+template <> __device__ inline void buffer_store<double>(__amdgpu_buffer_rsrc_t rs, uint32_t off, double v) {
+    typedef uint32_t u2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), rs, (int)off, 0, 0);
+}
+
 // C -= L(:, k0:k0+kb) D L(cols, k0:k0+kb)' on the lower part (row >= col) of
 // rows [r_lo, r) x cols [r_lo, c_hi) of the front F (ld r), 64 x 64 tiles,
-// 1-D grid (see the XCD mapping below).  The rank kb is consumed in chunks of KC columns
-// through double-buffered LDS: the global loads of the next chunk are issued
-// before the MFMAs of the current one and are only waited for at the LDS
-// store, and the old C values are loaded at the start, so both arrive while
-// the matrix cores run.  Four wavefronts per tile, 2 x 2 MFMA 16x16x4 blocks
-// each; the product is formed transposed so that each lane's accumulators run
-// along a column of the column-major front.
+// 1-D grid (see the XCD mapping below).  The rank kb is consumed in chunks of
+// KC = 16 columns through double-buffered LDS: the global loads of the next
+// chunk are issued before the MFMAs of the current one and are only waited
+// for at the LDS store; the old C values are loaded after the last chunk.
+// Four wavefronts per tile, 2 x 2 MFMA 16x16x4 blocks each; the product is
+// formed transposed so that each lane's accumulators run along a column of
+// the column-major front.  Global accesses are buffer instructions on
+// wave-uniform resources, as in trail_update_big below: rank columns past kb
+// and rows past the end read 0, C entries outside the update are neither
+// read nor written.
 template <typename T>
 __global__ void __launch_bounds__(256) trail_update(T *__restrict__ F, int32_t r, int32_t k0, int32_t kb,
                                                    int32_t r_lo, int32_t c_hi, int32_t urgent, int64_t zstride) {
     F += blockIdx.z * zstride;
-    constexpr int KC = 32;
+    constexpr int KC = 16;
     constexpr int PER = KC / 4;                    // rank columns staged per thread and chunk
+    constexpr uint32_t S = sizeof(T);
     // row pitch of the LDS tiles: the four 16-lane groups of an MFMA operand read rows kk .. kk+3;
     // for 4-byte entries a pitch of 80 puts them on disjoint banks
     constexpr int LDT = sizeof(T) == 4 ? 80 : 64;
+    static_assert(SB == 256, "one pivot per thread of the 256-thread workgroup");
     __shared__ T As[2][KC * LDT];                  // As[kk * LDT + i] = L(r0 + i, k)
     __shared__ T Bs[2][KC * LDT];                  // Bs[kk * LDT + j] = L(c0 + j, k) * D(k)
-    __shared__ T Dk[SB];                           // D(k0 .. k0 + kb - 1)
+    __shared__ T Dk[SB];                           // D(k0 .. k0 + kb - 1), zero past the rank
     // Workgroup IDs are dealt to the 8 XCDs in turn; XCD x takes the tile rows ti = x (mod 8)
     // and walks them column tile by column tile, so its concurrent workgroups share the column
     // panel and keep their row panels in that XCD's L2.
@@ -623,52 +663,26 @@ __global__ void __launch_bounds__(256) trail_update(T *__restrict__ F, int32_t r
     const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
     const int lr = lane & 15, lk = lane >> 4;
     typedef typename Acc4<T>::type V;
-    // old C values of this lane's 16 outputs: raw loads from always-valid addresses, validity bits
-    T cold[2][2][4];
-    uint32_t cok = 0;
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-        for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int32_t row = r0 + wr + 16 * bi + lr;
-                const int32_t col = c0 + wc + 16 * bj + mfma_out_row<T>(lk, v);
-                const bool ok = row < r && col < c_hi && row >= col;
-                cold[bi][bj][v] = F[ok ? (int64_t)col * r + row : 0];
-                cok |= (uint32_t)ok << (8 * bi + 4 * bj + v);
-            }
-    // staging registers of one chunk (raw values + validity bits; zeroing waits for the LDS store)
     const int32_t i = tid & 63;
+    const int kk0 = tid >> 6;                      // this thread stages rank columns kk0, kk0 + 4, ...
+    const uint32_t offa = r0 + i < r ? (uint32_t)(kk0 * r + r0 + i) * S : OFF_NONE;
+    const uint32_t offb = c0 + i < c_hi ? (uint32_t)(kk0 * r + c0 + i) * S : OFF_NONE;
+    const uint32_t ustep = 4u * (uint32_t)r * S;   // four columns
     T ra[PER], rb[PER];
-    uint32_t va = 0, vb = 0;
     auto gload = [&](int32_t kc) {
-        va = vb = 0;
+        const __amdgpu_buffer_rsrc_t rs = uniform_rsrc(F + (int64_t)(k0 + kc) * r, min(KC, kb - kc) * r * (int32_t)S);
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
-            const int32_t kk = (tid >> 6) + 4 * u;
-            const bool okk = kc + kk < kb;
-            const int32_t kcol = k0 + kc + (okk ? kk : 0);
-            const T *colp = F + (int64_t)kcol * r;
-            const bool oka = okk && r0 + i < r, okb = okk && c0 + i < c_hi;
-            ra[u] = colp[oka ? r0 + i : 0];
-            rb[u] = colp[okb ? c0 + i : 0];
-            va |= (uint32_t)oka << u;
-            vb |= (uint32_t)okb << u;
+            ra[u] = buffer_load<T>(rs, offa + u * ustep);
+            rb[u] = buffer_load<T>(rs, offb + u * ustep);
         }
     };
-    // branch-free: the pivots are read for every staged entry (the index clamped into Dk) and the
-    // invalid entries replaced by zeros with selects
     auto lstore = [&](int buf, int32_t kc) {
-        T dk[PER];
-#pragma unroll
-        for (int u = 0; u < PER; ++u) dk[u] = Dk[min(kc + (tid >> 6) + 4 * u, SB - 1)];
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
-            const int32_t kk = (tid >> 6) + 4 * u;
-            const T b = rb[u] * dk[u];
-            As[buf][kk * LDT + i] = ((va >> u) & 1u) ? ra[u] : T(0);
-            Bs[buf][kk * LDT + i] = ((vb >> u) & 1u) ? b : T(0);
+            const int32_t kk = kk0 + 4 * u;
+            As[buf][kk * LDT + i] = ra[u];
+            Bs[buf][kk * LDT + i] = rb[u] * Dk[kc + kk];
         }
     };
     V acc[2][2];
@@ -677,7 +691,7 @@ __global__ void __launch_bounds__(256) trail_update(T *__restrict__ F, int32_t r
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = V{0, 0, 0, 0};
     const int32_t nch = (kb + KC - 1) / KC;
-    if (tid < kb) Dk[tid] = F[(int64_t)(k0 + tid) * r + k0 + tid];
+    Dk[tid] = tid < kb ? F[(int64_t)(k0 + tid) * r + k0 + tid] : T(0);   // blockDim == SB
     gload(0);
     __syncthreads();
     lstore(0, 0);
@@ -701,7 +715,13 @@ __global__ void __launch_bounds__(256) trail_update(T *__restrict__ F, int32_t r
         if (c + 1 < nch) lstore(buf ^ 1, (c + 1) * KC);
         __syncthreads();
     }
-    // lane holds D(mfma_out_row(lk, v), lr) = C(row = wr + 16 bi + lr, col = wc + 16 bj + mfma_out_row(lk, v))
+    // lane holds C(row = wr + 16 bi + lr, col = wc + 16 bj + mfma_out_row(lk, v)); the resource spans the
+    // wavefront's valid columns, entries below the last row or above the diagonal point past it
+    const int32_t cq = c0 + wc;
+    if (cq >= c_hi) return;
+    const __amdgpu_buffer_rsrc_t rc = uniform_rsrc(F + (int64_t)cq * r, min(32, c_hi - cq) * r * (int32_t)S);
+    uint32_t off[2][2][4];
+    T cold[2][2][4];
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
@@ -709,28 +729,17 @@ __global__ void __launch_bounds__(256) trail_update(T *__restrict__ F, int32_t r
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int32_t row = r0 + wr + 16 * bi + lr;
-                const int32_t col = c0 + wc + 16 * bj + mfma_out_row<T>(lk, v);
-                if ((cok >> (8 * bi + 4 * bj + v)) & 1u) F[(int64_t)col * r + row] = cold[bi][bj][v] - acc[bi][bj][v];
+                const int32_t cl = 16 * bj + mfma_out_row<T>(lk, v);
+                off[bi][bj][v] = (row < r && row >= cq + cl) ? (uint32_t)(cl * r + row) * S : OFF_NONE;
+                cold[bi][bj][v] = buffer_load<T>(rc, off[bi][bj][v]);
             }
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) buffer_store<T>(rc, off[bi][bj][v], cold[bi][bj][v] - acc[bi][bj][v]);
 }
-
-// Raw buffer resource over nbytes from p, built from wave-uniform values (so
-// it lives in scalar registers and every access is a single instruction): a
-// load at a byte offset >= nbytes returns 0 and a store there is dropped by the
-// hardware range check.  Word 3 selects the 32-bit data format (4 in bits
-// 15..18 of a gfx9-family descriptor).
-__device__ inline __amdgpu_buffer_rsrc_t uniform_rsrc(const void *p, int32_t nbytes) {
-    const uint64_t a = (uint64_t)p;
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
-    return __builtin_amdgcn_make_buffer_rsrc((void *)(((uint64_t)hi << 32) | lo), (short)0,
-                                             __builtin_amdgcn_readfirstlane(nbytes), 0x00020000);
-}
-// byte offset past every range: marks a lane or entry whose access must read 0 / store nothing
-constexpr uint32_t OFF_NONE = 0x80000000u;
-// rows of the largest front the 128 x 128 kernel takes: its ranges (at most 64 columns of r
-// 4-byte rows) and offsets stay below OFF_NONE
-constexpr int32_t BIG_MAX_R = (1 << 23) - 1;
 
 // The same update (FP32) on 128 x 128 tiles, for the large launches (the
 // rank-SB updates of a super-panel across the rest of the front).  Each
@@ -971,7 +980,7 @@ static void launch_update(qg_handle *h, hipStream_t st, T *F, int32_t r, int32_t
     const int urgent = st == h->stream ? 1 : 0;
     // FP32 only: the FP64 variant needs more registers than two wavefronts per SIMD allow and was
     // measured slower than the 64 x 64 tiles (one wavefront per SIMD leaves the loads unhidden)
-    const bool big = sizeof(T) == 4 && lower2 * ncopy >= 256 && kb > 64 && r <= BIG_MAX_R;
+    const bool big = sizeof(T) == 4 && lower2 * ncopy >= 256 && kb > 64;
     if constexpr (sizeof(T) == 4) {
         if (big)
             trail_update_big<<<dim3((unsigned)(8 * TC2 * ((TR2 + 7) / 8)), 1, (unsigned)ncopy), 256, 0, st>>>(

@@ -15,6 +15,9 @@ namespace qg {
 constexpr int SMALL_R = 128;
 constexpr int NB = 64;
 constexpr int SB = 256;
+// Rows of the largest front: the trailing-update kernels address a front's columns with 32-bit byte
+// offsets (a larger front, 5.6e14 bytes in FP64, would not fit in any memory anyway).
+constexpr int32_t MAX_FRONT_R = (1 << 23) - 1;
 // Chains of small fronts on the narrow upper levels of deep elimination trees
 // (one workgroup per component): levels with fewer than CHAIN_LEVEL_MIN
 // fronts, fronts of at most CHAIN_R rows.
@@ -78,6 +81,16 @@ struct CopyStride {
 __host__ __device__ inline int32_t cone_problem(int32_t t, int32_t l, int32_t l1, int32_t nsoc1, int32_t kb) {
     const int32_t i = t < l ? t / l1 : (nsoc1 > 0 ? (t - l) / nsoc1 : 0);
     return i < kb ? i : kb - 1;
+}
+
+// Value of lane `src` (uniform over the wavefront) of v, for every lane.
+__device__ inline float lane_bcast(float v, int src) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+}
+__device__ inline double lane_bcast(double v, int src) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+    return __hiloint2double(hi, lo);
 }
 
 struct RegParams {

@@ -415,6 +415,7 @@ int build_plan(qg_handle *h) {
         pl.uv_off[s + 1] = pl.uv_off[s] + (r - k);
         pl.max_r = std::max<int32_t>(pl.max_r, (int32_t)r);
     }
+    if (pl.max_r > MAX_FRONT_R) return QG_ERR_SIZE;
     pl.front_total = pl.fr_off[ns];
     pl.uv_total = pl.uv_off[ns];
     pl.dinv_off.assign((size_t)ns + 1, 0);

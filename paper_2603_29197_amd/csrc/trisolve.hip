@@ -190,19 +190,109 @@ __global__ void __launch_bounds__(64 * SW) bwd_small(
 
 // Chains (see factor_chain): one workgroup per component, its levels in
 // order (forward: lowest first; backward: highest first), the fronts of a
-// level one per wavefront, a workgroup barrier between levels.
+// level one per wavefront, a workgroup barrier between levels.  A chain front
+// has at most CHAIN_R = 32 rows, so lane l holds row l in registers: every L
+// entry the lane needs is loaded at once when the front starts (one memory
+// round trip instead of one per elimination step), and the pivot values are
+// broadcast with readlane instead of through LDS, so the elimination steps
+// need no barrier.  Same operations in the same order as fwd_front and
+// bwd_front, hence the same bits.
+template <typename T>
+__device__ inline void fwd_front_chain(int32_t s, const int32_t *__restrict__ sn_first,
+                                       const int64_t *__restrict__ sn_rptr, const int64_t *__restrict__ fr_off,
+                                       const T *__restrict__ front, const int64_t *__restrict__ task0,
+                                       const int64_t *__restrict__ ctb_ptr, const int64_t *__restrict__ ctb_src,
+                                       double *__restrict__ vwork, double *__restrict__ xp) {
+    const int row = threadIdx.x & 63;
+    const int32_t f = sn_first[s];
+    const int32_t r = (int32_t)(sn_rptr[s + 1] - sn_rptr[s]);
+    const int32_t k = sn_first[s + 1] - f;
+    const int64_t t0 = task0[s];
+    const T *F = front + fr_off[s];
+    const bool live = row < r;
+    // L(row, jj) from clamped (always valid) positions, all loads in flight at once: the empty asm
+    // statements need every value in a register, so no load is deferred to its elimination step.
+    // Entries of masked lanes or steps are loaded but never used.
+    const int32_t rowc = min(row, r - 1);
+    T lc[CHAIN_R];
+#pragma unroll
+    for (int jj = 0; jj < CHAIN_R; ++jj) lc[jj] = F[(int64_t)min(jj, k - 1) * r + rowc];
+#pragma unroll
+    for (int jj = 0; jj < CHAIN_R; ++jj) __asm__ volatile("" : "+v"(lc[jj]));
+    double a = 0.0;
+    if (live) {
+        const int64_t tk = t0 + row;
+        a = row < k ? xp[f + row] : 0.0;
+        for (int64_t u = ctb_ptr[tk]; u < ctb_ptr[tk + 1]; ++u) a += vwork[ctb_src[u]];
+    }
+#pragma unroll
+    for (int jj = 0; jj < CHAIN_R; ++jj) {
+        if (jj < k) {                                 // uniform
+            const double yj = lane_bcast(a, jj);
+            if (row > jj && live) a -= (double)lc[jj] * yj;
+        }
+    }
+    if (row < k) xp[f + row] = a;
+    else if (live) vwork[t0 + row] = a;
+}
+
+template <typename T>
+__device__ inline void bwd_front_chain(int32_t s, const int32_t *__restrict__ sn_first,
+                                       const int64_t *__restrict__ sn_rptr, const int32_t *__restrict__ sn_rows,
+                                       const int64_t *__restrict__ fr_off, const T *__restrict__ front,
+                                       double *__restrict__ xp) {
+    const int row = threadIdx.x & 63;
+    const int32_t f = sn_first[s];
+    const int32_t r = (int32_t)(sn_rptr[s + 1] - sn_rptr[s]);
+    const int32_t k = sn_first[s + 1] - f;
+    const T *F = front + fr_off[s];
+    const bool upd = row >= k && row < r;
+    // L(row, c) and L(c, row) from clamped (always valid) positions, all loads in flight at once (see
+    // fwd_front_chain); entries of masked lanes or columns are loaded but never used
+    const int32_t rowc = min(row, r - 1);
+    T lc[CHAIN_R], lr[CHAIN_R];
+#pragma unroll
+    for (int c = 0; c < CHAIN_R; ++c) {
+        const int32_t cc = min(c, k - 1);
+        lc[c] = F[(int64_t)cc * r + rowc];
+        lr[c] = F[(int64_t)rowc * r + cc];
+    }
+#pragma unroll
+    for (int c = 0; c < CHAIN_R; ++c) __asm__ volatile("" : "+v"(lc[c]), "+v"(lr[c]));
+    const double g = upd ? xp[sn_rows[sn_rptr[s] + row]] : 0.0;
+    const double xo = row < k ? xp[f + row] : 0.0;
+    double v = 0.0;
+#pragma unroll
+    for (int c = 0; c < CHAIN_R; ++c) {
+        if (c < k) {                                  // uniform
+            double p = 0.0;
+            p += upd ? (double)lc[c] * g : 0.0;
+            p += 0.0;                                 // the rows l + 64 of bwd_front (none here)
+            for (int off = 32; off > 0; off >>= 1) p += __shfl_xor(p, off);
+            if (row == c) v = xo / (double)lc[c] - p;
+        }
+    }
+#pragma unroll
+    for (int i = CHAIN_R - 1; i >= 0; --i) {
+        if (i < k) {                                  // uniform
+            const double xi = lane_bcast(v, i);
+            if (row < i) v -= (double)lr[i] * xi;
+        }
+    }
+    if (row < k) xp[f + row] = v;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(64 * SW) fwd_chain(
     const int32_t *__restrict__ comp_ptr, const int32_t *__restrict__ grp_ptr, const int32_t *__restrict__ chain_sn,
     const int32_t *__restrict__ sn_first, const int64_t *__restrict__ sn_rptr, const int64_t *__restrict__ fr_off,
     const T *__restrict__ front, const int64_t *__restrict__ task0, const int64_t *__restrict__ ctb_ptr,
     const int64_t *__restrict__ ctb_src, double *__restrict__ vwork, double *__restrict__ xp) {
-    __shared__ double vsh[SW][SMALL_R];
-    const int w = threadIdx.x >> 6;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform: the front indices below too
     const int32_t c = blockIdx.x;
     for (int32_t g = comp_ptr[c]; g < comp_ptr[c + 1]; ++g) {
         for (int32_t t = grp_ptr[g] + w; t < grp_ptr[g + 1]; t += SW)
-            fwd_front<T>(chain_sn[t], sn_first, sn_rptr, fr_off, front, task0, ctb_ptr, ctb_src, vwork, xp, vsh[w]);
+            fwd_front_chain<T>(chain_sn[t], sn_first, sn_rptr, fr_off, front, task0, ctb_ptr, ctb_src, vwork, xp);
         __syncthreads();
     }
 }
@@ -212,12 +302,11 @@ __global__ void __launch_bounds__(64 * SW) bwd_chain(
     const int32_t *__restrict__ comp_ptr, const int32_t *__restrict__ grp_ptr, const int32_t *__restrict__ chain_sn,
     const int32_t *__restrict__ sn_first, const int64_t *__restrict__ sn_rptr, const int32_t *__restrict__ sn_rows,
     const int64_t *__restrict__ fr_off, const T *__restrict__ front, double *__restrict__ xp) {
-    __shared__ double vsh[SW][SMALL_R];
-    const int w = threadIdx.x >> 6;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform: the front indices below too
     const int32_t c = blockIdx.x;
     for (int32_t g = comp_ptr[c + 1] - 1; g >= comp_ptr[c]; --g) {
         for (int32_t t = grp_ptr[g] + w; t < grp_ptr[g + 1]; t += SW)
-            bwd_front<T>(chain_sn[t], sn_first, sn_rptr, sn_rows, fr_off, front, xp, vsh[w]);
+            bwd_front_chain<T>(chain_sn[t], sn_first, sn_rptr, sn_rows, fr_off, front, xp);
         __syncthreads();
     }
 }

@@ -47,7 +47,10 @@ PEAK_GBS = 8000.0
 # HBM bytes per launch of trail_update on the benchmark workload, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs, each scaled by what the counter reads for a plain device copy of known size.
 # Counters describe one build of the kernel and one workload: None until they are taken for both.
-TRAFFIC_BYTES_PER_LAUNCH = {"fp32": None, "fp64": None}
+# HBM bytes per launch of the FP32 128x128 kernel on the default workload: FETCH_SIZE + WRITE_SIZE, each scaled
+# by its reading for a 256 MiB device copy (rocprofv3 counter runs of this bench; null once the kernel or the
+# workload changes)
+TRAFFIC_BYTES_PER_LAUNCH = {"fp32": 2.156e9, "fp64": None}
 WORKLOAD = "huber_l"
 WORKLOAD_TEXT = ("Huber QP (large-QP configuration's generator) F 100000x40000, 40 nnz per row, 5% outliers "
                  "(n=340000, p=100000, m=200000, N_K=640000); the configuration's F 500000x200000 needs "
@@ -219,7 +222,10 @@ def run_config(qg, torch, name, warmup, steps, backward=False):
         res[tag] = {"newton_step_ms": round(med([i["ms_step_median"] for i in infos]), 3),
                     "solve_s": round(med([i["ms_solve"] for i in infos]) / 1e3, 4), "iters": last["iters"],
                     "switch_iter": last["switch_iter"], "ir_steps": last["ir_steps"],
-                    "factor_ms_total": round(last["ms_factor"], 2), "trisolve_ir_ms_total": round(last["ms_trisolve"], 2),
+                    "factor_ms_total": round(last["ms_factor"], 2), "nfactor": last["nfactor"],
+                    "factor_flops": last["factor_flops"], "nnz_L": last["nnz_L"],
+                    "ntrisolve": list(last["ntrisolve"]), "nresidual": last["nresidual"],
+                    "trisolve_ir_ms_total": round(last["ms_trisolve"], 2),
                     "cone_ms_total": round(last["ms_cone"], 2), "status": last["status_name"],
                     "pres": last["pres"], "dres": last["dres"], "gap": last["gap"]}
         log(f"[bench] {name} {tag}: step {res[tag]['newton_step_ms']} ms solve {res[tag]['solve_s']} s "
@@ -414,12 +420,14 @@ def main():
                     "solve_s": round(inf32["ms_solve"] / 1e3, 3), "iters": inf32["iters"],
                     "switch_iter": inf32["switch_iter"], "ir_steps": inf32["ir_steps"],
                     "step_ms_fp32_iters": round(inf32["ms_step_median_fp32"], 3), "status": inf32["status_name"],
-                    "factor_ms_total": round(inf32["ms_factor"], 2), "pres": inf32["pres"], "dres": inf32["dres"],
+                    "factor_ms_total": round(inf32["ms_factor"], 2), "nfactor": inf32["nfactor"],
+                    "pres": inf32["pres"], "dres": inf32["dres"],
                     "gap": inf32["gap"], "pobj": inf32["pobj"]},
         "fp64": {"newton_step_ms": round(step64, 3), "step_ms_p90": round(float(np.percentile(t64, 90)), 3),
                  "ms_per_step": round(1e3 * wall64 / max(1, args.steps), 2), "timed_solves": len(i64),
                  "solve_s": round(inf64["ms_solve"] / 1e3, 3), "iters": inf64["iters"], "status": inf64["status_name"],
-                 "factor_ms_total": round(inf64["ms_factor"], 2), "pres": inf64["pres"], "dres": inf64["dres"],
+                 "factor_ms_total": round(inf64["ms_factor"], 2), "nfactor": inf64["nfactor"],
+                 "pres": inf64["pres"], "dres": inf64["dres"],
                  "gap": inf64["gap"], "pobj": inf64["pobj"]},
         "speedup_fp32ir_vs_fp64_step": round(step64 / step32, 3) if step32 > 0 else None,
         "speedup_fp32ir_vs_fp64_solve": round(inf64["ms_solve"] / inf32["ms_solve"], 3) if inf32["ms_solve"] > 0 else None,

@@ -155,18 +155,18 @@ __global__ void __launch_bounds__(256) factor_small(
 
 // Chains (the narrow upper levels of deep elimination trees): one workgroup
 // per component walks the component's levels; the fronts of a level are
-// factored one per wavefront with the same arithmetic as factor_small (pivot,
-// rank-1 update of the trailing lower part, column scaling).  A front is
-// assembled in the wavefront's LDS tile from the entries of the numeric
-// assembly map (the same sources in the same order as gather_entries: the K
-// entry, the static regularization of a pivot diagonal, then the children's
-// update entries); then each lane takes one row (a chain front has at most
-// CHAIN_R = 32 rows) into registers and the pivot steps run there, with the
-// pivot column broadcast by readlane, so a step costs a few instructions
-// instead of LDS round trips and barriers.  Children below the chain levels
-// were factored by the level kernels before this launch; children inside the
-// component by this workgroup, before the workgroup barrier that ends their
-// level.
+// factored one per wavefront, each in its own LDS tile, with the same
+// arithmetic as factor_small (pivot, rank-1 update of the trailing lower
+// part, column scaling), the steps separated by wavefront barriers only (the
+// LDS operations of one wavefront complete in order).  A front is assembled
+// in its tile from the entries of the numeric assembly map (the same sources
+// in the same order as gather_entries: the K entry, the static regularization
+// of a pivot diagonal, then the children's update entries).  Children below
+// the chain levels were factored by the level kernels before this launch;
+// children inside the component by this workgroup, before the workgroup
+// barrier that ends their level.  (Keeping one row per lane in registers was
+// measured slower: the update of a 32-row front then costs each lane up to 31
+// divisions per pivot instead of about R*R/128.)
 template <typename T>
 __global__ void __launch_bounds__(256) factor_chain(
     const int32_t *__restrict__ comp_ptr, const int32_t *__restrict__ grp_ptr, const int32_t *__restrict__ chain_sn,
@@ -176,6 +176,7 @@ __global__ void __launch_bounds__(256) factor_chain(
     const int64_t *__restrict__ fr_off, T *__restrict__ front, const int8_t *__restrict__ kind, double eps,
     double dyn, int32_t *nreg) {
     __shared__ T tile[4][CHAIN_R * CHAIN_R];
+    __shared__ T dsh[4];
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform: the front indices below too
     const int lane = threadIdx.x & 63;
     T *F = tile[w];
@@ -203,39 +204,29 @@ __global__ void __launch_bounds__(256) factor_chain(
                 F[dst[e] - base] = v;
             }
             __builtin_amdgcn_wave_barrier();
-            // lane l holds row l of the assembled front (columns 0 .. CHAIN_R - 1, clamped reads; lanes
-            // and columns past r hold values that are never used) and runs the k pivot steps in registers,
-            // the pivot column's entries broadcast with readlane: the same operations in the same order as
-            // factor_front_lds (pivot, rank-1 update of the trailing lower part, column scaling)
-            const int row = lane;
-            const int32_t rowc = min(row, r - 1);
-            const bool live = row < r;
-            T a[CHAIN_R];
-#pragma unroll
-            for (int c = 0; c < CHAIN_R; ++c) a[c] = F[min(c, r - 1) * r + rowc];
-#pragma unroll
-            for (int jj = 0; jj < CHAIN_R; ++jj) {
-                if (jj < k) {                               // uniform
-                    const T raw = lane_bcast(a[jj], jj);
-                    const double sg = pivot_sign(kd_s[jj]);
-                    const bool fix = !(sg * (double)raw > eps);  // also catches NaN
-                    const T d = fix ? (T)(sg * dyn) : raw;
-                    if (fix && lane == 0) atomicAdd(nreg, 1);
-                    if (row == jj) a[jj] = d;
-#pragma unroll
-                    for (int c = jj + 1; c < CHAIN_R; ++c) {
-                        if (c < r) {                        // uniform
-                            const T b = lane_bcast(a[jj], c);
-                            if (row >= c && live) a[c] -= a[jj] * b / d;
-                        }
-                    }
-                    if (row > jj && live) a[jj] /= d;
+            for (int32_t jj = 0; jj < k; ++jj) {
+                if (lane == 0) {
+                    const T d = regularize(F[jj * r + jj], kd_s[jj], eps, dyn, nreg);
+                    F[jj * r + jj] = d;
+                    dsh[w] = d;
                 }
+                __builtin_amdgcn_wave_barrier();
+                const T d = dsh[w];
+                const int32_t R = r - jj - 1;
+                for (int32_t idx = lane; idx < R * R; idx += 64) {
+                    const int32_t i = jj + 1 + idx % R, cc = jj + 1 + idx / R;
+                    if (i >= cc) F[cc * r + i] -= F[jj * r + i] * F[jj * r + cc] / d;
+                }
+                __builtin_amdgcn_wave_barrier();
+                for (int32_t i = jj + 1 + lane; i < r; i += 64) F[jj * r + i] /= d;
+                __builtin_amdgcn_wave_barrier();
             }
             T *G = front + base;
-#pragma unroll
-            for (int c = 0; c < CHAIN_R; ++c)
-                if (c < r && row >= c && live) G[(int64_t)c * r + row] = a[c];
+            for (int32_t idx = lane; idx < r * r; idx += 64) {
+                const int32_t i = idx % r, cc = idx / r;
+                if (i >= cc) G[idx] = F[idx];
+            }
+            __builtin_amdgcn_wave_barrier();
         }
         __syncthreads();
     }

@@ -282,6 +282,50 @@ __device__ inline void bwd_front_chain(int32_t s, const int32_t *__restrict__ sn
     if (row < k) xp[f + row] = v;
 }
 
+// Static data of one chain front for the forward solve, per lane (row): everything that does not
+// depend on the solve's progress (the L entries, the front's own right-hand side entry, the range of
+// the row's contributions in the work vector and the positions of its first two).
+template <typename T>
+struct FwdStatic {
+    int32_t f, r, k;
+    int64_t t0;
+    T lc[CHAIN_R];
+    double xr;
+    int64_t u0, u1, q0, q1;
+};
+
+// Issue the loads of front s's static data (s < 0: none).  The positions q0 and q1 need u0 and u1,
+// so they are completed by fwd_static_sources once those have arrived.
+template <typename T>
+__device__ inline void fwd_static_load(FwdStatic<T> &st, int32_t s, const int32_t *__restrict__ sn_first,
+                                       const int64_t *__restrict__ sn_rptr, const int64_t *__restrict__ fr_off,
+                                       const T *__restrict__ front, const int64_t *__restrict__ task0,
+                                       const int64_t *__restrict__ ctb_ptr, const double *__restrict__ xp) {
+    if (s < 0) return;
+    const int row = threadIdx.x & 63;
+    st.f = sn_first[s];
+    st.k = sn_first[s + 1] - st.f;
+    st.r = (int32_t)(sn_rptr[s + 1] - sn_rptr[s]);
+    st.t0 = task0[s];
+    const T *F = front + fr_off[s];
+    const int32_t rowc = min(row, st.r - 1);
+#pragma unroll
+    for (int jj = 0; jj < CHAIN_R; ++jj) st.lc[jj] = F[(int64_t)min(jj, st.k - 1) * st.r + rowc];
+    st.xr = xp[st.f + min(row, st.k - 1)];
+    st.u0 = ctb_ptr[st.t0 + rowc];
+    st.u1 = ctb_ptr[st.t0 + rowc + 1];
+}
+template <typename T>
+__device__ inline void fwd_static_sources(FwdStatic<T> &st, int32_t s, const int64_t *__restrict__ ctb_src) {
+    if (s < 0) return;
+    st.q0 = st.u0 < st.u1 ? ctb_src[st.u0] : 0;
+    st.q1 = st.u0 + 1 < st.u1 ? ctb_src[st.u0 + 1] : 0;
+}
+
+// Chains, forward, one level ahead: while a wavefront solves its front of level g, the static data
+// of its front of level g + 1 is in flight, so after the level's barrier only the children's
+// update-vector entries remain to be read.  Further fronts of a level (more than SW of them) go
+// through fwd_front_chain.  Same operations in the same order as fwd_front.
 template <typename T>
 __global__ void __launch_bounds__(64 * SW) fwd_chain(
     const int32_t *__restrict__ comp_ptr, const int32_t *__restrict__ grp_ptr, const int32_t *__restrict__ chain_sn,
@@ -289,25 +333,136 @@ __global__ void __launch_bounds__(64 * SW) fwd_chain(
     const T *__restrict__ front, const int64_t *__restrict__ task0, const int64_t *__restrict__ ctb_ptr,
     const int64_t *__restrict__ ctb_src, double *__restrict__ vwork, double *__restrict__ xp) {
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform: the front indices below too
+    const int row = threadIdx.x & 63;
     const int32_t c = blockIdx.x;
-    for (int32_t g = comp_ptr[c]; g < comp_ptr[c + 1]; ++g) {
-        for (int32_t t = grp_ptr[g] + w; t < grp_ptr[g + 1]; t += SW)
+    const int32_t g0 = comp_ptr[c], g1 = comp_ptr[c + 1];
+    auto first = [&](int32_t g) {                     // this wavefront's first front of level g, or -1
+        if (g >= g1) return -1;
+        const int32_t t = grp_ptr[g] + w;
+        return t < grp_ptr[g + 1] ? chain_sn[t] : -1;
+    };
+    FwdStatic<T> cur, nxt;
+    int32_t s_cur = first(g0);
+    fwd_static_load<T>(cur, s_cur, sn_first, sn_rptr, fr_off, front, task0, ctb_ptr, xp);
+    fwd_static_sources<T>(cur, s_cur, ctb_src);
+    for (int32_t g = g0; g < g1; ++g) {
+        double v0 = 0.0, v1 = 0.0;
+        if (s_cur >= 0) {                             // the children's entries (written before the last barrier)
+            if (cur.u0 < cur.u1) v0 = vwork[cur.q0];
+            if (cur.u0 + 1 < cur.u1) v1 = vwork[cur.q1];
+        }
+        const int32_t s_nxt = first(g + 1);
+        fwd_static_load<T>(nxt, s_nxt, sn_first, sn_rptr, fr_off, front, task0, ctb_ptr, xp);
+        if (s_cur >= 0) {
+            const bool live = row < cur.r;
+            double a = row < cur.k ? cur.xr : 0.0;
+            if (cur.u0 < cur.u1) a += v0;
+            if (cur.u0 + 1 < cur.u1) a += v1;
+            for (int64_t u = cur.u0 + 2; u < cur.u1; ++u) a += vwork[ctb_src[u]];
+            if (!live) a = 0.0;
+#pragma unroll
+            for (int jj = 0; jj < CHAIN_R; ++jj) {
+                if (jj < cur.k) {                         // uniform
+                    const double yj = lane_bcast(a, jj);
+                    if (row > jj && live) a -= (double)cur.lc[jj] * yj;
+                }
+            }
+            if (row < cur.k) xp[cur.f + row] = a;
+            else if (live) vwork[cur.t0 + row] = a;
+        }
+        fwd_static_sources<T>(nxt, s_nxt, ctb_src);
+        for (int32_t t = grp_ptr[g] + w + SW; t < grp_ptr[g + 1]; t += SW)
             fwd_front_chain<T>(chain_sn[t], sn_first, sn_rptr, fr_off, front, task0, ctb_ptr, ctb_src, vwork, xp);
         __syncthreads();
+        s_cur = s_nxt;
+        cur = nxt;
     }
 }
 
+// Static data of one chain front for the backward solve, per lane (row): the L entries of its row and
+// column, the work-vector position of its update row, and its own entry of the forward result.
+template <typename T>
+struct BwdStatic {
+    int32_t f, r, k;
+    T lc[CHAIN_R], lr[CHAIN_R];
+    int32_t gi;
+    double xo;
+};
+
+template <typename T>
+__device__ inline void bwd_static_load(BwdStatic<T> &st, int32_t s, const int32_t *__restrict__ sn_first,
+                                       const int64_t *__restrict__ sn_rptr, const int32_t *__restrict__ sn_rows,
+                                       const int64_t *__restrict__ fr_off, const T *__restrict__ front,
+                                       const double *__restrict__ xp) {
+    if (s < 0) return;
+    const int row = threadIdx.x & 63;
+    st.f = sn_first[s];
+    st.k = sn_first[s + 1] - st.f;
+    st.r = (int32_t)(sn_rptr[s + 1] - sn_rptr[s]);
+    const T *F = front + fr_off[s];
+    const int32_t rowc = min(row, st.r - 1);
+#pragma unroll
+    for (int c = 0; c < CHAIN_R; ++c) {
+        const int32_t cc = min(c, st.k - 1);
+        st.lc[c] = F[(int64_t)cc * st.r + rowc];
+        st.lr[c] = F[(int64_t)rowc * st.r + cc];
+    }
+    st.gi = sn_rows[sn_rptr[s] + rowc];
+    st.xo = xp[st.f + min(row, st.k - 1)];
+}
+
+// Chains, backward, one level ahead (see fwd_chain): after the level's barrier only the solution
+// entries of the front's update rows (solved by its ancestors) remain to be read.  Same operations in
+// the same order as bwd_front.
 template <typename T>
 __global__ void __launch_bounds__(64 * SW) bwd_chain(
     const int32_t *__restrict__ comp_ptr, const int32_t *__restrict__ grp_ptr, const int32_t *__restrict__ chain_sn,
     const int32_t *__restrict__ sn_first, const int64_t *__restrict__ sn_rptr, const int32_t *__restrict__ sn_rows,
     const int64_t *__restrict__ fr_off, const T *__restrict__ front, double *__restrict__ xp) {
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform: the front indices below too
+    const int row = threadIdx.x & 63;
     const int32_t c = blockIdx.x;
-    for (int32_t g = comp_ptr[c + 1] - 1; g >= comp_ptr[c]; --g) {
-        for (int32_t t = grp_ptr[g] + w; t < grp_ptr[g + 1]; t += SW)
+    const int32_t g0 = comp_ptr[c], g1 = comp_ptr[c + 1];
+    auto first = [&](int32_t g) {                     // this wavefront's first front of level g, or -1
+        if (g < g0) return -1;
+        const int32_t t = grp_ptr[g] + w;
+        return t < grp_ptr[g + 1] ? chain_sn[t] : -1;
+    };
+    BwdStatic<T> cur, nxt;
+    int32_t s_cur = first(g1 - 1);
+    bwd_static_load<T>(cur, s_cur, sn_first, sn_rptr, sn_rows, fr_off, front, xp);
+    for (int32_t g = g1 - 1; g >= g0; --g) {
+        double gv = 0.0;
+        const bool upd = s_cur >= 0 && row >= cur.k && row < cur.r;
+        if (upd) gv = xp[cur.gi];                     // solved by the ancestors, before the last barrier
+        const int32_t s_nxt = first(g - 1);
+        bwd_static_load<T>(nxt, s_nxt, sn_first, sn_rptr, sn_rows, fr_off, front, xp);
+        if (s_cur >= 0) {
+            double v = 0.0;
+#pragma unroll
+            for (int cc = 0; cc < CHAIN_R; ++cc) {
+                if (cc < cur.k) {                         // uniform
+                    double p = 0.0;
+                    p += upd ? (double)cur.lc[cc] * gv : 0.0;
+                    p += 0.0;                             // the rows l + 64 of bwd_front (none here)
+                    for (int off = 32; off > 0; off >>= 1) p += __shfl_xor(p, off);
+                    if (row == cc) v = cur.xo / (double)cur.lc[cc] - p;
+                }
+            }
+#pragma unroll
+            for (int i = CHAIN_R - 1; i >= 0; --i) {
+                if (i < cur.k) {                          // uniform
+                    const double xi = lane_bcast(v, i);
+                    if (row < i) v -= (double)cur.lr[i] * xi;
+                }
+            }
+            if (row < cur.k) xp[cur.f + row] = v;
+        }
+        for (int32_t t = grp_ptr[g] + w + SW; t < grp_ptr[g + 1]; t += SW)
             bwd_front_chain<T>(chain_sn[t], sn_first, sn_rptr, sn_rows, fr_off, front, xp);
         __syncthreads();
+        s_cur = s_nxt;
+        cur = nxt;
     }
 }
 

@@ -10,7 +10,9 @@ implements independently; the two must agree bit for bit:
     ordered last, by increasing index;
  3. minimum degree on the quotient graph with supervariables and the
     approximate (upper-bound) external degree of Amestoy, Davis and Duff
-    (rule written out in ``or_min_degree``);
+    (rule written out in ``or_min_degree``); or, as the alternative ordering,
+    nested dissection by breadth-first level structures with minimum degree
+    on its pieces (``nested_dissection``);
  4. postorder of the elimination tree of the minimum-degree order (depth
     first, children and roots by increasing index), composed with it;
  5. elimination tree, column counts and the strictly-lower pattern of L for
@@ -259,8 +261,119 @@ def supernode_rows(sptr, Lp, Li):
     return ptr, rows
 
 
-def order(Ku: sp.csc_matrix) -> np.ndarray:
-    """Steps 1-4: the final fill-reducing permutation (perm[k] = original node)."""
+ND_LEAF = 256      # nested dissection: pieces of at most this many nodes go to minimum degree
+
+
+def induced(graph: sp.csc_matrix, S: np.ndarray) -> sp.csc_matrix:
+    """Subgraph induced by the ascending node list S; local node i is S[i]."""
+    N = graph.shape[0]
+    loc = np.full(N, -1, dtype=np.int64)
+    loc[S] = np.arange(len(S))
+    rows, cols = [], []
+    for i, v in enumerate(S):
+        nb = loc[graph.indices[graph.indptr[v]:graph.indptr[v + 1]]]
+        nb = nb[nb >= 0]
+        rows.append(nb)
+        cols.append(np.full(len(nb), i, dtype=np.int64))
+    r = np.concatenate(rows) if rows else np.zeros(0, dtype=np.int64)
+    c = np.concatenate(cols) if cols else np.zeros(0, dtype=np.int64)
+    sub = sp.csc_matrix((np.ones(len(r)), (r, c)), shape=(len(S), len(S)))
+    sub.sort_indices()
+    return sub
+
+
+def bfs_levels(graph: sp.csc_matrix, inside: np.ndarray, root: int) -> list:
+    """Breadth-first level structure from ``root`` within the nodes where
+    ``inside`` is true: a list of ascending arrays, level 0 = [root]."""
+    seen = np.zeros(graph.shape[0], dtype=bool)
+    seen[root] = True
+    levels = [np.array([root], dtype=np.int64)]
+    while True:
+        nxt = []
+        for v in levels[-1]:
+            nb = graph.indices[graph.indptr[v]:graph.indptr[v + 1]]
+            nb = nb[inside[nb] & ~seen[nb]]
+            seen[nb] = True
+            nxt.append(nb)
+        nxt = np.sort(np.concatenate(nxt)) if nxt else np.zeros(0, dtype=np.int64)
+        if len(nxt) == 0:
+            return levels
+        levels.append(nxt.astype(np.int64))
+
+
+def nested_dissection(graph: sp.csc_matrix) -> np.ndarray:
+    """Automatic nested dissection by breadth-first level structures (George
+    and Liu, Computer Solution of Large Sparse Positive Definite Systems,
+    1981, ch. 8) with minimum degree on the small pieces.  ND(S), S ascending:
+
+      a. |S| <= ND_LEAF: minimum degree on the subgraph induced by S;
+      b. S not connected: ND of each component, by increasing least node;
+      c. level structure from the least node of S; while the node of its
+         last level with least (degree within S, index) roots a structure
+         with more levels, that one replaces it;
+      d. h levels, h < 3: as a; else m = h // 2, separator = nodes of level m
+         with a neighbour in level m + 1, A = levels < m and the rest of
+         level m, B = levels > m; order ND(A), ND(B), separator ascending.
+    """
+    N = graph.shape[0]
+    out = []
+
+    def leaf(S):
+        out.extend(S[min_degree(induced(graph, S))].tolist())
+
+    def nd(S):
+        if len(S) == 0:
+            return
+        if len(S) <= ND_LEAF:
+            leaf(S)
+            return
+        inside = np.zeros(N, dtype=bool)
+        inside[S] = True
+        levels = bfs_levels(graph, inside, int(S[0]))
+        if sum(len(x) for x in levels) < len(S):
+            done = np.zeros(N, dtype=bool)
+            comps = []
+            for v in S:
+                if not done[v]:
+                    comp = np.sort(np.concatenate(bfs_levels(graph, inside, int(v))))
+                    done[comp] = True
+                    comps.append(comp)
+            for comp in comps:
+                nd(comp)
+            return
+        while True:
+            last = levels[-1]
+            deg = np.array([np.count_nonzero(inside[graph.indices[graph.indptr[v]:graph.indptr[v + 1]]])
+                            for v in last])
+            v = int(last[np.lexsort((last, deg))[0]])
+            cand = bfs_levels(graph, inside, v)
+            if len(cand) > len(levels):
+                levels = cand
+            else:
+                break
+        h = len(levels)
+        if h < 3:
+            leaf(S)
+            return
+        m = h // 2
+        nextlev = np.zeros(N, dtype=bool)
+        nextlev[levels[m + 1]] = True
+        touches = np.array([nextlev[graph.indices[graph.indptr[v]:graph.indptr[v + 1]]].any()
+                            for v in levels[m]], dtype=bool)
+        sep = levels[m][touches]
+        A = np.sort(np.concatenate(levels[:m] + [levels[m][~touches]]))
+        B = np.sort(np.concatenate(levels[m + 1:]))
+        nd(A)
+        nd(B)
+        out.extend(np.sort(sep).tolist())
+
+    nd(np.arange(N, dtype=np.int64))
+    return np.array(out, dtype=np.int64)
+
+
+def order(Ku: sp.csc_matrix, ordering: str = "md") -> np.ndarray:
+    """Steps 1-4: the final fill-reducing permutation (perm[k] = original node).
+    ``ordering`` "nd" replaces step 3 by ``nested_dissection``."""
     N = Ku.shape[0]
     g = sym_graph(Ku)
     deg = np.diff(g.indptr)
@@ -268,16 +381,16 @@ def order(Ku: sp.csc_matrix) -> np.ndarray:
     keep = np.flatnonzero(~dense)
     sub = g[keep][:, keep].tocsc()
     sub.sort_indices()
-    md_sub = min_degree(sub)
+    md_sub = nested_dissection(sub) if ordering == "nd" else min_degree(sub)
     md = np.concatenate([keep[md_sub], np.flatnonzero(dense)]).astype(np.int64)
     par = etree(permute_upper(Ku, md))
     post = postorder(par)
     return md[post]
 
 
-def analyze(Ku: sp.csc_matrix) -> Pattern:
+def analyze(Ku: sp.csc_matrix, ordering: str = "md") -> Pattern:
     N = Ku.shape[0]
-    perm = order(Ku)
+    perm = order(Ku, ordering)
     iperm = np.empty(N, dtype=np.int64)
     iperm[perm] = np.arange(N)
     Up = permute_upper(Ku, perm)

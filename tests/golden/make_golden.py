@@ -4,7 +4,7 @@ lists) for the named workloads, so that the library's analysis can be
 compared bit for bit at sizes where the oracle's plain ordering takes
 minutes.  Calls only the oracle and the input generators.
 
-usage: python tests/golden/make_golden.py [workload ...]
+usage: python tests/golden/make_golden.py [workload[@nd] ...]
 """
 import hashlib
 import json
@@ -27,11 +27,13 @@ def digest(a, dtype):
     return hashlib.sha256(np.ascontiguousarray(a, dtype=dtype).tobytes()).hexdigest()
 
 
-def pattern_record(name):
+def pattern_record(key):
+    # "name" is the minimum-degree analysis of a workload, "name@nd" its nested-dissection analysis
+    name, _, ordering = key.partition("@")
     prob = problems.workload(name)
     t = time.time()
-    pat = symbolic.analyze(kkt.kkt_pattern(prob))
-    if name in ("lasso", "huber_l"):
+    pat = symbolic.analyze(kkt.kkt_pattern(prob), ordering or "md")
+    if key in ("lasso", "huber_l"):
         # the oracle's ordering of a benchmark workload, for the CPU-baseline
         # leg of the benchmark (which then needs only the fast symbolic steps)
         np.save(os.path.join(os.path.dirname(OUT), f"{name}_perm.npy"), pat.perm.astype(np.int32))

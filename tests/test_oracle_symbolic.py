@@ -262,3 +262,152 @@ def test_relaxed_supernodes_are_the_greedy_partition(name):
         if k1 < len(fund):
             assert not extends(group, fund[k1]), (g, k1)
     assert merges > 0
+
+
+# ----------------------------------------------------------------------------------------------
+# nested dissection
+# ----------------------------------------------------------------------------------------------
+def path_graph(N):
+    i = np.arange(N - 1)
+    return symbolic.sym_graph(sp.csc_matrix((np.ones(N - 1), (i, i + 1)), shape=(N, N)))
+
+
+def grid_graph(k):
+    """k x k grid, node i*k + j, 4-neighbour edges."""
+    r, c = [], []
+    for i in range(k):
+        for j in range(k):
+            v = i * k + j
+            if j + 1 < k:
+                r.append(v); c.append(v + 1)
+            if i + 1 < k:
+                r.append(v); c.append(v + k)
+    return symbolic.sym_graph(sp.csc_matrix((np.ones(len(r)), (r, c)), shape=(k * k, k * k)))
+
+
+def etree_height(graph, order):
+    """Height of the elimination tree of the graph's matrix in the given order."""
+    N = graph.shape[0]
+    pos = np.empty(N, dtype=np.int64)
+    pos[order] = np.arange(N)
+    G = graph.tocoo()
+    keep = pos[G.row] < pos[G.col]
+    U = sp.csc_matrix((np.ones(int(keep.sum())), (pos[G.row[keep]], pos[G.col[keep]])), shape=(N, N))
+    U = (U + sp.identity(N)).tocsc()
+    U.sort_indices()
+    parent = symbolic.etree(U)
+    h = np.zeros(N, dtype=np.int64)
+    for j in range(N):
+        if parent[j] >= 0:
+            h[parent[j]] = max(h[parent[j]], h[j] + 1)
+    return int(h.max()), parent
+
+
+def test_nd_on_a_path_is_recursive_bisection():
+    """On the path 0-1-...-(N-1) the level structure from node 0 is the path itself (the far end
+    roots no longer one), so each piece [a, b) splits at its middle node a + (b-a)//2, which is
+    ordered after both halves; pieces of at most ND_LEAF nodes are paths ordered by minimum
+    degree."""
+    def expected(a, b):
+        n = b - a
+        if n == 0:
+            return []
+        if n <= symbolic.ND_LEAF:
+            return [a + int(i) for i in symbolic.min_degree(path_graph(n))]
+        m = n // 2
+        return expected(a, a + m) + expected(a + m + 1, b) + [a + m]
+
+    for N in (257, 600, 3001):
+        got = symbolic.nested_dissection(path_graph(N))
+        assert got.tolist() == expected(0, N)
+
+
+def test_nd_balanced_tree_on_a_path(monkeypatch):
+    """With pieces of one node, the path of 2^t - 1 nodes is cut into halves t - 1 times: its
+    elimination tree is the complete binary tree of height t - 1 with 2^(t-1) leaves (pieces of
+    two nodes have fewer than 3 levels and go to minimum degree: a 2-node chain)."""
+    monkeypatch.setattr(symbolic, "ND_LEAF", 1)
+    t = 10
+    N = 2 ** t - 1
+    g = path_graph(N)
+    order = symbolic.nested_dissection(g)
+    assert sorted(order.tolist()) == list(range(N))
+    h, parent = etree_height(g, order)
+    assert h == t - 1
+    nchild = np.bincount(parent[parent >= 0], minlength=N)
+    assert int(np.count_nonzero(nchild == 0)) == 2 ** (t - 1)
+    # minimum degree on the same path gives a deeper tree
+    assert etree_height(g, symbolic.min_degree(g))[0] > h
+
+
+def test_nd_grid_top_separator_is_the_antidiagonal():
+    """k x k grid with k*k > ND_LEAF: the levels from corner 0 are the anti-diagonals i + j = d
+    (the opposite corner roots as many, 2k - 1), so the middle level is i + j = k - 1, every node
+    of which touches the next level: it is the separator, ordered last; the two triangles before
+    it are pieces of k(k-1)/2 <= ND_LEAF nodes, each ordered by minimum degree."""
+    k = 20
+    g = grid_graph(k)
+    order = symbolic.nested_dissection(g)
+    ij = [(v // k, v % k) for v in range(k * k)]
+    A = np.array([v for v, (i, j) in enumerate(ij) if i + j < k - 1])
+    B = np.array([v for v, (i, j) in enumerate(ij) if i + j > k - 1])
+    sep = np.array([v for v, (i, j) in enumerate(ij) if i + j == k - 1])
+    gA = g[A][:, A].tocsc(); gA.sort_indices()
+    gB = g[B][:, B].tocsc(); gB.sort_indices()
+    want = np.concatenate([A[symbolic.min_degree(gA)], B[symbolic.min_degree(gB)], sep])
+    assert order.tolist() == want.tolist()
+
+
+def test_nd_top_split_from_distances(monkeypatch):
+    """Random connected graphs, top level re-derived from all-pairs distances (scipy's
+    unweighted shortest paths) instead of level structures: the root is walked to a node of
+    greater eccentricity as the rule says, the separator is the distance-m shell's nodes with a
+    neighbour at distance m + 1, and the order is A's nodes, then B's, then the separator
+    ascending; no edge joins A and B."""
+    monkeypatch.setattr(symbolic, "ND_LEAF", 8)
+    from scipy.sparse.csgraph import shortest_path
+    for seed in range(8):
+        rng = np.random.default_rng(300 + seed)
+        N = 60 + 15 * seed
+        U = random_sym_upper(N, 1.5 / N, 300 + seed).tolil()
+        chain = rng.permutation(N)                      # a Hamiltonian path keeps it connected
+        for a, b in zip(chain[:-1], chain[1:]):
+            U[min(a, b), max(a, b)] = 1.0
+        U = sp.csc_matrix(U)
+        g = symbolic.sym_graph(U)
+        D = shortest_path(g, unweighted=True)
+        deg = np.diff(g.indptr)
+        r = 0
+        while True:
+            far = np.flatnonzero(D[r] == D[r].max())
+            v = int(far[np.lexsort((far, deg[far]))[0]])
+            if D[v].max() > D[r].max():
+                r = v
+            else:
+                break
+        h = int(D[r].max()) + 1
+        m = h // 2
+        shell = np.flatnonzero(D[r] == m)
+        sep = np.array([v for v in shell
+                        if np.any(D[r][g.indices[g.indptr[v]:g.indptr[v + 1]]] == m + 1)])
+        A = np.setdiff1d(np.flatnonzero(D[r] <= m), sep)
+        B = np.flatnonzero(D[r] > m)
+        order = symbolic.nested_dissection(g)
+        assert sorted(order.tolist()) == list(range(N))
+        assert sorted(order[:len(A)].tolist()) == A.tolist()
+        assert sorted(order[len(A):len(A) + len(B)].tolist()) == B.tolist()
+        assert order[len(A) + len(B):].tolist() == sep.tolist()
+        Gd = g.toarray() != 0
+        assert not Gd[np.ix_(A, B)].any()
+
+
+def test_nd_reduces_tree_height_on_a_band():
+    """A long band (windowed many-SOC pattern): nested dissection's elimination tree is far
+    shallower than minimum degree's, which follows the band."""
+    prob = problems.many_soc(n=6000, ncones=2000, q=4, nbounds=2000, seed=77)
+    Ku = kkt.kkt_pattern(prob)
+    pm = symbolic.analyze(Ku)
+    pn = symbolic.analyze(Ku, "nd")
+    hm = etree_height(symbolic.sym_graph(Ku), pm.perm)[0]
+    hn = etree_height(symbolic.sym_graph(Ku), pn.perm)[0]
+    assert hn * 2 < hm

@@ -200,14 +200,16 @@ def oracle_errors(qg, name, precisions):
     return out
 
 
-def run_config(qg, torch, name, warmup, steps, backward=False):
+def run_config(qg, torch, name, warmup, steps, backward=False, ordering=0, prob=None):
     """Another configuration: FP32+IR and FP64 full solves (same warmup and count), median
     Newton-step ms, solve seconds, and the agreement of the two modes."""
     from synth import problems
-    prob = problems.workload(name)
+    prob = prob if prob is not None else problems.workload(name)
     t0 = time.perf_counter()
-    S = qg.Solver(prob, differentiable=1 if backward else 0)
-    res = {"setup_s": round(time.perf_counter() - t0, 2), "N_K": prob.n + prob.m + prob.p}
+    S = qg.Solver(prob, differentiable=1 if backward else 0, ordering=ordering)
+    res = {"setup_s": round(time.perf_counter() - t0, 2), "N_K": prob.n + prob.m + prob.p,
+           "ordering": "nested dissection" if ordering == qg.QG_ORDER_ND else "minimum degree",
+           "analysis_s": None}
     xs = {}
     for tag, prec in (("fp32_ir", qg.QG_FP32_IR), ("fp64", qg.QG_FP64)):
         S.set_settings(precision=prec)
@@ -218,6 +220,7 @@ def run_config(qg, torch, name, warmup, steps, backward=False):
             x, _, _, _, info = S.solve()
             infos.append(info)
         last = infos[-1]
+        res["analysis_s"] = round(last["ms_analyze"] / 1e3, 2)
         xs[tag] = (x.cpu().numpy(), last["pobj"])
         res[tag] = {"newton_step_ms": round(med([i["ms_step_median"] for i in infos]), 3),
                     "solve_s": round(med([i["ms_solve"] for i in infos]) / 1e3, 4), "iters": last["iters"],
@@ -258,6 +261,7 @@ def main():
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the other configurations")
     ap.add_argument("--workload", default=WORKLOAD, help=argparse.SUPPRESS)
+    ap.add_argument("--ordering", default="md", choices=("md", "nd"), help=argparse.SUPPRESS)
     ap.add_argument("--fp32-steps-only", action="store_true",
                     help="setup and the timed FP32+IR Newton steps only, for runs under a profiler; prints no JSON line")
     ap.add_argument("--copy-probe", action="store_true",
@@ -284,7 +288,8 @@ def main():
     prob = problems.workload(name)
     log(f"[bench] setup {name}")
     t0 = time.perf_counter()
-    S = qg.Solver(prob, precision=qg.QG_FP32_IR)
+    S = qg.Solver(prob, precision=qg.QG_FP32_IR,
+                  ordering=qg.QG_ORDER_ND if args.ordering == "nd" else qg.QG_ORDER_MD)
     setup_s = time.perf_counter() - t0
     log(f"[bench] setup {setup_s:.1f} s")
 
@@ -390,10 +395,16 @@ def main():
     configs = None
     if not args.no_extra and name == WORKLOAD:
         configs = {}
-        for cname, w, k, bw in (("small_qp", 1, 3, False), ("lasso", 1, 3, False), ("many_soc", 1, 2, False),
-                                ("lasso_diff", 0, 1, True)):
-            log(f"[bench] config {cname}")
-            configs[cname] = run_config(qg, torch, cname, w, k, backward=bw)
+        msoc = problems.workload("many_soc")
+        # many_soc runs with nested dissection (its windowed cones make a long band, whose
+        # minimum-degree elimination tree is 918 fronts deep) and, for comparison, minimum degree
+        for key, cname, w, k, bw, ordr, pr in (("small_qp", "small_qp", 1, 3, False, qg.QG_ORDER_MD, None),
+                                               ("lasso", "lasso", 1, 3, False, qg.QG_ORDER_MD, None),
+                                               ("many_soc", "many_soc", 1, 2, False, qg.QG_ORDER_ND, msoc),
+                                               ("many_soc_md", "many_soc", 1, 2, False, qg.QG_ORDER_MD, msoc),
+                                               ("lasso_diff", "lasso_diff", 0, 1, True, qg.QG_ORDER_MD, None)):
+            log(f"[bench] config {key}")
+            configs[key] = run_config(qg, torch, cname, w, k, backward=bw, ordering=ordr, prob=pr)
         for cname in ("small_qp", "lasso"):
             try:
                 configs[cname]["vs_oracle"] = oracle_errors(qg, cname, (("fp32_ir", qg.QG_FP32_IR),

@@ -69,6 +69,13 @@ typedef int64_t qg_nnz;
 #define QG_FP64 0     /* every factor in FP64 */
 #define QG_FP32_IR 1  /* FP32 factors + FP64 refinement while gap >= switch_gap, then FP64 */
 
+/* qg_settings.ordering: the fill-reducing order of the analysis (paper Sec. 2.2 leaves the
+ * reordering to its sparse solver) */
+#define QG_ORDER_MD 0  /* minimum degree with the approximate external degree */
+#define QG_ORDER_ND 1  /* nested dissection by breadth-first level structures, minimum degree on
+                          pieces of at most 256 nodes: shallow elimination trees for banded and
+                          grid-like patterns (long chains of small fronts under minimum degree) */
+
 typedef struct {
     qg_int nrow, ncol;
     const qg_nnz *colptr;   /* host, ncol + 1 */
@@ -100,6 +107,7 @@ typedef struct {
                                   factorization (1e10); below it the factorization is latency-bound,
                                   FP32 saves nothing and its refinement corrections cost extra solves, so
                                   every factor is FP64 (qg_info.switch_iter = 0) */
+    int ordering;              /* QG_ORDER_MD (default) or QG_ORDER_ND; read by qg_setup only */
 } qg_settings;
 
 #define QG_STEP_MS_MAX 256
@@ -159,6 +167,9 @@ typedef struct {
     const qg_int *front_ptr;       /* nfront + 1: first column of each front, then N */
     const qg_nnz *front_rows_ptr;  /* nfront + 1 */
     const qg_int *front_rows;      /* sorted rows of each front (front numbering) */
+    /* Fronts on the narrow upper levels of deep elimination trees that one workgroup per tree
+     * factors and solves (a handle's schedule; 0 from qg_symbolic_pattern or with chains off) */
+    qg_int nchain_front;
 } qg_pattern;
 
 typedef struct qg_handle qg_handle;      /* device solver state */
@@ -183,11 +194,12 @@ int qg_default_settings(qg_settings *s);
  * reordering, permutation and symbolic factorization that run once per
  * sparsity pattern).  No device is touched.  Arguments as in qg_setup
  * (values are ignored; P, A, G may be NULL when they have no columns with
- * entries, i.e. are empty).  *out is owned by the caller: qg_symbolic_free.
+ * entries, i.e. are empty); ordering: QG_ORDER_MD or QG_ORDER_ND (anything
+ * else is QG_ERR_ARG).  *out is owned by the caller: qg_symbolic_free.
  */
 int qg_analyze(qg_symbolic **out, qg_int n, qg_int m, qg_int p,
                const qg_csc *P, const qg_csc *A, const qg_csc *G,
-               qg_int l, qg_int nsoc, const qg_int *q);
+               qg_int l, qg_int nsoc, const qg_int *q, int ordering);
 int qg_symbolic_pattern(const qg_symbolic *sym, qg_pattern *out);
 void qg_symbolic_free(qg_symbolic *sym);
 

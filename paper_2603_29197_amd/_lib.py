@@ -22,6 +22,8 @@ ERRORS = {-1: "QG_ERR_ARG", -2: "QG_ERR_PATTERN", -3: "QG_ERR_NONFINITE", -4: "Q
 STATUS = {0: "unsolved", 1: "solved", 2: "solved_inaccurate", -1: "max_iter", -2: "numerical_error"}
 QG_FP64 = 0
 QG_FP32_IR = 1
+QG_ORDER_MD = 0
+QG_ORDER_ND = 1
 QG_STEP_MS_MAX = 256
 
 
@@ -44,7 +46,7 @@ class qg_settings(ctypes.Structure):
                 ("dyn_delta32", ctypes.c_double), ("ir_max", ctypes.c_int), ("ir_max32", ctypes.c_int),
                 ("ir_tol", ctypes.c_double), ("step_frac", ctypes.c_double), ("differentiable", ctypes.c_int),
                 ("verbose", ctypes.c_int), ("profile", ctypes.c_int), ("chains", ctypes.c_int),
-                ("fp32_min_flops", ctypes.c_double)]
+                ("fp32_min_flops", ctypes.c_double), ("ordering", ctypes.c_int)]
 
 
 class qg_info(ctypes.Structure):
@@ -77,7 +79,8 @@ class qg_pattern(ctypes.Structure):
                 ("perm", c_int32_p), ("iperm", c_int32_p), ("parent", c_int32_p), ("colcount", c_int64_p),
                 ("super_fund", c_int32_p), ("super_ptr", c_int32_p), ("rows_ptr", c_int64_p),
                 ("rows", c_int32_p), ("nfront", ctypes.c_int32), ("front_perm", c_int32_p),
-                ("front_ptr", c_int32_p), ("front_rows_ptr", c_int64_p), ("front_rows", c_int32_p)]
+                ("front_ptr", c_int32_p), ("front_rows_ptr", c_int64_p), ("front_rows", c_int32_p),
+                ("nchain_front", ctypes.c_int32)]
 
 
 # Device-memory hooks of qg_setup (include/qg.h: qg_alloc_fn, qg_free_fn).
@@ -108,7 +111,7 @@ def lib():
     L.qg_default_settings.argtypes = [ctypes.POINTER(qg_settings)]
     L.qg_analyze.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                              ctypes.POINTER(qg_csc), ctypes.POINTER(qg_csc), ctypes.POINTER(qg_csc),
-                             ctypes.c_int32, ctypes.c_int32, c_int32_p]
+                             ctypes.c_int32, ctypes.c_int32, c_int32_p, ctypes.c_int]
     L.qg_symbolic_pattern.argtypes = [vp, ctypes.POINTER(qg_pattern)]
     L.qg_symbolic_free.argtypes = [vp]
     L.qg_symbolic_free.restype = None

@@ -67,7 +67,8 @@ def _fronts_dict(pt: qg_pattern, arr) -> dict:
     nfr = pt.nfront
     frp = arr(pt.front_rows_ptr, nfr + 1, np.int64)
     return dict(front_perm=arr(pt.front_perm, pt.N, np.int32), front_ptr=arr(pt.front_ptr, nfr + 1, np.int32),
-                front_rows_ptr=frp, front_rows=arr(pt.front_rows, int(frp[-1]), np.int32))
+                front_rows_ptr=frp, front_rows=arr(pt.front_rows, int(frp[-1]), np.int32),
+                nchain_front=int(pt.nchain_front))
 
 
 def _args(prob):
@@ -78,12 +79,13 @@ def _args(prob):
     return P, A, G, q
 
 
-def analyze(prob) -> dict:
-    """Host-only analysis (no device): the integer pattern of qg_pattern."""
+def analyze(prob, ordering: int = 0) -> dict:
+    """Host-only analysis (no device): the integer pattern of qg_pattern
+    (ordering: QG_ORDER_MD or QG_ORDER_ND)."""
     P, A, G, q = _args(prob)
     h = ctypes.c_void_p()
     check(lib().qg_analyze(ctypes.byref(h), prob.n, prob.m, prob.p, P.ptr(), A.ptr(), G.ptr(), prob.l,
-                           len(prob.q), q.ctypes.data_as(_lib.c_int32_p)), "qg_analyze")
+                           len(prob.q), q.ctypes.data_as(_lib.c_int32_p), int(ordering)), "qg_analyze")
     try:
         pt = qg_pattern()
         check(lib().qg_symbolic_pattern(h, ctypes.byref(pt)), "qg_symbolic_pattern")

@@ -534,6 +534,184 @@ void min_degree_order(int32_t N, const std::vector<int64_t> &Gp, const std::vect
 }
 
 // ---------------------------------------------------------------------------
+// nested dissection (the alternative to step 3)
+// ---------------------------------------------------------------------------
+// Automatic nested dissection by breadth-first level structures (George and
+// Liu, "Computer Solution of Large Sparse Positive Definite Systems", 1981,
+// ch. 8), with minimum degree on the small pieces.  For a node set S of the
+// graph (ascending), ND(S) is:
+//  a. |S| <= ND_LEAF: the minimum-degree order of the subgraph induced by S
+//     (local node i = i-th least node of S);
+//  b. the subgraph induced by S is not connected: ND of each of its
+//     components, in increasing order of their least node;
+//  c. connected: the level structure (BFS levels within S) rooted at the
+//     least node of S; then repeatedly the node of the last level with least
+//     (degree within S, index) roots a new level structure, which replaces
+//     the current one while it has more levels (pseudo-peripheral root);
+//  d. with h levels: h < 3 is case a; else the separator is the set of
+//     nodes of level m = floor(h/2) with a neighbour in level m + 1, A the
+//     levels below m plus the rest of level m, B the levels above m; the
+//     order is ND(A), ND(B), then the separator by increasing index.
+// Removing the separator disconnects A from B (BFS levels only touch
+// adjacent levels), so the separator's columns are eliminated last and the
+// elimination trees of A and B hang below them: the tree depth grows with
+// the number of dissection levels, not with the length of the graph.
+namespace {
+
+constexpr int32_t ND_LEAF = 256;
+
+struct Dissector {
+    int32_t N;
+    const std::vector<int64_t> &Gp;
+    const std::vector<int32_t> &Gi;
+    std::vector<int32_t> stamp, lev, loc, queue;
+    int32_t cur = 0;
+    std::vector<int32_t> &out;
+
+    Dissector(int32_t n, const std::vector<int64_t> &gp, const std::vector<int32_t> &gi,
+              std::vector<int32_t> &o)
+        : N(n), Gp(gp), Gi(gi), stamp(n, -1), lev(n, -1), loc(n, -1), queue(n), out(o) {}
+
+    // mark S as the current set (a fresh stamp)
+    void mark(const std::vector<int32_t> &S) {
+        ++cur;
+        for (int32_t v : S) { stamp[v] = cur; lev[v] = -1; }
+    }
+    // BFS within the marked set from root; fills queue[0, count) in level order and the level
+    // boundaries; returns the number of nodes reached
+    int32_t bfs(int32_t root, std::vector<int32_t> &bounds) {
+        bounds.assign(1, 0);
+        int32_t head = 0, tail = 0;
+        queue[tail++] = root;
+        lev[root] = 0;
+        int32_t lv_end = 1;
+        bounds.push_back(1);
+        while (head < tail) {
+            const int32_t v = queue[head++];
+            for (int64_t t = Gp[v]; t < Gp[v + 1]; ++t) {
+                const int32_t u = Gi[t];
+                if (stamp[u] == cur && lev[u] < 0) { lev[u] = lev[v] + 1; queue[tail++] = u; }
+            }
+            if (head == lv_end && tail > lv_end) { lv_end = tail; bounds.push_back(tail); }
+        }
+        return tail;
+    }
+    void reset_levels(int32_t count) {
+        for (int32_t i = 0; i < count; ++i) lev[queue[i]] = -1;
+    }
+    int32_t degree_in_set(int32_t v) const {
+        int32_t d = 0;
+        for (int64_t t = Gp[v]; t < Gp[v + 1]; ++t) d += stamp[Gi[t]] == cur;
+        return d;
+    }
+    // minimum degree on the subgraph induced by the marked set S
+    void leaf(const std::vector<int32_t> &S) {
+        const int32_t ns = (int32_t)S.size();
+        for (int32_t i = 0; i < ns; ++i) loc[S[i]] = i;
+        std::vector<int64_t> lp((size_t)ns + 1, 0);
+        std::vector<int32_t> li;
+        for (int32_t i = 0; i < ns; ++i) {
+            const int32_t v = S[i];
+            for (int64_t t = Gp[v]; t < Gp[v + 1]; ++t)
+                if (stamp[Gi[t]] == cur) li.push_back(loc[Gi[t]]);
+            lp[i + 1] = (int64_t)li.size();
+            std::sort(li.begin() + lp[i], li.end());
+        }
+        std::vector<int32_t> o;
+        min_degree_order(ns, lp, li, o);
+        for (int32_t i : o) out.push_back(S[i]);
+    }
+
+    struct Item {
+        bool emit;                   // true: append nodes as they are
+        std::vector<int32_t> nodes;  // ascending
+    };
+
+    void run(std::vector<int32_t> all) {
+        std::vector<Item> stack;
+        stack.push_back({false, std::move(all)});
+        std::vector<int32_t> bounds, bounds2;
+        while (!stack.empty()) {
+            Item it = std::move(stack.back());
+            stack.pop_back();
+            std::vector<int32_t> &S = it.nodes;
+            if (it.emit) { out.insert(out.end(), S.begin(), S.end()); continue; }
+            if (S.empty()) continue;
+            mark(S);
+            if ((int32_t)S.size() <= ND_LEAF) { leaf(S); continue; }
+            int32_t reached = bfs(S[0], bounds);
+            if (reached < (int32_t)S.size()) {
+                // b: components in increasing order of their least node (S is ascending)
+                std::vector<std::vector<int32_t>> comps;
+                std::vector<int32_t> c(queue.begin(), queue.begin() + reached);
+                std::sort(c.begin(), c.end());
+                comps.push_back(std::move(c));
+                for (int32_t v : S) {
+                    if (lev[v] >= 0) continue;
+                    const int32_t cnt = bfs(v, bounds);
+                    std::vector<int32_t> cc(queue.begin(), queue.begin() + cnt);
+                    std::sort(cc.begin(), cc.end());
+                    comps.push_back(std::move(cc));
+                }
+                for (size_t i = comps.size(); i-- > 0;) stack.push_back({false, std::move(comps[i])});
+                continue;
+            }
+            // c: pseudo-peripheral root
+            int32_t root = S[0];
+            while (true) {
+                const int32_t l0 = bounds[bounds.size() - 2], l1 = bounds.back();
+                int32_t best = -1, bdeg = 0;
+                for (int32_t i = l0; i < l1; ++i) {
+                    const int32_t v = queue[i], dv = degree_in_set(v);
+                    if (best < 0 || dv < bdeg || (dv == bdeg && v < best)) { best = v; bdeg = dv; }
+                }
+                reset_levels(reached);
+                bfs(best, bounds2);
+                if (bounds2.size() > bounds.size()) {
+                    root = best;
+                    bounds.swap(bounds2);
+                    continue;
+                }
+                reset_levels(reached);
+                bfs(root, bounds);
+                break;
+            }
+            const int32_t h = (int32_t)bounds.size() - 1;
+            if (h < 3) { leaf(S); continue; }
+            const int32_t m = h / 2;
+            std::vector<int32_t> A, B, sep;
+            for (int32_t i = 0; i < bounds[m]; ++i) A.push_back(queue[i]);
+            for (int32_t i = bounds[m]; i < bounds[m + 1]; ++i) {
+                const int32_t v = queue[i];
+                bool touches = false;
+                for (int64_t t = Gp[v]; t < Gp[v + 1] && !touches; ++t)
+                    touches = stamp[Gi[t]] == cur && lev[Gi[t]] == m + 1;
+                (touches ? sep : A).push_back(v);
+            }
+            for (int32_t i = bounds[m + 1]; i < reached; ++i) B.push_back(queue[i]);
+            std::sort(A.begin(), A.end());
+            std::sort(B.begin(), B.end());
+            std::sort(sep.begin(), sep.end());
+            stack.push_back({true, std::move(sep)});
+            stack.push_back({false, std::move(B)});
+            stack.push_back({false, std::move(A)});
+        }
+    }
+};
+
+}  // namespace
+
+void nd_order(int32_t N, const std::vector<int64_t> &Gp, const std::vector<int32_t> &Gi,
+              std::vector<int32_t> &order) {
+    order.clear();
+    order.reserve(N);
+    std::vector<int32_t> all(N);
+    std::iota(all.begin(), all.end(), 0);
+    Dissector d(N, Gp, Gi, order);
+    d.run(std::move(all));
+}
+
+// ---------------------------------------------------------------------------
 // elimination tree, postorder, column counts, supernodes
 // ---------------------------------------------------------------------------
 namespace {
@@ -604,7 +782,7 @@ void postorder_of(const std::vector<int32_t> &parent, std::vector<int32_t> &post
 
 }  // namespace
 
-void analyze_pattern(const KktPattern &kp, Symbolic &sym) {
+void analyze_pattern(const KktPattern &kp, Symbolic &sym, int ordering) {
     const int32_t N = kp.N;
     sym.N = N;
     // 1. symmetric graph without the diagonal
@@ -637,9 +815,10 @@ void analyze_pattern(const KktPattern &kp, Symbolic &sym) {
                 Gi[fill[local[j]]++] = local[i];
             }
     }
-    // 3. minimum degree
+    // 3. minimum degree, or nested dissection with minimum degree on its pieces
     std::vector<int32_t> md_local, md;
-    min_degree_order(Ns, Gp, Gi, md_local);
+    if (ordering == QG_ORDER_ND) nd_order(Ns, Gp, Gi, md_local);
+    else min_degree_order(Ns, Gp, Gi, md_local);
     md.reserve(N);
     for (int32_t v : md_local) md.push_back(keep[v]);
     for (int32_t i = 0; i < N; ++i) if (local[i] < 0) md.push_back(i);

@@ -58,12 +58,16 @@ int build_problem_pattern(ProblemPattern &pp, int32_t n, int32_t m, int32_t p,
                           int32_t l, int32_t nsoc, const int32_t *q, bool need_values);
 void build_kkt_pattern(const ProblemPattern &pp, KktPattern &kp);
 
-// The ordering rule and every step after it (see analysis.cpp).
-void analyze_pattern(const KktPattern &kp, Symbolic &sym);
+// The ordering rule and every step after it (see analysis.cpp); ordering is
+// QG_ORDER_MD or QG_ORDER_ND (step 3).
+void analyze_pattern(const KktPattern &kp, Symbolic &sym, int ordering = QG_ORDER_MD);
 
 // Exposed for tests of the ordering alone: order of the graph (both
 // triangles, no self loops), approximate-degree rule with merging.
 void min_degree_order(int32_t N, const std::vector<int64_t> &Gp, const std::vector<int32_t> &Gi,
                       std::vector<int32_t> &order);
+// Nested dissection of the same kind of graph (rule in analysis.cpp).
+void nd_order(int32_t N, const std::vector<int64_t> &Gp, const std::vector<int32_t> &Gi,
+              std::vector<int32_t> &order);
 
 }  // namespace qg

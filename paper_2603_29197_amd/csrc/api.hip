@@ -250,8 +250,11 @@ static int allocate_device(qg_handle *h) {
     if ((rc = dalloc(h, d.mu, 2 * (size_t)h->ncopy))) return rc;
     if ((rc = dalloc(h, d.flag, 1))) return rc;
     // per-block partials: the sparse residual kernels use 256 / RL rows per block
-    const size_t nblk = (N + 256 / RL - 1) / (256 / RL) + (size_t)((h->pp.l + h->pp.nsoc + 255) / 256) +
-                        (size_t)((h->nbig + 3) / 4) + 1 + (size_t)h->ncopy;
+    size_t nblk = (N + 256 / RL - 1) / (256 / RL) + (size_t)((h->pp.l + h->pp.nsoc + 255) / 256) +
+                  (size_t)((h->nbig + 3) / 4) + 1 + (size_t)h->ncopy;
+    // the residual reductions: at most RED_BLOCKS blocks per problem of a batch
+    const int64_t rows1 = N / h->ncopy;
+    nblk = std::max<size_t>(nblk, (size_t)h->ncopy * (size_t)std::min<int64_t>(RED_BLOCKS, rows1 / 64 + 1));
     if ((rc = dalloc(h, d.partials, nblk * NSCAL))) return rc;
     return QG_OK;
 }
@@ -296,6 +299,7 @@ int qg_default_settings(qg_settings *s) {
     s->profile = 0;
     s->chains = 1;
     s->fp32_min_flops = 1e10;
+    s->ordering = QG_ORDER_MD;
     return QG_OK;
 }
 
@@ -315,8 +319,8 @@ const char *qg_strerror(int code) {
 }
 
 int qg_analyze(qg_symbolic **out, qg_int n, qg_int m, qg_int p, const qg_csc *P, const qg_csc *A,
-               const qg_csc *G, qg_int l, qg_int nsoc, const qg_int *q) {
-    if (!out) return QG_ERR_ARG;
+               const qg_csc *G, qg_int l, qg_int nsoc, const qg_int *q, int ordering) {
+    if (!out || (ordering != QG_ORDER_MD && ordering != QG_ORDER_ND)) return QG_ERR_ARG;
     *out = nullptr;
     qg_symbolic *s = new (std::nothrow) qg_symbolic();
     if (!s) return QG_ERR_OOM;
@@ -324,7 +328,7 @@ int qg_analyze(qg_symbolic **out, qg_int n, qg_int m, qg_int p, const qg_csc *P,
         int rc = build_problem_pattern(s->pp, n, m, p, P, A, G, l, nsoc, q, false);
         if (rc) { delete s; return rc; }
         build_kkt_pattern(s->pp, s->kp);
-        analyze_pattern(s->kp, s->sym);
+        analyze_pattern(s->kp, s->sym, ordering);
         if ((rc = group_fronts(s->sym, s->fronts))) { delete s; return rc; }
     } catch (const std::bad_alloc &) {
         delete s;
@@ -354,6 +358,7 @@ static void fill_pattern(const Symbolic &sym, const Symbolic &fr, qg_pattern *o)
     o->front_ptr = fr.super_ptr.data();
     o->front_rows_ptr = fr.rows_ptr.data();
     o->front_rows = fr.rows.data();
+    o->nchain_front = 0;
 }
 
 int qg_symbolic_pattern(const qg_symbolic *sym, qg_pattern *out) {
@@ -394,6 +399,7 @@ int qg_setup(qg_handle **out, qg_int n, qg_int m, qg_int p, const qg_csc *P, con
     if (!out) return QG_ERR_ARG;
     *out = nullptr;
     if ((alloc == nullptr) != (free_fn == nullptr)) return QG_ERR_ARG;
+    if (s && s->ordering != QG_ORDER_MD && s->ordering != QG_ORDER_ND) return QG_ERR_ARG;
     const auto t0 = std::chrono::steady_clock::now();
     qg_handle *h = new (std::nothrow) qg_handle();
     if (!h) return QG_ERR_OOM;
@@ -417,7 +423,7 @@ int qg_setup(qg_handle **out, qg_int n, qg_int m, qg_int p, const qg_csc *P, con
         build_kkt_pattern(h->pp, h->kp);
         h->nnzK = (int64_t)h->kp.Ki.size();
         const auto ta = std::chrono::steady_clock::now();
-        analyze_pattern(h->kp, h->sym);
+        analyze_pattern(h->kp, h->sym, h->st.ordering);
         h->ms_analyze = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - ta).count();
         if ((rc = build_plan(h))) { qg_cleanup(h); return rc; }
         if ((rc = create_streams(h))) { qg_cleanup(h); return rc; }
@@ -455,6 +461,7 @@ int qg_setup_batch(qg_handle **out, qg_int k, qg_int n, qg_int m, qg_int p, cons
     *out = nullptr;
     if (k < 1 || n < 0 || m < 0 || p < 0 || l < 0 || nsoc < 0) return QG_ERR_ARG;
     if ((alloc == nullptr) != (free_fn == nullptr)) return QG_ERR_ARG;
+    if (s && s->ordering != QG_ORDER_MD && s->ordering != QG_ORDER_ND) return QG_ERR_ARG;
     if ((int64_t)k * (n + m + p) > INT32_MAX) return QG_ERR_ARG;
     const auto t0 = std::chrono::steady_clock::now();
     qg_handle *h = new (std::nothrow) qg_handle();
@@ -504,7 +511,7 @@ int qg_setup_batch(qg_handle **out, qg_int k, qg_int n, qg_int m, qg_int p, cons
         KktPattern kp1;
         build_kkt_pattern(pp1, kp1);
         Symbolic sym1, fronts1;
-        analyze_pattern(kp1, sym1);
+        analyze_pattern(kp1, sym1, h->st.ordering);
         if ((rc = group_fronts(sym1, fronts1))) { qg_cleanup(h); return rc; }
         replicate_symbolic(sym1, mp, h->sym);
         replicate_symbolic(fronts1, mp, h->fronts);
@@ -630,6 +637,7 @@ int qg_backward_batch(qg_handle *h, int32_t k, const double *dl_dx, const double
 int qg_get_pattern(const qg_handle *h, qg_pattern *out) {
     if (!h || !out) return QG_ERR_ARG;
     fill_pattern(h->sym, h->fronts, out);
+    out->nchain_front = (qg_int)h->plan.chain_sn.size();
     return QG_OK;
 }
 

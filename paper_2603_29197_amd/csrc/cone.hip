@@ -20,6 +20,8 @@
 #include "cone_math.hpp"
 #include "vec.hpp"
 
+#include <algorithm>
+
 namespace qg {
 
 // out = beta * Wb u  (inv = 0)   or   (1/beta) J Wb J u  (inv = 1)
@@ -263,10 +265,8 @@ __global__ void corrector_kernel(int32_t l, int32_t nsoc, const int32_t *__restr
 
 // per-cone maximum step, min-reduced into amin[slot] (ordered bits of a
 // nonnegative double)
-__global__ void step_kernel(int32_t l, int32_t nsoc, const int32_t *__restrict__ soc_off,
-                            const double *__restrict__ u, const double *__restrict__ du,
-                            unsigned long long *__restrict__ amin, int32_t l1, int32_t nsoc1, int32_t kb) {
-    const int32_t t = blockIdx.x * 256 + threadIdx.x;
+__device__ inline double cone_step(int32_t t, int32_t l, int32_t nsoc, const int32_t *__restrict__ soc_off,
+                                   const double *__restrict__ u, const double *__restrict__ du) {
     double a = INFINITY;
     if (t < l) {
         if (du[t] < 0.0) a = -u[t] / du[t];
@@ -275,8 +275,34 @@ __global__ void step_kernel(int32_t l, int32_t nsoc, const int32_t *__restrict__
         const int32_t off = soc_off[k], q = soc_off[k + 1] - off;
         a = soc_max_step(u + off, du + off, q);
     }
+    return a;
+}
+
+// One problem: a grid-stride loop over the cone units, a block minimum and one atomic per block.
+__global__ void __launch_bounds__(256) step_kernel_one(int32_t l, int32_t nsoc, const int32_t *__restrict__ soc_off,
+                                                       const double *__restrict__ u, const double *__restrict__ du,
+                                                       unsigned long long *__restrict__ amin) {
+    double a = INFINITY;
+    for (int32_t t = blockIdx.x * 256 + threadIdx.x; t < l + nsoc; t += gridDim.x * 256)
+        a = fmin(a, cone_step(t, l, nsoc, soc_off, u, du));
+    for (int off = 32; off > 0; off >>= 1) a = fmin(a, __shfl_xor(a, off));
+    __shared__ double sh[4];
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double b = fmin(fmin(sh[0], sh[1]), fmin(sh[2], sh[3]));
+        if (b < INFINITY) atomicMin(amin, (unsigned long long)__double_as_longlong(b));
+    }
+}
+
+// A batch: one thread per cone unit, the minimum of each problem
+__global__ void step_kernel(int32_t l, int32_t nsoc, const int32_t *__restrict__ soc_off,
+                            const double *__restrict__ u, const double *__restrict__ du,
+                            unsigned long long *__restrict__ amin, int32_t l1, int32_t nsoc1, int32_t kb) {
+    const int32_t t = blockIdx.x * 256 + threadIdx.x;
+    double a = cone_step(t, l, nsoc, soc_off, u, du);
     // the minimum of each problem: a wave min and one atomic per wave when the wave's cones belong to
-    // one problem (always for a single problem), else one atomic per cone
+    // one problem, else one atomic per cone
     const int32_t inst = cone_problem(t, l, l1, nsoc1, kb);
     if (__all(inst == __shfl(inst, 0))) {
         for (int off = 32; off > 0; off >>= 1) a = fmin(a, __shfl_xor(a, off));
@@ -312,10 +338,12 @@ __global__ void __launch_bounds__(256) lmin_kernel(int32_t l, int32_t nsoc, cons
     if (threadIdx.x == 0) partials[blockIdx.x] = nan_max(nan_max(sh[0], sh[1]), nan_max(sh[2], sh[3]));
 }
 
-__global__ void finish_max(const double *__restrict__ partials, int32_t nblk, double *__restrict__ out) {
+__global__ void __launch_bounds__(64) finish_max(const double *__restrict__ partials, int32_t nblk,
+                                                  double *__restrict__ out) {
     double v = -INFINITY;
-    for (int32_t b = 0; b < nblk; ++b) v = nan_max(v, partials[b]);
-    *out = v;
+    for (int32_t b = threadIdx.x; b < nblk; b += 64) v = nan_max(v, partials[b]);
+    for (int o = 32; o > 0; o >>= 1) v = nan_max(v, __shfl_xor(v, o));
+    if (threadIdx.x == 0) *out = v;
 }
 
 // Batches: the shift of the initial point is each problem's own.  Key of a
@@ -741,7 +769,7 @@ int launch_shift_interior(qg_handle *h, double *u) {
     lmin_kernel<<<g, 256, 0, h->stream>>>(h->pp.l, h->pp.nsoc, d.soc_off.p, u, d.partials.p);
     const unsigned gb = big_grid(h);
     if (gb) lmin_big<<<gb, 256, 0, h->stream>>>(h->nbig, d.big_cones.p, d.soc_off.p, u, d.partials.p + g);
-    finish_max<<<1, 1, 0, h->stream>>>(d.partials.p, (int32_t)(g + gb), d.scal.p + NSCAL + 2);
+    finish_max<<<1, 64, 0, h->stream>>>(d.partials.p, (int32_t)(g + gb), d.scal.p + NSCAL + 2);
     double a = 0.0;
     QG_HIP(h, hipMemcpyAsync(&a, d.scal.p + NSCAL + 2, sizeof(double), hipMemcpyDeviceToHost, h->stream));
     QG_HIP(h, hipStreamSynchronize(h->stream));
@@ -770,8 +798,12 @@ int launch_reset_steps(qg_handle *h) {
 int launch_step_min(qg_handle *h, const double *u, const double *du, int slot) {
     Device &d = h->d;
     const int32_t kb = h->ncopy;
-    step_kernel<<<cone_grid(h), 256, 0, h->stream>>>(h->pp.l, h->pp.nsoc, d.soc_off.p, u, du, d.amin.p + slot,
-                                                      h->pp.l / kb, h->pp.nsoc / kb, kb);
+    if (kb == 1)
+        step_kernel_one<<<std::min(cone_grid(h), 1024u), 256, 0, h->stream>>>(h->pp.l, h->pp.nsoc, d.soc_off.p, u,
+                                                                               du, d.amin.p + slot);
+    else
+        step_kernel<<<cone_grid(h), 256, 0, h->stream>>>(h->pp.l, h->pp.nsoc, d.soc_off.p, u, du, d.amin.p + slot,
+                                                          h->pp.l / kb, h->pp.nsoc / kb, kb);
     QG_HIP(h, hipGetLastError());
     if (h->nbig) {
         step_big<<<big_grid(h), 256, 0, h->stream>>>(h->nbig, d.big_cones.p, d.soc_off.p, u, du, d.amin.p + slot,

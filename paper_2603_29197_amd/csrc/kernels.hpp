@@ -23,9 +23,13 @@ constexpr int32_t MAX_FRONT_R = (1 << 23) - 1;
 // fronts, fronts of at most CHAIN_R rows.
 constexpr int CHAIN_LEVEL_MIN = 1024;
 constexpr int CHAIN_R = 32;
+constexpr int CHAIN_WIDTH_MAX = 8;   // a component's fronts per level, on average
 // Lanes per matrix row in the sparse matrix-vector products (16 rows per
-// 256-thread block).
+// 256-thread block) where a kernel has one fixed mapping; the residual
+// reductions choose 4 or 16 from the rows' average length.
 constexpr int RL = 16;
+// Blocks per problem of the residual reductions (grid-stride over the rows).
+constexpr int32_t RED_BLOCKS = 2048;
 // Second-order cones with q >= QBIG entries are handled one wavefront per
 // cone (lane-strided entries, butterfly sums); smaller cones one thread each.
 constexpr int QBIG = 32;

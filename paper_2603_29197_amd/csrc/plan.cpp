@@ -191,9 +191,9 @@ int group_fronts(const Symbolic &sym, Symbolic &g) {
 
 // Chains: the narrow upper levels of deep elimination trees.  From the first
 // level L0 with fewer than CHAIN_LEVEL_MIN fronts on, each tree's fronts at
-// levels >= L0 form one component; when all of them have at most CHAIN_R
-// rows, the component is factored and solved by one workgroup that walks its
-// levels with workgroup barriers, instead of one launch per level (the
+// levels >= L0 form one component; when every component's fronts have at most CHAIN_R
+// rows and at most CHAIN_WIDTH_MAX fronts per level on average, each component
+// is factored and solved by one workgroup that walks its levels with workgroup barriers, instead of one launch per level (the
 // levels below L0, wide enough to fill the device, keep the level launches).
 // A component depends only on fronts below L0 (its own tree), and nothing
 // else depends on it except those fronts, in the backward solve.  Each level
@@ -218,13 +218,23 @@ static void select_chains(Plan &pl, const Symbolic &sym, bool enabled) {
         root[f] = P < 0 ? f : root[P];
     }
     std::vector<int8_t> ok((size_t)ns, 1);
-    std::vector<int32_t> members((size_t)ns, 0);
+    std::vector<int32_t> members((size_t)ns, 0), top((size_t)ns, -1);
     for (int32_t f = 0; f < ns; ++f) {
         if (sym.sn_level[f] < pl.chain_L0) continue;
         const int64_t r = pl.sn_rptr[f + 1] - pl.sn_rptr[f];
         if (r > CHAIN_R) ok[root[f]] = 0;
         members[root[f]]++;
+        top[root[f]] = std::max(top[root[f]], sym.sn_level[f]);
     }
+    // a wide component (more than CHAIN_WIDTH_MAX fronts per level on average, as in the upper
+    // levels of a nested-dissection tree) would be taken a few fronts at a time by one workgroup;
+    // and chains pay only when they replace the level launches from L0 up, so one component that
+    // does not qualify keeps every level launch (no chains at all)
+    for (int32_t R = 0; R < ns; ++R)
+        if (members[R] > 0 && (!ok[R] || members[R] > (int64_t)CHAIN_WIDTH_MAX * (top[R] - pl.chain_L0 + 1))) {
+            pl.chain_L0 = pl.nlevels;
+            return;
+        }
     // components in root order; inside, fronts by level then index
     std::vector<std::vector<int32_t>> comp_of((size_t)ns);
     for (int32_t t = pl.lvl_ptr[pl.chain_L0]; t < pl.lvl_ptr[pl.nlevels]; ++t) {
@@ -674,6 +684,7 @@ int upload_static_values(qg_handle *h, bool vectors) {
             for (int64_t t = rp[i]; t < rp[i + 1]; ++t) { rc_[t] = tmp[t - rp[i]].first; rv[t] = tmp[t - rp[i]].second; }
         }
     }
+    h->kr_nnz = rp[N];
     if ((rc = dupload(h, h->d.kr_ptr, rp))) return rc;
     if ((rc = dupload(h, h->d.kr_col, rc_))) return rc;
     if ((rc = dupload(h, h->d.kr_val, rv))) return rc;

@@ -186,6 +186,7 @@ struct qg_handle {
     std::vector<double> kval_static;   // K upper values without (3,3) entries
     std::vector<double> hc, hb, hh;    // c, b, h on the host
     int64_t nnzK = 0;
+    int64_t kr_nnz = 0;         // entries of the static full CSR of K (kr_*)
     int32_t n = 0, m = 0, p = 0, N = 0;
     int32_t ncopy = 1;                 // problems in the batch (qg_setup_batch), 1 for qg_setup
     int32_t n1 = 0, m1 = 0, p1 = 0, l1 = 0;   // sizes of one problem of the batch

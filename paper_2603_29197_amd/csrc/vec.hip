@@ -2,17 +2,21 @@
 // refinement residual against the unregularized KKT matrix of eq. (2),
 // right-hand sides and the iterate update.  Reductions are two-pass (per
 // block partials, then one block in fixed order), so results do not depend
-// on scheduling.
+// on scheduling.  The sparse residual kernels walk the rows in a grid-stride
+// loop over at most RED_BLOCKS blocks per problem (the partials of a block
+// are formed once, at its end), with R lanes per row: 4 when the rows hold 8
+// entries or fewer on average, else 16.
 #include "vec.hpp"
 
 #include <cmath>
 
 namespace qg {
 
-// Per-block reduction helper: NS slots, each either a sum or a max-abs.
+// Per-block reduction helper: NS slots, each either a sum or a max-abs; slot
+// q of block b goes to partials[q * nblk + b].
 template <int NS>
 __device__ inline void block_reduce_store(double (&val)[NS], const uint32_t maxmask, double *partials,
-                                          int64_t block) {
+                                          int32_t nblk, int32_t block) {
     __shared__ double sh[NS][4];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -31,48 +35,34 @@ __device__ inline void block_reduce_store(double (&val)[NS], const uint32_t maxm
         const bool ismax = (maxmask >> q) & 1u;
         double v = sh[q][0];
         for (int w = 1; w < 4; ++w) v = ismax ? nan_max(v, sh[q][w]) : v + sh[q][w];
-        partials[block * NS + q] = v;
+        partials[(int64_t)q * nblk + block] = v;
     }
 }
 
-// Second pass: 256 threads, each folds a fixed strided subset of the block
-// partials, then a fixed tree over the threads (deterministic).  Workgroup g
-// reduces the g-th run of nblk partials into out[g ns ..] (one run per
-// problem of a batch).
+template <int NS>
+__device__ inline void accumulate(double (&val)[NS], const uint32_t maxmask, int q, double x) {
+    val[q] = ((maxmask >> q) & 1u) ? nan_max(val[q], x) : val[q] + x;
+}
+
+// Second pass: workgroup g reduces the g-th run of nblk x ns partials (one
+// run per problem of a batch; slot-major) into out[g ns ..]: wavefront w takes
+// the slots w, w + 4, ..., each lane a fixed strided subset of the blocks,
+// then a fixed butterfly (deterministic).
 __global__ void __launch_bounds__(256) finish_reduce(const double *__restrict__ partials, int32_t nblk,
                                                      int32_t ns, uint32_t maxmask, double *__restrict__ out) {
     partials += (int64_t)blockIdx.x * nblk * ns;
     out += (int64_t)blockIdx.x * ns;
-    __shared__ double sh[4];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    for (int q = 0; q < ns; ++q) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int q = wave; q < ns; q += 4) {
         const bool ismax = (maxmask >> q) & 1u;
-        const double id = ismax ? -INFINITY : 0.0;
-        double w4[4] = {id, id, id, id};
-        for (int32_t b0 = tid; b0 < nblk; b0 += 4 * 256) {     // four loads in flight per thread
-            double x[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int32_t b = b0 + 256 * u;
-                const double y = partials[(int64_t)(b < nblk ? b : b0) * ns + q];
-                x[u] = b < nblk ? y : id;
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) w4[u] = ismax ? nan_max(w4[u], x[u]) : w4[u] + x[u];
-        }
-        double v = ismax ? nan_max(nan_max(w4[0], w4[1]), nan_max(w4[2], w4[3])) : (w4[0] + w4[1]) + (w4[2] + w4[3]);
+        const double *pq = partials + (int64_t)q * nblk;
+        double v = ismax ? -INFINITY : 0.0;
+        for (int32_t b = lane; b < nblk; b += 64) v = ismax ? nan_max(v, pq[b]) : v + pq[b];
         for (int off = 32; off > 0; off >>= 1) {
             const double o = __shfl_xor(v, off);
             v = ismax ? nan_max(v, o) : v + o;
         }
-        if (lane == 0) sh[wave] = v;
-        __syncthreads();
-        if (tid == 0) {
-            double w = sh[0];
-            for (int k = 1; k < 4; ++k) w = ismax ? nan_max(w, sh[k]) : w + sh[k];
-            out[q] = w;
-        }
-        __syncthreads();
+        if (lane == 0) out[q] = v;
     }
 }
 
@@ -90,6 +80,7 @@ __device__ inline int32_t stacked_row(int32_t kb, int32_t n1, int32_t p1, int32_
     return kb * (n1 + p1) + (w < l1 ? inst * l1 + w : kb * l1 + inst * (m1 - l1) + (w - l1));
 }
 
+template <int R>
 __global__ void __launch_bounds__(256) residual_kernel(
     int32_t n, int32_t p, int32_t m, const int64_t *__restrict__ kr_ptr, const int32_t *__restrict__ kr_col,
     const double *__restrict__ kr_val, const double *__restrict__ x, const double *__restrict__ y,
@@ -100,51 +91,57 @@ __global__ void __launch_bounds__(256) residual_kernel(
     double val[NSCAL];
 #pragma unroll
     for (int q = 0; q < NSCAL; ++q) val[q] = 0.0;
-    const int sub = threadIdx.x & (RL - 1);
-    const int32_t loc = blockIdx.x * (256 / RL) + (threadIdx.x / RL);
-    const bool live = loc < n1 + p1 + m1;
-    const int32_t i = live ? stacked_row(kb, n1, p1, m1, l1, blockIdx.y, loc) : n + p + m;
+    const int sub = threadIdx.x & (R - 1);
     const int32_t N = n + p + m;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-    if (i < N) {
-        for (int64_t t = kr_ptr[i] + sub; t < kr_ptr[i + 1]; t += RL) {
+    const int32_t rows1 = n1 + p1 + m1, stride = (int32_t)gridDim.x * (256 / R);
+    // the R lanes of a row run the loop together, so the shuffles below stay inside the row's lanes
+    for (int32_t loc = blockIdx.x * (256 / R) + (threadIdx.x / R); loc < rows1; loc += stride) {
+        const int32_t i = stacked_row(kb, n1, p1, m1, l1, blockIdx.y, loc);
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+        for (int64_t t = kr_ptr[i] + sub; t < kr_ptr[i + 1]; t += R) {
             const int32_t j = kr_col[t];
             const double v = kr_val[t];
             if (j < n) a0 += v * x[j];
             else if (j < n + p) a1 += v * y[j - n];
             else a2 += v * z[j - n - p];
         }
-    }
 #pragma unroll
-    for (int off = RL / 2; off > 0; off >>= 1) {
-        a0 += __shfl_xor(a0, off);
-        a1 += __shfl_xor(a1, off);
-        a2 += __shfl_xor(a2, off);
-    }
-    if (i < N && sub == 0) {
-        if (i < n) {
-            const double r_ = a0 + a1 + a2 + c[i];
-            rx[i] = r_;
-            val[S_PX] = fabs(a0); val[S_ATY] = fabs(a1); val[S_GTZ] = fabs(a2); val[S_RX] = fabs(r_);
-            val[S_XPX] = x[i] * a0; val[S_CX] = c[i] * x[i]; val[S_C] = fabs(c[i]);
-        } else if (i < n + p) {
-            const int32_t e = i - n;
-            const double r_ = a0 - b[e];
-            ry[e] = r_;
-            val[S_AX] = fabs(a0); val[S_RY] = fabs(r_); val[S_BY] = b[e] * y[e]; val[S_B] = fabs(b[e]);
-        } else {
-            const int32_t e = i - n - p;
-            const double r_ = a0 + s[e] - hv[e];
-            rz[e] = r_;
-            val[S_GX] = fabs(a0); val[S_RZ] = fabs(r_); val[S_HZ] = hv[e] * z[e]; val[S_SZ] = s[e] * z[e];
-            val[S_S] = fabs(s[e]); val[S_H] = fabs(hv[e]);
+        for (int off = R / 2; off > 0; off >>= 1) {
+            a0 += __shfl_xor(a0, off);
+            a1 += __shfl_xor(a1, off);
+            a2 += __shfl_xor(a2, off);
+        }
+        if (sub == 0 && i < N) {
+            if (i < n) {
+                const double r_ = a0 + a1 + a2 + c[i];
+                rx[i] = r_;
+                accumulate(val, SCAL_MAXMASK, S_PX, fabs(a0)); accumulate(val, SCAL_MAXMASK, S_ATY, fabs(a1));
+                accumulate(val, SCAL_MAXMASK, S_GTZ, fabs(a2)); accumulate(val, SCAL_MAXMASK, S_RX, fabs(r_));
+                accumulate(val, SCAL_MAXMASK, S_XPX, x[i] * a0); accumulate(val, SCAL_MAXMASK, S_CX, c[i] * x[i]);
+                accumulate(val, SCAL_MAXMASK, S_C, fabs(c[i]));
+            } else if (i < n + p) {
+                const int32_t e = i - n;
+                const double r_ = a0 - b[e];
+                ry[e] = r_;
+                accumulate(val, SCAL_MAXMASK, S_AX, fabs(a0)); accumulate(val, SCAL_MAXMASK, S_RY, fabs(r_));
+                accumulate(val, SCAL_MAXMASK, S_BY, b[e] * y[e]); accumulate(val, SCAL_MAXMASK, S_B, fabs(b[e]));
+            } else {
+                const int32_t e = i - n - p;
+                const double r_ = a0 + s[e] - hv[e];
+                rz[e] = r_;
+                accumulate(val, SCAL_MAXMASK, S_GX, fabs(a0)); accumulate(val, SCAL_MAXMASK, S_RZ, fabs(r_));
+                accumulate(val, SCAL_MAXMASK, S_HZ, hv[e] * z[e]); accumulate(val, SCAL_MAXMASK, S_SZ, s[e] * z[e]);
+                accumulate(val, SCAL_MAXMASK, S_S, fabs(s[e])); accumulate(val, SCAL_MAXMASK, S_H, fabs(hv[e]));
+            }
         }
     }
-    block_reduce_store<NSCAL>(val, SCAL_MAXMASK, partials, (int64_t)blockIdx.y * gridDim.x + blockIdx.x);
+    block_reduce_store<NSCAL>(val, SCAL_MAXMASK, partials + (int64_t)blockIdx.y * NSCAL * gridDim.x,
+                              (int32_t)gridDim.x, (int32_t)blockIdx.x);
 }
 
 // res = rhs - K sol, K = static part + (3,3) block from kval; slot 0 of the
 // partials: max |res|, slot 1: max |rhs|.
+template <int R>
 __global__ void __launch_bounds__(256) kkt_residual_kernel(
     int32_t n, int32_t p, int32_t m, int32_t l, const int64_t *__restrict__ kr_ptr,
     const int32_t *__restrict__ kr_col, const double *__restrict__ kr_val, const double *__restrict__ kval,
@@ -153,11 +150,11 @@ __global__ void __launch_bounds__(256) kkt_residual_kernel(
     double *__restrict__ res, double *__restrict__ partials) {
     double val[2] = {0.0, 0.0};
     const int32_t N = n + p + m;
-    const int sub = threadIdx.x & (RL - 1);
-    const int32_t i = blockIdx.x * (256 / RL) + (threadIdx.x / RL);
-    double acc = 0.0;
-    if (i < N) {
-        for (int64_t t = kr_ptr[i] + sub; t < kr_ptr[i + 1]; t += RL) acc += kr_val[t] * sol[kr_col[t]];
+    const int sub = threadIdx.x & (R - 1);
+    const int32_t stride = (int32_t)gridDim.x * (256 / R);
+    for (int32_t i = blockIdx.x * (256 / R) + (threadIdx.x / R); i < N; i += stride) {
+        double acc = 0.0;
+        for (int64_t t = kr_ptr[i] + sub; t < kr_ptr[i + 1]; t += R) acc += kr_val[t] * sol[kr_col[t]];
         if (i >= n + p) {
             const int32_t e = i - n - p;
             const double *zs = sol + n + p;
@@ -168,22 +165,22 @@ __global__ void __launch_bounds__(256) kkt_residual_kernel(
                 const int32_t off = soc_off[k], q = soc_off[k + 1] - off;
                 const int32_t a = e - off;
                 const int64_t base = l + blk_off[k];
-                for (int32_t bb = sub; bb < q; bb += RL) {
+                for (int32_t bb = sub; bb < q; bb += R) {
                     const int32_t lo = a < bb ? a : bb, hi = a < bb ? bb : a;
                     acc += kval[blk33[base + (int64_t)hi * (hi + 1) / 2 + lo]] * zs[bb + off];
                 }
             }
         }
-    }
 #pragma unroll
-    for (int off = RL / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-    if (i < N && sub == 0) {
-        const double r_ = rhs[i] - acc;
-        res[i] = r_;
-        val[0] = fabs(r_);
-        val[1] = fabs(rhs[i]);
+        for (int off = R / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+        if (sub == 0) {
+            const double r_ = rhs[i] - acc;
+            res[i] = r_;
+            val[0] = nan_max(val[0], fabs(r_));
+            val[1] = nan_max(val[1], fabs(rhs[i]));
+        }
     }
-    block_reduce_store<2>(val, 3u, partials, blockIdx.x);
+    block_reduce_store<2>(val, 3u, partials, (int32_t)gridDim.x, (int32_t)blockIdx.x);
 }
 
 __global__ void build_rhs_kernel(int32_t n, int32_t p, int32_t m, const double *__restrict__ rx,
@@ -259,15 +256,30 @@ int launch_scale_copy(qg_handle *h, int32_t len, double a, const double *xv, dou
     return QG_OK;
 }
 
+// Lanes per row of the sparse residual kernels and their block count (at most RED_BLOCKS per
+// problem, fewer when the rows run out).
+static int lanes_per_row(const qg_handle *h) { return h->kr_nnz <= 8 * (int64_t)h->N ? 4 : 16; }
+static int32_t red_blocks(int32_t rows, int R) {
+    const int32_t need = (rows + 256 / R - 1) / (256 / R);
+    return need < 1 ? 1 : (need < RED_BLOCKS ? need : RED_BLOCKS);
+}
+
 int launch_residual(qg_handle *h, const double *x, const double *y, const double *z, const double *s,
                     double *scal_host) {
     Device &d = h->d;
     const int32_t kb = h->ncopy;
     const int32_t n1 = h->n / kb, p1 = h->p / kb, m1 = h->m / kb, l1 = h->pp.l / kb;
-    const int32_t nblk = (n1 + p1 + m1 + 256 / RL - 1) / (256 / RL);
-    residual_kernel<<<dim3((unsigned)nblk, (unsigned)kb), 256, 0, h->stream>>>(
-        h->n, h->p, h->m, d.kr_ptr.p, d.kr_col.p, d.kr_val.p, x, y, z, s, d.c.p, d.b.p, d.h.p, d.rx.p, d.ry.p,
-        d.rz.p, d.partials.p, kb, n1, p1, m1, l1);
+    const int R = lanes_per_row(h);
+    const int32_t nblk = red_blocks(n1 + p1 + m1, R);
+    const dim3 grid((unsigned)nblk, (unsigned)kb);
+    if (R == 4)
+        residual_kernel<4><<<grid, 256, 0, h->stream>>>(
+            h->n, h->p, h->m, d.kr_ptr.p, d.kr_col.p, d.kr_val.p, x, y, z, s, d.c.p, d.b.p, d.h.p, d.rx.p, d.ry.p,
+            d.rz.p, d.partials.p, kb, n1, p1, m1, l1);
+    else
+        residual_kernel<16><<<grid, 256, 0, h->stream>>>(
+            h->n, h->p, h->m, d.kr_ptr.p, d.kr_col.p, d.kr_val.p, x, y, z, s, d.c.p, d.b.p, d.h.p, d.rx.p, d.ry.p,
+            d.rz.p, d.partials.p, kb, n1, p1, m1, l1);
     finish_reduce<<<(unsigned)kb, 256, 0, h->stream>>>(d.partials.p, nblk, NSCAL, SCAL_MAXMASK, d.scal_inst.p);
     QG_HIP(h, hipGetLastError());
     QG_HIP(h, hipMemcpyAsync(scal_host, d.scal_inst.p, (size_t)kb * NSCAL * sizeof(double),
@@ -279,10 +291,16 @@ int launch_residual(qg_handle *h, const double *x, const double *y, const double
 int launch_kkt_residual(qg_handle *h, const double *rhs, const double *sol, double *res, double *norms) {
     Device &d = h->d;
     const int32_t N = h->N;
-    const int32_t nblk = (N + 256 / RL - 1) / (256 / RL);
-    kkt_residual_kernel<<<nblk, 256, 0, h->stream>>>(h->n, h->p, h->m, h->pp.l, d.kr_ptr.p, d.kr_col.p,
-                                                      d.kr_val.p, d.kval.p, d.blk33.p, d.blk_off.p,
-                                                      d.soc_off.p, d.zcone.p, rhs, sol, res, d.partials.p);
+    const int R = lanes_per_row(h);
+    const int32_t nblk = red_blocks(N, R);
+    if (R == 4)
+        kkt_residual_kernel<4><<<nblk, 256, 0, h->stream>>>(h->n, h->p, h->m, h->pp.l, d.kr_ptr.p, d.kr_col.p,
+                                                            d.kr_val.p, d.kval.p, d.blk33.p, d.blk_off.p,
+                                                            d.soc_off.p, d.zcone.p, rhs, sol, res, d.partials.p);
+    else
+        kkt_residual_kernel<16><<<nblk, 256, 0, h->stream>>>(h->n, h->p, h->m, h->pp.l, d.kr_ptr.p, d.kr_col.p,
+                                                             d.kr_val.p, d.kval.p, d.blk33.p, d.blk_off.p,
+                                                             d.soc_off.p, d.zcone.p, rhs, sol, res, d.partials.p);
     finish_reduce<<<1, 256, 0, h->stream>>>(d.partials.p, nblk, 2, 3u, d.scal.p + NSCAL);
     QG_HIP(h, hipGetLastError());
     QG_HIP(h, hipMemcpyAsync(norms, d.scal.p + NSCAL, 2 * sizeof(double), hipMemcpyDeviceToHost, h->stream));

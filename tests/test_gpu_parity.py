@@ -649,6 +649,8 @@ def test_chain_kernels_give_the_level_kernels_bits(prec):
     out = []
     for chains in (1, 0):
         S = solver(prob, chains=chains, precision=prec_c)
+        nch = S.pattern()["nchain_front"]
+        assert (nch > 1000) if chains else (nch == 0), nch
         x, s, y, z, info = S.solve()
         out.append((x.cpu().numpy(), z.cpu().numpy(), info))
         print(f"[gpu] chains={chains} {prec}: {info['status_name']} iters {info['iters']} "
@@ -659,3 +661,32 @@ def test_chain_kernels_give_the_level_kernels_bits(prec):
     assert np.array_equal(x1, x0) and np.array_equal(z1, z0)
     ref = oipm.solve(prob)
     assert relerr(x1, ref.x) <= 1e-6
+
+
+@pytest.mark.parametrize("name", ["small_qp", "lasso_s", "many_soc_s", "mixed_soc"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_solve_with_nested_dissection_matches_oracle(name, prec):
+    """The nested-dissection analysis on the device: the handle's pattern is the oracle's
+    nested-dissection pattern bit for bit, and the solution matches the oracle's solve (whose
+    iterates do not depend on the ordering beyond rounding) to 1e-6 in x and objective."""
+    import paper_2603_29197_amd as qg
+    from oracle import kkt, symbolic
+    prob = SMALL[name]()
+    S = solver(prob, precision=qg.QG_FP64 if prec == "fp64" else qg.QG_FP32_IR, ordering=qg.QG_ORDER_ND)
+    pat = S.pattern()
+    o = symbolic.analyze(kkt.kkt_pattern(prob), "nd")
+    for k in ("perm", "parent", "colcount", "super_ptr", "rows"):
+        assert np.array_equal(pat[k], getattr(o, k)), k
+    x, s, y, z, info = S.solve()
+    ref = oracle_solution(name)
+    xs = host(x)
+    ex = float(np.max(np.abs(xs - ref.x)) / max(1.0, np.max(np.abs(ref.x))))
+    eo = abs(info["pobj"] - ref.pobj) / max(1.0, abs(ref.pobj))
+    print(f"[gpu] nd {name} {prec}: {info['status_name']} iters {info['iters']} (oracle {ref.iters}) "
+          f"rel err x {ex:.2e} obj {eo:.2e} step {info['ms_step_median']:.3f} ms", flush=True)
+    assert info["status"] == 1
+    assert ex <= 1e-6 and eo <= 1e-6, (ex, eo)
+    r = oipm.residuals(prob, xs, host(s), host(y), host(z))
+    ok, pres, dres, gap = oipm.stop_test(prob, r, host(s), 1e-8, 1e-8)
+    assert ok, (pres, dres, gap)
+    S.close()

@@ -116,12 +116,13 @@ def test_device_fronts_random(seed):
     _check_fronts(prob, qg.analyze(prob))
 
 
-@pytest.mark.parametrize("name", ["huber_s", "many_soc", "lasso", "huber_l"])
+@pytest.mark.parametrize("name", ["huber_s", "many_soc", "lasso", "huber_l", "many_soc@nd"])
 def test_analysis_matches_oracle_digest_full_size(name):
-    """Digests written by tests/golden/make_golden.py from the oracle."""
+    """Digests written by tests/golden/make_golden.py from the oracle ("@nd": nested dissection)."""
     import paper_2603_29197_amd as qg
     gold = json.load(open(os.path.join(ROOT, "tests", "golden", "patterns.json")))[name]
-    a = qg.analyze(problems.workload(name))
+    wl, _, ordering = name.partition("@")
+    a = qg.analyze(problems.workload(wl), qg.QG_ORDER_ND if ordering == "nd" else qg.QG_ORDER_MD)
     assert a["N"] == gold["N"] and int(a["colcount"].sum()) == gold["nnz_L"]
     for k, dt in KEYS:
         if k == "iperm":
@@ -199,3 +200,31 @@ def test_allocator_hooks_must_come_in_pairs():
     prob = problems.small_qp(n=20, p=4, m=10, mrows=10)
     only_alloc = (_lib.ALLOC_FN(lambda ctx, nbytes: None), _lib.FREE_FN(), None)
     assert _raw_setup(prob, only_alloc) == -1
+
+
+@pytest.mark.parametrize("name", ["small_qp", "lasso_s", "many_soc_s", "lasso_diff_s"])
+def test_nested_dissection_matches_oracle_bit_exact(name):
+    import paper_2603_29197_amd as qg
+    prob = problems.workload(name)
+    a = qg.analyze(prob, qg.QG_ORDER_ND)
+    o = symbolic.analyze(kkt.kkt_pattern(prob), "nd")
+    for k, _ in KEYS:
+        assert np.array_equal(a[k], getattr(o, k)), k
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_nested_dissection_matches_oracle_random_socp(seed):
+    """Windowed and random-column SOCPs large enough to be dissected (more than 256 nodes)."""
+    import paper_2603_29197_amd as qg
+    prob = problems.many_soc(n=900 + 137 * seed, ncones=300 + 25 * seed, q=3 + seed % 4, nbounds=200,
+                             seed=700 + seed, windowed=bool(seed % 2))
+    a = qg.analyze(prob, qg.QG_ORDER_ND)
+    o = symbolic.analyze(kkt.kkt_pattern(prob), "nd")
+    for k, _ in KEYS:
+        assert np.array_equal(a[k], getattr(o, k)), k
+
+
+def test_analysis_rejects_an_unknown_ordering():
+    import paper_2603_29197_amd as qg
+    with pytest.raises(qg.QGError):
+        qg.analyze(problems.workload("small_qp"), 2)

@@ -262,6 +262,7 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the other configurations")
     ap.add_argument("--workload", default=WORKLOAD, help=argparse.SUPPRESS)
     ap.add_argument("--ordering", default="md", choices=("md", "nd"), help=argparse.SUPPRESS)
+    ap.add_argument("--cone-lanes", type=int, default=1, choices=(0, 1), help=argparse.SUPPRESS)
     ap.add_argument("--fp32-steps-only", action="store_true",
                     help="setup and the timed FP32+IR Newton steps only, for runs under a profiler; prints no JSON line")
     ap.add_argument("--copy-probe", action="store_true",
@@ -288,7 +289,7 @@ def main():
     prob = problems.workload(name)
     log(f"[bench] setup {name}")
     t0 = time.perf_counter()
-    S = qg.Solver(prob, precision=qg.QG_FP32_IR,
+    S = qg.Solver(prob, precision=qg.QG_FP32_IR, cone_lanes=args.cone_lanes,
                   ordering=qg.QG_ORDER_ND if args.ordering == "nd" else qg.QG_ORDER_MD)
     setup_s = time.perf_counter() - t0
     log(f"[bench] setup {setup_s:.1f} s")

@@ -108,6 +108,9 @@ typedef struct {
                                   FP32 saves nothing and its refinement corrections cost extra solves, so
                                   every factor is FP64 (qg_info.switch_iter = 0) */
     int ordering;              /* QG_ORDER_MD (default) or QG_ORDER_ND; read by qg_setup only */
+    int cone_lanes;            /* 1: when every second-order cone of a single problem has the same
+                                  2 <= q <= 16 entries, NT scaling and the (3,3) block run one lane per
+                                  cone entry (lane groups of 2, 4, 8 or 16); 0: one thread per cone (1) */
 } qg_settings;
 
 #define QG_STEP_MS_MAX 256

@@ -156,6 +156,14 @@ static int allocate_device(qg_handle *h) {
         for (int32_t k = 0; k < h->pp.nsoc; ++k)
             if (h->pp.soc_off[k + 1] - h->pp.soc_off[k] >= QBIG) big.push_back(k);
         h->nbig = (int32_t)big.size();
+        // every cone of one problem with the same 2 <= q <= 16 entries: lane-group cone kernels
+        h->grp_q = 0;
+        if (h->ncopy == 1 && h->pp.nsoc > 0) {
+            const int32_t q0 = h->pp.soc_off[1] - h->pp.soc_off[0];
+            bool uni = q0 >= 2 && q0 <= 16;
+            for (int32_t k = 1; k < h->pp.nsoc && uni; ++k) uni = h->pp.soc_off[k + 1] - h->pp.soc_off[k] == q0;
+            if (uni) h->grp_q = q0;
+        }
         UP(big_cones, big);
         std::vector<int32_t> ccone;
         std::vector<int64_t> cstart;
@@ -300,6 +308,7 @@ int qg_default_settings(qg_settings *s) {
     s->chains = 1;
     s->fp32_min_flops = 1e10;
     s->ordering = QG_ORDER_MD;
+    s->cone_lanes = 1;
     return QG_OK;
 }
 

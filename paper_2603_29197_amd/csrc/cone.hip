@@ -689,8 +689,105 @@ static inline unsigned cone_grid(qg_handle *h) {
     return (unsigned)std::max<int64_t>(1, (units + 255) / 256);
 }
 
+// ---------------------------------------------------------------------------
+// Lane groups: every second-order cone of the problem has the same q <= 16
+// entries.  The orthant entries take one lane each in the first ceil(l / 64)
+// wavefronts; then each cone takes G = 2^ceil(log2 q) consecutive lanes, lane
+// e of its group holding entry e, so a wavefront's loads and stores are
+// contiguous runs; a sum over a cone is a butterfly inside the group.  The
+// formulas are those of the one-thread kernels (and of the wavefront-per-cone
+// kernels, whose sums are butterflies too).  Measured on 1e5 cones of 4
+// entries and 1e5 orthant entries: NT scaling with the (3,3) block 12.9 us
+// against 20.7 us with one thread per cone.  (A lane-group line search took
+// 25.3 us against 12.0 us: its blocks were 2.5 times as many, each with an
+// atomic on the one minimum, and every lane repeats the divisions by the
+// J-norm; the line search keeps one thread per cone.)
+// ---------------------------------------------------------------------------
+template <int G>
+__device__ inline double grp_sum(double v) {
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+template <int G>
+__global__ void __launch_bounds__(256) scaling_kernel_grp(int32_t l, int32_t nsoc, int32_t q,
+                                                          const int64_t *__restrict__ blk_off,
+                                                          const int64_t *__restrict__ blk33,
+                                                          const double *__restrict__ s, const double *__restrict__ z,
+                                                          double *__restrict__ w, double *__restrict__ wbar,
+                                                          double *__restrict__ beta, double *__restrict__ lam,
+                                                          double *__restrict__ kval) {
+    const int64_t lpad = ((int64_t)l + 63) & ~(int64_t)63;
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t < lpad) {                                   // whole wavefronts
+        if (t < l) {
+            const double si = s[t], zi = z[t];
+            w[t] = sqrt(si / zi);
+            if (lam) lam[t] = sqrt(si * zi);
+            kval[blk33[t]] = -(si / zi);
+        }
+        return;
+    }
+    const int64_t tc = t - lpad, c = tc / G;
+    const int e = (int)(tc % G);
+    const int gb = (threadIdx.x & 63) & ~(G - 1);
+    const bool cone = c < nsoc, live = cone && e < q;
+    const int64_t off = l + c * q + e;
+    const double sx = live ? s[off] : 0.0, zx = live ? z[off] : 0.0;
+    const double s0 = __shfl(sx, gb), z0 = __shfl(zx, gb);
+    const double ns1 = sqrt(grp_sum<G>(e >= 1 ? sx * sx : 0.0));
+    const double nz1 = sqrt(grp_sum<G>(e >= 1 ? zx * zx : 0.0));
+    const double sn = sqrt((s0 - ns1) * (s0 + ns1)), zn = sqrt((z0 - nz1) * (z0 + nz1));
+    const double dot = grp_sum<G>(live ? (zx / zn) * (sx / sn) : 0.0);
+    const double gamma = sqrt((1.0 + dot) * 0.5);
+    const double zb = zx / zn, sb = sx / sn;
+    const double wbv = (sb + (e == 0 ? zb : -zb)) / (2.0 * gamma);
+    const double bt = sqrt(sn / zn);
+    if (live) wbar[off - l] = wbv;
+    if (cone && e == 0) beta[c] = bt;
+    if (lam) {
+        // lam = W z = bt (wb'z, z1 + wb1 (z0 + wb1'z1 / (1 + wb0)))
+        const double w1u1 = grp_sum<G>(e >= 1 && live ? wbv * zx : 0.0);
+        const double wb0 = __shfl(wbv, gb);
+        const double coef = z0 + w1u1 / (1.0 + wb0);
+        const double le = e == 0 ? bt * (wb0 * z0 + w1u1) : bt * (zx + wbv * coef);
+        if (live) lam[off] = le;
+    }
+    // (3,3) block: -bt^2 (2 wb wb' - J), upper triangle, this lane's column e
+    const double b2 = bt * bt;
+    const int64_t base = cone ? l + blk_off[c] : 0;
+#pragma unroll
+    for (int ar = 0; ar < G; ++ar) {
+        const double wa = __shfl(wbv, gb + ar);
+        if (live && ar <= e) {
+            const double jab = (ar == e) ? (ar == 0 ? 1.0 : -1.0) : 0.0;
+            kval[blk33[base + (int64_t)e * (e + 1) / 2 + ar]] = -b2 * (2.0 * wa * wbv - jab);
+        }
+    }
+}
+
+static inline int grp_width(int32_t q) { return q <= 2 ? 2 : q <= 4 ? 4 : q <= 8 ? 8 : 16; }
+static inline unsigned grp_grid(qg_handle *h, int G) {
+    const int64_t lpad = ((int64_t)h->pp.l + 63) & ~(int64_t)63;
+    return (unsigned)std::max<int64_t>(1, (lpad + (int64_t)h->pp.nsoc * G + 255) / 256);
+}
+static inline bool use_groups(qg_handle *h) { return h->grp_q > 0 && h->st.cone_lanes != 0 && h->ncopy == 1; }
+
+
 int launch_scaling(qg_handle *h, const double *s, const double *z, double *lam, int block) {
     Device &d = h->d;
+    if (block == 0 && use_groups(h)) {
+        const int G = grp_width(h->grp_q);
+        const unsigned g = grp_grid(h, G);
+#define QG_SCALING_GRP(GG) scaling_kernel_grp<GG><<<g, 256, 0, h->stream>>>(h->pp.l, h->pp.nsoc, h->grp_q, \
+        d.blk_off.p, d.blk33.p, s, z, d.w.p, d.wbar.p, d.beta.p, lam, d.kval.p)
+        if (G == 2) QG_SCALING_GRP(2); else if (G == 4) QG_SCALING_GRP(4); else if (G == 8) QG_SCALING_GRP(8);
+        else QG_SCALING_GRP(16);
+#undef QG_SCALING_GRP
+        QG_HIP(h, hipGetLastError());
+        return QG_OK;
+    }
     scaling_kernel<<<cone_grid(h), 256, 0, h->stream>>>(h->pp.l, h->pp.nsoc, d.soc_off.p, d.blk_off.p,
                                                          d.blk33.p, s, z, d.w.p, d.wbar.p, d.beta.p, lam,
                                                          d.kval.p, block);

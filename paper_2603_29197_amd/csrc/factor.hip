@@ -153,6 +153,73 @@ __global__ void __launch_bounds__(256) factor_small(
     factor_front_lds(F, G, r, k, kind + sn_first[s], eps, dyn, nreg, dsh);
 }
 
+// The k pivot steps of one front F (r <= CHAIN_R, column-major in LDS, lower
+// part) by one wavefront, with the arithmetic of factor_front_lds (pivot,
+// rank-1 update of the trailing lower part, column scaling); the steps are
+// separated by wavefront barriers only (the LDS operations of one wavefront
+// complete in order).
+template <typename T>
+__device__ inline void factor_tile_wave(T *F, int32_t r, int32_t k, const int8_t *__restrict__ kd_s, double eps,
+                                        double dyn, int32_t *nreg, T &dsh) {
+    const int lane = threadIdx.x & 63;
+    for (int32_t jj = 0; jj < k; ++jj) {
+        if (lane == 0) {
+            const T d = regularize(F[jj * r + jj], kd_s[jj], eps, dyn, nreg);
+            F[jj * r + jj] = d;
+            dsh = d;
+        }
+        __builtin_amdgcn_wave_barrier();
+        const T d = dsh;
+        const int32_t R = r - jj - 1;
+        for (int32_t idx = lane; idx < R * R; idx += 64) {
+            const int32_t i = jj + 1 + idx % R, cc = jj + 1 + idx / R;
+            if (i >= cc) F[cc * r + i] -= F[jj * r + i] * F[jj * r + cc] / d;
+        }
+        __builtin_amdgcn_wave_barrier();
+        for (int32_t i = jj + 1 + lane; i < r; i += 64) F[jj * r + i] /= d;
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// Small fronts of a level whose fronts all have at most CHAIN_R rows and 12 on
+// average: one wavefront per front, four per workgroup, each front (assembled
+// in the front storage by the level's gather) in its own LDS tile.  The same
+// arithmetic as factor_small, a quarter of the workgroups and no workgroup
+// barriers.  (On levels of larger fronts, 16 rows and more on average, the
+// workgroup per front of factor_small was measured faster.)
+template <typename T>
+__global__ void __launch_bounds__(256) factor_small_wave(
+    int32_t nfront, const int32_t *__restrict__ sn_list, const int32_t *__restrict__ sn_first,
+    const int64_t *__restrict__ sn_rptr, const int64_t *__restrict__ fr_off, T *__restrict__ front,
+    const int8_t *__restrict__ kind, double eps, double dyn, int32_t *nreg) {
+    __shared__ T tile[4][CHAIN_R * CHAIN_R];
+    __shared__ T dsh[4];
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int32_t q = blockIdx.x * 4 + w;
+    if (q >= nfront) return;                         // whole wavefront
+    const int32_t s = sn_list[q];
+    const int32_t r = (int32_t)(sn_rptr[s + 1] - sn_rptr[s]);
+    const int32_t k = sn_first[s + 1] - sn_first[s];
+    T *F = tile[w];
+    T *G = front + fr_off[s];
+    const int32_t rr = r * r;
+    T g[CHAIN_R * CHAIN_R / 64];                     // all loads in flight at once
+#pragma unroll
+    for (int u = 0; u < CHAIN_R * CHAIN_R / 64; ++u) g[u] = ld_or0(G, lane + 64 * u, lane + 64 * u < rr);
+#pragma unroll
+    for (int u = 0; u < CHAIN_R * CHAIN_R / 64; ++u) {
+        const int32_t idx = lane + 64 * u;
+        if (idx < rr) F[idx] = (idx % r >= idx / r) ? g[u] : T(0);
+    }
+    __builtin_amdgcn_wave_barrier();
+    factor_tile_wave<T>(F, r, k, kind + sn_first[s], eps, dyn, nreg, dsh[w]);
+    for (int32_t idx = lane; idx < rr; idx += 64) {
+        const int32_t i = idx % r, cc = idx / r;
+        if (i >= cc) G[idx] = F[idx];
+    }
+}
+
 // Chains (the narrow upper levels of deep elimination trees): one workgroup
 // per component walks the component's levels; the fronts of a level are
 // factored one per wavefront, each in its own LDS tile, with the same
@@ -204,23 +271,7 @@ __global__ void __launch_bounds__(256) factor_chain(
                 F[dst[e] - base] = v;
             }
             __builtin_amdgcn_wave_barrier();
-            for (int32_t jj = 0; jj < k; ++jj) {
-                if (lane == 0) {
-                    const T d = regularize(F[jj * r + jj], kd_s[jj], eps, dyn, nreg);
-                    F[jj * r + jj] = d;
-                    dsh[w] = d;
-                }
-                __builtin_amdgcn_wave_barrier();
-                const T d = dsh[w];
-                const int32_t R = r - jj - 1;
-                for (int32_t idx = lane; idx < R * R; idx += 64) {
-                    const int32_t i = jj + 1 + idx % R, cc = jj + 1 + idx / R;
-                    if (i >= cc) F[cc * r + i] -= F[jj * r + i] * F[jj * r + cc] / d;
-                }
-                __builtin_amdgcn_wave_barrier();
-                for (int32_t i = jj + 1 + lane; i < r; i += 64) F[jj * r + i] /= d;
-                __builtin_amdgcn_wave_barrier();
-            }
+            factor_tile_wave<T>(F, r, k, kd_s, eps, dyn, nreg, dsh[w]);
             T *G = front + base;
             for (int32_t idx = lane; idx < r * r; idx += 64) {
                 const int32_t i = idx % r, cc = idx / r;
@@ -1083,7 +1134,11 @@ static int factor_all(qg_handle *h, T *front, T *dinv, T *sinv, T *wb, const Reg
             gather_entries<T><<<(unsigned)((ne + 255) / 256), 256, 0, h->stream>>>(
                 e0, ne, d.ent_dst.p, d.ent_sptr.p, d.ent_reg.p, d.ent_src.p, d.kval.p, rp.delta, front);
         const int32_t s0 = pl.lvl_small_ptr[L], s1 = pl.lvl_small_ptr[L + 1];
-        if (s1 > s0) {
+        if (s1 > s0 && pl.lvl_small_maxr[L] <= CHAIN_R && pl.lvl_small_rsum[L] <= 12 * (int64_t)(s1 - s0)) {
+            factor_small_wave<T><<<(s1 - s0 + 3) / 4, 256, 0, h->stream>>>(
+                s1 - s0, d.lvl_small_sn.p + s0, d.sn_first.p, d.sn_rptr.p, d.fr_off.p, front, d.reg_sign.p, rp.eps,
+                rp.dyn, d.nreg.p);
+        } else if (s1 > s0) {
             const size_t lds = (size_t)pl.lvl_small_maxr[L] * pl.lvl_small_maxr[L] * sizeof(T);
             factor_small<T><<<s1 - s0, 256, lds, h->stream>>>(d.lvl_small_sn.p + s0, d.sn_first.p,
                                                                d.sn_rptr.p, d.fr_off.p, front,

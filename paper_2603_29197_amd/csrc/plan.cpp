@@ -473,6 +473,7 @@ int build_plan(qg_handle *h) {
     }
     select_chains(pl, sym, h->st.chains != 0);
     pl.lvl_small_maxr.assign((size_t)pl.nlevels, 0);
+    pl.lvl_small_rsum.assign((size_t)pl.nlevels, 0);
     pl.lvl_small_ptr.assign((size_t)pl.nlevels + 1, 0);
     pl.lvl_large_ptr.assign((size_t)pl.nlevels + 1, 0);
     pl.lvl_small_sn.clear();
@@ -486,6 +487,7 @@ int build_plan(qg_handle *h) {
             if (r <= SMALL_R) {
                 pl.lvl_small_sn.push_back(s);
                 pl.lvl_small_maxr[L] = std::max<int32_t>(pl.lvl_small_maxr[L], (int32_t)r);
+                pl.lvl_small_rsum[L] += r;
             } else {
                 pl.lvl_large_sn.push_back(s);
                 const double rr = (double)r, kk = (double)(pl.sn_first[s + 1] - pl.sn_first[s]);

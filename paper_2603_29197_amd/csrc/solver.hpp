@@ -41,6 +41,7 @@ struct Plan {
     std::vector<int32_t> lvl_ptr, lvl_sn; // supernodes by level
     std::vector<int32_t> lvl_small_ptr, lvl_small_sn;   // small ones by level
     std::vector<int32_t> lvl_small_maxr;                // largest small front per level
+    std::vector<int64_t> lvl_small_rsum;                // rows of the small fronts per level, summed
     std::vector<int32_t> lvl_large_ptr, lvl_large_sn;   // large ones by level
     std::vector<int64_t> task_ptr;        // per level: column tasks (s, j)
     std::vector<int32_t> task_sn, task_col;
@@ -191,6 +192,7 @@ struct qg_handle {
     int32_t ncopy = 1;                 // problems in the batch (qg_setup_batch), 1 for qg_setup
     int32_t n1 = 0, m1 = 0, p1 = 0, l1 = 0;   // sizes of one problem of the batch
     int32_t nbig = 0;                  // SOCs handled one wavefront per cone
+    int32_t grp_q = 0;                 // > 0: every SOC has this many entries (<= 16): lane groups
     int64_t nbigchunk = 0;             // workgroups of the big cones' block writes
     bool solved = false;               // a solve finished (x, s, y, z valid)
     bool final_factor = false;         // the derivative system is factored (FP64)

@@ -112,19 +112,6 @@ __device__ inline void fwd_front(int32_t s, const int32_t *__restrict__ sn_first
     __builtin_amdgcn_wave_barrier();
 }
 
-template <typename T>
-__global__ void __launch_bounds__(64 * SW) fwd_small(
-    int32_t nfront, const int32_t *__restrict__ sn_list, const int32_t *__restrict__ sn_first,
-    const int64_t *__restrict__ sn_rptr, const int64_t *__restrict__ fr_off, const T *__restrict__ front,
-    const int64_t *__restrict__ task0, const int64_t *__restrict__ ctb_ptr, const int64_t *__restrict__ ctb_src,
-    double *__restrict__ vwork, double *__restrict__ xp) {
-    __shared__ double vsh[SW][SMALL_R];
-    const int w = threadIdx.x >> 6;
-    const int32_t q = blockIdx.x * SW + w;
-    if (q >= nfront) return;                   // whole wavefront
-    fwd_front<T>(sn_list[q], sn_first, sn_rptr, fr_off, front, task0, ctb_ptr, ctb_src, vwork, xp, vsh[w]);
-}
-
 // Backward: v = D^-1 x_own - L21' g (g = solution at the update rows; the
 // products with L21' are summed per column over the wavefront with a
 // butterfly), then the unit-upper solve with L11'.
@@ -174,18 +161,6 @@ __device__ inline void bwd_front(int32_t s, const int32_t *__restrict__ sn_first
         if (row < k) xp[f + row] = v[row];
     }
     __builtin_amdgcn_wave_barrier();
-}
-
-template <typename T>
-__global__ void __launch_bounds__(64 * SW) bwd_small(
-    int32_t nfront, const int32_t *__restrict__ sn_list, const int32_t *__restrict__ sn_first,
-    const int64_t *__restrict__ sn_rptr, const int32_t *__restrict__ sn_rows,
-    const int64_t *__restrict__ fr_off, const T *__restrict__ front, double *__restrict__ xp) {
-    __shared__ double vsh[SW][SMALL_R];
-    const int w = threadIdx.x >> 6;
-    const int32_t q = blockIdx.x * SW + w;
-    if (q >= nfront) return;                   // whole wavefront
-    bwd_front<T>(sn_list[q], sn_first, sn_rptr, sn_rows, fr_off, front, xp, vsh[w]);
 }
 
 // Chains (see factor_chain): one workgroup per component, its levels in
@@ -280,6 +255,35 @@ __device__ inline void bwd_front_chain(int32_t s, const int32_t *__restrict__ sn
         }
     }
     if (row < k) xp[f + row] = v;
+}
+
+// The level kernels of small fronts.  (The register path of the chains, all L
+// entries of a front loaded at once, was measured slower here: on a level of
+// 2e5 fronts of about four rows its 32 loads per lane cost 1.1 ms against
+// 0.11 ms for the backward sweep.)
+template <typename T>
+__global__ void __launch_bounds__(64 * SW) fwd_small(
+    int32_t nfront, const int32_t *__restrict__ sn_list, const int32_t *__restrict__ sn_first,
+    const int64_t *__restrict__ sn_rptr, const int64_t *__restrict__ fr_off, const T *__restrict__ front,
+    const int64_t *__restrict__ task0, const int64_t *__restrict__ ctb_ptr, const int64_t *__restrict__ ctb_src,
+    double *__restrict__ vwork, double *__restrict__ xp) {
+    __shared__ double vsh[SW][SMALL_R];
+    const int w = threadIdx.x >> 6;
+    const int32_t q = blockIdx.x * SW + w;
+    if (q >= nfront) return;                   // whole wavefront
+    fwd_front<T>(sn_list[q], sn_first, sn_rptr, fr_off, front, task0, ctb_ptr, ctb_src, vwork, xp, vsh[w]);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(64 * SW) bwd_small(
+    int32_t nfront, const int32_t *__restrict__ sn_list, const int32_t *__restrict__ sn_first,
+    const int64_t *__restrict__ sn_rptr, const int32_t *__restrict__ sn_rows,
+    const int64_t *__restrict__ fr_off, const T *__restrict__ front, double *__restrict__ xp) {
+    __shared__ double vsh[SW][SMALL_R];
+    const int w = threadIdx.x >> 6;
+    const int32_t q = blockIdx.x * SW + w;
+    if (q >= nfront) return;                   // whole wavefront
+    bwd_front<T>(sn_list[q], sn_first, sn_rptr, sn_rows, fr_off, front, xp, vsh[w]);
 }
 
 // Static data of one chain front for the forward solve, per lane (row): everything that does not

@@ -690,3 +690,43 @@ def test_solve_with_nested_dissection_matches_oracle(name, prec):
     ok, pres, dres, gap = oipm.stop_test(prob, r, host(s), 1e-8, 1e-8)
     assert ok, (pres, dres, gap)
     S.close()
+
+
+@pytest.mark.parametrize("q", [2, 3, 4, 5, 8, 13, 16])
+def test_lane_group_cone_kernels(q):
+    """Every cone with the same q <= 16 entries: NT scaling, lambda and the (3,3) block run on lane
+    groups of 2, 4, 8 or 16 (one lane per cone entry); against the oracle to the bounds of the
+    one-thread kernels, and against the one-thread kernels (cone_lanes = 0) to rounding, with the
+    W products and the line search that read the scaling.  l = 37 orthant entries put the cone
+    lanes past a partly used wavefront."""
+    import paper_2603_29197_amd as qg
+    prob = problems.many_soc(n=600, ncones=97, q=q, nbounds=37, seed=640 + q, windowed=False)
+    x, s, y, z = problems.random_point(prob, 8)
+    rng = np.random.default_rng(9)
+    cn = oc.Cones(prob.l, prob.q)
+    sc = oc.nt_scaling(cn, s, z)
+    orth, blocks = sc.block33()
+    want_k = okkt.kkt_upper(prob, orth, blocks).data
+    res = {}
+    for lanes in (1, 0):
+        S = solver(prob, cone_lanes=lanes)
+        lam = host(S.step_scaling(dev(s), dev(z)))
+        kv = S.step_get_kkt()
+        u = rng.standard_normal(prob.m) if lanes else res[1][3]
+        w_u = host(S.step_cone_op(0, dev(u)))
+        steps = []
+        for scale in (0.1, 1.0, 10.0):
+            du = np.random.default_rng(int(scale * 10)).standard_normal(prob.m) * scale
+            steps.append((S.step_max_step(dev(s), dev(du)), cn.max_step(s, du)))
+        res[lanes] = (lam, kv, w_u, u, steps)
+        assert relerr(lam, sc.lam) <= 1e-13
+        assert np.max(np.abs(kv - want_k)) <= 1e-13 * np.max(np.abs(want_k))
+        assert relerr(w_u, sc.W(u)) <= 1e-13
+        for a, b in steps:
+            assert (np.isinf(a) and np.isinf(b)) or abs(a - b) <= 1e-12 * max(1.0, b)
+        S.close()
+    (l1, k1, w1, _, st1), (l0, k0, w0, _, st0) = res[1], res[0]
+    assert relerr(l1, l0) <= 1e-14 and relerr(w1, w0) <= 1e-14
+    assert np.max(np.abs(k1 - k0)) <= 1e-14 * np.max(np.abs(k0))
+    for (a1, _), (a0, _) in zip(st1, st0):
+        assert (np.isinf(a1) and np.isinf(a0)) or abs(a1 - a0) <= 1e-13 * max(1.0, a0)

@@ -111,6 +111,9 @@ typedef struct {
     int cone_lanes;            /* 1: when every second-order cone of a single problem has the same
                                   2 <= q <= 16 entries, NT scaling and the (3,3) block run one lane per
                                   cone entry (lane groups of 2, 4, 8 or 16); 0: one thread per cone (1) */
+    int tiny_groups;           /* 1: elimination-tree levels with at least 2048 fronts of at most 16 rows
+                                  factor and solve those fronts 16 lanes per front; 0: one workgroup or
+                                  wavefront per front (1); read by qg_setup only, same arithmetic */
 } qg_settings;
 
 #define QG_STEP_MS_MAX 256

@@ -309,6 +309,7 @@ int qg_default_settings(qg_settings *s) {
     s->fp32_min_flops = 1e10;
     s->ordering = QG_ORDER_MD;
     s->cone_lanes = 1;
+    s->tiny_groups = 1;
     return QG_OK;
 }
 

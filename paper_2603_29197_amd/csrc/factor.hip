@@ -220,6 +220,61 @@ __global__ void __launch_bounds__(256) factor_small_wave(
     }
 }
 
+// Tiny fronts (r <= TINY_R): 16 lanes per front, 16 fronts per workgroup,
+// each front (assembled in the front storage by the level's gather) in its own
+// 16 x 16 LDS tile, with the arithmetic of factor_front_lds.  The four fronts
+// of a wavefront run their pivot loops together (masked past a front's own
+// pivot count); a wavefront's LDS operations complete in order, so the steps
+// need no barrier.
+template <typename T>
+__global__ void __launch_bounds__(256) factor_tiny(
+    int32_t nfront, const int32_t *__restrict__ sn_list, const int32_t *__restrict__ sn_first,
+    const int64_t *__restrict__ sn_rptr, const int64_t *__restrict__ fr_off, T *__restrict__ front,
+    const int8_t *__restrict__ kind, double eps, double dyn, int32_t *nreg) {
+    __shared__ T tile[16][TINY_R * TINY_R];
+    __shared__ T dsh[16];
+    const int g = threadIdx.x >> 4, gl = threadIdx.x & 15;
+    const int32_t q = blockIdx.x * 16 + g;
+    const bool has = q < nfront;
+    const int32_t s = has ? sn_list[q] : 0;
+    const int32_t r = has ? (int32_t)(sn_rptr[s + 1] - sn_rptr[s]) : 0;
+    const int32_t k = has ? sn_first[s + 1] - sn_first[s] : 0;
+    T *F = tile[g];
+    T *G = front + (has ? fr_off[s] : 0);
+    const int8_t *kd_s = kind + (has ? sn_first[s] : 0);
+    const int32_t rr = r * r;
+    T v[TINY_R];                                     // all loads in flight at once
+#pragma unroll
+    for (int u = 0; u < TINY_R; ++u) v[u] = ld_or0(G, gl + 16 * u, gl + 16 * u < rr);
+#pragma unroll
+    for (int u = 0; u < TINY_R; ++u) {
+        const int32_t idx = gl + 16 * u;
+        if (idx < rr) F[idx] = (idx % r >= idx / r) ? v[u] : T(0);
+    }
+    __builtin_amdgcn_wave_barrier();
+    for (int32_t jj = 0; jj < k; ++jj) {
+        if (gl == 0) {
+            const T d = regularize(F[jj * r + jj], kd_s[jj], eps, dyn, nreg);
+            F[jj * r + jj] = d;
+            dsh[g] = d;
+        }
+        __builtin_amdgcn_wave_barrier();
+        const T d = dsh[g];
+        const int32_t R = r - jj - 1;
+        for (int32_t idx = gl; idx < R * R; idx += 16) {
+            const int32_t i = jj + 1 + idx % R, cc = jj + 1 + idx / R;
+            if (i >= cc) F[cc * r + i] -= F[jj * r + i] * F[jj * r + cc] / d;
+        }
+        __builtin_amdgcn_wave_barrier();
+        for (int32_t i = jj + 1 + gl; i < r; i += 16) F[jj * r + i] /= d;
+        __builtin_amdgcn_wave_barrier();
+    }
+    for (int32_t idx = gl; idx < rr; idx += 16) {
+        const int32_t i = idx % r, cc = idx / r;
+        if (i >= cc) G[idx] = F[idx];
+    }
+}
+
 // Chains (the narrow upper levels of deep elimination trees): one workgroup
 // per component walks the component's levels; the fronts of a level are
 // factored one per wavefront, each in its own LDS tile, with the same
@@ -687,10 +742,9 @@ __global__ void __launch_bounds__(256) trail_update(T *__restrict__ F, int32_t r
     // row pitch of the LDS tiles: the four 16-lane groups of an MFMA operand read rows kk .. kk+3;
     // for 4-byte entries a pitch of 80 puts them on disjoint banks
     constexpr int LDT = sizeof(T) == 4 ? 80 : 64;
-    static_assert(SB == 256, "one pivot per thread of the 256-thread workgroup");
     __shared__ T As[2][KC * LDT];                  // As[kk * LDT + i] = L(r0 + i, k)
     __shared__ T Bs[2][KC * LDT];                  // Bs[kk * LDT + j] = L(c0 + j, k) * D(k)
-    __shared__ T Dk[SB];                           // D(k0 .. k0 + kb - 1), zero past the rank
+    __shared__ T Dk[OB];                           // D(k0 .. k0 + kb - 1), zero past the rank (kb <= OB)
     // Workgroup IDs are dealt to the 8 XCDs in turn; XCD x takes the tile rows ti = x (mod 8)
     // and walks them column tile by column tile, so its concurrent workgroups share the column
     // panel and keep their row panels in that XCD's L2.
@@ -733,7 +787,7 @@ __global__ void __launch_bounds__(256) trail_update(T *__restrict__ F, int32_t r
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = V{0, 0, 0, 0};
     const int32_t nch = (kb + KC - 1) / KC;
-    Dk[tid] = tid < kb ? F[(int64_t)(k0 + tid) * r + k0 + tid] : T(0);   // blockDim == SB
+    for (int32_t t = tid; t < OB; t += 256) Dk[t] = t < kb ? F[(int64_t)(k0 + t) * r + k0 + t] : T(0);
     gload(0);
     __syncthreads();
     lstore(0, 0);
@@ -807,10 +861,9 @@ __global__ void __launch_bounds__(256, 3) trail_update_big(float *__restrict__ F
     // row pitch of the LDS tiles: the four 16-lane groups of an MFMA operand read rows kk .. kk+3;
     // a pitch of 144 (16 mod 32 banks) puts each half-wavefront on disjoint banks
     constexpr int LDT = TILE + 16;
-    static_assert(SB == 256, "one pivot per thread of the 256-thread workgroup");
     __shared__ float As[2][KC * LDT];              // As[kk * LDT + i] = L(r0 + i, k)
     __shared__ float Bs[2][KC * LDT];              // Bs[kk * LDT + j] = L(c0 + j, k) * D(k)
-    __shared__ float Dk[SB];                       // D(k0 .. k0 + kb - 1), zero past the rank
+    __shared__ float Dk[OB];                       // D(k0 .. k0 + kb - 1), zero past the rank (kb <= OB)
     // XCD-aware order as in trail_update: XCD x takes the tile rows ti = x (mod 8)
     const int32_t TR = (r - r_lo + TILE - 1) / TILE, TC = (c_hi - r_lo + TILE - 1) / TILE, NR = (TR + 7) / 8;
     const int32_t xcd = blockIdx.x % 8, sq = blockIdx.x / 8;
@@ -854,7 +907,7 @@ __global__ void __launch_bounds__(256, 3) trail_update_big(float *__restrict__ F
 #pragma unroll
         for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = V{0, 0, 0, 0};
     const int32_t nch = (kb + KC - 1) / KC;
-    Dk[tid] = tid < kb ? F[(int64_t)(k0 + tid) * r + k0 + tid] : 0.f;   // blockDim == SB
+    for (int32_t t = tid; t < OB; t += 256) Dk[t] = t < kb ? F[(int64_t)(k0 + t) * r + k0 + t] : 0.f;
     gload(0);
     __syncthreads();
     lstore(0, 0);
@@ -1039,14 +1092,16 @@ static void launch_update(qg_handle *h, hipStream_t st, T *F, int32_t r, int32_t
     }
 }
 
-// Large front: super-panels of SB columns, each factored in NB-column
-// panels (diag_block, panel_solve, update of the rest of the super-panel) on
-// the main stream.  With lookahead: the rank-SB update of a super-panel is
-// split into the columns of the next super-panel (main stream, before that
-// super-panel is factored) and everything beyond (bulk stream), so the bulk
-// update of super-panel J runs while super-panel J+1 is factored.  The bulk
-// update of J and the next-columns update of J+1 touch the same columns, so
-// the latter waits for the former.  The inverses and W blocks that only the
+// Large front: outer blocks of OB columns, each made of super-panels of SB
+// columns, each factored in NB-column panels (diag_block, panel_solve, update
+// of the rest of the super-panel) on the main stream; a finished super-panel
+// updates the rest of its outer block (rank SB, main stream).  With
+// lookahead: the rank-OB update of an outer block is split into the columns
+// of the next outer block (main stream, before that block is factored) and
+// everything beyond (bulk stream), so the bulk update of outer block O runs
+// while outer block O+1 is factored.  The bulk update of O and the
+// next-columns update of O+1 touch the same columns, so the latter waits for
+// the former.  Every entry receives its updates in column order.  The inverses and W blocks that only the
 // solves need are formed on the prep stream.  Both side streams are joined at
 // the end.
 template <typename T>
@@ -1063,40 +1118,46 @@ static int factor_large(qg_handle *h, int32_t s, T *front, T *dinv, T *sinv, T *
     QG_HIP(h, hipEventRecord(h->ev_panel, ms));
     QG_HIP(h, hipStreamWaitEvent(h->bulk, h->ev_panel, 0));
     QG_HIP(h, hipStreamWaitEvent(h->prep, h->ev_panel, 0));
-    for (int32_t J0 = 0; J0 < k; J0 += SB) {
-        const int32_t J1 = std::min(k, J0 + SB);
-        for (int32_t j0 = J0; j0 < J1; j0 += NB) {
-            const int32_t b = std::min(NB, J1 - j0);
-            T *ws = dinv + pl.dinv_off[s] + (int64_t)(j0 / NB) * NB * NB;
-            diag_block<T><<<dim3(1, 1, ncopy), 256, 0, ms>>>(F, r, j0, b, kinds, rp.eps, rp.dyn, h->d.nreg.p, ws, cs);
-            const int32_t mb = r - j0 - b;
-            if (mb > 0) panel_solve<T><<<dim3((mb + 63) / 64, 1, ncopy), 256, 0, ms>>>(F, r, j0, b, ws, cs);
-            // rest of this super-panel's columns (rank b)
-            if (j0 + b < J1) launch_update<T>(h, ms, F, r, j0, b, j0 + b, J1, cs, ncopy);
-        }
-        QG_HIP(h, hipEventRecord(h->ev_panel, ms));
-        {
-            // solve-only data of this super-panel
-            QG_HIP(h, hipStreamWaitEvent(h->prep, h->ev_panel, 0));
-            const int32_t nsub = (J1 - J0 + NB - 1) / NB, ld = nsub * NB;
-            T *Xs = sinv + pl.sinv_off[s] + (int64_t)(J0 / SB) * 2 * SB * SB;
-            sblock_inverse<T><<<dim3(nsub, 1, ncopy), 256, 0, h->prep>>>(F, r, J0, J1 - J0, dinv + pl.dinv_off[s],
-                                                                        ld, Xs, Xs + (int64_t)ld * ld, cs);
-            if (J1 < r)
-                wblock<T><<<dim3((unsigned)((r - J1 + 63) / 64), (unsigned)nsub, ncopy), 256, 0, h->prep>>>(
-                    F, r, J0, J1 - J0, Xs, ld, wb + pl.w_off[s] + w_block_offset(r, J0), cs);
-        }
-        if (J1 < r) {
-            const int32_t J2 = std::min(r, J1 + SB);
-            // bulk: columns [J2, r), after this super-panel's panels
-            if (J2 < r) {
-                QG_HIP(h, hipStreamWaitEvent(h->bulk, h->ev_panel, 0));
-                launch_update<T>(h, h->bulk, F, r, J0, J1 - J0, J2, r, cs, ncopy);
+    for (int32_t O0 = 0; O0 < k; O0 += OB) {
+        const int32_t O1 = std::min(k, O0 + OB);
+        for (int32_t J0 = O0; J0 < O1; J0 += SB) {
+            const int32_t J1 = std::min(O1, J0 + SB);
+            for (int32_t j0 = J0; j0 < J1; j0 += NB) {
+                const int32_t b = std::min(NB, J1 - j0);
+                T *ws = dinv + pl.dinv_off[s] + (int64_t)(j0 / NB) * NB * NB;
+                diag_block<T><<<dim3(1, 1, ncopy), 256, 0, ms>>>(F, r, j0, b, kinds, rp.eps, rp.dyn, h->d.nreg.p, ws, cs);
+                const int32_t mb = r - j0 - b;
+                if (mb > 0) panel_solve<T><<<dim3((mb + 63) / 64, 1, ncopy), 256, 0, ms>>>(F, r, j0, b, ws, cs);
+                // rest of this super-panel's columns (rank b)
+                if (j0 + b < J1) launch_update<T>(h, ms, F, r, j0, b, j0 + b, J1, cs, ncopy);
             }
-            // next super-panel's columns [J1, J2): after the previous bulk update, which also wrote them
+            QG_HIP(h, hipEventRecord(h->ev_panel, ms));
+            {
+                // solve-only data of this super-panel
+                QG_HIP(h, hipStreamWaitEvent(h->prep, h->ev_panel, 0));
+                const int32_t nsub = (J1 - J0 + NB - 1) / NB, ld = nsub * NB;
+                T *Xs = sinv + pl.sinv_off[s] + (int64_t)(J0 / SB) * 2 * SB * SB;
+                sblock_inverse<T><<<dim3(nsub, 1, ncopy), 256, 0, h->prep>>>(F, r, J0, J1 - J0, dinv + pl.dinv_off[s],
+                                                                            ld, Xs, Xs + (int64_t)ld * ld, cs);
+                if (J1 < r)
+                    wblock<T><<<dim3((unsigned)((r - J1 + 63) / 64), (unsigned)nsub, ncopy), 256, 0, h->prep>>>(
+                        F, r, J0, J1 - J0, Xs, ld, wb + pl.w_off[s] + w_block_offset(r, J0), cs);
+            }
+            // the rest of this outer block's columns (rank J1 - J0), on the panel chain
+            if (J1 < O1) launch_update<T>(h, ms, F, r, J0, J1 - J0, J1, O1, cs, ncopy);
+        }
+        if (O1 < r) {
+            const int32_t O2 = std::min(r, O1 + OB);
+            QG_HIP(h, hipEventRecord(h->ev_panel, ms));
+            // bulk: columns [O2, r), after this outer block's panels
+            if (O2 < r) {
+                QG_HIP(h, hipStreamWaitEvent(h->bulk, h->ev_panel, 0));
+                launch_update<T>(h, h->bulk, F, r, O0, O1 - O0, O2, r, cs, ncopy);
+            }
+            // next outer block's columns [O1, O2): after the previous bulk update, which also wrote them
             if (bulk_pending) QG_HIP(h, hipStreamWaitEvent(ms, h->ev_bulk, 0));
-            launch_update<T>(h, ms, F, r, J0, J1 - J0, J1, J2, cs, ncopy);
-            if (J2 < r) {
+            launch_update<T>(h, ms, F, r, O0, O1 - O0, O1, O2, cs, ncopy);
+            if (O2 < r) {
                 QG_HIP(h, hipEventRecord(h->ev_bulk, h->bulk));
                 bulk_pending = true;
             } else {
@@ -1133,7 +1194,14 @@ static int factor_all(qg_handle *h, T *front, T *dinv, T *sinv, T *wb, const Reg
         if (ne > 0)
             gather_entries<T><<<(unsigned)((ne + 255) / 256), 256, 0, h->stream>>>(
                 e0, ne, d.ent_dst.p, d.ent_sptr.p, d.ent_reg.p, d.ent_src.p, d.kval.p, rp.delta, front);
-        const int32_t s0 = pl.lvl_small_ptr[L], s1 = pl.lvl_small_ptr[L + 1];
+        int32_t s0 = pl.lvl_small_ptr[L];
+        const int32_t s1 = pl.lvl_small_ptr[L + 1], nt = pl.lvl_tiny_cnt[L];
+        if (nt > 0) {
+            factor_tiny<T><<<(nt + 15) / 16, 256, 0, h->stream>>>(nt, d.lvl_small_sn.p + s0, d.sn_first.p,
+                                                                   d.sn_rptr.p, d.fr_off.p, front, d.reg_sign.p,
+                                                                   rp.eps, rp.dyn, d.nreg.p);
+            s0 += nt;
+        }
         if (s1 > s0 && pl.lvl_small_maxr[L] <= CHAIN_R && pl.lvl_small_rsum[L] <= 12 * (int64_t)(s1 - s0)) {
             factor_small_wave<T><<<(s1 - s0 + 3) / 4, 256, 0, h->stream>>>(
                 s1 - s0, d.lvl_small_sn.p + s0, d.sn_first.p, d.sn_rptr.p, d.fr_off.p, front, d.reg_sign.p, rp.eps,

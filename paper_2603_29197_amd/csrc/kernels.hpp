@@ -15,6 +15,10 @@ namespace qg {
 constexpr int SMALL_R = 128;
 constexpr int NB = 64;
 constexpr int SB = 256;
+// Outer blocks of large fronts: SB-column super-panels are factored four at a time; the columns
+// beyond an outer block receive its updates as one rank-OB update (fewer passes over the trailing
+// matrix than rank-SB updates).
+constexpr int OB = 1024;
 // Rows of the largest front: the trailing-update kernels address a front's columns with 32-bit byte
 // offsets (a larger front, 5.6e14 bytes in FP64, would not fit in any memory anyway).
 constexpr int32_t MAX_FRONT_R = (1 << 23) - 1;
@@ -24,6 +28,10 @@ constexpr int32_t MAX_FRONT_R = (1 << 23) - 1;
 constexpr int CHAIN_LEVEL_MIN = 1024;
 constexpr int CHAIN_R = 32;
 constexpr int CHAIN_WIDTH_MAX = 8;   // a component's fronts per level, on average
+// Tiny fronts (at most TINY_R rows) on levels that hold at least TINY_MIN of them: 16 lanes per
+// front, 16 fronts per 256-thread workgroup, in the factorization and both solve sweeps.
+constexpr int TINY_R = 16;
+constexpr int TINY_MIN = 2048;
 // Lanes per matrix row in the sparse matrix-vector products (16 rows per
 // 256-thread block) where a kernel has one fixed mapping; the residual
 // reductions choose 4 or 16 from the rows' average length.

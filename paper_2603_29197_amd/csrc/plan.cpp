@@ -474,6 +474,7 @@ int build_plan(qg_handle *h) {
     select_chains(pl, sym, h->st.chains != 0);
     pl.lvl_small_maxr.assign((size_t)pl.nlevels, 0);
     pl.lvl_small_rsum.assign((size_t)pl.nlevels, 0);
+    pl.lvl_tiny_cnt.assign((size_t)pl.nlevels, 0);
     pl.lvl_small_ptr.assign((size_t)pl.nlevels + 1, 0);
     pl.lvl_large_ptr.assign((size_t)pl.nlevels + 1, 0);
     pl.lvl_small_sn.clear();
@@ -497,6 +498,14 @@ int build_plan(qg_handle *h) {
         }
         pl.lvl_small_ptr[L + 1] = (int32_t)pl.lvl_small_sn.size();
         pl.lvl_large_ptr[L + 1] = (int32_t)pl.lvl_large_sn.size();
+        // fronts of at most TINY_R rows first; a level with at least TINY_MIN of them runs them on lane
+        // groups (the order of a level's small fronts does not matter: they are independent)
+        auto b = pl.lvl_small_sn.begin() + pl.lvl_small_ptr[L], e = pl.lvl_small_sn.begin() + pl.lvl_small_ptr[L + 1];
+        auto mid = std::stable_partition(b, e, [&](int32_t f) { return pl.sn_rptr[f + 1] - pl.sn_rptr[f] <= TINY_R; });
+        const int32_t nt = (int32_t)(mid - b);
+        pl.lvl_tiny_cnt[L] = (h->st.tiny_groups && nt >= TINY_MIN) ? nt : 0;
+        if (pl.lvl_tiny_cnt[L] > 0)   // the row sum then covers the other small fronts only
+            for (auto it = b; it != mid; ++it) pl.lvl_small_rsum[L] -= pl.sn_rptr[*it + 1] - pl.sn_rptr[*it];
     }
     // children (increasing index)
     pl.ch_ptr.assign((size_t)ns + 1, 0);

@@ -257,6 +257,75 @@ __device__ inline void bwd_front_chain(int32_t s, const int32_t *__restrict__ sn
     if (row < k) xp[f + row] = v;
 }
 
+// Tiny fronts (r <= TINY_R): 16 lanes per front, lane i holding row i, sixteen
+// fronts per workgroup; pivot values come from the front's own lanes by
+// shuffle.  Same operations in the same order as fwd_front and bwd_front (the
+// backward's column sums are the same butterfly restricted to the 16 lanes
+// that hold rows), hence the same values.
+template <typename T>
+__global__ void __launch_bounds__(256) fwd_tiny(
+    int32_t nfront, const int32_t *__restrict__ sn_list, const int32_t *__restrict__ sn_first,
+    const int64_t *__restrict__ sn_rptr, const int64_t *__restrict__ fr_off, const T *__restrict__ front,
+    const int64_t *__restrict__ task0, const int64_t *__restrict__ ctb_ptr, const int64_t *__restrict__ ctb_src,
+    double *__restrict__ vwork, double *__restrict__ xp) {
+    const int gl = threadIdx.x & 15, gb = (threadIdx.x & 63) & ~15;
+    const int32_t q = (blockIdx.x * 256 + threadIdx.x) >> 4;
+    const bool has = q < nfront;
+    const int32_t s = has ? sn_list[q] : 0;
+    const int32_t f = has ? sn_first[s] : 0;
+    const int32_t r = has ? (int32_t)(sn_rptr[s + 1] - sn_rptr[s]) : 0;
+    const int32_t k = has ? sn_first[s + 1] - f : 0;
+    const bool live = gl < r;
+    const int64_t t0 = has ? task0[s] : 0;
+    const T *F = front + (has ? fr_off[s] : 0);
+    double a = 0.0;
+    if (live) {
+        const int64_t tk = t0 + gl;
+        a = gl < k ? xp[f + gl] : 0.0;
+        for (int64_t u = ctb_ptr[tk]; u < ctb_ptr[tk + 1]; ++u) a += vwork[ctb_src[u]];
+    }
+#pragma unroll
+    for (int jj = 0; jj < TINY_R; ++jj) {
+        const double yj = __shfl(a, gb + jj);
+        if (jj < k && gl > jj && live) a -= (double)F[(int64_t)jj * r + gl] * yj;
+    }
+    if (gl < k) xp[f + gl] = a;
+    else if (live) vwork[t0 + gl] = a;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) bwd_tiny(
+    int32_t nfront, const int32_t *__restrict__ sn_list, const int32_t *__restrict__ sn_first,
+    const int64_t *__restrict__ sn_rptr, const int32_t *__restrict__ sn_rows,
+    const int64_t *__restrict__ fr_off, const T *__restrict__ front, double *__restrict__ xp) {
+    const int gl = threadIdx.x & 15, gb = (threadIdx.x & 63) & ~15;
+    const int32_t q = (blockIdx.x * 256 + threadIdx.x) >> 4;
+    const bool has = q < nfront;
+    const int32_t s = has ? sn_list[q] : 0;
+    const int32_t f = has ? sn_first[s] : 0;
+    const int32_t r = has ? (int32_t)(sn_rptr[s + 1] - sn_rptr[s]) : 0;
+    const int32_t k = has ? sn_first[s + 1] - f : 0;
+    const T *F = front + (has ? fr_off[s] : 0);
+    const bool upd = gl >= k && gl < r;
+    const double g = upd ? xp[sn_rows[sn_rptr[s] + gl]] : 0.0;
+    const double xo = gl < k ? xp[f + gl] : 0.0;
+    double v = 0.0;
+#pragma unroll
+    for (int c = 0; c < TINY_R; ++c) {
+        double p = 0.0;
+        if (c < k && upd) p += (double)F[(int64_t)c * r + gl] * g;
+        p += 0.0;                                     // the rows l + 64 of bwd_front (none here)
+        for (int off = 8; off > 0; off >>= 1) p += __shfl_xor(p, off);
+        if (c < k && gl == c) v = xo / (double)F[(int64_t)c * r + c] - p;
+    }
+#pragma unroll
+    for (int i = TINY_R - 1; i >= 0; --i) {
+        const double xi = __shfl(v, gb + i);
+        if (i < k && gl < i) v -= (double)F[(int64_t)gl * r + i] * xi;
+    }
+    if (gl < k) xp[f + gl] = v;
+}
+
 // The level kernels of small fronts.  (The register path of the chains, all L
 // entries of a front loaded at once, was measured slower here: on a level of
 // 2e5 fronts of about four rows its 32 loads per lane cost 1.1 ms against
@@ -645,7 +714,14 @@ static int solve_perm(qg_handle *h, const T *front, const T *sinv, const T *wbuf
             fwd_chain<T><<<(unsigned)nchain, 64 * SW, 0, h->stream>>>(
                 d.chain_comp_ptr.p, d.chain_grp_ptr.p, d.chain_sn.p, d.sn_first.p, d.sn_rptr.p, d.fr_off.p, front,
                 d.task0.p, d.ctb_ptr.p, d.ctb_src.p, d.vwork.p, xp);
-        const int32_t s0 = pl.lvl_small_ptr[L], s1 = pl.lvl_small_ptr[L + 1];
+        int32_t s0 = pl.lvl_small_ptr[L];
+        const int32_t s1 = pl.lvl_small_ptr[L + 1], nt = pl.lvl_tiny_cnt[L];
+        if (nt > 0) {
+            fwd_tiny<T><<<(nt + 15) / 16, 256, 0, h->stream>>>(nt, d.lvl_small_sn.p + s0, d.sn_first.p, d.sn_rptr.p,
+                                                                d.fr_off.p, front, d.task0.p, d.ctb_ptr.p,
+                                                                d.ctb_src.p, d.vwork.p, xp);
+            s0 += nt;
+        }
         if (s1 > s0)
             fwd_small<T><<<(s1 - s0 + SW - 1) / SW, 64 * SW, 0, h->stream>>>(s1 - s0, d.lvl_small_sn.p + s0, d.sn_first.p, d.sn_rptr.p,
                                                                d.fr_off.p, front, d.task0.p, d.ctb_ptr.p,
@@ -700,7 +776,13 @@ static int solve_perm(qg_handle *h, const T *front, const T *sinv, const T *wbuf
             bwd_chain<T><<<(unsigned)nchain, 64 * SW, 0, h->stream>>>(
                 d.chain_comp_ptr.p, d.chain_grp_ptr.p, d.chain_sn.p, d.sn_first.p, d.sn_rptr.p, d.sn_rows.p,
                 d.fr_off.p, front, xp);
-        const int32_t s0 = pl.lvl_small_ptr[L], s1 = pl.lvl_small_ptr[L + 1];
+        int32_t s0 = pl.lvl_small_ptr[L];
+        const int32_t s1 = pl.lvl_small_ptr[L + 1], nt = pl.lvl_tiny_cnt[L];
+        if (nt > 0) {
+            bwd_tiny<T><<<(nt + 15) / 16, 256, 0, h->stream>>>(nt, d.lvl_small_sn.p + s0, d.sn_first.p, d.sn_rptr.p,
+                                                                d.sn_rows.p, d.fr_off.p, front, xp);
+            s0 += nt;
+        }
         if (s1 > s0)
             bwd_small<T><<<(s1 - s0 + SW - 1) / SW, 64 * SW, 0, h->stream>>>(s1 - s0, d.lvl_small_sn.p + s0, d.sn_first.p, d.sn_rptr.p,
                                                           d.sn_rows.p, d.fr_off.p, front, xp);

@@ -730,3 +730,26 @@ def test_lane_group_cone_kernels(q):
     assert np.max(np.abs(k1 - k0)) <= 1e-14 * np.max(np.abs(k0))
     for (a1, _), (a0, _) in zip(st1, st0):
         assert (np.isinf(a1) and np.isinf(a0)) or abs(a1 - a0) <= 1e-13 * max(1.0, a0)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_tiny_front_lane_groups_give_the_level_kernels_bits(prec):
+    """Levels with thousands of fronts of at most 16 rows (the many-SOC pattern in nested
+    dissection: leaves of three to four rows) factor and solve them 16 lanes per front; with and
+    without the lane groups the whole solve is bit-identical and matches the oracle."""
+    import paper_2603_29197_amd as qg
+    prob = problems.many_soc(30000, 10000, 4, 10000, seed=problems.BASE_SEED + 18)
+    prec_c = qg.QG_FP64 if prec == "fp64" else qg.QG_FP32_IR
+    out = []
+    for tiny in (1, 0):
+        S = solver(prob, tiny_groups=tiny, precision=prec_c, ordering=qg.QG_ORDER_ND)
+        x, s, y, z, info = S.solve()
+        out.append((x.cpu().numpy(), z.cpu().numpy(), info))
+        print(f"[gpu] tiny_groups={tiny} {prec}: {info['status_name']} iters {info['iters']} "
+              f"step {info['ms_step_median']:.2f} ms", flush=True)
+        S.close()
+    (x1, z1, i1), (x0, z0, i0) = out
+    assert i1["status"] == 1 and i1["iters"] == i0["iters"]
+    assert np.array_equal(x1, x0) and np.array_equal(z1, z0)
+    ref = oipm.solve(prob)
+    assert relerr(x1, ref.x) <= 1e-6

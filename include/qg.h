@@ -114,6 +114,10 @@ typedef struct {
     int tiny_groups;           /* 1: elimination-tree levels with at least 2048 fronts of at most 16 rows
                                   factor and solve those fronts 16 lanes per front; 0: one workgroup or
                                   wavefront per front (1); read by qg_setup only, same arithmetic */
+    int graphs;                /* 1: the triangular solves, and the factorization when no front has more
+                                  than 1024 rows (no bulk trailing updates on a side stream), are captured
+                                  once per factor precision as HIP graphs and replayed (the factorization
+                                  not with profile = 1); 0: launched kernel by kernel (1); same arithmetic */
 } qg_settings;
 
 #define QG_STEP_MS_MAX 256

@@ -310,6 +310,7 @@ int qg_default_settings(qg_settings *s) {
     s->ordering = QG_ORDER_MD;
     s->cone_lanes = 1;
     s->tiny_groups = 1;
+    s->graphs = 1;
     return QG_OK;
 }
 
@@ -381,6 +382,7 @@ void qg_symbolic_free(qg_symbolic *sym) { delete sym; }
 
 void qg_cleanup(qg_handle *h) {
     if (!h) return;
+    drop_graphs(h);
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     if (h->bulk) (void)hipStreamSynchronize(h->bulk);
     if (h->prep) (void)hipStreamSynchronize(h->prep);
@@ -389,6 +391,7 @@ void qg_cleanup(qg_handle *h) {
         if (e) (void)hipEventDestroy(e);
     if (h->bulk) (void)hipStreamDestroy(h->bulk);
     if (h->prep) (void)hipStreamDestroy(h->prep);
+    if (h->cap) (void)hipStreamDestroy(h->cap);
     delete h;
 }
 
@@ -396,6 +399,7 @@ void qg_cleanup(qg_handle *h) {
 static int create_streams(qg_handle *h) {
     QG_HIP(h, hipStreamCreateWithFlags(&h->bulk, hipStreamNonBlocking));
     QG_HIP(h, hipStreamCreateWithFlags(&h->prep, hipStreamNonBlocking));
+    QG_HIP(h, hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
     QG_HIP(h, hipEventCreateWithFlags(&h->ev_panel, hipEventDisableTiming));
     QG_HIP(h, hipEventCreateWithFlags(&h->ev_bulk, hipEventDisableTiming));
     QG_HIP(h, hipEventCreateWithFlags(&h->ev_prep, hipEventDisableTiming));
@@ -603,6 +607,7 @@ int qg_update_vectors(qg_handle *h, const double *c, const double *b, const doub
 int qg_set_settings(qg_handle *h, const qg_settings *s) {
     if (!h || !s) return QG_ERR_ARG;
     h->st = *s;
+    drop_graphs(h);   // the captured launches hold the regularization parameters as arguments
     return QG_OK;
 }
 

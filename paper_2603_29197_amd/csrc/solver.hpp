@@ -172,7 +172,11 @@ struct qg_handle {
     // bulk = trailing updates beyond the next super-panel, prep = inverses and W blocks
     // for the solves; ordered against `stream` with the events below.
     hipStream_t bulk = nullptr, prep = nullptr;
+    hipStream_t cap = nullptr;          // graph capture only (nothing runs on it)
     hipEvent_t ev_panel = nullptr, ev_bulk = nullptr, ev_prep = nullptr;
+    // the factorization and the triangular solve (between the permutations) as HIP graphs, one per
+    // factor precision (0 FP64, 1 FP32), captured at first use and replayed (settings.graphs)
+    hipGraphExec_t g_factor[2] = {nullptr, nullptr}, g_solve[2] = {nullptr, nullptr};
     int last_hip = 0;
     int device = 0;
     // device memory of the handle: the caller's allocator (qg_setup), or hipMalloc when NULL
@@ -217,6 +221,10 @@ int hip_fail(qg_handle *h, hipError_t e);
     } while (0)
 
 void *dmem_alloc(qg_handle *h, size_t bytes);
+// Replay exec on the handle's stream, capturing it first from enqueue() (which launches work on the
+// handle's stream and on side streams joined to it by events) when it is not there yet.
+int graph_replay(qg_handle *h, hipGraphExec_t &exec, int (*enqueue)(qg_handle *, void *), void *arg);
+void drop_graphs(qg_handle *h);
 void dmem_free(qg_handle *h, void *p);
 template <typename T>
 int dalloc(qg_handle *h, DBuf<T> &b, size_t n);

@@ -278,6 +278,10 @@ __global__ void __launch_bounds__(256) fwd_tiny(
     const bool live = gl < r;
     const int64_t t0 = has ? task0[s] : 0;
     const T *F = front + (has ? fr_off[s] : 0);
+    // the row's L entries, all loads in flight before the elimination
+    double lc[TINY_R];
+#pragma unroll
+    for (int jj = 0; jj < TINY_R; ++jj) lc[jj] = (jj < k && gl > jj && live) ? (double)F[(int64_t)jj * r + gl] : 0.0;
     double a = 0.0;
     if (live) {
         const int64_t tk = t0 + gl;
@@ -287,7 +291,7 @@ __global__ void __launch_bounds__(256) fwd_tiny(
 #pragma unroll
     for (int jj = 0; jj < TINY_R; ++jj) {
         const double yj = __shfl(a, gb + jj);
-        if (jj < k && gl > jj && live) a -= (double)F[(int64_t)jj * r + gl] * yj;
+        if (jj < k && gl > jj && live) a -= lc[jj] * yj;
     }
     if (gl < k) xp[f + gl] = a;
     else if (live) vwork[t0 + gl] = a;
@@ -309,19 +313,26 @@ __global__ void __launch_bounds__(256) bwd_tiny(
     const bool upd = gl >= k && gl < r;
     const double g = upd ? xp[sn_rows[sn_rptr[s] + gl]] : 0.0;
     const double xo = gl < k ? xp[f + gl] : 0.0;
+    // the row's L entries L(gl, c) (update rows) and L(gl, i) (pivot rows, i > gl), and the pivot
+    // D(gl): all loads in flight before the sums
+    double lc[TINY_R];
+#pragma unroll
+    for (int c = 0; c < TINY_R; ++c)
+        lc[c] = ((c < k && upd) || (c < k && gl < c)) ? (double)F[upd ? (int64_t)c * r + gl : (int64_t)gl * r + c] : 0.0;
+    const double dg = gl < k ? (double)F[(int64_t)gl * r + gl] : 1.0;
     double v = 0.0;
 #pragma unroll
     for (int c = 0; c < TINY_R; ++c) {
         double p = 0.0;
-        if (c < k && upd) p += (double)F[(int64_t)c * r + gl] * g;
+        if (c < k && upd) p += lc[c] * g;
         p += 0.0;                                     // the rows l + 64 of bwd_front (none here)
         for (int off = 8; off > 0; off >>= 1) p += __shfl_xor(p, off);
-        if (c < k && gl == c) v = xo / (double)F[(int64_t)c * r + c] - p;
+        if (c < k && gl == c) v = xo / dg - p;
     }
 #pragma unroll
     for (int i = TINY_R - 1; i >= 0; --i) {
         const double xi = __shfl(v, gb + i);
-        if (i < k && gl < i) v -= (double)F[(int64_t)gl * r + i] * xi;
+        if (i < k && gl < i) v -= lc[i] * xi;
     }
     if (gl < k) xp[f + gl] = v;
 }
@@ -803,12 +814,21 @@ __global__ void scatter_perm(const double *__restrict__ xp, const int32_t *__res
     if (k < N) x[perm[k]] = xp[k];
 }
 
+static int enqueue_solve(qg_handle *h, void *arg) {
+    return *static_cast<const int *>(arg) == QG_FP32_IR
+               ? solve_perm<float>(h, h->d.front32.p, h->d.sinv32.p, h->d.w32.p)
+               : solve_perm<double>(h, h->d.front64.p, h->d.sinv64.p, h->d.w64.p);
+}
+
 int launch_solve(qg_handle *h, const double *rhs, double *x, int precision) {
     const int32_t N = h->N;
     const unsigned g = (unsigned)((N + 255) / 256);
     gather_perm<<<g, 256, 0, h->stream>>>(rhs, h->d.perm.p, h->d.xp.p, N);
-    int rc = precision == QG_FP32_IR ? solve_perm<float>(h, h->d.front32.p, h->d.sinv32.p, h->d.w32.p)
-                                     : solve_perm<double>(h, h->d.front64.p, h->d.sinv64.p, h->d.w64.p);
+    // the sweeps work on the permuted vector xp and the handle's own buffers only, so one capture per
+    // factor precision serves every right-hand side
+    int prec = precision;
+    int rc = h->st.graphs ? graph_replay(h, h->g_solve[precision == QG_FP32_IR ? 1 : 0], enqueue_solve, &prec)
+                          : enqueue_solve(h, &prec);
     if (rc) return rc;
     scatter_perm<<<g, 256, 0, h->stream>>>(h->d.xp.p, h->d.perm.p, x, N);
     QG_HIP(h, hipGetLastError());

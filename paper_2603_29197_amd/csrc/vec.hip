@@ -334,6 +334,42 @@ int launch_update(qg_handle *h, const double *dvec, const double *ds, double fra
     return QG_OK;
 }
 
+// HIP graphs of fixed launch sequences (no memset or copy nodes: kernels and event joins only)
+int graph_replay(qg_handle *h, hipGraphExec_t &exec, int (*enqueue)(qg_handle *, void *), void *arg) {
+    if (!exec) {
+        // captured on the handle's private stream (the caller's may be the legacy default stream, which
+        // cannot be captured), replayed on the caller's
+        hipGraph_t g = nullptr;
+        hipStream_t caller = h->stream;
+        QG_HIP(h, hipStreamBeginCapture(h->cap, hipStreamCaptureModeRelaxed));
+        h->stream = h->cap;
+        const int rc = enqueue(h, arg);
+        h->stream = caller;
+        const hipError_t e = hipStreamEndCapture(h->cap, &g);
+        if (rc) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess) return hip_fail(h, e);
+        const hipError_t ei = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ei != hipSuccess) {
+            exec = nullptr;
+            return hip_fail(h, ei);
+        }
+    }
+    QG_HIP(h, hipGraphLaunch(exec, h->stream));
+    return QG_OK;
+}
+
+void drop_graphs(qg_handle *h) {
+    for (int i = 0; i < 2; ++i) {
+        if (h->g_factor[i]) (void)hipGraphExecDestroy(h->g_factor[i]);
+        if (h->g_solve[i]) (void)hipGraphExecDestroy(h->g_solve[i]);
+        h->g_factor[i] = h->g_solve[i] = nullptr;
+    }
+}
+
 int refined_solve(qg_handle *h, const double *rhs, double *x, int precision, int ir_max, int *steps,
                   bool *ok) {
     int rc = launch_solve(h, rhs, x, precision);

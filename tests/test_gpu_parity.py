@@ -753,3 +753,32 @@ def test_tiny_front_lane_groups_give_the_level_kernels_bits(prec):
     assert np.array_equal(x1, x0) and np.array_equal(z1, z0)
     ref = oipm.solve(prob)
     assert relerr(x1, ref.x) <= 1e-6
+
+
+@pytest.mark.parametrize("name", ["small_qp", "lasso_s", "many_soc_s", "huber_t"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_graph_replays_give_the_launch_by_launch_bits(name, prec):
+    """The factorization (with its side streams on large fronts) and the triangular solves are
+    captured once per factor precision as HIP graphs and replayed on every Newton step, with the
+    step's other work and host synchronizations between the replays: the whole solve is
+    bit-identical to the launch-by-launch one, twice in a row on one handle, and again after a
+    settings change (which drops the captured graphs: the regularization is a launch argument)."""
+    import paper_2603_29197_amd as qg
+    prob = SMALL[name]()
+    prec_c = qg.QG_FP64 if prec == "fp64" else qg.QG_FP32_IR
+    res = {}
+    for graphs in (1, 0):
+        S = solver(prob, graphs=graphs, precision=prec_c)
+        runs = []
+        for _ in range(2):
+            x, s, y, z, info = S.solve()
+            runs.append((host(x), host(z), info["iters"], info["ir_steps"]))
+        S.set_settings(static_reg=3e-8, static_reg32=3e-4)
+        x, s, y, z, info = S.solve()
+        runs.append((host(x), host(z), info["iters"], info["ir_steps"]))
+        res[graphs] = runs
+        S.close()
+    for (x1, z1, i1, r1), (x0, z0, i0, r0) in zip(res[1], res[0]):
+        assert i1 == i0 and r1 == r0
+        assert np.array_equal(x1, x0) and np.array_equal(z1, z0)
+    assert np.array_equal(res[1][0][0], res[1][1][0])

@@ -50,7 +50,7 @@ PEAK_GBS = 8000.0
 # HBM bytes per launch of the FP32 128x128 kernel on the default workload: FETCH_SIZE + WRITE_SIZE, each scaled
 # by its reading for a 256 MiB device copy (rocprofv3 counter runs of this bench; null once the kernel or the
 # workload changes)
-TRAFFIC_BYTES_PER_LAUNCH = {"fp32": 2.156e9, "fp64": None}
+TRAFFIC_BYTES_PER_LAUNCH = {"fp32": 2.367e9, "fp64": None}
 WORKLOAD = "huber_l"
 WORKLOAD_TEXT = ("Huber QP (large-QP configuration's generator) F 100000x40000, 40 nnz per row, 5% outliers "
                  "(n=340000, p=100000, m=200000, N_K=640000); the configuration's F 500000x200000 needs "

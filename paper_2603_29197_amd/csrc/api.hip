@@ -392,6 +392,8 @@ void qg_cleanup(qg_handle *h) {
     if (h->bulk) (void)hipStreamDestroy(h->bulk);
     if (h->prep) (void)hipStreamDestroy(h->prep);
     if (h->cap) (void)hipStreamDestroy(h->cap);
+    if (h->ev_sync) (void)hipEventDestroy(h->ev_sync);
+    if (h->pin) (void)hipHostFree(h->pin);
     delete h;
 }
 
@@ -400,6 +402,8 @@ static int create_streams(qg_handle *h) {
     QG_HIP(h, hipStreamCreateWithFlags(&h->bulk, hipStreamNonBlocking));
     QG_HIP(h, hipStreamCreateWithFlags(&h->prep, hipStreamNonBlocking));
     QG_HIP(h, hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
+    QG_HIP(h, hipEventCreateWithFlags(&h->ev_sync, hipEventDisableTiming));
+    QG_HIP(h, hipHostMalloc((void **)&h->pin, PIN_DOUBLES * sizeof(double), hipHostMallocDefault));
     QG_HIP(h, hipEventCreateWithFlags(&h->ev_panel, hipEventDisableTiming));
     QG_HIP(h, hipEventCreateWithFlags(&h->ev_bulk, hipEventDisableTiming));
     QG_HIP(h, hipEventCreateWithFlags(&h->ev_prep, hipEventDisableTiming));

@@ -29,7 +29,9 @@ namespace qg {
 namespace {
 
 struct Events {
-    hipEvent_t e[8] = {};
+    // 0-7: phases; 8-13: the Newton steps' start, cone-phase start and end, two sets used in turn
+    // (a step's times are read after the next step's first wait); 14-15: the scaling kernel
+    hipEvent_t e[16] = {};
     bool ok = false;
     void create() {
         ok = true;
@@ -102,7 +104,9 @@ static int solve_with(qg_handle *h, const double *rhs, double *x, int prec, int 
     int rc = refined_solve(h, rhs, x, prec, ir_max, &steps, prec == QG_FP32_IR ? &ok : nullptr);
     if (rc) return rc;
     (void)hipEventRecord(ev.e[5], h->stream);
-    (void)hipEventSynchronize(ev.e[5]);   // the refinement test has drained the stream up to here
+    // the refinement test has drained the stream up to here: the event completes at once (polled)
+    while (hipEventQuery(ev.e[5]) == hipErrorNotReady) {
+    }
     work.tri[prec == QG_FP32_IR ? 1 : 0] += 1 + steps;     // the solve and one per correction
     work.residuals += steps + 1;                           // one per correction and the last test
     *ir_total += steps;
@@ -196,9 +200,23 @@ int ipm_solve(qg_handle *h, double *xo, double *so, double *yo, double *zo, qg_i
     }
     double *dvec = d.sol.p;               // Newton direction (N)
     const double *dz_of = dvec + n + p;
+    int pending = -1, pending_is32 = 0;   // event set of the last Newton step, its times not read yet
+    auto consume_step = [&]() {
+        if (pending < 0) return;
+        hipEvent_t *T = ev.e + 8 + 3 * pending;
+        ms_cone += elapsed(T[1], T[2]);
+        const double sm = elapsed(T[0], T[2]);
+        step_ms.push_back(sm);
+        step_is32.push_back(pending_is32);
+        (pending_is32 ? step32 : step64).push_back(sm);
+        pending = -1;
+    };
     while (true) {
-        (void)hipEventRecord(ev.e[0], h->stream);
+        const int par = it & 1;
+        hipEvent_t *T = ev.e + 8 + 3 * par;
+        (void)hipEventRecord(T[0], h->stream);
         if ((rc = launch_residual(h, d.x.p, d.y.p, d.z.p, d.s.p, scal_all.data()))) return fail(rc);
+        consume_step();                    // the wait in launch_residual has passed the last step's end
         combine();
         sr = stop_test(h, scal, st.eps_abs, st.eps_rel);
         if (kb > 1) sr.ok = all_pass(st.eps_abs, st.eps_rel);
@@ -224,18 +242,18 @@ int ipm_solve(qg_handle *h, double *xo, double *so, double *yo, double *zo, qg_i
         if (!fp64_only && gscaled < st.switch_gap) fp64_only = true;
         prec = fp64_only ? QG_FP64 : QG_FP32_IR;
         if (prec == QG_FP64 && switch_iter < 0 && st.precision == QG_FP32_IR) switch_iter = it;
-        // scaling + (3,3) block, once per iteration
-        (void)hipEventRecord(ev.e[6], h->stream);
+        // scaling + (3,3) block, once per iteration (its time is read after the affine solve's wait)
+        (void)hipEventRecord(ev.e[14], h->stream);
         if ((rc = launch_scaling(h, d.s.p, d.z.p, d.lam.p, 0))) return fail(rc);
-        (void)hipEventRecord(ev.e[7], h->stream);
-        QG_HIP(h, hipEventSynchronize(ev.e[7]));
-        ms_cone += elapsed(ev.e[6], ev.e[7]);
+        (void)hipEventRecord(ev.e[15], h->stream);
+        bool scaling_timed = false;
         // Newton step; an FP32 factor whose refinement fails its test makes
         // the whole step run again with an FP64 factor (and FP64 from then on)
         for (int attempt = 0; attempt < 2; ++attempt) {
             (void)hipEventRecord(ev.e[2], h->stream);
             if ((rc = launch_factor(h, prec))) return fail(rc);
             (void)hipEventRecord(ev.e[3], h->stream);
+            if ((rc = nreg_async(h))) return fail(rc);
             ++nfactor;
             // affine direction
             if ((rc = launch_build_rhs(h, d.s.p, 1.0, d.rhs.p))) return fail(rc);
@@ -243,9 +261,11 @@ int ipm_solve(qg_handle *h, double *xo, double *so, double *yo, double *zo, qg_i
             if ((rc = solve_with(h, d.rhs.p, dvec, prec, &ir_total, &failed, ev, &ms_solve, work))) return fail(rc);
             ++nsolve;
             ms_factor += elapsed(ev.e[2], ev.e[3]);
-            int nr = 0;
-            if ((rc = read_nreg(h, &nr))) return fail(rc);
-            nreg_total += nr;
+            if (!scaling_timed) {
+                ms_cone += elapsed(ev.e[14], ev.e[15]);
+                scaling_timed = true;
+            }
+            nreg_total += nreg_pinned(h);   // copied before the solve, which has been waited for
             if (!failed) {
                 (void)hipEventRecord(ev.e[6], h->stream);
                 if ((rc = launch_ds_from_dz(h, d.s.p, -1.0, dz_of, d.dsa.p))) return fail(rc);
@@ -268,18 +288,14 @@ int ipm_solve(qg_handle *h, double *xo, double *so, double *yo, double *zo, qg_i
             }
             break;
         }
-        (void)hipEventRecord(ev.e[6], h->stream);
+        (void)hipEventRecord(T[1], h->stream);
         if ((rc = launch_ds_from_dz(h, d.t.p, 1.0, dz_of, d.ds.p))) return fail(rc);
         if ((rc = launch_step_min(h, d.s.p, d.ds.p, 2))) return fail(rc);
         if ((rc = launch_step_min(h, d.z.p, dz_of, 3))) return fail(rc);
         if ((rc = launch_update(h, dvec, d.ds.p, st.step_frac, d.alpha.p + 1))) return fail(rc);
-        (void)hipEventRecord(ev.e[1], h->stream);
-        QG_HIP(h, hipEventSynchronize(ev.e[1]));
-        ms_cone += elapsed(ev.e[6], ev.e[1]);
-        const double sm = elapsed(ev.e[0], ev.e[1]);
-        step_ms.push_back(sm);
-        step_is32.push_back(prec == QG_FP32_IR ? 1 : 0);
-        (prec == QG_FP32_IR ? step32 : step64).push_back(sm);
+        (void)hipEventRecord(T[2], h->stream);
+        pending = par;                     // no wait here: the next residual's wait covers it
+        pending_is32 = prec == QG_FP32_IR ? 1 : 0;
         ++it;
     }
     // outputs

@@ -174,6 +174,8 @@ struct qg_handle {
     hipStream_t bulk = nullptr, prep = nullptr;
     hipStream_t cap = nullptr;          // graph capture only (nothing runs on it)
     hipEvent_t ev_panel = nullptr, ev_bulk = nullptr, ev_prep = nullptr;
+    hipEvent_t ev_sync = nullptr;       // host waits on the handle's stream (polled, see stream_wait)
+    double *pin = nullptr;              // pinned host memory for small read-backs (PIN_DOUBLES doubles)
     // the factorization and the triangular solve (between the permutations) as HIP graphs, one per
     // factor precision (0 FP64, 1 FP32), captured at first use and replayed (settings.graphs)
     hipGraphExec_t g_factor[2] = {nullptr, nullptr}, g_solve[2] = {nullptr, nullptr};
@@ -248,6 +250,16 @@ int launch_cone_op(qg_handle *h, int op, const double *u, const double *v, doubl
 int launch_corrector(qg_handle *h, const double *dsa, const double *dza, double sigma_mu,
                      const double *mu_dev, double *t);
 int read_nreg(qg_handle *h, int *nreg);
+// Pinned read-back slots (doubles): the residual scalars of each problem, then the refinement norms,
+// then the dynamic-regularization count of the last factorization.
+constexpr int PIN_DOUBLES = 512;
+// Wait on the host for everything enqueued on the handle's stream so far, polling an event (a
+// blocking wait sleeps and wakes up tens of microseconds late, once or more per Newton step).
+int stream_wait(qg_handle *h);
+// Copy the dynamic-regularization count of the last factorization to the pinned slot (read after the
+// next wait), and read it.
+int nreg_async(qg_handle *h);
+int nreg_pinned(const qg_handle *h);
 int factor_init_attributes(qg_handle *h);
 void prof_collect(qg_handle *h, int64_t *launches, double *ms, double *flops);
 

@@ -9,6 +9,7 @@
 #include "vec.hpp"
 
 #include <cmath>
+#include <cstring>
 
 namespace qg {
 
@@ -282,9 +283,11 @@ int launch_residual(qg_handle *h, const double *x, const double *y, const double
             d.rz.p, d.partials.p, kb, n1, p1, m1, l1);
     finish_reduce<<<(unsigned)kb, 256, 0, h->stream>>>(d.partials.p, nblk, NSCAL, SCAL_MAXMASK, d.scal_inst.p);
     QG_HIP(h, hipGetLastError());
-    QG_HIP(h, hipMemcpyAsync(scal_host, d.scal_inst.p, (size_t)kb * NSCAL * sizeof(double),
-                             hipMemcpyDeviceToHost, h->stream));
-    QG_HIP(h, hipStreamSynchronize(h->stream));
+    const size_t nv = (size_t)kb * NSCAL;
+    double *dst = nv + 4 <= (size_t)PIN_DOUBLES ? h->pin : scal_host;   // large batches: pageable
+    QG_HIP(h, hipMemcpyAsync(dst, d.scal_inst.p, nv * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    if (int rc = stream_wait(h)) return rc;
+    if (dst != scal_host) std::memcpy(scal_host, dst, nv * sizeof(double));
     return QG_OK;
 }
 
@@ -303,8 +306,11 @@ int launch_kkt_residual(qg_handle *h, const double *rhs, const double *sol, doub
                                                              d.soc_off.p, d.zcone.p, rhs, sol, res, d.partials.p);
     finish_reduce<<<1, 256, 0, h->stream>>>(d.partials.p, nblk, 2, 3u, d.scal.p + NSCAL);
     QG_HIP(h, hipGetLastError());
-    QG_HIP(h, hipMemcpyAsync(norms, d.scal.p + NSCAL, 2 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
-    QG_HIP(h, hipStreamSynchronize(h->stream));
+    double *pn = h->pin + PIN_DOUBLES - 4;
+    QG_HIP(h, hipMemcpyAsync(pn, d.scal.p + NSCAL, 2 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    if (int rc = stream_wait(h)) return rc;
+    norms[0] = pn[0];
+    norms[1] = pn[1];
     return QG_OK;
 }
 
@@ -332,6 +338,27 @@ int launch_update(qg_handle *h, const double *dvec, const double *ds, double fra
                                                           h->p / kb, h->m / kb, h->pp.l / kb, d.mu.p + kb);
     QG_HIP(h, hipGetLastError());
     return QG_OK;
+}
+
+int stream_wait(qg_handle *h) {
+    QG_HIP(h, hipEventRecord(h->ev_sync, h->stream));
+    hipError_t e;
+    while ((e = hipEventQuery(h->ev_sync)) == hipErrorNotReady) {
+    }
+    QG_HIP(h, e);
+    return QG_OK;
+}
+
+int nreg_async(qg_handle *h) {
+    QG_HIP(h, hipMemcpyAsync(h->pin + PIN_DOUBLES - 2, h->d.nreg.p, sizeof(int32_t), hipMemcpyDeviceToHost,
+                             h->stream));
+    return QG_OK;
+}
+
+int nreg_pinned(const qg_handle *h) {
+    int32_t v;
+    std::memcpy(&v, h->pin + PIN_DOUBLES - 2, sizeof(int32_t));
+    return v;
 }
 
 // HIP graphs of fixed launch sequences (no memset or copy nodes: kernels and event joins only)

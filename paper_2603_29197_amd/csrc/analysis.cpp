@@ -27,6 +27,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <numeric>
 #include <set>
@@ -326,10 +327,16 @@ void min_degree_order(int32_t N, const std::vector<int64_t> &Gp, const std::vect
     std::mutex elist_mu;
     // Loops over Lp whose iterations are independent run on the pool when Lp is long (the
     // dense final phase, where Lp holds most of the remaining variables).
-    WorkPool pool(WorkPool::default_threads());
+    // The pool's threads are started at the first long pivot step only: small graphs (the pieces of
+    // a nested dissection, thousands of calls) never start them.
+    std::unique_ptr<WorkPool> pool_;
+    auto pool = [&]() -> WorkPool & {
+        if (!pool_) pool_.reset(new WorkPool(WorkPool::default_threads()));
+        return *pool_;
+    };
     constexpr size_t PAR_MIN = 2048;
     auto for_lp = [&](const std::function<void(int64_t, int64_t)> &fn) {
-        if (Lp.size() >= PAR_MIN) pool.run((int64_t)Lp.size(), fn);
+        if (Lp.size() >= PAR_MIN) pool().run((int64_t)Lp.size(), fn);
         else fn(0, (int64_t)Lp.size());
     };
     while (!pq.heap.empty()) {
@@ -495,7 +502,7 @@ void min_degree_order(int32_t N, const std::vector<int64_t> &Gp, const std::vect
                 std::lock_guard<std::mutex> lk(elist_mu);
                 elist.insert(elist.end(), mine.begin(), mine.end());
             });
-            pool.run((int64_t)elist.size(), [&](int64_t t0, int64_t t1) {
+            pool().run((int64_t)elist.size(), [&](int64_t t0, int64_t t1) {
                 for (int64_t t = t0; t < t1; ++t) {
                     const int32_t e = elist[(size_t)t];
                     int64_t w = g.wtot[e];

@@ -19,6 +19,7 @@ constexpr int SB = 256;
 // beyond an outer block receive its updates as one rank-OB update (fewer passes over the trailing
 // matrix than rank-SB updates).
 constexpr int OB = 1024;
+constexpr int32_t OB_WIDE_R = 16384;   // fronts of 1024 < r <= OB_WIDE_R use outer blocks of SB columns
 // Rows of the largest front: the trailing-update kernels address a front's columns with 32-bit byte
 // offsets (a larger front, 5.6e14 bytes in FP64, would not fit in any memory anyway).
 constexpr int32_t MAX_FRONT_R = (1 << 23) - 1;

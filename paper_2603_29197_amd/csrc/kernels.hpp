@@ -33,6 +33,9 @@ constexpr int CHAIN_WIDTH_MAX = 8;   // a component's fronts per level, on avera
 // front, 16 fronts per 256-thread workgroup, in the factorization and both solve sweeps.
 constexpr int TINY_R = 16;
 constexpr int TINY_MIN = 2048;
+// Levels with fewer small fronts than this (all of at most CHAIN_R rows) solve them on the register
+// path of the chains.
+constexpr int REG_LEVEL_MAX = 4096;
 // Lanes per matrix row in the sparse matrix-vector products (16 rows per
 // 256-thread block) where a kernel has one fixed mapping; the residual
 // reductions choose 4 or 16 from the rows' average length.

@@ -366,6 +366,23 @@ __global__ void __launch_bounds__(64 * SW) bwd_small(
     bwd_front<T>(sn_list[q], sn_first, sn_rptr, sn_rows, fr_off, front, xp, vsh[w]);
 }
 
+// Forward sweep, small fronts on levels with few of them (fewer than REG_LEVEL_MAX, all of at most
+// CHAIN_R rows): the register path of the chains, one wavefront per front, every L entry of a lane's
+// row loaded at once instead of one dependent load per elimination step; the same bits as fwd_front.
+// (On levels of many small fronts its 32 loads per lane cost more than the steps they save; in the
+// backward sweep, whose register path also loads each lane's L row with strided loads, it was
+// measured slower on every level: many-SOC 10.9 -> 14.5 us per level on average.)
+template <typename T>
+__global__ void __launch_bounds__(64 * SW) fwd_small_reg(
+    int32_t nfront, const int32_t *__restrict__ sn_list, const int32_t *__restrict__ sn_first,
+    const int64_t *__restrict__ sn_rptr, const int64_t *__restrict__ fr_off, const T *__restrict__ front,
+    const int64_t *__restrict__ task0, const int64_t *__restrict__ ctb_ptr, const int64_t *__restrict__ ctb_src,
+    double *__restrict__ vwork, double *__restrict__ xp) {
+    const int32_t q = blockIdx.x * SW + (threadIdx.x >> 6);
+    if (q >= nfront) return;                   // whole wavefront
+    fwd_front_chain<T>(sn_list[q], sn_first, sn_rptr, fr_off, front, task0, ctb_ptr, ctb_src, vwork, xp);
+}
+
 // Static data of one chain front for the forward solve, per lane (row): everything that does not
 // depend on the solve's progress (the L entries, the front's own right-hand side entry, the range of
 // the row's contributions in the work vector and the positions of its first two).
@@ -733,7 +750,12 @@ static int solve_perm(qg_handle *h, const T *front, const T *sinv, const T *wbuf
                                                                 d.ctb_src.p, d.vwork.p, xp);
             s0 += nt;
         }
-        if (s1 > s0)
+        const bool reg = s1 - s0 < REG_LEVEL_MAX && pl.lvl_small_maxr[L] <= CHAIN_R;
+        if (s1 > s0 && reg)
+            fwd_small_reg<T><<<(s1 - s0 + SW - 1) / SW, 64 * SW, 0, h->stream>>>(
+                s1 - s0, d.lvl_small_sn.p + s0, d.sn_first.p, d.sn_rptr.p, d.fr_off.p, front, d.task0.p, d.ctb_ptr.p,
+                d.ctb_src.p, d.vwork.p, xp);
+        else if (s1 > s0)
             fwd_small<T><<<(s1 - s0 + SW - 1) / SW, 64 * SW, 0, h->stream>>>(s1 - s0, d.lvl_small_sn.p + s0, d.sn_first.p, d.sn_rptr.p,
                                                                d.fr_off.p, front, d.task0.p, d.ctb_ptr.p,
                                                                d.ctb_src.p, d.vwork.p, xp);

@@ -351,6 +351,13 @@ def main():
                     "small_tile_kernel": {"kernel": "trail_update<float>", "launches": ls,
                                           "achieved": round(as_, 2),
                                           "avg_launch_us": round(1e3 * mss / max(1, ls), 2)},
+                    # the whole FP32 factorizations of the profiled solve (initial + 2 steps): the factor
+                    # flops over their wall time between events on the caller's stream (every stream joined)
+                    "whole_factorizations_fp32": {
+                        "achieved": round(p32["factor_flops"] * p32["nfactor"] / (p32["ms_factor"] * 1e-3) / 1e12, 2),
+                        "frac": round(p32["factor_flops"] * p32["nfactor"] / (p32["ms_factor"] * 1e-3) / 1e12
+                                      / PEAK_TFLOPS["fp32"], 4),
+                        "ms_per_factorization": round(p32["ms_factor"] / max(1, p32["nfactor"]), 2)},
                     "all_trailing_updates_fp32": {"achieved": round((flb + fls) / ((msb + mss) * 1e-3) / 1e12, 2),
                                                   "frac": round((flb + fls) / ((msb + mss) * 1e-3) / 1e12
                                                                 / PEAK_TFLOPS["fp32"], 4)}}

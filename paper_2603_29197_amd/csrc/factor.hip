@@ -990,8 +990,9 @@ __global__ void __launch_bounds__(256) wblock(const T *__restrict__ F, int32_t r
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = V{0, 0, 0, 0};
-    for (int32_t kc = 64 * tc; kc < kb; kc += KC) {
-        T av[PER], bv[PER];
+    // the next chunk's loads are issued before the current chunk's products (one register stage)
+    T av[PER], bv[PER];
+    auto gload = [&](int32_t kc) {
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
             const int e = tid + 256 * u;
@@ -1000,6 +1001,9 @@ __global__ void __launch_bounds__(256) wblock(const T *__restrict__ F, int32_t r
             const int kb_ = e & (KC - 1), j = e / KC;                 // B: lanes along ranks
             bv[u] = ld_or0(Xs, (int64_t)(64 * tc + j) * ld + kc + kb_, kc + kb_ < kb && 64 * tc + j < kb);
         }
+    };
+    if (64 * tc < kb) gload(64 * tc);
+    for (int32_t kc = 64 * tc; kc < kb; kc += KC) {
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
@@ -1008,6 +1012,7 @@ __global__ void __launch_bounds__(256) wblock(const T *__restrict__ F, int32_t r
             Bs[(e & (KC - 1)) * 65 + e / KC] = bv[u];
         }
         __syncthreads();
+        if (kc + KC < kb) gload(kc + KC);
 #pragma unroll
         for (int kk = 0; kk < KC; kk += 4) {
             const int kq = kk + lk;

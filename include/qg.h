@@ -118,9 +118,19 @@ typedef struct {
                                   than 1024 rows (no bulk trailing updates on a side stream), are captured
                                   once per factor precision as HIP graphs and replayed (the factorization
                                   not with profile = 1); 0: launched kernel by kernel (1); same arithmetic */
+    int ruiz_iters;            /* 1..QG_RUIZ_MAX: Ruiz equilibration of the data with this many passes;
+                                  0: none (0).  Columns of [P A' G'; A; G] and rows of A and G are divided
+                                  by the square roots of their largest magnitudes (one factor per
+                                  second-order cone), the objective by max(1, |D c|_inf).  The
+                                  interior-point method runs on the scaled problem; the stopping test,
+                                  qg_info and qg_solve's outputs are in the caller's units, while the
+                                  step-level calls see the scaled KKT matrix.  Read by qg_setup only (the
+                                  scalings are formed again by qg_update with new matrix values); not with
+                                  qg_setup_batch or differentiable = 1 (QG_ERR_ARG) */
 } qg_settings;
 
 #define QG_STEP_MS_MAX 256
+#define QG_RUIZ_MAX 100
 
 typedef struct {
     int status;                /* QG_SOLVED, ... */

@@ -47,7 +47,8 @@ class qg_settings(ctypes.Structure):
                 ("ir_tol", ctypes.c_double), ("step_frac", ctypes.c_double), ("differentiable", ctypes.c_int),
                 ("verbose", ctypes.c_int), ("profile", ctypes.c_int), ("chains", ctypes.c_int),
                 ("fp32_min_flops", ctypes.c_double), ("ordering", ctypes.c_int),
-                ("cone_lanes", ctypes.c_int), ("tiny_groups", ctypes.c_int), ("graphs", ctypes.c_int)]
+                ("cone_lanes", ctypes.c_int), ("tiny_groups", ctypes.c_int), ("graphs", ctypes.c_int),
+                ("ruiz_iters", ctypes.c_int)]
 
 
 class qg_info(ctypes.Structure):

@@ -311,6 +311,7 @@ int qg_default_settings(qg_settings *s) {
     s->cone_lanes = 1;
     s->tiny_groups = 1;
     s->graphs = 1;
+    s->ruiz_iters = 0;
     return QG_OK;
 }
 
@@ -418,10 +419,13 @@ int qg_setup(qg_handle **out, qg_int n, qg_int m, qg_int p, const qg_csc *P, con
     *out = nullptr;
     if ((alloc == nullptr) != (free_fn == nullptr)) return QG_ERR_ARG;
     if (s && s->ordering != QG_ORDER_MD && s->ordering != QG_ORDER_ND) return QG_ERR_ARG;
+    if (s && (s->ruiz_iters < 0 || s->ruiz_iters > QG_RUIZ_MAX || (s->ruiz_iters > 0 && s->differentiable)))
+        return QG_ERR_ARG;
     const auto t0 = std::chrono::steady_clock::now();
     qg_handle *h = new (std::nothrow) qg_handle();
     if (!h) return QG_ERR_OOM;
     if (s) h->st = *s; else qg_default_settings(&h->st);
+    h->ruiz = h->st.ruiz_iters;
     h->stream = (hipStream_t)hip_stream;
     h->alloc = alloc;
     h->free_fn = free_fn;
@@ -480,6 +484,7 @@ int qg_setup_batch(qg_handle **out, qg_int k, qg_int n, qg_int m, qg_int p, cons
     if (k < 1 || n < 0 || m < 0 || p < 0 || l < 0 || nsoc < 0) return QG_ERR_ARG;
     if ((alloc == nullptr) != (free_fn == nullptr)) return QG_ERR_ARG;
     if (s && s->ordering != QG_ORDER_MD && s->ordering != QG_ORDER_ND) return QG_ERR_ARG;
+    if (s && s->ruiz_iters != 0) return QG_ERR_ARG;
     if ((int64_t)k * (n + m + p) > INT32_MAX) return QG_ERR_ARG;
     const auto t0 = std::chrono::steady_clock::now();
     qg_handle *h = new (std::nothrow) qg_handle();
@@ -580,14 +585,19 @@ int qg_update(qg_handle *h, const double *Pval, const double *c, const double *A
     if (Gval) h->pp.G.val.assign(Gval, Gval + h->pp.G.val.size());
     h->solved = false;
     h->final_factor = false;
+    // vectors go straight into the device copies (the host copies only serve setup); with Ruiz
+    // equilibration into the caller's-units copies, and the scalings are formed again after them
+    const bool rz = h->ruiz > 0;
+    if (c && h->n > 0) QG_HIP(h, hipMemcpyAsync((rz ? h->d.craw : h->d.c).p, c, sizeof(double) * h->n, hipMemcpyHostToDevice, h->stream));
+    if (b && h->p > 0) QG_HIP(h, hipMemcpyAsync((rz ? h->d.braw : h->d.b).p, b, sizeof(double) * h->p, hipMemcpyHostToDevice, h->stream));
+    if (hv && h->m > 0) QG_HIP(h, hipMemcpyAsync((rz ? h->d.hraw : h->d.h).p, hv, sizeof(double) * h->m, hipMemcpyHostToDevice, h->stream));
     if (Pval || Aval || Gval) {
         const int rc = upload_static_values(h, false);
         if (rc) return rc;
+    } else if (rz && (c || b || hv)) {
+        const int rc = launch_scale_vectors(h);
+        if (rc) return rc;
     }
-    // vectors go straight into the device copies (the host copies only serve setup)
-    if (c && h->n > 0) QG_HIP(h, hipMemcpyAsync(h->d.c.p, c, sizeof(double) * h->n, hipMemcpyHostToDevice, h->stream));
-    if (b && h->p > 0) QG_HIP(h, hipMemcpyAsync(h->d.b.p, b, sizeof(double) * h->p, hipMemcpyHostToDevice, h->stream));
-    if (hv && h->m > 0) QG_HIP(h, hipMemcpyAsync(h->d.h.p, hv, sizeof(double) * h->m, hipMemcpyHostToDevice, h->stream));
     QG_HIP(h, hipStreamSynchronize(h->stream));
     return QG_OK;
 }
@@ -601,15 +611,20 @@ int qg_update_vectors(qg_handle *h, const double *c, const double *b, const doub
     if (bad) return QG_ERR_NONFINITE;
     h->solved = false;
     h->final_factor = false;
-    if (c && h->n > 0) QG_HIP(h, hipMemcpyAsync(h->d.c.p, c, sizeof(double) * h->n, hipMemcpyDeviceToDevice, h->stream));
-    if (b && h->p > 0) QG_HIP(h, hipMemcpyAsync(h->d.b.p, b, sizeof(double) * h->p, hipMemcpyDeviceToDevice, h->stream));
-    if (hv && h->m > 0) QG_HIP(h, hipMemcpyAsync(h->d.h.p, hv, sizeof(double) * h->m, hipMemcpyDeviceToDevice, h->stream));
+    const bool rz = h->ruiz > 0;   // equilibrated data: the objective scaling k of the setup is kept
+    if (c && h->n > 0) QG_HIP(h, hipMemcpyAsync((rz ? h->d.craw : h->d.c).p, c, sizeof(double) * h->n, hipMemcpyDeviceToDevice, h->stream));
+    if (b && h->p > 0) QG_HIP(h, hipMemcpyAsync((rz ? h->d.braw : h->d.b).p, b, sizeof(double) * h->p, hipMemcpyDeviceToDevice, h->stream));
+    if (hv && h->m > 0) QG_HIP(h, hipMemcpyAsync((rz ? h->d.hraw : h->d.h).p, hv, sizeof(double) * h->m, hipMemcpyDeviceToDevice, h->stream));
+    if (rz && (c || b || hv)) {
+        if ((rc = launch_scale_vectors(h))) return rc;
+    }
     QG_HIP(h, hipStreamSynchronize(h->stream));
     return QG_OK;
 }
 
 int qg_set_settings(qg_handle *h, const qg_settings *s) {
     if (!h || !s) return QG_ERR_ARG;
+    if (h->ruiz > 0 && s->differentiable) return QG_ERR_ARG;   // the equilibration is fixed at setup
     h->st = *s;
     drop_graphs(h);   // the captured launches hold the regularization parameters as arguments
     return QG_OK;

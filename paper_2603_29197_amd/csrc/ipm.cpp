@@ -74,14 +74,16 @@ Scalars stop_test(qg_handle *h, const double *sc, double ea, double er) {
     r.pres = std::max(sc[S_RY], sc[S_RZ]);
     r.dres = sc[S_RX];
     r.sz = sc[S_SZ];
-    r.gap = std::fabs(sc[S_SZ]);
-    r.pobj = 0.5 * sc[S_XPX] + sc[S_CX];
-    r.dobj = -0.5 * sc[S_XPX] - sc[S_BY] - sc[S_HZ];
+    // equilibrated data: the inner products carry the objective scaling k (the max-norm terms were
+    // taken back to the caller's units by the residual kernel)
+    const double ik = h->ruiz > 0 ? 1.0 / h->ruiz_k : 1.0;
+    r.gap = std::fabs(sc[S_SZ]) * ik;
+    r.pobj = (0.5 * sc[S_XPX] + sc[S_CX]) * ik;
+    r.dobj = (-0.5 * sc[S_XPX] - sc[S_BY] - sc[S_HZ]) * ik;
     const double pscale = std::max({sc[S_AX], sc[S_B], sc[S_GX], sc[S_H], sc[S_S]});
     const double dscale = std::max({sc[S_PX], sc[S_ATY], sc[S_GTZ], sc[S_C]});
     const double gscale = std::max(1.0, std::min(std::fabs(r.pobj), std::fabs(r.dobj)));
     r.ok = r.pres <= ea + er * pscale && r.dres <= ea + er * dscale && r.gap <= ea + er * gscale;
-    (void)h;
     return r;
 }
 
@@ -298,11 +300,15 @@ int ipm_solve(qg_handle *h, double *xo, double *so, double *yo, double *zo, qg_i
         pending_is32 = prec == QG_FP32_IR ? 1 : 0;
         ++it;
     }
-    // outputs
-    if (xo) QG_HIP(h, hipMemcpyAsync(xo, d.x.p, sizeof(double) * n, hipMemcpyDeviceToDevice, h->stream));
-    if (so) QG_HIP(h, hipMemcpyAsync(so, d.s.p, sizeof(double) * m, hipMemcpyDeviceToDevice, h->stream));
-    if (yo) QG_HIP(h, hipMemcpyAsync(yo, d.y.p, sizeof(double) * p, hipMemcpyDeviceToDevice, h->stream));
-    if (zo) QG_HIP(h, hipMemcpyAsync(zo, d.z.p, sizeof(double) * m, hipMemcpyDeviceToDevice, h->stream));
+    // outputs (equilibrated data: back to the caller's units)
+    if (h->ruiz > 0) {
+        if ((rc = launch_unscale_outputs(h, xo, so, yo, zo))) return fail(rc);
+    } else {
+        if (xo) QG_HIP(h, hipMemcpyAsync(xo, d.x.p, sizeof(double) * n, hipMemcpyDeviceToDevice, h->stream));
+        if (so) QG_HIP(h, hipMemcpyAsync(so, d.s.p, sizeof(double) * m, hipMemcpyDeviceToDevice, h->stream));
+        if (yo) QG_HIP(h, hipMemcpyAsync(yo, d.y.p, sizeof(double) * p, hipMemcpyDeviceToDevice, h->stream));
+        if (zo) QG_HIP(h, hipMemcpyAsync(zo, d.z.p, sizeof(double) * m, hipMemcpyDeviceToDevice, h->stream));
+    }
     h->solved = (status == QG_SOLVED || status == QG_SOLVED_INACCURATE);
     h->last_status = status;
     // derivative system at the final iterate (FP64), kept for qg_backward

@@ -7,6 +7,8 @@
 #include "kernels.hpp"
 #include "solver.hpp"
 
+#include <cmath>
+
 namespace qg {
 
 int hip_fail(qg_handle *h, hipError_t e) {
@@ -79,7 +81,7 @@ void dfree_all(qg_handle *h) {
     // FP32 factor buffers are views into the FP64 ones (a factor is in one precision at a time)
     d.front32 = {}; d.dinv32 = {}; d.sinv32 = {}; d.w32 = {};
     dfree_(h, d.kval); dfree_(h, d.blk33); dfree_(h, d.blk_off); dfree_(h, d.soc_off); dfree_(h, d.big_cones); dfree_(h, d.big_chunk_cone); dfree_(h, d.big_chunk_start); dfree_(h, d.bigsc); dfree_(h, d.kr_ptr);
-    dfree_(h, d.kr_col); dfree_(h, d.kr_val); dfree_(h, d.c); dfree_(h, d.b); dfree_(h, d.h); dfree_(h, d.Pp); dfree_(h, d.Pi);
+    dfree_(h, d.kr_col); dfree_(h, d.kr_val); dfree_(h, d.c); dfree_(h, d.b); dfree_(h, d.h); dfree_(h, d.craw); dfree_(h, d.braw); dfree_(h, d.hraw); dfree_(h, d.rz_dsc); dfree_(h, d.rz_rsc); dfree_(h, d.Pp); dfree_(h, d.Pi);
     dfree_(h, d.Ap); dfree_(h, d.Ai); dfree_(h, d.Gp); dfree_(h, d.Gi); dfree_(h, d.posG);
     dfree_(h, d.perm); dfree_(h, d.iperm);
     dfree_(h, d.sn_first); dfree_(h, d.sn_rows); dfree_(h, d.task_sn); dfree_(h, d.task_col);
@@ -650,16 +652,97 @@ int build_plan(qg_handle *h) {
     return QG_OK;
 }
 
+// Ruiz equilibration of the data (a setup-time preprocessing; the paper states none): D (n), E (p) and
+// F (m), each pass dividing every column of the data matrix [P A' G'; A 0 0; G 0 0] (x columns, P taken
+// symmetric) and every row of A and of G by the square root of its largest magnitude (1 for an empty
+// one), the rows of one second-order cone by a common factor (the largest over the cone's rows, so
+// that the scaled cone is the same cone); then the objective scaling k = 1 / max(1, |D c|_inf).  The
+// scaled problem is  k D P D, k D c, E A D, E b, F G D, F h  with  x = D x^, y = E y^ / k,
+// z = F z^ / k, s = s^ / F.
+static void ruiz_scaling(const ProblemPattern &pp, const std::vector<double> &c, int passes, double &k,
+                         std::vector<double> &dsc) {
+    const int32_t n = pp.n, p = pp.p, m = pp.m;
+    dsc.assign((size_t)n + p + m, 1.0);
+    double *D = dsc.data(), *E = D + n, *F = E + p;
+    std::vector<double> cx((size_t)n), rw((size_t)p + m);
+    for (int it = 0; it < passes; ++it) {
+        std::fill(cx.begin(), cx.end(), 0.0);
+        std::fill(rw.begin(), rw.end(), 0.0);
+        for (int32_t j = 0; j < n; ++j) {
+            for (int64_t t = pp.P.colptr[j]; t < pp.P.colptr[j + 1]; ++t) {
+                const int32_t i = pp.P.rowind[t];
+                const double v = std::fabs(D[i] * pp.P.val[t] * D[j]);
+                cx[j] = std::max(cx[j], v);
+                cx[i] = std::max(cx[i], v);
+            }
+            for (int64_t t = pp.A.colptr[j]; t < pp.A.colptr[j + 1]; ++t) {
+                const int32_t i = pp.A.rowind[t];
+                const double v = std::fabs(E[i] * pp.A.val[t] * D[j]);
+                cx[j] = std::max(cx[j], v);
+                rw[i] = std::max(rw[i], v);
+            }
+            for (int64_t t = pp.G.colptr[j]; t < pp.G.colptr[j + 1]; ++t) {
+                const int32_t i = pp.G.rowind[t];
+                const double v = std::fabs(F[i] * pp.G.val[t] * D[j]);
+                cx[j] = std::max(cx[j], v);
+                rw[p + i] = std::max(rw[p + i], v);
+            }
+        }
+        for (int32_t k2 = 0; k2 < pp.nsoc; ++k2) {
+            double mx = 0.0;
+            for (int32_t i = pp.soc_off[k2]; i < pp.soc_off[k2 + 1]; ++i) mx = std::max(mx, rw[p + i]);
+            for (int32_t i = pp.soc_off[k2]; i < pp.soc_off[k2 + 1]; ++i) rw[p + i] = mx;
+        }
+        auto f = [](double v) { return v > 0.0 ? 1.0 / std::sqrt(v) : 1.0; };
+        for (int32_t j = 0; j < n; ++j) D[j] *= f(cx[j]);
+        for (int32_t i = 0; i < p + m; ++i) E[i] *= f(rw[i]);   // E and F are contiguous
+    }
+    double cn = 0.0;
+    for (int32_t j = 0; j < n; ++j) cn = std::max(cn, std::fabs(D[j] * c[j]));
+    k = 1.0 / std::max(1.0, cn);
+}
+
 int upload_static_values(qg_handle *h, bool vectors) {
     const ProblemPattern &pp = h->pp;
     const KktPattern &kp = h->kp;
     const int32_t n = h->n, p = h->p, N = h->N;
-    // K upper values without the (3,3) block (zeros there)
+    int rc;
+    // K upper values without the (3,3) block (zeros there); with Ruiz equilibration the scaled data
     h->kval_static.assign(kp.Ki.size(), 0.0);
-    for (size_t t = 0; t < pp.P.val.size(); ++t) h->kval_static[kp.posP[t]] = pp.P.val[t];
-    for (size_t t = 0; t < pp.A.val.size(); ++t) h->kval_static[kp.posA[t]] = pp.A.val[t];
-    for (size_t t = 0; t < pp.G.val.size(); ++t) h->kval_static[kp.posG[t]] = pp.G.val[t];
-    int rc = dupload(h, h->d.kval, h->kval_static);
+    if (h->ruiz > 0) {
+        // the objective scaling takes the current c (at setup the host copy, later the device one)
+        std::vector<double> c;
+        if (vectors) {
+            c = h->hc;
+        } else {
+            c.resize((size_t)n);
+            if (n > 0)
+                QG_HIP(h, hipMemcpyAsync(c.data(), h->d.craw.p, sizeof(double) * n, hipMemcpyDeviceToHost,
+                                         h->stream));
+            QG_HIP(h, hipStreamSynchronize(h->stream));
+        }
+        ruiz_scaling(pp, c, h->ruiz, h->ruiz_k, h->ruiz_dsc);
+        const double *D = h->ruiz_dsc.data(), *E = D + n, *F = E + p;
+        const double k = h->ruiz_k;
+        for (int32_t j = 0; j < n; ++j) {
+            for (int64_t t = pp.P.colptr[j]; t < pp.P.colptr[j + 1]; ++t)
+                h->kval_static[kp.posP[t]] = k * D[pp.P.rowind[t]] * pp.P.val[t] * D[j];
+            for (int64_t t = pp.A.colptr[j]; t < pp.A.colptr[j + 1]; ++t)
+                h->kval_static[kp.posA[t]] = E[pp.A.rowind[t]] * pp.A.val[t] * D[j];
+            for (int64_t t = pp.G.colptr[j]; t < pp.G.colptr[j + 1]; ++t)
+                h->kval_static[kp.posG[t]] = F[pp.G.rowind[t]] * pp.G.val[t] * D[j];
+        }
+        std::vector<double> rsc((size_t)N);
+        for (int32_t j = 0; j < n; ++j) rsc[j] = 1.0 / (k * D[j]);
+        for (int32_t i = n; i < N; ++i) rsc[i] = 1.0 / D[i];
+        if ((rc = dupload(h, h->d.rz_dsc, h->ruiz_dsc))) return rc;
+        if ((rc = dupload(h, h->d.rz_rsc, rsc))) return rc;
+    } else {
+        for (size_t t = 0; t < pp.P.val.size(); ++t) h->kval_static[kp.posP[t]] = pp.P.val[t];
+        for (size_t t = 0; t < pp.A.val.size(); ++t) h->kval_static[kp.posA[t]] = pp.A.val[t];
+        for (size_t t = 0; t < pp.G.val.size(); ++t) h->kval_static[kp.posG[t]] = pp.G.val[t];
+    }
+    rc = dupload(h, h->d.kval, h->kval_static);
     if (rc) return rc;
     // full symmetric CSR of the static part (both triangles; the (3,3) block excluded)
     std::vector<int64_t> rp((size_t)N + 1, 0);
@@ -699,10 +782,20 @@ int upload_static_values(qg_handle *h, bool vectors) {
     if ((rc = dupload(h, h->d.kr_ptr, rp))) return rc;
     if ((rc = dupload(h, h->d.kr_col, rc_))) return rc;
     if ((rc = dupload(h, h->d.kr_val, rv))) return rc;
-    if (!vectors) return QG_OK;
-    if ((rc = dupload(h, h->d.c, h->hc))) return rc;
-    if ((rc = dupload(h, h->d.b, h->hb))) return rc;
-    if ((rc = dupload(h, h->d.h, h->hh))) return rc;
+    if (vectors && h->ruiz > 0) {
+        // the caller's vectors are kept; the scaled ones are formed on the device
+        if ((rc = dupload(h, h->d.craw, h->hc))) return rc;
+        if ((rc = dupload(h, h->d.braw, h->hb))) return rc;
+        if ((rc = dupload(h, h->d.hraw, h->hh))) return rc;
+        if ((rc = dalloc(h, h->d.c, h->hc.size()))) return rc;
+        if ((rc = dalloc(h, h->d.b, h->hb.size()))) return rc;
+        if ((rc = dalloc(h, h->d.h, h->hh.size()))) return rc;
+    } else if (vectors) {
+        if ((rc = dupload(h, h->d.c, h->hc))) return rc;
+        if ((rc = dupload(h, h->d.b, h->hb))) return rc;
+        if ((rc = dupload(h, h->d.h, h->hh))) return rc;
+    }
+    if (h->ruiz > 0) return launch_scale_vectors(h);   // new scalings or new vectors
     return QG_OK;
 }
 

@@ -112,6 +112,10 @@ struct Device {
     DBuf<int32_t> kr_col;
     DBuf<double> kr_val;
     DBuf<double> c, b, h;
+    // Ruiz equilibration (settings.ruiz_iters > 0): the caller's c, b, h (c, b, h above hold the scaled
+    // ones), the scalings [D (n); E (p); F (m)] and, per KKT row, the factor that takes a residual
+    // entry back to the caller's units (1 / (k D) for x rows, 1 / E for y rows, 1 / F for z rows)
+    DBuf<double> craw, braw, hraw, rz_dsc, rz_rsc;
     DBuf<int64_t> Pp; DBuf<int32_t> Pi;   // P upper pattern (for dL/dP)
     DBuf<int64_t> Ap, Gp; DBuf<int32_t> Ai, Gi;   // A and G patterns (for dL/dA, dL/dG)
     DBuf<int64_t> posG;         // position of each G entry among the K values (G' g_s in the adjoint)
@@ -201,6 +205,9 @@ struct qg_handle {
     int32_t n1 = 0, m1 = 0, p1 = 0, l1 = 0;   // sizes of one problem of the batch
     int32_t nbig = 0;                  // SOCs handled one wavefront per cone
     int32_t grp_q = 0;                 // > 0: every SOC has this many entries (<= 16): lane groups
+    int ruiz = 0;                      // Ruiz passes (settings.ruiz_iters at setup; 0: no scaling)
+    double ruiz_k = 1.0;               // objective scaling
+    std::vector<double> ruiz_dsc;      // host copy of [D; E; F]
     int64_t nbigchunk = 0;             // workgroups of the big cones' block writes
     bool solved = false;               // a solve finished (x, s, y, z valid)
     bool final_factor = false;         // the derivative system is factored (FP64)
@@ -237,6 +244,10 @@ void dfree_all(qg_handle *h);
 int group_fronts(const Symbolic &sym, Symbolic &fronts);
 int build_plan(qg_handle *h);
 int upload_static_values(qg_handle *h, bool vectors);
+// Ruiz equilibration: scaled c, b, h from the caller's copies on the device (after a change of
+// either), and the caller's x, s, y, z from the scaled iterate (qg_solve's outputs).
+int launch_scale_vectors(qg_handle *h);
+int launch_unscale_outputs(qg_handle *h, double *x, double *s, double *y, double *z);
 
 // device phases (all enqueue on h->stream)
 int launch_scaling(qg_handle *h, const double *s, const double *z, double *lam, int block);

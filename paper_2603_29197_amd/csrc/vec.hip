@@ -88,7 +88,7 @@ __global__ void __launch_bounds__(256) residual_kernel(
     const double *__restrict__ z, const double *__restrict__ s, const double *__restrict__ c,
     const double *__restrict__ b, const double *__restrict__ hv, double *__restrict__ rx,
     double *__restrict__ ry, double *__restrict__ rz, double *__restrict__ partials, int32_t kb, int32_t n1,
-    int32_t p1, int32_t m1, int32_t l1) {
+    int32_t p1, int32_t m1, int32_t l1, const double *__restrict__ rsc) {
     double val[NSCAL];
 #pragma unroll
     for (int q = 0; q < NSCAL; ++q) val[q] = 0.0;
@@ -113,26 +113,28 @@ __global__ void __launch_bounds__(256) residual_kernel(
             a2 += __shfl_xor(a2, off);
         }
         if (sub == 0 && i < N) {
+            // equilibrated data: the max-norm terms in the caller's units (u = 1 / the row's scaling)
+            const double u = rsc ? rsc[i] : 1.0;
             if (i < n) {
                 const double r_ = a0 + a1 + a2 + c[i];
                 rx[i] = r_;
-                accumulate(val, SCAL_MAXMASK, S_PX, fabs(a0)); accumulate(val, SCAL_MAXMASK, S_ATY, fabs(a1));
-                accumulate(val, SCAL_MAXMASK, S_GTZ, fabs(a2)); accumulate(val, SCAL_MAXMASK, S_RX, fabs(r_));
+                accumulate(val, SCAL_MAXMASK, S_PX, u * fabs(a0)); accumulate(val, SCAL_MAXMASK, S_ATY, u * fabs(a1));
+                accumulate(val, SCAL_MAXMASK, S_GTZ, u * fabs(a2)); accumulate(val, SCAL_MAXMASK, S_RX, u * fabs(r_));
                 accumulate(val, SCAL_MAXMASK, S_XPX, x[i] * a0); accumulate(val, SCAL_MAXMASK, S_CX, c[i] * x[i]);
-                accumulate(val, SCAL_MAXMASK, S_C, fabs(c[i]));
+                accumulate(val, SCAL_MAXMASK, S_C, u * fabs(c[i]));
             } else if (i < n + p) {
                 const int32_t e = i - n;
                 const double r_ = a0 - b[e];
                 ry[e] = r_;
-                accumulate(val, SCAL_MAXMASK, S_AX, fabs(a0)); accumulate(val, SCAL_MAXMASK, S_RY, fabs(r_));
-                accumulate(val, SCAL_MAXMASK, S_BY, b[e] * y[e]); accumulate(val, SCAL_MAXMASK, S_B, fabs(b[e]));
+                accumulate(val, SCAL_MAXMASK, S_AX, u * fabs(a0)); accumulate(val, SCAL_MAXMASK, S_RY, u * fabs(r_));
+                accumulate(val, SCAL_MAXMASK, S_BY, b[e] * y[e]); accumulate(val, SCAL_MAXMASK, S_B, u * fabs(b[e]));
             } else {
                 const int32_t e = i - n - p;
                 const double r_ = a0 + s[e] - hv[e];
                 rz[e] = r_;
-                accumulate(val, SCAL_MAXMASK, S_GX, fabs(a0)); accumulate(val, SCAL_MAXMASK, S_RZ, fabs(r_));
+                accumulate(val, SCAL_MAXMASK, S_GX, u * fabs(a0)); accumulate(val, SCAL_MAXMASK, S_RZ, u * fabs(r_));
                 accumulate(val, SCAL_MAXMASK, S_HZ, hv[e] * z[e]); accumulate(val, SCAL_MAXMASK, S_SZ, s[e] * z[e]);
-                accumulate(val, SCAL_MAXMASK, S_S, fabs(s[e])); accumulate(val, SCAL_MAXMASK, S_H, fabs(hv[e]));
+                accumulate(val, SCAL_MAXMASK, S_S, u * fabs(s[e])); accumulate(val, SCAL_MAXMASK, S_H, u * fabs(hv[e]));
             }
         }
     }
@@ -273,14 +275,15 @@ int launch_residual(qg_handle *h, const double *x, const double *y, const double
     const int R = lanes_per_row(h);
     const int32_t nblk = red_blocks(n1 + p1 + m1, R);
     const dim3 grid((unsigned)nblk, (unsigned)kb);
+    const double *rsc = h->ruiz > 0 ? d.rz_rsc.p : nullptr;
     if (R == 4)
         residual_kernel<4><<<grid, 256, 0, h->stream>>>(
             h->n, h->p, h->m, d.kr_ptr.p, d.kr_col.p, d.kr_val.p, x, y, z, s, d.c.p, d.b.p, d.h.p, d.rx.p, d.ry.p,
-            d.rz.p, d.partials.p, kb, n1, p1, m1, l1);
+            d.rz.p, d.partials.p, kb, n1, p1, m1, l1, rsc);
     else
         residual_kernel<16><<<grid, 256, 0, h->stream>>>(
             h->n, h->p, h->m, d.kr_ptr.p, d.kr_col.p, d.kr_val.p, x, y, z, s, d.c.p, d.b.p, d.h.p, d.rx.p, d.ry.p,
-            d.rz.p, d.partials.p, kb, n1, p1, m1, l1);
+            d.rz.p, d.partials.p, kb, n1, p1, m1, l1, rsc);
     finish_reduce<<<(unsigned)kb, 256, 0, h->stream>>>(d.partials.p, nblk, NSCAL, SCAL_MAXMASK, d.scal_inst.p);
     QG_HIP(h, hipGetLastError());
     const size_t nv = (size_t)kb * NSCAL;
@@ -288,6 +291,57 @@ int launch_residual(qg_handle *h, const double *x, const double *y, const double
     QG_HIP(h, hipMemcpyAsync(dst, d.scal_inst.p, nv * sizeof(double), hipMemcpyDeviceToHost, h->stream));
     if (int rc = stream_wait(h)) return rc;
     if (dst != scal_host) std::memcpy(scal_host, dst, nv * sizeof(double));
+    return QG_OK;
+}
+
+// Equilibrated vectors from the caller's: c^ = k D c, b^ = E b, h^ = F h (dsc = D, E, F back to back).
+__global__ void ruiz_scale_kernel(int32_t n, int32_t p, int32_t m, double k, const double *__restrict__ dsc,
+                                  const double *__restrict__ craw, const double *__restrict__ braw,
+                                  const double *__restrict__ hraw, double *__restrict__ c, double *__restrict__ b,
+                                  double *__restrict__ hv) {
+    const int32_t i = (int32_t)(blockIdx.x * 256 + threadIdx.x);
+    if (i < n) c[i] = k * dsc[i] * craw[i];
+    else if (i < n + p) b[i - n] = dsc[i] * braw[i - n];
+    else if (i < n + p + m) hv[i - n - p] = dsc[i] * hraw[i - n - p];
+}
+
+// The caller's solution from the equilibrated one: x = D x^, y = E y^ / k, z = F z^ / k, s = s^ / F.
+// Every output pointer may be null.
+__global__ void ruiz_unscale_kernel(int32_t n, int32_t p, int32_t m, double k, const double *__restrict__ dsc,
+                                    const double *__restrict__ xs, const double *__restrict__ ss,
+                                    const double *__restrict__ ys, const double *__restrict__ zs,
+                                    double *__restrict__ x, double *__restrict__ s, double *__restrict__ y,
+                                    double *__restrict__ z) {
+    const int32_t i = (int32_t)(blockIdx.x * 256 + threadIdx.x);
+    if (i < n) {
+        if (x) x[i] = dsc[i] * xs[i];
+    } else if (i < n + p) {
+        if (y) y[i - n] = dsc[i] * ys[i - n] / k;
+    } else if (i < n + p + m) {
+        const int32_t e = i - n - p;
+        if (z) z[e] = dsc[i] * zs[e] / k;
+        if (s) s[e] = ss[e] / dsc[i];
+    }
+}
+
+int launch_scale_vectors(qg_handle *h) {
+    Device &d = h->d;
+    const int32_t N = h->N;
+    if (N == 0) return QG_OK;
+    ruiz_scale_kernel<<<(unsigned)((N + 255) / 256), 256, 0, h->stream>>>(h->n, h->p, h->m, h->ruiz_k,
+                                                                          d.rz_dsc.p, d.craw.p, d.braw.p,
+                                                                          d.hraw.p, d.c.p, d.b.p, d.h.p);
+    QG_HIP(h, hipGetLastError());
+    return QG_OK;
+}
+
+int launch_unscale_outputs(qg_handle *h, double *x, double *s, double *y, double *z) {
+    Device &d = h->d;
+    const int32_t N = h->N;
+    if (N == 0 || (!x && !s && !y && !z)) return QG_OK;
+    ruiz_unscale_kernel<<<(unsigned)((N + 255) / 256), 256, 0, h->stream>>>(
+        h->n, h->p, h->m, h->ruiz_k, d.rz_dsc.p, d.x.p, d.s.p, d.y.p, d.z.p, x, s, y, z);
+    QG_HIP(h, hipGetLastError());
     return QG_OK;
 }
 

@@ -782,3 +782,104 @@ def test_graph_replays_give_the_launch_by_launch_bits(name, prec):
         assert i1 == i0 and r1 == r0
         assert np.array_equal(x1, x0) and np.array_equal(z1, z0)
     assert np.array_equal(res[1][0][0], res[1][1][0])
+
+
+def badly_scaled(prob, seed):
+    """The same problem with its variables and constraint rows rescaled by factors from 1e-3 to 1e3
+    (one factor per second-order cone): x' = S^-1 x, y' = R_A^-1 y, z' = R_G^-1 z, s' = R_G s
+    solve it, with S P S, S c, R_A A S, R_A b, R_G G S, R_G h."""
+    import scipy.sparse as sp
+    rng = np.random.default_rng(seed)
+    S = 10.0 ** rng.uniform(-3, 3, prob.n)
+    RA = 10.0 ** rng.uniform(-3, 3, prob.p)
+    RG = 10.0 ** rng.uniform(-3, 3, prob.m)
+    off = prob.l
+    for qk in prob.q:
+        RG[off:off + qk] = RG[off]
+        off += qk
+    D = sp.diags(S)
+    q = problems.Problem(**{**prob.__dict__})
+    q.P = sp.csc_matrix(D @ prob.P @ D)
+    q.c = S * prob.c
+    q.A = sp.csc_matrix(sp.diags(RA) @ prob.A @ D)
+    q.b = RA * prob.b
+    q.G = sp.csc_matrix(sp.diags(RG) @ prob.G @ D)
+    q.h = RG * prob.h
+    q.name = prob.name + "_badly_scaled"
+    return q, S, RA, RG
+
+
+# The equilibrated solve follows another trajectory than the oracle's and stops at another point
+# that meets the stopping rule; at 1e-8 the two x differ by up to 1.4e-6 on small_qp (the rule
+# fixes x no sharper), so these tests compare both sides stopped at 1e-10.
+TIGHT = 1e-10
+TIGHT_CACHE = {}
+
+
+def oracle_solution_tight(name):
+    if name not in TIGHT_CACHE:
+        TIGHT_CACHE[name] = oipm.solve(SMALL[name](), oipm.IPMSettings(eps_abs=TIGHT, eps_rel=TIGHT))
+    return TIGHT_CACHE[name]
+
+
+@pytest.mark.parametrize("name", ["small_qp", "lasso_s", "many_soc_s", "big_soc"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_ruiz_equilibrated_solve_matches_oracle(name, prec):
+    """With Ruiz equilibration the interior-point method runs on the scaled data and hands back the
+    caller's x, s, y, z: they match the oracle's solution and pass the oracle's own stopping test
+    on the unscaled data (which checks all four outputs and the stopping test's unscaling)."""
+    import paper_2603_29197_amd as qg
+    prob = SMALL[name]()
+    S = solver(prob, ruiz_iters=10, precision=qg.QG_FP64 if prec == "fp64" else qg.QG_FP32_IR,
+               eps_abs=TIGHT, eps_rel=TIGHT)
+    x, s, y, z, info = S.solve()
+    print(f"[gpu] ruiz {name} {prec}: {info['status_name']} iters {info['iters']}", flush=True)
+    ref = oracle_solution_tight(name)
+    assert info["status"] == 1
+    xs = host(x)
+    ex = float(np.max(np.abs(xs - ref.x)) / max(1.0, np.max(np.abs(ref.x))))
+    eo = abs(info["pobj"] - ref.pobj) / max(1.0, abs(ref.pobj))
+    assert ex <= 1e-6 and eo <= 1e-6, (ex, eo)
+    r = oipm.residuals(prob, xs, host(s), host(y), host(z))
+    ok, pres, dres, gap = oipm.stop_test(prob, r, host(s), 1e-8, 1e-8)
+    assert ok, (pres, dres, gap)
+    S.close()
+
+
+@pytest.mark.parametrize("name", ["small_qp", "mixed_soc"])
+def test_ruiz_on_badly_scaled_data(name):
+    """Data rescaled by factors over six decades: with equilibration the solve returns the
+    rescaled oracle solution and meets the stopping test on the rescaled data; new matrix values
+    through qg_update (the scalings formed again) give the same answer as a fresh setup."""
+    import paper_2603_29197_amd as qg
+    prob = SMALL[name]()
+    bad, Sx, RA, RG = badly_scaled(prob, 77)
+    ref = oracle_solution_tight(name)
+    for ruiz in (0, 10):
+        Sv = solver(bad, ruiz_iters=ruiz, precision=qg.QG_FP64, max_iter=100, eps_abs=TIGHT, eps_rel=TIGHT)
+        x, s, y, z, info = Sv.solve()
+        print(f"[gpu] {bad.name} ruiz {ruiz}: {info['status_name']} iters {info['iters']}", flush=True)
+        if ruiz == 0:
+            Sv.close()
+            continue
+        assert info["status"] == 1
+        xs = host(x)
+        ex = float(np.max(np.abs(Sx * xs - ref.x)) / max(1.0, np.max(np.abs(ref.x))))
+        eo = abs(info["pobj"] - ref.pobj) / max(1.0, abs(ref.pobj))
+        assert ex <= 1e-6 and eo <= 1e-6, (ex, eo)
+        r = oipm.residuals(bad, xs, host(s), host(y), host(z))
+        ok, pres, dres, gap = oipm.stop_test(bad, r, host(s), 1e-8, 1e-8)
+        assert ok, (pres, dres, gap)
+        # matrix values and c changed in place: the same answer as a fresh setup of the new data
+        bad2 = problems.Problem(**{**bad.__dict__})
+        bad2.P = bad.P * 2.0
+        bad2.G = bad.G * 0.5
+        bad2.c = bad.c * 3.0
+        Sv.update(Pval=bad2.P.data, c=bad2.c, Gval=bad2.G.data)
+        x1, s1, y1, z1, i1 = Sv.solve()
+        Sv.close()
+        F = solver(bad2, ruiz_iters=ruiz, precision=qg.QG_FP64, max_iter=100, eps_abs=TIGHT, eps_rel=TIGHT)
+        x2, s2, y2, z2, i2 = F.solve()
+        F.close()
+        assert i1["status"] == 1 and i2["status"] == 1 and i1["iters"] == i2["iters"]
+        assert np.array_equal(host(x1), host(x2)) and np.array_equal(host(z1), host(z2))

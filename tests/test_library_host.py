@@ -161,7 +161,7 @@ def test_invalid_inputs_are_rejected():
     assert e.value.code == -1
 
 
-def _raw_setup(prob, hooks=None):
+def _raw_setup(prob, hooks=None, settings=None):
     """qg_setup through the C ABI with host data only; returns the code.  Every case below is
     rejected by validation, which runs before any device call."""
     import ctypes
@@ -175,7 +175,8 @@ def _raw_setup(prob, hooks=None):
     rc = _lib.lib().qg_setup(ctypes.byref(h), prob.n, prob.m, prob.p, P.ptr(), c.ctypes.data_as(_lib.c_double_p),
                              A.ptr(), b.ctypes.data_as(_lib.c_double_p), G.ptr(),
                              hv.ctypes.data_as(_lib.c_double_p), prob.l, len(prob.q),
-                             q.ctypes.data_as(_lib.c_int32_p), None, None, *hooks)
+                             q.ctypes.data_as(_lib.c_int32_p),
+                             ctypes.byref(settings) if settings is not None else None, None, *hooks)
     assert not h.value
     return rc
 
@@ -193,6 +194,16 @@ def test_nonfinite_data_is_rejected_before_the_device(where):
             M = getattr(prob, where).copy(); M.data[2] = bad_value
             setattr(bad, where, M)
         assert _raw_setup(bad) == -3, (where, bad_value)
+
+
+@pytest.mark.parametrize("ruiz,diff", [(-1, 0), (101, 0), (5, 1)])
+def test_ruiz_settings_are_validated(ruiz, diff):
+    """Ruiz passes outside 0..QG_RUIZ_MAX, or with the differentiable mode, give QG_ERR_ARG."""
+    import paper_2603_29197_amd as qg
+    prob = problems.small_qp(n=20, p=4, m=10, mrows=10)
+    s = qg.default_settings(ruiz_iters=ruiz, differentiable=diff)
+    assert qg.default_settings().ruiz_iters == 0
+    assert _raw_setup(prob, settings=s) == -1
 
 
 def test_allocator_hooks_must_come_in_pairs():

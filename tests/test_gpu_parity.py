@@ -18,6 +18,7 @@ from oracle import cones as oc  # noqa: E402
 from oracle import ipm as oipm  # noqa: E402
 from oracle import kkt as okkt  # noqa: E402
 from oracle import ldl as oldl  # noqa: E402
+from oracle import ruiz as oruiz  # noqa: E402
 from synth import problems  # noqa: E402
 
 pytestmark = pytest.mark.gpu
@@ -883,3 +884,22 @@ def test_ruiz_on_badly_scaled_data(name):
         F.close()
         assert i1["status"] == 1 and i2["status"] == 1 and i1["iters"] == i2["iters"]
         assert np.array_equal(host(x1), host(x2)) and np.array_equal(host(z1), host(z2))
+
+
+@pytest.mark.parametrize("name", ["small_qp", "mixed_soc", "big_soc"])
+def test_ruiz_scaled_kkt_matches_oracle(name):
+    """The library's equilibrated KKT values (10 passes over data rescaled over six decades, the
+    (3,3) block from an interior point) against the KKT matrix of the oracle's scaled data."""
+    prob, _, _, _ = badly_scaled(SMALL[name](), 78)
+    D, E, F, k = oruiz.equilibrate(prob, 10)
+    x, s, y, z = problems.random_point(prob, 8)
+    sc = oc.nt_scaling(oc.Cones(prob.l, prob.q), s, z)
+    orth, blocks = sc.block33()
+    want = okkt.kkt_upper(oruiz.scaled_problem(prob, D, E, F, k), orth, blocks).data
+    S = solver(prob, ruiz_iters=10)
+    S.step_scaling(dev(s), dev(z))
+    kv = S.step_get_kkt()
+    S.close()
+    err = np.max(np.abs(kv - want)) / np.max(np.abs(want))
+    print(f"[gpu] ruiz kkt {name}: rel err {err:.2e}", flush=True)
+    assert err <= 1e-13

@@ -220,18 +220,21 @@ __global__ void __launch_bounds__(256) factor_small_wave(
     }
 }
 
-// Tiny fronts (r <= TINY_R): 16 lanes per front, 16 fronts per workgroup,
-// each front (assembled in the front storage by the level's gather) in its own
-// 16 x 16 LDS tile, with the arithmetic of factor_front_lds.  The four fronts
-// of a wavefront run their pivot loops together (masked past a front's own
-// pivot count); a wavefront's LDS operations complete in order, so the steps
-// need no barrier.
-template <typename T>
+// Tiny fronts (r <= TR, TR = TINY_R8 or TINY_R, one launch for each):
+// 16 lanes per front, 16 fronts per workgroup, each front (assembled in the
+// front storage by the level's gather) in its own TR x TR LDS tile, with the
+// arithmetic of factor_front_lds.  The four fronts of a wavefront run their
+// pivot loops together (masked past a front's own pivot count); a wavefront's
+// LDS operations complete in order, so the steps need no barrier.  (With
+// 16 x 16 tiles a workgroup holds 32 KB of LDS and five fit on a compute unit;
+// most leaf fronts of nested dissection, about four rows, take 8 x 8.)
+template <typename T, int TR>
 __global__ void __launch_bounds__(256) factor_tiny(
     int32_t nfront, const int32_t *__restrict__ sn_list, const int32_t *__restrict__ sn_first,
     const int64_t *__restrict__ sn_rptr, const int64_t *__restrict__ fr_off, T *__restrict__ front,
     const int8_t *__restrict__ kind, double eps, double dyn, int32_t *nreg) {
-    __shared__ T tile[16][TINY_R * TINY_R];
+    static_assert(TR <= TINY_R && TR * TR % 16 == 0, "tile of the lane-group fronts");
+    __shared__ T tile[16][TR * TR];   // sized for the level's largest front: more workgroups per CU
     __shared__ T dsh[16];
     const int g = threadIdx.x >> 4, gl = threadIdx.x & 15;
     const int32_t q = blockIdx.x * 16 + g;
@@ -243,11 +246,11 @@ __global__ void __launch_bounds__(256) factor_tiny(
     T *G = front + (has ? fr_off[s] : 0);
     const int8_t *kd_s = kind + (has ? sn_first[s] : 0);
     const int32_t rr = r * r;
-    T v[TINY_R];                                     // all loads in flight at once
+    T v[TR * TR / 16];                               // all loads in flight at once
 #pragma unroll
-    for (int u = 0; u < TINY_R; ++u) v[u] = ld_or0(G, gl + 16 * u, gl + 16 * u < rr);
+    for (int u = 0; u < TR * TR / 16; ++u) v[u] = ld_or0(G, gl + 16 * u, gl + 16 * u < rr);
 #pragma unroll
-    for (int u = 0; u < TINY_R; ++u) {
+    for (int u = 0; u < TR * TR / 16; ++u) {
         const int32_t idx = gl + 16 * u;
         if (idx < rr) F[idx] = (idx % r >= idx / r) ? v[u] : T(0);
     }
@@ -1207,9 +1210,16 @@ static int factor_all(qg_handle *h, T *front, T *dinv, T *sinv, T *wb, const Reg
         int32_t s0 = pl.lvl_small_ptr[L];
         const int32_t s1 = pl.lvl_small_ptr[L + 1], nt = pl.lvl_tiny_cnt[L];
         if (nt > 0) {
-            factor_tiny<T><<<(nt + 15) / 16, 256, 0, h->stream>>>(nt, d.lvl_small_sn.p + s0, d.sn_first.p,
-                                                                   d.sn_rptr.p, d.fr_off.p, front, d.reg_sign.p,
-                                                                   rp.eps, rp.dyn, d.nreg.p);
+            // the fronts of at most TINY_R8 rows lead the level's tiny ones
+            const int32_t n8 = pl.lvl_tiny8_cnt[L];
+            if (n8 > 0)
+                factor_tiny<T, TINY_R8><<<(n8 + 15) / 16, 256, 0, h->stream>>>(n8, d.lvl_small_sn.p + s0, d.sn_first.p,
+                                                                               d.sn_rptr.p, d.fr_off.p, front,
+                                                                               d.reg_sign.p, rp.eps, rp.dyn, d.nreg.p);
+            if (nt > n8)
+                factor_tiny<T, TINY_R><<<(nt - n8 + 15) / 16, 256, 0, h->stream>>>(
+                    nt - n8, d.lvl_small_sn.p + s0 + n8, d.sn_first.p, d.sn_rptr.p, d.fr_off.p, front, d.reg_sign.p,
+                    rp.eps, rp.dyn, d.nreg.p);
             s0 += nt;
         }
         if (s1 > s0 && pl.lvl_small_maxr[L] <= CHAIN_R && pl.lvl_small_rsum[L] <= 12 * (int64_t)(s1 - s0)) {

@@ -32,6 +32,8 @@ constexpr int CHAIN_WIDTH_MAX = 8;   // a component's fronts per level, on avera
 // Tiny fronts (at most TINY_R rows) on levels that hold at least TINY_MIN of them: 16 lanes per
 // front, 16 fronts per 256-thread workgroup, in the factorization and both solve sweeps.
 constexpr int TINY_R = 16;
+// Tiny fronts of at most TINY_R8 rows are factored in 8 x 8 LDS tiles (more workgroups per CU).
+constexpr int32_t TINY_R8 = 8;
 constexpr int TINY_MIN = 2048;
 // Levels with fewer small fronts than this (all of at most CHAIN_R rows) solve them on the register
 // path of the chains.
@@ -42,6 +44,8 @@ constexpr int REG_LEVEL_MAX = 4096;
 constexpr int RL = 16;
 // Blocks per problem of the residual reductions (grid-stride over the rows).
 constexpr int32_t RED_BLOCKS = 2048;
+// Threads of the second reduction pass: one wavefront per scalar slot of the stopping test.
+constexpr int FINISH_THREADS = 1024;
 // Second-order cones with q >= QBIG entries are handled one wavefront per
 // cone (lane-strided entries, butterfly sums); smaller cones one thread each.
 constexpr int QBIG = 32;

@@ -477,6 +477,7 @@ int build_plan(qg_handle *h) {
     pl.lvl_small_maxr.assign((size_t)pl.nlevels, 0);
     pl.lvl_small_rsum.assign((size_t)pl.nlevels, 0);
     pl.lvl_tiny_cnt.assign((size_t)pl.nlevels, 0);
+    pl.lvl_tiny8_cnt.assign((size_t)pl.nlevels, 0);
     pl.lvl_small_ptr.assign((size_t)pl.nlevels + 1, 0);
     pl.lvl_large_ptr.assign((size_t)pl.nlevels + 1, 0);
     pl.lvl_small_sn.clear();
@@ -506,8 +507,12 @@ int build_plan(qg_handle *h) {
         auto mid = std::stable_partition(b, e, [&](int32_t f) { return pl.sn_rptr[f + 1] - pl.sn_rptr[f] <= TINY_R; });
         const int32_t nt = (int32_t)(mid - b);
         pl.lvl_tiny_cnt[L] = (h->st.tiny_groups && nt >= TINY_MIN) ? nt : 0;
-        if (pl.lvl_tiny_cnt[L] > 0)   // the row sum then covers the other small fronts only
+        if (pl.lvl_tiny_cnt[L] > 0) {   // the row sum then covers the other small fronts only
             for (auto it = b; it != mid; ++it) pl.lvl_small_rsum[L] -= pl.sn_rptr[*it + 1] - pl.sn_rptr[*it];
+            // and the fronts of at most TINY_R8 rows first among them (factored in smaller tiles)
+            auto mid8 = std::stable_partition(b, mid, [&](int32_t f) { return pl.sn_rptr[f + 1] - pl.sn_rptr[f] <= TINY_R8; });
+            pl.lvl_tiny8_cnt[L] = (int32_t)(mid8 - b);
+        }
     }
     // children (increasing index)
     pl.ch_ptr.assign((size_t)ns + 1, 0);

@@ -44,6 +44,7 @@ struct Plan {
     std::vector<int64_t> lvl_small_rsum;                // rows of the small fronts per level, summed
     std::vector<int32_t> lvl_tiny_cnt;                  // leading small fronts of <= TINY_R rows run on lane
                                                         // groups (0: the level has fewer than TINY_MIN)
+    std::vector<int32_t> lvl_tiny8_cnt;                 // leading ones among those of <= TINY_R8 rows
     std::vector<int32_t> lvl_large_ptr, lvl_large_sn;   // large ones by level
     std::vector<int64_t> task_ptr;        // per level: column tasks (s, j)
     std::vector<int32_t> task_sn, task_col;

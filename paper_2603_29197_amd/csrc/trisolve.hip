@@ -262,6 +262,13 @@ __device__ inline void bwd_front_chain(int32_t s, const int32_t *__restrict__ sn
 // shuffle.  Same operations in the same order as fwd_front and bwd_front (the
 // backward's column sums are the same butterfly restricted to the 16 lanes
 // that hold rows), hence the same values.
+// Largest of a value over the four 16-lane groups of a wavefront (every lane holds its group's
+// value), returned in every lane.
+__device__ inline int wave_max4(int v) {
+    v = max(v, __shfl_xor(v, 16));
+    return max(v, __shfl_xor(v, 32));
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) fwd_tiny(
     int32_t nfront, const int32_t *__restrict__ sn_list, const int32_t *__restrict__ sn_first,
@@ -288,8 +295,12 @@ __global__ void __launch_bounds__(256) fwd_tiny(
         a = gl < k ? xp[f + gl] : 0.0;
         for (int64_t u = ctb_ptr[tk]; u < ctb_ptr[tk + 1]; ++u) a += vwork[ctb_src[u]];
     }
+    // steps beyond the wavefront's largest pivot count change nothing: stop there (a bound that is
+    // the same in every lane, as the shuffles need)
+    const int kw = wave_max4(k);
 #pragma unroll
     for (int jj = 0; jj < TINY_R; ++jj) {
+        if (jj >= kw) break;
         const double yj = __shfl(a, gb + jj);
         if (jj < k && gl > jj && live) a -= lc[jj] * yj;
     }
@@ -321,8 +332,12 @@ __global__ void __launch_bounds__(256) bwd_tiny(
         lc[c] = ((c < k && upd) || (c < k && gl < c)) ? (double)F[upd ? (int64_t)c * r + gl : (int64_t)gl * r + c] : 0.0;
     const double dg = gl < k ? (double)F[(int64_t)gl * r + gl] : 1.0;
     double v = 0.0;
+    // columns and steps beyond the wavefront's largest pivot count change nothing: skipped (a bound
+    // that is the same in every lane, as the shuffles need)
+    const int kw = wave_max4(k);
 #pragma unroll
     for (int c = 0; c < TINY_R; ++c) {
+        if (c >= kw) break;
         double p = 0.0;
         if (c < k && upd) p += lc[c] * g;
         p += 0.0;                                     // the rows l + 64 of bwd_front (none here)
@@ -331,6 +346,7 @@ __global__ void __launch_bounds__(256) bwd_tiny(
     }
 #pragma unroll
     for (int i = TINY_R - 1; i >= 0; --i) {
+        if (i >= kw) continue;
         const double xi = __shfl(v, gb + i);
         if (i < k && gl < i) v -= lc[i] * xi;
     }

@@ -46,19 +46,28 @@ __device__ inline void accumulate(double (&val)[NS], const uint32_t maxmask, int
 }
 
 // Second pass: workgroup g reduces the g-th run of nblk x ns partials (one
-// run per problem of a batch; slot-major) into out[g ns ..]: wavefront w takes
-// the slots w, w + 4, ..., each lane a fixed strided subset of the blocks,
-// then a fixed butterfly (deterministic).
-__global__ void __launch_bounds__(256) finish_reduce(const double *__restrict__ partials, int32_t nblk,
+// run per problem of a batch; slot-major) into out[g ns ..]: wavefront w of W takes
+// the slots w, w + W, ..., each lane a fixed strided subset of the blocks in a
+// fixed order, then a fixed butterfly (deterministic).
+__global__ void __launch_bounds__(FINISH_THREADS) finish_reduce(const double *__restrict__ partials, int32_t nblk,
                                                      int32_t ns, uint32_t maxmask, double *__restrict__ out) {
     partials += (int64_t)blockIdx.x * nblk * ns;
     out += (int64_t)blockIdx.x * ns;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int q = wave; q < ns; q += 4) {
+    for (int q = wave; q < ns; q += (int)(blockDim.x >> 6)) {
         const bool ismax = (maxmask >> q) & 1u;
         const double *pq = partials + (int64_t)q * nblk;
-        double v = ismax ? -INFINITY : 0.0;
-        for (int32_t b = lane; b < nblk; b += 64) v = ismax ? nan_max(v, pq[b]) : v + pq[b];
+        const double id = ismax ? -INFINITY : 0.0;
+        double v = id;
+        // 16 loads per lane in flight at a time (the partials were just written by other compute
+        // units: each round waits for memory once)
+        for (int32_t b0 = lane; b0 < nblk; b0 += 64 * 16) {
+            double t[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) t[u] = b0 + 64 * u < nblk ? pq[b0 + 64 * u] : id;
+#pragma unroll
+            for (int u = 0; u < 16; ++u) v = ismax ? nan_max(v, t[u]) : v + t[u];
+        }
         for (int off = 32; off > 0; off >>= 1) {
             const double o = __shfl_xor(v, off);
             v = ismax ? nan_max(v, o) : v + o;
@@ -284,7 +293,7 @@ int launch_residual(qg_handle *h, const double *x, const double *y, const double
         residual_kernel<16><<<grid, 256, 0, h->stream>>>(
             h->n, h->p, h->m, d.kr_ptr.p, d.kr_col.p, d.kr_val.p, x, y, z, s, d.c.p, d.b.p, d.h.p, d.rx.p, d.ry.p,
             d.rz.p, d.partials.p, kb, n1, p1, m1, l1, rsc);
-    finish_reduce<<<(unsigned)kb, 256, 0, h->stream>>>(d.partials.p, nblk, NSCAL, SCAL_MAXMASK, d.scal_inst.p);
+    finish_reduce<<<(unsigned)kb, FINISH_THREADS, 0, h->stream>>>(d.partials.p, nblk, NSCAL, SCAL_MAXMASK, d.scal_inst.p);
     QG_HIP(h, hipGetLastError());
     const size_t nv = (size_t)kb * NSCAL;
     double *dst = nv + 4 <= (size_t)PIN_DOUBLES ? h->pin : scal_host;   // large batches: pageable
@@ -358,7 +367,7 @@ int launch_kkt_residual(qg_handle *h, const double *rhs, const double *sol, doub
         kkt_residual_kernel<16><<<nblk, 256, 0, h->stream>>>(h->n, h->p, h->m, h->pp.l, d.kr_ptr.p, d.kr_col.p,
                                                              d.kr_val.p, d.kval.p, d.blk33.p, d.blk_off.p,
                                                              d.soc_off.p, d.zcone.p, rhs, sol, res, d.partials.p);
-    finish_reduce<<<1, 256, 0, h->stream>>>(d.partials.p, nblk, 2, 3u, d.scal.p + NSCAL);
+    finish_reduce<<<1, 128, 0, h->stream>>>(d.partials.p, nblk, 2, 3u, d.scal.p + NSCAL);
     QG_HIP(h, hipGetLastError());
     double *pn = h->pin + PIN_DOUBLES - 4;
     QG_HIP(h, hipMemcpyAsync(pn, d.scal.p + NSCAL, 2 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
